@@ -1,0 +1,166 @@
+"""One step-then-truncate time step in TT form (paper Sec. 4).
+
+Transport (Sec. 4.3).  n_x = sin(theta) (x) cos(phi) and
+n_y = sin(theta) (x) sin(phi) are rank 1 and so are the upwind masks, so the
+explicit update of eq. lhs is a sum of TTs.  Reading used (one block per
+axis and sign):
+    I* = I + sum_a [ (D_a^- X) (tf_a^+ Theta) (-lam_a pf_a^+ Phi)
+                   + (D_a^+ X) (tf_a^- Theta) (-lam_a pf_a^- Phi) ]
+with D_a^- X = X_i - X_{i-e_a}, D_a^+ X = X_{i+e_a} - X_i (ghost rows 0, or
+wrapped when periodic), and for x/y: tf^+ = tf^- = sin(theta),
+pf^+ = max(cos or sin, 0), pf^- = min(cos or sin, 0); for z (3-D):
+tf^+ = max(mu, 0), tf^- = min(mu, 0), pf = 1.  Dirichlet inflow adds one
+rank-1 block per inflow face (Sec. 4.5: ghost value added as a rank-1
+term): on a lo face  e_face (x) tf^+ theta_w (x) lam pf^+ phi_w, on a hi face
+e_face (x) tf^- theta_w (x) (-lam) pf^- phi_w.
+
+Source (Sec. 4.4): every X-block row i is scaled by d_i and the emission
+block s (x) 1 (x) 1 is appended (omitted when the temperature is frozen at
+zero everywhere).
+
+TT sum (Sec. 4.1 Addition): cores concatenated, middle core block-diagonal.
+Block order: base, then per axis (minus, plus), then inflow entries in input
+order, then emission.
+
+Rounding: Gram-SVD (``rounding.round_gram``), once after the fused
+transport + source sum by default; schedule "twice" also rounds after the
+transport sum, as the paper does after each transport and each split update
+(Sec. 4.2).
+"""
+import numpy as np
+
+from . import material as mat
+from . import rounding
+from .setup import PERIODIC
+
+
+def shift(X, setup, axis, direction):
+    """Rows X_{i + direction*e_a}: zero ghost rows, or wrapped if periodic."""
+    r = X.shape[1]
+    G = X.reshape(setup.grid_shape() + (r,))
+    ax = 2 - axis
+    S = np.roll(G, -direction, axis=ax)
+    periodic = setup.bc_lo[axis] == PERIODIC
+    if not periodic:
+        sl = [slice(None)] * 4
+        sl[ax] = 0 if direction < 0 else -1
+        S[tuple(sl)] = 0.0
+    return S.reshape(-1, r)
+
+
+def transport_blocks(X, Th, Ph, setup):
+    blocks = [(X, Th, Ph)]
+    for a in range(setup.dim):
+        tf, pf = setup.cosine_factors(a)
+        lam = setup.lam[a]
+        Dm = X - shift(X, setup, a, -1)
+        Dp = shift(X, setup, a, +1) - X
+        if a < 2:
+            tpos = tneg = tf
+            ppos, pneg = np.maximum(pf, 0.0), np.minimum(pf, 0.0)
+        else:
+            tpos, tneg = np.maximum(tf, 0.0), np.minimum(tf, 0.0)
+            ppos = pneg = pf
+        blocks.append((Dm, Th * tpos[None, :, None], Ph * (-lam * ppos)[None, :]))
+        blocks.append((Dp, Th * tneg[None, :, None], Ph * (-lam * pneg)[None, :]))
+    for (f, fw, tw, pw) in setup.inflow:
+        a, hi = divmod(f, 2)
+        tf, pf = setup.cosine_factors(a)
+        lam = setup.lam[a]
+        e = np.zeros(setup.ns)
+        e[setup.face_cells(f)] = fw
+        if a < 2:
+            tpart = tf * tw
+            ppart = (lam * np.maximum(pf, 0.0) if not hi else -lam * np.minimum(pf, 0.0)) * pw
+        else:
+            tpart = (np.maximum(tf, 0.0) if not hi else np.minimum(tf, 0.0)) * tw
+            ppart = (lam if not hi else -lam) * pf * pw
+        blocks.append((e[:, None], tpart[None, :, None], ppart[None, :]))
+    return blocks
+
+
+def concat(blocks):
+    """TT sum by core concatenation (Sec. 4.1 Addition)."""
+    Xc = np.concatenate([b[0] for b in blocks], axis=1)
+    R1 = Xc.shape[1]
+    R2 = sum(b[2].shape[0] for b in blocks)
+    nt = blocks[0][1].shape[1]
+    Thc = np.zeros((R1, nt, R2))
+    o1 = o2 = 0
+    for (_, Th, Ph) in blocks:
+        a, _, b = Th.shape
+        Thc[o1:o1 + a, :, o2:o2 + b] = Th
+        o1 += a
+        o2 += b
+    Phc = np.concatenate([b[2] for b in blocks], axis=0)
+    return Xc, Thc, Phc
+
+
+def energy(X, Th, Ph, setup):
+    """E_i = (1/c) X_i (sum_l Theta_l w_l)(sum_p Phi_p v_p)  (eq. tt_energy_density)."""
+    th = np.einsum("alb,l->ab", Th, setup.w)
+    ph = Ph @ setup.v
+    return X @ (th @ ph) / setup.c
+
+
+def source_blocks(blocks, d, s, setup):
+    out = [(d[:, None] * Xb, Thb, Phb) for (Xb, Thb, Phb) in blocks]
+    if setup.n_em:
+        out.append((s[:, None], np.ones((1, setup.nt, 1)), np.ones((1, setup.np_))))
+    return out
+
+
+def step(X, Th, Ph, T, setup, tol, rmax, schedule="once", ranks=None):
+    """One TT step.  Returns ((X, Th, Ph), T_new, info).
+
+    ``ranks``: replayed ranks, a pair (r1, r2) for "once" or a pair of
+    pairs for "twice"; None uses the rank rule.
+    """
+    blocks = transport_blocks(X, Th, Ph, setup)
+    infos = []
+    rk_last = ranks
+    if schedule == "twice":
+        Xc, Thc, Phc = concat(blocks)
+        rk = None if ranks is None else ranks[0]
+        rk_last = None if ranks is None else ranks[1]
+        (X1, Th1, Ph1), inf = rounding.round_gram(Xc, Thc, Phc, tol, rmax, rk)
+        infos.append(inf)
+        blocks = [(X1, Th1, Ph1)]
+    Estar = sum(energy(*b, setup) for b in blocks)
+    d, s, Tdag = mat.source_coefficients(Estar, T, setup)
+    cat = concat(source_blocks(blocks, d, s, setup))
+    (Xn, Thn, Phn), inf = rounding.round_gram(*cat, tol, rmax, rk_last)
+    infos.append(inf)
+    Enew = energy(Xn, Thn, Phn, setup)
+    Tnew = mat.temperature_update(T, Estar, Enew, setup)
+    return (Xn, Thn, Phn), Tnew, dict(Estar=Estar, Enew=Enew, d=d, s=s,
+                                       round=infos, R=(cat[0].shape[1], cat[2].shape[0]))
+
+
+def step_untruncated(X, Th, Ph, T, setup):
+    """The same step without rounding: concatenated cores (ranks R1, R2)."""
+    blocks = transport_blocks(X, Th, Ph, setup)
+    Estar = sum(energy(*b, setup) for b in blocks)
+    d, s, Tdag = mat.source_coefficients(Estar, T, setup)
+    cat = concat(source_blocks(blocks, d, s, setup))
+    Enew = energy(*cat, setup)
+    return cat, mat.temperature_update(T, Estar, Enew, setup), dict(Estar=Estar, Enew=Enew, Tdag=Tdag)
+
+
+def run(setup, nsteps, tol=None, rmax=None, schedule="once", cores=None, T=None,
+        rank_schedule=None, callback=None):
+    p = setup.p
+    tol = p["tol"] if tol is None else tol
+    rmax = p["rmax"] if rmax is None else rmax
+    X, Th, Ph = cores if cores is not None else (np.asarray(p["X0"], float),
+                                                  np.asarray(p["Th0"], float),
+                                                  np.asarray(p["Ph0"], float))
+    T = setup.T0.copy() if T is None else T
+    history = []
+    for m in range(nsteps):
+        rk = None if rank_schedule is None else rank_schedule[m]
+        (X, Th, Ph), T, info = step(X, Th, Ph, T, setup, tol, rmax, schedule, rk)
+        history.append((X.shape[1], Ph.shape[0]))
+        if callback is not None:
+            callback(m, (X, Th, Ph), T, info)
+    return (X, Th, Ph), T, history

@@ -1,0 +1,331 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test ties one oracle function to a closed form, an invariant, a value
+printed in the paper, or a library routine (SVD / QR / ODE integrator), so
+that a dropped term, wrong sign, wrong neighbour or transposed operand in
+the oracle fails at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import Setup, full, tt, rounding, metrics, material, adjoint, quadrature
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("nt,npf", [(2, 4), (8, 16), (32, 64)])
+def test_quadrature_closed_forms(nt, npf):
+    mu, w, phi, v = quadrature.ordinates(nt, npf)
+    dom = quadrature.solid_angles(nt, npf)
+    assert abs(dom.sum() - 4 * np.pi) < 1e-13          # sum dOmega = 4 pi (Sec. 3)
+    st, cp, sp, mu2 = quadrature.direction_cosines(nt, npf)
+    for n in (np.outer(st, cp), np.outer(st, sp), np.outer(mu2, np.ones(npf))):
+        assert abs((dom * n).sum()) < 1e-13            # no net flux direction
+    # midpoint rule on int mu^2 dmu over [-1,1]: 2/3 (1 - 1/Nt^2) exactly
+    assert abs(w @ mu ** 2 - 2.0 / 3.0 * (1 - 1.0 / nt ** 2)) < 1e-14
+    # midpoint rule over a full period is exact for cos^2: pi
+    assert abs(v @ np.cos(phi) ** 2 - np.pi) < 1e-13
+    assert np.all(np.abs(np.outer(st, cp)) > 0) and np.all(np.abs(mu2) > 0)
+
+
+# ------------------------------------------------------------ full transport
+def _line_problem(nx=16, nt=4, npf=8, bc="periodic", kappa=0.0):
+    p = wl._base(2, nx, 1, 1, nt, npf, tol=0.0, rmax=0, steps=1)
+    p["ly"] = p["lx"] / nx
+    p["bc_lo"] = [wl.PERIODIC if bc == "periodic" else wl.INFLOW, wl.PERIODIC, 0]
+    p["bc_hi"] = [wl.PERIODIC if bc == "periodic" else wl.VACUUM, wl.PERIODIC, 0]
+    p["kappa"][:] = kappa
+    p["T0"][:] = 0.0
+    return p
+
+
+def test_upwind_fourier_amplification():
+    """Upwind scheme on a periodic line: a Fourier mode evolves by the
+    textbook amplification factor g = 1 - nu (1 - e^{-ih}) (nu >= 0) or
+    g = 1 - nu (e^{ih} - 1) (nu < 0), nu = lam n_x; checked over 5 steps."""
+    p = _line_problem()
+    s = Setup(p)
+    k = 3
+    x = (np.arange(s.nx) + 0.5) * s.dx
+    theta = 2 * np.pi * k * x
+    h = 2 * np.pi * k * s.dx
+    I = np.broadcast_to(np.cos(theta)[None, None, :, None, None],
+                        (1, 1, s.nx, s.nt, s.np_)).copy()
+    m = 5
+    for _ in range(m):
+        I = full.transport(I, s)
+    nu = s.lam[0] * np.outer(s.sin_t, s.cos_p)
+    g = np.where(nu >= 0, 1 - nu * (1 - np.exp(-1j * h)), 1 - nu * (np.exp(1j * h) - 1))
+    expect = np.real(g[None, :, :] ** m * np.exp(1j * theta)[:, None, None])
+    assert np.max(np.abs(I[0, 0] - expect)) < 1e-13
+
+
+def test_upwind_inflow_steady_state():
+    """Constant inflow g on the x-lo face, absorption d: the scheme's steady
+    state is I_i = q^{i+1} g with q = d nu / (1 - d (1 - nu)) for n_x > 0 and
+    zero for n_x < 0 (vacuum on the far face)."""
+    nx, nt, npf = 6, 4, 8
+    p = _line_problem(nx=nx, nt=nt, npf=npf, bc="inflow", kappa=0.7)
+    p["inflow"] = [(0, np.array([1.3]), np.ones(nt), np.ones(npf))]
+    p["cfl"] = 0.9
+    s = Setup(p)
+    I = np.zeros((1, 1, nx, nt, npf))
+    for _ in range(4000):
+        I, _, _ = full.step(I, s.T0, s)
+    nu = s.lam[0] * np.outer(s.sin_t, s.cos_p)
+    d = 1.0 / (1.0 + s.c * s.dt * 0.7)
+    q = d * nu / (1 - d * (1 - nu))
+    i = np.arange(nx)[:, None, None]
+    expect = np.where(nu[None] > 0, 1.3 * q[None] ** (i + 1), 0.0)
+    assert np.max(np.abs(I[0, 0] - expect)) < 1e-12
+
+
+def test_transport_conserves_per_ordinate_and_stays_positive():
+    p = wl.small_random(bc="periodic", seed=7)
+    p["kappa"][:] = 0.0
+    s = Setup(p)
+    I = full.initial_intensity(s)
+    I1 = full.transport(I, s)
+    assert np.allclose(I1.sum(axis=(0, 1, 2)), I.sum(axis=(0, 1, 2)), rtol=1e-14, atol=0)
+    assert I1.min() >= 0 and I1.max() <= I.max() * (1 + 1e-15)  # convex combination (CFL)
+
+
+def test_energy_of_isotropic_field():
+    p = wl.small_random(seed=3)
+    s = Setup(p)
+    I = np.full(s.grid_shape() + (s.nt, s.np_), 2.5)
+    assert np.allclose(full.energy(I, s), 4 * np.pi * 2.5 / s.c, rtol=1e-14)
+
+
+# ------------------------------------------------------------------ material
+def test_newton_root_and_identity():
+    p = wl.small_random(material=wl.COUPLED, seed=11)
+    s = Setup(p)
+    rng = np.random.default_rng(5)
+    Estar = rng.random(s.ns) * 3
+    d, sv, Tdag = material.source_coefficients(Estar, s.T0, s)
+    g = s.c * s.dt * s.kappa / s.cv / (1 + s.c * s.dt * s.rho * s.kappa)
+    f = Tdag - s.T0 + g * (s.a_r * Tdag ** 4 - Estar)
+    assert np.max(np.abs(f)) < 1e-14 * np.max(Tdag)
+    # untruncated step: T^{m+1} = T_dag exactly (energy-conserving update)
+    cat, T1, info = tt.step_untruncated(p["X0"], p["Th0"], p["Ph0"], s.T0, s)
+    assert np.allclose(T1, info["Tdag"], rtol=1e-12, atol=1e-13)
+
+
+def _relaxation_run(kappa, steps, dt=0.01):
+    p = wl.relaxation(kappa=kappa, steps=steps)
+    p["dt"] = dt
+    s = Setup(p)
+    Ts, Es, ranks = [], [], []
+
+    def cb(m, cores, T, info):
+        Ts.append(T.copy()); Es.append(info["Enew"].copy())
+        ranks.append((cores[0].shape[1], cores[2].shape[0]))
+    tt.run(s, steps, callback=cb)
+    return np.array(Ts), np.array(Es), ranks
+
+
+def test_relaxation_paper_example():
+    """Thermal relaxation (Sec. 5.2): rho c_v T + a_r T_r^4 is conserved,
+    kappa = 1e6 equilibrates in one step to the root of 8T + T^4 = 17,
+    ranks stay (1, 1), and kappa = 1 converges to the ODE solution at first
+    order in dt (backward Euler) when going from 300 to 600 steps to t = 3."""
+    Ts, Es, ranks = _relaxation_run(1e6, 3)
+    roots = np.roots([1, 0, 0, 8, -17])
+    Teq = float(np.real(roots[(np.abs(roots.imag) < 1e-12) & (roots.real > 0)][0]))
+    assert abs(Teq - 1.497) < 1e-3
+    assert np.allclose(Ts[0], Teq, rtol=1e-3)
+    assert np.allclose(8 * Ts + Es, 17.0, rtol=1e-12)
+    assert all(r == (1, 1) for r in ranks)
+    from scipy.integrate import solve_ivp
+
+    def rhs(t, y):
+        T, E = y
+        q = 1.0 * (T ** 4 - E)
+        return [-q / 8.0, q]
+    sol = solve_ivp(rhs, (0, 3), [2.0, 1.0], rtol=1e-12, atol=1e-14, dense_output=True)
+    errs = []
+    for steps in (300, 600):
+        Ts, Es, ranks = _relaxation_run(1.0, steps, dt=3.0 / steps)
+        assert all(r == (1, 1) for r in ranks)
+        assert np.allclose(8 * Ts + Es, 17.0, rtol=1e-12)
+        Tode = sol.sol(3.0 / steps * np.arange(1, steps + 1))[0]
+        errs.append(np.max(np.abs(Ts[:, 0] - Tode)))
+    assert errs[0] < 5e-3
+    assert 1.8 < errs[0] / errs[1] < 2.2
+
+
+# ------------------------------------------------------------------ rounding
+def _orth(n, r, rng):
+    q, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    return q
+
+
+def _spectrum_tt(ns, nt, npf, s, rng):
+    """Orthonormal X, orthonormal Phi rows and Theta_{a,l,b} = s_a d_ab
+    d_{l, a mod nt}: both bond unfoldings have singular values s."""
+    r = s.size
+    X = _orth(ns, r, rng)
+    Ph = _orth(npf, r, rng).T
+    Th = np.zeros((r, nt, r))
+    for a in range(r):
+        Th[a, a % nt, a] = s[a]
+    return X, Th, Ph
+
+
+def test_gram_svd_recovers_constructed_spectrum_and_ranks():
+    rng = np.random.default_rng(0)
+    s = 10.0 ** (-np.arange(10) / 1.5)
+    X, Th, Ph = _spectrum_tt(60, 5, 16, s, rng)
+    tol = 1e-4
+    (Xn, Thn, Phn), (i1, i2) = rounding.round_gram(X, Th, Ph, tol, 0)
+    assert np.allclose(i1["sigma"][:s.size], s, rtol=1e-10, atol=1e-12)
+    delta2 = tol ** 2 * np.sum(s ** 2) / 2
+    tail = np.array([np.sum(s[k:] ** 2) for k in range(s.size + 1)])
+    expect = int(np.argmax(tail <= delta2))
+    assert Xn.shape[1] == expect and Phn.shape[0] == expect
+    assert np.allclose(i2["sigma"][:expect], s[:expect], rtol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gram_svd_equals_dense_and_ttsvd(seed):
+    """Gram-SVD, TT-SVD (QR) and dense SVD truncate the same unfoldings, so
+    they agree up to rounding where the spectrum has a gap at the cut."""
+    rng = np.random.default_rng(seed)
+    X, Th, Ph = wl.random_tt(40, 6, 12, 8, 5, seed, decay=0.15)
+    T = metrics.reconstruct(X, Th, Ph)
+    tol = 1e-5
+    g = rounding.round_gram(X, Th, Ph, tol, 0)[0]
+    d = rounding.round_dense(T, tol, 0)
+    q = rounding.round_ttsvd(X, Th, Ph, tol, 0)
+    assert g[0].shape[1] == d[0].shape[1] == q[0].shape[1]
+    assert g[2].shape[0] == d[2].shape[0] == q[2].shape[0]
+    assert metrics.rel_diff(g, d) < 1e-9
+    assert metrics.rel_diff(q, d) < 1e-11
+    # error bound of the tolerance split, and orthonormal left factor
+    assert np.linalg.norm(metrics.reconstruct(*g) - T) <= tol * np.linalg.norm(T) * (1 + 1e-6)
+    assert np.allclose(g[0].T @ g[0], np.eye(g[0].shape[1]), atol=1e-10)
+
+
+def test_rank_one_exact_self_sum_and_zero():
+    p = wl.c1()
+    X, Th, Ph = p["X0"], p["Th0"], p["Ph0"]
+    (Xn, Thn, Phn), _ = rounding.round_gram(X, Th, Ph, 1e-8, 0)
+    assert (Xn.shape[1], Phn.shape[0]) == (1, 1)
+    T = metrics.reconstruct(X, Th, Ph)
+    assert np.linalg.norm(metrics.reconstruct(Xn, Thn, Phn) - T) < 1e-14 * np.linalg.norm(T)
+    # T + T by concatenation rounds back to rank(T), values 2T
+    A = wl.random_tt(30, 4, 8, 3, 2, 9)
+    cat = tt.concat([A, A])
+    (Xs, Ts, Ps), _ = rounding.round_gram(*cat, 1e-10, 0)
+    assert (Xs.shape[1], Ps.shape[0]) == (3, 2)
+    TA = metrics.reconstruct(*A)
+    assert np.linalg.norm(metrics.reconstruct(Xs, Ts, Ps) - 2 * TA) < 1e-12 * np.linalg.norm(TA)
+    # zero tensor -> rank (1,1), zero cores
+    (Xz, Tz, Pz), _ = rounding.round_gram(np.zeros((20, 3)), np.ones((3, 4, 2)), np.ones((2, 8)), 1e-6, 0)
+    assert (Xz.shape[1], Pz.shape[0]) == (1, 1) and not Xz.any()
+
+
+def test_cluster_and_cap_rules():
+    sig = np.array([3.0, 2.0, 2.0, 1.0, 1e-9])
+    # tolerance would cut inside the degenerate pair: extended to the end
+    assert rounding.select_rank(sig, 1.5, 0) == 3
+    # cap inside the pair: cut before it
+    assert rounding.select_rank(sig, 1e-30, 2) == 1
+    assert rounding.select_rank(sig, 1e-30, 4) == 4
+    assert rounding.select_rank(np.zeros(3), 0.0, 0) == 1
+
+
+# ---------------------------------------------------------------- TT vs full
+@pytest.mark.parametrize("kw", [dict(seed=1), dict(bc="periodic", seed=2),
+                                dict(bc="inflow", seed=3, material=wl.COUPLED),
+                                dict(dim=3, nx=4, ny=3, nz=5, bc="inflow", seed=4, material=wl.COUPLED),
+                                dict(dim=3, nx=4, ny=3, nz=4, bc="periodic", seed=5)])
+def test_tt_step_without_truncation_is_the_full_grid_step(kw):
+    p = wl.small_random(**kw)
+    s = Setup(p)
+    I1, T1, _ = full.step(full.initial_intensity(s), s.T0, s)
+    cat, T1t, _ = tt.step_untruncated(p["X0"], p["Th0"], p["Ph0"], s.T0, s)
+    F = metrics.reconstruct(*cat).reshape(I1.shape)
+    assert np.linalg.norm(F - I1) < 1e-13 * np.linalg.norm(I1)
+    (Xn, Thn, Phn), T2, _ = tt.step(p["X0"], p["Th0"], p["Ph0"], s.T0, s, 0.0, 0)
+    F2 = metrics.reconstruct(Xn, Thn, Phn).reshape(I1.shape)
+    assert np.linalg.norm(F2 - I1) < 1e-12 * np.linalg.norm(I1)
+
+
+def test_conservation_periodic_no_absorption():
+    p = wl.small_random(bc="periodic", seed=12, nx=8, ny=6)
+    p["kappa"][:] = 0.0
+    p["T0"][:] = 0.0
+    s = Setup(p)
+    X, Th, Ph = p["X0"], p["Th0"], p["Ph0"]
+    tol = 1e-6
+    E0 = tt.energy(X, Th, Ph, s).sum()
+    for _ in range(5):
+        cat, _, info = tt.step_untruncated(X, Th, Ph, s.T0, s)
+        assert abs(info["Enew"].sum() - E0) < 1e-14 * abs(E0) * 10
+        nrm = metrics.tt_norm(*cat)
+        (X, Th, Ph), _ = rounding.round_gram(*cat, tol, 0)
+        E1 = tt.energy(X, Th, Ph, s).sum()
+        bound = tol * nrm * np.sqrt(s.ns) * 4 * np.pi / np.sqrt(s.nt * s.np_) / s.c
+        assert abs(E1 - E0) <= bound
+        E0 = E1
+
+
+def test_c1_symmetry_of_the_square():
+    """C1 (square, centred pulse, symmetric quadrature): E is invariant under
+    the 8 symmetries of the square up to the truncation level."""
+    p = wl.c1()
+    p["tol"] = 1e-6
+    s = Setup(p)
+    (X, Th, Ph), _, hist = tt.run(s, 6)
+    E = tt.energy(X, Th, Ph, s).reshape(32, 32)
+    ref = np.abs(E).max()
+    for img in (E.T, E[::-1], E[:, ::-1], E[::-1, ::-1], E.T[::-1], E.T[:, ::-1], E.T[::-1, ::-1]):
+        assert np.max(np.abs(img - E)) < 1e-5 * ref
+
+
+# ------------------------------------------------------------------ adjoint
+@pytest.mark.parametrize("kw", [dict(seed=1), dict(bc="periodic", seed=2),
+                                dict(dim=3, nx=3, ny=4, nz=3, seed=3)])
+def test_transport_adjoint_dot_product(kw):
+    s = Setup(wl.small_random(**kw))
+    rng = np.random.default_rng(1)
+    shp = s.grid_shape() + (s.nt, s.np_)
+    x, y = rng.standard_normal(shp), rng.standard_normal(shp)
+    lhs = np.sum(adjoint.transport_linear(x, s) * y)
+    rhs = np.sum(x * adjoint.transport_adjoint(y, s))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_full_grid_gradient_matches_finite_differences():
+    p = wl.small_random(nx=7, ny=6, seed=21)
+    p["material"] = wl.FROZEN
+    s = Setup(p)
+    det = np.zeros(s.ns); det[[10, 11, 17, 18]] = 1.0
+    L, g = adjoint.grad_full(s, 4, det)
+    cells = [3, 10, 17, 25, 40]
+    gfd = adjoint.grad_fd(lambda k: adjoint.loss_full(s, k, 4, det), s.kappa, cells)
+    assert np.allclose(g[cells], gfd, rtol=1e-6, atol=1e-10 * np.abs(g).max())
+
+
+# ------------------------------------------------------------------ metrics
+def test_compression_reproduces_printed_values():
+    with open(os.path.join(GOLDEN, "compression_pins.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        C = metrics.compression(c["ns"], c["nt"], c["np"], c["r1"], c["r2"])
+        assert abs(C - c["printed"]) <= c["rel"] * c["printed"], c["what"]
+
+
+def test_tt_difference_norm_matches_dense():
+    A = wl.random_tt(50, 4, 6, 3, 2, 1)
+    B = wl.random_tt(50, 4, 6, 2, 3, 2)
+    dn = np.linalg.norm(metrics.reconstruct(*A) - metrics.reconstruct(*B))
+    assert abs(metrics.tt_diff_norm(A, B) - dn) < 1e-12 * dn
+    assert abs(metrics.rel_diff(A, B, dense_limit=0) - metrics.rel_diff(A, B)) < 1e-12

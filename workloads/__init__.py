@@ -1,0 +1,270 @@
+"""Seeded synthetic workloads for the tensor-train S_N step.
+
+This module only *describes* problems: grid and angle counts, physical
+constants, boundary codes, per-cell material fields, initial TT cores and
+inflow beam profiles.  It holds none of the method's arithmetic (no
+quadrature, no transport, no rounding); both the CPU oracle and the HIP
+library read the arrays produced here, so they see bit-identical inputs.
+
+Every generator returns a plain ``dict``:
+
+========== ==============================================================
+key        meaning
+========== ==============================================================
+dim        2 or 3
+nx,ny,nz   cells per axis (nz = 1 when dim == 2)
+ntheta     polar ordinates (uniform in cos(theta)); even
+nphi       azimuthal ordinates; multiple of 4
+lx,ly,lz   domain extents (cell size = l/n)
+c, a_r     speed of light, radiation constant
+cfl        time step = cfl * min cell size / c
+tol        relative Frobenius rounding tolerance
+rmax       rank cap (<= 0: none)
+bc_lo/hi   per axis: 0 vacuum, 1 periodic, 2 inflow
+material   0 frozen temperature, 1 coupled (backward-Euler material)
+kappa,rho,cv,T0  per-cell float64 arrays of length N_s = nx*ny*nz
+X0,Th0,Ph0 initial cores, shapes (N_s,r1), (r1,ntheta,r2), (r2,nphi)
+inflow     list of (face, face_w, theta_w, phi_w); face 0..5 =
+           x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; face_w is indexed by the
+           face's own 2-D cell index (see ``face_cells``)
+steps      number of steps of the workload
+========== ==============================================================
+
+Spatial cells are flattened as ``i = ix + nx*(iy + ny*iz)``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+VACUUM, PERIODIC, INFLOW = 0, 1, 2
+FROZEN, COUPLED = 0, 1
+
+
+def _cell_centres(n, l):
+    return (np.arange(n) + 0.5) * (l / n)
+
+
+def _base(dim, nx, ny, nz, ntheta, nphi, *, tol, rmax, steps, l=1.0):
+    ns = nx * ny * nz
+    return dict(dim=dim, nx=nx, ny=ny, nz=nz, ntheta=ntheta, nphi=nphi,
+                lx=l, ly=l, lz=(l if dim == 3 else 1.0), c=1.0, a_r=1.0,
+                cfl=0.5, tol=tol, rmax=rmax, steps=steps,
+                bc_lo=[VACUUM] * 3, bc_hi=[VACUUM] * 3, material=FROZEN,
+                kappa=np.ones(ns), rho=np.ones(ns), cv=np.ones(ns),
+                T0=np.ones(ns), inflow=[])
+
+
+def gaussian_pulse_cores(p, sigma=0.05, U0=1.0):
+    """Isotropic Gaussian pulse centred in the unit square/cube, rank (1,1).
+
+    Intensity (c/4pi) * U0/(2 pi sigma^2) * exp(-|x-xc|^2/(2 sigma^2)),
+    sampled at cell centres, carried entirely by the spatial core.
+    """
+    xs = _cell_centres(p["nx"], p["lx"]) - 0.5 * p["lx"]
+    ys = _cell_centres(p["ny"], p["ly"]) - 0.5 * p["ly"]
+    r2 = xs[None, :] ** 2 + ys[:, None] ** 2
+    if p["dim"] == 3:
+        zs = _cell_centres(p["nz"], p["lz"]) - 0.5 * p["lz"]
+        r2 = r2[None, :, :] + zs[:, None, None] ** 2
+    amp = p["c"] / (4 * np.pi) * U0 / (2 * np.pi * sigma ** 2)
+    X0 = (amp * np.exp(-r2 / (2 * sigma ** 2))).reshape(-1, 1)
+    return X0, np.ones((1, p["ntheta"], 1)), np.ones((1, p["nphi"]))
+
+
+def zero_cores(p):
+    ns = p["nx"] * p["ny"] * p["nz"]
+    return np.zeros((ns, 1)), np.ones((1, p["ntheta"], 1)), np.ones((1, p["nphi"]))
+
+
+def face_cells(p, face):
+    """Flattened spatial indices of the cells on ``face``, in face order.
+
+    x-faces are indexed by iy + ny*iz, y-faces by ix + nx*iz, z-faces by
+    ix + nx*iy.
+    """
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    ix = np.arange(nx); iy = np.arange(ny); iz = np.arange(nz)
+    axis, hi = divmod(face, 2)
+    if axis == 0:
+        x = nx - 1 if hi else 0
+        return (x + nx * (iy[None, :] + ny * iz[:, None])).reshape(-1)
+    if axis == 1:
+        y = ny - 1 if hi else 0
+        return (ix[None, :] + nx * (y + ny * iz[:, None])).reshape(-1)
+    z = nz - 1 if hi else 0
+    return (ix[None, :] + nx * (iy[:, None] + ny * z)).reshape(-1)
+
+
+def _beam_profile(t):
+    """Collimation profile in units of one ordinate spacing, cut at 3."""
+    b = np.exp(-0.5 * t ** 2)
+    b[np.abs(t) > 3.0] = 0.0
+    return b
+
+
+def crossing_beams(p, width=8, L=1.0):
+    """Two collimated beams entering through the x-lo and y-lo faces.
+
+    The profiles are expressed in ordinate-index units (one ordinate
+    spacing = 1): polar offset from the equator (cos theta = 0) is
+    ``l + 1/2 - ntheta/2``; azimuthal offset from the beam axis is
+    ``p + 1/2 - p_axis`` wrapped to [-nphi/2, nphi/2), with p_axis = 0
+    for +x and nphi/4 for +y.
+    """
+    nt, npf = p["ntheta"], p["nphi"]
+    theta_w = _beam_profile(np.arange(nt) + 0.5 - nt / 2)
+
+    def phi_prof(axis_index):
+        t = np.arange(npf) + 0.5 - axis_index
+        t = (t + npf / 2) % npf - npf / 2
+        return _beam_profile(t)
+
+    beams = []
+    # x-lo face: rows iy in the central band
+    fw = np.zeros(p["ny"] * p["nz"])
+    band = np.arange(p["ny"] // 2 - width // 2, p["ny"] // 2 + width // 2)
+    for iz in range(p["nz"]):
+        fw[band + p["ny"] * iz] = L
+    beams.append((0, fw, theta_w.copy(), phi_prof(0.0)))
+    # y-lo face: columns ix in the central band
+    fw = np.zeros(p["nx"] * p["nz"])
+    band = np.arange(p["nx"] // 2 - width // 2, p["nx"] // 2 + width // 2)
+    for iz in range(p["nz"]):
+        fw[band + p["nx"] * iz] = L
+    beams.append((2, fw, theta_w.copy(), phi_prof(npf / 4)))
+    return beams
+
+
+def gaussian_random_field(n, corr_len, seed, l=1.0):
+    """Stationary Gaussian random field on the periodic n x n grid.
+
+    White noise from ``default_rng(seed)`` filtered in Fourier space by the
+    square root of the spectral density of the covariance
+    exp(-r^2 / (2 corr_len^2)), then standardised to sample mean 0, std 1.
+    """
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal((n, n))
+    k = 2 * np.pi * np.fft.fftfreq(n, d=l / n)
+    k2 = k[None, :] ** 2 + k[:, None] ** 2
+    filt = np.exp(-0.25 * k2 * corr_len ** 2)
+    f = np.real(np.fft.ifft2(np.fft.fft2(xi) * filt))
+    return (f - f.mean()) / f.std()
+
+
+# --------------------------------------------------------------------------
+# The named workloads
+# --------------------------------------------------------------------------
+
+def c1():
+    """2-D parity case: 32^2, 8x16 ordinates, kappa = 1, T = 1 frozen,
+    centred Gaussian pulse, vacuum, CFL 0.5, 10 steps, tolerance 1e-8."""
+    p = _base(2, 32, 32, 1, 8, 16, tol=1e-8, rmax=0, steps=10)
+    p["X0"], p["Th0"], p["Ph0"] = gaussian_pulse_cores(p)
+    p["name"] = "c1_pulse_32sq_8x16"
+    return p
+
+
+def c2(steps=400):
+    """Optically thin crossing beams: 256^2, 32x64 ordinates, kappa = 1e-3,
+    cold medium (T = 0), two inflow beams, tolerance 1e-6, rank cap 64."""
+    p = _base(2, 256, 256, 1, 32, 64, tol=1e-6, rmax=64, steps=steps)
+    p["kappa"][:] = 1e-3
+    p["T0"][:] = 0.0
+    p["bc_lo"] = [INFLOW, INFLOW, VACUUM]
+    p["inflow"] = crossing_beams(p)
+    p["X0"], p["Th0"], p["Ph0"] = zero_cores(p)
+    p["name"] = "c2_beams_256sq_32x64"
+    return p
+
+
+def c4(n=128, steps=200):
+    """Optically thick two-region 3-D medium, coupled material (cv = 1)."""
+    p = _base(3, n, n, n, 32, 64, tol=1e-6, rmax=128, steps=steps)
+    xc = _cell_centres(n, 1.0)
+    inside = (xc >= 0.25) & (xc <= 0.75)
+    cube = inside[None, None, :] & inside[None, :, None] & inside[:, None, None]
+    p["kappa"] = np.where(cube.reshape(-1), 1e3, 1.0)
+    rng = np.random.default_rng(0)
+    xi = rng.standard_normal(n ** 3)
+    p["T0"] = np.clip(0.75 * (1 + 0.05 * xi), 0.5, 1.0)
+    p["material"] = COUPLED
+    ns = n ** 3
+    p["X0"] = (p["c"] / (4 * np.pi) * p["a_r"] * p["T0"] ** 4).reshape(ns, 1)
+    p["Th0"] = np.ones((1, 32, 1))
+    p["Ph0"] = np.ones((1, 64))
+    p["name"] = f"c4_thick_{n}cube_32x64"
+    return p
+
+
+def c5(n=128, steps=50):
+    """Differentiation case: 128^2, 16x32, kappa = exp(GRF), pulse, T = 1."""
+    p = _base(2, n, n, 1, 16, 32, tol=1e-6, rmax=128, steps=steps)
+    p["kappa"] = np.exp(gaussian_random_field(n, 0.1, seed=0)).reshape(-1)
+    p["X0"], p["Th0"], p["Ph0"] = gaussian_pulse_cores(p)
+    p["ckpt_every"] = 10
+    det = np.zeros((n, n))
+    det[56 * n // 128:72 * n // 128, 72 * n // 128:88 * n // 128] = 1.0  # [iy, ix]
+    p["detector"] = det.reshape(-1)
+    p["name"] = f"c5_grad_{n}sq_16x32"
+    return p
+
+
+def relaxation(kappa=1.0, ntheta=8, nphi=16, steps=300):
+    """Thermal relaxation, four cells (here 4 x 1 in 2-D, periodic)."""
+    p = _base(2, 4, 1, 1, ntheta, nphi, tol=1e-6, rmax=0, steps=steps, l=4.0)
+    p["ly"] = 1.0
+    p["bc_lo"] = [PERIODIC, PERIODIC, VACUUM]
+    p["bc_hi"] = [PERIODIC, PERIODIC, VACUUM]
+    p["material"] = COUPLED
+    p["kappa"][:] = kappa
+    p["cv"][:] = 8.0
+    p["T0"][:] = 2.0
+    Er = 1.0  # a_r * T_r^4 with T_r = 1
+    p["X0"] = np.full((4, 1), p["c"] * Er / (4 * np.pi))
+    p["Th0"] = np.ones((1, ntheta, 1))
+    p["Ph0"] = np.ones((1, nphi))
+    p["name"] = f"relaxation_kappa{kappa:g}"
+    return p
+
+
+def random_tt(ns, ntheta, nphi, r1, r2, seed, decay=None):
+    """Random TT cores (seeded); optional geometric decay of the bond-1
+    spectrum ``decay**k`` imposed through the middle core."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((ns, r1))
+    Th = rng.standard_normal((r1, ntheta, r2))
+    Ph = rng.standard_normal((r2, nphi))
+    if decay is not None:
+        Th *= (decay ** np.arange(r1))[:, None, None]
+    return X, Th, Ph
+
+
+def small_random(dim=2, nx=6, ny=5, nz=1, ntheta=4, nphi=8, r1=3, r2=2,
+                 seed=0, bc="vacuum", material=FROZEN, tol=1e-6, rmax=0):
+    """Small seeded problem for parity tests: random positive material
+    fields and random cores; ``bc`` in {vacuum, periodic, inflow}."""
+    rng = np.random.default_rng(seed)
+    p = _base(dim, nx, ny, nz if dim == 3 else 1, ntheta, nphi, tol=tol,
+              rmax=rmax, steps=3)
+    ns = p["nx"] * p["ny"] * p["nz"]
+    p["kappa"] = np.exp(rng.standard_normal(ns))
+    p["rho"] = 0.5 + rng.random(ns)
+    p["cv"] = 0.5 + rng.random(ns)
+    p["T0"] = 0.5 + 0.5 * rng.random(ns)
+    p["material"] = material
+    X, Th, Ph = random_tt(ns, ntheta, nphi, r1, r2, seed + 1000)
+    p["X0"], p["Th0"], p["Ph0"] = np.abs(X), np.abs(Th), np.abs(Ph)
+    if bc == "periodic":
+        p["bc_lo"] = [PERIODIC] * 3
+        p["bc_hi"] = [PERIODIC] * 3
+    elif bc == "inflow":
+        p["bc_lo"] = [INFLOW, INFLOW, INFLOW if dim == 3 else VACUUM]
+        p["bc_hi"] = [VACUUM, INFLOW, VACUUM]
+        faces = [0, 2, 3] + ([4] if dim == 3 else [])
+        for f in faces:
+            nface = {0: ny * p["nz"], 2: nx * p["nz"], 3: nx * p["nz"],
+                     4: nx * ny}[f]
+            p["inflow"].append((f, rng.random(nface), rng.random(ntheta),
+                                rng.random(nphi)))
+    p["name"] = f"small_{dim}d_{bc}_s{seed}"
+    return p
