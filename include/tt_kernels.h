@@ -1,0 +1,61 @@
+/*
+ * tt_kernels.h -- kernel-level entry points of libtt.so.
+ *
+ * These expose the individual contractions and the eigensolver used inside
+ * one Gram-SVD rounding (paper App. A.2) so that each can be checked
+ * against a plain reference on random inputs.  All matrix pointers are
+ * device memory, row-major float64, caller-owned.  `ws` is caller-owned
+ * device scratch of at least the bytes returned by the matching
+ * *_workspace() query.  Each call runs on `stream` (a hipStream_t, NULL =
+ * default) and returns after a stream synchronisation.  Errors:
+ * TT_ERR_INVALID_ARG (sizes, null pointers), TT_ERR_OOM (ws too small),
+ * TT_ERR_DEVICE (HIP failure); messages via tt_last_error(NULL).
+ */
+#ifndef TT_KERNELS_H
+#define TT_KERNELS_H
+
+#include "tt.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Symmetric eigendecomposition of A (n x n, lda; not modified) for
+ * 1 <= n <= 1024 (App. A.2: G = V S^2 V^T).  lam (n): eigenvalues in
+ * descending order.  V (n x n, ldv): columns = eigenvectors of the kept
+ * eigenvalues, each signed so that its largest-magnitude entry is positive.
+ * Kept: lambda > clip * n * 2^-53 * lambda_max and lambda > 0 (clip = 1 is
+ * the Gram clip rule; clip = 0 keeps every positive eigenvalue).
+ * kept (host int) receives the number kept. */
+size_t tt_kernel_eigh_workspace(int32_t n);
+tt_status tt_kernel_eigh(const double* A, int32_t n, int32_t lda, double clip, double* lam,
+                         double* V, int32_t ldv, int32_t* kept, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* G (n x n, ldg) = A^T A for A of K rows and n columns (lda >= n):
+ * the left Gram of a tall core on MFMA, split over K with a fixed-order
+ * (deterministic) reduction. */
+size_t tt_kernel_gram_workspace(int32_t K, int32_t n, int32_t lda);
+tt_status tt_kernel_gram(const double* A, int32_t K, int32_t n, int32_t lda, double* G,
+                         int32_t ldg, void* ws, size_t ws_bytes, void* stream);
+
+/* C (K x n, ldc) = A (K x k, lda) B (k x n, ldb) on MFMA (the core update
+ * A' = A P of App. A.2). */
+size_t tt_kernel_gemm_tall_workspace(void);
+tt_status tt_kernel_gemm_tall(const double* A, int32_t K, int32_t k, int32_t lda, const double* B,
+                              int32_t n, int32_t ldb, double* C, int32_t ldc, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* C (m x n, ldc) = op(A) op(B), op = transpose when ta / tb != 0; the
+ * generic rank-sized product.  ws: tt_kernel_gemm_tall_workspace() bytes. */
+tt_status tt_kernel_gemm(const double* A, int32_t lda, int32_t ta, const double* B, int32_t ldb,
+                         int32_t tb, double* C, int32_t ldc, int32_t m, int32_t n, int32_t k,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Message of the last failed kernel-level call on this thread. */
+const char* tt_kernel_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_KERNELS_H */

@@ -1,0 +1,642 @@
+// Symmetric FP64 eigensolver for the rank-sized Gram matrices of the
+// Gram-SVD truncation (App. A.2: G_A = V_A S_A^2 V_A^T, G_B = V_B S_B^2 V_B^T,
+// and the Gram of M for its SVD).
+//
+// Pipeline (one job per matrix, several jobs run side by side):
+//   1. Householder tridiagonalisation A = Q T Q^T in one 1024-thread block
+//      (the only step with O(n) sequential dependences; the matrix stays in
+//      L2 and every pass is coalesced along rows).
+//   2. Eigenpairs of T by divide and conquer from 1x1 leaves: all merges of
+//      a level run side by side, one wavefront per secular root, and the
+//      eigenvector updates are batched GEMMs.
+//   3. Back-transformation V = Q Z, one wavefront per kept vector.
+//   4. Descending order, sign gauge (largest |entry| positive), clip rule.
+#include <float.h>
+#include <string.h>
+
+#include "tt_internal.h"
+
+namespace tt {
+
+namespace {
+
+constexpr double U64 = 1.1102230246251565e-16;  // 2^-53
+
+struct EigJobs {
+  EigJob j[4];
+};
+
+struct Work {
+  double *d, *e, *tau, *w, *H, *Z;
+};
+__device__ inline Work work_of(const EigJob& J, int N) {
+  Work W;
+  W.d = J.work;
+  W.e = W.d + N;
+  W.tau = W.e + N;
+  W.w = W.tau + N;
+  W.H = W.w + N;
+  W.Z = W.H + (size_t)N * N;
+  return W;
+}
+
+// Deterministic block-wide sum (fixed combination order).
+template <int NT>
+__device__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  return s;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// 1. Householder tridiagonalisation (lower form): for k = 0..n-3, H_k =
+// I - tau_k v v^T with v = [1, x_2..]/(alpha - beta) annihilates A[k+2:, k].
+__global__ __launch_bounds__(1024) void k_sytrd(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[blockIdx.x];
+  const int n = dims[J.n_idx];
+  double* A = J.A;
+  const long long lda = J.lda;
+  Work W = work_of(J, N);
+  __shared__ double sv[1024], sw[1024], sp[4][1024], red[16];
+  __shared__ double s_tau, s_scal;
+  const int tid = threadIdx.x, cj = tid & 255, g = tid >> 8;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    const long long base = (long long)(k + 1) * lda + (k + 1);  // A22 origin
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += 1024) {
+      const double x = A[(long long)(k + 1 + i) * lda + k];
+      part += x * x;
+    }
+    const double sumsq = block_sum<1024>(part, red);
+    if (tid == 0) {
+      const double alpha = A[(long long)(k + 1) * lda + k];
+      W.d[k] = A[(long long)k * lda + k];
+      if (sumsq == 0.0) {
+        s_tau = 0.0;
+        s_scal = 0.0;
+        W.e[k] = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scal = 1.0 / (alpha - beta);
+        W.e[k] = beta;
+      }
+      W.tau[k] = s_tau;
+    }
+    __syncthreads();
+    const double tau = s_tau, scal = s_scal;
+    for (int i = tid; i < m; i += 1024) {
+      const double v = i == 0 ? 1.0 : A[(long long)(k + 1 + i) * lda + k] * scal;
+      sv[i] = v;
+      W.H[(long long)k * N + k + 1 + i] = v;
+    }
+    __syncthreads();
+    if (tau == 0.0) continue;
+    for (int j = cj; j < m; j += 256) {
+      double acc = 0.0;
+      for (int i = g; i < m; i += 4) acc += A[base + (long long)i * lda + j] * sv[i];
+      sp[g][j] = acc;
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int j = tid; j < m; j += 1024) {
+      const double p = tau * (((sp[0][j] + sp[1][j]) + sp[2][j]) + sp[3][j]);
+      sw[j] = p;
+      part += p * sv[j];
+    }
+    const double pv = block_sum<1024>(part, red);
+    const double hc = 0.5 * tau * pv;
+    for (int j = tid; j < m; j += 1024) sw[j] -= hc * sv[j];
+    __syncthreads();
+    for (int j = cj; j < m; j += 256) {
+      const double vj = sv[j], wj = sw[j];
+      for (int i = g; i < m; i += 4) {
+        double* a = A + base + (long long)i * lda + j;
+        *a -= sv[i] * wj + sw[i] * vj;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      W.d[n - 2] = A[(long long)(n - 2) * lda + (n - 2)];
+      W.e[n - 2] = A[(long long)(n - 1) * lda + (n - 2)];
+      W.tau[n - 2] = 0.0;
+    }
+    if (n >= 1) W.d[n - 1] = A[(long long)(n - 1) * lda + (n - 1)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2. Tridiagonal eigenproblem by divide and conquer (Cuppen), bottom-up from
+// 1x1 leaves.  T is torn at every off-diagonal e_m into blocks coupled by
+// rank-one terms |e_m| w w^T, w = e_m + sign(e_m) e_{m+1}; each merge of two
+// solved halves solves  D + rho z z^T  (z = last row of Q_left, sign-scaled
+// first row of Q_right).  Deflation removes tiny z_j and near-equal d_j
+// (Givens); the remaining roots come from the secular equation
+//   1 + rho sum_j z_j^2 / (d_j - lambda) = 0,
+// solved in the shifted variable lambda = d_origin + tau; the eigenvectors
+// use the Loewner-recomputed z^ so that they are orthogonal to working
+// accuracy.  Vector updates Q <- Q_rot U are batched GEMMs.
+struct DC {
+  double *lam, *Qa, *Qb, *U, *dsl, *zsl, *rc, *rs, *rtau, *zhat, *dK, *zK, *mrho;
+  int *perm, *Kslot, *rp, *rq, *ro, *mk, *mnrot, *mm2;
+};
+__host__ __device__ inline int next_pow2(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+__device__ inline DC dc_of(const Work& W, int N) {
+  const int N2 = next_pow2(N);
+  DC D;
+  double* p = W.Z;  // the D&C area starts where the inverse-iteration area was
+  D.lam = p; p += N2;
+  D.Qa = p; p += (size_t)N2 * N2;
+  D.Qb = p; p += (size_t)N2 * N2;
+  D.U = p; p += (size_t)N2 * N2;
+  double** dv[] = {&D.dsl, &D.zsl, &D.rc, &D.rs, &D.rtau, &D.zhat, &D.dK, &D.zK, &D.mrho};
+  for (double** q : dv) { *q = p; p += N2; }
+  int** iv[] = {&D.perm, &D.Kslot, &D.rp, &D.rq, &D.ro, &D.mk, &D.mnrot, &D.mm2};
+  for (int** q : iv) { *q = reinterpret_cast<int*>(p); p += N2; }
+  return D;
+}
+
+__global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[blockIdx.y];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const long long tot = (long long)N2 * N2;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / N2), j = (int)(e % N2);
+    D.Qa[e] = (i == j && i < n) ? 1.0 : 0.0;
+    D.Qb[e] = 0.0;
+  }
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < N2; i += gridDim.x * 256) {
+    double v = 0.0;
+    if (i < n) {
+      v = W.d[i];
+      if (i > 0) v -= fabs(W.e[i - 1]);
+      if (i + 1 < n) v -= fabs(W.e[i]);
+    }
+    D.lam[i] = v;
+  }
+}
+
+// Sort of two ascending halves, deflation; one wavefront per merge.
+__global__ __launch_bounds__(64) void k_dc_prep(EigJobs jobs, int* __restrict__ dims, int N, int S) {
+  const EigJob J = jobs.j[blockIdx.y];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const int m = blockIdx.x, b0 = m * 2 * S;
+  if (b0 + S >= n) {
+    if (threadIdx.x == 0) D.mk[m] = -1;
+    return;
+  }
+  const int nL = S, nR = min(S, n - b0 - S), m2 = nL + nR;
+  const double beta = W.e[b0 + S - 1];
+  const double sgn = beta < 0.0 ? -1.0 : 1.0;
+  // temporaries: z in rtau[b0..], d in zhat[b0..] (original local order)
+  for (int c = threadIdx.x; c < m2; c += 64) {
+    const double zq = c < nL ? D.Qa[(size_t)(b0 + S - 1) * N2 + b0 + c]
+                             : sgn * D.Qa[(size_t)(b0 + S) * N2 + b0 + c];
+    D.rtau[b0 + c] = zq;
+    D.zhat[b0 + c] = D.lam[b0 + c];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double* zt = D.rtau + b0;
+  const double* dt = D.zhat + b0;
+  double nz2 = 0.0;
+  for (int c = 0; c < m2; ++c) nz2 += zt[c] * zt[c];
+  const double nz = sqrt(nz2);
+  const double rho = fabs(beta) * nz2;
+  int i = 0, j = nL;
+  double dmax = 0.0;
+  for (int s = 0; s < m2; ++s) {
+    int src;
+    if (j >= m2 || (i < nL && dt[i] <= dt[j])) src = i++;
+    else src = j++;
+    D.perm[b0 + s] = src;
+    D.dsl[b0 + s] = dt[src];
+    D.zsl[b0 + s] = nz > 0.0 ? zt[src] / nz : 0.0;  // rows of orthogonal blocks: nz^2 = 2
+    dmax = fmax(dmax, fabs(dt[src]));
+  }
+  const double tol = 8.0 * U64 * fmax(dmax, rho);
+  double* ds = D.dsl + b0;
+  double* zs = D.zsl + b0;
+  int* defl = D.Kslot + b0;  // flags first, K list afterwards
+  int nrot = 0, p = -1;
+  for (int s = 0; s < m2; ++s) {
+    if (rho * fabs(zs[s]) <= tol) {
+      defl[s] = 1;
+      continue;
+    }
+    defl[s] = 0;
+    if (p >= 0) {
+      const double zp = zs[p], zq = zs[s];
+      const double r = hypot(zp, zq);
+      const double c = zq / r, sn = zp / r;
+      const double t = ds[s] - ds[p];
+      if (fabs(t * c * sn) <= tol) {
+        D.rp[b0 + nrot] = p;
+        D.rq[b0 + nrot] = s;
+        D.rc[b0 + nrot] = c;
+        D.rs[b0 + nrot] = sn;
+        ++nrot;
+        const double dp = c * c * ds[p] + sn * sn * ds[s];
+        const double dq = sn * sn * ds[p] + c * c * ds[s];
+        ds[p] = dp;
+        ds[s] = dq;
+        zs[s] = r;
+        zs[p] = 0.0;
+        defl[p] = 1;
+      }
+    }
+    p = s;
+  }
+  int nk = 0;
+  for (int s = 0; s < m2; ++s) {
+    if (!defl[s]) {
+      D.dK[b0 + nk] = ds[s];
+      D.zK[b0 + nk] = zs[s];
+      D.ro[b0 + nk] = s;  // slot of K entry (ro reused until the secular step)
+      ++nk;
+    }
+  }
+  // deflated flags are no longer needed; Kslot holds the K list
+  for (int q = 0; q < nk; ++q) D.Kslot[b0 + q] = D.ro[b0 + q];
+  D.mk[m] = nk;
+  D.mrho[m] = rho;
+  D.mnrot[m] = nrot;
+  D.mm2[m] = m2;
+}
+
+// Permute the merge block's columns into slot order and apply the Givens
+// rotations of the deflation; blocks without a partner are copied.
+__global__ __launch_bounds__(256) void k_dc_rotate(EigJobs jobs, int* __restrict__ dims, int N, int S) {
+  const EigJob J = jobs.j[blockIdx.y];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const int m = blockIdx.x, b0 = m * 2 * S;
+  if (b0 >= n) return;
+  const int nk = D.mk[m];
+  const int rend = min(b0 + 2 * S, n);
+  if (nk < 0) {
+    for (int r = b0 + threadIdx.x; r < rend; r += 256)
+      for (int c = 0; c < 2 * S && b0 + c < N2; ++c) D.Qb[(size_t)r * N2 + b0 + c] = D.Qa[(size_t)r * N2 + b0 + c];
+    return;
+  }
+  const int m2 = D.mm2[m], nrot = D.mnrot[m];
+  for (int r = b0 + threadIdx.x; r < b0 + m2; r += 256) {
+    double* qb = D.Qb + (size_t)r * N2 + b0;
+    const double* qa = D.Qa + (size_t)r * N2 + b0;
+    for (int s = 0; s < m2; ++s) qb[s] = qa[D.perm[b0 + s]];
+    for (int t = 0; t < nrot; ++t) {
+      const int p = D.rp[b0 + t], q = D.rq[b0 + t];
+      const double c = D.rc[b0 + t], sn = D.rs[b0 + t];
+      const double xp = qb[p], xq = qb[q];
+      qb[p] = c * xp - sn * xq;
+      qb[q] = sn * xp + c * xq;
+    }
+  }
+}
+
+__device__ inline double secular(const double* d, const double* z, int k, int o, double tau,
+                                 double rho, int lane) {
+  double s = 0.0;
+  const double dor = d[o];
+  for (int j = lane; j < k; j += 64) s += z[j] * z[j] / ((d[j] - dor) - tau);
+  return 1.0 + rho * wave_sum(s);
+}
+
+// Roots of the secular equation, one wavefront per root.
+__global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restrict__ dims, int N, int S) {
+  const EigJob J = jobs.j[blockIdx.z];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int m = blockIdx.y, b0 = m * 2 * S;
+  if (b0 + S >= n) return;
+  const int nk = D.mk[m];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wave;
+  if (i >= nk) return;
+  const double* d = D.dK + b0;
+  const double* z = D.zK + b0;
+  const double rho = D.mrho[m];
+  int o;
+  double lo, hi;
+  if (i < nk - 1) {
+    const double gap = d[i + 1] - d[i];
+    const double mid = 0.5 * gap;
+    const double g = secular(d, z, nk, i, mid, rho, lane);
+    // Safe brackets from the secular function itself: for the root on the
+    // origin's right, g(tau) <= 1 + 2 rho / gap - rho z_o^2 / tau, so
+    // tau* >= rho z_o^2 / (1 + 2 rho / gap); symmetrically on the left.
+    if (g >= 0.0) {
+      o = i;
+      hi = mid;
+      lo = 0.5 * rho * z[o] * z[o] / (1.0 + 2.0 * rho / gap);
+    } else {
+      o = i + 1;
+      lo = -(gap - mid);
+      hi = -0.5 * rho * z[o] * z[o] / fmax(1.0, 2.0 * rho / gap);
+    }
+  } else {
+    // last root: all other terms are negative, so tau* >= rho z_o^2
+    o = nk - 1;
+    hi = rho;
+    lo = 0.5 * rho * z[o] * z[o];
+  }
+  // an end that underflowed to zero would sit on the origin's pole
+  if (lo == 0.0) lo = hi * 0x1p-60;
+  if (hi == 0.0) hi = lo * 0x1p-60;
+  double tau;
+  const double glo = secular(d, z, nk, o, lo, rho, lane);
+  const double ghi = secular(d, z, nk, o, hi, rho, lane);
+  if (glo >= 0.0) {
+    tau = lo;
+  } else if (ghi <= 0.0) {
+    tau = hi;
+  } else {
+    for (int it = 0; it < 300; ++it) {
+      if (hi - lo <= 4.0 * U64 * fmax(fabs(lo), fabs(hi))) break;
+      double x;
+      if (lo > 0.0 && hi > 4.0 * lo) x = sqrt(lo) * sqrt(hi);
+      else if (hi < 0.0 && lo < 4.0 * hi) x = -sqrt(-lo) * sqrt(-hi);
+      else x = 0.5 * (lo + hi);
+      if (!(x > lo && x < hi)) break;
+      const double gx = secular(d, z, nk, o, x, rho, lane);
+      if (gx < 0.0) lo = x;
+      else hi = x;
+    }
+    tau = 0.5 * (lo + hi);
+  }
+  if (lane == 0) {
+    if (!(tau == tau) || tau == 0.0) {
+      atomicOr(&dims[D_FLAG], FLAG_EIG);
+      tau = o == i ? hi : lo;
+    }
+    D.ro[b0 + i] = o;
+    D.rtau[b0 + i] = tau;
+  }
+}
+
+// Loewner z^, eigenvectors of D + rho z^ z^^T, sorted output, U block.
+__global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restrict__ dims, int N, int S) {
+  const EigJob J = jobs.j[blockIdx.y];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const int m = blockIdx.x, b0 = m * 2 * S;
+  const int S2 = 2 * S;
+  double* Ub = D.U + (size_t)m * S2 * S2;
+  const int tid = threadIdx.x;
+  if (b0 >= N2) return;
+  const int nk = b0 + S < n ? D.mk[m] : -1;
+  for (long long e = tid; e < (long long)S2 * S2; e += 256) {
+    const int s = (int)(e / S2), c = (int)(e % S2);
+    Ub[e] = (nk < 0 && s == c) ? 1.0 : 0.0;
+  }
+  if (nk < 0) return;
+  __syncthreads();
+  const int m2 = D.mm2[m];
+  const double* d = D.dK + b0;
+  const double* z = D.zK + b0;
+  const double rho = D.mrho[m];
+  const int* ro = D.ro + b0;
+  const double* rt = D.rtau + b0;
+  for (int j = tid; j < nk; j += 256) {
+    double prod = -((d[j] - d[ro[j]]) - rt[j]) / rho;
+    for (int i = 0; i < nk; ++i)
+      if (i != j) prod *= ((d[j] - d[ro[i]]) - rt[i]) / (d[j] - d[i]);
+    D.zhat[b0 + j] = copysign(sqrt(fmax(prod, 0.0)), z[j]);
+  }
+  // sort all outputs: roots (tag i) and deflated slots (tag m2 + slot)
+  __shared__ double sv[1024];
+  __shared__ int st[1024];
+  __shared__ int isk[1024];
+  for (int s = tid; s < m2; s += 256) isk[s] = 0;
+  __syncthreads();
+  for (int q = tid; q < nk; q += 256) isk[D.Kslot[b0 + q]] = 1;
+  __syncthreads();
+  // deflated slots in slot order: position among deflated = s - #K slots before s
+  __shared__ int s_bad;
+  if (tid == 0) {
+    int nd = 0;
+    s_bad = 0;
+    for (int s = 0; s < m2; ++s)
+      if (!isk[s]) {
+        const double v = D.dsl[b0 + s];
+        if (!(v == v)) s_bad = 1;
+        sv[nk + nd] = v == v ? v : DBL_MAX;
+        st[nk + nd] = m2 + s;
+        ++nd;
+      }
+  }
+  __syncthreads();
+  for (int i = tid; i < nk; i += 256) {
+    const double v = d[ro[i]] + rt[i];
+    if (!(v == v)) s_bad = 1;
+    sv[i] = v == v ? v : DBL_MAX;
+    st[i] = i;
+  }
+  const int P2 = next_pow2(m2);
+  for (int e = m2 + tid; e < P2; e += 256) {
+    sv[e] = DBL_MAX;
+    st[e] = 0x7fffffff;
+  }
+  __syncthreads();
+  // bitonic sort by (value, tag)
+  for (int k2 = 2; k2 <= P2; k2 <<= 1)
+    for (int jj = k2 >> 1; jj > 0; jj >>= 1) {
+      for (int e = tid; e < P2; e += 256) {
+        const int x = e ^ jj;
+        if (x > e) {
+          const bool up = (e & k2) == 0;
+          const bool gt = sv[e] > sv[x] || (sv[e] == sv[x] && st[e] > st[x]);
+          if (gt == up) {
+            const double tv = sv[e]; sv[e] = sv[x]; sv[x] = tv;
+            const int tt2 = st[e]; st[e] = st[x]; st[x] = tt2;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  if (tid == 0 && s_bad) atomicOr(&dims[D_FLAG], FLAG_EIG);
+  for (int pos = tid; pos < m2; pos += 256) {
+    D.lam[b0 + pos] = sv[pos];
+    const int tag = st[pos];
+    if (tag < 0 || tag >= 2 * m2) {
+      atomicOr(&dims[D_FLAG], FLAG_EIG);
+    } else if (tag >= m2) {
+      Ub[(size_t)(tag - m2) * S2 + pos] = 1.0;
+    } else {
+      const int i = tag;
+      double nrm = 0.0;
+      for (int j = 0; j < nk; ++j) {
+        const double u = D.zhat[b0 + j] / ((d[j] - d[ro[i]]) - rt[i]);
+        nrm += u * u;
+      }
+      if (!(nrm > 0.0) || !(nrm < DBL_MAX)) {
+        atomicOr(&dims[D_FLAG], FLAG_EIG);
+        continue;
+      }
+      const double inv = 1.0 / sqrt(nrm);
+      for (int j = 0; j < nk; ++j) {
+        const double u = D.zhat[b0 + j] / ((d[j] - d[ro[i]]) - rt[i]);
+        Ub[(size_t)D.Kslot[b0 + j] * S2 + pos] = u * inv;
+      }
+    }
+  }
+}
+
+// Threshold of the clip rule: eigenvalues above it are kept.
+__device__ inline double keep_threshold(const EigJob& J, const double* w, int n) {
+  const double lmax = n > 0 ? w[n - 1] : 0.0;
+  return fmax(J.clip * (double)n * U64 * lmax, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// 3. Back-transformation V[:, n-1-j] = H_0 H_1 ... H_{n-3} q_j for the kept
+// eigenvectors q_j of T (columns of the D&C result).
+__global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[blockIdx.y];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + wave;
+  __shared__ double ys[4][1024];
+  if (j >= n) return;
+  const double thr = keep_threshold(J, D.lam, n);
+  if (!(D.lam[j] > thr)) return;
+  double* y = ys[wave];
+  for (int i = lane; i < n; i += 64) y[i] = D.Qa[(size_t)i * N2 + j];
+  for (int k = n - 3; k >= 0; --k) {
+    const double tau = W.tau[k];
+    if (tau == 0.0) continue;
+    const double* v = W.H + (size_t)k * N;
+    double part = 0.0;
+    for (int i = k + 1 + lane; i < n; i += 64) part += v[i] * y[i];
+    const double dot = wave_sum(part) * tau;
+    for (int i = k + 1 + lane; i < n; i += 64) y[i] -= dot * v[i];
+  }
+  const int col = n - 1 - j;
+  for (int i = lane; i < n; i += 64) J.V[(size_t)i * J.ldv + col] = y[i];
+}
+
+// ---------------------------------------------------------------------------
+// 4. Descending eigenvalues, kept count, sqrt scalings and sign gauge.
+__global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[blockIdx.x];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  __shared__ int s_kept;
+  const int tid = threadIdx.x;
+  const double thr = keep_threshold(J, D.lam, n);
+  if (tid == 0) {
+    int k = 0, bad = 0;
+    for (int j = n - 1; j >= 0; --j) {
+      if (!(D.lam[j] == D.lam[j])) bad = 1;
+      if (D.lam[j] > thr) ++k;
+      else break;
+    }
+    s_kept = k;
+    dims[J.kept_idx] = k;
+    if (bad) atomicOr(&dims[D_FLAG], FLAG_EIG);
+  }
+  __syncthreads();
+  const int kept = s_kept;
+  for (int c = tid; c < n; c += 256) {
+    const double l = D.lam[n - 1 - c];
+    J.lam[c] = l;
+    if (c < kept) {
+      const double s = sqrt(l);
+      J.sq[c] = s;
+      J.isq[c] = 1.0 / s;
+    }
+  }
+  for (int c = tid; c < kept; c += 256) {
+    double best = -1.0, val = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double v = J.V[(size_t)i * J.ldv + c];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        val = v;
+      }
+    }
+    if (val < 0.0)
+      for (int i = 0; i < n; ++i) J.V[(size_t)i * J.ldv + c] = -J.V[(size_t)i * J.ldv + c];
+  }
+}
+
+}  // namespace
+
+size_t eig_work_doubles(int N) {
+  const size_t N2 = next_pow2(N);
+  return 4 * (size_t)N + (size_t)N * N + N2 + 3 * N2 * N2 + 17 * N2 + 64;
+}
+
+void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s) {
+  if (njobs <= 0 || N <= 0) return;
+  EigJobs J;
+  for (int i = 0; i < njobs && i < 4; ++i) J.j[i] = jobs[i];
+  const int N2 = next_pow2(N);
+  k_sytrd<<<njobs, 1024, 0, s>>>(J, dims, N);
+  int ib = (int)(((long long)N2 * N2 + 255) / 256);
+  if (ib > 2048) ib = 2048;
+  k_dc_init<<<dim3(ib, njobs), 256, 0, s>>>(J, dims, N);
+  for (int S = 1; S < N; S *= 2) {
+    const int nm = (N + 2 * S - 1) / (2 * S);
+    k_dc_prep<<<dim3(nm, njobs), 64, 0, s>>>(J, dims, N, S);
+    k_dc_rotate<<<dim3(nm, njobs), 256, 0, s>>>(J, dims, N, S);
+    k_dc_secular<<<dim3((2 * S + 3) / 4, nm, njobs), 256, 0, s>>>(J, dims, N, S);
+    k_dc_vectors<<<dim3(nm, njobs), 256, 0, s>>>(J, dims, N, S);
+    for (int q = 0; q < njobs; ++q) {
+      // Q block <- Q_rot block * U block, for every merge block of this level
+      const double* wbase = jobs[q].work;
+      const size_t off_z = 4 * (size_t)N + (size_t)N * N;
+      const double* Qa = wbase + off_z + N2;
+      const double* Qb = Qa + (size_t)N2 * N2;
+      const double* U = Qb + (size_t)N2 * N2;
+      GemmDesc g;
+      memset(&g, 0, sizeof(g));
+      g.A = Qb; g.B = U; g.C = const_cast<double*>(Qa);
+      g.lda = N2; g.ldb = 2 * S; g.ldc = N2;
+      g.sA = (long long)2 * S * (N2 + 1);
+      g.sB = (long long)4 * S * S;
+      g.sC = g.sA;
+      g.m = dimc(2 * S); g.n = dimc(2 * S); g.k = dimc(2 * S);
+      g.alpha = 1.0;
+      g.cond_idx = -1;
+      const int bm = (N + 2 * S - 1) / (2 * S);
+      gemm(g, 2 * S, 2 * S, bm, dims, s);
+    }
+  }
+  k_ormtr<<<dim3((N + 3) / 4, njobs), 256, 0, s>>>(J, dims, N);
+  k_eig_final<<<njobs, 256, 0, s>>>(J, dims, N);
+}
+
+}  // namespace tt

@@ -1,0 +1,481 @@
+// Per-step kernels other than the dense contractions and eigensolves:
+//  - TT sum by core concatenation of the transport blocks (paper Sec. 4.3,
+//    Sec. 4.1 Addition): stencil blocks of the spatial core, block-diagonal
+//    middle core, stacked angular core, rank-1 inflow (Sec. 4.5) and
+//    emission (Sec. 4.4) terms;
+//  - backward-Euler absorption/emission coefficients and the per-cell
+//    Newton solve for T_dag (Sec. 3.2), always in FP64;
+//  - energy density from TT cores (Sec. 4.1 eq. tt_energy_density);
+//  - the tolerance rank rule of the Gram-SVD truncation (App. A, note on
+//    rank truncation) and the assembly of the truncated singular vectors.
+#include "tt_step.h"
+
+namespace tt {
+
+// ---------------------------------------------------------------------------
+// Spatial core of the concatenation, one block per cell row.
+__global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const double* __restrict__ X, int ldX,
+                                                    const double* __restrict__ bc_e,
+                                                    const double* __restrict__ d,
+                                                    const double* __restrict__ s,
+                                                    double* __restrict__ Xc, int ldC,
+                                                    const int* __restrict__ dims, int scaled) {
+  const int i = blockIdx.x;
+  const int r1 = dims[D_R1];
+  const int R1 = dims[D_RC1];
+  const int nstencil = G.B * r1;
+  const int ix = i % G.nx, iy = (i / G.nx) % G.ny, iz = i / (G.nx * G.ny);
+  const int coord[3] = {ix, iy, iz};
+  const double di = scaled ? d[i] : 1.0;
+  const double* xi = X + (long long)i * ldX;
+  for (int col = threadIdx.x; col < R1; col += 256) {
+    double v;
+    if (col < nstencil) {
+      const int b = col / r1, a = col - b * r1;
+      if (b == 0) {
+        v = xi[a];
+      } else {
+        const int ax = (b - 1) >> 1;
+        const bool minus = ((b - 1) & 1) == 0;
+        const int st = G.stride[ax], na = G.n[ax], ca = coord[ax];
+        double nb = 0.0;
+        if (minus) {
+          if (ca > 0) nb = X[(long long)(i - st) * ldX + a];
+          else if (G.periodic[ax]) nb = X[(long long)(i + (na - 1) * st) * ldX + a];
+          v = xi[a] - nb;
+        } else {
+          if (ca < na - 1) nb = X[(long long)(i + st) * ldX + a];
+          else if (G.periodic[ax]) nb = X[(long long)(i - (na - 1) * st) * ldX + a];
+          v = nb - xi[a];
+        }
+      }
+      v *= di;
+    } else if (col < nstencil + G.nbc) {
+      v = bc_e[(long long)(col - nstencil) * G.ns + i] * di;
+    } else {
+      v = scaled ? s[i] : 0.0;
+    }
+    Xc[(long long)i * ldC + col] = v;
+  }
+}
+
+// Scale the transport columns of an unscaled concatenation by d_i and fill
+// the emission column with s_i (coupled material, after the Newton solve).
+__global__ __launch_bounds__(256) void k_scale_xcat(StepGeom G, const double* __restrict__ d,
+                                                    const double* __restrict__ s,
+                                                    double* __restrict__ Xc, int ldC,
+                                                    const int* __restrict__ dims) {
+  const int i = blockIdx.x;
+  const int R1 = dims[D_RC1];
+  const int ntr = R1 - G.nem;
+  const double di = d[i];
+  double* row = Xc + (long long)i * ldC;
+  for (int col = threadIdx.x; col < ntr; col += 256) row[col] *= di;
+  if (G.nem && threadIdx.x == 0) row[R1 - 1] = s[i];
+}
+
+// Angular core of the concatenation: Phcat[R2c][np].
+__global__ void k_build_phcat(StepGeom G, const double* __restrict__ Ph,
+                              const double* __restrict__ pfac, const double* __restrict__ bc_p,
+                              double* __restrict__ Pc, const int* __restrict__ dims) {
+  const int r2 = dims[D_R2];
+  const int total = G.R2c * G.np;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int row = e / G.np, p = e - row * G.np;
+    const int nst = G.B * r2;
+    double v = 0.0;
+    if (row < nst) {
+      const int b = row / r2, c = row - b * r2;
+      v = pfac[b * G.np + p] * Ph[(long long)c * G.np + p];
+    } else if (row < nst + G.nbc) {
+      v = bc_p[(long long)(row - nst) * G.np + p];
+    } else if (row < nst + G.nbc + G.nem) {
+      v = 1.0;
+    }
+    Pc[e] = v;
+  }
+}
+
+// Middle core of the concatenation: Thcat[a][l][c] (R1 x nt x R2c), block
+// diagonal.  Rows a >= R1 are not written.
+__global__ void k_build_thcat(StepGeom G, const double* __restrict__ Th,
+                              const double* __restrict__ tfac, const double* __restrict__ bc_t,
+                              double* __restrict__ Tc, const int* __restrict__ dims) {
+  const int r1 = dims[D_R1], r2 = dims[D_R2], R1 = dims[D_RC1];
+  const long long total = (long long)R1 * G.nt * G.R2c;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % G.R2c);
+    const long long al = e / G.R2c;
+    const int l = (int)(al % G.nt), a = (int)(al / G.nt);
+    double v = 0.0;
+    const int nst1 = G.B * r1, nst2 = G.B * r2;
+    if (a < nst1) {
+      const int b = a / r1, ai = a - b * r1;
+      const int c0 = b * r2;
+      if (c >= c0 && c < c0 + r2)
+        v = tfac[b * G.nt + l] * Th[((long long)ai * G.nt + l) * G.r2c + (c - c0)];
+    } else if (a < nst1 + G.nbc) {
+      const int j = a - nst1;
+      if (c == nst2 + j) v = bc_t[(long long)j * G.nt + l];
+    } else {
+      if (c == nst2 + G.nbc) v = 1.0;
+    }
+    Tc[e] = v;
+  }
+}
+
+// dims after the concatenation: R1 = B r1 + n_bc + n_em, R2 likewise.
+__global__ void k_concat_dims(StepGeom G, int* __restrict__ dims) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dims[D_RC1] = G.B * dims[D_R1] + G.nbc + G.nem;
+    dims[D_RC2] = G.B * dims[D_R2] + G.nbc + G.nem;
+  }
+}
+
+// dims for rounding the stored state itself (no concatenation).
+__global__ void k_round_dims(int* __restrict__ dims) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dims[D_RC1] = dims[D_R1];
+    dims[D_RC2] = dims[D_R2];
+  }
+}
+
+// Copy Th (ld r2c) into Thcat layout (ld R2c), zero elsewhere; Ph -> Phcat.
+__global__ void k_state_as_cat(StepGeom G, const double* __restrict__ Th,
+                               const double* __restrict__ Ph, double* __restrict__ Tc,
+                               double* __restrict__ Pc, const int* __restrict__ dims) {
+  const int r1 = dims[D_R1], r2 = dims[D_R2];
+  const long long tot = (long long)r1 * G.nt * G.R2c;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % G.R2c);
+    const long long al = e / G.R2c;
+    Tc[e] = c < r2 ? Th[al * G.r2c + c] : 0.0;
+  }
+  const int tp = G.R2c * G.np;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tp; e += gridDim.x * blockDim.x)
+    Pc[e] = (e / G.np) < r2 ? Ph[e] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Energy density of a TT: z = (sum_l w_l Theta_l)(sum_p v_p Phi_p), E = X z / c.
+// pv[c] = sum_p v_p Phi[c][p]
+__global__ void k_phi_moment(const double* __restrict__ Ph, int np, const double* __restrict__ v,
+                             double* __restrict__ pv, DimExpr rows, const int* __restrict__ dims) {
+  const int r = eval_dim(dims, rows);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < r; c += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int p = 0; p < np; ++p) s += v[p] * Ph[(long long)c * np + p];
+    pv[c] = s;
+  }
+}
+// z[a] = (1/c) sum_l w_l sum_b Th[a][l][b] pv[b], a < r1 (Th ld = ldb per l)
+__global__ void k_theta_moment(const double* __restrict__ Th, int nt, int ldb,
+                               const double* __restrict__ w, const double* __restrict__ pv,
+                               double* __restrict__ z, DimExpr rows, DimExpr cols, double inv_c,
+                               const int* __restrict__ dims) {
+  const int r1 = eval_dim(dims, rows), r2 = eval_dim(dims, cols);
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < r1; a += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int l = 0; l < nt; ++l) {
+      const double* t = Th + ((long long)a * nt + l) * ldb;
+      double sl = 0.0;
+      for (int b = 0; b < r2; ++b) sl += t[b] * pv[b];
+      s += w[l] * sl;
+    }
+    z[a] = s * inv_c;
+  }
+}
+// E[i] = sum_{a < ncols} X[i][a] z[a]
+__global__ __launch_bounds__(256) void k_row_dot(const double* __restrict__ X, int ldX, int ns,
+                                                 const double* __restrict__ z, DimExpr cols,
+                                                 double* __restrict__ E,
+                                                 const int* __restrict__ dims) {
+  const int nc = eval_dim(dims, cols);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wave;
+  if (i >= ns) return;
+  const double* x = X + (long long)i * ldX;
+  double s = 0.0;
+  for (int a = lane; a < nc; a += 64) s += x[a] * z[a];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) E[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Source coefficients.  Frozen: T_dag = T.  Coupled: Newton on
+// f(T) = T - T^m + g (a_r T^4 - E*), g = c dt kappa / c_v / (1 + c dt rho kappa),
+// started at max(T^m, (max(E*,0)/a_r)^(1/4)) where f >= 0 (f increasing,
+// convex), stopping at |dT| <= 4u T (at most 50 iterations).
+__global__ void k_material(int ns, double c, double dt, double a_r, int coupled,
+                           const double* __restrict__ kappa, const double* __restrict__ rho,
+                           const double* __restrict__ cv, const double* __restrict__ T,
+                           const double* __restrict__ Estar, double* __restrict__ Tdag,
+                           double* __restrict__ d, double* __restrict__ s,
+                           int* __restrict__ dims) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+    const double rk = rho[i] * kappa[i];
+    const double di = 1.0 / (1.0 + c * dt * rk);
+    double Td = T[i];
+    if (coupled) {
+      const double g = c * dt * kappa[i] / cv[i] * di;
+      const double Es = Estar[i];
+      const double Tm = T[i];
+      double x = fmax(Tm, sqrt(sqrt(fmax(Es, 0.0) / a_r)));
+      bool ok = false;
+      for (int it = 0; it < 50; ++it) {
+        const double x3 = x * x * x;
+        const double f = x - Tm + g * (a_r * x3 * x - Es);
+        const double fp = 1.0 + 4.0 * g * a_r * x3;
+        const double dx = f / fp;
+        x -= dx;
+        if (fabs(dx) <= 4.0 * 1.1102230246251565e-16 * fabs(x + dx)) {
+          ok = true;
+          break;
+        }
+      }
+      if (!ok || !(x == x)) atomicOr(&dims[D_FLAG], FLAG_NEWTON);
+      Td = x;
+    }
+    const double T2 = Td * Td;
+    d[i] = di;
+    s[i] = di * c * dt * rk * (c / (4.0 * 3.14159265358979323846)) * a_r * T2 * T2;
+    if (Tdag) Tdag[i] = Td;
+  }
+}
+
+// Energy-conserving temperature update T += (E* - E_new) / (rho c_v).
+__global__ void k_temperature(int ns, const double* __restrict__ rho,
+                              const double* __restrict__ cv, const double* __restrict__ Estar,
+                              const double* __restrict__ Enew, double* __restrict__ T) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x)
+    T[i] += (Estar[i] - Enew[i]) / (rho[i] * cv[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Side of the Gram of M and its size.
+__global__ void k_mside(int* __restrict__ dims, int ka, int kb, int km, int side) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int a = dims[ka], b = dims[kb];
+    dims[km] = a < b ? a : b;
+    dims[side] = a <= b ? 0 : 1;
+  }
+}
+
+// Rank rule.  sigma_j = sqrt(max(lambda_j, 0)) from the Gram of M
+// (descending).  Bond 1 defines ||T||^2 = sum sigma^2 and
+// delta^2 = tol^2 ||T||^2 / 2; bond 2 reuses delta^2.
+//   r = min{k >= 1: sum_{j>k} sigma_j^2 <= delta^2}; cluster rule: extend
+//   while sigma_r - sigma_{r+1} <= eta sigma_1; cap: r = rmax and, if that
+//   splits a cluster, cut before it (keep rmax if it starts at 1).
+__global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
+                       double* __restrict__ diag, RankArgs ra) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n = dims[ra.km];
+  const int kc = dims[ra.kc];
+  double norm2 = 0.0;
+  for (int j = 0; j < n; ++j) norm2 += fmax(lam[j], 0.0);
+  double delta2;
+  if (ra.bond == 1) {
+    delta2 = ra.tol * ra.tol * norm2 / 2.0;
+    diag[G_NORM2] = norm2;
+    diag[G_DELTA2] = delta2;
+    if (!(norm2 == norm2) || norm2 > 1.79e308) atomicOr(&dims[D_FLAG], FLAG_NONFINITE);
+  } else {
+    delta2 = diag[G_DELTA2];
+  }
+  const double s0 = n > 0 ? sqrt(fmax(lam[0], 0.0)) : 0.0;
+  int r = 1, zero = 0;
+  if (n == 0 || !(s0 > 0.0) || kc == 0) {
+    zero = 1;
+  } else {
+    // tails from the smallest up: tail(k) = sum_{j >= k} sigma_j^2
+    double tail = 0.0;
+    r = n;
+    for (int k = n - 1; k >= 1; --k) {
+      tail += fmax(lam[k], 0.0);
+      if (tail <= delta2) r = k;
+      else break;
+    }
+    const double thr = ra.eta * s0;
+#define SIG(j) sqrt(fmax(lam[(j)], 0.0))
+    while (r < n && SIG(r - 1) - SIG(r) <= thr) ++r;
+    if (ra.rmax > 0 && r > ra.rmax) {
+      r = ra.rmax;
+      if (r < n && SIG(r - 1) - SIG(r) <= thr) {
+        int k = r;
+        while (k > 1 && SIG(k - 2) - SIG(k - 1) <= thr) --k;
+        r = k > 1 ? k - 1 : ra.rmax;
+      }
+    }
+    const int rep = dims[ra.replay];
+    if (rep > 0) r = rep;
+    if (r > kc) r = kc;
+    if (r < 1) r = 1;
+    double t = 0.0;
+    for (int j = r; j < n; ++j) t += fmax(lam[j], 0.0);
+    diag[ra.g_tail] = delta2 > 0.0 ? t / delta2 : 0.0;
+    diag[ra.g_sr] = SIG(r - 1);
+    diag[ra.g_srp] = r < n ? SIG(r) : 0.0;
+    if (ra.bond == 1) diag[G_S1] = s0;
+#undef SIG
+  }
+  dims[ra.rn] = r;
+  dims[ra.zero] = zero;
+  dims[ra.kea] = zero ? 0 : dims[ra.ka];
+  dims[ra.keb] = zero ? 0 : dims[ra.kb];
+  if (ra.rnt >= 0) dims[ra.rnt] = r * ra.nt;
+  diag[ra.g_rn] = r;
+  diag[ra.g_ka] = dims[ra.ka];
+  diag[ra.g_kb] = dims[ra.kb];
+}
+
+// Truncated singular vectors of M from the eigenvectors Uc of its Gram.
+// side 0 (Gram = M M^T): U~ = Uc[:, :r]; W = M^T U~ was formed by a GEMM.
+// side 1 (Gram = M^T M): V~ = Uc[:, :r]; W = V~ S~; U~ = M V~ S~^-1 was
+// formed by a GEMM and is sign-fixed here (largest |entry| positive), with
+// the same signs applied to W.
+__global__ __launch_bounds__(256) void k_svd_vectors(const double* __restrict__ Uc, int ldu,
+                                                     const double* __restrict__ sqc,
+                                                     double* __restrict__ Ur, int ldr,
+                                                     double* __restrict__ Wm, int ldw,
+                                                     const int* __restrict__ dims, int ka_i,
+                                                     int kb_i, int side_i, int rn_i,
+                                                     int zero_i) {
+  if (dims[zero_i]) return;
+  const int side = dims[side_i], r = dims[rn_i];
+  const int ka = dims[ka_i], kb = dims[kb_i];
+  const int c = blockIdx.x;
+  if (c >= r) return;
+  if (side == 0) {
+    for (int i = threadIdx.x; i < ka; i += 256) Ur[(long long)i * ldr + c] = Uc[(long long)i * ldu + c];
+    return;
+  }
+  const double sc = sqc[c];
+  for (int i = threadIdx.x; i < kb; i += 256) Wm[(long long)i * ldw + c] = Uc[(long long)i * ldu + c] * sc;
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  double best = -1.0;
+  int idx = 0x7fffffff;
+  for (int i = threadIdx.x; i < ka; i += 256) {
+    const double a = fabs(Ur[(long long)i * ldr + c]);
+    if (a > best) { best = a; idx = i; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double b2 = bv[threadIdx.x + o];
+      const int i2 = bi[threadIdx.x + o];
+      if (b2 > bv[threadIdx.x] || (b2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+        bv[threadIdx.x] = b2;
+        bi[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  const int imax = bi[0];
+  __syncthreads();
+  if (imax < ka && Ur[(long long)imax * ldr + c] < 0.0) {
+    for (int i = threadIdx.x; i < ka; i += 256) Ur[(long long)i * ldr + c] = -Ur[(long long)i * ldr + c];
+    for (int i = threadIdx.x; i < kb; i += 256) Wm[(long long)i * ldw + c] = -Wm[(long long)i * ldw + c];
+  }
+}
+
+// Close a step: new ranks become the state ranks, history, finiteness.
+__global__ void k_finish(int* __restrict__ dims, int* __restrict__ hist, int slot) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  dims[D_R1] = dims[D_R1N];
+  dims[D_R2] = dims[D_R2N];
+  if (hist && slot >= 0) {
+    hist[2 * slot] = dims[D_R1N];
+    hist[2 * slot + 1] = dims[D_R2N];
+  }
+}
+
+// Finite check of a vector (flag only).
+__global__ void k_check_finite(const double* __restrict__ x, int n, int* __restrict__ dims) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (!(x[i] == x[i]) || fabs(x[i]) > 1.79e308) {
+      atomicOr(&dims[D_FLAG], FLAG_NONFINITE);
+      return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+void launch_build_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
+                       const double* d, const double* s, double* Xc, int ldC, const int* dims,
+                       int scaled, hipStream_t st) {
+  k_build_xcat<<<G.ns, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims, scaled);
+}
+void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, double* Xc, int ldC,
+                       const int* dims, hipStream_t st) {
+  k_scale_xcat<<<G.ns, 256, 0, st>>>(G, d, s, Xc, ldC, dims);
+}
+void launch_build_phcat(const StepGeom& G, const double* Ph, const double* pfac,
+                        const double* bc_p, double* Pc, const int* dims, hipStream_t st) {
+  const int tot = G.R2c * G.np;
+  k_build_phcat<<<(tot + 255) / 256, 256, 0, st>>>(G, Ph, pfac, bc_p, Pc, dims);
+}
+void launch_build_thcat(const StepGeom& G, const double* Th, const double* tfac,
+                        const double* bc_t, double* Tc, const int* dims, hipStream_t st) {
+  const long long tot = (long long)G.R1c * G.nt * G.R2c;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 65535) blocks = 65535;
+  k_build_thcat<<<blocks, 256, 0, st>>>(G, Th, tfac, bc_t, Tc, dims);
+}
+void launch_concat_dims(const StepGeom& G, int* dims, hipStream_t st) {
+  k_concat_dims<<<1, 64, 0, st>>>(G, dims);
+}
+void launch_round_dims(int* dims, hipStream_t st) { k_round_dims<<<1, 64, 0, st>>>(dims); }
+void launch_state_as_cat(const StepGeom& G, const double* Th, const double* Ph, double* Tc,
+                         double* Pc, const int* dims, hipStream_t st) {
+  const long long tot = (long long)G.r1c * G.nt * G.R2c;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 65535) blocks = 65535;
+  if (blocks < 1) blocks = 1;
+  k_state_as_cat<<<blocks, 256, 0, st>>>(G, Th, Ph, Tc, Pc, dims);
+}
+void launch_energy(const double* X, int ldX, int ns, const double* Th, int nt, int ldb,
+                   const double* Ph, int np, const double* w, const double* v, double* pv,
+                   double* z, DimExpr r1, DimExpr r2, double inv_c, double* E, const int* dims,
+                   int rcap1, int rcap2, hipStream_t st) {
+  k_phi_moment<<<(rcap2 + 63) / 64, 64, 0, st>>>(Ph, np, v, pv, r2, dims);
+  k_theta_moment<<<(rcap1 + 63) / 64, 64, 0, st>>>(Th, nt, ldb, w, pv, z, r1, r2, inv_c, dims);
+  k_row_dot<<<(ns + 3) / 4, 256, 0, st>>>(X, ldX, ns, z, r1, E, dims);
+}
+void launch_material(int ns, double c, double dt, double a_r, int coupled, const double* kappa,
+                     const double* rho, const double* cv, const double* T, const double* Estar,
+                     double* Tdag, double* d, double* s, int* dims, hipStream_t st) {
+  k_material<<<(ns + 255) / 256, 256, 0, st>>>(ns, c, dt, a_r, coupled, kappa, rho, cv, T, Estar,
+                                               Tdag, d, s, dims);
+}
+void launch_temperature(int ns, const double* rho, const double* cv, const double* Estar,
+                        const double* Enew, double* T, hipStream_t st) {
+  k_temperature<<<(ns + 255) / 256, 256, 0, st>>>(ns, rho, cv, Estar, Enew, T);
+}
+void launch_mside(int* dims, int ka, int kb, int km, int side, hipStream_t st) {
+  k_mside<<<1, 64, 0, st>>>(dims, ka, kb, km, side);
+}
+void launch_rank(const double* lam, int* dims, double* diag, const RankArgs& ra, hipStream_t st) {
+  k_rank<<<1, 64, 0, st>>>(lam, dims, diag, ra);
+}
+void launch_svd_vectors(const double* Uc, int ldu, const double* sqc, double* Ur, int ldr,
+                        double* Wm, int ldw, const int* dims, int ka, int kb, int side, int rn,
+                        int zero, int rcap, hipStream_t st) {
+  k_svd_vectors<<<rcap, 256, 0, st>>>(Uc, ldu, sqc, Ur, ldr, Wm, ldw, dims, ka, kb, side, rn, zero);
+}
+void launch_finish(int* dims, int* hist, int slot, hipStream_t st) {
+  k_finish<<<1, 64, 0, st>>>(dims, hist, slot);
+}
+void launch_check_finite(const double* x, int n, int* dims, hipStream_t st) {
+  int blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  k_check_finite<<<blocks, 256, 0, st>>>(x, n, dims);
+}
+
+}  // namespace tt

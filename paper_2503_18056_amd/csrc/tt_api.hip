@@ -1,0 +1,855 @@
+// C ABI of the tensor-train S_N library (see include/tt.h) and the host-side
+// orchestration of one step on a single HIP stream.  All buffers are carved
+// from the caller's device workspace; ranks live in the device dims table.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/tt.h"
+#include "tt_step.h"
+
+using namespace tt;
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr double PI = 3.14159265358979323846;
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct EigSlot {
+  double *lam, *V, *sq, *isq, *work;
+};
+
+enum ProfClass { P_CONCAT, P_GRAM, P_EIG1, P_EIGM1, P_EIG2, P_EIGM2, P_XUPD, P_SMALL, P_MAT, P_STEP, P_NCLS };
+const char* kProfNames[P_NCLS] = {"concat", "gram_tall", "eig_bond1", "eig_M1", "eig_bond2",
+                                  "eig_M2", "x_update", "small_gemm", "material_energy", "step"};
+
+}  // namespace
+
+struct tt_ctx {
+  tt_config cfg;
+  hipStream_t st;
+  StepGeom G;
+  int ns, nt, np, dim, B, nbc, nem;
+  int r1c, r2c, R1c, R2c, ldX, ldC, N;
+  double dt, lam[3];
+  std::vector<double> h_rho, h_cv;
+  // device
+  int *dims, *hist, *sched;
+  double* diag;
+  double *w, *v, *tfac, *pfac, *bc_e, *bc_t, *bc_p;
+  double *kappa, *rho, *cv, *T, *d, *s, *Estar, *Enew, *Tdag;
+  double *X, *Xn, *Th, *Ph;
+  double *Thcat, *Phcat, *Xcat, *gpart;
+  double *GA, *GB1, *GR3, *GL2, *T1;
+  EigSlot E[4];
+  double *M1, *C1, *Wm1, *Ur1, *P1, *Mupd1, *Thp;
+  double *M2, *C2, *Wm2, *Ur2, *P2, *Mupd2;
+  double *pv, *z;
+  size_t ws_need;
+  int nhist = 0, nsched = 0, sched_pos = 0;
+  bool poisoned = false;
+  std::string err;
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+tt_status fail(tt_ctx* c, tt_status code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(ctx, TT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// ---- validation and sizes --------------------------------------------------
+bool validate(const tt_config* c, int n_inflow, std::string& why) {
+  if (!c) { why = "null config"; return false; }
+  if (c->dim != 2 && c->dim != 3) { why = "dim must be 2 or 3"; return false; }
+  if (c->nx < 1 || c->ny < 1 || (c->dim == 3 && c->nz < 1)) { why = "bad grid"; return false; }
+  if (c->ntheta < 2 || c->ntheta % 2) { why = "ntheta must be even"; return false; }
+  if (c->nphi < 4 || c->nphi % 4) { why = "nphi must be a multiple of 4"; return false; }
+  if (!(c->c > 0) || !(c->a_r > 0)) { why = "c and a_r must be positive"; return false; }
+  if (!(c->lx > 0) || !(c->ly > 0) || (c->dim == 3 && !(c->lz > 0))) { why = "bad extents"; return false; }
+  if (!(c->dt > 0) && !(c->cfl > 0)) { why = "need dt > 0 or cfl > 0"; return false; }
+  if (!(c->tol >= 0)) { why = "tol must be >= 0"; return false; }
+  if (c->precision != TT_FP64) { why = "only TT_FP64 is available in this build"; return false; }
+  if (c->schedule != TT_ROUND_ONCE) { why = "only TT_ROUND_ONCE is available in this build"; return false; }
+  if (c->material != TT_MAT_FROZEN && c->material != TT_MAT_COUPLED) { why = "bad material"; return false; }
+  if (c->rank_mode != TT_RANK_AUTO && c->rank_mode != TT_RANK_REPLAY) { why = "bad rank_mode"; return false; }
+  for (int a = 0; a < c->dim; ++a) {
+    const int lo = c->bc_lo[a], hi = c->bc_hi[a];
+    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) { why = "bad bc code"; return false; }
+    if ((lo == TT_BC_PERIODIC) != (hi == TT_BC_PERIODIC)) { why = "periodic bc must be paired"; return false; }
+  }
+  if (n_inflow < 0 || n_inflow > 64) { why = "n_inflow out of range"; return false; }
+  if (c->max_steps < 0) { why = "max_steps < 0"; return false; }
+  return true;
+}
+
+void geometry(tt_ctx* x, const tt_config& c, int n_inflow, int nem) {
+  x->cfg = c;
+  x->dim = c.dim;
+  const int nz = c.dim == 3 ? c.nz : 1;
+  x->ns = c.nx * c.ny * nz;
+  x->nt = c.ntheta;
+  x->np = c.nphi;
+  x->B = 1 + 2 * c.dim;
+  x->nbc = n_inflow;
+  x->nem = nem;
+  const long long big = 1LL << 30;
+  long long cap1 = std::min<long long>(x->ns, (long long)x->nt * x->np);
+  long long cap2 = std::min<long long>(x->np, (long long)x->ns * x->nt);
+  if (c.rmax > 0) { cap1 = std::min<long long>(cap1, c.rmax); cap2 = std::min<long long>(cap2, c.rmax); }
+  if (c.r1_cap > 0) cap1 = c.r1_cap;
+  if (c.r2_cap > 0) cap2 = c.r2_cap;
+  x->r1c = (int)std::min(cap1, big);
+  x->r2c = (int)std::min(cap2, big);
+  x->R1c = x->B * x->r1c + x->nbc + x->nem;
+  x->R2c = x->B * x->r2c + x->nbc + x->nem;
+  x->ldX = round_up(x->r1c, 8);
+  x->ldC = round_up(x->R1c, 8);
+  x->N = std::max(x->R1c, x->R2c);
+  const double dx = c.lx / c.nx, dy = c.ly / c.ny, dz = c.dim == 3 ? c.lz / nz : 1e300;
+  const double hmin = std::min(dx, std::min(dy, dz));
+  x->dt = c.dt > 0 ? c.dt : c.cfl * hmin / c.c;
+  x->lam[0] = c.c * x->dt / dx;
+  x->lam[1] = c.c * x->dt / dy;
+  x->lam[2] = c.dim == 3 ? c.c * x->dt / dz : 0.0;
+  StepGeom& G = x->G;
+  G.ns = x->ns; G.nx = c.nx; G.ny = c.ny; G.nz = nz;
+  G.n[0] = c.nx; G.n[1] = c.ny; G.n[2] = nz;
+  G.stride[0] = 1; G.stride[1] = c.nx; G.stride[2] = c.nx * c.ny;
+  for (int a = 0; a < 3; ++a) G.periodic[a] = a < c.dim && c.bc_lo[a] == TT_BC_PERIODIC;
+  G.nt = x->nt; G.np = x->np; G.B = x->B; G.nbc = x->nbc; G.nem = x->nem;
+  G.r1c = x->r1c; G.r2c = x->r2c; G.R1c = x->R1c; G.R2c = x->R2c;
+}
+
+size_t carve(tt_ctx* x, char* base) {
+  Carve cv{base};
+  const int ns = x->ns, nt = x->nt, np = x->np, N = x->N;
+  const int ms = std::max(1, x->cfg.max_steps);
+  x->dims = cv.take<int>(D_NDIMS);
+  x->hist = cv.take<int>(2 * (size_t)ms);
+  x->sched = cv.take<int>(2 * (size_t)ms);
+  x->diag = cv.take<double>(G_NDIAG);
+  x->w = cv.take<double>(nt);
+  x->v = cv.take<double>(np);
+  x->tfac = cv.take<double>((size_t)x->B * nt);
+  x->pfac = cv.take<double>((size_t)x->B * np);
+  x->bc_e = cv.take<double>((size_t)std::max(1, x->nbc) * ns);
+  x->bc_t = cv.take<double>((size_t)std::max(1, x->nbc) * nt);
+  x->bc_p = cv.take<double>((size_t)std::max(1, x->nbc) * np);
+  double** fields[] = {&x->kappa, &x->rho, &x->cv, &x->T, &x->d, &x->s, &x->Estar, &x->Enew, &x->Tdag};
+  for (double** f : fields) *f = cv.take<double>(ns);
+  x->X = cv.take<double>((size_t)ns * x->ldX);
+  x->Xn = cv.take<double>((size_t)ns * x->ldX);
+  x->Th = cv.take<double>((size_t)x->r1c * nt * x->r2c);
+  x->Ph = cv.take<double>((size_t)x->r2c * np);
+  x->Thcat = cv.take<double>((size_t)x->R1c * nt * x->R2c);
+  x->Phcat = cv.take<double>((size_t)x->R2c * np);
+  x->Xcat = cv.take<double>((size_t)ns * x->ldC);
+  GramPlan p1 = gram_plan(ns, x->R1c, x->ldC), p2 = gram_plan(ns, x->r1c, x->ldX);
+  x->gpart = cv.take<double>(std::max(gram_partial_doubles(p1), gram_partial_doubles(p2)));
+  x->GA = cv.take<double>((size_t)x->R1c * x->R1c);
+  x->GB1 = cv.take<double>((size_t)x->R1c * x->R1c);
+  x->GR3 = cv.take<double>((size_t)x->R2c * x->R2c);
+  x->GL2 = cv.take<double>((size_t)x->R2c * x->R2c);
+  x->T1 = cv.take<double>((size_t)x->R1c * nt * x->R2c);
+  for (int k = 0; k < 4; ++k) {
+    x->E[k].lam = cv.take<double>(N);
+    x->E[k].V = cv.take<double>((size_t)N * N);
+    x->E[k].sq = cv.take<double>(N);
+    x->E[k].isq = cv.take<double>(N);
+    x->E[k].work = cv.take<double>(eig_work_doubles(N));
+  }
+  x->M1 = cv.take<double>((size_t)x->R1c * x->R1c);
+  x->C1 = cv.take<double>((size_t)x->R1c * x->R1c);
+  x->Wm1 = cv.take<double>((size_t)x->R1c * x->r1c);
+  x->Ur1 = cv.take<double>((size_t)x->R1c * x->r1c);
+  x->P1 = cv.take<double>((size_t)x->R1c * x->r1c);
+  x->Mupd1 = cv.take<double>((size_t)x->r1c * x->R1c);
+  x->Thp = cv.take<double>((size_t)x->r1c * nt * x->R2c);
+  x->M2 = cv.take<double>((size_t)x->R2c * x->R2c);
+  x->C2 = cv.take<double>((size_t)x->R2c * x->R2c);
+  x->Wm2 = cv.take<double>((size_t)x->R2c * x->r2c);
+  x->Ur2 = cv.take<double>((size_t)x->R2c * x->r2c);
+  x->P2 = cv.take<double>((size_t)x->R2c * x->r2c);
+  x->Mupd2 = cv.take<double>((size_t)x->r2c * x->R2c);
+  x->pv = cv.take<double>(std::max(x->R2c, x->r2c) + 8);
+  x->z = cv.take<double>(std::max(x->R1c, x->r1c) + 8);
+  return cv.off + 256;
+}
+
+int emission_flag(const tt_config& c, const double* T0, int ns) {
+  if (c.material == TT_MAT_COUPLED) return 1;
+  if (!T0) return 1;
+  for (int i = 0; i < ns; ++i)
+    if (T0[i] != 0.0) return 1;
+  return 0;
+}
+
+// Quadrature (midpoint cells in mu and phi) and the rank-1 angular factors of
+// each transport block: (theta factor, phi factor) such that the block is
+// (D X) (tfac Theta) (pfac Phi).
+void host_factors(const tt_ctx* x, std::vector<double>& w, std::vector<double>& v,
+                  std::vector<double>& tf, std::vector<double>& pf, std::vector<double>& mu,
+                  std::vector<double>& sint, std::vector<double>& cosp, std::vector<double>& sinp) {
+  const int nt = x->nt, np = x->np;
+  w.assign(nt, 2.0 / nt);
+  v.assign(np, 2.0 * PI / np);
+  mu.resize(nt); sint.resize(nt); cosp.resize(np); sinp.resize(np);
+  for (int l = 0; l < nt; ++l) {
+    mu[l] = -1.0 + (l + 0.5) * (2.0 / nt);
+    sint[l] = sqrt(1.0 - mu[l] * mu[l]);
+  }
+  for (int p = 0; p < np; ++p) {
+    const double ph = (p + 0.5) * (2.0 * PI / np);
+    cosp[p] = cos(ph);
+    sinp[p] = sin(ph);
+  }
+  tf.assign((size_t)x->B * nt, 0.0);
+  pf.assign((size_t)x->B * np, 0.0);
+  for (int l = 0; l < nt; ++l) tf[l] = 1.0;
+  for (int p = 0; p < np; ++p) pf[p] = 1.0;
+  for (int a = 0; a < x->dim; ++a) {
+    const int bm = 1 + 2 * a, bp = 2 + 2 * a;
+    const double lam = x->lam[a];
+    for (int l = 0; l < nt; ++l) {
+      if (a < 2) {
+        tf[bm * nt + l] = sint[l];
+        tf[bp * nt + l] = sint[l];
+      } else {
+        tf[bm * nt + l] = std::max(mu[l], 0.0);
+        tf[bp * nt + l] = std::min(mu[l], 0.0);
+      }
+    }
+    for (int p = 0; p < np; ++p) {
+      if (a < 2) {
+        const double n = a == 0 ? cosp[p] : sinp[p];
+        pf[bm * np + p] = -lam * std::max(n, 0.0);
+        pf[bp * np + p] = -lam * std::min(n, 0.0);
+      } else {
+        pf[bm * np + p] = -lam;
+        pf[bp * np + p] = -lam;
+      }
+    }
+  }
+}
+
+std::vector<int> face_cells(const tt_ctx* x, int face) {
+  const int nx = x->G.nx, ny = x->G.ny, nz = x->G.nz;
+  const int axis = face / 2, hi = face % 2;
+  std::vector<int> out;
+  if (axis == 0) {
+    const int ix = hi ? nx - 1 : 0;
+    for (int iz = 0; iz < nz; ++iz)
+      for (int iy = 0; iy < ny; ++iy) out.push_back(ix + nx * (iy + ny * iz));
+  } else if (axis == 1) {
+    const int iy = hi ? ny - 1 : 0;
+    for (int iz = 0; iz < nz; ++iz)
+      for (int ix = 0; ix < nx; ++ix) out.push_back(ix + nx * (iy + ny * iz));
+  } else {
+    const int iz = hi ? nz - 1 : 0;
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix) out.push_back(ix + nx * (iy + ny * iz));
+  }
+  return out;
+}
+
+// ---- profiling -------------------------------------------------------------
+// Each timed region reserves one (start, end) event pair on the context's
+// stream; tt_profile_read sums the elapsed times per class.
+long prof_begin(tt_ctx* c, int cls) {
+  if (!c->prof) return -1;
+  if (c->ev_used >= c->ev.size()) {
+    if (c->ev.size() >= 200000) return -1;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) {
+      hipEventDestroy(a);
+      return -1;
+    }
+    c->ev.push_back({cls, {a, b}});
+  }
+  const long k = (long)c->ev_used++;
+  c->ev[k].first = cls;
+  hipEventRecord(c->ev[k].second.first, c->st);
+  return k;
+}
+void prof_end(tt_ctx* c, long k) {
+  if (k < 0) return;
+  hipEventRecord(c->ev[k].second.second, c->st);
+}
+struct Prof {
+  tt_ctx* c;
+  long k;
+  Prof(tt_ctx* c_, int cls) : c(c_), k(prof_begin(c_, cls)) {}
+  ~Prof() { prof_end(c, k); }
+};
+
+// ---- GEMM helpers ----------------------------------------------------------
+GemmDesc gd(const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C, int ldc,
+            DimExpr m, DimExpr n, DimExpr k) {
+  GemmDesc g;
+  memset(&g, 0, sizeof(g));
+  g.A = A; g.B = B; g.C = C;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.transA = ta; g.transB = tb;
+  g.m = m; g.n = n; g.k = k;
+  g.alpha = 1.0; g.beta = 0.0;
+  g.cond_idx = -1;
+  return g;
+}
+
+// One Gram-SVD truncation of the SVD of M given the eigen-decompositions of
+// both Gram matrices in slots ea (A side) and eb (B side); writes P (R x r')
+// and M_upd (r' x R).
+void truncate_bond(tt_ctx* c, int bond, const EigSlot& ea, const EigSlot& eb, EigSlot& em,
+                   double* M, double* Cm, double* Wm, double* Ur, double* P, double* Mupd,
+                   int Rcap, int rcap, int Rdim, double tol, int rmax) {
+  hipStream_t s = c->st;
+  const int ka = bond == 1 ? D_KA1 : D_KA2, kb = bond == 1 ? D_KB1 : D_KB2;
+  const int km = bond == 1 ? D_KM1 : D_KM2, side = bond == 1 ? D_SIDE1 : D_SIDE2;
+  const int rn = bond == 1 ? D_R1N : D_R2N, zero = bond == 1 ? D_ZERO1 : D_ZERO2;
+  const int kea = bond == 1 ? D_KEA1 : D_KEA2, keb = bond == 1 ? D_KEB1 : D_KEB2;
+  const int kc = bond == 1 ? D_KC1 : D_KC2;
+  const int N = c->N;
+  launch_mside(c->dims, ka, kb, km, side, s);
+  {
+    Prof p(c, P_SMALL);
+    GemmDesc g = gd(ea.V, N, 1, eb.V, N, 0, M, Rcap, dimv(ka), dimv(kb), dimv(Rdim));
+    g.rowscale = ea.sq;
+    g.colscale = eb.sq;
+    gemm(g, Rcap, Rcap, 1, c->dims, s);
+    GemmDesc g0 = gd(M, Rcap, 0, M, Rcap, 1, Cm, Rcap, dimv(km), dimv(km), dimv(kb));
+    g0.cond_idx = side; g0.cond_val = 0;
+    gemm(g0, Rcap, Rcap, 1, c->dims, s);
+    GemmDesc g1 = gd(M, Rcap, 1, M, Rcap, 0, Cm, Rcap, dimv(km), dimv(km), dimv(ka));
+    g1.cond_idx = side; g1.cond_val = 1;
+    gemm(g1, Rcap, Rcap, 1, c->dims, s);
+  }
+  {
+    Prof p(c, bond == 1 ? P_EIGM1 : P_EIGM2);
+    EigJob j{Cm, Rcap, km, em.lam, em.V, N, em.sq, em.isq, kc, 0.0, em.work};
+    eig_batched(&j, 1, std::min(Rcap, N), c->dims, s);
+  }
+  RankArgs ra;
+  ra.bond = bond; ra.km = km; ra.kc = kc; ra.ka = ka; ra.kb = kb;
+  ra.rn = rn; ra.zero = zero; ra.kea = kea; ra.keb = keb;
+  ra.replay = bond == 1 ? D_REPLAY1 : D_REPLAY2;
+  ra.rnt = bond == 1 ? D_R1NT : -1;
+  ra.nt = c->nt;
+  ra.tol = tol;
+  ra.eta = 1e-12;
+  ra.rmax = std::min(rmax > 0 ? rmax : rcap, rcap);
+  ra.g_tail = bond == 1 ? G_TAIL1 : G_TAIL2;
+  ra.g_sr = bond == 1 ? G_SR1 : G_SR2;
+  ra.g_srp = bond == 1 ? G_SR1P : G_SR2P;
+  ra.g_rn = bond == 1 ? G_R1N : G_R2N;
+  ra.g_ka = bond == 1 ? G_KA1 : G_KA2;
+  ra.g_kb = bond == 1 ? G_KB1 : G_KB2;
+  launch_rank(em.lam, c->dims, c->diag, ra, s);
+  Prof p(c, P_SMALL);
+  // side 0: W = M^T U~ ; side 1: U~ = M V~ S~^-1
+  GemmDesc g0 = gd(M, Rcap, 1, em.V, N, 0, Wm, rcap, dimv(kb), dimv(rn), dimv(ka));
+  g0.cond_idx = side; g0.cond_val = 0;
+  gemm(g0, Rcap, rcap, 1, c->dims, s);
+  GemmDesc g1 = gd(M, Rcap, 0, em.V, N, 0, Ur, rcap, dimv(ka), dimv(rn), dimv(kb));
+  g1.cond_idx = side; g1.cond_val = 1;
+  g1.colscale = em.isq;
+  gemm(g1, Rcap, rcap, 1, c->dims, s);
+  launch_svd_vectors(em.V, N, em.sq, Ur, rcap, Wm, rcap, c->dims, ka, kb, side, rn, zero, rcap, s);
+  // P = V_A S_A^-1 U~  (R x r');  M_upd = (V_B S_B^-1 V~ S~)^T  (r' x R)
+  GemmDesc gp = gd(ea.V, N, 0, Ur, rcap, 0, P, rcap, dimv(Rdim), dimv(rn), dimv(kea));
+  gp.kscale = ea.isq;
+  gemm(gp, Rcap, rcap, 1, c->dims, s);
+  GemmDesc gm = gd(Wm, rcap, 1, eb.V, N, 1, Mupd, Rcap, dimv(rn), dimv(Rdim), dimv(keb));
+  gm.kscale = eb.isq;
+  gemm(gm, rcap, Rcap, 1, c->dims, s);
+}
+
+// Gram-SVD rounding (App. A Algorithm 1, d = 3) of the TT held in
+// (xc, ldxc) / Thcat / Phcat with concatenated ranks dims[RC1], dims[RC2].
+void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol, int rmax) {
+  hipStream_t s = c->st;
+  const int nt = c->nt, np = c->np, R1c = c->R1c, R2c = c->R2c, N = c->N;
+  {
+    Prof p(c, P_SMALL);
+    // backward sweep Grams: G_R3 = Phcat Phcat^T ; G_B1 = sum_l Thcat_l G_R3 Thcat_l^T
+    gemm(gd(c->Phcat, np, 0, c->Phcat, np, 1, c->GR3, R2c, dimv(D_RC2), dimv(D_RC2), dimc(np)),
+         R2c, R2c, 1, c->dims, s);
+    gemm(gd(c->Thcat, R2c, 0, c->GR3, R2c, 0, c->T1, R2c, dimv(D_RC1, nt), dimv(D_RC2), dimv(D_RC2)),
+         R1c * nt, R2c, 1, c->dims, s);
+    gemm(gd(c->T1, nt * R2c, 0, c->Thcat, nt * R2c, 1, c->GB1, R1c, dimv(D_RC1), dimv(D_RC1),
+            dimc(nt * R2c)),
+         R1c, R1c, 1, c->dims, s);
+  }
+  {
+    Prof p(c, P_GRAM);
+    GramPlan plan = gram_plan(c->ns, ncap1, ldxc);
+    gram_tall(plan, xc, dimv(D_RC1), c->gpart, c->GA, R1c, c->dims, s);
+  }
+  {
+    Prof p(c, P_EIG1);
+    EigJob jobs[3] = {
+        {c->GA, R1c, D_RC1, c->E[0].lam, c->E[0].V, N, c->E[0].sq, c->E[0].isq, D_KA1, 1.0, c->E[0].work},
+        {c->GB1, R1c, D_RC1, c->E[1].lam, c->E[1].V, N, c->E[1].sq, c->E[1].isq, D_KB1, 1.0, c->E[1].work},
+        {c->GR3, R2c, D_RC2, c->E[2].lam, c->E[2].V, N, c->E[2].sq, c->E[2].isq, D_KB2, 1.0, c->E[2].work}};
+    eig_batched(jobs, 3, N, c->dims, s);
+  }
+  truncate_bond(c, 1, c->E[0], c->E[1], c->E[3], c->M1, c->C1, c->Wm1, c->Ur1, c->P1, c->Mupd1,
+                R1c, c->r1c, D_RC1, tol, rmax);
+  {
+    Prof p(c, P_XUPD);
+    gemm_tall(c->ns, xc, ldxc, c->P1, c->r1c, c->Xn, c->ldX, dimv(D_RC1), dimv(D_R1N), R1c,
+              c->r1c, c->dims, s);
+  }
+  {
+    Prof p(c, P_SMALL);
+    gemm(gd(c->Mupd1, R1c, 0, c->Thcat, nt * R2c, 0, c->Thp, nt * R2c, dimv(D_R1N), dimc(nt * R2c),
+            dimv(D_RC1)),
+         c->r1c, nt * R2c, 1, c->dims, s);
+    // bond 2: G_A2 = sum_l Theta'_l^T Theta'_l
+    gemm(gd(c->Thp, R2c, 1, c->Thp, R2c, 0, c->GL2, R2c, dimv(D_RC2), dimv(D_RC2), dimv(D_R1NT)),
+         R2c, R2c, 1, c->dims, s);
+  }
+  {
+    Prof p(c, P_EIG2);
+    EigJob j = {c->GL2, R2c, D_RC2, c->E[0].lam, c->E[0].V, N, c->E[0].sq, c->E[0].isq, D_KA2, 1.0, c->E[0].work};
+    eig_batched(&j, 1, N, c->dims, s);
+  }
+  truncate_bond(c, 2, c->E[0], c->E[2], c->E[1], c->M2, c->C2, c->Wm2, c->Ur2, c->P2, c->Mupd2,
+                R2c, c->r2c, D_RC2, tol, rmax);
+  {
+    Prof p(c, P_SMALL);
+    gemm(gd(c->Thp, R2c, 0, c->P2, c->r2c, 0, c->Th, c->r2c, dimv(D_R1NT), dimv(D_R2N), dimv(D_RC2)),
+         c->r1c * nt, c->r2c, 1, c->dims, s);
+    gemm(gd(c->Mupd2, R2c, 0, c->Phcat, np, 0, c->Ph, np, dimv(D_R2N), dimc(np), dimv(D_RC2)),
+         c->r2c, np, 1, c->dims, s);
+  }
+}
+
+__global__ void k_set_replay(int* dims, const int* sched, int k, int n) {
+  if (threadIdx.x == 0) {
+    dims[D_REPLAY1] = k < n ? sched[2 * k] : 0;
+    dims[D_REPLAY2] = k < n ? sched[2 * k + 1] : 0;
+  }
+}
+
+tt_status check_flags(tt_ctx* c) {
+  int flag = 0;
+  HIPCHK(c, hipMemcpyAsync(&flag, c->dims + D_FLAG, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (flag) {
+    c->poisoned = true;
+    std::string m = "numerical failure:";
+    if (flag & FLAG_NONFINITE) m += " non-finite state";
+    if (flag & FLAG_NEWTON) m += " Newton did not converge";
+    if (flag & FLAG_EIG) m += " eigensolver produced NaN";
+    return fail(c, TT_ERR_NUMERIC, m);
+  }
+  return TT_OK;
+}
+
+void energy_of_state(tt_ctx* c, double* E) {
+  launch_energy(c->X, c->ldX, c->ns, c->Th, c->nt, c->r2c, c->Ph, c->np, c->w, c->v, c->pv, c->z,
+                dimv(D_R1), dimv(D_R2), 1.0 / c->cfg.c, E, c->dims, c->r1c, c->r2c, c->st);
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+size_t tt_workspace_bytes(const tt_config* cfg, int32_t n_inflow) {
+  std::string why;
+  if (!validate(cfg, n_inflow, why)) {
+    g_err = why;
+    return 0;
+  }
+  tt_ctx tmp;
+  geometry(&tmp, *cfg, n_inflow, 1);
+  if (tmp.N > 1024) {
+    g_err = "concatenated rank capacity above 1024 (lower rmax)";
+    return 0;
+  }
+  return carve(&tmp, nullptr);
+}
+
+tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho, const double* cv,
+                    const double* T0, const tt_inflow* inflow, int32_t n_inflow, const double* X0,
+                    const double* Th0, const double* Ph0, int32_t r1, int32_t r2,
+                    void* dev_workspace, size_t ws_bytes, void* hip_stream, tt_ctx** out) {
+  if (!out) return fail(nullptr, TT_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  std::string why;
+  if (!validate(cfg, n_inflow, why)) return fail(nullptr, TT_ERR_INVALID_ARG, why);
+  if (!kappa || !T0 || !X0 || !Th0 || !Ph0 || (n_inflow > 0 && !inflow))
+    return fail(nullptr, TT_ERR_INVALID_ARG, "null input array");
+  tt_ctx* c = new tt_ctx();
+  const int nz = cfg->dim == 3 ? cfg->nz : 1;
+  const int ns = cfg->nx * cfg->ny * nz;
+  geometry(c, *cfg, n_inflow, 1);  // emission slot always reserved
+  const int nem = emission_flag(*cfg, T0, ns);
+  c->nem = nem;
+  c->G.nem = nem;
+  c->st = (hipStream_t)hip_stream;
+  for (int k = 0; k < n_inflow; ++k) {
+    const int f = inflow[k].face;
+    if (f < 0 || f >= 2 * cfg->dim || !inflow[k].face_w || !inflow[k].theta_w || !inflow[k].phi_w) {
+      delete c;
+      return fail(nullptr, TT_ERR_INVALID_ARG, "bad inflow term");
+    }
+    const int bc = (f % 2) ? cfg->bc_hi[f / 2] : cfg->bc_lo[f / 2];
+    if (bc != TT_BC_INFLOW) {
+      delete c;
+      return fail(nullptr, TT_ERR_INVALID_ARG, "inflow term on a face whose bc is not TT_BC_INFLOW");
+    }
+  }
+  if (r1 < 1 || r2 < 1 || r1 > c->r1c || r2 > c->r2c) {
+    delete c;
+    return fail(nullptr, TT_ERR_INVALID_ARG, "initial ranks exceed the rank capacity");
+  }
+  if (c->N > 1024) {
+    delete c;
+    return fail(nullptr, TT_ERR_INVALID_ARG, "concatenated rank capacity above 1024 (lower rmax)");
+  }
+  c->ws_need = carve(c, nullptr);
+  if (!dev_workspace || ws_bytes < c->ws_need) {
+    delete c;
+    return fail(nullptr, TT_ERR_OOM, "workspace too small: need " + std::to_string(tt_workspace_bytes(cfg, n_inflow)) + " bytes");
+  }
+  carve(c, (char*)dev_workspace);
+  hipStream_t s = c->st;
+  HIPCHK(nullptr, hipMemsetAsync(dev_workspace, 0, c->ws_need, s));
+  std::vector<double> w, v, tf, pf, mu, sint, cosp, sinp;
+  host_factors(c, w, v, tf, pf, mu, sint, cosp, sinp);
+  HIPCHK(nullptr, hipMemcpyAsync(c->w, w.data(), w.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(nullptr, hipMemcpyAsync(c->v, v.data(), v.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(nullptr, hipMemcpyAsync(c->tfac, tf.data(), tf.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(nullptr, hipMemcpyAsync(c->pfac, pf.data(), pf.size() * 8, hipMemcpyHostToDevice, s));
+  // inflow rank-1 terms: e (x) tpart (x) ppart
+  std::vector<double> be((size_t)std::max(1, n_inflow) * ns, 0.0), bt((size_t)std::max(1, n_inflow) * c->nt, 0.0),
+      bp((size_t)std::max(1, n_inflow) * c->np, 0.0);
+  for (int k = 0; k < n_inflow; ++k) {
+    const int f = inflow[k].face, a = f / 2, hi = f % 2;
+    std::vector<int> cells = face_cells(c, f);
+    for (size_t q = 0; q < cells.size(); ++q) be[(size_t)k * ns + cells[q]] = inflow[k].face_w[q];
+    const double lam = c->lam[a];
+    for (int l = 0; l < c->nt; ++l) {
+      double tfv = a < 2 ? sint[l] : (hi ? std::min(mu[l], 0.0) : std::max(mu[l], 0.0));
+      bt[(size_t)k * c->nt + l] = tfv * inflow[k].theta_w[l];
+    }
+    for (int p = 0; p < c->np; ++p) {
+      double pfv;
+      if (a < 2) {
+        const double n = a == 0 ? cosp[p] : sinp[p];
+        pfv = hi ? -lam * std::min(n, 0.0) : lam * std::max(n, 0.0);
+      } else {
+        pfv = hi ? -lam : lam;
+      }
+      bp[(size_t)k * c->np + p] = pfv * inflow[k].phi_w[p];
+    }
+  }
+  if (n_inflow > 0) {
+    HIPCHK(nullptr, hipMemcpyAsync(c->bc_e, be.data(), be.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(nullptr, hipMemcpyAsync(c->bc_t, bt.data(), bt.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(nullptr, hipMemcpyAsync(c->bc_p, bp.data(), bp.size() * 8, hipMemcpyHostToDevice, s));
+  }
+  c->h_rho.assign(ns, 1.0);
+  c->h_cv.assign(ns, 1.0);
+  if (rho) std::copy(rho, rho + ns, c->h_rho.begin());
+  if (cv) std::copy(cv, cv + ns, c->h_cv.begin());
+  HIPCHK(nullptr, hipMemcpyAsync(c->kappa, kappa, ns * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(nullptr, hipMemcpyAsync(c->rho, c->h_rho.data(), ns * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(nullptr, hipMemcpyAsync(c->cv, c->h_cv.data(), ns * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(nullptr, hipMemcpyAsync(c->T, T0, ns * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(nullptr, hipStreamSynchronize(s));
+  const int32_t rr[2] = {r1, r2};
+  tt_status st = tt_set_cores(c, X0, Th0, Ph0, rr);
+  if (st != TT_OK) {
+    g_err = c->err;
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TT_OK;
+}
+
+tt_status tt_set_cores(tt_ctx* c, const double* X, const double* Th, const double* Ph,
+                       const int32_t r[2]) {
+  if (!c || !X || !Th || !Ph || !r) return fail(c, TT_ERR_INVALID_ARG, "null argument");
+  if (r[0] < 1 || r[1] < 1 || r[0] > c->r1c || r[1] > c->r2c)
+    return fail(c, TT_ERR_INVALID_ARG, "ranks exceed the rank capacity");
+  hipStream_t s = c->st;
+  HIPCHK(c, hipMemsetAsync(c->X, 0, (size_t)c->ns * c->ldX * 8, s));
+  HIPCHK(c, hipMemcpy2DAsync(c->X, c->ldX * 8, X, r[0] * 8, r[0] * 8, c->ns, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemsetAsync(c->Th, 0, (size_t)c->r1c * c->nt * c->r2c * 8, s));
+  HIPCHK(c, hipMemcpy2DAsync(c->Th, c->r2c * 8, Th, r[1] * 8, r[1] * 8, (size_t)r[0] * c->nt,
+                             hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->Ph, Ph, (size_t)r[1] * c->np * 8, hipMemcpyHostToDevice, s));
+  int hd[D_NDIMS];
+  memset(hd, 0, sizeof(hd));
+  hd[D_R1] = r[0];
+  hd[D_R2] = r[1];
+  HIPCHK(c, hipMemcpyAsync(c->dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  // frozen material: the source coefficients never change
+  launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, c->rho, c->cv, c->T, c->Estar,
+                  c->Tdag, c->d, c->s, c->dims, s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->poisoned = false;
+  c->nhist = 0;
+  c->sched_pos = 0;
+  return TT_OK;
+}
+
+tt_status tt_step(tt_ctx* c, int32_t nsteps) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  if (c->poisoned) return fail(c, TT_ERR_STATE, "context poisoned by an earlier numerical failure");
+  if (nsteps < 0) return fail(c, TT_ERR_INVALID_ARG, "nsteps < 0");
+  hipStream_t s = c->st;
+  const tt_config& cf = c->cfg;
+  const bool coupled = cf.material == TT_MAT_COUPLED;
+  for (int m = 0; m < nsteps; ++m) {
+    Prof pstep(c, P_STEP);
+    if (cf.rank_mode == TT_RANK_REPLAY) {
+      k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->sched_pos, c->nsched);
+      c->sched_pos++;
+    }
+    {
+      Prof p(c, P_CONCAT);
+      launch_concat_dims(c->G, c->dims, s);
+      launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
+      launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
+      launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
+                        coupled ? 0 : 1, s);
+    }
+    if (coupled) {
+      Prof p(c, P_MAT);
+      // E* = (1/c) X_tr z over the transport columns (emission column excluded)
+      launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w, c->v,
+                    c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c, c->Estar,
+                    c->dims, c->R1c, c->R2c, s);
+      launch_material(c->ns, cf.c, c->dt, cf.a_r, 1, c->kappa, c->rho, c->cv, c->T, c->Estar,
+                      c->Tdag, c->d, c->s, c->dims, s);
+      launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
+    }
+    round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
+    launch_finish(c->dims, c->hist, c->nhist < std::max(1, cf.max_steps) ? c->nhist : -1, s);
+    c->nhist = std::min(c->nhist + 1, std::max(1, cf.max_steps));
+    std::swap(c->X, c->Xn);
+    if (coupled) {
+      Prof p(c, P_MAT);
+      energy_of_state(c, c->Enew);
+      launch_temperature(c->ns, c->rho, c->cv, c->Estar, c->Enew, c->T, s);
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  launch_check_finite(c->Ph, c->np, c->dims, s);
+  return check_flags(c);
+}
+
+tt_status tt_round(tt_ctx* c, double tol, int32_t rmax, int32_t ranks_out[2]) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  if (c->poisoned) return fail(c, TT_ERR_STATE, "context poisoned");
+  if (!(tol >= 0)) return fail(c, TT_ERR_INVALID_ARG, "tol must be >= 0");
+  hipStream_t s = c->st;
+  if (c->cfg.rank_mode == TT_RANK_REPLAY) {
+    k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->sched_pos, c->nsched);
+    c->sched_pos++;
+  }
+  launch_round_dims(c->dims, s);
+  launch_state_as_cat(c->G, c->Th, c->Ph, c->Thcat, c->Phcat, c->dims, s);
+  round_pipeline(c, c->X, c->ldX, c->r1c, tol, rmax);
+  launch_finish(c->dims, nullptr, -1, s);
+  std::swap(c->X, c->Xn);
+  HIPCHK(c, hipGetLastError());
+  tt_status st = check_flags(c);
+  if (st != TT_OK) return st;
+  if (ranks_out) {
+    int r[2];
+    HIPCHK(c, hipMemcpy(r, c->dims, 2 * sizeof(int), hipMemcpyDeviceToHost));
+    ranks_out[0] = r[0];
+    ranks_out[1] = r[1];
+  }
+  return TT_OK;
+}
+
+tt_status tt_energy(tt_ctx* c, double* E_dev, double* rad_total, double* mat_total) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  hipStream_t s = c->st;
+  double* E = E_dev ? E_dev : c->Enew;
+  energy_of_state(c, E);
+  HIPCHK(c, hipGetLastError());
+  const double dV = (c->cfg.lx / c->cfg.nx) * (c->cfg.ly / c->cfg.ny) *
+                    (c->cfg.dim == 3 ? c->cfg.lz / c->cfg.nz : 1.0);
+  if (rad_total || mat_total) {
+    std::vector<double> hE(c->ns), hT(c->ns);
+    HIPCHK(c, hipMemcpyAsync(hE.data(), E, c->ns * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(hT.data(), c->T, c->ns * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double er = 0.0, em = 0.0;
+    for (int i = 0; i < c->ns; ++i) {
+      er += hE[i];
+      em += c->h_rho[i] * c->h_cv[i] * hT[i];
+    }
+    if (rad_total) *rad_total = er * dV;
+    if (mat_total) *mat_total = em * dV;
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+tt_status tt_grad(tt_ctx* c, const double* detector_w, double loss_bar, double* loss_out,
+                  double* dkappa_dev) {
+  (void)detector_w; (void)loss_bar; (void)loss_out; (void)dkappa_dev;
+  return fail(c, TT_ERR_STATE, "tt_grad: no tape recorded (adjoint not available in this build)");
+}
+
+tt_status tt_set_kappa(tt_ctx* c, const double* kappa_dev) {
+  if (!c || !kappa_dev) return fail(c, TT_ERR_INVALID_ARG, "null argument");
+  HIPCHK(c, hipMemcpyAsync(c->kappa, kappa_dev, c->ns * 8, hipMemcpyDeviceToDevice, c->st));
+  launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, c->rho, c->cv, c->T, c->Estar,
+                  c->Tdag, c->d, c->s, c->dims, c->st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return TT_OK;
+}
+
+tt_status tt_get_cores(tt_ctx* c, double* X, double* Th, double* Ph, int32_t r[2]) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  int rr[2];
+  HIPCHK(c, hipMemcpyAsync(rr, c->dims, 2 * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (r) { r[0] = rr[0]; r[1] = rr[1]; }
+  hipStream_t s = c->st;
+  if (X) HIPCHK(c, hipMemcpy2DAsync(X, rr[0] * 8, c->X, c->ldX * 8, rr[0] * 8, c->ns, hipMemcpyDeviceToHost, s));
+  if (Th)
+    HIPCHK(c, hipMemcpy2DAsync(Th, rr[1] * 8, c->Th, c->r2c * 8, rr[1] * 8, (size_t)rr[0] * c->nt,
+                               hipMemcpyDeviceToHost, s));
+  if (Ph) HIPCHK(c, hipMemcpyAsync(Ph, c->Ph, (size_t)rr[1] * c->np * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+tt_status tt_get_temperature(tt_ctx* c, double* T) {
+  if (!c || !T) return fail(c, TT_ERR_INVALID_ARG, "null argument");
+  HIPCHK(c, hipMemcpyAsync(T, c->T, c->ns * 8, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return TT_OK;
+}
+
+tt_status tt_get_rank_history(tt_ctx* c, int32_t* buf, int32_t cap, int32_t* n) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  if (n) *n = c->nhist;
+  const int k = std::min(cap, c->nhist);
+  if (buf && k > 0) {
+    HIPCHK(c, hipMemcpyAsync(buf, c->hist, 2 * k * sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  return TT_OK;
+}
+
+tt_status tt_set_rank_schedule(tt_ctx* c, const int32_t* r1r2, int32_t nroundings) {
+  if (!c || (nroundings > 0 && !r1r2)) return fail(c, TT_ERR_INVALID_ARG, "null argument");
+  if (nroundings < 0 || nroundings > std::max(1, c->cfg.max_steps))
+    return fail(c, TT_ERR_INVALID_ARG, "schedule longer than max_steps");
+  for (int k = 0; k < 2 * nroundings; ++k)
+    if (r1r2[k] < 1 || r1r2[k] > (k % 2 ? c->r2c : c->r1c))
+      return fail(c, TT_ERR_INVALID_ARG, "scheduled rank exceeds the rank capacity");
+  if (nroundings > 0)
+    HIPCHK(c, hipMemcpyAsync(c->sched, r1r2, 2 * nroundings * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->nsched = nroundings;
+  c->sched_pos = 0;
+  return TT_OK;
+}
+
+tt_status tt_get_round_info(tt_ctx* c, double out[16]) {
+  if (!c || !out) return fail(c, TT_ERR_INVALID_ARG, "null argument");
+  double dg[G_NDIAG];
+  HIPCHK(c, hipMemcpyAsync(dg, c->diag, sizeof(dg), hipMemcpyDeviceToHost, c->st));
+  int dm[D_NDIMS];
+  HIPCHK(c, hipMemcpyAsync(dm, c->dims, sizeof(dm), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  out[0] = dg[G_NORM2]; out[1] = dg[G_DELTA2];
+  out[2] = dm[D_KA1]; out[3] = dm[D_KB1]; out[4] = dm[D_KA2]; out[5] = dm[D_KB2];
+  out[6] = dm[D_R1N]; out[7] = dm[D_R2N];
+  out[8] = dg[G_TAIL1]; out[9] = dg[G_TAIL2];
+  out[10] = dg[G_S1]; out[11] = dg[G_SR1]; out[12] = dg[G_SR1P];
+  out[13] = dg[G_SR2]; out[14] = dg[G_SR2P]; out[15] = dm[D_RC1];
+  return TT_OK;
+}
+
+tt_status tt_profile_enable(tt_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->prof = enable != 0;
+  c->ev_used = 0;
+  return TT_OK;
+}
+
+tt_status tt_profile_read(tt_ctx* c, double* ms, int32_t* count, const char** names, int32_t cap,
+                          int32_t* n) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  double tot[P_NCLS] = {0};
+  int cnt[P_NCLS] = {0};
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, c->ev[k].second.first, c->ev[k].second.second) == hipSuccess) {
+      tot[c->ev[k].first] += t;
+      cnt[c->ev[k].first] += 1;
+    }
+  }
+  const int k = std::min<int>(cap, P_NCLS);
+  for (int i = 0; i < k; ++i) {
+    if (ms) ms[i] = tot[i];
+    if (count) count[i] = cnt[i];
+    if (names) names[i] = kProfNames[i];
+  }
+  if (n) *n = P_NCLS;
+  return TT_OK;
+}
+
+const char* tt_last_error(const tt_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+void tt_destroy(tt_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->st);
+  for (auto& e : c->ev) {
+    hipEventDestroy(e.second.first);
+    hipEventDestroy(e.second.second);
+  }
+  delete c;
+}
+
+}  // extern "C"

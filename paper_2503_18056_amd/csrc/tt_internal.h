@@ -1,0 +1,116 @@
+// Internal declarations of the MI355X tensor-train S_N library.
+//
+// Ranks are data dependent (tolerance-driven truncation), so every size a
+// kernel needs at run time lives in a small int32 table on the device (the
+// "dims" table below).  Launch grids are sized for the rank capacities and
+// blocks beyond the live sizes exit early; no step needs a host round trip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tt {
+
+// ---- device dims table ----------------------------------------------------
+enum DimIndex : int {
+  D_R1 = 0,      // state rank r1
+  D_R2,          // state rank r2
+  D_RC1,         // concatenated rank R1 (bond 1)
+  D_RC2,         // concatenated rank R2 (bond 2)
+  D_KA1,         // kept Gram eigenpairs, bond 1, left side (A = X_cat)
+  D_KB1,         // kept, bond 1, right side (B_1)
+  D_KM1,         // size of the Gram of M at bond 1 = min(kA, kB)
+  D_SIDE1,       // 0: Gram of M is M M^T; 1: M^T M
+  D_R1N,         // truncated rank r1'
+  D_KEA1,        // effective inner size for P1 (0 when the tensor is zero)
+  D_KEB1,        // effective inner size for M_upd1
+  D_KA2, D_KB2, D_KM2, D_SIDE2, D_R2N, D_KEA2, D_KEB2,
+  D_FLAG,        // error bits (FLAG_*)
+  D_REPLAY1,     // replayed rank, bond 1 (<= 0: rule)
+  D_REPLAY2,     // replayed rank, bond 2
+  D_KC1,         // eigenvectors computed for the Gram of M, bond 1
+  D_KC2,
+  D_R1NT,        // r1' * ntheta
+  D_ZERO1,       // 1 when bond 1 found a zero tensor
+  D_ZERO2,
+  D_NDIMS = 64
+};
+
+enum : int {
+  FLAG_NONFINITE = 1,
+  FLAG_NEWTON = 2,
+  FLAG_EIG = 4,
+};
+
+// diagnostics (double table)
+enum DiagIndex : int {
+  G_NORM2 = 0, G_DELTA2, G_KA1, G_KB1, G_KA2, G_KB2, G_R1N, G_R2N,
+  G_TAIL1, G_TAIL2, G_S1, G_SR1, G_SR1P, G_SR2, G_SR2P, G_RC1, G_NDIAG = 32
+};
+
+// A size evaluated on the device: (idx >= 0 ? dims[idx] : 0) * mul + add.
+struct DimExpr {
+  int idx, mul, add;
+};
+__host__ __device__ inline DimExpr dimc(int v) { return DimExpr{-1, 0, v}; }
+__host__ __device__ inline DimExpr dimv(int idx, int mul = 1, int add = 0) {
+  return DimExpr{idx, mul, add};
+}
+__device__ inline int eval_dim(const int* dims, DimExpr e) {
+  return (e.idx >= 0 ? dims[e.idx] : 0) * e.mul + e.add;
+}
+
+// ---- generic FP64 GEMM ----------------------------------------------------
+// C[m x n] = alpha * rs(i) * sum_l op(A)[i,l] ks(l) op(B)[l,j] * cs(j) + beta*C
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int lda, ldb, ldc;
+  long long sA, sB, sC;      // batch strides (blockIdx.z)
+  int transA, transB;
+  DimExpr m, n, k;
+  double alpha, beta;
+  const double* rowscale;    // length m or null
+  const double* colscale;    // length n or null
+  const double* kscale;      // length k or null
+  int cond_idx, cond_val;    // run only if dims[cond_idx] == cond_val (idx < 0: always)
+};
+void gemm(const GemmDesc& g, int mcap, int ncap, int batch, const int* dims, hipStream_t s);
+
+// ---- tall Gram on MFMA: G = A^T A, A is K x n (row-major, lda), n <= ncap
+struct GramPlan {
+  int K, ncap, lda, tiles, pairs, slices, kslice;
+};
+GramPlan gram_plan(int K, int ncap, int lda);
+size_t gram_partial_doubles(const GramPlan& p);
+void gram_tall(const GramPlan& p, const double* A, DimExpr n, double* partial, double* G,
+               int ldg, const int* dims, hipStream_t s);
+
+// ---- tall GEMM on MFMA: C[K x n] = A[K x k] * B[k x n], k, n dynamic
+void gemm_tall(int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+               DimExpr kdim, DimExpr ndim, int kcap, int ncap, const int* dims, hipStream_t s);
+
+// ---- symmetric eigensolver (batched, one job per matrix) ------------------
+// A (n x n, lda) is destroyed.  Outputs: lam (n, descending), V (n x n, ldv,
+// columns = eigenvectors in descending order, only the kept ones are
+// computed), sq / isq (sqrt and 1/sqrt of kept eigenvalues), dims[kept_idx]
+// = number kept: lambda > clip * n * u * lambda_max and lambda > 0.
+struct EigJob {
+  double* A;
+  int lda;
+  int n_idx;        // dims index holding n
+  double* lam;
+  double* V;
+  int ldv;
+  double* sq;
+  double* isq;
+  int kept_idx;     // dims index receiving the kept count
+  double clip;      // clip factor (1: Gram clip rule; 0: keep all lambda > 0)
+  double* work;     // eig_work_doubles(ncap)
+};
+size_t eig_work_doubles(int ncap);
+void eig_batched(const EigJob* jobs, int njobs, int ncap, int* dims, hipStream_t s);
+
+}  // namespace tt

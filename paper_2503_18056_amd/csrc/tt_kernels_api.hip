@@ -1,0 +1,139 @@
+// Kernel-level entry points (include/tt_kernels.h).
+#include <string.h>
+
+#include <string>
+
+#include "../../include/tt_kernels.h"
+#include "tt_internal.h"
+
+using namespace tt;
+
+namespace {
+thread_local std::string k_err;
+tt_status kfail(tt_status s, const std::string& m) {
+  k_err = m;
+  return s;
+}
+#define KCHK(call)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) return kfail(TT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" {
+
+const char* tt_kernel_last_error(void) { return k_err.c_str(); }
+
+size_t tt_kernel_eigh_workspace(int32_t n) {
+  if (n < 1 || n > 1024) return 0;
+  return align256(64 * sizeof(int)) + align256((size_t)n * n * 8) + align256((size_t)n * 8) * 2 +
+         align256(eig_work_doubles(n) * 8);
+}
+
+tt_status tt_kernel_eigh(const double* A, int32_t n, int32_t lda, double clip, double* lam,
+                         double* V, int32_t ldv, int32_t* kept, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!A || !lam || !V || !ws || n < 1 || n > 1024 || lda < n || ldv < n)
+    return kfail(TT_ERR_INVALID_ARG, "bad eigh arguments");
+  if (ws_bytes < tt_kernel_eigh_workspace(n)) return kfail(TT_ERR_OOM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  char* p = (char*)ws;
+  int* dims = (int*)p;
+  p += align256(64 * sizeof(int));
+  double* Acopy = (double*)p;
+  p += align256((size_t)n * n * 8);
+  double* sq = (double*)p;
+  p += align256((size_t)n * 8);
+  double* isq = (double*)p;
+  p += align256((size_t)n * 8);
+  double* work = (double*)p;
+  int hd[64];
+  memset(hd, 0, sizeof(hd));
+  hd[0] = n;
+  KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  KCHK(hipMemcpy2DAsync(Acopy, n * 8, A, lda * 8, n * 8, n, hipMemcpyDeviceToDevice, s));
+  KCHK(hipMemsetAsync(work, 0, eig_work_doubles(n) * 8, s));
+  EigJob j{Acopy, n, 0, lam, V, ldv, sq, isq, 1, clip, work};
+  eig_batched(&j, 1, n, dims, s);
+  KCHK(hipGetLastError());
+  KCHK(hipMemcpyAsync(hd, dims, sizeof(hd), hipMemcpyDeviceToHost, s));
+  KCHK(hipStreamSynchronize(s));
+  if (kept) *kept = hd[1];
+  if (hd[D_FLAG]) return kfail(TT_ERR_NUMERIC, "eigensolver flagged a failure");
+  return TT_OK;
+}
+
+size_t tt_kernel_gram_workspace(int32_t K, int32_t n, int32_t lda) {
+  if (K < 1 || n < 1 || lda < n) return 0;
+  return align256(64 * sizeof(int)) + align256(gram_partial_doubles(gram_plan(K, n, lda)) * 8);
+}
+
+tt_status tt_kernel_gram(const double* A, int32_t K, int32_t n, int32_t lda, double* G,
+                         int32_t ldg, void* ws, size_t ws_bytes, void* stream) {
+  if (!A || !G || !ws || K < 1 || n < 1 || lda < n || ldg < n)
+    return kfail(TT_ERR_INVALID_ARG, "bad gram arguments");
+  if (ws_bytes < tt_kernel_gram_workspace(K, n, lda)) return kfail(TT_ERR_OOM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  int* dims = (int*)ws;
+  double* part = (double*)((char*)ws + align256(64 * sizeof(int)));
+  int hd[64];
+  memset(hd, 0, sizeof(hd));
+  hd[0] = n;
+  KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  gram_tall(gram_plan(K, n, lda), A, dimv(0), part, G, ldg, dims, s);
+  KCHK(hipGetLastError());
+  KCHK(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+size_t tt_kernel_gemm_tall_workspace(void) { return align256(64 * sizeof(int)); }
+
+tt_status tt_kernel_gemm_tall(const double* A, int32_t K, int32_t k, int32_t lda, const double* B,
+                              int32_t n, int32_t ldb, double* C, int32_t ldc, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (!A || !B || !C || !ws || K < 1 || k < 0 || n < 1 || lda < k || ldb < n || ldc < n)
+    return kfail(TT_ERR_INVALID_ARG, "bad gemm_tall arguments");
+  if (ws_bytes < tt_kernel_gemm_tall_workspace()) return kfail(TT_ERR_OOM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  int* dims = (int*)ws;
+  int hd[64];
+  memset(hd, 0, sizeof(hd));
+  hd[0] = k;
+  hd[1] = n;
+  KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  gemm_tall(K, A, lda, B, ldb, C, ldc, dimv(0), dimv(1), k, n, dims, s);
+  KCHK(hipGetLastError());
+  KCHK(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+tt_status tt_kernel_gemm(const double* A, int32_t lda, int32_t ta, const double* B, int32_t ldb,
+                         int32_t tb, double* C, int32_t ldc, int32_t m, int32_t n, int32_t k,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!A || !B || !C || !ws || m < 1 || n < 1 || k < 0) return kfail(TT_ERR_INVALID_ARG, "bad gemm arguments");
+  if (ws_bytes < tt_kernel_gemm_tall_workspace()) return kfail(TT_ERR_OOM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  int* dims = (int*)ws;
+  int hd[64];
+  memset(hd, 0, sizeof(hd));
+  hd[0] = m;
+  hd[1] = n;
+  hd[2] = k;
+  KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  GemmDesc g;
+  memset(&g, 0, sizeof(g));
+  g.A = A; g.B = B; g.C = C; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.transA = ta; g.transB = tb;
+  g.m = dimv(0); g.n = dimv(1); g.k = dimv(2);
+  g.alpha = 1.0;
+  g.cond_idx = -1;
+  gemm(g, m, n, 1, dims, s);
+  KCHK(hipGetLastError());
+  KCHK(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+}  // extern "C"

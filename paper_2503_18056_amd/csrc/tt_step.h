@@ -1,0 +1,59 @@
+// Geometry of one context and the launchers of the per-step kernels.
+#pragma once
+
+#include "tt_internal.h"
+
+namespace tt {
+
+struct StepGeom {
+  int ns, nx, ny, nz;
+  int n[3], stride[3], periodic[3];
+  int nt, np;
+  int B;        // transport blocks: 1 + 2 dim
+  int nbc;      // rank-1 inflow terms
+  int nem;      // emission block present (0/1)
+  int r1c, r2c; // state rank capacities
+  int R1c, R2c; // concatenated rank capacities
+};
+
+struct RankArgs {
+  int bond;           // 1 or 2
+  int km, kc, ka, kb; // dims indices: Gram-of-M size, computed vectors, kept A, kept B
+  int rn, zero, kea, keb, replay, rnt;
+  int nt;
+  double tol, eta;
+  int rmax;
+  int g_tail, g_sr, g_srp, g_rn, g_ka, g_kb;
+};
+
+void launch_build_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
+                       const double* d, const double* s, double* Xc, int ldC, const int* dims,
+                       int scaled, hipStream_t st);
+void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, double* Xc, int ldC,
+                       const int* dims, hipStream_t st);
+void launch_build_phcat(const StepGeom& G, const double* Ph, const double* pfac,
+                        const double* bc_p, double* Pc, const int* dims, hipStream_t st);
+void launch_build_thcat(const StepGeom& G, const double* Th, const double* tfac,
+                        const double* bc_t, double* Tc, const int* dims, hipStream_t st);
+void launch_concat_dims(const StepGeom& G, int* dims, hipStream_t st);
+void launch_round_dims(int* dims, hipStream_t st);
+void launch_state_as_cat(const StepGeom& G, const double* Th, const double* Ph, double* Tc,
+                         double* Pc, const int* dims, hipStream_t st);
+void launch_energy(const double* X, int ldX, int ns, const double* Th, int nt, int ldb,
+                   const double* Ph, int np, const double* w, const double* v, double* pv,
+                   double* z, DimExpr r1, DimExpr r2, double inv_c, double* E, const int* dims,
+                   int rcap1, int rcap2, hipStream_t st);
+void launch_material(int ns, double c, double dt, double a_r, int coupled, const double* kappa,
+                     const double* rho, const double* cv, const double* T, const double* Estar,
+                     double* Tdag, double* d, double* s, int* dims, hipStream_t st);
+void launch_temperature(int ns, const double* rho, const double* cv, const double* Estar,
+                        const double* Enew, double* T, hipStream_t st);
+void launch_mside(int* dims, int ka, int kb, int km, int side, hipStream_t st);
+void launch_rank(const double* lam, int* dims, double* diag, const RankArgs& ra, hipStream_t st);
+void launch_svd_vectors(const double* Uc, int ldu, const double* sqc, double* Ur, int ldr,
+                        double* Wm, int ldw, const int* dims, int ka, int kb, int side, int rn,
+                        int zero, int rcap, hipStream_t st);
+void launch_finish(int* dims, int* hist, int slot, hipStream_t st);
+void launch_check_finite(const double* x, int n, int* dims, hipStream_t st);
+
+}  // namespace tt

@@ -1,0 +1,162 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+FP64 bar: identical ranks and relative Frobenius difference of the
+reconstructed intensity below the stated tolerance.  Two independent
+Gram-SVD implementations differ by rounding noise of order
+c u / (relative gap at the cut) / eps (Gram floor of App. A.4 "Stability"),
+so the tight 1e-10 bar is asserted where the case has a healthy gap; cases
+at the Gram floor are compared with ranks replayed and a looser bound.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import Setup, metrics, rounding, tt
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(p, **kw):
+    from paper_2503_18056_amd import TTState
+    return TTState(p, device=0, **kw)
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ rounding
+@pytest.mark.parametrize("seed", [0, 1])
+def test_round_random_tt(seed):
+    X, Th, Ph = wl.random_tt(300, 6, 12, 8, 5, seed, decay=0.15)
+    p = wl.small_random(nx=20, ny=15, ntheta=6, nphi=12, seed=seed)
+    st = _state(p, cores=(X, Th, Ph), r1_cap=8, r2_cap=5)
+    r = st.tt_round(1e-5, 0)
+    (Xo, To, Po), (i1, i2) = rounding.round_gram(X, Th, Ph, 1e-5, 0)
+    got = st.cores()
+    err = metrics.rel_diff(got, (Xo, To, Po))
+    _log(f"round seed={seed} ranks gpu={r} oracle={(Xo.shape[1], Po.shape[0])} err={err:.2e}")
+    assert r == (Xo.shape[1], Po.shape[0])
+    assert err < 1e-10
+    Xg = got[0]
+    assert np.allclose(Xg.T @ Xg, np.eye(Xg.shape[1]), atol=1e-10)
+
+
+def test_round_constructed_spectrum():
+    rng = np.random.default_rng(0)
+    s = 10.0 ** (-np.arange(10) / 1.5)
+    ns, nt, npf = 240, 5, 16
+    X = np.linalg.qr(rng.standard_normal((ns, 10)))[0]
+    Ph = np.linalg.qr(rng.standard_normal((npf, 10)))[0].T
+    Th = np.zeros((10, nt, 10))
+    for a in range(10):
+        Th[a, a % nt, a] = s[a]
+    p = wl.small_random(nx=16, ny=15, ntheta=nt + 1, nphi=npf, seed=0)
+    p["ntheta"] = nt + 1  # even ntheta required: pad one zero slice
+    Thp = np.zeros((10, nt + 1, 10)); Thp[:, :nt] = Th
+    st = _state(p, cores=(X, Thp, Ph), r1_cap=10, r2_cap=10)
+    tol = 1e-4
+    r = st.tt_round(tol, 0)
+    delta2 = tol ** 2 * np.sum(s ** 2) / 2
+    tail = np.array([np.sum(s[k:] ** 2) for k in range(11)])
+    expect = int(np.argmax(tail <= delta2))
+    info = st.tt_get_round_info()
+    _log("spectrum ranks", r, "expect", expect, "s1", info["s1"])
+    assert r == (expect, expect)
+    assert abs(info["s1"] - s[0]) < 1e-12
+
+
+def test_round_rank_one_and_zero():
+    p = wl.c1()
+    st = _state(p)
+    assert st.tt_round(1e-8, 0) == (1, 1)
+    X, Th, Ph = st.cores()
+    T0 = metrics.reconstruct(p["X0"], p["Th0"], p["Ph0"])
+    assert np.linalg.norm(metrics.reconstruct(X, Th, Ph) - T0) < 1e-14 * np.linalg.norm(T0)
+    p2 = wl.small_random(seed=4)
+    st2 = _state(p2, cores=(np.zeros((30, 3)), np.ones((3, 4, 2)), np.ones((2, 8))))
+    assert st2.tt_round(1e-6, 0) == (1, 1)
+    X, Th, Ph = st2.cores()
+    assert not np.any(metrics.reconstruct(X, Th, Ph))
+
+
+# ------------------------------------------------------------------- steps
+CASES = [
+    dict(seed=1),
+    dict(bc="periodic", seed=2),
+    dict(bc="inflow", seed=3, material=wl.COUPLED),
+    dict(dim=3, nx=4, ny=3, nz=5, bc="inflow", seed=4, material=wl.COUPLED),
+    dict(dim=3, nx=5, ny=4, nz=4, bc="periodic", seed=5),
+    dict(nx=33, ny=17, ntheta=8, nphi=16, r1=5, r2=3, seed=6, bc="inflow"),
+]
+
+
+@pytest.mark.parametrize("kw", CASES, ids=[f"case{i}" for i in range(len(CASES))])
+def test_step_matches_oracle(kw):
+    p = wl.small_random(**kw)
+    p["tol"] = 1e-6
+    s = Setup(p)
+    nsteps = 3
+    st = _state(p, max_steps=nsteps)
+    st.step(nsteps)
+    hist_gpu = st.tt_get_rank_history()
+    (X, Th, Ph), T, hist = tt.run(s, nsteps)
+    got = st.cores()
+    err = metrics.rel_diff(got, (X, Th, Ph))
+    Tg = st.tt_get_temperature()
+    terr = np.max(np.abs(Tg - T)) / np.max(np.abs(T))
+    _log(f"{p['name']}: ranks gpu={hist_gpu} oracle={hist} err={err:.2e} Terr={terr:.2e}")
+    assert hist_gpu == hist
+    assert err < 1e-9
+    assert terr < 1e-11
+
+
+def test_energy_matches_oracle():
+    p = wl.small_random(bc="inflow", seed=8, material=wl.COUPLED)
+    s = Setup(p)
+    st = _state(p)
+    st.step(2)
+    E, rad, mat = st.tt_energy()
+    (X, Th, Ph), T, _ = tt.run(s, 2)
+    Eo = tt.energy(X, Th, Ph, s)
+    e = E.cpu().numpy()
+    assert np.max(np.abs(e - Eo)) < 1e-10 * np.max(np.abs(Eo))
+    assert abs(rad - Eo.sum() * s.cell_volume) < 1e-10 * abs(rad)
+    assert abs(mat - np.sum(s.rho * s.cv * T) * s.cell_volume) < 1e-10 * abs(mat)
+
+
+def test_c1_parity():
+    """C1 (32^2, 8x16, 10 steps).  Its tolerance 1e-8 sits at the FP64
+    Gram floor, so it is checked with ranks replayed from the GPU run, plus
+    the same case at 1e-6 with the rank rule on both sides."""
+    p = wl.c1()
+    s = Setup(p)
+    for tol in (1e-6, 1e-8):
+        p["tol"] = tol
+        st = _state(p, max_steps=10)
+        st.step(10)
+        hist_gpu = st.tt_get_rank_history()
+        got = st.cores()
+        (X, Th, Ph), T, hist = tt.run(s, 10, tol=tol, rank_schedule=hist_gpu)
+        err = metrics.rel_diff(got, (X, Th, Ph))
+        (_, _, _), _, hist_auto = tt.run(s, 10, tol=tol)
+        _log(f"C1 tol={tol}: gpu ranks {hist_gpu}\n   oracle auto {hist_auto}\n   replay err={err:.2e}")
+        assert err < (1e-9 if tol == 1e-6 else 1e-6)
+        if tol == 1e-6:
+            assert hist_gpu == hist_auto
+
+
+def test_c2_first_steps():
+    p = wl.c2(steps=40)
+    s = Setup(p)
+    st = _state(p, max_steps=40)
+    st.step(40)
+    hist_gpu = st.tt_get_rank_history()
+    got = st.cores()
+    (X, Th, Ph), T, hist = tt.run(s, 40)
+    err = metrics.rel_diff(got, (X, Th, Ph))
+    _log(f"C2 40 steps: gpu {hist_gpu[-5:]} oracle {hist[-5:]} err={err:.2e}")
+    assert hist_gpu == hist
+    assert err < 1e-8
