@@ -1,0 +1,141 @@
+"""Benchmark: tensor-train S_N steps/s on the 256^2 x 2048-ordinate crossing-beam
+workload on one MI355X.
+
+A step is one pass of the whole hot path: TT-format upwind transport
+operator, absorption/emission, TT sum by concatenation, Gram-SVD rounding
+(Gram contractions, eigensolves, truncation, core updates).  The workload is
+the crossing-beam case: 256^2 cells, 32 x 64 ordinates, kappa = 1e-3, cold
+medium, two inflow beams, tolerance 1e-6, rank cap 64, 400 steps in total
+(warmup + timed steps).  Inputs are resident in HBM before timing.
+
+Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
+this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TT steps/s at 256²×2048 angles; FP32-mixed vs FP64 speedup at rel err 1e-6"
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def gram_flops(ns, R1):
+    """Algorithmic flops of the symmetric left Gram of an N_s x R1 core."""
+    return float(ns) * R1 * (R1 + 1)
+
+
+def cpu_baseline(p, start_cores, nsteps_target_s=15.0, max_steps=60):
+    """The CPU oracle (FP64, NumPy) on a bounded sample of the same workload:
+    steps from the GPU run's post-warmup state until ~15 s have elapsed."""
+    import numpy as np
+    from oracle import Setup, tt
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    s = Setup(p)
+    X, Th, Ph = start_cores
+    T = s.T0.copy()
+    t0 = time.perf_counter()
+    n = 0
+    while n < max_steps and time.perf_counter() - t0 < nsteps_target_s:
+        (X, Th, Ph), T, _ = tt.step(X, Th, Ph, T, s, p["tol"], p["rmax"])
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} consecutive steps of the same workload starting from the GPU "
+                      f"state after the warmup (ranks {X.shape[1]},{Ph.shape[0]}), "
+                      f"NumPy FP64, {len(os.sched_getaffinity(0))} host cores visible"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=380)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the "
+              "hot path on one GPU (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as wl
+    from paper_2503_18056_amd import TTState
+
+    W, K = args.warmup, args.steps
+    p = wl.c2(steps=W + K)
+    st = TTState(p, device=0, max_steps=W + K)
+    if W:
+        st.step(W)
+    torch.cuda.synchronize()
+    warm_cores = st.cores() if not args.no_cpu_baseline else None
+    r_start = st.ranks()
+    st.tt_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = st.tt_profile_read()
+    st.tt_profile_enable(False)
+    hist = st.tt_get_rank_history()
+    dt = t1 - t0
+    ns = p["nx"] * p["ny"]
+    nang = p["ntheta"] * p["nphi"]
+    # concatenated rank R1 entering each timed step: 5 r1 + 2 inflow terms
+    r_in = [r_start] + hist[W:W + K - 1]
+    R1s = [5 * r1 + 2 for (r1, _) in r_in]
+    gram_ms, gram_n = prof.get("gram_tall", (0.0, 0))
+    flops = sum(gram_flops(ns, R) for R in R1s)
+    achieved = flops / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else 0.0
+    breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1]} for k, v in prof.items()}
+    out = {
+        "metric": METRIC,
+        "value": K / dt,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": dt * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "crossing beams 256x256 cells, 32x64 ordinates, kappa 1e-3, "
+                               "cold medium, 2 inflow beams, tol 1e-6, rank cap 64, steps "
+                               f"{W + 1}-{W + K} of {W + K}",
+                   "precision": "fp64", "nx": 256, "ny": 256, "ntheta": 32, "nphi": 64,
+                   "tol": 1e-6, "rmax": 64},
+        "ranks_end": list(st.ranks()),
+        "zcps": ns * K / dt,
+        "angle_updates_per_s": ns * nang * K / dt,
+        "roofline": {
+            "kernel": "k_gram_tall (left Gram X_cat^T X_cat, FP64 MFMA)",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "avg_launch_ms": gram_ms / gram_n if gram_n else None,
+            "algorithmic_flops_per_launch_avg": flops / max(1, gram_n),
+        },
+        "kernel_breakdown_ms": breakdown,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, warm_cores)
+    print(json.dumps(out), flush=True)
+    st.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -10,7 +10,11 @@ Rules where the paper is silent (applied identically by every form here):
   delta^2 = eps^2 ||T||^2 / 2, with ||T||^2 := sum of the squared singular
   values found at bond 1;
 * rank rule: r' = min{k >= 1 : sum_{j>k} sigma_j^2 <= delta^2}, then the
-  cluster rule, then the cap (``select_rank``);
+  cluster rule, then the cap (``select_rank``).  Two neighbouring singular
+  values form a cluster when they differ by no more than what the Gram
+  route can resolve: max(eta sigma_1, R u sigma_1^2 / sigma_r) (App. A.4:
+  Gram singular values carry only sqrt(u) relative precision; an error
+  ||dG|| ~ R u sigma_1^2 moves sigma_r by ~R u sigma_1^2 / sigma_r);
 * clip rule for singular Gram matrices: eigenpairs with lambda <= tau
   lambda_max (tau = R u, R the Gram dimension, u = 2^-53) or lambda <= 0
   are dropped before Sigma^-1 is formed;
@@ -34,14 +38,17 @@ def gauge(V):
     return V * sgn[None, :], sgn
 
 
-def select_rank(sig, delta2, rmax, eta=ETA_FP64):
+def select_rank(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
     """Rank rule with the cluster rule and the cap.
 
     tail(k) = sum_{j>k} sigma_j^2; r = min{k >= 1: tail(k) <= delta^2}.
-    Cluster rule: while sigma_r - sigma_{r+1} <= eta sigma_1, r += 1 (a cut
-    never splits a set of numerically equal singular values).  Cap: if
-    r > rmax > 0, r = rmax and, if that cut splits a cluster, r moves down
-    to just before the cluster (kept at rmax if the cluster starts at 1).
+    Cluster rule: while sigma_r - sigma_{r+1} <= thr(r), r += 1, with
+    thr(r) = max(eta sigma_1, noise sigma_1^2 / sigma_r), so a cut never
+    splits a set of singular values that are equal to the resolution of the
+    computation (``noise`` = R u for a Gram of dimension R, 0 for a direct
+    SVD).  Cap: if r > rmax > 0, r = rmax and, if that cut splits a
+    cluster, r moves down to just before the cluster (kept at rmax if the
+    cluster starts at 1).
     """
     sig = np.asarray(sig, float)
     n = sig.size
@@ -50,14 +57,17 @@ def select_rank(sig, delta2, rmax, eta=ETA_FP64):
     sq = sig * sig
     tail = np.concatenate([np.cumsum(sq[::-1])[::-1], [0.0]])  # tail[k] = sum_{j>=k}
     r = next(k for k in range(1, n + 1) if tail[k] <= delta2)
-    thr = eta * sig[0]
-    while r < n and sig[r - 1] - sig[r] <= thr:
+
+    def tied(j):  # sigma_j and sigma_{j+1} (1-based j) in one cluster
+        thr = max(eta * sig[0], noise * sig[0] ** 2 / sig[j - 1] if sig[j - 1] > 0 else np.inf)
+        return sig[j - 1] - sig[j] <= thr
+    while r < n and tied(r):
         r += 1
     if rmax > 0 and r > rmax:
         r = rmax
-        if r < n and sig[r - 1] - sig[r] <= thr:
+        if r < n and tied(r):
             k = r
-            while k > 1 and sig[k - 2] - sig[k - 1] <= thr:
+            while k > 1 and tied(k - 1):
                 k -= 1
             r = k - 1 if k > 1 else rmax
     return r
@@ -105,7 +115,8 @@ def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None):
     if sig.size == 0 or sig[0] <= 0.0:
         info.update(rank=1, zero=True)
         return np.zeros((A.shape[0], 1)), np.zeros((1, R)), np.zeros((R, 1)), info
-    r = select_rank(sig, delta2, rmax, eta) if rank is None else min(int(rank), sig.size)
+    r = (select_rank(sig, delta2, rmax, eta, noise=R * U) if rank is None
+         else min(int(rank), sig.size))
     P = VA @ (Ut[:, :r] / SA[:, None])
     Mupd = (sig[:r, None] * Vt[:r]) @ (VB / SB[None, :]).T
     sq = sig * sig

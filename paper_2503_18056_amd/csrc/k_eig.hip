@@ -298,12 +298,7 @@ __global__ __launch_bounds__(256) void k_dc_rotate(EigJobs jobs, int* __restrict
   const int m = blockIdx.x, b0 = m * 2 * S;
   if (b0 >= n) return;
   const int nk = D.mk[m];
-  const int rend = min(b0 + 2 * S, n);
-  if (nk < 0) {
-    for (int r = b0 + threadIdx.x; r < rend; r += 256)
-      for (int c = 0; c < 2 * S && b0 + c < N2; ++c) D.Qb[(size_t)r * N2 + b0 + c] = D.Qa[(size_t)r * N2 + b0 + c];
-    return;
-  }
+  if (nk < 0) return;  // no partner: the block is left as it is
   const int m2 = D.mm2[m], nrot = D.mnrot[m];
   for (int r = b0 + threadIdx.x; r < b0 + m2; r += 256) {
     double* qb = D.Qb + (size_t)r * N2 + b0;
@@ -411,15 +406,11 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   const int S2 = 2 * S;
   double* Ub = D.U + (size_t)m * S2 * S2;
   const int tid = threadIdx.x;
-  if (b0 >= N2) return;
-  const int nk = b0 + S < n ? D.mk[m] : -1;
-  for (long long e = tid; e < (long long)S2 * S2; e += 256) {
-    const int s = (int)(e / S2), c = (int)(e % S2);
-    Ub[e] = (nk < 0 && s == c) ? 1.0 : 0.0;
-  }
-  if (nk < 0) return;
-  __syncthreads();
+  if (b0 + S >= n) return;  // no merge in this block; its GEMM batch is skipped
+  const int nk = D.mk[m];
   const int m2 = D.mm2[m];
+  for (long long e = tid; e < (long long)m2 * S2; e += 256) Ub[e] = 0.0;
+  __syncthreads();
   const double* d = D.dK + b0;
   const double* z = D.zK + b0;
   const double rho = D.mrho[m];
@@ -631,6 +622,11 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
       g.m = dimc(2 * S); g.n = dimc(2 * S); g.k = dimc(2 * S);
       g.alpha = 1.0;
       g.cond_idx = -1;
+      // block z holds rows/cols [z 2S, z 2S + min(2S, n - z 2S)); it has a
+      // merge only when n - z 2S > S
+      g.bclip_idx = jobs[q].n_idx;
+      g.bclip_mul = 2 * S;
+      g.bclip_min = S;
       const int bm = (N + 2 * S - 1) / (2 * S);
       gemm(g, 2 * S, 2 * S, bm, dims, s);
     }

@@ -13,7 +13,14 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict__ dims) {
   if (g.cond_idx >= 0 && dims[g.cond_idx] != g.cond_val) return;
-  const int m = eval_dim(dims, g.m), n = eval_dim(dims, g.n), k = eval_dim(dims, g.k);
+  int m = eval_dim(dims, g.m), n = eval_dim(dims, g.n), k = eval_dim(dims, g.k);
+  if (g.bclip_idx >= 0) {
+    const int lim = dims[g.bclip_idx] - (int)blockIdx.z * g.bclip_mul;
+    if (lim <= g.bclip_min) return;
+    m = min(m, lim);
+    n = min(n, lim);
+    k = min(k, lim);
+  }
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   if (i0 >= m || j0 >= n) return;
   const double* A = g.A + (long long)blockIdx.z * g.sA;
@@ -79,6 +86,28 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
       *dst = g.beta == 0.0 ? v : v + g.beta * *dst;
     }
   }
+}
+
+__global__ void k_sum_partials(const double* __restrict__ part, long long zstride, int nz,
+                               double* __restrict__ out, int ldo, int ldp, DimExpr mdim,
+                               DimExpr ndim, const int* __restrict__ dims) {
+  const int m = eval_dim(dims, mdim), n = eval_dim(dims, ndim);
+  const long long tot = (long long)m * n;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    double acc = 0.0;
+    for (int z = 0; z < nz; ++z) acc += part[z * zstride + (long long)i * ldp + j];
+    out[(long long)i * ldo + j] = acc;
+  }
+}
+
+void sum_partials(const double* part, long long zstride, int nz, double* out, int ldo, int ldp,
+                  DimExpr m, DimExpr n, int mcap, int ncap, const int* dims, hipStream_t s) {
+  long long tot = (long long)mcap * ncap;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  k_sum_partials<<<blocks, 256, 0, s>>>(part, zstride, nz, out, ldo, ldp, m, n, dims);
 }
 
 void gemm(const GemmDesc& g, int mcap, int ncap, int batch, const int* dims, hipStream_t s) {
@@ -194,12 +223,20 @@ GramPlan gram_plan(int K, int ncap, int lda) {
 
 size_t gram_partial_doubles(const GramPlan& p) { return (size_t)p.slices * p.pairs * 4096; }
 
-void gram_tall(const GramPlan& p, const double* A, DimExpr n, double* partial, double* G, int ldg,
-               const int* dims, hipStream_t s) {
+void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* partial,
+                       const int* dims, hipStream_t s) {
   k_gram_tall<<<dim3(p.pairs, p.slices), 256, 0, s>>>(A, p.lda, p.K, p.kslice, n, dims, p.tiles,
                                                       partial);
+}
+void gram_tall_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
+                      const int* dims, hipStream_t s) {
   k_gram_reduce<<<dim3(4, p.pairs), 256, 0, s>>>(partial, p.slices, p.pairs, p.tiles, n, dims, G,
                                                  ldg);
+}
+void gram_tall(const GramPlan& p, const double* A, DimExpr n, double* partial, double* G, int ldg,
+               const int* dims, hipStream_t s) {
+  gram_tall_partial(p, A, n, partial, dims, s);
+  gram_tall_reduce(p, n, partial, G, ldg, dims, s);
 }
 
 // ---------------------------------------------------------------------------

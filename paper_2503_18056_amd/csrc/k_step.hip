@@ -298,14 +298,17 @@ __global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
       if (tail <= delta2) r = k;
       else break;
     }
-    const double thr = ra.eta * s0;
+    // sigma_j and sigma_{j+1} (1-based j) are tied when they differ by no more
+    // than the Gram route resolves: max(eta s1, R u s1^2 / sigma_j)
+    const double noise = (double)dims[ra.rdim] * 1.1102230246251565e-16;
 #define SIG(j) sqrt(fmax(lam[(j)], 0.0))
-    while (r < n && SIG(r - 1) - SIG(r) <= thr) ++r;
+#define TIED(j) (SIG((j) - 1) - SIG(j) <= fmax(ra.eta * s0, SIG((j) - 1) > 0.0 ? noise * s0 * s0 / SIG((j) - 1) : 1.79e308))
+    while (r < n && TIED(r)) ++r;
     if (ra.rmax > 0 && r > ra.rmax) {
       r = ra.rmax;
-      if (r < n && SIG(r - 1) - SIG(r) <= thr) {
+      if (r < n && TIED(r)) {
         int k = r;
-        while (k > 1 && SIG(k - 2) - SIG(k - 1) <= thr) --k;
+        while (k > 1 && TIED(k - 1)) --k;
         r = k > 1 ? k - 1 : ra.rmax;
       }
     }
@@ -319,6 +322,7 @@ __global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
     diag[ra.g_sr] = SIG(r - 1);
     diag[ra.g_srp] = r < n ? SIG(r) : 0.0;
     if (ra.bond == 1) diag[G_S1] = s0;
+#undef TIED
 #undef SIG
   }
   dims[ra.rn] = r;

@@ -35,9 +35,11 @@ struct EigSlot {
   double *lam, *V, *sq, *isq, *work;
 };
 
-enum ProfClass { P_CONCAT, P_GRAM, P_EIG1, P_EIGM1, P_EIG2, P_EIGM2, P_XUPD, P_SMALL, P_MAT, P_STEP, P_NCLS };
-const char* kProfNames[P_NCLS] = {"concat", "gram_tall", "eig_bond1", "eig_M1", "eig_bond2",
-                                  "eig_M2", "x_update", "small_gemm", "material_energy", "step"};
+enum ProfClass { P_CONCAT, P_GRAM, P_GRAMRED, P_EIG1, P_EIGM1, P_EIG2, P_EIGM2, P_XUPD, P_SMALL,
+                 P_MAT, P_STEP, P_NCLS };
+const char* kProfNames[P_NCLS] = {"concat", "gram_tall", "gram_reduce", "eig_bond1", "eig_M1",
+                                  "eig_bond2", "eig_M2", "x_update", "small_gemm",
+                                  "material_energy", "step"};
 
 }  // namespace
 
@@ -176,7 +178,9 @@ size_t carve(tt_ctx* x, char* base) {
   x->Phcat = cv.take<double>((size_t)x->R2c * np);
   x->Xcat = cv.take<double>((size_t)ns * x->ldC);
   GramPlan p1 = gram_plan(ns, x->R1c, x->ldC), p2 = gram_plan(ns, x->r1c, x->ldX);
-  x->gpart = cv.take<double>(std::max(gram_partial_doubles(p1), gram_partial_doubles(p2)));
+  x->gpart = cv.take<double>(std::max(std::max(gram_partial_doubles(p1), gram_partial_doubles(p2)),
+                                      std::max((size_t)(nt / 2) * x->R1c * x->R1c,
+                                               (size_t)nt * x->R2c * x->R2c)));
   x->GA = cv.take<double>((size_t)x->R1c * x->R1c);
   x->GB1 = cv.take<double>((size_t)x->R1c * x->R1c);
   x->GR3 = cv.take<double>((size_t)x->R2c * x->R2c);
@@ -325,6 +329,7 @@ GemmDesc gd(const double* A, int lda, int ta, const double* B, int ldb, int tb, 
   g.m = m; g.n = n; g.k = k;
   g.alpha = 1.0; g.beta = 0.0;
   g.cond_idx = -1;
+  g.bclip_idx = -1;
   return g;
 }
 
@@ -369,6 +374,7 @@ void truncate_bond(tt_ctx* c, int bond, const EigSlot& ea, const EigSlot& eb, Ei
   ra.tol = tol;
   ra.eta = 1e-12;
   ra.rmax = std::min(rmax > 0 ? rmax : rcap, rcap);
+  ra.rdim = Rdim;
   ra.g_tail = bond == 1 ? G_TAIL1 : G_TAIL2;
   ra.g_sr = bond == 1 ? G_SR1 : G_SR2;
   ra.g_srp = bond == 1 ? G_SR1P : G_SR2P;
@@ -407,14 +413,25 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
          R2c, R2c, 1, c->dims, s);
     gemm(gd(c->Thcat, R2c, 0, c->GR3, R2c, 0, c->T1, R2c, dimv(D_RC1, nt), dimv(D_RC2), dimv(D_RC2)),
          R1c * nt, R2c, 1, c->dims, s);
-    gemm(gd(c->T1, nt * R2c, 0, c->Thcat, nt * R2c, 1, c->GB1, R1c, dimv(D_RC1), dimv(D_RC1),
-            dimc(nt * R2c)),
-         R1c, R1c, 1, c->dims, s);
+    // G_B1 = sum_l T1_l Thcat_l^T, one partial per pair of ordinates l
+    // (batched), then a fixed-order sum
+    const int nq = nt / 2;
+    GemmDesc gb = gd(c->T1, nt * R2c, 0, c->Thcat, nt * R2c, 1, c->gpart, R1c, dimv(D_RC1),
+                     dimv(D_RC1), dimc(2 * R2c));
+    gb.sA = gb.sB = 2LL * R2c;
+    gb.sC = (long long)R1c * R1c;
+    gemm(gb, R1c, R1c, nq, c->dims, s);
+    sum_partials(c->gpart, (long long)R1c * R1c, nq, c->GB1, R1c, R1c, dimv(D_RC1), dimv(D_RC1),
+                 R1c, R1c, c->dims, s);
   }
   {
-    Prof p(c, P_GRAM);
     GramPlan plan = gram_plan(c->ns, ncap1, ldxc);
-    gram_tall(plan, xc, dimv(D_RC1), c->gpart, c->GA, R1c, c->dims, s);
+    {
+      Prof p(c, P_GRAM);
+      gram_tall_partial(plan, xc, dimv(D_RC1), c->gpart, c->dims, s);
+    }
+    Prof p(c, P_GRAMRED);
+    gram_tall_reduce(plan, dimv(D_RC1), c->gpart, c->GA, R1c, c->dims, s);
   }
   {
     Prof p(c, P_EIG1);
@@ -436,9 +453,14 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
     gemm(gd(c->Mupd1, R1c, 0, c->Thcat, nt * R2c, 0, c->Thp, nt * R2c, dimv(D_R1N), dimc(nt * R2c),
             dimv(D_RC1)),
          c->r1c, nt * R2c, 1, c->dims, s);
-    // bond 2: G_A2 = sum_l Theta'_l^T Theta'_l
-    gemm(gd(c->Thp, R2c, 1, c->Thp, R2c, 0, c->GL2, R2c, dimv(D_RC2), dimv(D_RC2), dimv(D_R1NT)),
-         R2c, R2c, 1, c->dims, s);
+    // bond 2: G_A2 = sum_l Theta'_l^T Theta'_l, one partial per ordinate l
+    GemmDesc gl = gd(c->Thp, nt * R2c, 1, c->Thp, nt * R2c, 0, c->gpart, R2c, dimv(D_RC2),
+                     dimv(D_RC2), dimv(D_R1N));
+    gl.sA = gl.sB = R2c;
+    gl.sC = (long long)R2c * R2c;
+    gemm(gl, R2c, R2c, nt, c->dims, s);
+    sum_partials(c->gpart, (long long)R2c * R2c, nt, c->GL2, R2c, R2c, dimv(D_RC2), dimv(D_RC2),
+                 R2c, R2c, c->dims, s);
   }
   {
     Prof p(c, P_EIG2);

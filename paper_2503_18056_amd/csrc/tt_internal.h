@@ -76,8 +76,15 @@ struct GemmDesc {
   const double* colscale;    // length n or null
   const double* kscale;      // length k or null
   int cond_idx, cond_val;    // run only if dims[cond_idx] == cond_val (idx < 0: always)
+  // per-batch live size: with bclip_idx >= 0, batch z uses
+  // lim = dims[bclip_idx] - z * bclip_mul; it is skipped when lim <= bclip_min
+  // and m, n, k are clipped to lim.
+  int bclip_idx, bclip_mul, bclip_min;
 };
 void gemm(const GemmDesc& g, int mcap, int ncap, int batch, const int* dims, hipStream_t s);
+// out[i][j] = sum_{z < nz} part[z][i][j] (fixed order), i < m, j < n (dynamic).
+void sum_partials(const double* part, long long zstride, int nz, double* out, int ldo, int ldp,
+                  DimExpr m, DimExpr n, int mcap, int ncap, const int* dims, hipStream_t s);
 
 // ---- tall Gram on MFMA: G = A^T A, A is K x n (row-major, lda), n <= ncap
 struct GramPlan {
@@ -87,6 +94,10 @@ GramPlan gram_plan(int K, int ncap, int lda);
 size_t gram_partial_doubles(const GramPlan& p);
 void gram_tall(const GramPlan& p, const double* A, DimExpr n, double* partial, double* G,
                int ldg, const int* dims, hipStream_t s);
+void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* partial,
+                       const int* dims, hipStream_t s);
+void gram_tall_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
+                      const int* dims, hipStream_t s);
 
 // ---- tall GEMM on MFMA: C[K x n] = A[K x k] * B[k x n], k, n dynamic
 void gemm_tall(int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,

@@ -130,6 +130,7 @@ tt_status tt_kernel_gemm(const double* A, int32_t lda, int32_t ta, const double*
   g.m = dimv(0); g.n = dimv(1); g.k = dimv(2);
   g.alpha = 1.0;
   g.cond_idx = -1;
+  g.bclip_idx = -1;
   gemm(g, m, n, 1, dims, s);
   KCHK(hipGetLastError());
   KCHK(hipStreamSynchronize(s));

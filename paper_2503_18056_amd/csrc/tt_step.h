@@ -23,6 +23,7 @@ struct RankArgs {
   int nt;
   double tol, eta;
   int rmax;
+  int rdim;           // dims index of the Gram dimension R (resolution R u sigma_1^2 / sigma)
   int g_tail, g_sr, g_srp, g_rn, g_ka, g_kb;
 };
 

@@ -239,6 +239,11 @@ def test_cluster_and_cap_rules():
     assert rounding.select_rank(sig, 1e-30, 2) == 1
     assert rounding.select_rank(sig, 1e-30, 4) == 4
     assert rounding.select_rank(np.zeros(3), 0.0, 0) == 1
+    # a pair split only at the Gram resolution (R u sigma_1^2 / sigma) is a cluster
+    pair = np.array([1.0, 1e-3, 1e-6 + 4e-11, 1e-6, 1e-9])
+    d2 = 1.01 * (1e-6 ** 2 + 1e-18)
+    assert rounding.select_rank(pair, d2, 0) == 3
+    assert rounding.select_rank(pair, d2, 0, noise=42 * rounding.U) == 4
 
 
 # ---------------------------------------------------------------- TT vs full
