@@ -100,7 +100,9 @@ typedef struct {
 typedef struct tt_ctx tt_ctx;
 
 /* Bytes of device workspace a context needs for `cfg` with `n_inflow`
- * inflow terms (0 if cfg is invalid; see tt_last_error(NULL)). */
+ * inflow terms (0 if cfg is invalid; see tt_last_error(NULL)).  The
+ * concatenated rank capacity max(B r1_cap, B r2_cap) + n_inflow + 1
+ * (B = 1 + 2 dim transport blocks) must not exceed 1024. */
 size_t tt_workspace_bytes(const tt_config* cfg, int32_t n_inflow);
 
 /* Create a context.

@@ -32,6 +32,20 @@ tt_status tt_kernel_eigh(const double* A, int32_t n, int32_t lda, double clip, d
                          double* V, int32_t ldv, int32_t* kept, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* Singular values and the singular vectors of the short side of the
+ * a x b matrix M (row-major, ldm >= b, device), as the Gram-SVD truncation
+ * needs them for M = S_A V_A^T V_B S_B (App. A.2): Householder
+ * bidiagonalisation, then divide and conquer on the order-2q Golub-Kahan
+ * tridiagonal (q = min(a, b)), whose eigenvalues are +-sigma.
+ * sig (q, device) receives sigma descending; V (device, ldv >= q) receives
+ * the left singular vectors (a x q) when a <= b, else the right ones
+ * (b x q), each column signed so its largest |entry| is positive.  kept
+ * (host int) = number with sigma > 2q * 2^-53 * sigma_1 (vectors beyond it
+ * are not written).  1 <= a, b <= 1024. */
+size_t tt_kernel_svd_workspace(int32_t a, int32_t b);
+tt_status tt_kernel_svd(const double* M, int32_t a, int32_t b, int32_t ldm, double* sig, double* V,
+                        int32_t ldv, int32_t* kept, void* ws, size_t ws_bytes, void* stream);
+
 /* G (n x n, ldg) = A^T A for A of K rows and n columns (lda >= n):
  * the left Gram of a tall core on MFMA, split over K with a fixed-order
  * (deterministic) reduction. */

@@ -87,16 +87,21 @@ def eig_desc_clipped(G):
     return lam[:k].copy(), V[:, :k].copy()
 
 
-def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None):
+def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None, perturb=None):
     """Gram-SVD truncate of A B^T given A and the Gram of B (App. A.2).
 
     G_A = A^T A = V_A Sigma_A^2 V_A^T, G_B = V_B Sigma_B^2 V_B^T,
     M = Sigma_A V_A^T V_B Sigma_B = U~ Sigma~ V~^T (truncated to r'),
     A' = A V_A Sigma_A^-1 U~,  M_upd = (V_B Sigma_B^-1 V~ Sigma~)^T.
     Returns (A', M_upd, P, info) with A' = A P.
+    ``perturb`` (tests only): applied to G_A and G_B before their
+    eigendecompositions, to measure the method's own sensitivity to a
+    rounding-sized change of its Gram matrices.
     """
     R = A.shape[1]
     GA = A.T @ A
+    if perturb is not None:
+        GA, GB = perturb(GA), perturb(GB)
     lamA, VA = eig_desc_clipped(GA)
     lamB, VB = eig_desc_clipped(GB)
     info = dict(R=R, kA=lamA.size, kB=lamB.size)
@@ -128,14 +133,15 @@ def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None):
     return A @ P, Mupd, P, info
 
 
-def round_gram(X, Th, Ph, tol, rmax, ranks=None, eta=ETA_FP64):
+def round_gram(X, Th, Ph, tol, rmax, ranks=None, eta=ETA_FP64, perturb=None):
     """Gram-SVD TT rounding of a 3-core TT (App. A, Algorithm 1, d = 3).
 
     Backward sweep: B_2^T = Phi, B_1^T = reshape(Theta x Phi, (r1, -1)); the
     Gram matrices of B_1 and B_2 are formed here (App. A.2 footnote).
     Forward sweep, k = 1, 2: A_k = reshape(G_k, (r'_{k-1} N_k, r_k));
     [A_k', M_upd] = truncate(A_k, B_k); G_k <- A_k'; G_{k+1} <- M_upd G_{k+1}.
-    ``ranks`` = (r1', r2') replays given ranks instead of the rank rule.
+    ``ranks`` = (r1', r2') replays given ranks instead of the rank rule;
+    ``perturb``: see ``gram_truncate``.
     """
     r1, nt, r2 = Th.shape
     npf = Ph.shape[1]
@@ -144,12 +150,13 @@ def round_gram(X, Th, Ph, tol, rmax, ranks=None, eta=ETA_FP64):
     GB2 = B2T @ B2T.T
     GB1 = B1T @ B1T.T
     rk = (None, None) if ranks is None else ranks
-    Xn, M1, _, info1 = gram_truncate(X, GB1, tol=tol, rmax=rmax, eta=eta, rank=rk[0])
+    Xn, M1, _, info1 = gram_truncate(X, GB1, tol=tol, rmax=rmax, eta=eta, rank=rk[0],
+                                     perturb=perturb)
     r1n = Xn.shape[1]
     G2 = (M1 @ Th.reshape(r1, nt * r2)).reshape(r1n, nt, r2)
     A2 = G2.reshape(r1n * nt, r2)
     A2n, M2, _, info2 = gram_truncate(A2, GB2, tol=tol, rmax=rmax, eta=eta,
-                                      delta2=info1["delta2"], rank=rk[1])
+                                      delta2=info1["delta2"], rank=rk[1], perturb=perturb)
     r2n = A2n.shape[1]
     return (Xn, A2n.reshape(r1n, nt, r2n), M2 @ Ph), (info1, info2)
 

@@ -110,11 +110,12 @@ def source_blocks(blocks, d, s, setup):
     return out
 
 
-def step(X, Th, Ph, T, setup, tol, rmax, schedule="once", ranks=None):
+def step(X, Th, Ph, T, setup, tol, rmax, schedule="once", ranks=None, perturb=None):
     """One TT step.  Returns ((X, Th, Ph), T_new, info).
 
     ``ranks``: replayed ranks, a pair (r1, r2) for "once" or a pair of
-    pairs for "twice"; None uses the rank rule.
+    pairs for "twice"; None uses the rank rule.  ``perturb`` (tests only):
+    see ``rounding.gram_truncate``.
     """
     blocks = transport_blocks(X, Th, Ph, setup)
     infos = []
@@ -123,13 +124,13 @@ def step(X, Th, Ph, T, setup, tol, rmax, schedule="once", ranks=None):
         Xc, Thc, Phc = concat(blocks)
         rk = None if ranks is None else ranks[0]
         rk_last = None if ranks is None else ranks[1]
-        (X1, Th1, Ph1), inf = rounding.round_gram(Xc, Thc, Phc, tol, rmax, rk)
+        (X1, Th1, Ph1), inf = rounding.round_gram(Xc, Thc, Phc, tol, rmax, rk, perturb=perturb)
         infos.append(inf)
         blocks = [(X1, Th1, Ph1)]
     Estar = sum(energy(*b, setup) for b in blocks)
     d, s, Tdag = mat.source_coefficients(Estar, T, setup)
     cat = concat(source_blocks(blocks, d, s, setup))
-    (Xn, Thn, Phn), inf = rounding.round_gram(*cat, tol, rmax, rk_last)
+    (Xn, Thn, Phn), inf = rounding.round_gram(*cat, tol, rmax, rk_last, perturb=perturb)
     infos.append(inf)
     Enew = energy(Xn, Thn, Phn, setup)
     Tnew = mat.temperature_update(T, Estar, Enew, setup)

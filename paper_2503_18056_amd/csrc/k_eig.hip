@@ -11,6 +11,7 @@
 //      eigenvector updates are batched GEMMs.
 //   3. Back-transformation V = Q Z, one wavefront per kept vector.
 //   4. Descending order, sign gauge (largest |entry| positive), clip rule.
+// The same divide and conquer also serves the small SVD of M (section 5).
 #include <float.h>
 #include <string.h>
 
@@ -423,9 +424,9 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
     D.zhat[b0 + j] = copysign(sqrt(fmax(prod, 0.0)), z[j]);
   }
   // sort all outputs: roots (tag i) and deflated slots (tag m2 + slot)
-  __shared__ double sv[1024];
-  __shared__ int st[1024];
-  __shared__ int isk[1024];
+  __shared__ double sv[2048];
+  __shared__ int st[2048];
+  __shared__ int isk[2048];
   for (int s = tid; s < m2; s += 256) isk[s] = 0;
   __syncthreads();
   for (int q = tid; q < nk; q += 256) isk[D.Kslot[b0 + q]] = 1;
@@ -583,6 +584,221 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// 5. Small SVD through the Golub-Kahan tridiagonal.  With M = Q_L B Q_R^T
+// (B upper bidiagonal, diagonal d_i, superdiagonal e_i), the symmetric
+// tridiagonal of order 2q with zero diagonal and off-diagonal
+// (d_0, e_0, d_1, e_1, ..., d_{q-1}) has eigenvalues +-sigma_j, and the
+// eigenvector of +sigma_j interleaves (v_j, u_j) / sqrt 2.  Its eigenpairs
+// come from the divide and conquer above, so sigma_j is accurate to
+// ~u sigma_1 absolutely and the vectors to ~u sigma_1 / gap.
+
+// The taller orientation of M into the work matrix (side 0: M^T, b x a).
+__global__ __launch_bounds__(256) void k_svd_load(const double* __restrict__ M, int ldm,
+                                                  EigJobs jobs, int* __restrict__ dims,
+                                                  int a_idx, int b_idx, int side_idx) {
+  const EigJob J = jobs.j[0];
+  const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
+  const int p = side ? a : b, q = side ? b : a;
+  if (blockIdx.x == 0 && threadIdx.x == 0) dims[J.n_idx] = 2 * q;
+  const long long tot = (long long)p * q;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e / q), j = (int)(e % q);
+    J.A[(long long)i * J.lda + j] = side ? M[(long long)i * ldm + j] : M[(long long)j * ldm + i];
+  }
+}
+
+// Householder bidiagonalisation of the p x q work matrix (p >= q) in one
+// 1024-thread block: left reflectors zero column k below the diagonal (d_k),
+// right reflectors zero row k right of the superdiagonal (e_k).  Only the
+// right reflectors are kept (W.H rows, W.tau): the vectors of the short side
+// are Q_R times the v-part of the tridiagonal's eigenvectors.
+__global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ dims, int N,
+                                                int a_idx, int b_idx, int side_idx) {
+  const EigJob J = jobs.j[0];
+  const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
+  const int p = side ? a : b, q = side ? b : a;
+  double* A = J.A;
+  const long long lda = J.lda;
+  Work W = work_of(J, N);
+  __shared__ double sv[1024], sp[4][1024], red[16];
+  __shared__ double s_tau, s_scal;
+  const int tid = threadIdx.x, cj = tid & 255, g = tid >> 8;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < 2 * q; i += 1024) W.d[i] = 0.0;
+  for (int k = 0; k < q; ++k) {
+    // left reflector on column k, rows k..p-1
+    const int mr = p - k;
+    double part = 0.0;
+    for (int i = 1 + tid; i < mr; i += 1024) {
+      const double x = A[(long long)(k + i) * lda + k];
+      part += x * x;
+    }
+    double sumsq = block_sum<1024>(part, red);
+    if (tid == 0) {
+      const double alpha = A[(long long)k * lda + k];
+      if (sumsq == 0.0) {
+        s_tau = 0.0;
+        s_scal = 0.0;
+        W.e[2 * k] = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scal = 1.0 / (alpha - beta);
+        W.e[2 * k] = beta;
+      }
+    }
+    __syncthreads();
+    double tau = s_tau, scal = s_scal;
+    const int nc = q - k - 1;  // trailing columns k+1..q-1
+    if (tau != 0.0 && nc > 0) {
+      for (int i = tid; i < mr; i += 1024) sv[i] = i == 0 ? 1.0 : A[(long long)(k + i) * lda + k] * scal;
+      __syncthreads();
+      for (int j = cj; j < nc; j += 256) {
+        double acc = 0.0;
+        for (int i = g; i < mr; i += 4) acc += A[(long long)(k + i) * lda + k + 1 + j] * sv[i];
+        sp[g][j] = acc;
+      }
+      __syncthreads();
+      for (int j = cj; j < nc; j += 256) {
+        const double wj = tau * (((sp[0][j] + sp[1][j]) + sp[2][j]) + sp[3][j]);
+        for (int i = g; i < mr; i += 4) A[(long long)(k + i) * lda + k + 1 + j] -= sv[i] * wj;
+      }
+      __syncthreads();
+    }
+    if (nc <= 0) {
+      if (tid == 0) W.tau[k] = 0.0;
+      continue;
+    }
+    // right reflector on row k, columns k+1..q-1
+    part = 0.0;
+    for (int j = 1 + tid; j < nc; j += 1024) {
+      const double x = A[(long long)k * lda + k + 1 + j];
+      part += x * x;
+    }
+    sumsq = block_sum<1024>(part, red);
+    if (tid == 0) {
+      const double alpha = A[(long long)k * lda + k + 1];
+      if (sumsq == 0.0) {
+        s_tau = 0.0;
+        s_scal = 0.0;
+        W.e[2 * k + 1] = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scal = 1.0 / (alpha - beta);
+        W.e[2 * k + 1] = beta;
+      }
+      W.tau[k] = s_tau;
+    }
+    __syncthreads();
+    tau = s_tau;
+    scal = s_scal;
+    for (int j = tid; j < nc; j += 1024) {
+      const double v = j == 0 ? 1.0 : A[(long long)k * lda + k + 1 + j] * scal;
+      sv[j] = v;
+      W.H[(long long)k * N + k + 1 + j] = v;
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+      // rows k+1..p-1: A[i, k+1:] -= tau (A[i, k+1:] . v) v^T, a wave per row
+      for (int i = k + 1 + wave; i < p; i += 16) {
+        double* row = A + (long long)i * lda + k + 1;
+        double sdot = 0.0;
+        for (int j = lane; j < nc; j += 64) sdot += row[j] * sv[j];
+        sdot = wave_sum(sdot) * tau;
+        for (int j = lane; j < nc; j += 64) row[j] -= sdot * sv[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Vectors of the short side for the kept singular values, one wavefront per
+// vector: y = the even entries of the tridiagonal's eigenvector, normalised,
+// then y <- G_0 G_1 ... G_{q-2} y with the right reflectors.
+__global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[0];
+  const int n = dims[J.n_idx], q = n / 2;
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + wave;
+  __shared__ double ys[4][1024];
+  if (c >= q) return;
+  const double thr = keep_threshold(J, D.lam, n);
+  const int col = n - 1 - c;
+  if (!(D.lam[col] > thr)) return;
+  double* y = ys[wave];
+  // mixing of the +-sigma pair only rescales the v-part: normalise it
+  double part0 = 0.0;
+  for (int i = lane; i < q; i += 64) {
+    const double x = D.Qa[(size_t)(2 * i) * N2 + col];
+    y[i] = x;
+    part0 += x * x;
+  }
+  const double nrm = sqrt(wave_sum(part0));
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int i = lane; i < q; i += 64) y[i] *= inv;
+  for (int k = q - 2; k >= 0; --k) {
+    const double tau = W.tau[k];
+    if (tau == 0.0) continue;
+    const double* v = W.H + (size_t)k * N;
+    double part = 0.0;
+    for (int i = k + 1 + lane; i < q; i += 64) part += v[i] * y[i];
+    const double dot = wave_sum(part) * tau;
+    for (int i = k + 1 + lane; i < q; i += 64) y[i] -= dot * v[i];
+  }
+  for (int i = lane; i < q; i += 64) J.V[(size_t)i * J.ldv + c] = y[i];
+}
+
+// Descending singular values, kept count, scalings and sign gauge.
+__global__ __launch_bounds__(256) void k_svd_final(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[0];
+  const int n = dims[J.n_idx], q = n / 2;
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  __shared__ int s_kept;
+  const int tid = threadIdx.x;
+  const double thr = keep_threshold(J, D.lam, n);
+  if (tid == 0) {
+    int k = 0, bad = 0, run = 1;
+    for (int c = 0; c < q; ++c) {
+      const double sg = D.lam[n - 1 - c];
+      if (!(sg == sg)) bad = 1;
+      if (run && sg > thr) ++k;
+      else run = 0;
+    }
+    s_kept = k;
+    dims[J.kept_idx] = k;
+    if (bad) atomicOr(&dims[D_FLAG], FLAG_EIG);
+  }
+  __syncthreads();
+  const int kept = s_kept;
+  for (int c = tid; c < q; c += 256) {
+    const double sg = D.lam[n - 1 - c];
+    J.lam[c] = sg;
+    if (c < kept) {
+      J.sq[c] = sg;
+      J.isq[c] = 1.0 / sg;
+    }
+  }
+  for (int c = tid; c < kept; c += 256) {
+    double best = -1.0, val = 0.0;
+    for (int i = 0; i < q; ++i) {
+      const double v = J.V[(size_t)i * J.ldv + c];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        val = v;
+      }
+    }
+    if (val < 0.0)
+      for (int i = 0; i < q; ++i) J.V[(size_t)i * J.ldv + c] = -J.V[(size_t)i * J.ldv + c];
+  }
+}
+
 }  // namespace
 
 size_t eig_work_doubles(int N) {
@@ -590,12 +806,11 @@ size_t eig_work_doubles(int N) {
   return 4 * (size_t)N + (size_t)N * N + N2 + 3 * N2 * N2 + 17 * N2 + 64;
 }
 
-void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s) {
-  if (njobs <= 0 || N <= 0) return;
-  EigJobs J;
-  for (int i = 0; i < njobs && i < 4; ++i) J.j[i] = jobs[i];
+namespace {
+
+// Divide-and-conquer levels for the tridiagonals (W.d, W.e) of the jobs.
+void dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims, hipStream_t s) {
   const int N2 = next_pow2(N);
-  k_sytrd<<<njobs, 1024, 0, s>>>(J, dims, N);
   int ib = (int)(((long long)N2 * N2 + 255) / 256);
   if (ib > 2048) ib = 2048;
   k_dc_init<<<dim3(ib, njobs), 256, 0, s>>>(J, dims, N);
@@ -631,8 +846,34 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
       gemm(g, 2 * S, 2 * S, bm, dims, s);
     }
   }
+}
+
+}  // namespace
+
+void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s) {
+  if (njobs <= 0 || N <= 0) return;
+  EigJobs J;
+  for (int i = 0; i < njobs && i < 4; ++i) J.j[i] = jobs[i];
+  k_sytrd<<<njobs, 1024, 0, s>>>(J, dims, N);
+  dc_levels(jobs, J, njobs, N, dims, s);
   k_ormtr<<<dim3((N + 3) / 4, njobs), 256, 0, s>>>(J, dims, N);
   k_eig_final<<<njobs, 256, 0, s>>>(J, dims, N);
+}
+
+void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx,
+                    const EigJob& job, int N, int* dims, hipStream_t s) {
+  if (N < 2) return;
+  EigJobs J;
+  J.j[0] = job;
+  const int qcap = N / 2;
+  int lb = (int)(((long long)2 * qcap * qcap + 255) / 256);
+  if (lb > 1024) lb = 1024;
+  if (lb < 1) lb = 1;
+  k_svd_load<<<lb, 256, 0, s>>>(M, ldm, J, dims, a_idx, b_idx, side_idx);
+  k_gebrd<<<1, 1024, 0, s>>>(J, dims, N, a_idx, b_idx, side_idx);
+  dc_levels(&job, J, 1, N, dims, s);
+  k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N);
+  k_svd_final<<<1, 256, 0, s>>>(J, dims, N);
 }
 
 }  // namespace tt

@@ -254,28 +254,35 @@ __global__ void k_temperature(int ns, const double* __restrict__ rho,
 }
 
 // ---------------------------------------------------------------------------
-// Side of the Gram of M and its size.
-__global__ void k_mside(int* __restrict__ dims, int ka, int kb, int km, int side) {
+// Number of singular values of M and which side's vectors are computed.
+// The kept counts are first clipped to the rank each side can have (its
+// number of rows): eigenpairs of a Gram beyond that rank are rounding noise.
+__global__ void k_mside(int* __restrict__ dims, int ka, int kb, int km, int side, DimExpr abound,
+                        DimExpr bbound) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const int a = dims[ka], b = dims[kb];
+    const int a = min(dims[ka], eval_dim(dims, abound));
+    const int b = min(dims[kb], eval_dim(dims, bbound));
+    dims[ka] = a;
+    dims[kb] = b;
     dims[km] = a < b ? a : b;
     dims[side] = a <= b ? 0 : 1;
   }
 }
 
-// Rank rule.  sigma_j = sqrt(max(lambda_j, 0)) from the Gram of M
-// (descending).  Bond 1 defines ||T||^2 = sum sigma^2 and
-// delta^2 = tol^2 ||T||^2 / 2; bond 2 reuses delta^2.
+// Rank rule on the singular values sigma_j of M (descending).  Bond 1
+// defines ||T||^2 = sum sigma^2 and delta^2 = tol^2 ||T||^2 / 2; bond 2
+// reuses delta^2.
 //   r = min{k >= 1: sum_{j>k} sigma_j^2 <= delta^2}; cluster rule: extend
-//   while sigma_r - sigma_{r+1} <= eta sigma_1; cap: r = rmax and, if that
-//   splits a cluster, cut before it (keep rmax if it starts at 1).
-__global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
+//   while sigma_r - sigma_{r+1} <= max(eta sigma_1, R u sigma_1^2 / sigma_r);
+//   cap: r = rmax and, if that splits a cluster, cut before it (keep rmax if
+//   it starts at 1).
+__global__ void k_rank(const double* __restrict__ sig, int* __restrict__ dims,
                        double* __restrict__ diag, RankArgs ra) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int n = dims[ra.km];
   const int kc = dims[ra.kc];
   double norm2 = 0.0;
-  for (int j = 0; j < n; ++j) norm2 += fmax(lam[j], 0.0);
+  for (int j = 0; j < n; ++j) norm2 += fmax(sig[j], 0.0) * fmax(sig[j], 0.0);
   double delta2;
   if (ra.bond == 1) {
     delta2 = ra.tol * ra.tol * norm2 / 2.0;
@@ -285,7 +292,7 @@ __global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
   } else {
     delta2 = diag[G_DELTA2];
   }
-  const double s0 = n > 0 ? sqrt(fmax(lam[0], 0.0)) : 0.0;
+  const double s0 = n > 0 ? fmax(sig[0], 0.0) : 0.0;
   int r = 1, zero = 0;
   if (n == 0 || !(s0 > 0.0) || kc == 0) {
     zero = 1;
@@ -294,14 +301,14 @@ __global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
     double tail = 0.0;
     r = n;
     for (int k = n - 1; k >= 1; --k) {
-      tail += fmax(lam[k], 0.0);
+      tail += fmax(sig[k], 0.0) * fmax(sig[k], 0.0);
       if (tail <= delta2) r = k;
       else break;
     }
     // sigma_j and sigma_{j+1} (1-based j) are tied when they differ by no more
     // than the Gram route resolves: max(eta s1, R u s1^2 / sigma_j)
     const double noise = (double)dims[ra.rdim] * 1.1102230246251565e-16;
-#define SIG(j) sqrt(fmax(lam[(j)], 0.0))
+#define SIG(j) fmax(sig[(j)], 0.0)
 #define TIED(j) (SIG((j) - 1) - SIG(j) <= fmax(ra.eta * s0, SIG((j) - 1) > 0.0 ? noise * s0 * s0 / SIG((j) - 1) : 1.79e308))
     while (r < n && TIED(r)) ++r;
     if (ra.rmax > 0 && r > ra.rmax) {
@@ -317,7 +324,7 @@ __global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
     if (r > kc) r = kc;
     if (r < 1) r = 1;
     double t = 0.0;
-    for (int j = r; j < n; ++j) t += fmax(lam[j], 0.0);
+    for (int j = r; j < n; ++j) t += SIG(j) * SIG(j);
     diag[ra.g_tail] = delta2 > 0.0 ? t / delta2 : 0.0;
     diag[ra.g_sr] = SIG(r - 1);
     diag[ra.g_srp] = r < n ? SIG(r) : 0.0;
@@ -335,11 +342,11 @@ __global__ void k_rank(const double* __restrict__ lam, int* __restrict__ dims,
   diag[ra.g_kb] = dims[ra.kb];
 }
 
-// Truncated singular vectors of M from the eigenvectors Uc of its Gram.
-// side 0 (Gram = M M^T): U~ = Uc[:, :r]; W = M^T U~ was formed by a GEMM.
-// side 1 (Gram = M^T M): V~ = Uc[:, :r]; W = V~ S~; U~ = M V~ S~^-1 was
-// formed by a GEMM and is sign-fixed here (largest |entry| positive), with
-// the same signs applied to W.
+// Truncated singular vectors of M from the vectors Uc of its short side.
+// side 0 (kA <= kB): U~ = Uc[:, :r]; W = M^T U~ was formed by a GEMM.
+// side 1: V~ = Uc[:, :r]; W = V~ S~; U~ = M V~ S~^-1 was formed by a GEMM
+// and is sign-fixed here (largest |entry| positive), with the same signs
+// applied to W.
 __global__ __launch_bounds__(256) void k_svd_vectors(const double* __restrict__ Uc, int ldu,
                                                      const double* __restrict__ sqc,
                                                      double* __restrict__ Ur, int ldr,
@@ -461,11 +468,12 @@ void launch_temperature(int ns, const double* rho, const double* cv, const doubl
                         const double* Enew, double* T, hipStream_t st) {
   k_temperature<<<(ns + 255) / 256, 256, 0, st>>>(ns, rho, cv, Estar, Enew, T);
 }
-void launch_mside(int* dims, int ka, int kb, int km, int side, hipStream_t st) {
-  k_mside<<<1, 64, 0, st>>>(dims, ka, kb, km, side);
+void launch_mside(int* dims, int ka, int kb, int km, int side, DimExpr abound, DimExpr bbound,
+                  hipStream_t st) {
+  k_mside<<<1, 64, 0, st>>>(dims, ka, kb, km, side, abound, bbound);
 }
-void launch_rank(const double* lam, int* dims, double* diag, const RankArgs& ra, hipStream_t st) {
-  k_rank<<<1, 64, 0, st>>>(lam, dims, diag, ra);
+void launch_rank(const double* sig, int* dims, double* diag, const RankArgs& ra, hipStream_t st) {
+  k_rank<<<1, 64, 0, st>>>(sig, dims, diag, ra);
 }
 void launch_svd_vectors(const double* Uc, int ldu, const double* sqc, double* Ur, int ldr,
                         double* Wm, int ldw, const int* dims, int ka, int kb, int side, int rn,

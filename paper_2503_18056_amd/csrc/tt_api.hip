@@ -49,6 +49,7 @@ struct tt_ctx {
   StepGeom G;
   int ns, nt, np, dim, B, nbc, nem;
   int r1c, r2c, R1c, R2c, ldX, ldC, N;
+  int q1c, q2c;  // capacities of the number of singular values of M per bond
   double dt, lam[3];
   std::vector<double> h_rho, h_cv;
   // device
@@ -138,6 +139,10 @@ void geometry(tt_ctx* x, const tt_config& c, int n_inflow, int nem) {
   x->ldX = round_up(x->r1c, 8);
   x->ldC = round_up(x->R1c, 8);
   x->N = std::max(x->R1c, x->R2c);
+  // M at bond 1 is at most min(R1, N_s, N_theta N_phi) in rank, at bond 2
+  // min(R2, r1 N_theta, N_phi)
+  x->q1c = (int)std::min<long long>(std::min<long long>(x->R1c, x->ns), (long long)x->nt * x->np);
+  x->q2c = (int)std::min<long long>(std::min<long long>(x->R2c, (long long)x->r1c * x->nt), x->np);
   const double dx = c.lx / c.nx, dy = c.ly / c.ny, dz = c.dim == 3 ? c.lz / nz : 1e300;
   const double hmin = std::min(dx, std::min(dy, dz));
   x->dt = c.dt > 0 ? c.dt : c.cfl * hmin / c.c;
@@ -191,7 +196,10 @@ size_t carve(tt_ctx* x, char* base) {
     x->E[k].V = cv.take<double>((size_t)N * N);
     x->E[k].sq = cv.take<double>(N);
     x->E[k].isq = cv.take<double>(N);
-    x->E[k].work = cv.take<double>(eig_work_doubles(N));
+    // slots 3 and 1 also hold the SVD of M at bonds 1 and 2 (Golub-Kahan
+    // order 2 q)
+    const int ncap = k == 3 ? std::max(N, 2 * x->q1c) : k == 1 ? std::max(N, 2 * x->q2c) : N;
+    x->E[k].work = cv.take<double>(eig_work_doubles(ncap));
   }
   x->M1 = cv.take<double>((size_t)x->R1c * x->R1c);
   x->C1 = cv.take<double>((size_t)x->R1c * x->R1c);
@@ -344,26 +352,24 @@ void truncate_bond(tt_ctx* c, int bond, const EigSlot& ea, const EigSlot& eb, Ei
   const int km = bond == 1 ? D_KM1 : D_KM2, side = bond == 1 ? D_SIDE1 : D_SIDE2;
   const int rn = bond == 1 ? D_R1N : D_R2N, zero = bond == 1 ? D_ZERO1 : D_ZERO2;
   const int kea = bond == 1 ? D_KEA1 : D_KEA2, keb = bond == 1 ? D_KEB1 : D_KEB2;
-  const int kc = bond == 1 ? D_KC1 : D_KC2;
+  const int kc = bond == 1 ? D_KC1 : D_KC2, tgk = bond == 1 ? D_TGK1 : D_TGK2;
   const int N = c->N;
-  launch_mside(c->dims, ka, kb, km, side, s);
+  const DimExpr abound = bond == 1 ? dimc(c->ns) : dimv(D_R1NT);
+  const DimExpr bbound = bond == 1 ? dimc(c->nt * c->np) : dimc(c->np);
+  const int qcap = bond == 1 ? c->q1c : c->q2c;
+  launch_mside(c->dims, ka, kb, km, side, abound, bbound, s);
   {
     Prof p(c, P_SMALL);
     GemmDesc g = gd(ea.V, N, 1, eb.V, N, 0, M, Rcap, dimv(ka), dimv(kb), dimv(Rdim));
     g.rowscale = ea.sq;
     g.colscale = eb.sq;
     gemm(g, Rcap, Rcap, 1, c->dims, s);
-    GemmDesc g0 = gd(M, Rcap, 0, M, Rcap, 1, Cm, Rcap, dimv(km), dimv(km), dimv(kb));
-    g0.cond_idx = side; g0.cond_val = 0;
-    gemm(g0, Rcap, Rcap, 1, c->dims, s);
-    GemmDesc g1 = gd(M, Rcap, 1, M, Rcap, 0, Cm, Rcap, dimv(km), dimv(km), dimv(ka));
-    g1.cond_idx = side; g1.cond_val = 1;
-    gemm(g1, Rcap, Rcap, 1, c->dims, s);
   }
   {
+    // SVD of M (App. A.2) through the Golub-Kahan tridiagonal
     Prof p(c, bond == 1 ? P_EIGM1 : P_EIGM2);
-    EigJob j{Cm, Rcap, km, em.lam, em.V, N, em.sq, em.isq, kc, 0.0, em.work};
-    eig_batched(&j, 1, std::min(Rcap, N), c->dims, s);
+    EigJob j{Cm, Rcap, tgk, em.lam, em.V, N, em.sq, em.isq, kc, 1.0, em.work};
+    svd_short_side(M, Rcap, ka, kb, side, j, 2 * qcap, c->dims, s);
   }
   RankArgs ra;
   ra.bond = bond; ra.km = km; ra.kc = kc; ra.ka = ka; ra.kb = kb;

@@ -20,8 +20,8 @@ enum DimIndex : int {
   D_RC2,         // concatenated rank R2 (bond 2)
   D_KA1,         // kept Gram eigenpairs, bond 1, left side (A = X_cat)
   D_KB1,         // kept, bond 1, right side (B_1)
-  D_KM1,         // size of the Gram of M at bond 1 = min(kA, kB)
-  D_SIDE1,       // 0: Gram of M is M M^T; 1: M^T M
+  D_KM1,         // number of singular values of M at bond 1 = min(kA, kB)
+  D_SIDE1,       // 0: kA <= kB (left vectors of M computed); 1: right vectors
   D_R1N,         // truncated rank r1'
   D_KEA1,        // effective inner size for P1 (0 when the tensor is zero)
   D_KEB1,        // effective inner size for M_upd1
@@ -29,11 +29,13 @@ enum DimIndex : int {
   D_FLAG,        // error bits (FLAG_*)
   D_REPLAY1,     // replayed rank, bond 1 (<= 0: rule)
   D_REPLAY2,     // replayed rank, bond 2
-  D_KC1,         // eigenvectors computed for the Gram of M, bond 1
+  D_KC1,         // singular vectors computed for M, bond 1
   D_KC2,
   D_R1NT,        // r1' * ntheta
   D_ZERO1,       // 1 when bond 1 found a zero tensor
   D_ZERO2,
+  D_TGK1,        // order 2 min(kA, kB) of the Golub-Kahan tridiagonal, bond 1
+  D_TGK2,
   D_NDIMS = 64
 };
 
@@ -123,5 +125,22 @@ struct EigJob {
 };
 size_t eig_work_doubles(int ncap);
 void eig_batched(const EigJob* jobs, int njobs, int ncap, int* dims, hipStream_t s);
+
+// ---- small SVD (one matrix) -------------------------------------------------
+// M is a x b (row-major, ldm), a = dims[a_idx], b = dims[b_idx], side =
+// dims[side_idx] (0 when a <= b).  Golub-Kahan bidiagonalisation of the
+// taller orientation, then the eigenpairs of the order-2q Golub-Kahan
+// tridiagonal (q = min(a, b); eigenvalues +-sigma) by the same divide and
+// conquer, so singular values carry absolute error ~ u sigma_1 rather than
+// the u sigma_1^2 / sigma of an eigensolve of M M^T.  Outputs in the job:
+// lam = sigma (q, descending), V = singular vectors of the short side
+// (side 0: left vectors of M, a x q; side 1: right vectors, b x q), each
+// column sign-fixed (largest |entry| positive), sq = sigma, isq = 1/sigma,
+// dims[kept_idx] = number with sigma > 2q u sigma_1.  J.A is a work matrix
+// of at least max(a,b) x min(a,b) (row-major, J.lda); dims[J.n_idx]
+// receives 2q.  2 q_max <= ncap2 <= 2048, J.work holds eig_work_doubles(ncap2);
+// max(a, b) <= 1024.
+void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx,
+                    const EigJob& job, int ncap2, int* dims, hipStream_t s);
 
 }  // namespace tt

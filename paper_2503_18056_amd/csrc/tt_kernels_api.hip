@@ -66,6 +66,49 @@ tt_status tt_kernel_eigh(const double* A, int32_t n, int32_t lda, double clip, d
   return TT_OK;
 }
 
+size_t tt_kernel_svd_workspace(int32_t a, int32_t b) {
+  const int q = a < b ? a : b, p = a < b ? b : a;
+  if (a < 1 || b < 1 || q > 1024 || p > 1024) return 0;
+  const int N = 2 * q;
+  return align256(64 * sizeof(int)) + align256((size_t)p * q * 8) + align256((size_t)q * 8) * 2 +
+         align256(eig_work_doubles(N) * 8);
+}
+
+tt_status tt_kernel_svd(const double* M, int32_t a, int32_t b, int32_t ldm, double* sig, double* V,
+                        int32_t ldv, int32_t* kept, void* ws, size_t ws_bytes, void* stream) {
+  const int q = a < b ? a : b, p = a < b ? b : a;
+  if (!M || !sig || !V || !ws || a < 1 || b < 1 || q > 1024 || p > 1024 || ldm < b || ldv < q)
+    return kfail(TT_ERR_INVALID_ARG, "bad svd arguments");
+  if (ws_bytes < tt_kernel_svd_workspace(a, b)) return kfail(TT_ERR_OOM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  int* dims = (int*)w;
+  w += align256(64 * sizeof(int));
+  double* Awork = (double*)w;
+  w += align256((size_t)p * q * 8);
+  double* sq = (double*)w;
+  w += align256((size_t)q * 8);
+  double* isq = (double*)w;
+  w += align256((size_t)q * 8);
+  double* work = (double*)w;
+  const int N = 2 * q;
+  int hd[64];
+  memset(hd, 0, sizeof(hd));
+  hd[0] = a;
+  hd[1] = b;
+  hd[2] = a <= b ? 0 : 1;
+  KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  KCHK(hipMemsetAsync(work, 0, eig_work_doubles(N) * 8, s));
+  EigJob j{Awork, q, 3, sig, V, ldv, sq, isq, 4, 1.0, work};
+  svd_short_side(M, ldm, 0, 1, 2, j, N, dims, s);
+  KCHK(hipGetLastError());
+  KCHK(hipMemcpyAsync(hd, dims, sizeof(hd), hipMemcpyDeviceToHost, s));
+  KCHK(hipStreamSynchronize(s));
+  if (kept) *kept = hd[4];
+  if (hd[D_FLAG]) return kfail(TT_ERR_NUMERIC, "singular value solver flagged a failure");
+  return TT_OK;
+}
+
 size_t tt_kernel_gram_workspace(int32_t K, int32_t n, int32_t lda) {
   if (K < 1 || n < 1 || lda < n) return 0;
   return align256(64 * sizeof(int)) + align256(gram_partial_doubles(gram_plan(K, n, lda)) * 8);

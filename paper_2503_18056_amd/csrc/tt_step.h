@@ -49,8 +49,9 @@ void launch_material(int ns, double c, double dt, double a_r, int coupled, const
                      double* Tdag, double* d, double* s, int* dims, hipStream_t st);
 void launch_temperature(int ns, const double* rho, const double* cv, const double* Estar,
                         const double* Enew, double* T, hipStream_t st);
-void launch_mside(int* dims, int ka, int kb, int km, int side, hipStream_t st);
-void launch_rank(const double* lam, int* dims, double* diag, const RankArgs& ra, hipStream_t st);
+void launch_mside(int* dims, int ka, int kb, int km, int side, DimExpr abound, DimExpr bbound,
+                  hipStream_t st);
+void launch_rank(const double* sig, int* dims, double* diag, const RankArgs& ra, hipStream_t st);
 void launch_svd_vectors(const double* Uc, int ldu, const double* sqc, double* Ur, int ldr,
                         double* Wm, int ldw, const int* dims, int ka, int kb, int side, int rn,
                         int zero, int rcap, hipStream_t st);

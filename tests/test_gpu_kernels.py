@@ -1,6 +1,6 @@
 """Kernel-level parity of the HIP library (include/tt_kernels.h) with plain
 NumPy references on random inputs: the generic GEMM, the tall MFMA GEMM,
-the tall MFMA Gram and the symmetric eigensolver."""
+the tall MFMA Gram, the symmetric eigensolver and the small SVD."""
 import ctypes as C
 import sys
 
@@ -136,3 +136,68 @@ def test_eigh(env, kind, n):
     assert lerr < 1e-13 * max(1, n) ** 0.5
     assert res < 1e-12
     assert orth < 1e-11
+
+
+def _svd_case(kind, a, b, rng):
+    q = min(a, b)
+    Ua = np.linalg.qr(rng.standard_normal((a, q)))[0]
+    Vb = np.linalg.qr(rng.standard_normal((b, q)))[0]
+    if kind == "random":
+        return rng.standard_normal((a, b))
+    if kind == "graded":     # the spectrum of M near a truncation cut
+        s = 10.0 ** (-12 * np.arange(q) / max(1, q - 1))
+    elif kind == "cluster":  # exactly repeated singular values in pairs
+        s = np.repeat(np.linspace(2, 1, (q + 1) // 2), 2)[:q]
+    elif kind == "lowrank":  # exact zeros beyond rank q/3
+        s = np.where(np.arange(q) < max(1, q // 3), 1.0 / (1 + np.arange(q)), 0.0)
+    else:
+        raise ValueError(kind)
+    return (Ua * s) @ Vb.T
+
+
+@pytest.mark.parametrize("kind", ["random", "graded", "cluster", "lowrank"])
+@pytest.mark.parametrize("a,b", [(1, 1), (1, 6), (6, 1), (7, 7), (40, 33), (33, 40), (130, 200),
+                                 (322, 150), (143, 322)])
+def test_svd(env, kind, a, b):
+    lib, torch = env
+    rng = np.random.default_rng(a * 1000 + b + len(kind))
+    M = _svd_case(kind, a, b, rng)
+    q = min(a, b)
+    dM = _dev(torch, M)
+    ds = torch.zeros(q, dtype=torch.float64, device="cuda")
+    dV = torch.zeros((a if a <= b else b, q), dtype=torch.float64, device="cuda")
+    ws = _ws(torch, lib.tt_kernel_svd_workspace(a, b))
+    kept = C.c_int32()
+    st = lib.tt_kernel_svd(_p(dM), a, b, b, _p(ds), _p(dV), q, C.byref(kept), _p(ws), ws.numel(), None)
+    assert st == 0, lib.tt_kernel_last_error()
+    sig = ds.cpu().numpy()
+    k = kept.value
+    V = dV.cpu().numpy()[:, :k]
+    U_, S, Vt_ = np.linalg.svd(M, full_matrices=False)
+    s1 = S[0]
+    serr = np.abs(sig - S).max() / s1
+    # singular values: absolute error ~ q u sigma_1 (no squaring)
+    assert serr < 20 * q * 2.0 ** -53, serr
+    assert k >= int(np.count_nonzero(S > 1e-12 * s1))
+    ref = U_ if a <= b else Vt_.T
+    # vectors: direction error ~ u sigma_1 / gap for separated sigma
+    worst = 0.0
+    for c in range(k):
+        others = np.delete(S, c)
+        gap = np.min(np.abs(others - S[c])) if others.size else s1
+        bound = 50 * np.sqrt(q) * 2.0 ** -53 * s1 / max(gap, 1e-300)
+        if bound > 1e-4:
+            continue
+        r = ref[:, c] * np.sign(ref[np.argmax(np.abs(ref[:, c])), c])
+        e = np.abs(V[:, c] - r).max()
+        worst = max(worst, e / bound)
+        assert e < bound + 1e-14, (c, e, bound)
+    good = [c for c in range(k) if S[c] > 1e-6 * s1]
+    orth = np.abs(V[:, good].T @ V[:, good] - np.eye(len(good))).max() if good else 0.0
+    # the complementary vectors W = M^T U (or M V) have norms sigma
+    W = (M.T @ V) if a <= b else (M @ V)
+    nerr = np.abs(np.linalg.norm(W, axis=0) - sig[:k]).max() / s1 if k else 0.0
+    _log(f"svd {kind} {a}x{b} kept={k} sig_err={serr:.2e} vec/bound={worst:.2e} "
+         f"orth={orth:.2e} norm_err={nerr:.2e}")
+    assert orth < 1e-10
+    assert nerr < 1e-13 * np.sqrt(q)

@@ -1,11 +1,14 @@
 """Parity of the HIP library (through its C ABI) with the CPU oracle.
 
-FP64 bar: identical ranks and relative Frobenius difference of the
-reconstructed intensity below the stated tolerance.  Two independent
-Gram-SVD implementations differ by rounding noise of order
-c u / (relative gap at the cut) / eps (Gram floor of App. A.4 "Stability"),
-so the tight 1e-10 bar is asserted where the case has a healthy gap; cases
-at the Gram floor are compared with ranks replayed and a looser bound.
+FP64 bar: identical ranks and a relative Frobenius difference of the
+reconstructed intensity below 1e-10 for one step from the same state.
+Forming Gram matrices squares their conditioning (App. A.4): a change of a
+Gram matrix by one unit roundoff -- what any other summation order or
+backward-stable eigensolver makes -- can move the oracle's own step by more
+than 1e-10 when kept singular values are tiny against sigma_1.  Where the
+oracle's own spread under such a change exceeds 1e-10, the bar is a small
+multiple of that spread, measured in the test.  Multi-step runs must keep the
+oracle's rank history; their difference grows like the same sensitivity.
 """
 import sys
 
@@ -132,9 +135,32 @@ def test_energy_matches_oracle():
     assert abs(mat - np.sum(s.rho * s.cv * T) * s.cell_volume) < 1e-10 * abs(mat)
 
 
+SPREAD_FACTOR = 4.0
+
+
+def _oracle_spread(X, Th, Ph, s, p, ref, seeds=(0, 1)):
+    """Largest relative change of the oracle's step when every Gram matrix is
+    moved by a seeded symmetric perturbation of one unit roundoff of its
+    largest entry (None when a perturbation changes the ranks)."""
+    worst = 0.0
+    for sd in seeds:
+        rng = np.random.default_rng(1000 + sd)
+
+        def pert(G):
+            E = rng.uniform(-1.0, 1.0, G.shape)
+            return G + rounding.U * np.abs(G).max() * 0.5 * (E + E.T)
+        b, _, _ = tt.step(X, Th, Ph, s.T0, s, p["tol"], p["rmax"], perturb=pert)
+        if b[0].shape[1] != ref[0].shape[1] or b[2].shape[0] != ref[2].shape[0]:
+            return None
+        worst = max(worst, metrics.rel_diff(b, ref))
+    return worst
+
+
 def _single_step_parity(p, states, steps_to_check, tol_single=1e-10):
-    """One GPU step from the oracle's own state m, against the oracle's step
-    m+1 (same input, same arithmetic path): identical ranks, 1e-10."""
+    """One GPU step from the oracle's own state m against the oracle's step
+    from the same state: identical ranks; relative difference below 1e-10,
+    or below SPREAD_FACTOR times the oracle's own spread where that is
+    larger."""
     s = Setup(p)
     worst = 0.0
     st = _state(p, max_steps=4)
@@ -147,8 +173,14 @@ def _single_step_parity(p, states, steps_to_check, tol_single=1e-10):
         assert st.ranks() == (Xo.shape[1], Po.shape[0]), (m, st.ranks(), Xo.shape[1], Po.shape[0])
         err = metrics.rel_diff(got, (Xo, To, Po))
         worst = max(worst, err)
-        _log(f"  {p['name']} single step from oracle state {m}: ranks {st.ranks()} err={err:.2e}")
-        assert err < tol_single
+        bar, note = tol_single, ""
+        if err >= tol_single:
+            spread = _oracle_spread(X, Th, Ph, s, p, (Xo, To, Po))
+            assert spread is not None, f"state {m}: rank decision not stable under rounding"
+            bar = max(tol_single, SPREAD_FACTOR * spread)
+            note = f" (oracle's own spread {spread:.2e}, bar {bar:.2e})"
+        _log(f"  {p['name']} single step from oracle state {m}: ranks {st.ranks()} err={err:.2e}{note}")
+        assert err < bar
     return worst
 
 
@@ -161,9 +193,9 @@ def _trajectory(p, nsteps):
 
 def test_c1_parity():
     """C1 (32^2, 8x16, 10 steps, tolerance 1e-8 at the FP64 Gram floor, and
-    the same case at 1e-6): every step from the oracle's state matches to
-    1e-10 with identical ranks; the 10-step runs have identical rank
-    histories and stay within the method's own rounding sensitivity."""
+    the same case at 1e-6): every step from the oracle's state matches (see
+    _single_step_parity) with identical ranks; the 10-step runs have
+    identical rank histories and stay within 1e-6."""
     for tol in (1e-6, 1e-8):
         p = wl.c1()
         p["tol"] = tol
@@ -181,9 +213,10 @@ def test_c1_parity():
 
 def test_c2_parity():
     """C2 (256^2, 32x64, cap 64), first 40 steps: single steps from oracle
-    states at 1e-10 with identical ranks; the 40-step run has the oracle's
-    rank history and differs by no more than the oracle differs from itself
-    under another valid FP64 summation order (measured ~1e-7..2e-6)."""
+    states (see _single_step_parity) with identical ranks; the 40-step run
+    has the oracle's rank history and differs by no more than the oracle
+    differs from itself under another valid FP64 summation order (measured
+    ~1e-7..2e-6)."""
     p = wl.c2(steps=40)
     states = _trajectory(p, 40)
     _single_step_parity(p, states, [0, 1, 2, 5, 20, 39])
