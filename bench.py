@@ -49,6 +49,9 @@ def cpu_baseline(p, start_cores, nsteps_target_s=15.0, max_steps=60):
         (X, Th, Ph), T, _ = tt.step(X, Th, Ph, T, s, p["tol"], p["rmax"])
         n += 1
     dt = time.perf_counter() - t0
+    if not all(np.isfinite(a).all() for a in (X, Th, Ph)):
+        return {"value": None, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+                "sample": f"oracle state became non-finite within {n} steps; no rate reported"}
     return {"value": n / dt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} consecutive steps of the same workload starting from the GPU "
                       f"state after the warmup (ranks {X.shape[1]},{Ph.shape[0]}), "
@@ -61,6 +64,9 @@ def main():
     ap.add_argument("--steps", type=int, default=380)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB before the "
+                         "warmup (a known-size kernel to scale hardware byte counters by)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the "
@@ -71,6 +77,13 @@ def main():
     from paper_2503_18056_amd import TTState
 
     W, K = args.warmup, args.steps
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p = wl.c2(steps=W + K)
     st = TTState(p, device=0, max_steps=W + K)
     if W:
