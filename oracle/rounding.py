@@ -73,6 +73,42 @@ def select_rank(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
     return r
 
 
+def rank_margin(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
+    """Smallest relative distance to its threshold among the comparisons that
+    ``select_rank`` makes for these singular values: tail(k) against delta^2
+    at the first k that passes and the one before it, and every tie test
+    sigma_j - sigma_{j+1} against its threshold.  A small margin means a
+    rounding-sized change of sigma can flip the decision (diagnostic only;
+    the rank rule itself is ``select_rank``)."""
+    sig = np.asarray(sig, float)
+    n = sig.size
+    if n == 0 or sig[0] <= 0.0 or delta2 <= 0.0:
+        return np.inf
+    sq = sig * sig
+    tail = np.concatenate([np.cumsum(sq[::-1])[::-1], [0.0]])
+    r = next(k for k in range(1, n + 1) if tail[k] <= delta2)
+    margins = [abs(tail[r] / delta2 - 1.0)]
+    if r > 1:
+        margins.append(abs(tail[r - 1] / delta2 - 1.0))
+
+    def thr(j):
+        return max(eta * sig[0], noise * sig[0] ** 2 / sig[j - 1] if sig[j - 1] > 0 else np.inf)
+
+    def test(j):
+        t = thr(j)
+        margins.append(abs((sig[j - 1] - sig[j]) / t - 1.0) if np.isfinite(t) and t > 0 else np.inf)
+        return sig[j - 1] - sig[j] <= t
+    while r < n and test(r):
+        r += 1
+    if rmax > 0 and r > rmax:
+        r = rmax
+        if r < n and test(r):
+            k = r
+            while k > 1 and test(k - 1):
+                k -= 1
+    return float(min(margins))
+
+
 def eig_desc_clipped(G):
     """Symmetric eigendecomposition, descending, gauge-fixed, clip rule."""
     R = G.shape[0]
@@ -126,6 +162,8 @@ def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None, per
     Mupd = (sig[:r, None] * Vt[:r]) @ (VB / SB[None, :]).T
     sq = sig * sig
     tail = lambda k: float(np.sum(sq[k:]))  # noqa: E731
+    if rank is None:
+        info.update(margin=rank_margin(sig, delta2, rmax, eta, noise=R * U))
     info.update(rank=r, zero=False,
                 tail_over_delta2=tail(r) / delta2 if delta2 > 0 else np.inf,
                 tail_prev_over_delta2=tail(r - 1) / delta2 if delta2 > 0 else np.inf,

@@ -62,9 +62,12 @@ __device__ inline double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // 1. Householder tridiagonalisation (lower form): for k = 0..n-3, H_k =
 // I - tau_k v v^T with v = [1, x_2..]/(alpha - beta) annihilates A[k+2:, k].
+constexpr int SYTRD_LDS_MAX = 180;  // packed lower triangle: 16290 doubles of LDS
+
 __global__ __launch_bounds__(1024) void k_sytrd(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.x];
   const int n = dims[J.n_idx];
+  if (n <= SYTRD_LDS_MAX) return;  // k_sytrd_lds
   double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
@@ -139,6 +142,91 @@ __global__ __launch_bounds__(1024) void k_sytrd(EigJobs jobs, int* __restrict__ 
   }
 }
 
+// The same reduction with the matrix resident in LDS (n <= SYTRD_LDS_MAX):
+// the lower triangle is packed, L(i, j) = Lp[i (i + 1) / 2 + j] for j <= i,
+// so every pass of a Householder step (column norm, A22 v, rank-2 update)
+// reads LDS instead of L2.  Outputs (d, e, tau, reflectors) as k_sytrd.
+__device__ inline int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+__global__ __launch_bounds__(1024) void k_sytrd_lds(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[blockIdx.x];
+  const int n = dims[J.n_idx];
+  if (n > SYTRD_LDS_MAX) return;
+  __shared__ double Lp[SYTRD_LDS_MAX * (SYTRD_LDS_MAX + 1) / 2];
+  __shared__ double sv[SYTRD_LDS_MAX], sw[SYTRD_LDS_MAX], red[16];
+  __shared__ double s_tau, s_scal;
+  const double* A = J.A;
+  const long long lda = J.lda;
+  Work W = work_of(J, N);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int i = wave; i < n; i += 16)
+    for (int j = lane; j <= i; j += 64) Lp[tri(i, j)] = A[(long long)i * lda + j];
+  __syncthreads();
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1, o = k + 1;  // trailing block rows/cols o..n-1
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += 1024) {
+      const double x = Lp[tri(o + i, k)];
+      part += x * x;
+    }
+    const double sumsq = block_sum<1024>(part, red);
+    if (tid == 0) {
+      const double alpha = Lp[tri(o, k)];
+      W.d[k] = Lp[tri(k, k)];
+      if (sumsq == 0.0) {
+        s_tau = 0.0;
+        s_scal = 0.0;
+        W.e[k] = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scal = 1.0 / (alpha - beta);
+        W.e[k] = beta;
+      }
+      W.tau[k] = s_tau;
+    }
+    __syncthreads();
+    const double tau = s_tau, scal = s_scal;
+    for (int i = tid; i < m; i += 1024) {
+      const double v = i == 0 ? 1.0 : Lp[tri(o + i, k)] * scal;
+      sv[i] = v;
+      W.H[(long long)k * N + o + i] = v;
+    }
+    __syncthreads();
+    if (tau == 0.0) continue;
+    // p = tau A22 v, a wavefront per row j
+    for (int j = wave; j < m; j += 16) {
+      double acc = 0.0;
+      for (int i = lane; i < m; i += 64)
+        acc += (i <= j ? Lp[tri(o + j, o + i)] : Lp[tri(o + i, o + j)]) * sv[i];
+      acc = wave_sum(acc);
+      if (lane == 0) sw[j] = tau * acc;
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int j = tid; j < m; j += 1024) part += sw[j] * sv[j];
+    const double pv = block_sum<1024>(part, red);
+    const double hc = 0.5 * tau * pv;
+    for (int j = tid; j < m; j += 1024) sw[j] -= hc * sv[j];
+    __syncthreads();
+    // A22 -= v w^T + w v^T on the lower triangle, a wavefront per row
+    for (int i = wave; i < m; i += 16) {
+      const double vi = sv[i], wi = sw[i];
+      double* row = Lp + tri(o + i, o);
+      for (int j = lane; j <= i; j += 64) row[j] -= vi * sw[j] + wi * sv[j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      W.d[n - 2] = Lp[tri(n - 2, n - 2)];
+      W.e[n - 2] = Lp[tri(n - 1, n - 2)];
+      W.tau[n - 2] = 0.0;
+    }
+    if (n >= 1) W.d[n - 1] = Lp[tri(n - 1, n - 1)];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 2. Tridiagonal eigenproblem by divide and conquer (Cuppen), bottom-up from
 // 1x1 leaves.  T is torn at every off-diagonal e_m into blocks coupled by
@@ -180,11 +268,11 @@ __global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
-  const long long tot = (long long)N2 * N2;
+  // only the live n x n block of Q is ever read
+  const long long tot = (long long)n * n;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
-    const int i = (int)(e / N2), j = (int)(e % N2);
-    D.Qa[e] = (i == j && i < n) ? 1.0 : 0.0;
-    D.Qb[e] = 0.0;
+    const int i = (int)(e / n), j = (int)(e % n);
+    D.Qa[(size_t)i * N2 + j] = i == j ? 1.0 : 0.0;
   }
   for (int i = blockIdx.x * 256 + threadIdx.x; i < N2; i += gridDim.x * 256) {
     double v = 0.0;
@@ -197,8 +285,15 @@ __global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__
   }
 }
 
-// Sort of two ascending halves, deflation; one wavefront per merge.
-__global__ __launch_bounds__(64) void k_dc_prep(EigJobs jobs, int* __restrict__ dims, int N, int S) {
+// Shared-memory bytes per merge element of k_dc_prep (4 doubles, 2 ints).
+constexpr int PREP_BYTES_PER = 4 * 8 + 2 * 4;
+
+// Sort of two ascending halves and deflation; one 256-thread block per
+// merge, the merge's arrays staged in LDS.  The halves are merged in
+// parallel (each element's rank in the other half by binary search; ties
+// put the left element first); the deflation sweep, which carries the last
+// kept entry along, runs on one lane over LDS.
+__global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__ dims, int N, int S) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
@@ -209,83 +304,145 @@ __global__ __launch_bounds__(64) void k_dc_prep(EigJobs jobs, int* __restrict__ 
     if (threadIdx.x == 0) D.mk[m] = -1;
     return;
   }
+  extern __shared__ double smem[];
   const int nL = S, nR = min(S, n - b0 - S), m2 = nL + nR;
+  double* dt = smem;            // original local order
+  double* zt = dt + 2 * S;
+  double* ds = zt + 2 * S;      // sorted
+  double* zs = ds + 2 * S;
+  int* perm = reinterpret_cast<int*>(zs + 2 * S);
+  int* defl = perm + 2 * S;
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
   const double beta = W.e[b0 + S - 1];
   const double sgn = beta < 0.0 ? -1.0 : 1.0;
-  // temporaries: z in rtau[b0..], d in zhat[b0..] (original local order)
-  for (int c = threadIdx.x; c < m2; c += 64) {
+  double part = 0.0, pmax = 0.0;
+  for (int c = tid; c < m2; c += 256) {
     const double zq = c < nL ? D.Qa[(size_t)(b0 + S - 1) * N2 + b0 + c]
                              : sgn * D.Qa[(size_t)(b0 + S) * N2 + b0 + c];
-    D.rtau[b0 + c] = zq;
-    D.zhat[b0 + c] = D.lam[b0 + c];
+    const double dv = D.lam[b0 + c];
+    zt[c] = zq;
+    dt[c] = dv;
+    part += zq * zq;
+    pmax = fmax(pmax, fabs(dv));
   }
+  const double nz2 = block_sum<256>(part, red);
+  for (int o = 32; o > 0; o >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, o));
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  const double* zt = D.rtau + b0;
-  const double* dt = D.zhat + b0;
-  double nz2 = 0.0;
-  for (int c = 0; c < m2; ++c) nz2 += zt[c] * zt[c];
+  if ((tid & 63) == 0) red[tid >> 6] = pmax;
+  __syncthreads();
+  const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   const double nz = sqrt(nz2);
   const double rho = fabs(beta) * nz2;
-  int i = 0, j = nL;
-  double dmax = 0.0;
-  for (int s = 0; s < m2; ++s) {
-    int src;
-    if (j >= m2 || (i < nL && dt[i] <= dt[j])) src = i++;
-    else src = j++;
-    D.perm[b0 + s] = src;
-    D.dsl[b0 + s] = dt[src];
-    D.zsl[b0 + s] = nz > 0.0 ? zt[src] / nz : 0.0;  // rows of orthogonal blocks: nz^2 = 2
-    dmax = fmax(dmax, fabs(dt[src]));
-  }
-  const double tol = 8.0 * U64 * fmax(dmax, rho);
-  double* ds = D.dsl + b0;
-  double* zs = D.zsl + b0;
-  int* defl = D.Kslot + b0;  // flags first, K list afterwards
-  int nrot = 0, p = -1;
-  for (int s = 0; s < m2; ++s) {
-    if (rho * fabs(zs[s]) <= tol) {
-      defl[s] = 1;
-      continue;
+  // parallel merge by ranks
+  for (int c = tid; c < m2; c += 256) {
+    const double x = dt[c];
+    int pos;
+    if (c < nL) {  // count right entries strictly below x
+      int lo = 0, hi = nR;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (dt[nL + mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      pos = c + lo;
+    } else {       // count left entries at or below x
+      int lo = 0, hi = nL;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (dt[mid] <= x) lo = mid + 1;
+        else hi = mid;
+      }
+      pos = (c - nL) + lo;
     }
-    defl[s] = 0;
-    if (p >= 0) {
-      const double zp = zs[p], zq = zs[s];
-      const double r = hypot(zp, zq);
-      const double c = zq / r, sn = zp / r;
-      const double t = ds[s] - ds[p];
-      if (fabs(t * c * sn) <= tol) {
-        D.rp[b0 + nrot] = p;
-        D.rq[b0 + nrot] = s;
-        D.rc[b0 + nrot] = c;
-        D.rs[b0 + nrot] = sn;
-        ++nrot;
-        const double dp = c * c * ds[p] + sn * sn * ds[s];
-        const double dq = sn * sn * ds[p] + c * c * ds[s];
-        ds[p] = dp;
-        ds[s] = dq;
-        zs[s] = r;
-        zs[p] = 0.0;
-        defl[p] = 1;
+    perm[pos] = c;
+    ds[pos] = x;
+    zs[pos] = nz > 0.0 ? zt[c] / nz : 0.0;  // rows of orthogonal blocks: nz^2 = 2
+  }
+  __syncthreads();
+  const double tol = 8.0 * U64 * fmax(dmax, rho);
+  if (tid == 0) {
+    int nrot = 0, p = -1;
+    double dp = 0.0, zp = 0.0;  // current values of entry p
+    for (int s0 = 0; s0 < m2; s0 += 8) {
+      double dd[8], zz[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        dd[t] = s0 + t < m2 ? ds[s0 + t] : 0.0;
+        zz[t] = s0 + t < m2 ? zs[s0 + t] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int sI = s0 + t;
+        if (sI >= m2) break;
+        if (rho * fabs(zz[t]) <= tol) {
+          defl[sI] = 1;
+          continue;
+        }
+        defl[sI] = 0;
+        double dcur = dd[t], zcur = zz[t];
+        if (p >= 0) {
+          const double r = hypot(zp, zcur);
+          const double c = zcur / r, sn = zp / r;
+          const double tt = dcur - dp;
+          if (fabs(tt * c * sn) <= tol) {
+            D.rp[b0 + nrot] = p;
+            D.rq[b0 + nrot] = sI;
+            D.rc[b0 + nrot] = c;
+            D.rs[b0 + nrot] = sn;
+            ++nrot;
+            const double dpn = c * c * dp + sn * sn * dcur;
+            const double dqn = sn * sn * dp + c * c * dcur;
+            ds[p] = dpn;
+            zs[p] = 0.0;
+            defl[p] = 1;
+            dcur = dqn;
+            zcur = r;
+            ds[sI] = dcur;
+            zs[sI] = zcur;
+          }
+        }
+        p = sI;
+        dp = dcur;
+        zp = zcur;
       }
     }
-    p = s;
+    D.mnrot[m] = nrot;
   }
-  int nk = 0;
-  for (int s = 0; s < m2; ++s) {
-    if (!defl[s]) {
-      D.dK[b0 + nk] = ds[s];
-      D.zK[b0 + nk] = zs[s];
-      D.ro[b0 + nk] = s;  // slot of K entry (ro reused until the secular step)
-      ++nk;
+  __syncthreads();
+  // K list (non-deflated slots in order) by a block prefix count
+  __shared__ int wcnt[4];
+  __shared__ int s_nk;
+  int base = 0;
+  for (int c0 = 0; c0 < m2; c0 += 256) {
+    const int c = c0 + tid;
+    const int keep = c < m2 && !defl[c];
+    const unsigned long long bal = __ballot(keep);
+    const int lane = tid & 63, wv = tid >> 6;
+    const int before = __popcll(bal & ((1ULL << lane) - 1ULL));
+    if (lane == 0) wcnt[wv] = __popcll(bal);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wv; ++w) off += wcnt[w];
+    if (keep) {
+      const int q = off + before;
+      D.dK[b0 + q] = ds[c];
+      D.zK[b0 + q] = zs[c];
+      D.Kslot[b0 + q] = c;
     }
+    base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
   }
-  // deflated flags are no longer needed; Kslot holds the K list
-  for (int q = 0; q < nk; ++q) D.Kslot[b0 + q] = D.ro[b0 + q];
-  D.mk[m] = nk;
-  D.mrho[m] = rho;
-  D.mnrot[m] = nrot;
-  D.mm2[m] = m2;
+  for (int c = tid; c < m2; c += 256) {
+    D.perm[b0 + c] = perm[c];
+    D.dsl[b0 + c] = ds[c];
+    D.zsl[b0 + c] = zs[c];
+  }
+  if (tid == 0) {
+    D.mk[m] = base;
+    D.mrho[m] = rho;
+    D.mm2[m] = m2;
+  }
 }
 
 // Permute the merge block's columns into slot order and apply the Givens
@@ -315,15 +472,17 @@ __global__ __launch_bounds__(256) void k_dc_rotate(EigJobs jobs, int* __restrict
   }
 }
 
-__device__ inline double secular(const double* d, const double* z, int k, int o, double tau,
+// Secular function on LDS-staged d and z^2 (the merge's K entries).
+__device__ inline double secular(const double* d, const double* z2, int k, int o, double tau,
                                  double rho, int lane) {
   double s = 0.0;
   const double dor = d[o];
-  for (int j = lane; j < k; j += 64) s += z[j] * z[j] / ((d[j] - dor) - tau);
+  for (int j = lane; j < k; j += 64) s += z2[j] / ((d[j] - dor) - tau);
   return 1.0 + rho * wave_sum(s);
 }
 
-// Roots of the secular equation, one wavefront per root.
+// Roots of the secular equation, one wavefront per root; the merge's d and
+// z^2 are staged in LDS by every block (4 roots per block).
 __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restrict__ dims, int N, int S) {
   const EigJob J = jobs.j[blockIdx.z];
   const int n = dims[J.n_idx];
@@ -332,42 +491,50 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
   const int m = blockIdx.y, b0 = m * 2 * S;
   if (b0 + S >= n) return;
   const int nk = D.mk[m];
+  if (blockIdx.x * 4 >= nk) return;
+  extern __shared__ double smem[];
+  double* d = smem;
+  double* z2 = smem + 2 * S;
+  for (int j = threadIdx.x; j < nk; j += 256) {
+    d[j] = D.dK[b0 + j];
+    const double zj = D.zK[b0 + j];
+    z2[j] = zj * zj;
+  }
+  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + wave;
   if (i >= nk) return;
-  const double* d = D.dK + b0;
-  const double* z = D.zK + b0;
   const double rho = D.mrho[m];
   int o;
   double lo, hi;
   if (i < nk - 1) {
     const double gap = d[i + 1] - d[i];
     const double mid = 0.5 * gap;
-    const double g = secular(d, z, nk, i, mid, rho, lane);
+    const double g = secular(d, z2, nk, i, mid, rho, lane);
     // Safe brackets from the secular function itself: for the root on the
     // origin's right, g(tau) <= 1 + 2 rho / gap - rho z_o^2 / tau, so
     // tau* >= rho z_o^2 / (1 + 2 rho / gap); symmetrically on the left.
     if (g >= 0.0) {
       o = i;
       hi = mid;
-      lo = 0.5 * rho * z[o] * z[o] / (1.0 + 2.0 * rho / gap);
+      lo = 0.5 * rho * z2[o] / (1.0 + 2.0 * rho / gap);
     } else {
       o = i + 1;
       lo = -(gap - mid);
-      hi = -0.5 * rho * z[o] * z[o] / fmax(1.0, 2.0 * rho / gap);
+      hi = -0.5 * rho * z2[o] / fmax(1.0, 2.0 * rho / gap);
     }
   } else {
     // last root: all other terms are negative, so tau* >= rho z_o^2
     o = nk - 1;
     hi = rho;
-    lo = 0.5 * rho * z[o] * z[o];
+    lo = 0.5 * rho * z2[o];
   }
   // an end that underflowed to zero would sit on the origin's pole
   if (lo == 0.0) lo = hi * 0x1p-60;
   if (hi == 0.0) hi = lo * 0x1p-60;
   double tau;
-  const double glo = secular(d, z, nk, o, lo, rho, lane);
-  const double ghi = secular(d, z, nk, o, hi, rho, lane);
+  const double glo = secular(d, z2, nk, o, lo, rho, lane);
+  const double ghi = secular(d, z2, nk, o, hi, rho, lane);
   if (glo >= 0.0) {
     tau = lo;
   } else if (ghi <= 0.0) {
@@ -380,7 +547,7 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
       else if (hi < 0.0 && lo < 4.0 * hi) x = -sqrt(-lo) * sqrt(-hi);
       else x = 0.5 * (lo + hi);
       if (!(x > lo && x < hi)) break;
-      const double gx = secular(d, z, nk, o, x, rho, lane);
+      const double gx = secular(d, z2, nk, o, x, rho, lane);
       if (gx < 0.0) lo = x;
       else hi = x;
     }
@@ -397,12 +564,13 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
 }
 
 // Loewner z^, eigenvectors of D + rho z^ z^^T, sorted output, U block.
+// The merge's K arrays (d, d at each root's origin, tau, z^, slots) are
+// staged in LDS.
 __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restrict__ dims, int N, int S) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
-  const int N2 = next_pow2(N);
   const int m = blockIdx.x, b0 = m * 2 * S;
   const int S2 = 2 * S;
   double* Ub = D.U + (size_t)m * S2 * S2;
@@ -410,44 +578,54 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   if (b0 + S >= n) return;  // no merge in this block; its GEMM batch is skipped
   const int nk = D.mk[m];
   const int m2 = D.mm2[m];
+  extern __shared__ double smem[];
+  double* d = smem;
+  double* dro = d + S2;
+  double* rt = dro + S2;
+  double* zh = rt + S2;
+  int* ks = reinterpret_cast<int*>(zh + S2);
   for (long long e = tid; e < (long long)m2 * S2; e += 256) Ub[e] = 0.0;
-  __syncthreads();
-  const double* d = D.dK + b0;
-  const double* z = D.zK + b0;
-  const double rho = D.mrho[m];
-  const int* ro = D.ro + b0;
-  const double* rt = D.rtau + b0;
   for (int j = tid; j < nk; j += 256) {
-    double prod = -((d[j] - d[ro[j]]) - rt[j]) / rho;
+    d[j] = D.dK[b0 + j];
+    rt[j] = D.rtau[b0 + j];
+    ks[j] = D.Kslot[b0 + j];
+  }
+  __syncthreads();
+  for (int j = tid; j < nk; j += 256) dro[j] = d[D.ro[b0 + j]];
+  __syncthreads();
+  const double rho = D.mrho[m];
+  for (int j = tid; j < nk; j += 256) {
+    const double dj = d[j];
+    double prod = -((dj - dro[j]) - rt[j]) / rho;
     for (int i = 0; i < nk; ++i)
-      if (i != j) prod *= ((d[j] - d[ro[i]]) - rt[i]) / (d[j] - d[i]);
-    D.zhat[b0 + j] = copysign(sqrt(fmax(prod, 0.0)), z[j]);
+      if (i != j) prod *= ((dj - dro[i]) - rt[i]) / (dj - d[i]);
+    zh[j] = copysign(sqrt(fmax(prod, 0.0)), D.zK[b0 + j]);
   }
   // sort all outputs: roots (tag i) and deflated slots (tag m2 + slot)
   __shared__ double sv[2048];
   __shared__ int st[2048];
   __shared__ int isk[2048];
-  for (int s = tid; s < m2; s += 256) isk[s] = 0;
+  for (int c = tid; c < m2; c += 256) isk[c] = 0;
   __syncthreads();
-  for (int q = tid; q < nk; q += 256) isk[D.Kslot[b0 + q]] = 1;
+  for (int q = tid; q < nk; q += 256) isk[ks[q]] = 1;
   __syncthreads();
   // deflated slots in slot order: position among deflated = s - #K slots before s
   __shared__ int s_bad;
   if (tid == 0) {
     int nd = 0;
     s_bad = 0;
-    for (int s = 0; s < m2; ++s)
-      if (!isk[s]) {
-        const double v = D.dsl[b0 + s];
+    for (int c = 0; c < m2; ++c)
+      if (!isk[c]) {
+        const double v = D.dsl[b0 + c];
         if (!(v == v)) s_bad = 1;
         sv[nk + nd] = v == v ? v : DBL_MAX;
-        st[nk + nd] = m2 + s;
+        st[nk + nd] = m2 + c;
         ++nd;
       }
   }
   __syncthreads();
   for (int i = tid; i < nk; i += 256) {
-    const double v = d[ro[i]] + rt[i];
+    const double v = dro[i] + rt[i];
     if (!(v == v)) s_bad = 1;
     sv[i] = v == v ? v : DBL_MAX;
     st[i] = i;
@@ -484,9 +662,10 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
       Ub[(size_t)(tag - m2) * S2 + pos] = 1.0;
     } else {
       const int i = tag;
+      const double di = dro[i], ti = rt[i];
       double nrm = 0.0;
       for (int j = 0; j < nk; ++j) {
-        const double u = D.zhat[b0 + j] / ((d[j] - d[ro[i]]) - rt[i]);
+        const double u = zh[j] / ((d[j] - di) - ti);
         nrm += u * u;
       }
       if (!(nrm > 0.0) || !(nrm < DBL_MAX)) {
@@ -495,8 +674,8 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
       }
       const double inv = 1.0 / sqrt(nrm);
       for (int j = 0; j < nk; ++j) {
-        const double u = D.zhat[b0 + j] / ((d[j] - d[ro[i]]) - rt[i]);
-        Ub[(size_t)D.Kslot[b0 + j] * S2 + pos] = u * inv;
+        const double u = zh[j] / ((d[j] - di) - ti);
+        Ub[(size_t)ks[j] * S2 + pos] = u * inv;
       }
     }
   }
@@ -594,7 +773,10 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
 // come from the divide and conquer above, so sigma_j is accurate to
 // ~u sigma_1 absolutely and the vectors to ~u sigma_1 / gap.
 
-// The taller orientation of M into the work matrix (side 0: M^T, b x a).
+constexpr int GEBRD_LDS_MAX = 16384;  // p q doubles held in LDS by k_gebrd_lds
+
+// The taller orientation of M into the work matrix (side 0: M^T, b x a);
+// only for matrices too large for k_gebrd_lds.
 __global__ __launch_bounds__(256) void k_svd_load(const double* __restrict__ M, int ldm,
                                                   EigJobs jobs, int* __restrict__ dims,
                                                   int a_idx, int b_idx, int side_idx) {
@@ -602,6 +784,7 @@ __global__ __launch_bounds__(256) void k_svd_load(const double* __restrict__ M, 
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
   if (blockIdx.x == 0 && threadIdx.x == 0) dims[J.n_idx] = 2 * q;
+  if ((long long)p * q <= GEBRD_LDS_MAX && p <= 1024) return;  // k_gebrd_lds loads M itself
   const long long tot = (long long)p * q;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
     const int i = (int)(e / q), j = (int)(e % q);
@@ -619,6 +802,7 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
   const EigJob J = jobs.j[0];
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
+  if ((long long)p * q <= GEBRD_LDS_MAX && p <= 1024) return;  // k_gebrd_lds
   double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
@@ -705,6 +889,114 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
       // rows k+1..p-1: A[i, k+1:] -= tau (A[i, k+1:] . v) v^T, a wave per row
       for (int i = k + 1 + wave; i < p; i += 16) {
         double* row = A + (long long)i * lda + k + 1;
+        double sdot = 0.0;
+        for (int j = lane; j < nc; j += 64) sdot += row[j] * sv[j];
+        sdot = wave_sum(sdot) * tau;
+        for (int j = lane; j < nc; j += 64) row[j] -= sdot * sv[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Bidiagonalisation with the p x q matrix in LDS (p q <= GEBRD_LDS_MAX,
+// p <= 1024, hence q <= 128): loads the taller orientation of M directly.
+__global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M, int ldm,
+                                                    EigJobs jobs, int* __restrict__ dims, int N,
+                                                    int a_idx, int b_idx, int side_idx) {
+  const EigJob J = jobs.j[0];
+  const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
+  const int p = side ? a : b, q = side ? b : a;
+  if ((long long)p * q > GEBRD_LDS_MAX || p > 1024) return;
+  __shared__ double A[GEBRD_LDS_MAX];
+  __shared__ double sv[1024], sp[8][128], red[16];
+  __shared__ double s_tau, s_scal;
+  Work W = work_of(J, N);
+  const int tid = threadIdx.x, cj = tid & 127, g = tid >> 7;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < p * q; e += 1024) {
+    const int i = e / q, j = e - i * q;
+    A[e] = side ? M[(long long)i * ldm + j] : M[(long long)j * ldm + i];
+  }
+  for (int i = tid; i < 2 * q; i += 1024) W.d[i] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < q; ++k) {
+    const int mr = p - k;
+    double part = 0.0;
+    for (int i = 1 + tid; i < mr; i += 1024) {
+      const double x = A[(k + i) * q + k];
+      part += x * x;
+    }
+    double sumsq = block_sum<1024>(part, red);
+    if (tid == 0) {
+      const double alpha = A[k * q + k];
+      if (sumsq == 0.0) {
+        s_tau = 0.0;
+        s_scal = 0.0;
+        W.e[2 * k] = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scal = 1.0 / (alpha - beta);
+        W.e[2 * k] = beta;
+      }
+    }
+    __syncthreads();
+    double tau = s_tau, scal = s_scal;
+    const int nc = q - k - 1;
+    if (tau != 0.0 && nc > 0) {
+      for (int i = tid; i < mr; i += 1024) sv[i] = i == 0 ? 1.0 : A[(k + i) * q + k] * scal;
+      __syncthreads();
+      if (cj < nc) {
+        double acc = 0.0;
+        for (int i = g; i < mr; i += 8) acc += A[(k + i) * q + k + 1 + cj] * sv[i];
+        sp[g][cj] = acc;
+      }
+      __syncthreads();
+      if (cj < nc) {
+        double wj = 0.0;
+        for (int t = 0; t < 8; ++t) wj += sp[t][cj];
+        wj *= tau;
+        for (int i = g; i < mr; i += 8) A[(k + i) * q + k + 1 + cj] -= sv[i] * wj;
+      }
+      __syncthreads();
+    }
+    if (nc <= 0) {
+      if (tid == 0) W.tau[k] = 0.0;
+      continue;
+    }
+    part = 0.0;
+    for (int j = 1 + tid; j < nc; j += 1024) {
+      const double x = A[k * q + k + 1 + j];
+      part += x * x;
+    }
+    sumsq = block_sum<1024>(part, red);
+    if (tid == 0) {
+      const double alpha = A[k * q + k + 1];
+      if (sumsq == 0.0) {
+        s_tau = 0.0;
+        s_scal = 0.0;
+        W.e[2 * k + 1] = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        s_tau = (beta - alpha) / beta;
+        s_scal = 1.0 / (alpha - beta);
+        W.e[2 * k + 1] = beta;
+      }
+      W.tau[k] = s_tau;
+    }
+    __syncthreads();
+    tau = s_tau;
+    scal = s_scal;
+    for (int j = tid; j < nc; j += 1024) {
+      const double v = j == 0 ? 1.0 : A[k * q + k + 1 + j] * scal;
+      sv[j] = v;
+      W.H[(long long)k * N + k + 1 + j] = v;
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int i = k + 1 + wave; i < p; i += 16) {
+        double* row = A + i * q + k + 1;
         double sdot = 0.0;
         for (int j = lane; j < nc; j += 64) sdot += row[j] * sv[j];
         sdot = wave_sum(sdot) * tau;
@@ -816,10 +1108,10 @@ void dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims
   k_dc_init<<<dim3(ib, njobs), 256, 0, s>>>(J, dims, N);
   for (int S = 1; S < N; S *= 2) {
     const int nm = (N + 2 * S - 1) / (2 * S);
-    k_dc_prep<<<dim3(nm, njobs), 64, 0, s>>>(J, dims, N, S);
+    k_dc_prep<<<dim3(nm, njobs), 256, (size_t)2 * S * PREP_BYTES_PER, s>>>(J, dims, N, S);
     k_dc_rotate<<<dim3(nm, njobs), 256, 0, s>>>(J, dims, N, S);
-    k_dc_secular<<<dim3((2 * S + 3) / 4, nm, njobs), 256, 0, s>>>(J, dims, N, S);
-    k_dc_vectors<<<dim3(nm, njobs), 256, 0, s>>>(J, dims, N, S);
+    k_dc_secular<<<dim3((2 * S + 3) / 4, nm, njobs), 256, (size_t)2 * S * 16, s>>>(J, dims, N, S);
+    k_dc_vectors<<<dim3(nm, njobs), 256, (size_t)2 * S * 36, s>>>(J, dims, N, S);
     for (int q = 0; q < njobs; ++q) {
       // Q block <- Q_rot block * U block, for every merge block of this level
       const double* wbase = jobs[q].work;
@@ -854,7 +1146,8 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   if (njobs <= 0 || N <= 0) return;
   EigJobs J;
   for (int i = 0; i < njobs && i < 4; ++i) J.j[i] = jobs[i];
-  k_sytrd<<<njobs, 1024, 0, s>>>(J, dims, N);
+  k_sytrd_lds<<<njobs, 1024, 0, s>>>(J, dims, N);
+  if (N > SYTRD_LDS_MAX) k_sytrd<<<njobs, 1024, 0, s>>>(J, dims, N);
   dc_levels(jobs, J, njobs, N, dims, s);
   k_ormtr<<<dim3((N + 3) / 4, njobs), 256, 0, s>>>(J, dims, N);
   k_eig_final<<<njobs, 256, 0, s>>>(J, dims, N);
@@ -870,6 +1163,7 @@ void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx
   if (lb > 1024) lb = 1024;
   if (lb < 1) lb = 1;
   k_svd_load<<<lb, 256, 0, s>>>(M, ldm, J, dims, a_idx, b_idx, side_idx);
+  k_gebrd_lds<<<1, 1024, 0, s>>>(M, ldm, J, dims, N, a_idx, b_idx, side_idx);
   k_gebrd<<<1, 1024, 0, s>>>(J, dims, N, a_idx, b_idx, side_idx);
   dc_levels(&job, J, 1, N, dims, s);
   k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N);

@@ -334,3 +334,17 @@ def test_tt_difference_norm_matches_dense():
     dn = np.linalg.norm(metrics.reconstruct(*A) - metrics.reconstruct(*B))
     assert abs(metrics.tt_diff_norm(A, B) - dn) < 1e-12 * dn
     assert abs(metrics.rel_diff(A, B, dense_limit=0) - metrics.rel_diff(A, B)) < 1e-12
+
+
+def test_rank_margin_flags_boundary_decisions():
+    """rank_margin is small exactly when a comparison of the rank rule sits
+    on its threshold: tail(k) = delta^2, or a tie test at its threshold."""
+    sig = np.array([1.0, 0.5, 0.1, 0.01])
+    # tail(2) = 0.0101 exactly on delta^2 -> margin 0
+    assert rounding.rank_margin(sig, 0.0101, 0) < 1e-12
+    # far from every threshold
+    m = rounding.rank_margin(sig, 0.02, 0)
+    assert m > 0.4
+    # a tie test sitting on eta sigma_1: sigma_2 - sigma_3 = eta sigma_1
+    sig2 = np.array([1.0, 0.5, 0.5 - 1e-12, 1e-3])
+    assert rounding.rank_margin(sig2, 0.3, 0) < 1e-3  # r = 2 before the tie test
