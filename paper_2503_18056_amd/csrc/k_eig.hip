@@ -153,61 +153,74 @@ __global__ __launch_bounds__(1024) void k_sytrd_lds(EigJobs jobs, int* __restric
   const int n = dims[J.n_idx];
   if (n > SYTRD_LDS_MAX) return;
   __shared__ double Lp[SYTRD_LDS_MAX * (SYTRD_LDS_MAX + 1) / 2];
-  __shared__ double sv[SYTRD_LDS_MAX], sw[SYTRD_LDS_MAX], red[16];
-  __shared__ double s_tau, s_scal;
+  __shared__ double sv[SYTRD_LDS_MAX], sw[SYTRD_LDS_MAX], sp[8][SYTRD_LDS_MAX];
+  __shared__ double s_tau;
   const double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rj = tid & 127, rc = tid >> 7;  // matvec: row, column chunk
   for (int i = wave; i < n; i += 16)
     for (int j = lane; j <= i; j += 64) Lp[tri(i, j)] = A[(long long)i * lda + j];
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1, o = k + 1;  // trailing block rows/cols o..n-1
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += 1024) {
-      const double x = Lp[tri(o + i, k)];
-      part += x * x;
-    }
-    const double sumsq = block_sum<1024>(part, red);
-    if (tid == 0) {
-      const double alpha = Lp[tri(o, k)];
-      W.d[k] = Lp[tri(k, k)];
-      if (sumsq == 0.0) {
-        s_tau = 0.0;
-        s_scal = 0.0;
-        W.e[k] = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        s_tau = (beta - alpha) / beta;
-        s_scal = 1.0 / (alpha - beta);
-        W.e[k] = beta;
+    if (wave == 0) {
+      // Householder vector of column k, by one wavefront
+      double part = 0.0;
+      for (int i = 1 + lane; i < m; i += 64) {
+        const double x = Lp[tri(o + i, k)];
+        part += x * x;
       }
-      W.tau[k] = s_tau;
+      const double sumsq = wave_sum(part);
+      const double alpha = Lp[tri(o, k)];
+      double tau, scal, beta;
+      if (sumsq == 0.0) {
+        tau = 0.0;
+        scal = 0.0;
+        beta = alpha;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      if (lane == 0) {
+        W.d[k] = Lp[tri(k, k)];
+        W.e[k] = beta;
+        W.tau[k] = tau;
+        s_tau = tau;
+      }
+      for (int i = lane; i < m; i += 64) {
+        const double v = i == 0 ? 1.0 : Lp[tri(o + i, k)] * scal;
+        sv[i] = v;
+        W.H[(long long)k * N + o + i] = v;
+      }
     }
     __syncthreads();
-    const double tau = s_tau, scal = s_scal;
-    for (int i = tid; i < m; i += 1024) {
-      const double v = i == 0 ? 1.0 : Lp[tri(o + i, k)] * scal;
-      sv[i] = v;
-      W.H[(long long)k * N + o + i] = v;
-    }
-    __syncthreads();
+    const double tau = s_tau;
     if (tau == 0.0) continue;
-    // p = tau A22 v, a wavefront per row j
-    for (int j = wave; j < m; j += 16) {
+    // partial products of A22 v: row j, columns i = rc (mod 8)
+    for (int j = rj; j < m; j += 128) {
       double acc = 0.0;
-      for (int i = lane; i < m; i += 64)
+      for (int i = rc; i < m; i += 8)
         acc += (i <= j ? Lp[tri(o + j, o + i)] : Lp[tri(o + i, o + j)]) * sv[i];
-      acc = wave_sum(acc);
-      if (lane == 0) sw[j] = tau * acc;
+      sp[rc][j] = acc;
     }
     __syncthreads();
-    part = 0.0;
-    for (int j = tid; j < m; j += 1024) part += sw[j] * sv[j];
-    const double pv = block_sum<1024>(part, red);
-    const double hc = 0.5 * tau * pv;
-    for (int j = tid; j < m; j += 1024) sw[j] -= hc * sv[j];
+    if (wave == 0) {
+      // p = tau A22 v, then w = p - (tau p.v / 2) v, by one wavefront
+      double part = 0.0;
+      for (int j = lane; j < m; j += 64) {
+        double p = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) p += sp[c][j];
+        p *= tau;
+        sw[j] = p;
+        part += p * sv[j];
+      }
+      const double hc = 0.5 * tau * wave_sum(part);
+      for (int j = lane; j < m; j += 64) sw[j] -= hc * sv[j];
+    }
     __syncthreads();
     // A22 -= v w^T + w v^T on the lower triangle, a wavefront per row
     for (int i = wave; i < m; i += 16) {
@@ -481,8 +494,18 @@ __device__ inline double secular(const double* d, const double* z2, int k, int o
   return 1.0 + rho * wave_sum(s);
 }
 
-// Roots of the secular equation, one wavefront per root; the merge's d and
-// z^2 are staged in LDS by every block (4 roots per block).
+// Roots of the secular equation f(tau) = 1 + rho sum_j z_j^2 / (delta_j - tau)
+// (delta_j = d_j - d_o, o the nearer end of the root's interval), one
+// wavefront per root, the merge's d and z^2 staged in LDS (4 roots per
+// block).  f is increasing between the poles delta_i < tau < delta_{i+1};
+// the root is kept in a bracket [lo, hi] with f(lo) < 0 < f(hi).  Each
+// iteration fits the two-pole rational model of Bunch, Nielsen and Sorensen
+// (1978): the terms left of the root, psi, and right of it, phi, are each
+// replaced by a / (delta - tau) + b matching value and slope at the current
+// iterate at their nearest pole; the model's root in the bracket is the
+// next iterate (bisection when it falls outside).  Stops when |f| is at the
+// level of its evaluation error, 8u (1 + rho sum |terms|), or at a relative
+// change of 2u.
 __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restrict__ dims, int N, int S) {
   const EigJob J = jobs.j[blockIdx.z];
   const int n = dims[J.n_idx];
@@ -532,26 +555,74 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
   // an end that underflowed to zero would sit on the origin's pole
   if (lo == 0.0) lo = hi * 0x1p-60;
   if (hi == 0.0) hi = lo * 0x1p-60;
-  double tau;
-  const double glo = secular(d, z2, nk, o, lo, rho, lane);
-  const double ghi = secular(d, z2, nk, o, hi, rho, lane);
-  if (glo >= 0.0) {
-    tau = lo;
-  } else if (ghi <= 0.0) {
-    tau = hi;
-  } else {
-    for (int it = 0; it < 300; ++it) {
-      if (hi - lo <= 4.0 * U64 * fmax(fabs(lo), fabs(hi))) break;
-      double x;
-      if (lo > 0.0 && hi > 4.0 * lo) x = sqrt(lo) * sqrt(hi);
-      else if (hi < 0.0 && lo < 4.0 * hi) x = -sqrt(-lo) * sqrt(-hi);
-      else x = 0.5 * (lo + hi);
-      if (!(x > lo && x < hi)) break;
-      const double gx = secular(d, z2, nk, o, x, rho, lane);
-      if (gx < 0.0) lo = x;
-      else hi = x;
+  const double dor = d[o];
+  // nearest poles left and right of the root, in the shifted variable
+  const double pl = d[i] - dor;
+  const bool has_right = i < nk - 1;
+  const double pr = has_right ? d[i + 1] - dor : 0.0;
+  double tau = 0.0;
+  bool done = false;
+  {
+    // the bracket ends themselves may already be the root to working accuracy
+    const double glo = secular(d, z2, nk, o, lo, rho, lane);
+    const double ghi = secular(d, z2, nk, o, hi, rho, lane);
+    if (glo >= 0.0) { tau = lo; done = true; }
+    else if (ghi <= 0.0) { tau = hi; done = true; }
+  }
+  double x = (lo > 0.0 && hi > 4.0 * lo) ? sqrt(lo) * sqrt(hi)
+           : (hi < 0.0 && lo < 4.0 * hi) ? -sqrt(-lo) * sqrt(-hi) : 0.5 * (lo + hi);
+  for (int it = 0; it < 100 && !done; ++it) {
+    // psi, psi', phi, phi' at x
+    double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
+    for (int j = lane; j < nk; j += 64) {
+      const double r = 1.0 / ((d[j] - dor) - x);
+      const double t = z2[j] * r;
+      if (j <= i) { ps += t; dps += t * r; }
+      else { ph += t; dph += t * r; }
     }
-    tau = 0.5 * (lo + hi);
+    ps = wave_sum(ps);
+    dps = wave_sum(dps);
+    ph = wave_sum(ph);
+    dph = wave_sum(dph);
+    const double f = 1.0 + rho * (ps + ph);
+    // converged once f is at the level of its own rounding error
+    if (f == 0.0 || fabs(f) <= 8.0 * U64 * (1.0 + rho * (ph - ps))) { tau = x; break; }
+    if (f < 0.0) lo = x;
+    else hi = x;
+    if (hi - lo <= 4.0 * U64 * fmax(fabs(lo), fabs(hi))) { tau = 0.5 * (lo + hi); break; }
+    // model: a0 + al / (pl - t) + ga / (pr - t) = 0
+    const double al = rho * dps * (pl - x) * (pl - x);
+    double a0 = 1.0 + rho * (ps - dps * (pl - x));
+    double xn;
+    if (has_right) {
+      const double ga = rho * dph * (pr - x) * (pr - x);
+      a0 += rho * (ph - dph * (pr - x));
+      // a0 t^2 - b t + c = 0
+      const double b = a0 * (pl + pr) + al + ga;
+      const double c = a0 * pl * pr + al * pr + ga * pl;
+      const double disc = b * b - 4.0 * a0 * c;
+      xn = NAN;
+      if (disc >= 0.0) {
+        const double sq = sqrt(disc);
+        const double qq = b >= 0.0 ? b + sq : b - sq;  // no cancellation
+        const double r1 = qq != 0.0 ? 2.0 * c / qq : NAN;
+        const double r2 = a0 != 0.0 ? qq / (2.0 * a0) : NAN;
+        if (r1 > lo && r1 < hi) xn = r1;
+        else if (r2 > lo && r2 < hi) xn = r2;
+      }
+    } else {
+      // a0 + al / (pl - t) = 0  ->  t = pl + al / a0 (phi is empty)
+      a0 += rho * ph;
+      xn = a0 != 0.0 ? pl + al / a0 : NAN;
+    }
+    if (!(xn > lo && xn < hi)) {
+      xn = (lo > 0.0 && hi > 4.0 * lo) ? sqrt(lo) * sqrt(hi)
+         : (hi < 0.0 && lo < 4.0 * hi) ? -sqrt(-lo) * sqrt(-hi) : 0.5 * (lo + hi);
+      if (!(xn > lo && xn < hi)) { tau = 0.5 * (lo + hi); break; }
+    }
+    if (fabs(xn - x) <= 2.0 * U64 * fabs(xn)) { tau = xn; break; }
+    x = xn;
+    tau = x;
   }
   if (lane == 0) {
     if (!(tau == tau) || tau == 0.0) {
@@ -774,6 +845,10 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
 // ~u sigma_1 absolutely and the vectors to ~u sigma_1 / gap.
 
 constexpr int GEBRD_LDS_MAX = 16384;  // p q doubles held in LDS by k_gebrd_lds
+__device__ inline int gebrd_ld(int q) { return q | 1; }
+__device__ inline bool gebrd_fits(int p, int q) {
+  return (long long)p * gebrd_ld(q) <= GEBRD_LDS_MAX && p <= 1024;
+}
 
 // The taller orientation of M into the work matrix (side 0: M^T, b x a);
 // only for matrices too large for k_gebrd_lds.
@@ -784,7 +859,7 @@ __global__ __launch_bounds__(256) void k_svd_load(const double* __restrict__ M, 
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
   if (blockIdx.x == 0 && threadIdx.x == 0) dims[J.n_idx] = 2 * q;
-  if ((long long)p * q <= GEBRD_LDS_MAX && p <= 1024) return;  // k_gebrd_lds loads M itself
+  if (gebrd_fits(p, q)) return;  // k_gebrd_lds loads M itself
   const long long tot = (long long)p * q;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
     const int i = (int)(e / q), j = (int)(e % q);
@@ -802,7 +877,7 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
   const EigJob J = jobs.j[0];
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
-  if ((long long)p * q <= GEBRD_LDS_MAX && p <= 1024) return;  // k_gebrd_lds
+  if (gebrd_fits(p, q)) return;  // k_gebrd_lds
   double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
@@ -899,65 +974,74 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
   }
 }
 
-// Bidiagonalisation with the p x q matrix in LDS (p q <= GEBRD_LDS_MAX,
-// p <= 1024, hence q <= 128): loads the taller orientation of M directly.
+// Bidiagonalisation with the p x q matrix in LDS (p ldq <= GEBRD_LDS_MAX,
+// ldq = q rounded up to odd so a thread per row reads distinct banks;
+// p <= 1024): loads the taller orientation of M directly.  Householder
+// vectors are formed by one wavefront; the left reflector is applied by
+// column partial sums, the right one by a thread per row.
+
 __global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M, int ldm,
                                                     EigJobs jobs, int* __restrict__ dims, int N,
                                                     int a_idx, int b_idx, int side_idx) {
   const EigJob J = jobs.j[0];
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
-  if ((long long)p * q > GEBRD_LDS_MAX || p > 1024) return;
+  if (!gebrd_fits(p, q)) return;
+  const int lq = gebrd_ld(q);
   __shared__ double A[GEBRD_LDS_MAX];
-  __shared__ double sv[1024], sp[8][128], red[16];
-  __shared__ double s_tau, s_scal;
+  __shared__ double sv[1024], sp[8][128];
+  __shared__ double s_tau;
   Work W = work_of(J, N);
   const int tid = threadIdx.x, cj = tid & 127, g = tid >> 7;
   const int wave = tid >> 6, lane = tid & 63;
   for (int e = tid; e < p * q; e += 1024) {
     const int i = e / q, j = e - i * q;
-    A[e] = side ? M[(long long)i * ldm + j] : M[(long long)j * ldm + i];
+    A[i * lq + j] = side ? M[(long long)i * ldm + j] : M[(long long)j * ldm + i];
   }
   for (int i = tid; i < 2 * q; i += 1024) W.d[i] = 0.0;
   __syncthreads();
   for (int k = 0; k < q; ++k) {
-    const int mr = p - k;
-    double part = 0.0;
-    for (int i = 1 + tid; i < mr; i += 1024) {
-      const double x = A[(k + i) * q + k];
-      part += x * x;
-    }
-    double sumsq = block_sum<1024>(part, red);
-    if (tid == 0) {
-      const double alpha = A[k * q + k];
-      if (sumsq == 0.0) {
-        s_tau = 0.0;
-        s_scal = 0.0;
-        W.e[2 * k] = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        s_tau = (beta - alpha) / beta;
-        s_scal = 1.0 / (alpha - beta);
-        W.e[2 * k] = beta;
+    const int mr = p - k, nc = q - k - 1;
+    if (wave == 0) {
+      // left reflector of column k (rows k..p-1)
+      double part = 0.0;
+      for (int i = 1 + lane; i < mr; i += 64) {
+        const double x = A[(k + i) * lq + k];
+        part += x * x;
       }
+      const double sumsq = wave_sum(part);
+      const double alpha = A[k * lq + k];
+      double tau, scal, beta;
+      if (sumsq == 0.0) {
+        tau = 0.0;
+        scal = 0.0;
+        beta = alpha;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      if (lane == 0) {
+        W.e[2 * k] = beta;
+        s_tau = tau;
+      }
+      for (int i = lane; i < mr; i += 64) sv[i] = i == 0 ? 1.0 : A[(k + i) * lq + k] * scal;
     }
     __syncthreads();
-    double tau = s_tau, scal = s_scal;
-    const int nc = q - k - 1;
+    double tau = s_tau;
     if (tau != 0.0 && nc > 0) {
-      for (int i = tid; i < mr; i += 1024) sv[i] = i == 0 ? 1.0 : A[(k + i) * q + k] * scal;
-      __syncthreads();
       if (cj < nc) {
         double acc = 0.0;
-        for (int i = g; i < mr; i += 8) acc += A[(k + i) * q + k + 1 + cj] * sv[i];
+        for (int i = g; i < mr; i += 8) acc += A[(k + i) * lq + k + 1 + cj] * sv[i];
         sp[g][cj] = acc;
       }
       __syncthreads();
       if (cj < nc) {
         double wj = 0.0;
+#pragma unroll
         for (int t = 0; t < 8; ++t) wj += sp[t][cj];
         wj *= tau;
-        for (int i = g; i < mr; i += 8) A[(k + i) * q + k + 1 + cj] -= sv[i] * wj;
+        for (int i = g; i < mr; i += 8) A[(k + i) * lq + k + 1 + cj] -= sv[i] * wj;
       }
       __syncthreads();
     }
@@ -965,42 +1049,46 @@ __global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M
       if (tid == 0) W.tau[k] = 0.0;
       continue;
     }
-    part = 0.0;
-    for (int j = 1 + tid; j < nc; j += 1024) {
-      const double x = A[k * q + k + 1 + j];
-      part += x * x;
-    }
-    sumsq = block_sum<1024>(part, red);
-    if (tid == 0) {
-      const double alpha = A[k * q + k + 1];
-      if (sumsq == 0.0) {
-        s_tau = 0.0;
-        s_scal = 0.0;
-        W.e[2 * k + 1] = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        s_tau = (beta - alpha) / beta;
-        s_scal = 1.0 / (alpha - beta);
-        W.e[2 * k + 1] = beta;
+    if (wave == 0) {
+      // right reflector of row k (columns k+1..q-1)
+      double part = 0.0;
+      for (int j = 1 + lane; j < nc; j += 64) {
+        const double x = A[k * lq + k + 1 + j];
+        part += x * x;
       }
-      W.tau[k] = s_tau;
+      const double sumsq = wave_sum(part);
+      const double alpha = A[k * lq + k + 1];
+      double tr, scal, beta;
+      if (sumsq == 0.0) {
+        tr = 0.0;
+        scal = 0.0;
+        beta = alpha;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        tr = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      if (lane == 0) {
+        W.e[2 * k + 1] = beta;
+        W.tau[k] = tr;
+        s_tau = tr;
+      }
+      for (int j = lane; j < nc; j += 64) {
+        const double v = j == 0 ? 1.0 : A[k * lq + k + 1 + j] * scal;
+        sv[j] = v;
+        W.H[(long long)k * N + k + 1 + j] = v;
+      }
     }
     __syncthreads();
     tau = s_tau;
-    scal = s_scal;
-    for (int j = tid; j < nc; j += 1024) {
-      const double v = j == 0 ? 1.0 : A[k * q + k + 1 + j] * scal;
-      sv[j] = v;
-      W.H[(long long)k * N + k + 1 + j] = v;
-    }
-    __syncthreads();
     if (tau != 0.0) {
-      for (int i = k + 1 + wave; i < p; i += 16) {
-        double* row = A + i * q + k + 1;
+      // rows k+1..p-1: A[i, k+1:] -= tau (A[i, k+1:] . v) v^T, a thread per row
+      for (int i = k + 1 + tid; i < p; i += 1024) {
+        double* row = A + i * lq + k + 1;
         double sdot = 0.0;
-        for (int j = lane; j < nc; j += 64) sdot += row[j] * sv[j];
-        sdot = wave_sum(sdot) * tau;
-        for (int j = lane; j < nc; j += 64) row[j] -= sdot * sv[j];
+        for (int j = 0; j < nc; ++j) sdot += row[j] * sv[j];
+        sdot *= tau;
+        for (int j = 0; j < nc; ++j) row[j] -= sdot * sv[j];
       }
     }
     __syncthreads();
