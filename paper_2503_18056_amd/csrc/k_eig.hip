@@ -298,6 +298,146 @@ __global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__
   }
 }
 
+// Leaves of DC_LEAF rows, solved directly: block b holds rows
+// [DC_LEAF b, DC_LEAF (b + 1)) of
+// T torn only at its two boundary off-diagonals (its diagonal loses |e| at a
+// torn boundary; inside the block T keeps its off-diagonals).  Each block
+// is diagonalised in LDS by parallel cyclic Jacobi (round-robin pairs, all
+// rotations of a round applied together), its eigenvalues sorted ascending
+// with their vectors, and written where the merges up to blocks of 32
+// would have left them: lam[block] and the diagonal block of Q.  One
+// wavefront per leaf.
+constexpr int DC_LEAF = 16;
+constexpr int LEAF_T = 64;  // one wavefront per leaf: its barriers cost next to nothing
+
+__global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restrict__ dims, int N) {
+  const EigJob J = jobs.j[blockIdx.y];
+  const int n = dims[J.n_idx];
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const int r0 = blockIdx.x * DC_LEAF;
+  if (r0 >= n) return;
+  const int nb = min(DC_LEAF, n - r0);
+  const int nbe = nb + (nb & 1);  // even count for the pairing (a decoupled pad)
+  __shared__ double A[DC_LEAF][DC_LEAF + 1], V[DC_LEAF][DC_LEAF + 1];
+  __shared__ double rc_[DC_LEAF / 2], rs_[DC_LEAF / 2];
+  __shared__ int rp_[DC_LEAF / 2], rq_[DC_LEAF / 2];
+  __shared__ int s_rot, s_ord[DC_LEAF];
+  __shared__ double s_scale;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < DC_LEAF * DC_LEAF; e += LEAF_T) {
+    const int i = e / DC_LEAF, j = e % DC_LEAF;
+    double a = 0.0;
+    if (i < nb && j < nb) {
+      const int gi = r0 + i, gj = r0 + j;
+      if (i == j) {
+        a = W.d[gi];
+        if (i == 0 && gi > 0) a -= fabs(W.e[gi - 1]);
+        if (i == nb - 1 && gi + 1 < n) a -= fabs(W.e[gi]);
+      } else if (j == i + 1) {
+        a = W.e[gi];
+      } else if (i == j + 1) {
+        a = W.e[gj];
+      }
+    }
+    A[i][j] = a;
+    V[i][j] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double f = 0.0;
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j) f += A[i][j] * A[i][j];
+    s_scale = sqrt(f);
+  }
+  __syncthreads();
+  const double tiny = U64 * s_scale;
+  const int npair = nbe / 2;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < nbe - 1; ++round) {
+      // round-robin: position 0 fixed, the others rotate
+      if (tid < npair) {
+        const int k = tid;
+        int a = k == 0 ? 0 : 1 + (k - 1 + round) % (nbe - 1);
+        int b = 1 + (nbe - 2 - k + round) % (nbe - 1);
+        if (a > b) { const int t = a; a = b; b = t; }
+        double c = 1.0, sn = 0.0;
+        if (b < nb) {
+          const double apq = A[a][b], app = A[a][a], aqq = A[b][b];
+          if (fabs(apq) > fmax(U64 * sqrt(fabs(app) * fabs(aqq)), tiny * U64) && apq != 0.0) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+            s_rot = 1;
+          }
+        }
+        rp_[k] = a;
+        rq_[k] = b;
+        rc_[k] = c;
+        rs_[k] = sn;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = tid; e < npair * DC_LEAF; e += LEAF_T) {
+        const int k = e / DC_LEAF, j = e % DC_LEAF;
+        const int a = rp_[k], b = rq_[k];
+        if (b < nb && rs_[k] != 0.0) {
+          const double c = rc_[k], sn = rs_[k];
+          const double x = A[a][j], y = A[b][j];
+          A[a][j] = c * x - sn * y;
+          A[b][j] = sn * x + c * y;
+        }
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = tid; e < npair * DC_LEAF; e += LEAF_T) {
+        const int k = e / DC_LEAF, i = e % DC_LEAF;
+        const int a = rp_[k], b = rq_[k];
+        if (b < nb && rs_[k] != 0.0) {
+          const double c = rc_[k], sn = rs_[k];
+          const double x = A[i][a], y = A[i][b];
+          A[i][a] = c * x - sn * y;
+          A[i][b] = sn * x + c * y;
+          const double vx = V[i][a], vy = V[i][b];
+          V[i][a] = c * vx - sn * vy;
+          V[i][b] = sn * vx + c * vy;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = s_rot;
+    __syncthreads();
+    if (!any) break;
+  }
+  // ascending order of the eigenvalues (stable: index breaks ties); the
+  // identity first, so a NaN (flagged below) cannot leave a slot unset
+  if (tid < DC_LEAF) s_ord[tid] = tid < nb ? tid : 0;
+  __syncthreads();
+  if (tid < nb) {
+    const double v = A[tid][tid];
+    int pos = 0;
+    for (int j = 0; j < nb; ++j) {
+      const double w = A[j][j];
+      pos += (w < v) || (w == v && j < tid);
+    }
+    s_ord[pos] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += LEAF_T) {
+    const int i = e / nb, c = e % nb;
+    D.Qa[(size_t)(r0 + i) * N2 + r0 + c] = V[i][s_ord[c]];
+  }
+  if (tid < nb) {
+    const double v = A[s_ord[tid]][s_ord[tid]];
+    if (!(v == v)) atomicOr(&dims[D_FLAG], FLAG_EIG);
+    D.lam[r0 + tid] = v;
+  }
+}
+
 // Shared-memory bytes per merge element of k_dc_prep (4 doubles, 2 ints).
 constexpr int PREP_BYTES_PER = 4 * 8 + 2 * 4;
 
@@ -1194,7 +1334,8 @@ void dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims
   int ib = (int)(((long long)N2 * N2 + 255) / 256);
   if (ib > 2048) ib = 2048;
   k_dc_init<<<dim3(ib, njobs), 256, 0, s>>>(J, dims, N);
-  for (int S = 1; S < N; S *= 2) {
+  k_dc_leaf<<<dim3((N + DC_LEAF - 1) / DC_LEAF, njobs), LEAF_T, 0, s>>>(J, dims, N);
+  for (int S = DC_LEAF; S < N; S *= 2) {
     const int nm = (N + 2 * S - 1) / (2 * S);
     k_dc_prep<<<dim3(nm, njobs), 256, (size_t)2 * S * PREP_BYTES_PER, s>>>(J, dims, N, S);
     k_dc_rotate<<<dim3(nm, njobs), 256, 0, s>>>(J, dims, N, S);
