@@ -6,7 +6,10 @@ operator, absorption/emission, TT sum by concatenation, Gram-SVD rounding
 (Gram contractions, eigensolves, truncation, core updates).  The workload is
 the crossing-beam case: 256^2 cells, 32 x 64 ordinates, kappa = 1e-3, cold
 medium, two inflow beams, tolerance 1e-6, rank cap 64, 400 steps in total
-(warmup + timed steps).  Inputs are resident in HBM before timing.
+(warmup + timed steps).  Inputs are resident in HBM before timing.  The
+same protocol is then run in the FP32-mixed precision form; its steps/s,
+speedup over FP64 and end-state difference from the FP64 run are reported
+under "fp32_mixed".
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
 this build runs on one GPU.
@@ -22,12 +25,50 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TT steps/s at 256²×2048 angles; FP32-mixed vs FP64 speedup at rel err 1e-6"
 FP64_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
 def gram_flops(ns, R1):
     """Algorithmic flops of the symmetric left Gram of an N_s x R1 core."""
     return float(ns) * R1 * (R1 + 1)
+
+
+def tt_inner(A, B):
+    """<A, B> of two three-core TTs by core contractions (no full tensor)."""
+    import numpy as np
+    XA, TA, PA = A
+    XB, TB, PB = B
+    G = XA.T @ XB                                        # r1a x r1b
+    H = np.einsum("alc,ab,bld->cd", TA, G, TB)           # r2a x r2b
+    return float(np.sum(H * (PA @ PB.T)))
+
+
+def tt_rel_diff(A, B):
+    """||A - B|| / ||B|| from inner products (resolves differences above ~1e-8)."""
+    aa, bb, ab = tt_inner(A, A), tt_inner(B, B), tt_inner(A, B)
+    return max(aa + bb - 2.0 * ab, 0.0) ** 0.5 / bb ** 0.5
+
+
+def timed_run(p, W, K, precision):
+    """Steps 1..W untimed, W+1..W+K timed (inputs resident in HBM)."""
+    import torch
+    from paper_2503_18056_amd import TTState
+    st = TTState(p, device=0, max_steps=W + K, precision=precision)
+    if W:
+        st.step(W)
+    torch.cuda.synchronize()
+    warm = st.cores()
+    r_start = st.ranks()
+    st.tt_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = st.tt_profile_read()
+    st.tt_profile_enable(False)
+    return st, t1 - t0, prof, warm, r_start
 
 
 def cpu_baseline(p, start_cores, nsteps_target_s=15.0, max_steps=60):
@@ -72,12 +113,12 @@ def main():
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the "
               "hot path on one GPU (see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
-    import torch
     import workloads as wl
-    from paper_2503_18056_amd import TTState
+    from paper_2503_18056_amd import TT_FP32_MIXED, TT_FP64
 
     W, K = args.warmup, args.steps
     if args.calib_copy_mib > 0:
+        import torch
         n = args.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -85,22 +126,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     p = wl.c2(steps=W + K)
-    st = TTState(p, device=0, max_steps=W + K)
-    if W:
-        st.step(W)
-    torch.cuda.synchronize()
-    warm_cores = st.cores() if not args.no_cpu_baseline else None
-    r_start = st.ranks()
-    st.tt_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st.step(K)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = st.tt_profile_read()
-    st.tt_profile_enable(False)
+    st, dt, prof, warm_cores, r_start = timed_run(p, W, K, TT_FP64)
     hist = st.tt_get_rank_history()
-    dt = t1 - t0
     ns = p["nx"] * p["ny"]
     nang = p["ntheta"] * p["nphi"]
     # concatenated rank R1 entering each timed step: 5 r1 + 2 inflow terms
@@ -110,6 +137,33 @@ def main():
     flops = sum(gram_flops(ns, R) for R in R1s)
     achieved = flops / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else 0.0
     breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1]} for k, v in prof.items()}
+    end64 = st.cores()
+    ranks64 = list(st.ranks())
+    st.close()
+    # the FP32-mixed precision form on the same workload and protocol
+    sm, dtm, profm, _, rm_start = timed_run(p, W, K, TT_FP32_MIXED)
+    histm = sm.tt_get_rank_history()
+    endm = sm.cores()
+    gm_ms, gm_n = profm.get("gram_tall", (0.0, 0))
+    rm_in = [rm_start] + histm[W:W + K - 1]
+    flops_m = sum(gram_flops(ns, 5 * r1 + 2) for (r1, _) in rm_in)
+    mixed = {
+        "steps_per_s": K / dtm,
+        "ms_per_step": dtm * 1e3 / K,
+        "speedup_vs_fp64": (K / dtm) / (K / dt),
+        "rel_diff_vs_fp64_gpu_end": tt_rel_diff(endm, end64),
+        "rank_history_equal_steps": sum(a == b for a, b in zip(histm, hist)),
+        "ranks_end": list(sm.ranks()),
+        "gram_kernel": {
+            "kernel": "k_gram_split (sliced Gram on FP32 MFMA, 10 slice products)",
+            "avg_launch_ms": gm_ms / gm_n if gm_n else None,
+            "achieved_algorithmic_TFLOPs": flops_m / (gm_ms * 1e-3) / 1e12 if gm_ms > 0 else 0.0,
+            "peak_fp32_mfma_TFLOPs": FP32_MFMA_PEAK_TFLOPS,
+        },
+        "kernel_breakdown_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
+                                for k, v in profm.items()},
+    }
+    sm.close()
     out = {
         "metric": METRIC,
         "value": K / dt,
@@ -128,7 +182,7 @@ def main():
                                f"{W + 1}-{W + K} of {W + K}",
                    "precision": "fp64", "nx": 256, "ny": 256, "ntheta": 32, "nphi": 64,
                    "tol": 1e-6, "rmax": 64},
-        "ranks_end": list(st.ranks()),
+        "ranks_end": ranks64,
         "zcps": ns * K / dt,
         "angle_updates_per_s": ns * nang * K / dt,
         "roofline": {
@@ -143,11 +197,11 @@ def main():
             "algorithmic_flops_per_launch_avg": flops / max(1, gram_n),
         },
         "kernel_breakdown_ms": breakdown,
+        "fp32_mixed": mixed,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, warm_cores)
     print(json.dumps(out), flush=True)
-    st.close()
 
 
 if __name__ == "__main__":

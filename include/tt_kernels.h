@@ -53,6 +53,18 @@ size_t tt_kernel_gram_workspace(int32_t K, int32_t n, int32_t lda);
 tt_status tt_kernel_gram(const double* A, int32_t K, int32_t n, int32_t lda, double* G,
                          int32_t ldg, void* ws, size_t ws_bytes, void* stream);
 
+/* G (n x n, ldg, FP64) = A^T A for an FP32 matrix A (K rows, n <= 1024
+ * columns, lda >= n): the Gram formation of the FP32-mixed precision form.
+ * Each entry is split on its column's exponent grid into four 11-bit integer
+ * slices; slice products are summed four rows at a time on FP32 MFMA, where
+ * the sums are exact, and accumulated in FP64.  G is therefore the Gram of
+ * A to within 2^-44 of the product of the two columns' largest entries per
+ * term (compensated split products; App. A.2 needs the Gram accurate down
+ * to the truncation tolerance squared). */
+size_t tt_kernel_gram_f32_workspace(int32_t K, int32_t n, int32_t lda);
+tt_status tt_kernel_gram_f32(const float* A, int32_t K, int32_t n, int32_t lda, double* G,
+                             int32_t ldg, void* ws, size_t ws_bytes, void* stream);
+
 /* C (K x n, ldc) = A (K x k, lda) B (k x n, ldb) on MFMA (the core update
  * A' = A P of App. A.2). */
 size_t tt_kernel_gemm_tall_workspace(void);

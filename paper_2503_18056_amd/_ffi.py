@@ -63,6 +63,9 @@ SIGNATURES = {
     "tt_kernel_svd_workspace": (C.c_size_t, [C.c_int32, C.c_int32]),
     "tt_kernel_svd": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, VP, VP, C.c_int32, PI, VP,
                                 C.c_size_t, VP]),
+    "tt_kernel_gram_f32_workspace": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "tt_kernel_gram_f32": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, VP, C.c_int32, VP,
+                                     C.c_size_t, VP]),
     "tt_kernel_gram_workspace": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "tt_kernel_gram": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, VP, C.c_int32, VP, C.c_size_t, VP]),
     "tt_kernel_gemm_tall_workspace": (C.c_size_t, []),

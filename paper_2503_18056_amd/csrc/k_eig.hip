@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__
 // with their vectors, and written where the merges up to blocks of 32
 // would have left them: lam[block] and the diagonal block of Q.  One
 // wavefront per leaf.
-constexpr int DC_LEAF = 16;
+constexpr int DC_LEAF = 8;
 constexpr int LEAF_T = 64;  // one wavefront per leaf: its barriers cost next to nothing
 
 __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restrict__ dims, int N) {
@@ -367,7 +367,9 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
         double c = 1.0, sn = 0.0;
         if (b < nb) {
           const double apq = A[a][b], app = A[a][a], aqq = A[b][b];
-          if (fabs(apq) > fmax(U64 * sqrt(fabs(app) * fabs(aqq)), tiny * U64) && apq != 0.0) {
+          // absolute threshold: the merges above deflate at 8 u ||T|| anyway, and a
+          // relative one would chase rounding noise next to near-zero diagonals
+          if (fabs(apq) > fmax(U64 * sqrt(fabs(app) * fabs(aqq)), 0.125 * tiny) && apq != 0.0) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -928,6 +930,28 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   for (int i = lane; i < n; i += 64) J.V[(size_t)i * J.ldv + col] = y[i];
 }
 
+// Sign gauge of columns c < ncol of V (rows < nrow): the largest-magnitude
+// entry (first on ties) made positive; a wavefront per column (256-thread
+// block, four columns at a time).
+__device__ void gauge_columns(double* V, int ldv, int nrow, int ncol) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = wave; c < ncol; c += 4) {
+    double best = -1.0, val = 0.0;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < nrow; i += 64) {
+      const double v = V[(size_t)i * ldv + c];
+      if (fabs(v) > best) { best = fabs(v); val = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b2 = __shfl_xor(best, o), v2 = __shfl_xor(val, o);
+      const int i2 = __shfl_xor(bi, o);
+      if (b2 > best || (b2 == best && i2 < bi)) { best = b2; val = v2; bi = i2; }
+    }
+    if (val < 0.0)
+      for (int i = lane; i < nrow; i += 64) V[(size_t)i * ldv + c] = -V[(size_t)i * ldv + c];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 4. Descending eigenvalues, kept count, sqrt scalings and sign gauge.
 __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict__ dims, int N) {
@@ -960,18 +984,7 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
       J.isq[c] = 1.0 / s;
     }
   }
-  for (int c = tid; c < kept; c += 256) {
-    double best = -1.0, val = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double v = J.V[(size_t)i * J.ldv + c];
-      if (fabs(v) > best) {
-        best = fabs(v);
-        val = v;
-      }
-    }
-    if (val < 0.0)
-      for (int i = 0; i < n; ++i) J.V[(size_t)i * J.ldv + c] = -J.V[(size_t)i * J.ldv + c];
-  }
+  gauge_columns(J.V, J.ldv, n, kept);
 }
 
 
@@ -1305,18 +1318,7 @@ __global__ __launch_bounds__(256) void k_svd_final(EigJobs jobs, int* __restrict
       J.isq[c] = 1.0 / sg;
     }
   }
-  for (int c = tid; c < kept; c += 256) {
-    double best = -1.0, val = 0.0;
-    for (int i = 0; i < q; ++i) {
-      const double v = J.V[(size_t)i * J.ldv + c];
-      if (fabs(v) > best) {
-        best = fabs(v);
-        val = v;
-      }
-    }
-    if (val < 0.0)
-      for (int i = 0; i < q; ++i) J.V[(size_t)i * J.ldv + c] = -J.V[(size_t)i * J.ldv + c];
-  }
+  gauge_columns(J.V, J.ldv, q, kept);
 }
 
 }  // namespace

@@ -8,6 +8,14 @@ namespace tt {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// row-slice Gram (k_gram_rows) shape
+constexpr int GR_CH = 16;
+constexpr int GR_MAXN = 384;  // columns held per LDS row
+constexpr int GR_WAVES = 8;
+constexpr int GR_THREADS = GR_WAVES * 64;
+constexpr int GR_TPW = 2;     // tasks per wavefront per pass
+
+
 // ---------------------------------------------------------------------------
 // Generic GEMM (vector FP64, 64x64 tiles, 16-deep K slabs staged in LDS).
 template <int TA, int TB>
@@ -203,6 +211,13 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   }
 }
 
+template <typename T>
+__global__ void k_gram_rows(const T* __restrict__ A, int lda, int K, int rows_per_blk, DimExpr ndim,
+                            const int* __restrict__ dims, const unsigned* __restrict__ colmax,
+                            double* __restrict__ partial);
+__global__ void k_gram_rows_reduce(const double* __restrict__ partial, int nblk, DimExpr ndim,
+                                   const int* __restrict__ dims, double* __restrict__ G, int ldg);
+
 GramPlan gram_plan(int K, int ncap, int lda) {
   GramPlan p;
   p.K = K;
@@ -218,18 +233,39 @@ GramPlan gram_plan(int K, int ncap, int lda) {
   p.kslice = (ks + 3) / 4 * 4;
   p.slices = (K + p.kslice - 1) / p.kslice;
   if (p.slices < 1) p.slices = 1;
+  // row-slice form (LDS-staged) when the columns fit one LDS row
+  p.rows_mode = ncap <= 384;
+  const int t32 = (ncap + 31) / 32;
+  p.ntask_cap = t32 * (t32 + 1) / 2;
+  int nb = (K + 63) / 64;
+  if (nb > 256) nb = 256;
+  if (nb < 1) nb = 1;
+  p.rows_per_blk = ((K + nb - 1) / nb + 15) / 16 * 16;
+  p.nblk = (K + p.rows_per_blk - 1) / p.rows_per_blk;
+  if (p.nblk < 1) p.nblk = 1;
   return p;
 }
 
-size_t gram_partial_doubles(const GramPlan& p) { return (size_t)p.slices * p.pairs * 4096; }
+size_t gram_partial_doubles(const GramPlan& p) {
+  return p.rows_mode ? (size_t)p.nblk * p.ntask_cap * 1024 : (size_t)p.slices * p.pairs * 4096;
+}
 
 void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* partial,
                        const int* dims, hipStream_t s) {
+  if (p.rows_mode) {
+    k_gram_rows<double><<<p.nblk, GR_THREADS, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n, dims, nullptr,
+                                                partial);
+    return;
+  }
   k_gram_tall<<<dim3(p.pairs, p.slices), 256, 0, s>>>(A, p.lda, p.K, p.kslice, n, dims, p.tiles,
                                                       partial);
 }
 void gram_tall_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
                       const int* dims, hipStream_t s) {
+  if (p.rows_mode) {
+    k_gram_rows_reduce<<<dim3(16, p.ntask_cap), 256, 0, s>>>(partial, p.nblk, n, dims, G, ldg);
+    return;
+  }
   k_gram_reduce<<<dim3(4, p.pairs), 256, 0, s>>>(partial, p.slices, p.pairs, p.tiles, n, dims, G,
                                                  ldg);
 }
@@ -283,6 +319,405 @@ __global__ __launch_bounds__(256) void k_gemm_tall(int K, const double* __restri
         const int j = j0 + 16 * q + l16;
         if (i < K && j < n) C[(long long)i * ldc + j] = acc[p][q][r];
       }
+}
+
+// ===========================================================================
+// FP32-mixed precision form: the N_s-long contractions on FP32 MFMA.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// D = A B + C for A 16x4, B 4x16 (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; item r of lane l is D[4 (l/16) + r][l%16]).
+__device__ inline f32x4 mfma16f(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Exponent E with |x| < 2^E for every entry of a column, from the bit
+// pattern of its largest magnitude (0 for a zero column).
+__device__ inline int col_exponent(unsigned bits) {
+  const float m = __uint_as_float(bits);
+  return m > 0.0f ? ilogbf(m) + 1 : 0;
+}
+
+// Error-free split of x (|x| < 2^E) into four integer slices of 11 bits:
+// x = 2^E (s0 2^-11 + s1 2^-22 + s2 2^-33 + s3 2^-44) + remainder below
+// 2^(E-45); |s0| <= 2^11, |s1..3| <= 2^10.  Every step is exact in FP32.
+__device__ inline void split4(float x, int E, float s[4]) {
+  float t = ldexpf(x, 11 - E);
+  s[0] = rintf(t);
+  t = (t - s[0]) * 2048.0f;
+  s[1] = rintf(t);
+  t = (t - s[1]) * 2048.0f;
+  s[2] = rintf(t);
+  t = (t - s[2]) * 2048.0f;
+  s[3] = rintf(t);
+}
+
+// Gram G = A^T A of an FP32 matrix on FP32 MFMA, exact to 2^-44 of each
+// column's largest entry (Ozaki-style error-free splitting).  Each entry is
+// split on a per-column exponent grid into 11-bit integer slices; the slice
+// pairs (s, t) with s + t <= 5 are multiplied on MFMA four rows at a time,
+// where every partial sum is an integer of at most 2^24 and so exact in FP32
+// (pairs sharing a scale 2^-11(s+t) share an accumulator when their bound
+// allows); each exact partial is flushed into FP64.  Output: the same
+// per-slice 64x64 partial tiles as k_gram_tall (reduced by k_gram_reduce).
+__global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ A, int lda, int K,
+                                                    int kslice, DimExpr ndim,
+                                                    const int* __restrict__ dims, int tiles,
+                                                    const unsigned* __restrict__ colmax,
+                                                    double* __restrict__ partial) {
+  const int n = eval_dim(dims, ndim);
+  const int pair = blockIdx.x, slice = blockIdx.y;
+  int ti = 0, rem = pair;
+  while (rem >= tiles - ti) { rem -= tiles - ti; ++ti; }
+  const int tj = ti + rem;
+  if (ti * 64 >= n || tj * 64 >= n) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int a0 = ti * 64 + wr * 32, b0 = tj * 64 + wc * 32;
+  const int col = lane & 15, krow = lane >> 4;
+  const int k_begin = slice * kslice;
+  const int k_end = min(K, k_begin + kslice);
+  const bool va0 = a0 + col < n, va1 = a0 + 16 + col < n;
+  const bool vb0 = b0 + col < n, vb1 = b0 + 16 + col < n;
+  const int ea0 = va0 ? col_exponent(colmax[a0 + col]) : 0;
+  const int ea1 = va1 ? col_exponent(colmax[a0 + 16 + col]) : 0;
+  const int eb0 = vb0 ? col_exponent(colmax[b0 + col]) : 0;
+  const int eb1 = vb1 ? col_exponent(colmax[b0 + 16 + col]) : 0;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const double sc2 = 0x1p-22, sc3 = 0x1p-33, sc4 = 0x1p-44, sc5 = 0x1p-55;
+  for (int k = k_begin; k < k_end; k += 4) {
+    const int row = k + krow;
+    const bool vr = row < k_end;
+    const float* rp = A + (long long)row * lda;
+    float xs[2][4], ys[2][4];
+    split4((vr && va0) ? rp[a0 + col] : 0.0f, ea0, xs[0]);
+    split4((vr && va1) ? rp[a0 + 16 + col] : 0.0f, ea1, xs[1]);
+    split4((vr && vb0) ? rp[b0 + col] : 0.0f, eb0, ys[0]);
+    split4((vr && vb1) ? rp[b0 + 16 + col] : 0.0f, eb1, ys[1]);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const float* x = xs[p];
+        const float* y = ys[q];
+        const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+        // scale 2^-22: (0,0)
+        const f32x4 g2 = mfma16f(x[0], y[0], z);
+        // 2^-33: (0,1) + (1,0)           <= 8 * 2^21
+        const f32x4 g3 = mfma16f(x[1], y[0], mfma16f(x[0], y[1], z));
+        // 2^-44: (0,2) + (2,0)           <= 8 * 2^21;  (1,1) <= 4 * 2^20
+        const f32x4 g4a = mfma16f(x[2], y[0], mfma16f(x[0], y[2], z));
+        const f32x4 g4b = mfma16f(x[1], y[1], z);
+        // 2^-55: (0,3) + (3,0)           <= 8 * 2^21;  (1,2) + (2,1) <= 8 * 2^20
+        const f32x4 g5a = mfma16f(x[3], y[0], mfma16f(x[0], y[3], z));
+        const f32x4 g5b = mfma16f(x[2], y[1], mfma16f(x[1], y[2], z));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double v = acc[p][q][r];
+          v = fma((double)g2[r], sc2, v);
+          v = fma((double)g3[r], sc3, v);
+          v = fma((double)g4a[r] + (double)g4b[r], sc4, v);
+          v = fma((double)g5a[r] + (double)g5b[r], sc5, v);
+          acc[p][q][r] = v;
+        }
+      }
+  }
+  const int npairs = gridDim.x;
+  double* out = partial + ((long long)slice * npairs + pair) * 4096;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = wr * 32 + 16 * p + 4 * (lane >> 4) + r;
+        const int jj = wc * 32 + 16 * q + (lane & 15);
+        const int ga = ti * 64 + ii, gb = tj * 64 + jj;
+        const int e = (ga < n ? col_exponent(colmax[ga]) : 0) + (gb < n ? col_exponent(colmax[gb]) : 0);
+        out[ii * 64 + jj] = ldexp(acc[p][q][r], e);
+      }
+}
+
+// colmax[c] = bits of max_i |A[i][c]| over i < K, c < n (FP32 A, row-major);
+// colmax must be zero on entry.  Non-negative floats order like their bits.
+__global__ __launch_bounds__(256) void k_colmax(const float* __restrict__ A, int lda, int K,
+                                                DimExpr ndim, const int* __restrict__ dims,
+                                                unsigned* __restrict__ colmax) {
+  const int n = eval_dim(dims, ndim);
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (c >= n) return;
+  const int r0 = blockIdx.y * 256 + (threadIdx.x >> 6);
+  unsigned m = 0;
+  for (int i = r0; i < K && i < blockIdx.y * 256 + 256; i += 4)
+    m = max(m, __float_as_uint(fabsf(A[(long long)i * lda + c])));
+  atomicMax(colmax + c, m);
+}
+
+__global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// C[K x n] (FP32) = A[K x k] (FP32) B[k x n] (FP64) on FP32 MFMA with B
+// split into FP32 hi + lo parts (separate accumulators); every four-term
+// partial is flushed into FP64, and C is rounded to FP32 once at the end.
+__global__ __launch_bounds__(256) void k_gemm_tall_f32(int K, const float* __restrict__ A, int lda,
+                                                       const double* __restrict__ B, int ldb,
+                                                       float* __restrict__ C, int ldc,
+                                                       DimExpr kdim, DimExpr ndim,
+                                                       const int* __restrict__ dims) {
+  const int kk = eval_dim(dims, kdim), n = eval_dim(dims, ndim);
+  const int j0b = blockIdx.x * 64, i0b = blockIdx.y * 64;
+  if (j0b >= n) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i0 = i0b + (wave >> 1) * 32, j0 = j0b + (wave & 1) * 32;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int ra0 = i0 + l16, ra1 = i0 + 16 + l16;
+  const bool vra0 = ra0 < K, vra1 = ra1 < K;
+  const bool vc0 = j0 + l16 < n, vc1 = j0 + 16 + l16 < n;
+  const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < kk; k0 += 4) {
+    const int kq = k0 + l4;
+    const bool vk = kq < kk;
+    const float x[2] = {(vk && vra0) ? A[(long long)ra0 * lda + kq] : 0.0f,
+                        (vk && vra1) ? A[(long long)ra1 * lda + kq] : 0.0f};
+    const double b0d = (vk && vc0) ? B[(long long)kq * ldb + j0 + l16] : 0.0;
+    const double b1d = (vk && vc1) ? B[(long long)kq * ldb + j0 + 16 + l16] : 0.0;
+    const float bh[2] = {(float)b0d, (float)b1d};
+    const float bl[2] = {(float)(b0d - (double)bh[0]), (float)(b1d - (double)bh[1])};
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const f32x4 hi = mfma16f(x[p], bh[q], z);
+        const f32x4 lo = mfma16f(x[p], bl[q], z);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[p][q][r] += (double)hi[r] + (double)lo[r];
+      }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * p + 4 * l4 + r;
+        const int j = j0 + 16 * q + l16;
+        if (i < K && j < n) C[(long long)i * ldc + j] = (float)acc[p][q][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Row-slice Gram: each block owns a contiguous slice of rows, stages it
+// through LDS in chunks of GR_CH rows (the next chunk is loaded into
+// registers while the current one is multiplied), and computes every
+// upper-triangular 32x32 output task of the slice from LDS, two tasks per
+// wavefront per pass, eight wavefronts per block (more passes re-stage the
+// slice).  A is read from HBM
+// once; each block writes its slice's partial Gram (tasks x 1024 doubles),
+// reduced in a fixed order by k_gram_rows_reduce.  T = double: FP64 MFMA;
+// T = float: the sliced error-free products of k_gram_split.
+
+__device__ inline void gr_task(int t, int& ti, int& tj, int T32) {
+  int a = 0, rem = t;
+  while (rem >= T32 - a) { rem -= T32 - a; ++a; }
+  ti = a;
+  tj = a + rem;
+}
+
+template <typename T>
+__global__ __launch_bounds__(GR_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gram_rows(const T* __restrict__ A, int lda, int K,
+                                                    int rows_per_blk, DimExpr ndim,
+                                                    const int* __restrict__ dims,
+                                                    const unsigned* __restrict__ colmax,
+                                                    double* __restrict__ partial) {
+  const int n = eval_dim(dims, ndim);
+  const int T32 = (n + 31) / 32, ntask = T32 * (T32 + 1) / 2;
+  const int k_begin = blockIdx.x * rows_per_blk;
+  const int k_end = min(K, k_begin + rows_per_blk);
+  __shared__ T lds[GR_CH][GR_MAXN + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int col = lane & 15, krow = lane >> 4;
+  const int nld = GR_CH * n;  // elements staged per chunk
+  constexpr int PER = (GR_CH * GR_MAXN + GR_THREADS - 1) / GR_THREADS;
+  for (int pass = 0; pass * GR_WAVES * GR_TPW < ntask; ++pass) {
+    int tI[GR_TPW], tJ[GR_TPW];
+    bool act[GR_TPW];
+    int ea[GR_TPW][2], eb[GR_TPW][2];
+#pragma unroll
+    for (int q = 0; q < GR_TPW; ++q) {
+      const int t = (pass * GR_TPW + q) * GR_WAVES + wave;
+      act[q] = t < ntask;
+      tI[q] = tJ[q] = 0;
+      if (act[q]) gr_task(t, tI[q], tJ[q], T32);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int ca = tI[q] * 32 + 16 * h + col, cb = tJ[q] * 32 + 16 * h + col;
+        ea[q][h] = (sizeof(T) == 4 && act[q] && ca < n) ? col_exponent(colmax[ca]) : 0;
+        eb[q][h] = (sizeof(T) == 4 && act[q] && cb < n) ? col_exponent(colmax[cb]) : 0;
+      }
+    }
+    f64x4 acc[GR_TPW][2][2];
+#pragma unroll
+    for (int q = 0; q < GR_TPW; ++q)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[q][a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // prefetch the first chunk
+    T nxt[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * GR_THREADS;
+      const int r = e / max(n, 1), c = e - r * max(n, 1);
+      const int row = k_begin + r;
+      nxt[u] = (e < nld && row < k_end) ? A[(long long)row * lda + c] : T(0);
+    }
+    for (int k0 = k_begin; k0 < k_end; k0 += GR_CH) {
+      __syncthreads();  // the previous chunk is no longer read
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * GR_THREADS;
+        if (e < nld) {
+          const int r = e / n, c = e - r * n;
+          lds[r][c] = nxt[u];
+        }
+      }
+      __syncthreads();
+      // load the next chunk while this one is multiplied
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * GR_THREADS;
+        const int r = e / max(n, 1), c = e - r * max(n, 1);
+        const int row = k0 + GR_CH + r;
+        nxt[u] = (e < nld && row < k_end) ? A[(long long)row * lda + c] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < GR_TPW; ++q) {
+        if (!act[q]) continue;
+        const int ca = tI[q] * 32 + col, cb = tJ[q] * 32 + col;
+#pragma unroll(sizeof(T) == 8 ? 4 : 1)
+        for (int kk = 0; kk < GR_CH; kk += 4) {
+          const int r = kk + krow;
+          const T x0 = ca < n ? lds[r][ca] : T(0), x1 = ca + 16 < n ? lds[r][ca + 16] : T(0);
+          const T y0 = cb < n ? lds[r][cb] : T(0), y1 = cb + 16 < n ? lds[r][cb + 16] : T(0);
+          if constexpr (sizeof(T) == 8) {
+            acc[q][0][0] = mfma16(x0, y0, acc[q][0][0]);
+            acc[q][0][1] = mfma16(x0, y1, acc[q][0][1]);
+            acc[q][1][0] = mfma16(x1, y0, acc[q][1][0]);
+            acc[q][1][1] = mfma16(x1, y1, acc[q][1][1]);
+          } else {
+            const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              float xv[4];
+              split4(a == 0 ? x0 : x1, ea[q][a], xv);
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                float yv[4];
+                split4(b == 0 ? y0 : y1, eb[q][b], yv);
+                const f32x4 g2 = mfma16f(xv[0], yv[0], z);
+                const f32x4 g3 = mfma16f(xv[1], yv[0], mfma16f(xv[0], yv[1], z));
+                const f32x4 g4a = mfma16f(xv[2], yv[0], mfma16f(xv[0], yv[2], z));
+                const f32x4 g4b = mfma16f(xv[1], yv[1], z);
+                const f32x4 g5a = mfma16f(xv[3], yv[0], mfma16f(xv[0], yv[3], z));
+                const f32x4 g5b = mfma16f(xv[2], yv[1], mfma16f(xv[1], yv[2], z));
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                  double v = acc[q][a][b][rr];
+                  v = fma((double)g2[rr], 0x1p-22, v);
+                  v = fma((double)g3[rr], 0x1p-33, v);
+                  v = fma((double)g4a[rr] + (double)g4b[rr], 0x1p-44, v);
+                  v = fma((double)g5a[rr] + (double)g5b[rr], 0x1p-55, v);
+                  acc[q][a][b][rr] = v;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    // write this block's partial tasks
+#pragma unroll
+    for (int q = 0; q < GR_TPW; ++q) {
+      if (!act[q]) continue;
+      const int t = (pass * GR_TPW + q) * GR_WAVES + wave;
+      double* out = partial + ((long long)blockIdx.x * ntask + t) * 1024;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            // FP64 MFMA item rr of lane l: row l/16 + 4 rr; FP32: row 4 (l/16) + rr
+            const int ii = 16 * a + (sizeof(T) == 8 ? (lane >> 4) + 4 * rr : 4 * (lane >> 4) + rr);
+            const int jj = 16 * b + (lane & 15);
+            double v = acc[q][a][b][rr];
+            if (sizeof(T) == 4) {
+              const int ga = tI[q] * 32 + ii, gb = tJ[q] * 32 + jj;
+              const int e = (ga < n ? col_exponent(colmax[ga]) : 0) + (gb < n ? col_exponent(colmax[gb]) : 0);
+              v = ldexp(v, e);
+            }
+            out[ii * 32 + jj] = v;
+          }
+    }
+  }
+}
+
+// G[a][b] = G[b][a] = sum over blocks of the partial tasks, in a fixed
+// order: four thread groups sum the blocks b = g (mod 4) for 64 elements,
+// then the four group sums are added in order.
+__global__ __launch_bounds__(256) void k_gram_rows_reduce(const double* __restrict__ partial,
+                                                          int nblk, DimExpr ndim,
+                                                          const int* __restrict__ dims,
+                                                          double* __restrict__ G, int ldg) {
+  const int n = eval_dim(dims, ndim);
+  const int T32 = (n + 31) / 32, ntask = T32 * (T32 + 1) / 2;
+  const int t = blockIdx.y;
+  if (t >= ntask) return;
+  int ti, tj;
+  gr_task(t, ti, tj, T32);
+  __shared__ double part[4][64];
+  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
+  double s = 0.0;
+  for (int b = g; b < nblk; b += 4) s += partial[((long long)b * ntask + t) * 1024 + e];
+  part[g][el] = s;
+  __syncthreads();
+  if (g != 0) return;
+  const double v = ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
+  const int ii = e >> 5, jj = e & 31;
+  const int i = ti * 32 + ii, j = tj * 32 + jj;
+  if (i >= n || j >= n) return;
+  G[(long long)i * ldg + j] = v;
+  G[(long long)j * ldg + i] = v;
+}
+
+void gram_split_partial(const GramPlan& p, const float* A, DimExpr n, unsigned* colmax,
+                        double* partial, const int* dims, hipStream_t s) {
+  k_zero_u32<<<(p.ncap + 255) / 256, 256, 0, s>>>(colmax, p.ncap);
+  k_colmax<<<dim3((p.ncap + 63) / 64, (p.K + 255) / 256), 256, 0, s>>>(A, p.lda, p.K, n, dims,
+                                                                       colmax);
+  if (p.rows_mode) {
+    k_gram_rows<float><<<p.nblk, GR_THREADS, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n, dims, colmax,
+                                               partial);
+    return;
+  }
+  k_gram_split<<<dim3(p.pairs, p.slices), 256, 0, s>>>(A, p.lda, p.K, p.kslice, n, dims, p.tiles,
+                                                       colmax, partial);
+}
+
+void gemm_tall_f32(int K, const float* A, int lda, const double* B, int ldb, float* C, int ldc,
+                   DimExpr kdim, DimExpr ndim, int ncap, const int* dims, hipStream_t s) {
+  dim3 grid((ncap + 63) / 64, (K + 63) / 64);
+  k_gemm_tall_f32<<<grid, 256, 0, s>>>(K, A, lda, B, ldb, C, ldc, kdim, ndim, dims);
 }
 
 void gemm_tall(int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,

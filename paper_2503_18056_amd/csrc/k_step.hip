@@ -13,40 +13,45 @@
 namespace tt {
 
 // ---------------------------------------------------------------------------
-// Spatial core of the concatenation, one block per cell row.
-__global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const double* __restrict__ X, int ldX,
+// Spatial core of the concatenation, a wavefront per cell row.
+// TX / TC: element type of X and X_cat (double, or float in the FP32-mixed
+// form; the arithmetic is FP64 and each entry is rounded once on store).
+template <typename TX, typename TC>
+__global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __restrict__ X, int ldX,
                                                     const double* __restrict__ bc_e,
                                                     const double* __restrict__ d,
                                                     const double* __restrict__ s,
-                                                    double* __restrict__ Xc, int ldC,
+                                                    TC* __restrict__ Xc, int ldC,
                                                     const int* __restrict__ dims, int scaled) {
-  const int i = blockIdx.x;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);  // a wavefront per cell row
+  if (i >= G.ns) return;
+  const int lane = threadIdx.x & 63;
   const int r1 = dims[D_R1];
   const int R1 = dims[D_RC1];
   const int nstencil = G.B * r1;
   const int ix = i % G.nx, iy = (i / G.nx) % G.ny, iz = i / (G.nx * G.ny);
   const int coord[3] = {ix, iy, iz};
   const double di = scaled ? d[i] : 1.0;
-  const double* xi = X + (long long)i * ldX;
-  for (int col = threadIdx.x; col < R1; col += 256) {
+  const TX* xi = X + (long long)i * ldX;
+  for (int col = lane; col < R1; col += 64) {
     double v;
     if (col < nstencil) {
       const int b = col / r1, a = col - b * r1;
       if (b == 0) {
-        v = xi[a];
+        v = (double)xi[a];
       } else {
         const int ax = (b - 1) >> 1;
         const bool minus = ((b - 1) & 1) == 0;
         const int st = G.stride[ax], na = G.n[ax], ca = coord[ax];
         double nb = 0.0;
         if (minus) {
-          if (ca > 0) nb = X[(long long)(i - st) * ldX + a];
-          else if (G.periodic[ax]) nb = X[(long long)(i + (na - 1) * st) * ldX + a];
-          v = xi[a] - nb;
+          if (ca > 0) nb = (double)X[(long long)(i - st) * ldX + a];
+          else if (G.periodic[ax]) nb = (double)X[(long long)(i + (na - 1) * st) * ldX + a];
+          v = (double)xi[a] - nb;
         } else {
-          if (ca < na - 1) nb = X[(long long)(i + st) * ldX + a];
-          else if (G.periodic[ax]) nb = X[(long long)(i - (na - 1) * st) * ldX + a];
-          v = nb - xi[a];
+          if (ca < na - 1) nb = (double)X[(long long)(i + st) * ldX + a];
+          else if (G.periodic[ax]) nb = (double)X[(long long)(i - (na - 1) * st) * ldX + a];
+          v = nb - (double)xi[a];
         }
       }
       v *= di;
@@ -55,23 +60,38 @@ __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const double* __
     } else {
       v = scaled ? s[i] : 0.0;
     }
-    Xc[(long long)i * ldC + col] = v;
+    Xc[(long long)i * ldC + col] = (TC)v;
   }
 }
 
 // Scale the transport columns of an unscaled concatenation by d_i and fill
 // the emission column with s_i (coupled material, after the Newton solve).
+template <typename TC>
 __global__ __launch_bounds__(256) void k_scale_xcat(StepGeom G, const double* __restrict__ d,
                                                     const double* __restrict__ s,
-                                                    double* __restrict__ Xc, int ldC,
+                                                    TC* __restrict__ Xc, int ldC,
                                                     const int* __restrict__ dims) {
-  const int i = blockIdx.x;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);  // a wavefront per cell row
+  if (i >= G.ns) return;
+  const int lane = threadIdx.x & 63;
   const int R1 = dims[D_RC1];
   const int ntr = R1 - G.nem;
   const double di = d[i];
-  double* row = Xc + (long long)i * ldC;
-  for (int col = threadIdx.x; col < ntr; col += 256) row[col] *= di;
-  if (G.nem && threadIdx.x == 0) row[R1 - 1] = s[i];
+  TC* row = Xc + (long long)i * ldC;
+  for (int col = lane; col < ntr; col += 64) row[col] = (TC)((double)row[col] * di);
+  if (G.nem && lane == 0) row[R1 - 1] = (TC)s[i];
+}
+
+// Core conversion between FP64 and FP32 storage (rows x cols, leading dims).
+template <typename TA, typename TB>
+__global__ void k_convert(const TA* __restrict__ a, int lda, TB* __restrict__ b, int ldb, int rows,
+                          int cols) {
+  const long long tot = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    b[(long long)i * ldb + j] = (TB)a[(long long)i * lda + j];
+  }
 }
 
 // Angular core of the concatenation: Phcat[R2c][np].
@@ -188,7 +208,8 @@ __global__ void k_theta_moment(const double* __restrict__ Th, int nt, int ldb,
   }
 }
 // E[i] = sum_{a < ncols} X[i][a] z[a]
-__global__ __launch_bounds__(256) void k_row_dot(const double* __restrict__ X, int ldX, int ns,
+template <typename TX>
+__global__ __launch_bounds__(256) void k_row_dot(const TX* __restrict__ X, int ldX, int ns,
                                                  const double* __restrict__ z, DimExpr cols,
                                                  double* __restrict__ E,
                                                  const int* __restrict__ dims) {
@@ -196,9 +217,9 @@ __global__ __launch_bounds__(256) void k_row_dot(const double* __restrict__ X, i
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + wave;
   if (i >= ns) return;
-  const double* x = X + (long long)i * ldX;
+  const TX* x = X + (long long)i * ldX;
   double s = 0.0;
-  for (int a = lane; a < nc; a += 64) s += x[a] * z[a];
+  for (int a = lane; a < nc; a += 64) s += (double)x[a] * z[a];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if (lane == 0) E[i] = s;
 }
@@ -420,11 +441,20 @@ __global__ void k_check_finite(const double* __restrict__ x, int n, int* __restr
 void launch_build_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
                        const double* d, const double* s, double* Xc, int ldC, const int* dims,
                        int scaled, hipStream_t st) {
-  k_build_xcat<<<G.ns, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims, scaled);
+  k_build_xcat<double, double><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims, scaled);
+}
+void launch_build_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
+                       const double* d, const double* s, float* Xc, int ldC, const int* dims,
+                       int scaled, hipStream_t st) {
+  k_build_xcat<float, float><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims, scaled);
 }
 void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, double* Xc, int ldC,
                        const int* dims, hipStream_t st) {
-  k_scale_xcat<<<G.ns, 256, 0, st>>>(G, d, s, Xc, ldC, dims);
+  k_scale_xcat<double><<<(G.ns + 3) / 4, 256, 0, st>>>(G, d, s, Xc, ldC, dims);
+}
+void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, float* Xc, int ldC,
+                       const int* dims, hipStream_t st) {
+  k_scale_xcat<float><<<(G.ns + 3) / 4, 256, 0, st>>>(G, d, s, Xc, ldC, dims);
 }
 void launch_build_phcat(const StepGeom& G, const double* Ph, const double* pfac,
                         const double* bc_p, double* Pc, const int* dims, hipStream_t st) {
@@ -450,13 +480,32 @@ void launch_state_as_cat(const StepGeom& G, const double* Th, const double* Ph, 
   if (blocks < 1) blocks = 1;
   k_state_as_cat<<<blocks, 256, 0, st>>>(G, Th, Ph, Tc, Pc, dims);
 }
+template <typename TX>
+static void energy_impl(const TX* X, int ldX, int ns, const double* Th, int nt, int ldb,
+                        const double* Ph, int np, const double* w, const double* v, double* pv,
+                        double* z, DimExpr r1, DimExpr r2, double inv_c, double* E,
+                        const int* dims, int rcap1, int rcap2, hipStream_t st) {
+  k_phi_moment<<<(rcap2 + 63) / 64, 64, 0, st>>>(Ph, np, v, pv, r2, dims);
+  k_theta_moment<<<(rcap1 + 63) / 64, 64, 0, st>>>(Th, nt, ldb, w, pv, z, r1, r2, inv_c, dims);
+  k_row_dot<TX><<<(ns + 3) / 4, 256, 0, st>>>(X, ldX, ns, z, r1, E, dims);
+}
 void launch_energy(const double* X, int ldX, int ns, const double* Th, int nt, int ldb,
                    const double* Ph, int np, const double* w, const double* v, double* pv,
                    double* z, DimExpr r1, DimExpr r2, double inv_c, double* E, const int* dims,
                    int rcap1, int rcap2, hipStream_t st) {
-  k_phi_moment<<<(rcap2 + 63) / 64, 64, 0, st>>>(Ph, np, v, pv, r2, dims);
-  k_theta_moment<<<(rcap1 + 63) / 64, 64, 0, st>>>(Th, nt, ldb, w, pv, z, r1, r2, inv_c, dims);
-  k_row_dot<<<(ns + 3) / 4, 256, 0, st>>>(X, ldX, ns, z, r1, E, dims);
+  energy_impl(X, ldX, ns, Th, nt, ldb, Ph, np, w, v, pv, z, r1, r2, inv_c, E, dims, rcap1, rcap2, st);
+}
+void launch_energy(const float* X, int ldX, int ns, const double* Th, int nt, int ldb,
+                   const double* Ph, int np, const double* w, const double* v, double* pv,
+                   double* z, DimExpr r1, DimExpr r2, double inv_c, double* E, const int* dims,
+                   int rcap1, int rcap2, hipStream_t st) {
+  energy_impl(X, ldX, ns, Th, nt, ldb, Ph, np, w, v, pv, z, r1, r2, inv_c, E, dims, rcap1, rcap2, st);
+}
+void launch_convert(const double* a, int lda, float* b, int ldb, int rows, int cols, hipStream_t st) {
+  k_convert<double, float><<<1024, 256, 0, st>>>(a, lda, b, ldb, rows, cols);
+}
+void launch_convert(const float* a, int lda, double* b, int ldb, int rows, int cols, hipStream_t st) {
+  k_convert<float, double><<<1024, 256, 0, st>>>(a, lda, b, ldb, rows, cols);
 }
 void launch_material(int ns, double c, double dt, double a_r, int coupled, const double* kappa,
                      const double* rho, const double* cv, const double* T, const double* Estar,

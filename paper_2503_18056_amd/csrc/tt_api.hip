@@ -58,6 +58,9 @@ struct tt_ctx {
   double *w, *v, *tfac, *pfac, *bc_e, *bc_t, *bc_p;
   double *kappa, *rho, *cv, *T, *d, *s, *Estar, *Enew, *Tdag;
   double *X, *Xn, *Th, *Ph;
+  bool mixed = false;        // TT_FP32_MIXED: X and X_cat stored in FP32
+  float *Xf, *Xnf, *Xcatf;   // FP32 state / update / concatenation (mixed form only)
+  unsigned* colmax;          // per-column max |X_cat| bits for the sliced Gram
   double *Thcat, *Phcat, *Xcat, *gpart;
   double *GA, *GB1, *GR3, *GL2, *T1;
   EigSlot E[4];
@@ -102,7 +105,7 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
   if (!(c->lx > 0) || !(c->ly > 0) || (c->dim == 3 && !(c->lz > 0))) { why = "bad extents"; return false; }
   if (!(c->dt > 0) && !(c->cfl > 0)) { why = "need dt > 0 or cfl > 0"; return false; }
   if (!(c->tol >= 0)) { why = "tol must be >= 0"; return false; }
-  if (c->precision != TT_FP64) { why = "only TT_FP64 is available in this build"; return false; }
+  if (c->precision != TT_FP64 && c->precision != TT_FP32_MIXED) { why = "bad precision"; return false; }
   if (c->schedule != TT_ROUND_ONCE) { why = "only TT_ROUND_ONCE is available in this build"; return false; }
   if (c->material != TT_MAT_FROZEN && c->material != TT_MAT_COUPLED) { why = "bad material"; return false; }
   if (c->rank_mode != TT_RANK_AUTO && c->rank_mode != TT_RANK_REPLAY) { why = "bad rank_mode"; return false; }
@@ -181,10 +184,15 @@ size_t carve(tt_ctx* x, char* base) {
   x->Ph = cv.take<double>((size_t)x->r2c * np);
   x->Thcat = cv.take<double>((size_t)x->R1c * nt * x->R2c);
   x->Phcat = cv.take<double>((size_t)x->R2c * np);
-  x->Xcat = cv.take<double>((size_t)ns * x->ldC);
+  x->mixed = x->cfg.precision == TT_FP32_MIXED;
+  x->Xcat = x->mixed ? nullptr : cv.take<double>((size_t)ns * x->ldC);
+  x->Xf = x->mixed ? cv.take<float>((size_t)ns * x->ldX) : nullptr;
+  x->Xnf = x->mixed ? cv.take<float>((size_t)ns * x->ldX) : nullptr;
+  x->Xcatf = x->mixed ? cv.take<float>((size_t)ns * x->ldC) : nullptr;
+  x->colmax = x->mixed ? cv.take<unsigned>((size_t)std::max(x->R1c, x->r1c) + 64) : nullptr;
   GramPlan p1 = gram_plan(ns, x->R1c, x->ldC), p2 = gram_plan(ns, x->r1c, x->ldX);
   x->gpart = cv.take<double>(std::max(std::max(gram_partial_doubles(p1), gram_partial_doubles(p2)),
-                                      std::max((size_t)(nt / 2) * x->R1c * x->R1c,
+                                      std::max((size_t)nt * x->R1c * x->R1c,
                                                (size_t)nt * x->R2c * x->R2c)));
   x->GA = cv.take<double>((size_t)x->R1c * x->R1c);
   x->GB1 = cv.take<double>((size_t)x->R1c * x->R1c);
@@ -409,7 +417,10 @@ void truncate_bond(tt_ctx* c, int bond, const EigSlot& ea, const EigSlot& eb, Ei
 
 // Gram-SVD rounding (App. A Algorithm 1, d = 3) of the TT held in
 // (xc, ldxc) / Thcat / Phcat with concatenated ranks dims[RC1], dims[RC2].
-void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol, int rmax) {
+// xcf != nullptr: the FP32-mixed form (X_cat in FP32, sliced Gram and
+// split-product update on FP32 MFMA, X' written to Xnf); else FP64 (X' to Xn).
+void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol, int rmax,
+                    const float* xcf = nullptr) {
   hipStream_t s = c->st;
   const int nt = c->nt, np = c->np, R1c = c->R1c, R2c = c->R2c, N = c->N;
   {
@@ -419,22 +430,22 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
          R2c, R2c, 1, c->dims, s);
     gemm(gd(c->Thcat, R2c, 0, c->GR3, R2c, 0, c->T1, R2c, dimv(D_RC1, nt), dimv(D_RC2), dimv(D_RC2)),
          R1c * nt, R2c, 1, c->dims, s);
-    // G_B1 = sum_l T1_l Thcat_l^T, one partial per pair of ordinates l
-    // (batched), then a fixed-order sum
-    const int nq = nt / 2;
+    // G_B1 = sum_l T1_l Thcat_l^T, one partial per ordinate l over the live
+    // R2 (batched), then a fixed-order sum
     GemmDesc gb = gd(c->T1, nt * R2c, 0, c->Thcat, nt * R2c, 1, c->gpart, R1c, dimv(D_RC1),
-                     dimv(D_RC1), dimc(2 * R2c));
-    gb.sA = gb.sB = 2LL * R2c;
+                     dimv(D_RC1), dimv(D_RC2));
+    gb.sA = gb.sB = R2c;
     gb.sC = (long long)R1c * R1c;
-    gemm(gb, R1c, R1c, nq, c->dims, s);
-    sum_partials(c->gpart, (long long)R1c * R1c, nq, c->GB1, R1c, R1c, dimv(D_RC1), dimv(D_RC1),
+    gemm(gb, R1c, R1c, nt, c->dims, s);
+    sum_partials(c->gpart, (long long)R1c * R1c, nt, c->GB1, R1c, R1c, dimv(D_RC1), dimv(D_RC1),
                  R1c, R1c, c->dims, s);
   }
   {
     GramPlan plan = gram_plan(c->ns, ncap1, ldxc);
     {
       Prof p(c, P_GRAM);
-      gram_tall_partial(plan, xc, dimv(D_RC1), c->gpart, c->dims, s);
+      if (xcf) gram_split_partial(plan, xcf, dimv(D_RC1), c->colmax, c->gpart, c->dims, s);
+      else gram_tall_partial(plan, xc, dimv(D_RC1), c->gpart, c->dims, s);
     }
     Prof p(c, P_GRAMRED);
     gram_tall_reduce(plan, dimv(D_RC1), c->gpart, c->GA, R1c, c->dims, s);
@@ -451,8 +462,12 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
                 R1c, c->r1c, D_RC1, tol, rmax);
   {
     Prof p(c, P_XUPD);
-    gemm_tall(c->ns, xc, ldxc, c->P1, c->r1c, c->Xn, c->ldX, dimv(D_RC1), dimv(D_R1N), R1c,
-              c->r1c, c->dims, s);
+    if (xcf)
+      gemm_tall_f32(c->ns, xcf, ldxc, c->P1, c->r1c, c->Xnf, c->ldX, dimv(D_RC1), dimv(D_R1N),
+                    c->r1c, c->dims, s);
+    else
+      gemm_tall(c->ns, xc, ldxc, c->P1, c->r1c, c->Xn, c->ldX, dimv(D_RC1), dimv(D_R1N), R1c,
+                c->r1c, c->dims, s);
   }
   {
     Prof p(c, P_SMALL);
@@ -507,6 +522,11 @@ tt_status check_flags(tt_ctx* c) {
 }
 
 void energy_of_state(tt_ctx* c, double* E) {
+  if (c->mixed) {
+    launch_energy(c->Xf, c->ldX, c->ns, c->Th, c->nt, c->r2c, c->Ph, c->np, c->w, c->v, c->pv, c->z,
+                  dimv(D_R1), dimv(D_R2), 1.0 / c->cfg.c, E, c->dims, c->r1c, c->r2c, c->st);
+    return;
+  }
   launch_energy(c->X, c->ldX, c->ns, c->Th, c->nt, c->r2c, c->Ph, c->np, c->w, c->v, c->pv, c->z,
                 dimv(D_R1), dimv(D_R2), 1.0 / c->cfg.c, E, c->dims, c->r1c, c->r2c, c->st);
 }
@@ -639,6 +659,7 @@ tt_status tt_set_cores(tt_ctx* c, const double* X, const double* Th, const doubl
   hipStream_t s = c->st;
   HIPCHK(c, hipMemsetAsync(c->X, 0, (size_t)c->ns * c->ldX * 8, s));
   HIPCHK(c, hipMemcpy2DAsync(c->X, c->ldX * 8, X, r[0] * 8, r[0] * 8, c->ns, hipMemcpyHostToDevice, s));
+  if (c->mixed) launch_convert(c->X, c->ldX, c->Xf, c->ldX, c->ns, c->ldX, s);
   HIPCHK(c, hipMemsetAsync(c->Th, 0, (size_t)c->r1c * c->nt * c->r2c * 8, s));
   HIPCHK(c, hipMemcpy2DAsync(c->Th, c->r2c * 8, Th, r[1] * 8, r[1] * 8, (size_t)r[0] * c->nt,
                              hipMemcpyHostToDevice, s));
@@ -677,23 +698,35 @@ tt_status tt_step(tt_ctx* c, int32_t nsteps) {
       launch_concat_dims(c->G, c->dims, s);
       launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
       launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
-      launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
-                        coupled ? 0 : 1, s);
+      if (c->mixed)
+        launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims,
+                          coupled ? 0 : 1, s);
+      else
+        launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
+                          coupled ? 0 : 1, s);
     }
     if (coupled) {
       Prof p(c, P_MAT);
       // E* = (1/c) X_tr z over the transport columns (emission column excluded)
-      launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w, c->v,
-                    c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c, c->Estar,
-                    c->dims, c->R1c, c->R2c, s);
+      if (c->mixed)
+        launch_energy(c->Xcatf, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
+                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
+                      c->Estar, c->dims, c->R1c, c->R2c, s);
+      else
+        launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
+                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
+                      c->Estar, c->dims, c->R1c, c->R2c, s);
       launch_material(c->ns, cf.c, c->dt, cf.a_r, 1, c->kappa, c->rho, c->cv, c->T, c->Estar,
                       c->Tdag, c->d, c->s, c->dims, s);
-      launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
+      if (c->mixed) launch_scale_xcat(c->G, c->d, c->s, c->Xcatf, c->ldC, c->dims, s);
+      else launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
     }
-    round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
+    if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
+    else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
     launch_finish(c->dims, c->hist, c->nhist < std::max(1, cf.max_steps) ? c->nhist : -1, s);
     c->nhist = std::min(c->nhist + 1, std::max(1, cf.max_steps));
-    std::swap(c->X, c->Xn);
+    if (c->mixed) std::swap(c->Xf, c->Xnf);
+    else std::swap(c->X, c->Xn);
     if (coupled) {
       Prof p(c, P_MAT);
       energy_of_state(c, c->Enew);
@@ -716,9 +749,11 @@ tt_status tt_round(tt_ctx* c, double tol, int32_t rmax, int32_t ranks_out[2]) {
   }
   launch_round_dims(c->dims, s);
   launch_state_as_cat(c->G, c->Th, c->Ph, c->Thcat, c->Phcat, c->dims, s);
-  round_pipeline(c, c->X, c->ldX, c->r1c, tol, rmax);
+  if (c->mixed) round_pipeline(c, nullptr, c->ldX, c->r1c, tol, rmax, c->Xf);
+  else round_pipeline(c, c->X, c->ldX, c->r1c, tol, rmax);
   launch_finish(c->dims, nullptr, -1, s);
-  std::swap(c->X, c->Xn);
+  if (c->mixed) std::swap(c->Xf, c->Xnf);
+  else std::swap(c->X, c->Xn);
   HIPCHK(c, hipGetLastError());
   tt_status st = check_flags(c);
   if (st != TT_OK) return st;
@@ -779,6 +814,7 @@ tt_status tt_get_cores(tt_ctx* c, double* X, double* Th, double* Ph, int32_t r[2
   HIPCHK(c, hipStreamSynchronize(c->st));
   if (r) { r[0] = rr[0]; r[1] = rr[1]; }
   hipStream_t s = c->st;
+  if (X && c->mixed) launch_convert(c->Xf, c->ldX, c->X, c->ldX, c->ns, rr[0], s);
   if (X) HIPCHK(c, hipMemcpy2DAsync(X, rr[0] * 8, c->X, c->ldX * 8, rr[0] * 8, c->ns, hipMemcpyDeviceToHost, s));
   if (Th)
     HIPCHK(c, hipMemcpy2DAsync(Th, rr[1] * 8, c->Th, c->r2c * 8, rr[1] * 8, (size_t)rr[0] * c->nt,

@@ -91,6 +91,10 @@ void sum_partials(const double* part, long long zstride, int nz, double* out, in
 // ---- tall Gram on MFMA: G = A^T A, A is K x n (row-major, lda), n <= ncap
 struct GramPlan {
   int K, ncap, lda, tiles, pairs, slices, kslice;
+  // row-slice form (ncap <= 384): nblk blocks of rows_per_blk rows, up to
+  // ntask_cap upper-triangular 32x32 tasks each
+  bool rows_mode;
+  int nblk, rows_per_blk, ntask_cap;
 };
 GramPlan gram_plan(int K, int ncap, int lda);
 size_t gram_partial_doubles(const GramPlan& p);
@@ -100,6 +104,15 @@ void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* pa
                        const int* dims, hipStream_t s);
 void gram_tall_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
                       const int* dims, hipStream_t s);
+
+// ---- FP32-mixed form: sliced (error-free) Gram of an FP32 matrix on FP32
+// MFMA into the same partial tiles as gram_tall_partial (reduce with
+// gram_tall_reduce); colmax is scratch of ncap words.
+void gram_split_partial(const GramPlan& p, const float* A, DimExpr n, unsigned* colmax,
+                        double* partial, const int* dims, hipStream_t s);
+// C (FP32) = A (FP32) * B (FP64, split hi/lo) on FP32 MFMA.
+void gemm_tall_f32(int K, const float* A, int lda, const double* B, int ldb, float* C, int ldc,
+                   DimExpr kdim, DimExpr ndim, int ncap, const int* dims, hipStream_t s);
 
 // ---- tall GEMM on MFMA: C[K x n] = A[K x k] * B[k x n], k, n dynamic
 void gemm_tall(int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,

@@ -132,6 +132,36 @@ tt_status tt_kernel_gram(const double* A, int32_t K, int32_t n, int32_t lda, dou
   return TT_OK;
 }
 
+size_t tt_kernel_gram_f32_workspace(int32_t K, int32_t n, int32_t lda) {
+  if (K < 1 || n < 1 || n > 1024 || lda < n) return 0;
+  return align256(64 * sizeof(int)) + align256(gram_partial_doubles(gram_plan(K, n, lda)) * 8) +
+         align256(((size_t)n + 64) * sizeof(unsigned));
+}
+
+tt_status tt_kernel_gram_f32(const float* A, int32_t K, int32_t n, int32_t lda, double* G,
+                             int32_t ldg, void* ws, size_t ws_bytes, void* stream) {
+  if (!A || !G || !ws || K < 1 || n < 1 || n > 1024 || lda < n || ldg < n)
+    return kfail(TT_ERR_INVALID_ARG, "bad gram_f32 arguments");
+  if (ws_bytes < tt_kernel_gram_f32_workspace(K, n, lda)) return kfail(TT_ERR_OOM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const GramPlan plan = gram_plan(K, n, lda);
+  char* p = (char*)ws;
+  int* dims = (int*)p;
+  p += align256(64 * sizeof(int));
+  double* part = (double*)p;
+  p += align256(gram_partial_doubles(plan) * 8);
+  unsigned* colmax = (unsigned*)p;
+  int hd[64];
+  memset(hd, 0, sizeof(hd));
+  hd[0] = n;
+  KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
+  gram_split_partial(plan, A, dimv(0), colmax, part, dims, s);
+  gram_tall_reduce(plan, dimv(0), part, G, ldg, dims, s);
+  KCHK(hipGetLastError());
+  KCHK(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
 size_t tt_kernel_gemm_tall_workspace(void) { return align256(64 * sizeof(int)); }
 
 tt_status tt_kernel_gemm_tall(const double* A, int32_t K, int32_t k, int32_t lda, const double* B,
