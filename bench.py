@@ -9,7 +9,11 @@ medium, two inflow beams, tolerance 1e-6, rank cap 64, 400 steps in total
 (warmup + timed steps).  Inputs are resident in HBM before timing.  The
 same protocol is then run in the FP32-mixed precision form; its steps/s,
 speedup over FP64 and end-state difference from the FP64 run are reported
-under "fp32_mixed".
+under "fp32_mixed".  Last, the reverse sweep: on the differentiation workload
+(128^2 cells, 16 x 32 ordinates, kappa = exp(random field), Gaussian pulse,
+tolerance 1e-6, rank cap 128, 50 steps, a checkpoint every 10 steps) the
+taped forward and tt_grad (d L / d kappa of the detector-patch energy) are
+timed and reported under "gradient".
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
 this build runs on one GPU.
@@ -99,12 +103,79 @@ def cpu_baseline(p, start_cores, nsteps_target_s=15.0, max_steps=60):
                       f"NumPy FP64, {len(os.sched_getaffinity(0))} host cores visible"}
 
 
+def mixed_run(p, W, K, dt, hist, end64):
+    """The FP32-mixed precision form on the same workload and protocol."""
+    from paper_2503_18056_amd import TT_FP32_MIXED
+    ns = p["nx"] * p["ny"]
+    sm, dtm, profm, _, rm_start = timed_run(p, W, K, TT_FP32_MIXED)
+    histm = sm.tt_get_rank_history()
+    endm = sm.cores()
+    gm_ms, gm_n = profm.get("gram_tall", (0.0, 0))
+    rm_in = [rm_start] + histm[W:W + K - 1]
+    flops_m = sum(gram_flops(ns, 5 * r1 + 2) for (r1, _) in rm_in)
+    mixed = {
+        "steps_per_s": K / dtm,
+        "ms_per_step": dtm * 1e3 / K,
+        "speedup_vs_fp64": (K / dtm) / (K / dt),
+        "rel_diff_vs_fp64_gpu_end": tt_rel_diff(endm, end64),
+        "rank_history_equal_steps": sum(a == b for a, b in zip(histm, hist)),
+        "ranks_end": list(sm.ranks()),
+        "gram_kernel": {
+            "kernel": "k_gram_split (sliced Gram on FP32 MFMA, 10 slice products)",
+            "avg_launch_ms": gm_ms / gm_n if gm_n else None,
+            "achieved_algorithmic_TFLOPs": flops_m / (gm_ms * 1e-3) / 1e12 if gm_ms > 0 else 0.0,
+            "peak_fp32_mfma_TFLOPs": FP32_MFMA_PEAK_TFLOPS,
+        },
+        "kernel_breakdown_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
+                                for k, v in profm.items()},
+    }
+    sm.close()
+    return mixed
+
+
+def gradient_run():
+    """Taped forward and reverse sweep of the differentiation workload."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2503_18056_amd import TTState
+    p = wl.c5()
+    nsteps, K = p["steps"], p["ckpt_every"]
+    st = TTState(p, device=0, max_steps=nsteps, ckpt_every=K)
+    st.step(1)  # first call: module load and code upload, not timed
+    st.tt_set_cores(p["X0"], p["Th0"], p["Ph0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.step(nsteps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L, g = st.tt_grad(p["detector"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = g.cpu().numpy()
+    out = {
+        "workload": f"{p['name']}: 128x128 cells, 16x32 ordinates, kappa = exp(GRF), pulse, "
+                    f"tol 1e-6, rank cap 128, {nsteps} steps, checkpoint every {K}",
+        "loss": L,
+        "grad_finite": bool(np.isfinite(g).all()),
+        "grad_max_abs": float(np.max(np.abs(g))),
+        "ranks_end": list(st.ranks()),
+        "forward_taped_s": t1 - t0,
+        "grad_s": t2 - t1,
+        "grad_over_forward": (t2 - t1) / (t1 - t0),
+    }
+    st.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=380)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed run")
+    ap.add_argument("--no-grad", action="store_true", help="skip the reverse-sweep run")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "warmup (a known-size kernel to scale hardware byte counters by)")
@@ -114,7 +185,7 @@ def main():
               "hot path on one GPU (see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import workloads as wl
-    from paper_2503_18056_amd import TT_FP32_MIXED, TT_FP64
+    from paper_2503_18056_amd import TT_FP64
 
     W, K = args.warmup, args.steps
     if args.calib_copy_mib > 0:
@@ -140,30 +211,7 @@ def main():
     end64 = st.cores()
     ranks64 = list(st.ranks())
     st.close()
-    # the FP32-mixed precision form on the same workload and protocol
-    sm, dtm, profm, _, rm_start = timed_run(p, W, K, TT_FP32_MIXED)
-    histm = sm.tt_get_rank_history()
-    endm = sm.cores()
-    gm_ms, gm_n = profm.get("gram_tall", (0.0, 0))
-    rm_in = [rm_start] + histm[W:W + K - 1]
-    flops_m = sum(gram_flops(ns, 5 * r1 + 2) for (r1, _) in rm_in)
-    mixed = {
-        "steps_per_s": K / dtm,
-        "ms_per_step": dtm * 1e3 / K,
-        "speedup_vs_fp64": (K / dtm) / (K / dt),
-        "rel_diff_vs_fp64_gpu_end": tt_rel_diff(endm, end64),
-        "rank_history_equal_steps": sum(a == b for a, b in zip(histm, hist)),
-        "ranks_end": list(sm.ranks()),
-        "gram_kernel": {
-            "kernel": "k_gram_split (sliced Gram on FP32 MFMA, 10 slice products)",
-            "avg_launch_ms": gm_ms / gm_n if gm_n else None,
-            "achieved_algorithmic_TFLOPs": flops_m / (gm_ms * 1e-3) / 1e12 if gm_ms > 0 else 0.0,
-            "peak_fp32_mfma_TFLOPs": FP32_MFMA_PEAK_TFLOPS,
-        },
-        "kernel_breakdown_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
-                                for k, v in profm.items()},
-    }
-    sm.close()
+    mixed = None if args.no_mixed else mixed_run(p, W, K, dt, hist, end64)
     out = {
         "metric": METRIC,
         "value": K / dt,
@@ -199,6 +247,8 @@ def main():
         "kernel_breakdown_ms": breakdown,
         "fp32_mixed": mixed,
     }
+    if not args.no_grad:
+        out["gradient"] = gradient_run()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, warm_cores)
     print(json.dumps(out), flush=True)

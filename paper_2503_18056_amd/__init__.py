@@ -6,6 +6,7 @@ device workspace and the stream.  There is no CPU fallback: if the library
 is not built, constructing a ``TTState`` raises.
 """
 import ctypes as C
+import functools
 
 import numpy as np
 
@@ -151,8 +152,31 @@ class TTState:
         self._check(self.lib.tt_set_rank_schedule(self.ctx, a.ctypes.data_as(_ffi.PI), len(a) // 2))
 
     def tt_set_kappa(self, kappa):
-        t = self.torch.as_tensor(np.asarray(kappa, float), device=self.device).contiguous()
+        """kappa: host array or float64 tensor on this device (copied)."""
+        if isinstance(kappa, self.torch.Tensor):
+            t = kappa.detach().to(device=self.device, dtype=self.torch.float64).contiguous()
+        else:
+            t = self.torch.as_tensor(np.asarray(kappa, float), device=self.device).contiguous()
         self._check(self.lib.tt_set_kappa(self.ctx, C.c_void_p(t.data_ptr())))
+        self.stream.synchronize()
+
+    def tt_grad(self, detector_w, loss_bar=1.0, dkappa=None):
+        """Reverse sweep over the steps taped since tt_set_cores (ckpt_every > 0).
+
+        Returns (L, dkappa) with L = dV sum_i w_i E_i(final) and dkappa a
+        float64 device tensor holding loss_bar * dL/dkappa.
+        """
+        w = _arr(detector_w)
+        if dkappa is None:
+            dkappa = self.torch.empty(self.ns, dtype=self.torch.float64, device=self.device)
+        L = C.c_double()
+        self._check(self.lib.tt_grad(self.ctx, _pd(w), float(loss_bar), C.byref(L),
+                                     C.c_void_p(dkappa.data_ptr())))
+        return L.value, dkappa
+
+    def cell_volume(self):
+        p = self.p
+        return (p["lx"] / p["nx"]) * (p["ly"] / p["ny"]) * (p["lz"] / p["nz"] if p["dim"] == 3 else 1.0)
 
     def tt_get_round_info(self):
         out = np.empty(16)
@@ -183,3 +207,43 @@ class TTState:
             self.close()
         except Exception:
             pass
+
+
+@functools.lru_cache(maxsize=None)
+def _autograd_function():
+    import torch
+
+    class TTDetectorLoss(torch.autograd.Function):
+        """L(kappa) = dV sum_i w_i E_i after ``nsteps`` steps from the state's
+        initial cores, with d L / d kappa from the library's reverse sweep.
+
+        ``state`` must be a TTState created with ckpt_every > 0 (FP64, frozen
+        material) and max_steps >= nsteps.  Forward installs kappa, resets the
+        cores to ``cores`` (default: the workload's initial cores), steps and
+        evaluates the loss from the library's energy density; backward calls
+        tt_grad with the incoming loss cotangent.
+        """
+
+        @staticmethod
+        def forward(ctx, kappa, state, nsteps, detector_w, cores=None):
+            state.tt_set_kappa(kappa)
+            X0, Th0, Ph0 = cores if cores is not None else (state.p["X0"], state.p["Th0"], state.p["Ph0"])
+            state.tt_set_cores(X0, Th0, Ph0)
+            state.tt_step(int(nsteps))
+            E, _, _ = state.tt_energy()
+            w = torch.as_tensor(np.asarray(detector_w, float), device=E.device)
+            state.stream.synchronize()
+            ctx.state, ctx.w = state, np.asarray(detector_w, float)
+            return (torch.dot(w, E) * state.cell_volume()).reshape(())
+
+        @staticmethod
+        def backward(ctx, gout):
+            _, dk = ctx.state.tt_grad(ctx.w, loss_bar=float(gout))
+            return dk, None, None, None, None
+
+    return TTDetectorLoss
+
+
+def detector_loss(kappa, state, nsteps, detector_w, cores=None):
+    """Differentiable detector loss (see TTDetectorLoss)."""
+    return _autograd_function().apply(kappa, state, nsteps, detector_w, cores)

@@ -34,6 +34,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
   const double* A = g.A + (long long)blockIdx.z * g.sA;
   const double* B = g.B + (long long)blockIdx.z * g.sB;
   double* C = g.C + (long long)blockIdx.z * g.sC;
+  const double* kscale = g.kscale;
+  if (g.ksplit > 0) {
+    const long long k0 = (long long)blockIdx.z * g.ksplit;
+    k = (int)max(0LL, min((long long)g.ksplit, (long long)k - k0));
+    A = g.A + (TA == 0 ? k0 : k0 * g.lda);
+    B = g.B + (TB == 0 ? k0 * g.ldb : k0);
+    if (kscale) kscale += k0;
+  }
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -51,7 +59,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
       double v = 0.0;
       if (gi < m && gl < k) {
         v = TA == 0 ? A[(long long)gi * g.lda + gl] : A[(long long)gl * g.lda + gi];
-        if (g.kscale) v *= g.kscale[gl];
+        if (kscale) v *= kscale[gl];
       }
       As[l][i] = v;
     }
@@ -98,24 +106,26 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
 
 __global__ void k_sum_partials(const double* __restrict__ part, long long zstride, int nz,
                                double* __restrict__ out, int ldo, int ldp, DimExpr mdim,
-                               DimExpr ndim, const int* __restrict__ dims) {
+                               DimExpr ndim, const int* __restrict__ dims, double beta) {
   const int m = eval_dim(dims, mdim), n = eval_dim(dims, ndim);
   const long long tot = (long long)m * n;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
     const int i = (int)(e / n), j = (int)(e % n);
     double acc = 0.0;
     for (int z = 0; z < nz; ++z) acc += part[z * zstride + (long long)i * ldp + j];
-    out[(long long)i * ldo + j] = acc;
+    double* o = out + (long long)i * ldo + j;
+    *o = beta == 0.0 ? acc : acc + beta * *o;
   }
 }
 
 void sum_partials(const double* part, long long zstride, int nz, double* out, int ldo, int ldp,
-                  DimExpr m, DimExpr n, int mcap, int ncap, const int* dims, hipStream_t s) {
+                  DimExpr m, DimExpr n, int mcap, int ncap, const int* dims, hipStream_t s,
+                  double beta) {
   long long tot = (long long)mcap * ncap;
   int blocks = (int)((tot + 255) / 256);
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  k_sum_partials<<<blocks, 256, 0, s>>>(part, zstride, nz, out, ldo, ldp, m, n, dims);
+  k_sum_partials<<<blocks, 256, 0, s>>>(part, zstride, nz, out, ldo, ldp, m, n, dims, beta);
 }
 
 void gemm(const GemmDesc& g, int mcap, int ncap, int batch, const int* dims, hipStream_t s) {

@@ -8,8 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tt.h"
-#include "tt_step.h"
+#include "tt_ctx.h"
 
 using namespace tt;
 
@@ -19,22 +18,6 @@ thread_local std::string g_err;
 
 constexpr double PI = 3.14159265358979323846;
 
-struct Carve {
-  char* base;
-  size_t off = 0;
-  template <class T>
-  T* take(size_t count) {
-    off = (off + 255) & ~(size_t)255;
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += count * sizeof(T);
-    return p;
-  }
-};
-
-struct EigSlot {
-  double *lam, *V, *sq, *isq, *work;
-};
-
 enum ProfClass { P_CONCAT, P_GRAM, P_GRAMRED, P_EIG1, P_EIGM1, P_EIG2, P_EIGM2, P_XUPD, P_SMALL,
                  P_MAT, P_STEP, P_NCLS };
 const char* kProfNames[P_NCLS] = {"concat", "gram_tall", "gram_reduce", "eig_bond1", "eig_M1",
@@ -42,40 +25,6 @@ const char* kProfNames[P_NCLS] = {"concat", "gram_tall", "gram_reduce", "eig_bon
                                   "material_energy", "step"};
 
 }  // namespace
-
-struct tt_ctx {
-  tt_config cfg;
-  hipStream_t st;
-  StepGeom G;
-  int ns, nt, np, dim, B, nbc, nem;
-  int r1c, r2c, R1c, R2c, ldX, ldC, N;
-  int q1c, q2c;  // capacities of the number of singular values of M per bond
-  double dt, lam[3];
-  std::vector<double> h_rho, h_cv;
-  // device
-  int *dims, *hist, *sched;
-  double* diag;
-  double *w, *v, *tfac, *pfac, *bc_e, *bc_t, *bc_p;
-  double *kappa, *rho, *cv, *T, *d, *s, *Estar, *Enew, *Tdag;
-  double *X, *Xn, *Th, *Ph;
-  bool mixed = false;        // TT_FP32_MIXED: X and X_cat stored in FP32
-  float *Xf, *Xnf, *Xcatf;   // FP32 state / update / concatenation (mixed form only)
-  unsigned* colmax;          // per-column max |X_cat| bits for the sliced Gram
-  double *Thcat, *Phcat, *Xcat, *gpart;
-  double *GA, *GB1, *GR3, *GL2, *T1;
-  EigSlot E[4];
-  double *M1, *C1, *Wm1, *Ur1, *P1, *Mupd1, *Thp;
-  double *M2, *C2, *Wm2, *Ur2, *P2, *Mupd2;
-  double *pv, *z;
-  size_t ws_need;
-  int nhist = 0, nsched = 0, sched_pos = 0;
-  bool poisoned = false;
-  std::string err;
-  // profiling
-  bool prof = false;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
-  size_t ev_used = 0;
-};
 
 namespace {
 
@@ -116,6 +65,10 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
   }
   if (n_inflow < 0 || n_inflow > 64) { why = "n_inflow out of range"; return false; }
   if (c->max_steps < 0) { why = "max_steps < 0"; return false; }
+  if (c->ckpt_every > 0 && (c->precision != TT_FP64 || c->material != TT_MAT_FROZEN)) {
+    why = "ckpt_every > 0 (the adjoint) needs TT_FP64 and TT_MAT_FROZEN";
+    return false;
+  }
   return true;
 }
 
@@ -199,14 +152,13 @@ size_t carve(tt_ctx* x, char* base) {
   x->GR3 = cv.take<double>((size_t)x->R2c * x->R2c);
   x->GL2 = cv.take<double>((size_t)x->R2c * x->R2c);
   x->T1 = cv.take<double>((size_t)x->R1c * nt * x->R2c);
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 6; ++k) {
     x->E[k].lam = cv.take<double>(N);
     x->E[k].V = cv.take<double>((size_t)N * N);
     x->E[k].sq = cv.take<double>(N);
     x->E[k].isq = cv.take<double>(N);
-    // slots 3 and 1 also hold the SVD of M at bonds 1 and 2 (Golub-Kahan
-    // order 2 q)
-    const int ncap = k == 3 ? std::max(N, 2 * x->q1c) : k == 1 ? std::max(N, 2 * x->q2c) : N;
+    // slots 3 and 5 hold the SVD of M at bonds 1 and 2 (Golub-Kahan order 2 q)
+    const int ncap = k == 3 ? std::max(N, 2 * x->q1c) : k == 5 ? std::max(N, 2 * x->q2c) : N;
     x->E[k].work = cv.take<double>(eig_work_doubles(ncap));
   }
   x->M1 = cv.take<double>((size_t)x->R1c * x->R1c);
@@ -224,6 +176,7 @@ size_t carve(tt_ctx* x, char* base) {
   x->Mupd2 = cv.take<double>((size_t)x->r2c * x->R2c);
   x->pv = cv.take<double>(std::max(x->R2c, x->r2c) + 8);
   x->z = cv.take<double>(std::max(x->R1c, x->r1c) + 8);
+  if (x->cfg.ckpt_every > 0) grad_carve(x, cv);
   return cv.off + 256;
 }
 
@@ -334,21 +287,6 @@ struct Prof {
   ~Prof() { prof_end(c, k); }
 };
 
-// ---- GEMM helpers ----------------------------------------------------------
-GemmDesc gd(const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C, int ldc,
-            DimExpr m, DimExpr n, DimExpr k) {
-  GemmDesc g;
-  memset(&g, 0, sizeof(g));
-  g.A = A; g.B = B; g.C = C;
-  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
-  g.transA = ta; g.transB = tb;
-  g.m = m; g.n = n; g.k = k;
-  g.alpha = 1.0; g.beta = 0.0;
-  g.cond_idx = -1;
-  g.bclip_idx = -1;
-  return g;
-}
-
 // One Gram-SVD truncation of the SVD of M given the eigen-decompositions of
 // both Gram matrices in slots ea (A side) and eb (B side); writes P (R x r')
 // and M_upd (r' x R).
@@ -453,9 +391,9 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
   {
     Prof p(c, P_EIG1);
     EigJob jobs[3] = {
-        {c->GA, R1c, D_RC1, c->E[0].lam, c->E[0].V, N, c->E[0].sq, c->E[0].isq, D_KA1, 1.0, c->E[0].work},
-        {c->GB1, R1c, D_RC1, c->E[1].lam, c->E[1].V, N, c->E[1].sq, c->E[1].isq, D_KB1, 1.0, c->E[1].work},
-        {c->GR3, R2c, D_RC2, c->E[2].lam, c->E[2].V, N, c->E[2].sq, c->E[2].isq, D_KB2, 1.0, c->E[2].work}};
+        {c->GA, R1c, D_RC1, c->E[0].lam, c->E[0].V, N, c->E[0].sq, c->E[0].isq, D_KA1, 1.0, c->E[0].work, c->eig_all},
+        {c->GB1, R1c, D_RC1, c->E[1].lam, c->E[1].V, N, c->E[1].sq, c->E[1].isq, D_KB1, 1.0, c->E[1].work, c->eig_all},
+        {c->GR3, R2c, D_RC2, c->E[2].lam, c->E[2].V, N, c->E[2].sq, c->E[2].isq, D_KB2, 1.0, c->E[2].work, c->eig_all}};
     eig_batched(jobs, 3, N, c->dims, s);
   }
   truncate_bond(c, 1, c->E[0], c->E[1], c->E[3], c->M1, c->C1, c->Wm1, c->Ur1, c->P1, c->Mupd1,
@@ -485,10 +423,10 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
   }
   {
     Prof p(c, P_EIG2);
-    EigJob j = {c->GL2, R2c, D_RC2, c->E[0].lam, c->E[0].V, N, c->E[0].sq, c->E[0].isq, D_KA2, 1.0, c->E[0].work};
+    EigJob j = {c->GL2, R2c, D_RC2, c->E[4].lam, c->E[4].V, N, c->E[4].sq, c->E[4].isq, D_KA2, 1.0, c->E[4].work, c->eig_all};
     eig_batched(&j, 1, N, c->dims, s);
   }
-  truncate_bond(c, 2, c->E[0], c->E[2], c->E[1], c->M2, c->C2, c->Wm2, c->Ur2, c->P2, c->Mupd2,
+  truncate_bond(c, 2, c->E[4], c->E[2], c->E[5], c->M2, c->C2, c->Wm2, c->Ur2, c->P2, c->Mupd2,
                 R2c, c->r2c, D_RC2, tol, rmax);
   {
     Prof p(c, P_SMALL);
@@ -532,6 +470,21 @@ void energy_of_state(tt_ctx* c, double* E) {
 }
 
 }  // namespace
+
+namespace tt {
+
+tt_status ctx_fail(tt_ctx* c, tt_status code, const std::string& msg) { return fail(c, code, msg); }
+
+void step_body_fp64_frozen(tt_ctx* c) {
+  hipStream_t s = c->st;
+  launch_concat_dims(c->G, c->dims, s);
+  launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
+  launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
+  launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims, 1, s);
+  round_pipeline(c, c->Xcat, c->ldC, c->R1c, c->cfg.tol, c->cfg.rmax);
+}
+
+}  // namespace tt
 
 // ============================================================================
 extern "C" {
@@ -677,6 +630,7 @@ tt_status tt_set_cores(tt_ctx* c, const double* X, const double* Th, const doubl
   c->poisoned = false;
   c->nhist = 0;
   c->sched_pos = 0;
+  c->gb.stale = false;
   return TT_OK;
 }
 
@@ -687,8 +641,11 @@ tt_status tt_step(tt_ctx* c, int32_t nsteps) {
   hipStream_t s = c->st;
   const tt_config& cf = c->cfg;
   const bool coupled = cf.material == TT_MAT_COUPLED;
+  if (c->gb.on && c->nhist + nsteps > std::max(1, cf.max_steps))
+    return fail(c, TT_ERR_STATE, "tape full: more steps since tt_set_cores than max_steps");
   for (int m = 0; m < nsteps; ++m) {
     Prof pstep(c, P_STEP);
+    if (c->gb.on) HIPCHK(c, grad_record(c));
     if (cf.rank_mode == TT_RANK_REPLAY) {
       k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->sched_pos, c->nsched);
       c->sched_pos++;
@@ -791,15 +748,10 @@ tt_status tt_energy(tt_ctx* c, double* E_dev, double* rad_total, double* mat_tot
   return TT_OK;
 }
 
-tt_status tt_grad(tt_ctx* c, const double* detector_w, double loss_bar, double* loss_out,
-                  double* dkappa_dev) {
-  (void)detector_w; (void)loss_bar; (void)loss_out; (void)dkappa_dev;
-  return fail(c, TT_ERR_STATE, "tt_grad: no tape recorded (adjoint not available in this build)");
-}
-
 tt_status tt_set_kappa(tt_ctx* c, const double* kappa_dev) {
   if (!c || !kappa_dev) return fail(c, TT_ERR_INVALID_ARG, "null argument");
   HIPCHK(c, hipMemcpyAsync(c->kappa, kappa_dev, c->ns * 8, hipMemcpyDeviceToDevice, c->st));
+  if (c->nhist > 0) c->gb.stale = true;  // the taped steps used the old opacity
   launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, c->rho, c->cv, c->T, c->Estar,
                   c->Tdag, c->d, c->s, c->dims, c->st);
   HIPCHK(c, hipGetLastError());

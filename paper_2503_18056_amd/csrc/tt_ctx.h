@@ -1,0 +1,124 @@
+// The library context (one TT state on one stream) and what the forward step
+// and the adjoint sweep share: the workspace carver, eigen slots, the GEMM
+// descriptor helper and the step body.
+#pragma once
+
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tt.h"
+#include "tt_step.h"
+
+namespace tt {
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct EigSlot {
+  double *lam, *V, *sq, *isq, *work;
+};
+
+// Device buffers of the reverse sweep (present when ckpt_every > 0).
+struct GradBufs {
+  bool on = false;
+  int K = 0;                   // steps per checkpoint
+  int nck = 0;                 // checkpoint slots
+  size_t xs = 0, ths = 0, phs = 0;  // doubles per stored X, Theta, Phi
+  double *ckX, *ckTh, *ckPh;   // checkpoints (state before steps 0, K, 2K, ...)
+  int* ckR;                    // their ranks (r1, r2)
+  double *sgX, *sgTh, *sgPh;   // the K states of the segment being reversed
+  int* sgR;
+  double *fX, *fTh, *fPh;      // the final state, restored after the sweep
+  int* fR;
+  // cotangents: of the step output (…b) and of its input (…nb)
+  double *Xb, *Xnb, *Thb, *Thnb, *Phb, *Phnb;
+  double *Xcb, *Thcb, *Phcb, *A2b;
+  double *kbar, *dd, *ds, *wdet, *xg, *loss;
+  // truncation adjoint scratch (N x N, ld N, unless noted)
+  double *Pb, *Mub;            // Pbar (R x r, ld r cap), M_upd bar (r x R, ld R cap)
+  double *U, *V, *Ub, *Vb, *G1, *G2, *In, *Tm, *Mb, *Cm, *VAb, *VBb, *W, *Ce, *Te;
+  double *GbA, *GbB, *GbR3;
+  double *Y;                   // R1 x N_theta R2 cap
+  double *sb, *SAb, *SBb, *cA, *cB, *lbA, *lbB;  // N each
+  double* part;                // split-K partial products
+  size_t part_n = 0;
+  int nsplit = 0, ksl = 0;     // split of the N_s-long contractions
+  bool stale = false;          // kappa changed after the steps were taped
+};
+
+inline GemmDesc gd(const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C,
+                   int ldc, DimExpr m, DimExpr n, DimExpr k) {
+  GemmDesc g;
+  memset(&g, 0, sizeof(g));
+  g.A = A; g.B = B; g.C = C;
+  g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+  g.transA = ta; g.transB = tb;
+  g.m = m; g.n = n; g.k = k;
+  g.alpha = 1.0; g.beta = 0.0;
+  g.cond_idx = -1;
+  g.bclip_idx = -1;
+  return g;
+}
+
+}  // namespace tt
+
+struct tt_ctx {
+  tt_config cfg;
+  hipStream_t st;
+  tt::StepGeom G;
+  int ns, nt, np, dim, B, nbc, nem;
+  int r1c, r2c, R1c, R2c, ldX, ldC, N;
+  int q1c, q2c;  // capacities of the number of singular values of M per bond
+  double dt, lam[3];
+  std::vector<double> h_rho, h_cv;
+  // device
+  int *dims, *hist, *sched;
+  double* diag;
+  double *w, *v, *tfac, *pfac, *bc_e, *bc_t, *bc_p;
+  double *kappa, *rho, *cv, *T, *d, *s, *Estar, *Enew, *Tdag;
+  double *X, *Xn, *Th, *Ph;
+  bool mixed = false;        // TT_FP32_MIXED: X and X_cat stored in FP32
+  float *Xf, *Xnf, *Xcatf;   // FP32 state / update / concatenation (mixed form only)
+  unsigned* colmax;          // per-column max |X_cat| bits for the sliced Gram
+  double *Thcat, *Phcat, *Xcat, *gpart;
+  double *GA, *GB1, *GR3, *GL2, *T1;
+  tt::EigSlot E[6];  // bond 1: 0 G_A, 1 G_B1, 2 G_R3, 3 SVD of M1; bond 2: 4 G_L2, 5 SVD of M2
+  int eig_all = 0;   // every eigenvector (recomputation for the adjoint)
+  double *M1, *C1, *Wm1, *Ur1, *P1, *Mupd1, *Thp;
+  double *M2, *C2, *Wm2, *Ur2, *P2, *Mupd2;
+  double *pv, *z;
+  tt::GradBufs gb;
+  size_t ws_need;
+  int nhist = 0, nsched = 0, sched_pos = 0;
+  bool poisoned = false;
+  std::string err;
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  size_t ev_used = 0;
+};
+
+namespace tt {
+
+tt_status ctx_fail(tt_ctx* c, tt_status code, const std::string& msg);
+// Concatenation and rounding of one FP64 step with frozen material, leaving
+// dims[R1], dims[R2] at the input ranks (no close of the step): X_cat,
+// Theta_cat, Phi_cat and every rounding intermediate stay in the context.
+void step_body_fp64_frozen(tt_ctx* c);
+// Adjoint buffers (appended to the workspace when ckpt_every > 0).
+void grad_carve(tt_ctx* c, Carve& cv);
+// Before step number c->nhist: store a checkpoint if one is due.
+hipError_t grad_record(tt_ctx* c);
+
+}  // namespace tt

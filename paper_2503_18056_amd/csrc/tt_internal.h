@@ -82,11 +82,17 @@ struct GemmDesc {
   // lim = dims[bclip_idx] - z * bclip_mul; it is skipped when lim <= bclip_min
   // and m, n, k are clipped to lim.
   int bclip_idx, bclip_mul, bclip_min;
+  // ksplit > 0: split-K, batch z contracts l in [z ksplit, min((z+1) ksplit, k))
+  // (A, B, kscale offset along k in the kernel; sA, sB unused); a batch past
+  // the end writes zeros, so its partial slot is defined
+  int ksplit;
 };
 void gemm(const GemmDesc& g, int mcap, int ncap, int batch, const int* dims, hipStream_t s);
-// out[i][j] = sum_{z < nz} part[z][i][j] (fixed order), i < m, j < n (dynamic).
+// out[i][j] = sum_{z < nz} part[z][i][j] (fixed order) + beta out[i][j],
+// i < m, j < n (dynamic).
 void sum_partials(const double* part, long long zstride, int nz, double* out, int ldo, int ldp,
-                  DimExpr m, DimExpr n, int mcap, int ncap, const int* dims, hipStream_t s);
+                  DimExpr m, DimExpr n, int mcap, int ncap, const int* dims, hipStream_t s,
+                  double beta = 0.0);
 
 // ---- tall Gram on MFMA: G = A^T A, A is K x n (row-major, lda), n <= ncap
 struct GramPlan {
@@ -135,6 +141,8 @@ struct EigJob {
   int kept_idx;     // dims index receiving the kept count
   double clip;      // clip factor (1: Gram clip rule; 0: keep all lambda > 0)
   double* work;     // eig_work_doubles(ncap)
+  int all = 0;      // 1: compute and sign-fix every eigenvector (the adjoint needs
+                    // the clipped ones too); the kept count is unchanged
 };
 size_t eig_work_doubles(int ncap);
 void eig_batched(const EigJob* jobs, int njobs, int ncap, int* dims, hipStream_t s);

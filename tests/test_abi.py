@@ -58,6 +58,24 @@ def test_workspace_and_validation(lib):
     assert b"periodic" in lib.tt_last_error(None)
 
 
+def test_tape_validation(lib):
+    """The reverse sweep is FP64 with frozen material: asking for a tape
+    (ckpt_every > 0) with the mixed form or coupled material is rejected on
+    the host; with a tape the workspace grows by the checkpoints."""
+    from paper_2503_18056_amd import TT_FP32_MIXED, make_config
+    p = wl.c5(n=32, steps=10)
+    base = lib.tt_workspace_bytes(C.byref(make_config(p)), 0)
+    taped = lib.tt_workspace_bytes(C.byref(make_config(p, ckpt_every=5)), 0)
+    ns, r1c = 32 * 32, 128
+    assert taped > base + 2 * ns * r1c * 8  # two checkpoints of X at least
+    assert lib.tt_workspace_bytes(C.byref(make_config(p, ckpt_every=5, precision=TT_FP32_MIXED)), 0) == 0
+    assert b"ckpt_every" in lib.tt_last_error(None)
+    q = dict(p)
+    q["material"] = wl.COUPLED
+    assert lib.tt_workspace_bytes(C.byref(make_config(q, ckpt_every=5)), 0) == 0
+    assert b"FROZEN" in lib.tt_last_error(None)
+
+
 def test_create_rejects_bad_input_on_host(lib):
     from paper_2503_18056_amd import _ffi
     cfg = _cfg(ntheta=5)
