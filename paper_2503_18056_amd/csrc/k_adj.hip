@@ -3,61 +3,24 @@
 // is the upwind transport in TT form (Sec. 3.1, Sec. 4.3), absorption /
 // emission with a frozen temperature (Sec. 3.2, Sec. 4.4), the TT sum by
 // concatenation (Sec. 4.1) and the Gram-SVD truncation of both bonds (App. A,
-// Algorithm 1; App. A.2).  Derivatives of symmetric eigendecompositions and
-// of the truncated SVD follow the standard first-order perturbation results:
-//   eigenvectors   dv_j = sum_{i != j} v_i (v_i^T dG v_j) / (lambda_j - lambda_i),
-//   singular pairs (thin SVD M = U S V^T) with F_ij = 1 / (s_j^2 - s_i^2):
+// Algorithm 1; App. A.2).  The truncation is differentiated as a truncated
+// SVD, by the standard first-order perturbation result for singular pairs
+// (thin SVD M = U S V^T, F_ij = 1 / (s_j^2 - s_i^2)):
 //   Mbar = U [diag(sbar) + (F o (U^T Ubar - Ubar^T U)) S + S (F o (V^T Vbar -
 //          Vbar^T V))] V^T + (I - U U^T) Ubar S^-1 V^T + U S^-1 Vbar^T (I - V V^T).
-// Exactly equal eigen / singular values get F = 0 (the loss does not depend
-// on the basis inside such a space).
+// Singular values within 1e-12 s_1^2 of each other get F = 0 (the loss does
+// not depend on the basis inside such a space).
 #include "tt_step.h"
 
 namespace tt {
-
-// ---------------------------------------------------------------------------
-// inner = diag(lambar_ext) + F o C for the eigen adjoint, in place in C
-// (n x k, ldc): F_ij = 1 / (lam_j - lam_i) for i != j with lam_i != lam_j;
-// lam holds all n eigenvalues (descending), lambar the first k.
-__global__ void k_eig_adj_inner(double* __restrict__ C, int ldc, const double* __restrict__ lam,
-                                const double* __restrict__ lambar, const int* __restrict__ dims,
-                                int n_idx, int k_idx) {
-  const int n = dims[n_idx], k = dims[k_idx];
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)n * k;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(e / k), j = (int)(e % k);
-    double v;
-    if (i == j) {
-      v = lambar[j];
-    } else {
-      const double dl = lam[j] - lam[i];
-      v = dl != 0.0 ? C[(long long)i * ldc + j] / dl : 0.0;
-    }
-    C[(long long)i * ldc + j] = v;
-  }
-}
-
-// Symmetric part G <- (G + G^T) / 2 of the leading n x n block.
-__global__ void k_symmetrize(double* __restrict__ G, int ldg, const int* __restrict__ dims,
-                             int n_idx) {
-  const int n = dims[n_idx];
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)n * n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    if (j <= i) continue;
-    const double a = G[(long long)i * ldg + j], b = G[(long long)j * ldg + i];
-    const double m = 0.5 * (a + b);
-    G[(long long)i * ldg + j] = m;
-    G[(long long)j * ldg + i] = m;
-  }
-}
 
 // Inner matrix of the truncated-SVD adjoint (kc x kc), with the two
 // complement-projector terms folded in:
 //   In = diag(sbar) + (F o (G1 - G1^T)) S + S (F o (G2 - G2^T)) - G1 S_r^-1 - S_r^-1 G2^T,
 // G1 = U^T Ubar, G2 = V^T Vbar (Ubar, Vbar zero beyond column r), F_ij =
 // 1/(s_j^2 - s_i^2) off ties (|s_j^2 - s_i^2| <= 1e-12 s_1^2 counts as a tie),
-// so that  Mbar = U In V^T + Ubar S_r^-1 V^T + U S_r^-1 Vbar^T.
+// so that  Mbar = U In V^T + Ubar S_r^-1 V^T + U S_r^-1 Vbar^T.  G2 or sbar may
+// be null (taken as zero).
 __global__ void k_svd_adj_inner(const double* __restrict__ G1, const double* __restrict__ G2,
                                 int ldg, const double* __restrict__ s,
                                 const double* __restrict__ sbar, double* __restrict__ out,
@@ -68,10 +31,11 @@ __global__ void k_svd_adj_inner(const double* __restrict__ G1, const double* __r
        e += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(e / kc), j = (int)(e % kc);
     const double g1ij = G1[(long long)i * ldg + j], g1ji = G1[(long long)j * ldg + i];
-    const double g2ij = G2[(long long)i * ldg + j], g2ji = G2[(long long)j * ldg + i];
+    const double g2ij = G2 ? G2[(long long)i * ldg + j] : 0.0;
+    const double g2ji = G2 ? G2[(long long)j * ldg + i] : 0.0;
     double v = 0.0;
     if (i == j) {
-      v = i < r ? sbar[i] : 0.0;
+      v = (i < r && sbar) ? sbar[i] : 0.0;
     } else {
       const double dl = s[j] * s[j] - s[i] * s[i];
       if (fabs(dl) > tie) v = ((g1ij - g1ji) * s[j] + s[i] * (g2ij - g2ji)) / dl;
@@ -79,90 +43,6 @@ __global__ void k_svd_adj_inner(const double* __restrict__ G1, const double* __r
     if (j < r) v -= g1ij / s[j];
     if (i < r) v -= g2ji / s[i];
     out[(long long)i * ldo + j] = v;
-  }
-}
-
-// out_j = scale_j * sum_{i < m} A[i][j] B[i][j] for j < n (a block per column).
-__global__ __launch_bounds__(256) void k_coldot(const double* __restrict__ A, int lda,
-                                                const double* __restrict__ B, int ldb,
-                                                const double* __restrict__ scale,
-                                                double* __restrict__ out,
-                                                const int* __restrict__ dims, DimExpr mdim,
-                                                DimExpr ndim) {
-  const int m = eval_dim(dims, mdim), n = eval_dim(dims, ndim);
-  const int j = blockIdx.x;
-  if (j >= n) return;
-  __shared__ double red[4];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < m; i += 256) s += A[(long long)i * lda + j] * B[(long long)i * ldb + j];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) out[j] = ((red[0] + red[1]) + red[2] + red[3]) * (scale ? scale[j] : 1.0);
-}
-
-// The W = Mupdbar V_B terms of the truncation adjoint (one block), from
-// M_upd = S_r V_r^T D_B V_B^T with D_B = S_B^-1:
-//   sbar_i = sum_j W[i][j] D_B,j V_r[j][i]                        (i < r)
-//   cB_j   = D_B,j dL/dD_B,j = D_B,j sum_i V_r[j][i] s_i W[i][j]   (j < kB)
-//   Vbar[j][i] = D_B,j W[i][j] s_i  (i < r; columns r..kc set to 0).
-__global__ __launch_bounds__(256) void k_trunc_w(const double* __restrict__ W, int ldw,
-                                                 const double* __restrict__ DB,
-                                                 const double* __restrict__ Vr, int ldv,
-                                                 const double* __restrict__ s,
-                                                 double* __restrict__ sbar,
-                                                 double* __restrict__ cB,
-                                                 double* __restrict__ Vbar, int ldvb,
-                                                 const int* __restrict__ dims, int r_idx,
-                                                 int kb_idx, int kc_idx) {
-  const int r = dims[r_idx], kB = dims[kb_idx], kc = dims[kc_idx];
-  for (int i = threadIdx.x; i < r; i += 256) {
-    double a = 0.0;
-    for (int j = 0; j < kB; ++j) a += W[(long long)i * ldw + j] * DB[j] * Vr[(long long)j * ldv + i];
-    sbar[i] = a;
-  }
-  for (int j = threadIdx.x; j < kB; j += 256) {
-    double a = 0.0;
-    for (int i = 0; i < r; ++i) a += Vr[(long long)j * ldv + i] * s[i] * W[(long long)i * ldw + j];
-    cB[j] = DB[j] * a;
-    for (int i = 0; i < kc; ++i)
-      Vbar[(long long)j * ldvb + i] = i < r ? DB[j] * W[(long long)i * ldw + j] * s[i] : 0.0;
-  }
-}
-
-// From M = S_A C S_B (C = V_A^T V_B):  SAbar_i = sum_j Mb[i][j] C[i][j] SB_j,
-// SBbar_j = sum_i Mb[i][j] SA_i C[i][j] (one block).
-__global__ __launch_bounds__(256) void k_mb_vecs(const double* __restrict__ Mb, int ldm,
-                                                 const double* __restrict__ C, int ldc,
-                                                 const double* __restrict__ SA,
-                                                 const double* __restrict__ SB,
-                                                 double* __restrict__ SAbar,
-                                                 double* __restrict__ SBbar,
-                                                 const int* __restrict__ dims, int ka_idx,
-                                                 int kb_idx) {
-  const int kA = dims[ka_idx], kB = dims[kb_idx];
-  for (int i = threadIdx.x; i < kA; i += 256) {
-    double a = 0.0;
-    for (int j = 0; j < kB; ++j) a += Mb[(long long)i * ldm + j] * C[(long long)i * ldc + j] * SB[j];
-    SAbar[i] = a;
-  }
-  for (int j = threadIdx.x; j < kB; j += 256) {
-    double a = 0.0;
-    for (int i = 0; i < kA; ++i) a += Mb[(long long)i * ldm + j] * SA[i] * C[(long long)i * ldc + j];
-    SBbar[j] = a;
-  }
-}
-
-// Eigenvalue cotangent of a Gram factor S = sqrt(lambda), D = 1/S:
-//   lambar_i = (Sbar_i - cD_i / S_i) / (2 S_i),
-// where cD_i = D_i dL/dD_i (the D-path term -dL/dD / S^2 = -cD / S).
-__global__ void k_lambar(const double* __restrict__ Sbar, const double* __restrict__ cD,
-                         const double* __restrict__ S, double* __restrict__ lambar,
-                         const int* __restrict__ dims, int k_idx) {
-  const int k = dims[k_idx];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-    const double sa = S[i];
-    lambar[i] = (Sbar[i] - cD[i] / sa) / (2.0 * sa);
   }
 }
 
@@ -206,6 +86,18 @@ __global__ __launch_bounds__(256) void k_gauge_pair(double* __restrict__ U, int 
   if (val < 0.0) {
     for (int i = lane; i < kA; i += 64) U[(long long)i * ldu + c] = -U[(long long)i * ldu + c];
     for (int i = lane; i < kB; i += 64) V[(long long)i * ldv + c] = -V[(long long)i * ldv + c];
+  }
+}
+
+// Y[i][j] += X[i][j] * s[j] for i < rows, j < dims[c_idx].
+__global__ void k_add_colscaled(const double* __restrict__ X, int ldx, const double* __restrict__ sc,
+                                double* __restrict__ Y, int ldy, const int* __restrict__ dims,
+                                DimExpr rdim, int c_idx) {
+  const int rows = eval_dim(dims, rdim), cols = dims[c_idx];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)rows * cols;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    Y[(long long)i * ldy + j] += X[(long long)i * ldx + j] * sc[j];
   }
 }
 
@@ -412,37 +304,11 @@ static int blocks_for(long long n) {
   return (int)b;
 }
 
-void launch_eig_adj_inner(double* C, int ldc, const double* lam, const double* lambar,
-                          const int* dims, int n_idx, int k_idx, int cap, hipStream_t s) {
-  k_eig_adj_inner<<<blocks_for((long long)cap * cap), 256, 0, s>>>(C, ldc, lam, lambar, dims, n_idx, k_idx);
-}
-void launch_symmetrize(double* G, int ldg, const int* dims, int n_idx, int cap, hipStream_t s) {
-  k_symmetrize<<<blocks_for((long long)cap * cap), 256, 0, s>>>(G, ldg, dims, n_idx);
-}
 void launch_svd_adj_inner(const double* G1, const double* G2, int ldg, const double* sv,
                           const double* sbar, double* out, int ldo, const int* dims, int kc_idx,
                           int r_idx, int cap, hipStream_t s) {
   k_svd_adj_inner<<<blocks_for((long long)cap * cap), 256, 0, s>>>(G1, G2, ldg, sv, sbar, out, ldo,
                                                                    dims, kc_idx, r_idx);
-}
-void launch_coldot(const double* A, int lda, const double* B, int ldb, const double* scale,
-                   double* out, const int* dims, DimExpr m, DimExpr n, int ncap, hipStream_t s) {
-  k_coldot<<<ncap, 256, 0, s>>>(A, lda, B, ldb, scale, out, dims, m, n);
-}
-void launch_trunc_w(const double* W, int ldw, const double* DB, const double* Vr, int ldv,
-                    const double* sv, double* sbar, double* DBbar, double* Vbar, int ldvb,
-                    const int* dims, int r_idx, int kb_idx, int kc_idx, hipStream_t s) {
-  k_trunc_w<<<1, 256, 0, s>>>(W, ldw, DB, Vr, ldv, sv, sbar, DBbar, Vbar, ldvb, dims, r_idx,
-                              kb_idx, kc_idx);
-}
-void launch_mb_vecs(const double* Mb, int ldm, const double* C, int ldc, const double* SA,
-                    const double* SB, double* SAbar, double* SBbar, const int* dims, int ka_idx,
-                    int kb_idx, hipStream_t s) {
-  k_mb_vecs<<<1, 256, 0, s>>>(Mb, ldm, C, ldc, SA, SB, SAbar, SBbar, dims, ka_idx, kb_idx);
-}
-void launch_lambar(const double* Sbar, const double* coldot, const double* S, double* lambar,
-                   const int* dims, int k_idx, int cap, hipStream_t s) {
-  k_lambar<<<blocks_for(cap), 256, 0, s>>>(Sbar, coldot, S, lambar, dims, k_idx);
 }
 void launch_copy_cond(const double* src, int lds, double* dst, int ldd, const int* dims,
                       int rows_idx, int kc_idx, int side_idx, int side, int cap, hipStream_t s) {
@@ -452,6 +318,10 @@ void launch_copy_cond(const double* src, int lds, double* dst, int ldd, const in
 void launch_gauge_pair(double* U, int ldu, double* V, int ldv, const int* dims, int ka_idx,
                        int kb_idx, int kc_idx, int side_idx, int cap, hipStream_t s) {
   k_gauge_pair<<<(cap + 3) / 4, 256, 0, s>>>(U, ldu, V, ldv, dims, ka_idx, kb_idx, kc_idx, side_idx);
+}
+void launch_add_colscaled(const double* X, int ldx, const double* sc, double* Y, int ldy,
+                          const int* dims, DimExpr r, int c_idx, int cap, hipStream_t s) {
+  k_add_colscaled<<<blocks_for((long long)cap * cap), 256, 0, s>>>(X, ldx, sc, Y, ldy, dims, r, c_idx);
 }
 void launch_zero_block(double* A, int lda, const int* dims, DimExpr r, DimExpr cdim, long long cap,
                        hipStream_t s) {

@@ -914,7 +914,7 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   __shared__ double ys[4][1024];
   if (j >= n) return;
   const double thr = keep_threshold(J, D.lam, n);
-  if (!J.all && !(D.lam[j] > thr)) return;
+  if (!(D.lam[j] > thr)) return;
   double* y = ys[wave];
   for (int i = lane; i < n; i += 64) y[i] = D.Qa[(size_t)i * N2 + j];
   for (int k = n - 3; k >= 0; --k) {
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
       J.isq[c] = 1.0 / s;
     }
   }
-  gauge_columns(J.V, J.ldv, n, J.all ? n : kept);
+  gauge_columns(J.V, J.ldv, n, kept);
 }
 
 

@@ -65,8 +65,8 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
   }
   if (n_inflow < 0 || n_inflow > 64) { why = "n_inflow out of range"; return false; }
   if (c->max_steps < 0) { why = "max_steps < 0"; return false; }
-  if (c->ckpt_every > 0 && (c->precision != TT_FP64 || c->material != TT_MAT_FROZEN)) {
-    why = "ckpt_every > 0 (the adjoint) needs TT_FP64 and TT_MAT_FROZEN";
+  if (c->ckpt_every > 0 && c->material != TT_MAT_FROZEN) {
+    why = "ckpt_every > 0 (the adjoint) needs TT_MAT_FROZEN";
     return false;
   }
   return true;
@@ -138,7 +138,8 @@ size_t carve(tt_ctx* x, char* base) {
   x->Thcat = cv.take<double>((size_t)x->R1c * nt * x->R2c);
   x->Phcat = cv.take<double>((size_t)x->R2c * np);
   x->mixed = x->cfg.precision == TT_FP32_MIXED;
-  x->Xcat = x->mixed ? nullptr : cv.take<double>((size_t)ns * x->ldC);
+  // the mixed form keeps an FP64 X_cat only for the reverse sweep
+  x->Xcat = (!x->mixed || x->cfg.ckpt_every > 0) ? cv.take<double>((size_t)ns * x->ldC) : nullptr;
   x->Xf = x->mixed ? cv.take<float>((size_t)ns * x->ldX) : nullptr;
   x->Xnf = x->mixed ? cv.take<float>((size_t)ns * x->ldX) : nullptr;
   x->Xcatf = x->mixed ? cv.take<float>((size_t)ns * x->ldC) : nullptr;
@@ -391,9 +392,9 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
   {
     Prof p(c, P_EIG1);
     EigJob jobs[3] = {
-        {c->GA, R1c, D_RC1, c->E[0].lam, c->E[0].V, N, c->E[0].sq, c->E[0].isq, D_KA1, 1.0, c->E[0].work, c->eig_all},
-        {c->GB1, R1c, D_RC1, c->E[1].lam, c->E[1].V, N, c->E[1].sq, c->E[1].isq, D_KB1, 1.0, c->E[1].work, c->eig_all},
-        {c->GR3, R2c, D_RC2, c->E[2].lam, c->E[2].V, N, c->E[2].sq, c->E[2].isq, D_KB2, 1.0, c->E[2].work, c->eig_all}};
+        {c->GA, R1c, D_RC1, c->E[0].lam, c->E[0].V, N, c->E[0].sq, c->E[0].isq, D_KA1, 1.0, c->E[0].work},
+        {c->GB1, R1c, D_RC1, c->E[1].lam, c->E[1].V, N, c->E[1].sq, c->E[1].isq, D_KB1, 1.0, c->E[1].work},
+        {c->GR3, R2c, D_RC2, c->E[2].lam, c->E[2].V, N, c->E[2].sq, c->E[2].isq, D_KB2, 1.0, c->E[2].work}};
     eig_batched(jobs, 3, N, c->dims, s);
   }
   truncate_bond(c, 1, c->E[0], c->E[1], c->E[3], c->M1, c->C1, c->Wm1, c->Ur1, c->P1, c->Mupd1,
@@ -423,7 +424,7 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
   }
   {
     Prof p(c, P_EIG2);
-    EigJob j = {c->GL2, R2c, D_RC2, c->E[4].lam, c->E[4].V, N, c->E[4].sq, c->E[4].isq, D_KA2, 1.0, c->E[4].work, c->eig_all};
+    EigJob j = {c->GL2, R2c, D_RC2, c->E[4].lam, c->E[4].V, N, c->E[4].sq, c->E[4].isq, D_KA2, 1.0, c->E[4].work};
     eig_batched(&j, 1, N, c->dims, s);
   }
   truncate_bond(c, 2, c->E[4], c->E[2], c->E[5], c->M2, c->C2, c->Wm2, c->Ur2, c->P2, c->Mupd2,
@@ -475,13 +476,18 @@ namespace tt {
 
 tt_status ctx_fail(tt_ctx* c, tt_status code, const std::string& msg) { return fail(c, code, msg); }
 
-void step_body_fp64_frozen(tt_ctx* c) {
+void step_body_frozen(tt_ctx* c) {
   hipStream_t s = c->st;
   launch_concat_dims(c->G, c->dims, s);
   launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
   launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
-  launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims, 1, s);
-  round_pipeline(c, c->Xcat, c->ldC, c->R1c, c->cfg.tol, c->cfg.rmax);
+  if (c->mixed) {
+    launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims, 1, s);
+    round_pipeline(c, nullptr, c->ldC, c->R1c, c->cfg.tol, c->cfg.rmax, c->Xcatf);
+  } else {
+    launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims, 1, s);
+    round_pipeline(c, c->Xcat, c->ldC, c->R1c, c->cfg.tol, c->cfg.rmax);
+  }
 }
 
 }  // namespace tt

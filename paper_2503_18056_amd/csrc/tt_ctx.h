@@ -34,26 +34,30 @@ struct GradBufs {
   bool on = false;
   int K = 0;                   // steps per checkpoint
   int nck = 0;                 // checkpoint slots
-  size_t xs = 0, ths = 0, phs = 0;  // doubles per stored X, Theta, Phi
-  double *ckX, *ckTh, *ckPh;   // checkpoints (state before steps 0, K, 2K, ...)
+  size_t xs = 0, ths = 0, phs = 0;  // doubles per stored X (cotangent), Theta, Phi
+  size_t xbytes = 0;           // bytes of a stored X (FP64, or FP32 in the mixed form)
+  char *ckX, *sgX, *fX;         // stored X (xbytes each; FP32 in the mixed form)
+  double *ckTh, *ckPh;         // checkpoints (state before steps 0, K, 2K, ...)
   int* ckR;                    // their ranks (r1, r2)
-  double *sgX, *sgTh, *sgPh;   // the K states of the segment being reversed
+  double *sgTh, *sgPh;         // the K states of the segment being reversed
   int* sgR;
-  double *fX, *fTh, *fPh;      // the final state, restored after the sweep
+  double *fTh, *fPh;           // the final state, restored after the sweep
   int* fR;
   // cotangents: of the step output (…b) and of its input (…nb)
   double *Xb, *Xnb, *Thb, *Thnb, *Phb, *Phnb;
   double *Xcb, *Thcb, *Phcb, *A2b;
   double *kbar, *dd, *ds, *wdet, *xg, *loss;
   // truncation adjoint scratch (N x N, ld N, unless noted)
-  double *Pb, *Mub;            // Pbar (R x r, ld r cap), M_upd bar (r x R, ld R cap)
-  double *U, *V, *Ub, *Vb, *G1, *G2, *In, *Tm, *Mb, *Cm, *VAb, *VBb, *W, *Ce, *Te;
-  double *GbA, *GbB, *GbR3;
+  double* Mub;                 // M_upd bar (r x R, ld R cap)
+  double *Xbt, *Tbt;           // A' bar_tot of bond 1 (N_s x ldX) and bond 2 (as Theta)
+  double *Uh, *Uh2;            // left singular vectors of the bond matrix (N_s x ldC; r1 N_theta x R2 cap)
+  double *Z2, *A2e;            // bond 2: Z and the effective A (r1 N_theta x R2 cap)
+  double *U1, *V1, *Y1, *U2, *V2, *Y2;  // per-bond factors of the truncation
+  double *G1, *In, *Pf, *YG, *Qm, *AZ, *Ta, *Hm, *GBs, *S3, *Mt, *Mt1;
   double *Y;                   // R1 x N_theta R2 cap
-  double *sb, *SAb, *SBb, *cA, *cB, *lbA, *lbB;  // N each
   double* part;                // split-K partial products
   size_t part_n = 0;
-  int nsplit = 0, ksl = 0;     // split of the N_s-long contractions
+  int ksl = 0;                 // row slice of the N_s-long contractions
   bool stale = false;          // kappa changed after the steps were taped
 };
 
@@ -94,7 +98,6 @@ struct tt_ctx {
   double *Thcat, *Phcat, *Xcat, *gpart;
   double *GA, *GB1, *GR3, *GL2, *T1;
   tt::EigSlot E[6];  // bond 1: 0 G_A, 1 G_B1, 2 G_R3, 3 SVD of M1; bond 2: 4 G_L2, 5 SVD of M2
-  int eig_all = 0;   // every eigenvector (recomputation for the adjoint)
   double *M1, *C1, *Wm1, *Ur1, *P1, *Mupd1, *Thp;
   double *M2, *C2, *Wm2, *Ur2, *P2, *Mupd2;
   double *pv, *z;
@@ -112,10 +115,11 @@ struct tt_ctx {
 namespace tt {
 
 tt_status ctx_fail(tt_ctx* c, tt_status code, const std::string& msg);
-// Concatenation and rounding of one FP64 step with frozen material, leaving
-// dims[R1], dims[R2] at the input ranks (no close of the step): X_cat,
-// Theta_cat, Phi_cat and every rounding intermediate stay in the context.
-void step_body_fp64_frozen(tt_ctx* c);
+// Concatenation and rounding of one step with frozen material (FP64 or the
+// FP32-mixed form), leaving dims[R1], dims[R2] at the input ranks (no close
+// of the step): X_cat, Theta_cat, Phi_cat and every rounding intermediate
+// stay in the context; X' is in Xn (FP64) or Xnf (mixed).
+void step_body_frozen(tt_ctx* c);
 // Adjoint buffers (appended to the workspace when ckpt_every > 0).
 void grad_carve(tt_ctx* c, Carve& cv);
 // Before step number c->nhist: store a checkpoint if one is due.

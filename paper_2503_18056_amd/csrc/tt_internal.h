@@ -141,8 +141,6 @@ struct EigJob {
   int kept_idx;     // dims index receiving the kept count
   double clip;      // clip factor (1: Gram clip rule; 0: keep all lambda > 0)
   double* work;     // eig_work_doubles(ncap)
-  int all = 0;      // 1: compute and sign-fix every eigenvector (the adjoint needs
-                    // the clipped ones too); the kept count is unchanged
 };
 size_t eig_work_doubles(int ncap);
 void eig_batched(const EigJob* jobs, int njobs, int ncap, int* dims, hipStream_t s);

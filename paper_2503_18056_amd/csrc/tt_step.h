@@ -71,26 +71,15 @@ void launch_finish(int* dims, int* hist, int slot, hipStream_t st);
 void launch_check_finite(const double* x, int n, int* dims, hipStream_t st);
 
 // ---- adjoint (reverse sweep) kernels -----------------------------------------
-void launch_eig_adj_inner(double* C, int ldc, const double* lam, const double* lambar,
-                          const int* dims, int n_idx, int k_idx, int cap, hipStream_t s);
-void launch_symmetrize(double* G, int ldg, const int* dims, int n_idx, int cap, hipStream_t s);
 void launch_svd_adj_inner(const double* G1, const double* G2, int ldg, const double* sv,
                           const double* sbar, double* out, int ldo, const int* dims, int kc_idx,
                           int r_idx, int cap, hipStream_t s);
-void launch_coldot(const double* A, int lda, const double* B, int ldb, const double* scale,
-                   double* out, const int* dims, DimExpr m, DimExpr n, int ncap, hipStream_t s);
-void launch_trunc_w(const double* W, int ldw, const double* DB, const double* Vr, int ldv,
-                    const double* sv, double* sbar, double* cB, double* Vbar, int ldvb,
-                    const int* dims, int r_idx, int kb_idx, int kc_idx, hipStream_t s);
-void launch_mb_vecs(const double* Mb, int ldm, const double* C, int ldc, const double* SA,
-                    const double* SB, double* SAbar, double* SBbar, const int* dims, int ka_idx,
-                    int kb_idx, hipStream_t s);
-void launch_lambar(const double* Sbar, const double* cD, const double* S, double* lambar,
-                   const int* dims, int k_idx, int cap, hipStream_t s);
 void launch_copy_cond(const double* src, int lds, double* dst, int ldd, const int* dims,
                       int rows_idx, int kc_idx, int side_idx, int side, int cap, hipStream_t s);
 void launch_gauge_pair(double* U, int ldu, double* V, int ldv, const int* dims, int ka_idx,
                        int kb_idx, int kc_idx, int side_idx, int cap, hipStream_t s);
+void launch_add_colscaled(const double* X, int ldx, const double* sc, double* Y, int ldy,
+                          const int* dims, DimExpr r, int c_idx, int cap, hipStream_t s);
 void launch_zero_block(double* A, int lda, const int* dims, DimExpr r, DimExpr cdim, long long cap,
                        hipStream_t s);
 void launch_xcat_adjoint(const StepGeom& G, const double* X, int ldX, const double* bc_e,

@@ -17,7 +17,15 @@ truncation ranks frozen at the taped ones.  Checks:
     discretisations (rank-truncated vs full), so the bar is the truncation
     effect, below 1e-4 relative at tolerance 1e-6;
   * the state after tt_grad is the state before it;
-  * the torch.autograd.Function path gives the same gradient.
+  * the torch.autograd.Function path gives the same gradient;
+  * the FP32-mixed form (recomputed in its own precision, reversed in FP64)
+    against the same oracle differences with its own ranks replayed (1e-4:
+    its trajectory differs from the FP64 one by ~1e-6 relative);
+  * the differentiation workload at full size (128^2, 16x32, 50 steps, a
+    checkpoint every 10): FP64 and FP32-mixed gradients against central
+    differences of the library's FP64 forward (ranks replayed) on 32 seeded
+    cells (1e-4), and the FP64 gradient against the oracle's full-grid
+    adjoint (bar: the truncation effect, stated in the test).
 """
 import sys
 
@@ -213,3 +221,77 @@ def test_grad_c5_small_vs_full_grid_adjoint():
     assert abs(L - Lf) <= 1e-5 * abs(Lf)
     assert rel < 1e-4
     assert err < 1e-4
+
+
+def test_grad_mixed_vs_oracle_fd():
+    from paper_2503_18056_amd import TT_FP32_MIXED
+    p = _small("inflow", 29)
+    nsteps = 5
+    rng = np.random.default_rng(29)
+    det = np.zeros(p["nx"] * p["ny"])
+    det[rng.choice(det.size, 12, replace=False)] = 1.0
+    st = _state(p, nsteps, 2, precision=TT_FP32_MIXED)
+    st.step(nsteps)
+    ranks = st.tt_get_rank_history()
+    L, g = st.tt_grad(det)
+    g = g.cpu().numpy()
+    L0 = _oracle_loss(p, p["kappa"], nsteps, det, ranks)
+    cells = rng.choice(det.size, 8, replace=False)
+    gfd = oadj.grad_fd(lambda k: _oracle_loss(p, k, nsteps, det, ranks), p["kappa"], cells, 1e-4)
+    err = _rel_err(g[cells], gfd)
+    _log(f"mixed grad: ranks {ranks} L={L:.10e} oracle {L0:.10e}; max rel err vs oracle FD {err:.2e}")
+    assert abs(L - L0) <= 1e-6 * abs(L0)
+    assert err < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_grad_c5_full_size():
+    """The differentiation workload as specified: 128^2 cells, 16x32
+    ordinates, kappa = exp(GRF), 50 steps, checkpoint every 10, detector
+    patch 16x16; 32 seeded cells."""
+    from paper_2503_18056_amd import TT_FP32_MIXED, TT_RANK_REPLAY
+    p = wl.c5()
+    steps, K = p["steps"], p["ckpt_every"]
+    det = p["detector"]
+    st = _state(p, steps, K)
+    st.step(steps)
+    ranks = st.tt_get_rank_history()
+    L, g = st.tt_grad(det)
+    g = g.cpu().numpy()
+    sm = _state(p, steps, K, precision=TT_FP32_MIXED)
+    sm.step(steps)
+    ranks_m = sm.tt_get_rank_history()
+    Lm, gm = sm.tt_grad(det)
+    gm = gm.cpu().numpy()
+    sm.close()
+    fd = _state(p, steps, 0, rank_mode=TT_RANK_REPLAY)
+
+    def loss(k, rk):
+        fd.tt_set_kappa(k)
+        fd.tt_set_cores(p["X0"], p["Th0"], p["Ph0"])
+        fd.tt_set_rank_schedule(rk)
+        fd.step(steps)
+        E, _, _ = fd.tt_energy()
+        return float(np.sum(det * E.cpu().numpy()) * fd.cell_volume())
+
+    rng = np.random.default_rng(5)
+    cand = np.flatnonzero(np.abs(g) >= 1e-3 * np.max(np.abs(g)))
+    cells = rng.choice(cand, 32, replace=False)
+    gfd = oadj.grad_fd(lambda k: loss(k, ranks), p["kappa"], cells, 1e-4)
+    err = _rel_err(g[cells], gfd)
+    same = ranks_m == ranks
+    gfd_m = gfd if same else oadj.grad_fd(lambda k: loss(k, ranks_m), p["kappa"], cells, 1e-4)
+    err_m = _rel_err(gm[cells], gfd_m)
+    mix_vs_64 = np.max(np.abs(gm - g)) / np.max(np.abs(g))
+    Lf, gf = oadj.grad_full(Setup(p), steps, det)
+    rel_full = np.max(np.abs(g - gf)) / np.max(np.abs(gf))
+    _log(f"c5 full size: ranks end {ranks[-1]} (max {max(r for r, _ in ranks)}), L={L:.10e}, "
+         f"mixed L={Lm:.10e}, full-grid L={Lf:.10e}")
+    _log(f"  fp64 vs FD (32 cells) {err:.2e}; mixed vs FD {err_m:.2e} (mixed ranks equal: {same}); "
+         f"mixed vs fp64 gradient {mix_vs_64:.2e}; fp64 vs full-grid adjoint {rel_full:.2e}")
+    assert err < 1e-4
+    assert err_m < 1e-4
+    # the TT forward at tolerance 1e-6 with rank cap 128 differs from the full
+    # grid by the truncation; its loss difference bounds the scale of the gap
+    rel_L = abs(L - Lf) / abs(Lf)
+    assert rel_full < max(1e-3, 100 * rel_L)
