@@ -29,6 +29,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TT steps/s at 256²×2048 angles; FP32-mixed vs FP64 speedup at rel err 1e-6"
 FP64_PEAK_TFLOPS = 78.6
+GRAM_ROWS_MAX = 384          # widest concatenated rank the row-slice Gram holds in LDS
+R1CAP = 5 * 64 + 2 + 1       # crossing beams: B r1_cap + 2 inflow terms + emission slot
+GRAM_KERNEL64 = "k_gram_rows<double> (left Gram X_cat^T X_cat, row slices staged in LDS, FP64 MFMA)"
+GRAM_KERNEL32 = "k_gram_rows<float> (sliced exact Gram on FP32 MFMA, 10 slice products)"
+ROUNDING_PHASES = ("gram_tall", "gram_reduce", "eig_bond1", "eig_M1", "eig_bond2", "eig_M2",
+                   "x_update", "small_gemm")
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
@@ -121,7 +127,7 @@ def mixed_run(p, W, K, dt, hist, end64):
         "rank_history_equal_steps": sum(a == b for a, b in zip(histm, hist)),
         "ranks_end": list(sm.ranks()),
         "gram_kernel": {
-            "kernel": "k_gram_split (sliced Gram on FP32 MFMA, 10 slice products)",
+            "kernel": GRAM_KERNEL32 if R1CAP <= GRAM_ROWS_MAX else "k_gram_split",
             "avg_launch_ms": gm_ms / gm_n if gm_n else None,
             "achieved_algorithmic_TFLOPs": flops_m / (gm_ms * 1e-3) / 1e12 if gm_ms > 0 else 0.0,
             "peak_fp32_mfma_TFLOPs": FP32_MFMA_PEAK_TFLOPS,
@@ -208,6 +214,7 @@ def main():
     flops = sum(gram_flops(ns, R) for R in R1s)
     achieved = flops / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else 0.0
     breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1]} for k, v in prof.items()}
+    round_ms = sum(prof.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES)
     end64 = st.cores()
     ranks64 = list(st.ranks())
     st.close()
@@ -233,8 +240,14 @@ def main():
         "ranks_end": ranks64,
         "zcps": ns * K / dt,
         "angle_updates_per_s": ns * nang * K / dt,
+        "rounding": {
+            "ms_per_rounding": round_ms / K,
+            "roundings_per_s": K / (round_ms * 1e-3) if round_ms > 0 else None,
+            "note": "Gram-SVD rounding phases of the timed steps (Grams, eigensolves, SVDs, "
+                    "truncation and core updates), from the library's HIP events",
+        },
         "roofline": {
-            "kernel": "k_gram_tall (left Gram X_cat^T X_cat, FP64 MFMA)",
+            "kernel": GRAM_KERNEL64 if R1CAP <= GRAM_ROWS_MAX else "k_gram_tall + k_gram_reduce",
             "bound": "mfma",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
