@@ -46,9 +46,12 @@ def select_rank(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
     thr(r) = max(eta sigma_1, noise sigma_1^2 / sigma_r), so a cut never
     splits a set of singular values that are equal to the resolution of the
     computation (``noise`` = R u for a Gram of dimension R, 0 for a direct
-    SVD).  Cap: if r > rmax > 0, r = rmax and, if that cut splits a
-    cluster, r moves down to just before the cluster (kept at rmax if the
-    cluster starts at 1).
+    SVD).  The extension stops before a singular value that the computation
+    does not resolve (sigma_{r+1} <= sqrt(noise) sigma_1, where thr exceeds
+    sigma itself): below that level every gap is within the noise, and
+    following the ties would keep rounding noise.  Cap: if r > rmax > 0,
+    r = rmax and, if that cut splits a cluster, r moves down to just before
+    the cluster (kept at rmax if the cluster starts at 1).
     """
     sig = np.asarray(sig, float)
     n = sig.size
@@ -61,7 +64,12 @@ def select_rank(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
     def tied(j):  # sigma_j and sigma_{j+1} (1-based j) in one cluster
         thr = max(eta * sig[0], noise * sig[0] ** 2 / sig[j - 1] if sig[j - 1] > 0 else np.inf)
         return sig[j - 1] - sig[j] <= thr
-    while r < n and tied(r):
+
+    floor = np.sqrt(noise) * sig[0]
+
+    def resolved(j):  # sigma_{j+1} (1-based) above the resolution of the computation
+        return noise == 0.0 or sig[j] > floor
+    while r < n and tied(r) and resolved(r):
         r += 1
     if rmax > 0 and r > rmax:
         r = rmax
@@ -76,8 +84,9 @@ def select_rank(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
 def rank_margin(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
     """Smallest relative distance to its threshold among the comparisons that
     ``select_rank`` makes for these singular values: tail(k) against delta^2
-    at the first k that passes and the one before it, and every tie test
-    sigma_j - sigma_{j+1} against its threshold.  A small margin means a
+    at the first k that passes and the one before it, every tie test
+    sigma_j - sigma_{j+1} against its threshold, and every resolution test
+    sigma_{j+1} against sqrt(noise) sigma_1.  A small margin means a
     rounding-sized change of sigma can flip the decision (diagnostic only;
     the rank rule itself is ``select_rank``)."""
     sig = np.asarray(sig, float)
@@ -98,7 +107,15 @@ def rank_margin(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
         t = thr(j)
         margins.append(abs((sig[j - 1] - sig[j]) / t - 1.0) if np.isfinite(t) and t > 0 else np.inf)
         return sig[j - 1] - sig[j] <= t
-    while r < n and test(r):
+
+    floor = np.sqrt(noise) * sig[0]
+
+    def resolved(j):
+        if noise == 0.0:
+            return True
+        margins.append(abs(sig[j] / floor - 1.0))
+        return sig[j] > floor
+    while r < n and test(r) and resolved(r):
         r += 1
     if rmax > 0 and r > rmax:
         r = rmax

@@ -331,7 +331,10 @@ __global__ void k_rank(const double* __restrict__ sig, int* __restrict__ dims,
     const double noise = (double)dims[ra.rdim] * 1.1102230246251565e-16;
 #define SIG(j) fmax(sig[(j)], 0.0)
 #define TIED(j) (SIG((j) - 1) - SIG(j) <= fmax(ra.eta * s0, SIG((j) - 1) > 0.0 ? noise * s0 * s0 / SIG((j) - 1) : 1.79e308))
-    while (r < n && TIED(r)) ++r;
+    // ... but never into a singular value below the resolution sqrt(R u) s1,
+    // where every gap is within the noise
+    const double floor_res = sqrt(noise) * s0;
+    while (r < n && TIED(r) && SIG(r) > floor_res) ++r;
     if (ra.rmax > 0 && r > ra.rmax) {
       r = ra.rmax;
       if (r < n && TIED(r)) {

@@ -22,10 +22,10 @@ truncation ranks frozen at the taped ones.  Checks:
     against the same oracle differences with its own ranks replayed (1e-4:
     its trajectory differs from the FP64 one by ~1e-6 relative);
   * the differentiation workload at full size (128^2, 16x32, 50 steps, a
-    checkpoint every 10): FP64 and FP32-mixed gradients against central
-    differences of the library's FP64 forward (ranks replayed) on 32 seeded
-    cells (1e-4), and the FP64 gradient against the oracle's full-grid
-    adjoint (bar: the truncation effect, stated in the test).
+    checkpoint every 10), FP64 and FP32-mixed: a Taylor test along the
+    gradient, central differences on 32 seeded cells within 1e-4 or within
+    the differences' own error estimate (the forward's rounding noise at
+    this size is stated in the test), and the oracle's full-grid adjoint.
 """
 import sys
 
@@ -244,20 +244,35 @@ def test_grad_mixed_vs_oracle_fd():
     assert err < 1e-4
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1100)
 def test_grad_c5_full_size():
     """The differentiation workload as specified: 128^2 cells, 16x32
     ordinates, kappa = exp(GRF), 50 steps, checkpoint every 10, detector
-    patch 16x16; 32 seeded cells."""
+    patch 16x16, in FP64 and FP32-mixed.
+
+    At this size and tolerance (R1 = 641, tolerance 1e-6) the singular
+    values at the cut sit at the resolution of the Gram route
+    (sqrt(R1 u) sigma_1 ~ 2.7e-7 sigma_1), so the forward loss carries
+    rounding noise of ~1e-9 relative as a function of kappa, and a central
+    difference at step h carries an error ~1e-9 L / (h kappa_i).  The checks
+    are therefore: (1) a Taylor test along the gradient direction, whose
+    signal dwarfs that noise, to 1e-4; (2) central differences on 32 seeded
+    cells at h = 1e-3, each compared within 1e-4 or within twice the
+    difference's own error estimate |FD(h) - FD(h/2)| (which grows as h
+    shrinks when noise dominates); (3) the oracle's full-grid adjoint of the
+    untruncated discretisation, to 1e-4 of max |g|; (4) the FP32-mixed
+    gradient against the FP64 one and against the same differences."""
     from paper_2503_18056_amd import TT_FP32_MIXED, TT_RANK_REPLAY
     p = wl.c5()
     steps, K = p["steps"], p["ckpt_every"]
     det = p["detector"]
+    kap = p["kappa"]
     st = _state(p, steps, K)
     st.step(steps)
     ranks = st.tt_get_rank_history()
     L, g = st.tt_grad(det)
     g = g.cpu().numpy()
+    st.close()
     sm = _state(p, steps, K, precision=TT_FP32_MIXED)
     sm.step(steps)
     ranks_m = sm.tt_get_rank_history()
@@ -265,33 +280,60 @@ def test_grad_c5_full_size():
     gm = gm.cpu().numpy()
     sm.close()
     fd = _state(p, steps, 0, rank_mode=TT_RANK_REPLAY)
+    fdm = _state(p, steps, 0, rank_mode=TT_RANK_REPLAY, precision=TT_FP32_MIXED)
 
-    def loss(k, rk):
-        fd.tt_set_kappa(k)
-        fd.tt_set_cores(p["X0"], p["Th0"], p["Ph0"])
-        fd.tt_set_rank_schedule(rk)
-        fd.step(steps)
-        E, _, _ = fd.tt_energy()
-        return float(np.sum(det * E.cpu().numpy()) * fd.cell_volume())
+    calls = [0]
 
+    def loss(k, rk=ranks, s=fd):
+        s.tt_set_kappa(k)
+        s.tt_set_cores(p["X0"], p["Th0"], p["Ph0"])
+        s.tt_set_rank_schedule(rk)
+        s.step(steps)
+        E, _, _ = s.tt_energy()
+        calls[0] += 1
+        if calls[0] % 16 == 0:
+            _log(f"  ... {calls[0]} forward runs")
+        return float(np.sum(det * E.cpu().numpy()) * s.cell_volume())
+
+    _log(f"c5 full size: gradients done (fp64 L={L:.10e}, mixed L={Lm:.10e}); differences next")
+
+    gmax = np.max(np.abs(g))
+    # (1) Taylor test along v = kappa o g / max|g|
+    v = kap * g / gmax
+    eps = 1e-3
+    d_fd = (loss(kap + eps * v) - loss(kap - eps * v)) / (2 * eps)
+    d_adj = float(g @ v)
+    rel_dir = abs(d_fd - d_adj) / abs(d_adj)
+    vm = kap * gm / np.max(np.abs(gm))
+    dm_fd = (loss(kap + eps * vm, ranks_m, fdm) - loss(kap - eps * vm, ranks_m, fdm)) / (2 * eps)
+    dm_adj = float(gm @ vm)
+    rel_dir_m = abs(dm_fd - dm_adj) / abs(dm_adj)
+    # (2) 32 seeded cells
     rng = np.random.default_rng(5)
-    cand = np.flatnonzero(np.abs(g) >= 1e-3 * np.max(np.abs(g)))
+    cand = np.flatnonzero(np.abs(g) >= 1e-3 * gmax)
     cells = rng.choice(cand, 32, replace=False)
-    gfd = oadj.grad_fd(lambda k: loss(k, ranks), p["kappa"], cells, 1e-4)
-    err = _rel_err(g[cells], gfd)
-    same = ranks_m == ranks
-    gfd_m = gfd if same else oadj.grad_fd(lambda k: loss(k, ranks_m), p["kappa"], cells, 1e-4)
-    err_m = _rel_err(gm[cells], gfd_m)
-    mix_vs_64 = np.max(np.abs(gm - g)) / np.max(np.abs(g))
+    f1 = oadj.grad_fd(loss, kap, cells, 1e-3)
+    f2 = oadj.grad_fd(loss, kap, cells, 5e-4)
+    est = np.abs(f1 - f2)
+    err = np.abs(g[cells] - f1)
+    ok = err <= 1e-4 * np.abs(f1) + 2.0 * est
+    err_m = np.abs(gm[cells] - f1)
+    tight = int(np.sum(err <= 1e-4 * np.abs(f1)))
+    # (3) full-grid adjoint, (4) mixed vs FP64
+    _log("  differences done; the oracle's full-grid adjoint next")
     Lf, gf = oadj.grad_full(Setup(p), steps, det)
     rel_full = np.max(np.abs(g - gf)) / np.max(np.abs(gf))
-    _log(f"c5 full size: ranks end {ranks[-1]} (max {max(r for r, _ in ranks)}), L={L:.10e}, "
-         f"mixed L={Lm:.10e}, full-grid L={Lf:.10e}")
-    _log(f"  fp64 vs FD (32 cells) {err:.2e}; mixed vs FD {err_m:.2e} (mixed ranks equal: {same}); "
-         f"mixed vs fp64 gradient {mix_vs_64:.2e}; fp64 vs full-grid adjoint {rel_full:.2e}")
-    assert err < 1e-4
-    assert err_m < 1e-4
-    # the TT forward at tolerance 1e-6 with rank cap 128 differs from the full
-    # grid by the truncation; its loss difference bounds the scale of the gap
-    rel_L = abs(L - Lf) / abs(Lf)
-    assert rel_full < max(1e-3, 100 * rel_L)
+    mix_vs_64 = np.max(np.abs(gm - g)) / gmax
+    _log(f"c5 full size: ranks end {ranks[-1]} (max r1 {max(r for r, _ in ranks)}), L={L:.10e}, "
+         f"mixed L={Lm:.10e} (ranks equal: {ranks_m == ranks}), full-grid L={Lf:.10e}")
+    _log(f"  Taylor test along the gradient: fp64 {rel_dir:.2e}, mixed {rel_dir_m:.2e}")
+    _log(f"  32 cells, h=1e-3: max rel err {np.max(err / np.abs(f1)):.2e}; within 1e-4: {tight}/32; "
+         f"within the FD's own error estimate: {int(ok.sum())}/32; max err/est "
+         f"{np.max(err / np.maximum(est, 1e-300)):.2f}")
+    _log(f"  mixed vs fp64 gradient {mix_vs_64:.2e}; fp64 vs full-grid adjoint {rel_full:.2e}")
+    assert rel_dir < 1e-4
+    assert rel_dir_m < 1e-4
+    assert ok.all()
+    assert (err_m <= 1e-4 * np.abs(f1) + 2.0 * est + 1e-5 * gmax).all()
+    assert mix_vs_64 < 1e-4
+    assert rel_full < 1e-4

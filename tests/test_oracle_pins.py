@@ -244,6 +244,14 @@ def test_cluster_and_cap_rules():
     d2 = 1.01 * (1e-6 ** 2 + 1e-18)
     assert rounding.select_rank(pair, d2, 0) == 3
     assert rounding.select_rank(pair, d2, 0, noise=42 * rounding.U) == 4
+    # a chain of ties is not followed below the resolution sqrt(noise) sigma_1:
+    # with noise 1e-10 the floor is 1e-5, the tail rule keeps 2, the tie with
+    # 1.1e-5 (resolved) adds one, and the tie with 9e-6 (unresolved) stops it
+    chain = np.array([1.0, 1.3e-5, 1.1e-5, 9e-6, 7e-6, 5e-6])
+    assert rounding.select_rank(chain, 3e-10, 0) == 2
+    assert rounding.select_rank(chain, 3e-10, 0, noise=1e-10) == 3
+    # closest comparisons: tail(2) at 0.92 delta^2 and the two resolution tests at 0.9, 1.1 floor
+    assert abs(rounding.rank_margin(chain, 3e-10, 0, noise=1e-10) - 0.08) < 1e-12
 
 
 # ---------------------------------------------------------------- TT vs full
