@@ -39,6 +39,38 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_gram_rows_fp64_traffic.md")
+
+
+def gram_rows_digest():
+    """Digest of the row-slice Gram kernel's source (its shape constants and
+    body), to tell whether stored byte counters still describe it."""
+    import hashlib
+    s = open(os.path.join(ROOT, "paper_2503_18056_amd", "csrc", "k_gemm.hip")).read()
+    a = s.index("// row-slice Gram (k_gram_rows) shape")
+    b = s.index("\n\n", s.index("constexpr int GR_TPW"))
+    k0 = s.index("template <typename T>\n__global__ __launch_bounds__(GR_THREADS)")
+    k1 = s.index("__global__ __launch_bounds__(256) void k_gram_rows_reduce")
+    return hashlib.sha256((s[a:b] + s[k0:k1]).encode()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """(bytes per launch, algorithmic bytes per launch) from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or (None, None) if the kernel
+    changed since the counters were taken."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith(("#", "|", " ", "`")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_digest") != gram_rows_digest():
+            return None, None
+        return float(kv["traffic_bytes_per_launch"]), float(kv["algorithmic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None, None
+
+
 def gram_flops(ns, R1):
     """Algorithmic flops of the symmetric left Gram of an N_s x R1 core."""
     return float(ns) * R1 * (R1 + 1)
@@ -55,9 +87,16 @@ def tt_inner(A, B):
 
 
 def tt_rel_diff(A, B):
-    """||A - B|| / ||B|| from inner products (resolves differences above ~1e-8)."""
+    """||A - B|| / ||B|| from inner products (resolves differences above ~1e-8);
+    None when B is the zero tensor."""
     aa, bb, ab = tt_inner(A, A), tt_inner(B, B), tt_inner(A, B)
+    if not bb > 0.0:
+        return None
     return max(aa + bb - 2.0 * ab, 0.0) ** 0.5 / bb ** 0.5
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def timed_run(p, W, K, precision):
@@ -203,7 +242,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     p = wl.c2(steps=W + K)
+    progress(f"crossing beams, FP64: {W} warmup + {K} timed steps")
     st, dt, prof, warm_cores, r_start = timed_run(p, W, K, TT_FP64)
+    progress(f"FP64 done: {K / dt:.1f} steps/s")
     hist = st.tt_get_rank_history()
     ns = p["nx"] * p["ny"]
     nang = p["ntheta"] * p["nphi"]
@@ -215,9 +256,14 @@ def main():
     achieved = flops / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else 0.0
     breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1]} for k, v in prof.items()}
     round_ms = sum(prof.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES)
+    traffic, alg_bytes = stored_traffic()
     end64 = st.cores()
     ranks64 = list(st.ranks())
     st.close()
+    progress(f"FP64 end state: ranks {ranks64}, max |X| {abs(end64[0]).max():.3e}, "
+             f"max |Phi| {abs(end64[2]).max():.3e}")
+    if not args.no_mixed:
+        progress("crossing beams, FP32-mixed")
     mixed = None if args.no_mixed else mixed_run(p, W, K, dt, hist, end64)
     out = {
         "metric": METRIC,
@@ -253,7 +299,10 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                            "profiles/c2_gram_rows_fp64_traffic.md)",
+            "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": gram_ms / gram_n if gram_n else None,
             "algorithmic_flops_per_launch_avg": flops / max(1, gram_n),
         },
@@ -261,8 +310,10 @@ def main():
         "fp32_mixed": mixed,
     }
     if not args.no_grad:
+        progress("differentiation workload: taped forward and reverse sweep")
         out["gradient"] = gradient_run()
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline (about 15 s)")
         out["cpu_baseline"] = cpu_baseline(p, warm_cores)
     print(json.dumps(out), flush=True)
 

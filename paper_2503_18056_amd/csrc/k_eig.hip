@@ -598,25 +598,14 @@ __global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__
     D.mrho[m] = rho;
     D.mm2[m] = m2;
   }
-}
-
-// Permute the merge block's columns into slot order and apply the Givens
-// rotations of the deflation; blocks without a partner are copied.
-__global__ __launch_bounds__(256) void k_dc_rotate(EigJobs jobs, int* __restrict__ dims, int N, int S) {
-  const EigJob J = jobs.j[blockIdx.y];
-  const int n = dims[J.n_idx];
-  Work W = work_of(J, N);
-  DC D = dc_of(W, N);
-  const int N2 = next_pow2(N);
-  const int m = blockIdx.x, b0 = m * 2 * S;
-  if (b0 >= n) return;
-  const int nk = D.mk[m];
-  if (nk < 0) return;  // no partner: the block is left as it is
-  const int m2 = D.mm2[m], nrot = D.mnrot[m];
-  for (int r = b0 + threadIdx.x; r < b0 + m2; r += 256) {
+  __syncthreads();
+  // permute the merge block's columns into slot order and apply the Givens
+  // rotations of the deflation (a thread per row)
+  const int nrot = D.mnrot[m];
+  for (int r = b0 + tid; r < b0 + m2; r += 256) {
     double* qb = D.Qb + (size_t)r * N2 + b0;
     const double* qa = D.Qa + (size_t)r * N2 + b0;
-    for (int s = 0; s < m2; ++s) qb[s] = qa[D.perm[b0 + s]];
+    for (int t = 0; t < m2; ++t) qb[t] = qa[perm[t]];
     for (int t = 0; t < nrot; ++t) {
       const int p = D.rp[b0 + t], q = D.rq[b0 + t];
       const double c = D.rc[b0 + t], sn = D.rs[b0 + t];
@@ -902,30 +891,57 @@ __device__ inline double keep_threshold(const EigJob& J, const double* w, int n)
 
 // ---------------------------------------------------------------------------
 // 3. Back-transformation V[:, n-1-j] = H_0 H_1 ... H_{n-3} q_j for the kept
-// eigenvectors q_j of T (columns of the D&C result).
+// eigenvectors q_j of T (columns of the D&C result), a wavefront per vector.
+// The reflectors are staged through LDS in chunks of ch (one cooperative
+// load per chunk), so the sequential loop over them reads only LDS.
+constexpr int ORM_CH = 32;
+__host__ __device__ inline int ormtr_chunk(int N) {
+  const int c = 12288 / (N > 0 ? N : 1);
+  return c < 1 ? 1 : (c > ORM_CH ? ORM_CH : c);
+}
+
 __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
+  const int ch = ormtr_chunk(N);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + wave;
-  __shared__ double ys[4][1024];
-  if (j >= n) return;
+  const int j0 = blockIdx.x * 4, j = j0 + wave;
+  if (j0 >= n) return;
   const double thr = keep_threshold(J, D.lam, n);
-  if (!(D.lam[j] > thr)) return;
+  // eigenvalues ascend, so the block's last vector is its largest
+  if (!(D.lam[min(j0 + 3, n - 1)] > thr)) return;
+  const bool active = j < n && D.lam[j] > thr;
+  __shared__ double ys[4][1024];
+  extern __shared__ double hs[];  // ch reflectors of length N, then their tau
+  double* ts = hs + (size_t)ch * N;
   double* y = ys[wave];
-  for (int i = lane; i < n; i += 64) y[i] = D.Qa[(size_t)i * N2 + j];
-  for (int k = n - 3; k >= 0; --k) {
-    const double tau = W.tau[k];
-    if (tau == 0.0) continue;
-    const double* v = W.H + (size_t)k * N;
-    double part = 0.0;
-    for (int i = k + 1 + lane; i < n; i += 64) part += v[i] * y[i];
-    const double dot = wave_sum(part) * tau;
-    for (int i = k + 1 + lane; i < n; i += 64) y[i] -= dot * v[i];
+  if (active)
+    for (int i = lane; i < n; i += 64) y[i] = D.Qa[(size_t)i * N2 + j];
+  for (int k1 = n - 3; k1 >= 0; k1 -= ch) {
+    const int k0 = max(0, k1 - ch + 1);
+    __syncthreads();
+    for (int kk = k0 + wave; kk <= k1; kk += 4) {
+      const double* src = W.H + (size_t)kk * N;
+      double* dst = hs + (size_t)(kk - k0) * N;
+      for (int i = kk + 1 + lane; i < n; i += 64) dst[i] = src[i];
+      if (lane == 0) ts[kk - k0] = W.tau[kk];
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int k = k1; k >= k0; --k) {
+      const double tau = ts[k - k0];
+      if (tau == 0.0) continue;
+      const double* v = hs + (size_t)(k - k0) * N;
+      double part = 0.0;
+      for (int i = k + 1 + lane; i < n; i += 64) part += v[i] * y[i];
+      const double dot = wave_sum(part) * tau;
+      for (int i = k + 1 + lane; i < n; i += 64) y[i] -= dot * v[i];
+    }
   }
+  if (!active) return;
   const int col = n - 1 - j;
   for (int i = lane; i < n; i += 64) J.V[(size_t)i * J.ldv + col] = y[i];
 }
@@ -953,40 +969,52 @@ __device__ void gauge_columns(double* V, int ldv, int nrow, int ncol) {
 }
 
 // ---------------------------------------------------------------------------
-// 4. Descending eigenvalues, kept count, sqrt scalings and sign gauge.
+// 4. Descending eigenvalues, kept count, sqrt scalings and sign gauge.  Each
+// block takes 16 columns of the gauge (and recounts the kept eigenvalues from
+// an LDS copy of them); block 0 also writes the count and the scalings.
+constexpr int FINAL_COLS = 16;
 __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict__ dims, int N) {
-  const EigJob J = jobs.j[blockIdx.x];
+  const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
+  const int c0 = blockIdx.x * FINAL_COLS;
+  if (c0 >= n && blockIdx.x > 0) return;  // block 0 always writes the count
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   __shared__ int s_kept;
+  __shared__ double sl[1024];
   const int tid = threadIdx.x;
   const double thr = keep_threshold(J, D.lam, n);
+  for (int c = tid; c < n; c += 256) sl[c] = D.lam[c];
+  __syncthreads();
   if (tid == 0) {
     int k = 0, bad = 0;
     for (int j = n - 1; j >= 0; --j) {
-      if (!(D.lam[j] == D.lam[j])) bad = 1;
-      if (D.lam[j] > thr) ++k;
+      if (!(sl[j] == sl[j])) bad = 1;
+      if (sl[j] > thr) ++k;
       else break;
     }
     s_kept = k;
-    dims[J.kept_idx] = k;
-    if (bad) atomicOr(&dims[D_FLAG], FLAG_EIG);
+    if (blockIdx.x == 0) {
+      dims[J.kept_idx] = k;
+      if (bad) atomicOr(&dims[D_FLAG], FLAG_EIG);
+    }
   }
   __syncthreads();
   const int kept = s_kept;
-  for (int c = tid; c < n; c += 256) {
-    const double l = D.lam[n - 1 - c];
-    J.lam[c] = l;
-    if (c < kept) {
-      const double s = sqrt(l);
-      J.sq[c] = s;
-      J.isq[c] = 1.0 / s;
+  if (blockIdx.x == 0) {
+    for (int c = tid; c < n; c += 256) {
+      const double l = sl[n - 1 - c];
+      J.lam[c] = l;
+      if (c < kept) {
+        const double s = sqrt(l);
+        J.sq[c] = s;
+        J.isq[c] = 1.0 / s;
+      }
     }
   }
-  gauge_columns(J.V, J.ldv, n, kept);
+  const int c1 = min(c0 + FINAL_COLS, kept);
+  if (c0 < c1) gauge_columns(J.V + c0, J.ldv, n, c1 - c0);
 }
-
 
 // ---------------------------------------------------------------------------
 // 5. Small SVD through the Golub-Kahan tridiagonal.  With M = Q_L B Q_R^T
@@ -1235,16 +1263,29 @@ __global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M
     __syncthreads();
     tau = s_tau;
     if (tau != 0.0) {
-      // rows k+1..p-1: A[i, k+1:] -= tau (A[i, k+1:] . v) v^T, a thread per row
-      for (int i = k + 1 + tid; i < p; i += 1024) {
+      // rows k+1..p-1: A[i, k+1:] -= tau (A[i, k+1:] . v) v^T; 128 rows at a
+      // time, each row's dot product split over 8 column groups
+      for (int r0 = k + 1; r0 < p; r0 += 128) {
+        const int i = r0 + cj;
         double* row = A + i * lq + k + 1;
-        double sdot = 0.0;
-        for (int j = 0; j < nc; ++j) sdot += row[j] * sv[j];
-        sdot *= tau;
-        for (int j = 0; j < nc; ++j) row[j] -= sdot * sv[j];
+        if (i < p) {
+          double acc = 0.0;
+          for (int j = g; j < nc; j += 8) acc += row[j] * sv[j];
+          sp[g][cj] = acc;
+        }
+        __syncthreads();
+        if (i < p) {
+          double sdot = 0.0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) sdot += sp[t][cj];
+          sdot *= tau;
+          for (int j = g; j < nc; j += 8) row[j] -= sdot * sv[j];
+        }
+        __syncthreads();
       }
+    } else {
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -1340,19 +1381,14 @@ void dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims
   for (int S = DC_LEAF; S < N; S *= 2) {
     const int nm = (N + 2 * S - 1) / (2 * S);
     k_dc_prep<<<dim3(nm, njobs), 256, (size_t)2 * S * PREP_BYTES_PER, s>>>(J, dims, N, S);
-    k_dc_rotate<<<dim3(nm, njobs), 256, 0, s>>>(J, dims, N, S);
     k_dc_secular<<<dim3((2 * S + 3) / 4, nm, njobs), 256, (size_t)2 * S * 16, s>>>(J, dims, N, S);
     k_dc_vectors<<<dim3(nm, njobs), 256, (size_t)2 * S * 36, s>>>(J, dims, N, S);
-    for (int q = 0; q < njobs; ++q) {
+    {
       // Q block <- Q_rot block * U block, for every merge block of this level
-      const double* wbase = jobs[q].work;
-      const size_t off_z = 4 * (size_t)N + (size_t)N * N;
-      const double* Qa = wbase + off_z + N2;
-      const double* Qb = Qa + (size_t)N2 * N2;
-      const double* U = Qb + (size_t)N2 * N2;
+      // of every job (one launch)
+      const int bm = (N + 2 * S - 1) / (2 * S);
       GemmDesc g;
       memset(&g, 0, sizeof(g));
-      g.A = Qb; g.B = U; g.C = const_cast<double*>(Qa);
       g.lda = N2; g.ldb = 2 * S; g.ldc = N2;
       g.sA = (long long)2 * S * (N2 + 1);
       g.sB = (long long)4 * S * S;
@@ -1362,11 +1398,23 @@ void dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims
       g.cond_idx = -1;
       // block z holds rows/cols [z 2S, z 2S + min(2S, n - z 2S)); it has a
       // merge only when n - z 2S > S
-      g.bclip_idx = jobs[q].n_idx;
+      g.bclip_idx = -1;
       g.bclip_mul = 2 * S;
       g.bclip_min = S;
-      const int bm = (N + 2 * S - 1) / (2 * S);
-      gemm(g, 2 * S, 2 * S, bm, dims, s);
+      g.njob = njobs;
+      g.zper = bm;
+      for (int q = 0; q < njobs; ++q) {
+        const double* wbase = jobs[q].work;
+        const size_t off_z = 4 * (size_t)N + (size_t)N * N;
+        const double* Qa = wbase + off_z + N2;
+        const double* Qb = Qa + (size_t)N2 * N2;
+        const double* U = Qb + (size_t)N2 * N2;
+        g.Aj[q] = Qb;
+        g.Bj[q] = U;
+        g.Cj[q] = const_cast<double*>(Qa);
+        g.bclipj[q] = jobs[q].n_idx;
+      }
+      gemm(g, 2 * S, 2 * S, njobs * bm, dims, s);
     }
   }
 }
@@ -1380,8 +1428,9 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   k_sytrd_lds<<<njobs, 1024, 0, s>>>(J, dims, N);
   if (N > SYTRD_LDS_MAX) k_sytrd<<<njobs, 1024, 0, s>>>(J, dims, N);
   dc_levels(jobs, J, njobs, N, dims, s);
-  k_ormtr<<<dim3((N + 3) / 4, njobs), 256, 0, s>>>(J, dims, N);
-  k_eig_final<<<njobs, 256, 0, s>>>(J, dims, N);
+  k_ormtr<<<dim3((N + 3) / 4, njobs), 256, ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8, s>>>(
+      J, dims, N);
+  k_eig_final<<<dim3((N + FINAL_COLS - 1) / FINAL_COLS, njobs), 256, 0, s>>>(J, dims, N);
 }
 
 void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx,

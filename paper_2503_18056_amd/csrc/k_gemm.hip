@@ -21,9 +21,22 @@ constexpr int GR_TPW = 2;     // tasks per wavefront per pass
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict__ dims) {
   if (g.cond_idx >= 0 && dims[g.cond_idx] != g.cond_val) return;
+  int z = blockIdx.z;
+  const double* Ab = g.A;
+  const double* Bb = g.B;
+  double* Cb = g.C;
+  int bidx = g.bclip_idx;
+  if (g.njob > 0) {
+    const int jb = z / g.zper;
+    z -= jb * g.zper;
+    Ab = g.Aj[jb];
+    Bb = g.Bj[jb];
+    Cb = g.Cj[jb];
+    bidx = g.bclipj[jb];
+  }
   int m = eval_dim(dims, g.m), n = eval_dim(dims, g.n), k = eval_dim(dims, g.k);
-  if (g.bclip_idx >= 0) {
-    const int lim = dims[g.bclip_idx] - (int)blockIdx.z * g.bclip_mul;
+  if (bidx >= 0) {
+    const int lim = dims[bidx] - z * g.bclip_mul;
     if (lim <= g.bclip_min) return;
     m = min(m, lim);
     n = min(n, lim);
@@ -31,15 +44,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
   }
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   if (i0 >= m || j0 >= n) return;
-  const double* A = g.A + (long long)blockIdx.z * g.sA;
-  const double* B = g.B + (long long)blockIdx.z * g.sB;
-  double* C = g.C + (long long)blockIdx.z * g.sC;
+  const double* A = Ab + (long long)z * g.sA;
+  const double* B = Bb + (long long)z * g.sB;
+  double* C = Cb + (long long)z * g.sC;
   const double* kscale = g.kscale;
   if (g.ksplit > 0) {
-    const long long k0 = (long long)blockIdx.z * g.ksplit;
+    const long long k0 = (long long)z * g.ksplit;
     k = (int)max(0LL, min((long long)g.ksplit, (long long)k - k0));
-    A = g.A + (TA == 0 ? k0 : k0 * g.lda);
-    B = g.B + (TB == 0 ? k0 * g.ldb : k0);
+    A = Ab + (TA == 0 ? k0 : k0 * g.lda);
+    B = Bb + (TB == 0 ? k0 * g.ldb : k0);
     if (kscale) kscale += k0;
   }
   __shared__ double As[16][65];
