@@ -39,7 +39,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_gram_rows_fp64_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "crossing_beams_256sq_fp64_gram_rows_traffic.md")
 
 
 def gram_rows_digest():
@@ -301,7 +301,7 @@ def main():
             "frac": achieved / FP64_PEAK_TFLOPS,
             "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
-                            "profiles/c2_gram_rows_fp64_traffic.md)",
+                            "profiles/crossing_beams_256sq_fp64_gram_rows_traffic.md)",
             "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": gram_ms / gram_n if gram_n else None,
             "algorithmic_flops_per_launch_avg": flops / max(1, gram_n),

@@ -616,12 +616,16 @@ tt_status tt_set_cores(tt_ctx* c, const double* X, const double* Th, const doubl
   if (r[0] < 1 || r[1] < 1 || r[0] > c->r1c || r[1] > c->r2c)
     return fail(c, TT_ERR_INVALID_ARG, "ranks exceed the rank capacity");
   hipStream_t s = c->st;
-  HIPCHK(c, hipMemsetAsync(c->X, 0, (size_t)c->ns * c->ldX * 8, s));
-  HIPCHK(c, hipMemcpy2DAsync(c->X, c->ldX * 8, X, r[0] * 8, r[0] * 8, c->ns, hipMemcpyHostToDevice, s));
+  // the padded device layouts are filled from host staging copies by plain
+  // 1D transfers (kept alive until the synchronisation below)
+  const size_t xs = (size_t)c->ns * c->ldX, ths = (size_t)c->r1c * c->nt * c->r2c;
+  std::vector<double> hx(xs, 0.0), ht(ths, 0.0);
+  for (int i = 0; i < c->ns; ++i) memcpy(&hx[(size_t)i * c->ldX], X + (size_t)i * r[0], (size_t)r[0] * 8);
+  for (size_t q = 0; q < (size_t)r[0] * c->nt; ++q)
+    memcpy(&ht[q * c->r2c], Th + q * r[1], (size_t)r[1] * 8);
+  HIPCHK(c, hipMemcpyAsync(c->X, hx.data(), xs * 8, hipMemcpyHostToDevice, s));
   if (c->mixed) launch_convert(c->X, c->ldX, c->Xf, c->ldX, c->ns, c->ldX, s);
-  HIPCHK(c, hipMemsetAsync(c->Th, 0, (size_t)c->r1c * c->nt * c->r2c * 8, s));
-  HIPCHK(c, hipMemcpy2DAsync(c->Th, c->r2c * 8, Th, r[1] * 8, r[1] * 8, (size_t)r[0] * c->nt,
-                             hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->Th, ht.data(), ths * 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->Ph, Ph, (size_t)r[1] * c->np * 8, hipMemcpyHostToDevice, s));
   int hd[D_NDIMS];
   memset(hd, 0, sizeof(hd));
@@ -772,13 +776,25 @@ tt_status tt_get_cores(tt_ctx* c, double* X, double* Th, double* Ph, int32_t r[2
   HIPCHK(c, hipStreamSynchronize(c->st));
   if (r) { r[0] = rr[0]; r[1] = rr[1]; }
   hipStream_t s = c->st;
+  // plain 1D transfers of the padded device layouts into host staging copies,
+  // unpacked into the caller's buffers after the synchronisation
+  std::vector<double> hx, ht;
   if (X && c->mixed) launch_convert(c->Xf, c->ldX, c->X, c->ldX, c->ns, rr[0], s);
-  if (X) HIPCHK(c, hipMemcpy2DAsync(X, rr[0] * 8, c->X, c->ldX * 8, rr[0] * 8, c->ns, hipMemcpyDeviceToHost, s));
-  if (Th)
-    HIPCHK(c, hipMemcpy2DAsync(Th, rr[1] * 8, c->Th, c->r2c * 8, rr[1] * 8, (size_t)rr[0] * c->nt,
-                               hipMemcpyDeviceToHost, s));
+  if (X) {
+    hx.resize((size_t)c->ns * c->ldX);
+    HIPCHK(c, hipMemcpyAsync(hx.data(), c->X, hx.size() * 8, hipMemcpyDeviceToHost, s));
+  }
+  if (Th) {
+    ht.resize((size_t)rr[0] * c->nt * c->r2c);
+    HIPCHK(c, hipMemcpyAsync(ht.data(), c->Th, ht.size() * 8, hipMemcpyDeviceToHost, s));
+  }
   if (Ph) HIPCHK(c, hipMemcpyAsync(Ph, c->Ph, (size_t)rr[1] * c->np * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  if (X)
+    for (int i = 0; i < c->ns; ++i) memcpy(X + (size_t)i * rr[0], &hx[(size_t)i * c->ldX], (size_t)rr[0] * 8);
+  if (Th)
+    for (size_t q = 0; q < (size_t)rr[0] * c->nt; ++q)
+      memcpy(Th + q * rr[1], &ht[q * c->r2c], (size_t)rr[1] * 8);
   return TT_OK;
 }
 
