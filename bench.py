@@ -13,7 +13,10 @@ under "fp32_mixed".  Last, the reverse sweep: on the differentiation workload
 (128^2 cells, 16 x 32 ordinates, kappa = exp(random field), Gaussian pulse,
 tolerance 1e-6, rank cap 128, 50 steps, a checkpoint every 10 steps) the
 taped forward and tt_grad (d L / d kappa of the detector-patch energy) are
-timed and reported under "gradient".
+timed and reported under "gradient".  Then the optically thick 3-D workload
+(128^3 cells, 32 x 64 ordinates, kappa = 1e3 in the central 64^3 cube,
+coupled material, rank cap 128; concatenated ranks up to 897) in both
+precisions, after its ranks have ramped to the cap, under "thick_3d".
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
 this build runs on one GPU.
@@ -76,23 +79,34 @@ def gram_flops(ns, R1):
     return float(ns) * R1 * (R1 + 1)
 
 
-def tt_inner(A, B):
-    """<A, B> of two three-core TTs by core contractions (no full tensor)."""
-    import numpy as np
-    XA, TA, PA = A
-    XB, TB, PB = B
-    G = XA.T @ XB                                        # r1a x r1b
-    H = np.einsum("alc,ab,bld->cd", TA, G, TB)           # r2a x r2b
-    return float(np.sum(H * (PA @ PB.T)))
-
-
 def tt_rel_diff(A, B):
-    """||A - B|| / ||B|| from inner products (resolves differences above ~1e-8);
+    """||A - B|| / ||B|| of two three-core TTs without forming either tensor
+    and without cancelling squared norms: with Q R = X_A (Cholesky QR; X_A
+    has full column rank), A - B = Q (R C_A - M C_B) - E C_B where
+    M = Q^T X_B and E = X_B - Q M is orthogonal to Q, so the two parts add
+    in squares.  C = Theta x Phi is the r1 x (N_theta N_phi) unfolding.
     None when B is the zero tensor."""
-    aa, bb, ab = tt_inner(A, A), tt_inner(B, B), tt_inner(A, B)
-    if not bb > 0.0:
+    import numpy as np
+
+    def unfold(Th, Ph):
+        r1, nt, r2 = Th.shape
+        return (Th.reshape(r1 * nt, r2) @ Ph).reshape(r1, -1)
+
+    def gram_norm2(G, C):
+        # ||X C||^2 = tr(C^T G C) with G = X^T X, as a sum of nonnegative terms
+        w, V = np.linalg.eigh(G)
+        return float(np.sum(np.clip(w, 0.0, None)[:, None] * (V.T @ C) ** 2))
+    XA, XB = A[0], B[0]
+    CA, CB = unfold(A[1], A[2]), unfold(B[1], B[2])
+    nb2 = gram_norm2(XB.T @ XB, CB)
+    if not nb2 > 0.0:
         return None
-    return max(aa + bb - 2.0 * ab, 0.0) ** 0.5 / bb ** 0.5
+    R = np.linalg.cholesky(XA.T @ XA).T
+    Q = np.linalg.solve(R.T, XA.T).T
+    M = Q.T @ XB
+    E = XB - Q @ M
+    d2 = float(np.sum((R @ CA - M @ CB) ** 2)) + gram_norm2(E.T @ E, CB)
+    return (d2 / nb2) ** 0.5
 
 
 def progress(msg):
@@ -178,6 +192,51 @@ def mixed_run(p, W, K, dt, hist, end64):
     return mixed
 
 
+def thick_3d_run(W, K):
+    """The optically thick 3-D workload (128^3 cells, 32 x 64 ordinates,
+    kappa = 1e3 in the central 64^3 cube, coupled material, rank cap 128) in
+    FP64 and in the FP32-mixed form: W untimed steps in which the ranks ramp
+    to the cap, then K timed steps."""
+    import workloads as wl
+    from paper_2503_18056_amd import TT_FP32_MIXED, TT_FP64
+    p = wl.c4(steps=W + K)
+    ns = p["nx"] * p["ny"] * p["nz"]
+    blocks = 1 + 2 * p["dim"]
+    out = {"workload": f"{p['name']}: 128^3 cells, 32x64 ordinates, kappa 1e3 in the central "
+                       f"64^3 cube and 1 outside, coupled material, tol 1e-6, rank cap 128, "
+                       f"steps {W + 1}-{W + K} of {W + K}"}
+    ends = {}
+    for name, prec in (("fp64", TT_FP64), ("fp32_mixed", TT_FP32_MIXED)):
+        progress(f"thick 3-D, {name}: {W} warmup + {K} timed steps")
+        st, dt, prof, _, r_start = timed_run(p, W, K, prec)
+        hist = st.tt_get_rank_history()
+        r_in = [r_start] + hist[W:W + K - 1]
+        # concatenated rank at bond 1: (1 + 2 dim) r1 plus the emission slot
+        flops = sum(gram_flops(ns, blocks * r1 + 1) for (r1, _) in r_in)
+        gms, gn = prof.get("gram_tall", (0.0, 0))
+        peak = FP64_PEAK_TFLOPS if prec == TT_FP64 else FP32_MFMA_PEAK_TFLOPS
+        achieved = flops / (gms * 1e-3) / 1e12 if gms > 0 else 0.0
+        round_ms = sum(prof.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES)
+        out[name] = {
+            "steps_per_s": K / dt,
+            "ms_per_step": dt * 1e3 / K,
+            "ranks_entering_timed_steps": [list(r) for r in r_in],
+            "ranks_end": list(st.ranks()),
+            "ms_per_rounding": round_ms / K,
+            "gram": {"avg_launch_ms": gms / gn if gn else None,
+                     "achieved_algorithmic_TFLOPs": achieved,
+                     "peak_TFLOPs": peak, "frac": achieved / peak},
+            "kernel_breakdown_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
+                                    for k, v in prof.items()},
+        }
+        ends[name] = st.cores()
+        st.close()
+        progress(f"thick 3-D, {name}: {K / dt:.2f} steps/s, ranks {out[name]['ranks_end']}")
+    out["speedup_mixed_vs_fp64"] = out["fp32_mixed"]["steps_per_s"] / out["fp64"]["steps_per_s"]
+    out["rel_diff_mixed_vs_fp64_end"] = tt_rel_diff(ends["fp32_mixed"], ends["fp64"])
+    return out
+
+
 def gradient_run():
     """Taped forward and reverse sweep of the differentiation workload."""
     import numpy as np
@@ -221,6 +280,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed run")
     ap.add_argument("--no-grad", action="store_true", help="skip the reverse-sweep run")
+    ap.add_argument("--thick3d-steps", type=int, default=6,
+                    help="timed steps of the thick 3-D workload in each precision (0 skips it)")
+    ap.add_argument("--thick3d-warmup", type=int, default=6)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "warmup (a known-size kernel to scale hardware byte counters by)")
@@ -312,6 +374,8 @@ def main():
     if not args.no_grad:
         progress("differentiation workload: taped forward and reverse sweep")
         out["gradient"] = gradient_run()
+    if args.thick3d_steps > 0:
+        out["thick_3d"] = thick_3d_run(args.thick3d_warmup, args.thick3d_steps)
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline (about 15 s)")
         out["cpu_baseline"] = cpu_baseline(p, warm_cores)
