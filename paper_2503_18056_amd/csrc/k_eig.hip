@@ -41,6 +41,12 @@ __device__ inline Work work_of(const EigJob& J, int N) {
   return W;
 }
 
+__host__ __device__ inline int next_pow2(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
 // Deterministic block-wide sum (fixed combination order).
 template <int NT>
 __device__ double block_sum(double v, double* red) {
@@ -64,81 +70,212 @@ __device__ inline double wave_sum(double v) {
 // I - tau_k v v^T with v = [1, x_2..]/(alpha - beta) annihilates A[k+2:, k].
 constexpr int SYTRD_LDS_MAX = 180;  // packed lower triangle: 16290 doubles of LDS
 
-__global__ __launch_bounds__(1024) void k_sytrd(EigJobs jobs, int* __restrict__ dims, int N) {
-  const EigJob J = jobs.j[blockIdx.x];
-  const int n = dims[J.n_idx];
-  if (n <= SYTRD_LDS_MAX) return;  // k_sytrd_lds
-  double* A = J.A;
-  const long long lda = J.lda;
-  Work W = work_of(J, N);
-  __shared__ double sv[1024], sw[1024], sp[4][1024], red[16];
-  __shared__ double s_tau, s_scal;
-  const int tid = threadIdx.x, cj = tid & 255, g = tid >> 8;
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
-    const long long base = (long long)(k + 1) * lda + (k + 1);  // A22 origin
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += 1024) {
-      const double x = A[(long long)(k + 1 + i) * lda + k];
-      part += x * x;
-    }
-    const double sumsq = block_sum<1024>(part, red);
-    if (tid == 0) {
-      const double alpha = A[(long long)(k + 1) * lda + k];
-      W.d[k] = A[(long long)k * lda + k];
-      if (sumsq == 0.0) {
-        s_tau = 0.0;
-        s_scal = 0.0;
-        W.e[k] = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        s_tau = (beta - alpha) / beta;
-        s_scal = 1.0 / (alpha - beta);
-        W.e[k] = beta;
+// Large orders (n > SYTRD_LDS_MAX): the matrix does not fit one CU's LDS,
+// and one block streaming the trailing matrix from L2 is bound by that CU's
+// share of the memory system.  Instead SYTRD_GRID_P blocks per job each keep
+// the rows i = b (mod P) of the full symmetric square in their own LDS
+// (at most ceil(N / P) rows), and step k, which needs T_k (the matrix after
+// reflectors 0..k-1), runs as:
+//   - every block forms row k of T_k from row k of T_{k-1} (published by its
+//     owner) and the previous reflector's (v, w), and v_k, tau_k from it,
+//     redundantly (same data and fixed-order sums, so identical everywhere);
+//   - each block applies T_k = T_{k-1} - v w^T - w v^T to its rows in LDS and
+//     in the same pass forms p_k = tau_k T_k,22 v_k on them and its share of
+//     p_k^T v_k; the owner of row k+1 publishes it;
+//   - one grid barrier; w_k = p_k - (tau_k / 2)(p_k^T v_k) v_k then follows
+//     from the published p_k and the partial dots summed in block order.
+// Only p, the partial dots and one row cross blocks per step.  The grid (at
+// most 4 x 64 blocks of 256 threads) is a small part of what the chip holds
+// resident, so an ordinary launch has all blocks resident together (a
+// cooperative launch would drain the queue on every call, also when all jobs
+// are small and the kernel returns at once); every wait is bounded by
+// SYTRD_SPIN_MAX polls, after which the eigensolver flag is raised and the
+// kernel runs out.  Outputs (d, e, tau, reflectors in H) as k_sytrd_lds.
+constexpr int SYTRD_GRID_P = 64;
+constexpr int SYTRD_GRID_T = 256;
+constexpr unsigned SYTRD_SPIN_MAX = 1u << 24;
+
+struct SytrdGridBufs {
+  double *Rp, *Pv, *Dv;  // published rows (2 x N), p (2 x N), block partial dots (2 x P)
+  unsigned* flag;        // per block: the last grid barrier it has reached
+};
+__device__ __host__ inline SytrdGridBufs sytrd_grid_bufs(double* work, int N) {
+  // inside the divide-and-conquer area, which is free until the reduction ends
+  const size_t N2 = next_pow2(N);
+  double* z = work + 4 * (size_t)N + (size_t)N * N + N2;
+  SytrdGridBufs B;
+  B.Rp = z;
+  B.Pv = z + 2 * (size_t)N;
+  B.Dv = B.Pv + 2 * (size_t)N;
+  B.flag = reinterpret_cast<unsigned*>(B.Dv + 2 * SYTRD_GRID_P);
+  return B;
+}
+inline int sytrd_grid_rows(int N) { return (N + SYTRD_GRID_P - 1) / SYTRD_GRID_P; }
+inline size_t sytrd_grid_lds(int N) { return ((size_t)sytrd_grid_rows(N) * N + 3 * (size_t)N) * 8; }
+
+__global__ void k_sytrd_grid_reset(EigJobs jobs, int N) {
+  sytrd_grid_bufs(jobs.j[blockIdx.x].work, N).flag[threadIdx.x] = 0u;
+}
+
+// Barrier number `ordinal` (1, 2, ...) over the P blocks of one job: each
+// block stores its ordinal into its own flag (a release store after the block
+// barrier, which orders the block's earlier stores before it); one wave polls
+// all P flags with one coherent load per lane, then an acquire fence.  No
+// read-modify-write, so no serialisation on one address.
+__device__ inline void grid_barrier(unsigned* flag, unsigned ordinal, int P, int* s_abort,
+                                    int* dims) {
+  __syncthreads();
+  if (threadIdx.x < 64 && !*s_abort) {
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(&flag[blockIdx.x], ordinal, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (true) {
+      const unsigned f =
+          lane < P ? __hip_atomic_load(&flag[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : ordinal;
+      if (__all(f >= ordinal)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > SYTRD_SPIN_MAX) {
+        if (lane == 0) {
+          *s_abort = 1;
+          atomicOr(&dims[D_FLAG], FLAG_EIG);
+        }
+        break;
       }
-      W.tau[k] = s_tau;
     }
-    __syncthreads();
-    const double tau = s_tau, scal = s_scal;
-    for (int i = tid; i < m; i += 1024) {
-      const double v = i == 0 ? 1.0 : A[(long long)(k + 1 + i) * lda + k] * scal;
-      sv[i] = v;
-      W.H[(long long)k * N + k + 1 + i] = v;
-    }
-    __syncthreads();
-    if (tau == 0.0) continue;
-    for (int j = cj; j < m; j += 256) {
-      double acc = 0.0;
-      for (int i = g; i < m; i += 4) acc += A[base + (long long)i * lda + j] * sv[i];
-      sp[g][j] = acc;
-    }
-    __syncthreads();
-    part = 0.0;
-    for (int j = tid; j < m; j += 1024) {
-      const double p = tau * (((sp[0][j] + sp[1][j]) + sp[2][j]) + sp[3][j]);
-      sw[j] = p;
-      part += p * sv[j];
-    }
-    const double pv = block_sum<1024>(part, red);
-    const double hc = 0.5 * tau * pv;
-    for (int j = tid; j < m; j += 1024) sw[j] -= hc * sv[j];
-    __syncthreads();
-    for (int j = cj; j < m; j += 256) {
-      const double vj = sv[j], wj = sw[j];
-      for (int i = g; i < m; i += 4) {
-        double* a = A + base + (long long)i * lda + j;
-        *a -= sv[i] * wj + sw[i] * vj;
-      }
-    }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
-  if (tid == 0) {
-    if (n >= 2) {
-      W.d[n - 2] = A[(long long)(n - 2) * lda + (n - 2)];
-      W.e[n - 2] = A[(long long)(n - 1) * lda + (n - 2)];
-      W.tau[n - 2] = 0.0;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* __restrict__ dims,
+                                                             int N) {
+  const int b = blockIdx.x, P = gridDim.x;
+  const EigJob J = jobs.j[blockIdx.y];
+  const int n = dims[J.n_idx];
+  if (n <= SYTRD_LDS_MAX) return;  // k_sytrd_lds (the same decision on all blocks of the job)
+  Work W = work_of(J, N);
+  const SytrdGridBufs G = sytrd_grid_bufs(J.work, N);
+  const double* A = J.A;
+  const long long lda = J.lda;
+  extern __shared__ double lds[];
+  const int RB = (N + P - 1) / P;
+  double* Lr = lds;                   // own rows: row i at Lr + (i / P) N
+  double* sv = Lr + (size_t)RB * N;   // v_k (and row k of T_k before scaling)
+  double* svp = sv + N;               // v_{k-1}
+  double* swp = svp + N;              // w_{k-1}
+  __shared__ double red[16];
+  __shared__ double s_tau, s_scal, s_taup, s_d;
+  __shared__ int s_abort;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int li = wave; li * P + b < n; li += 4) {
+    const double* ra = A + (long long)(li * P + b) * lda;
+    for (int j = lane; j < n; j += 64) Lr[(size_t)li * N + j] = ra[j];
+  }
+  for (int i = tid; i < N; i += SYTRD_GRID_T) svp[i] = swp[i] = 0.0;
+  if (tid == 0) { s_taup = 0.0; s_abort = 0; }
+  __syncthreads();
+  unsigned ordinal = 0;
+  for (int k = 0; k <= n - 2; ++k) {
+    // w_{k-1} on indices >= k from the published p_{k-1} and partial dots
+    // (every wave sums the P partials the same way), fused with row k of T_k
+    double hc = 0.0;
+    const double* pp = G.Pv + (size_t)((k - 1) & 1) * N;
+    if (k >= 1) {
+      const double* dp = G.Dv + (size_t)((k - 1) & 1) * SYTRD_GRID_P;
+      hc = 0.5 * s_taup * wave_sum(lane < P ? dp[lane] : 0.0);
     }
-    if (n >= 1) W.d[n - 1] = A[(long long)(n - 1) * lda + (n - 1)];
+    const double vk0 = svp[k];
+    const double wk0 = k >= 1 ? pp[k] - hc * vk0 : 0.0;
+    if (k == n - 2) {
+      for (int j = k + tid; j < n; j += SYTRD_GRID_T) swp[j] = pp[j] - hc * svp[j];
+      __syncthreads();
+    } else {
+      // row k of T_k (columns >= k)
+      const double* src = k == 0 ? A : G.Rp + (size_t)((k - 1) & 1) * N;
+      double part = 0.0;
+      for (int j = k + tid; j < n; j += SYTRD_GRID_T) {
+        const double wj = k >= 1 ? pp[j] - hc * svp[j] : 0.0;
+        swp[j] = wj;
+        const double r = src[j] - vk0 * wj - wk0 * svp[j];
+        if (j == k) s_d = r;
+        sv[j] = r;
+        if (j >= k + 2) part += r * r;
+      }
+      const double sumsq = block_sum<SYTRD_GRID_T>(part, red);
+      if (tid == 0) {
+        const double alpha = sv[k + 1];
+        double e;
+        if (sumsq == 0.0) {
+          s_tau = 0.0;
+          s_scal = 0.0;
+          e = alpha;
+        } else {
+          const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+          s_tau = (beta - alpha) / beta;
+          s_scal = 1.0 / (alpha - beta);
+          e = beta;
+        }
+        if (b == 0) {
+          W.d[k] = s_d;
+          W.e[k] = e;
+          W.tau[k] = s_tau;
+        }
+      }
+      __syncthreads();
+      const double tau = s_tau, scal = s_scal;
+      for (int j = k + 1 + tid; j < n; j += SYTRD_GRID_T) {
+        const double v = j == k + 1 ? 1.0 : sv[j] * scal;
+        sv[j] = v;
+        if (b == 0) W.H[(long long)k * N + j] = v;
+      }
+      __syncthreads();
+      // own rows: T_k = T_{k-1} - v w^T - w v^T, and p_k = tau T_k,22 v_k
+      double* pk = G.Pv + (size_t)(k & 1) * N;
+      double* rpub = G.Rp + (size_t)(k & 1) * N;
+      const int i0 = k + 1 + ((b - (k + 1)) % P + P) % P;
+      double wpart = 0.0;
+      for (int i = i0 + wave * P; i < n; i += 4 * P) {
+        const double vi = svp[i], wi = swp[i];
+        double* r = Lr + (size_t)(i / P) * N;
+        const bool publish = i == k + 1;
+        double acc = 0.0;
+        for (int j = k + 1 + lane; j < n; j += 64) {
+          const double t = r[j] - vi * swp[j] - wi * svp[j];
+          r[j] = t;
+          if (publish) rpub[j] = t;
+          acc += t * sv[j];
+        }
+        acc = wave_sum(acc);
+        const double p = tau * acc;
+        if (lane == 0) pk[i] = p;
+        wpart += p * sv[i];
+      }
+      __syncthreads();
+      if (lane == 0) red[wave] = wpart;
+      __syncthreads();
+      if (tid == 0) {
+        G.Dv[(size_t)(k & 1) * SYTRD_GRID_P + b] = ((red[0] + red[1]) + red[2]) + red[3];
+        s_taup = tau;
+      }
+      for (int j = k + 1 + tid; j < n; j += SYTRD_GRID_T) svp[j] = sv[j];
+      grid_barrier(G.flag, ++ordinal, P, &s_abort, dims);
+    }
+    if (k == n - 2 && tid == 0) {
+      // the last 2 x 2 block of T_{n-2}, from its owners' rows of T_{n-3}
+      const int i0 = n - 2, i1 = n - 1;
+      if (i0 % P == b) {
+        const double* r = Lr + (size_t)(i0 / P) * N;
+        W.d[i0] = r[i0] - 2.0 * svp[i0] * swp[i0];
+        W.e[i0] = r[i1] - svp[i0] * swp[i1] - swp[i0] * svp[i1];
+        W.tau[i0] = 0.0;
+      }
+      if (i1 % P == b) {
+        const double* r = Lr + (size_t)(i1 / P) * N;
+        W.d[i1] = r[i1] - 2.0 * svp[i1] * swp[i1];
+      }
+    }
   }
 }
 
@@ -255,11 +392,6 @@ struct DC {
   double *lam, *Qa, *Qb, *U, *dsl, *zsl, *rc, *rs, *rtau, *zhat, *dK, *zK, *mrho;
   int *perm, *Kslot, *rp, *rq, *ro, *mk, *mnrot, *mm2;
 };
-__host__ __device__ inline int next_pow2(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
-}
 __device__ inline DC dc_of(const Work& W, int N) {
   const int N2 = next_pow2(N);
   DC D;
@@ -1426,7 +1558,11 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   EigJobs J;
   for (int i = 0; i < njobs && i < 4; ++i) J.j[i] = jobs[i];
   k_sytrd_lds<<<njobs, 1024, 0, s>>>(J, dims, N);
-  if (N > SYTRD_LDS_MAX) k_sytrd<<<njobs, 1024, 0, s>>>(J, dims, N);
+  if (N > SYTRD_LDS_MAX) {
+    const int nj = njobs < 4 ? njobs : 4;
+    k_sytrd_grid_reset<<<nj, SYTRD_GRID_P, 0, s>>>(J, N);
+    k_sytrd_grid<<<dim3(SYTRD_GRID_P, nj), SYTRD_GRID_T, sytrd_grid_lds(N), s>>>(J, dims, N);
+  }
   dc_levels(jobs, J, njobs, N, dims, s);
   k_ormtr<<<dim3((N + 3) / 4, njobs), 256, ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8, s>>>(
       J, dims, N);
