@@ -117,10 +117,10 @@ __global__ void k_sytrd_grid_reset(EigJobs jobs, int N) {
   sytrd_grid_bufs(jobs.j[blockIdx.x].work, N).flag[threadIdx.x] = 0u;
 }
 
-// Barrier number `ordinal` (1, 2, ...) over the P blocks of one job: each
+// Barrier number `ordinal` (1, 2, ...) over the P <= 256 blocks of one job: each
 // block stores its ordinal into its own flag (a release store after the block
 // barrier, which orders the block's earlier stores before it); one wave polls
-// all P flags with one coherent load per lane, then an acquire fence.  No
+// all P flags with coherent loads, then an acquire fence.  No
 // read-modify-write, so no serialisation on one address.
 __device__ inline void grid_barrier(unsigned* flag, unsigned ordinal, int P, int* s_abort,
                                     int* dims) {
@@ -131,10 +131,10 @@ __device__ inline void grid_barrier(unsigned* flag, unsigned ordinal, int P, int
       __hip_atomic_store(&flag[blockIdx.x], ordinal, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
     while (true) {
-      const unsigned f =
-          lane < P ? __hip_atomic_load(&flag[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                   : ordinal;
-      if (__all(f >= ordinal)) break;
+      bool ok = true;
+      for (int q = lane; q < P; q += 64)
+        ok = ok && __hip_atomic_load(&flag[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= ordinal;
+      if (__all(ok)) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > SYTRD_SPIN_MAX) {
         if (lane == 0) {
@@ -1158,6 +1158,7 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
 // ~u sigma_1 absolutely and the vectors to ~u sigma_1 / gap.
 
 constexpr int GEBRD_LDS_MAX = 16384;  // p q doubles held in LDS by k_gebrd_lds
+constexpr int GEBRD_GRID_MIN = 384;   // longer side from which k_gebrd_grid takes over
 __device__ inline int gebrd_ld(int q) { return q | 1; }
 __device__ inline bool gebrd_fits(int p, int q) {
   return (long long)p * gebrd_ld(q) <= GEBRD_LDS_MAX && p <= 1024;
@@ -1190,7 +1191,7 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
   const EigJob J = jobs.j[0];
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
-  if (gebrd_fits(p, q)) return;  // k_gebrd_lds
+  if (gebrd_fits(p, q) || p >= GEBRD_GRID_MIN) return;  // k_gebrd_lds or k_gebrd_grid
   double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
@@ -1284,6 +1285,187 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
       }
     }
     __syncthreads();
+  }
+}
+
+// The same bidiagonalisation for large matrices (p >= GEBRD_GRID_MIN) on P
+// blocks, each holding the rows i = b (mod P) in LDS (row stride q).  Step k:
+//   A. every block reads column k of the current matrix (published by the
+//      row owners) and forms the left reflector u_k, tau_L, d_k from it
+//      redundantly; each block then publishes its partial of
+//      y = A(k:, k+1:)^T u over its own rows;
+//   -- grid barrier --
+//   B. every block sums the P partials in block order (y = tau_L sum), forms
+//      row k after the left reflector from the published row k and y, and
+//      from it the right reflector v_k, tau_R, e_k; each block applies both
+//      reflectors to its own rows in LDS (A_i -= u_i y, then
+//      A_i -= tau_R (A_i . v) v) and publishes column k+1 of its rows and,
+//      for the owner, row k+1;
+//   -- grid barrier --
+// Outputs (W.e[2k] = d_k, W.e[2k+1] = e_k, W.tau, right reflectors in W.H)
+// as k_gebrd.  Launch and barrier as k_sytrd_grid.
+
+struct GebrdGridBufs {
+  double *C, *R, *Y;  // published column (p), rows (2 x q), partials (P x q)
+  unsigned* flag;
+};
+__device__ __host__ inline GebrdGridBufs gebrd_grid_bufs(double* work, int N, int P) {
+  const size_t N2 = next_pow2(N);
+  double* z = work + 4 * (size_t)N + (size_t)N * N + N2;
+  GebrdGridBufs B;
+  B.C = z;
+  B.R = z + 1024;
+  B.Y = B.R + 2 * (size_t)N;
+  B.flag = reinterpret_cast<unsigned*>(B.Y + (size_t)P * N);
+  return B;
+}
+// blocks and dynamic LDS for rows up to pcap and columns up to qcap
+inline int gebrd_grid_blocks(int pcap, int qcap) {
+  const size_t small = ((size_t)4 * 1024 + 64) * 8;  // vectors and statics
+  return ((size_t)((pcap + 63) / 64) * qcap * 8 + small <= 160 * 1024) ? 64 : 128;
+}
+inline size_t gebrd_grid_lds(int pcap, int qcap) {
+  const int P = gebrd_grid_blocks(pcap, qcap);
+  return ((size_t)((pcap + P - 1) / P) * qcap + (size_t)pcap + 3 * (size_t)qcap) * 8;
+}
+
+__global__ void k_gebrd_grid_reset(EigJobs jobs, int N, int P) {
+  gebrd_grid_bufs(jobs.j[0].work, N, P).flag[threadIdx.x] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restrict__ dims, int N,
+                                                    int a_idx, int b_idx, int side_idx, int pcap,
+                                                    int qcap) {
+  const EigJob J = jobs.j[0];
+  const int a = dims[a_idx], bb = dims[b_idx], side = dims[side_idx];
+  const int p = side ? a : bb, q = side ? bb : a;
+  if (gebrd_fits(p, q) || p < GEBRD_GRID_MIN) return;  // k_gebrd_lds or k_gebrd
+  const int b = blockIdx.x, P = gridDim.x;
+  const double* A = J.A;
+  const long long lda = J.lda;
+  Work W = work_of(J, N);
+  const GebrdGridBufs G = gebrd_grid_bufs(J.work, N, P);
+  extern __shared__ double lds[];
+  const int RB = (pcap + P - 1) / P;
+  double* Lr = lds;                    // own rows: row i at Lr + (i / P) q
+  double* su = Lr + (size_t)RB * qcap; // u_k (p)
+  double* sy = su + pcap;              // y (q)
+  double* sv = sy + qcap;              // row k, then v_k (q)
+  __shared__ double red[16];
+  __shared__ double s_tl, s_sl, s_bl, s_tr, s_sr;
+  __shared__ int s_abort;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int li = wave; li * P + b < p; li += 4) {
+    const double* ra = A + (long long)(li * P + b) * lda;
+    for (int j = lane; j < q; j += 64) Lr[(size_t)li * q + j] = ra[j];
+  }
+  if (b == 0)
+    for (int i = tid; i < 2 * q; i += 256) W.d[i] = 0.0;
+  if (tid == 0) s_abort = 0;
+  __syncthreads();
+  unsigned ordinal = 0;
+  for (int k = 0; k < q; ++k) {
+    const int nc = q - k - 1;
+    // A. left reflector of column k, rows k..p-1
+    double part = 0.0;
+    for (int i = k + tid; i < p; i += 256) {
+      const double c = k == 0 ? A[(long long)i * lda] : G.C[i];
+      su[i] = c;
+      if (i > k) part += c * c;
+    }
+    const double sumsq = block_sum<256>(part, red);
+    if (tid == 0) {
+      const double alpha = su[k];
+      if (sumsq == 0.0) {
+        s_tl = 0.0;
+        s_sl = 0.0;
+        s_bl = alpha;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+        s_tl = (beta - alpha) / beta;
+        s_sl = 1.0 / (alpha - beta);
+        s_bl = beta;
+      }
+      if (b == 0) {
+        W.e[2 * k] = s_bl;
+        if (nc <= 0) W.tau[k] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (nc <= 0) break;  // the last column: no right reflector
+    const double tl = s_tl, sl = s_sl;
+    for (int i = k + tid; i < p; i += 256) su[i] = i == k ? 1.0 : su[i] * sl;
+    __syncthreads();
+    {
+      // this block's partial of A(k:, k+1:)^T u over its own rows
+      const int ifirst = k + ((b - k) % P + P) % P;
+      double* yp = G.Y + (size_t)b * N;
+      for (int j = tid; j < nc; j += 256) {
+        double acc = 0.0;
+        for (int i = ifirst; i < p; i += P) acc += su[i] * Lr[(size_t)(i / P) * q + k + 1 + j];
+        yp[j] = acc;
+      }
+    }
+    grid_barrier(G.flag, ++ordinal, P, &s_abort, dims);
+    // B. y, row k after the left reflector, right reflector
+    const double* rk = k == 0 ? A : G.R + (size_t)(k & 1) * N;
+    part = 0.0;
+    for (int j = tid; j < nc; j += 256) {
+      double acc = 0.0;
+      for (int q2 = 0; q2 < P; ++q2) acc += G.Y[(size_t)q2 * N + j];
+      const double y = tl * acc;
+      sy[j] = y;
+      const double r = rk[k + 1 + j] - y;
+      sv[j] = r;
+      if (j > 0) part += r * r;
+    }
+    const double sumr = block_sum<256>(part, red);
+    if (tid == 0) {
+      const double alpha = sv[0];
+      double beta;
+      if (sumr == 0.0) {
+        s_tr = 0.0;
+        s_sr = 0.0;
+        beta = alpha;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sumr), alpha);
+        s_tr = (beta - alpha) / beta;
+        s_sr = 1.0 / (alpha - beta);
+      }
+      if (b == 0) {
+        W.e[2 * k + 1] = beta;
+        W.tau[k] = s_tr;
+      }
+    }
+    __syncthreads();
+    const double tr = s_tr, sr = s_sr;
+    for (int j = tid; j < nc; j += 256) {
+      const double v = j == 0 ? 1.0 : sv[j] * sr;
+      sv[j] = v;
+      if (b == 0) W.H[(long long)k * N + k + 1 + j] = v;
+    }
+    __syncthreads();
+    double* rpub = G.R + (size_t)((k + 1) & 1) * N;
+    const int i0 = k + 1 + ((b - (k + 1)) % P + P) % P;
+    for (int i = i0 + wave * P; i < p; i += 4 * P) {
+      double* r = Lr + (size_t)(i / P) * q + k + 1;
+      const double ui = su[i];
+      double acc = 0.0;
+      for (int j = lane; j < nc; j += 64) {
+        const double t = r[j] - ui * sy[j];
+        r[j] = t;
+        acc += t * sv[j];
+      }
+      const double z = tr * wave_sum(acc);
+      const bool publish = i == k + 1;
+      for (int j = lane; j < nc; j += 64) {
+        const double t = r[j] - z * sv[j];
+        r[j] = t;
+        if (j == 0) G.C[i] = t;
+        if (publish) rpub[k + 1 + j] = t;
+      }
+    }
+    grid_barrier(G.flag, ++ordinal, P, &s_abort, dims);
   }
 }
 
@@ -1570,7 +1752,7 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
 }
 
 void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx,
-                    const EigJob& job, int N, int* dims, hipStream_t s) {
+                    const EigJob& job, int N, int pcap, int* dims, hipStream_t s) {
   if (N < 2) return;
   EigJobs J;
   J.j[0] = job;
@@ -1581,6 +1763,13 @@ void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx
   k_svd_load<<<lb, 256, 0, s>>>(M, ldm, J, dims, a_idx, b_idx, side_idx);
   k_gebrd_lds<<<1, 1024, 0, s>>>(M, ldm, J, dims, N, a_idx, b_idx, side_idx);
   k_gebrd<<<1, 1024, 0, s>>>(J, dims, N, a_idx, b_idx, side_idx);
+  if (pcap >= GEBRD_GRID_MIN) {
+    const int qc = qcap < pcap ? qcap : pcap;
+    const int P = gebrd_grid_blocks(pcap, qc);
+    k_gebrd_grid_reset<<<1, P, 0, s>>>(J, N, P);
+    k_gebrd_grid<<<P, 256, gebrd_grid_lds(pcap, qc), s>>>(J, dims, N, a_idx, b_idx, side_idx, pcap,
+                                                          qc);
+  }
   dc_levels(&job, J, 1, N, dims, s);
   k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N);
   k_svd_final<<<1, 256, 0, s>>>(J, dims, N);

@@ -316,7 +316,7 @@ void truncate_bond(tt_ctx* c, int bond, const EigSlot& ea, const EigSlot& eb, Ei
     // SVD of M (App. A.2) through the Golub-Kahan tridiagonal
     Prof p(c, bond == 1 ? P_EIGM1 : P_EIGM2);
     EigJob j{Cm, Rcap, tgk, em.lam, em.V, N, em.sq, em.isq, kc, 1.0, em.work};
-    svd_short_side(M, Rcap, ka, kb, side, j, 2 * qcap, c->dims, s);
+    svd_short_side(M, Rcap, ka, kb, side, j, 2 * qcap, Rcap, c->dims, s);
   }
   RankArgs ra;
   ra.bond = bond; ra.km = km; ra.kc = kc; ra.ka = ka; ra.kb = kb;

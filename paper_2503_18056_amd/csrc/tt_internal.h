@@ -165,8 +165,8 @@ void eig_batched(const EigJob* jobs, int njobs, int ncap, int* dims, hipStream_t
 // dims[kept_idx] = number with sigma > 2q u sigma_1.  J.A is a work matrix
 // of at least max(a,b) x min(a,b) (row-major, J.lda); dims[J.n_idx]
 // receives 2q.  2 q_max <= ncap2 <= 2048, J.work holds eig_work_doubles(ncap2);
-// max(a, b) <= 1024.
+// max(a, b) <= pcap <= 1024.
 void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx,
-                    const EigJob& job, int ncap2, int* dims, hipStream_t s);
+                    const EigJob& job, int ncap2, int pcap, int* dims, hipStream_t s);
 
 }  // namespace tt

@@ -100,7 +100,7 @@ tt_status tt_kernel_svd(const double* M, int32_t a, int32_t b, int32_t ldm, doub
   KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
   KCHK(hipMemsetAsync(work, 0, eig_work_doubles(N) * 8, s));
   EigJob j{Awork, q, 3, sig, V, ldv, sq, isq, 4, 1.0, work};
-  svd_short_side(M, ldm, 0, 1, 2, j, N, dims, s);
+  svd_short_side(M, ldm, 0, 1, 2, j, N, p, dims, s);
   KCHK(hipGetLastError());
   KCHK(hipMemcpyAsync(hd, dims, sizeof(hd), hipMemcpyDeviceToHost, s));
   KCHK(hipStreamSynchronize(s));

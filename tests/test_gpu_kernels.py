@@ -111,7 +111,7 @@ def _eig_case(kind, n, rng):
 
 
 @pytest.mark.parametrize("kind", ["random", "gram", "cluster", "lowrank"])
-@pytest.mark.parametrize("n", [1, 2, 5, 31, 64, 100, 322])
+@pytest.mark.parametrize("n", [1, 2, 5, 31, 64, 100, 181, 322, 641, 897, 1024])
 def test_eigh(env, kind, n):
     lib, torch = env
     rng = np.random.default_rng(n + len(kind))
@@ -158,7 +158,8 @@ def _svd_case(kind, a, b, rng):
 
 @pytest.mark.parametrize("kind", ["random", "graded", "cluster", "lowrank"])
 @pytest.mark.parametrize("a,b", [(1, 1), (1, 6), (6, 1), (7, 7), (40, 33), (33, 40), (130, 200),
-                                 (322, 150), (143, 322)])
+                                 (322, 150), (143, 322), (383, 383), (420, 390), (897, 641),
+                                 (641, 897), (1000, 1024)])
 def test_svd(env, kind, a, b):
     lib, torch = env
     rng = np.random.default_rng(a * 1000 + b + len(kind))
