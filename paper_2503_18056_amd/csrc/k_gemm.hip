@@ -159,60 +159,150 @@ __device__ inline f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Tall Gram: partial[slice][pair] = A[rows of slice, tile ti]^T A[rows, tile tj]
-// for the upper-triangular 64x64 tile pairs (ti <= tj).  Four waves per
-// block, each owning a 32x32 quarter of the tile (2x2 MFMA blocks).
-__global__ __launch_bounds__(256) void k_gram_tall(const double* __restrict__ A, int lda, int K,
-                                                   int kslice, DimExpr ndim,
-                                                   const int* __restrict__ dims, int tiles,
-                                                   double* __restrict__ partial) {
-  const int n = eval_dim(dims, ndim);
-  const int pair = blockIdx.x, slice = blockIdx.y;
-  int ti = 0, rem = pair;
-  while (rem >= tiles - ti) { rem -= tiles - ti; ++ti; }
-  const int tj = ti + rem;
-  if (ti * 64 >= n || tj * 64 >= n) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int a0 = ti * 64 + wr * 32, b0 = tj * 64 + wc * 32;
-  const int col = lane & 15, krow = lane >> 4;
-  const int k_begin = slice * kslice;
-  const int k_end = min(K, k_begin + kslice);
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const bool va0 = a0 + col < n, va1 = a0 + 16 + col < n;
-  const bool vb0 = b0 + col < n, vb1 = b0 + 16 + col < n;
-  for (int k = k_begin; k < k_end; k += 4) {
-    const int row = k + krow;
-    const bool vr = row < k_end;
-    const double* rp = A + (long long)row * lda;
-    const double x0 = (vr && va0) ? rp[a0 + col] : 0.0;
-    const double x1 = (vr && va1) ? rp[a0 + 16 + col] : 0.0;
-    const double y0 = (vr && vb0) ? rp[b0 + col] : 0.0;
-    const double y1 = (vr && vb1) ? rp[b0 + 16 + col] : 0.0;
-    acc[0][0] = mfma16(x0, y0, acc[0][0]);
-    acc[0][1] = mfma16(x0, y1, acc[0][1]);
-    acc[1][0] = mfma16(x1, y0, acc[1][0]);
-    acc[1][1] = mfma16(x1, y1, acc[1][1]);
-  }
-  const int npairs = gridDim.x;
-  double* out = partial + ((long long)slice * npairs + pair) * 4096;
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ii = wr * 32 + 16 * p + (lane >> 4) + 4 * r;
-        const int jj = wc * 32 + 16 * q + (lane & 15);
-        out[ii * 64 + jj] = acc[p][q][r];
-      }
+// Wide Gram (more than 384 columns, FP64): partial[slice][pair] =
+// A[rows of slice, tile ti]^T A[rows, tile tj] for the upper 128 x 128 tile
+// pairs (ti <= tj).  Rows stream through LDS in stages of GW_KB rows (double
+// buffered: the next stage is loaded into registers while the current one
+// feeds the MFMAs); each of the four waves owns a 64 x 64 quarter, sixteen
+// independent 16 x 16 accumulators.  16 x 16 blocks wholly past n are
+// skipped, and so is the lower quarter of a diagonal tile (its transpose is
+// the upper one).  XCD-aware order: consecutive blocks go to consecutive
+// XCDs, and all tile pairs of one row slice go to the same XCD, so the rows
+// they share are fetched into one L2.
+constexpr int GW_T = 128;
+constexpr int GW_KB = 16;
+constexpr int GW_LD = 144;  // LDS row stride: rows r and r+1 fall in opposite bank halves
+constexpr int GW_XCD = 8;
+
+__device__ inline void gw_pair(int pair, int tiles, int& ti, int& tj) {
+  int t = 0, rem = pair;
+  while (rem >= tiles - t) { rem -= tiles - t; ++t; }
+  ti = t;
+  tj = t + rem;
 }
 
-// Fixed-order reduction of the slices (deterministic), mirrored into G.
+__global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A, int lda, int K,
+                                                   int kslice, int slices, DimExpr ndim,
+                                                   const int* __restrict__ dims, int tiles,
+                                                   int pairs, double* __restrict__ partial) {
+  const int n = eval_dim(dims, ndim);
+  const int x = blockIdx.x % GW_XCD, jx = blockIdx.x / GW_XCD;
+  const int pair = jx % pairs, slice = x + GW_XCD * (jx / pairs);
+  if (slice >= slices) return;
+  int ti, tj;
+  gw_pair(pair, tiles, ti, tj);
+  if (ti * GW_T >= n || tj * GW_T >= n) return;
+  const bool diag = ti == tj;
+  __shared__ double sA[2][GW_KB][GW_LD], sB[2][GW_KB][GW_LD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const bool idle = diag && wr > wc;  // lower quarter of a diagonal tile
+  const int ca = ti * GW_T, cb = tj * GW_T;
+  // loads: thread t moves column t % 128 of rows t / 128 + 2u, u = 0..7
+  const int lc = tid & 127, lr = tid >> 7;
+  const bool va = ca + lc < n, vb = cb + lc < n;
+  const int k_begin = slice * kslice;
+  const int k_end = min(K, k_begin + kslice);
+  // valid 16 x 16 blocks of this wave
+  const int a0 = wr * 64, b0 = wc * 64;
+  int np = 0, nq = 0;
+  for (int t = 0; t < 4; ++t) {
+    if (ca + a0 + 16 * t < n) np = t + 1;
+    if (cb + b0 + 16 * t < n) nq = t + 1;
+  }
+  if (idle) np = nq = 0;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = k0 + lr + 2 * u;
+      const bool vr = row < k_end;
+      const double* rp = A + (long long)row * lda;
+      ra[u] = (vr && va) ? rp[ca + lc] : 0.0;
+      rb[u] = (vr && vb && !diag) ? rp[cb + lc] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sA[buf][lr + 2 * u][lc] = ra[u];
+      if (!diag) sB[buf][lr + 2 * u][lc] = rb[u];
+    }
+  };
+  const int nstage = (k_end - k_begin + GW_KB - 1) / GW_KB;
+  if (nstage > 0) {
+    load(k_begin);
+    store(0);
+  }
+  __syncthreads();
+  const int col = lane & 15, kr = lane >> 4;
+  for (int st = 0; st < nstage; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nstage) load(k_begin + (st + 1) * GW_KB);
+    const double(*SA)[GW_LD] = sA[buf];
+    const double(*SB)[GW_LD] = diag ? sA[buf] : sB[buf];
+#pragma unroll
+    for (int kk = 0; kk < GW_KB; kk += 4) {
+      double fa[4], fb[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        fa[t] = SA[kk + kr][a0 + 16 * t + col];
+        fb[t] = SB[kk + kr][b0 + 16 * t + col];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (p < np && q < nq) acc[p][q] = mfma16(fa[p], fb[q], acc[p][q]);
+    }
+    if (st + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+  double* out = partial + ((long long)slice * pairs + pair) * (GW_T * GW_T);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (p >= np || q >= nq) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ii = a0 + 16 * p + (lane >> 4) + 4 * r;
+        const int jj = b0 + 16 * q + (lane & 15);
+        out[ii * GW_T + jj] = acc[p][q][r];
+      }
+    }
+}
+
+// Fixed-order sum of the wide Gram's slices, mirrored into G.  Diagonal tiles
+// take the upper triangle (ii <= jj) only: their lower quarter is not formed.
+__global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restrict__ partial,
+                                                          int slices, int pairs, int tiles,
+                                                          DimExpr ndim, const int* __restrict__ dims,
+                                                          double* __restrict__ G, int ldg) {
+  const int n = eval_dim(dims, ndim);
+  const int pair = blockIdx.y;
+  int ti, tj;
+  gw_pair(pair, tiles, ti, tj);
+  if (ti * GW_T >= n || tj * GW_T >= n) return;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < GW_T * GW_T; e += gridDim.x * 256) {
+    const int ii = e / GW_T, jj = e % GW_T;
+    const int i = ti * GW_T + ii, j = tj * GW_T + jj;
+    if (i >= n || j >= n || (ti == tj && ii > jj)) continue;
+    double sum = 0.0;
+    for (int sl = 0; sl < slices; ++sl)
+      sum += partial[((long long)sl * pairs + pair) * (GW_T * GW_T) + e];
+    G[(long long)i * ldg + j] = sum;
+    G[(long long)j * ldg + i] = sum;
+  }
+}
+
+// Fixed-order reduction of the sliced FP32 Gram's 64 x 64 tile pairs
+// (deterministic), mirrored into G.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ partial,
                                                      int slices, int npairs, int tiles,
                                                      DimExpr ndim, const int* __restrict__ dims,
@@ -266,11 +356,23 @@ GramPlan gram_plan(int K, int ncap, int lda) {
   p.rows_per_blk = ((K + nb - 1) / nb + 15) / 16 * 16;
   p.nblk = (K + p.rows_per_blk - 1) / p.rows_per_blk;
   if (p.nblk < 1) p.nblk = 1;
+  // wide form: 128-column tile pairs, a multiple of GW_XCD row slices of at
+  // least 1024 rows (at most 64)
+  p.wtiles = (ncap + GW_T - 1) / GW_T;
+  p.wpairs = p.wtiles * (p.wtiles + 1) / 2;
+  int ws = K / 1024;
+  ws = ws < GW_XCD ? GW_XCD : (ws > 64 ? 64 : ws);
+  ws = ws / GW_XCD * GW_XCD;
+  p.wkslice = ((K + ws - 1) / ws + GW_KB - 1) / GW_KB * GW_KB;
+  p.wslices = ws;
   return p;
 }
 
 size_t gram_partial_doubles(const GramPlan& p) {
-  return p.rows_mode ? (size_t)p.nblk * p.ntask_cap * 1024 : (size_t)p.slices * p.pairs * 4096;
+  if (p.rows_mode) return (size_t)p.nblk * p.ntask_cap * 1024;
+  const size_t split = (size_t)p.slices * p.pairs * 4096;
+  const size_t wide = (size_t)p.wslices * p.wpairs * GW_T * GW_T;
+  return split > wide ? split : wide;
 }
 
 void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* partial,
@@ -280,11 +382,20 @@ void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* pa
                                                 partial);
     return;
   }
-  k_gram_tall<<<dim3(p.pairs, p.slices), 256, 0, s>>>(A, p.lda, p.K, p.kslice, n, dims, p.tiles,
-                                                      partial);
+  k_gram_wide<<<p.wslices * p.wpairs, 256, 0, s>>>(A, p.lda, p.K, p.wkslice, p.wslices, n, dims,
+                                                   p.wtiles, p.wpairs, partial);
 }
 void gram_tall_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
                       const int* dims, hipStream_t s) {
+  if (p.rows_mode) {
+    k_gram_rows_reduce<<<dim3(16, p.ntask_cap), 256, 0, s>>>(partial, p.nblk, n, dims, G, ldg);
+    return;
+  }
+  k_gram_wide_reduce<<<dim3(8, p.wpairs), 256, 0, s>>>(partial, p.wslices, p.wpairs, p.wtiles, n,
+                                                       dims, G, ldg);
+}
+void gram_split_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
+                       const int* dims, hipStream_t s) {
   if (p.rows_mode) {
     k_gram_rows_reduce<<<dim3(16, p.ntask_cap), 256, 0, s>>>(partial, p.nblk, n, dims, G, ldg);
     return;

@@ -387,7 +387,8 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
       else gram_tall_partial(plan, xc, dimv(D_RC1), c->gpart, c->dims, s);
     }
     Prof p(c, P_GRAMRED);
-    gram_tall_reduce(plan, dimv(D_RC1), c->gpart, c->GA, R1c, c->dims, s);
+    if (xcf) gram_split_reduce(plan, dimv(D_RC1), c->gpart, c->GA, R1c, c->dims, s);
+    else gram_tall_reduce(plan, dimv(D_RC1), c->gpart, c->GA, R1c, c->dims, s);
   }
   {
     Prof p(c, P_EIG1);

@@ -103,7 +103,11 @@ void sum_partials(const double* part, long long zstride, int nz, double* out, in
 
 // ---- tall Gram on MFMA: G = A^T A, A is K x n (row-major, lda), n <= ncap
 struct GramPlan {
-  int K, ncap, lda, tiles, pairs, slices, kslice;
+  int K, ncap, lda;
+  // sliced FP32 form above 384 columns: 64-column tile pairs
+  int tiles, pairs, slices, kslice;
+  // FP64 form above 384 columns: 128-column tile pairs, wslices row slices
+  int wtiles, wpairs, wslices, wkslice;
   // row-slice form (ncap <= 384): nblk blocks of rows_per_blk rows, up to
   // ntask_cap upper-triangular 32x32 tasks each
   bool rows_mode;
@@ -119,10 +123,12 @@ void gram_tall_reduce(const GramPlan& p, DimExpr n, const double* partial, doubl
                       const int* dims, hipStream_t s);
 
 // ---- FP32-mixed form: sliced (error-free) Gram of an FP32 matrix on FP32
-// MFMA into the same partial tiles as gram_tall_partial (reduce with
-// gram_tall_reduce); colmax is scratch of ncap words.
+// MFMA into partial tiles (reduce with gram_split_reduce); colmax is scratch
+// of ncap words.
 void gram_split_partial(const GramPlan& p, const float* A, DimExpr n, unsigned* colmax,
                         double* partial, const int* dims, hipStream_t s);
+void gram_split_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
+                       const int* dims, hipStream_t s);
 // C (FP32) = A (FP32) * B (FP64, split hi/lo) on FP32 MFMA.
 void gemm_tall_f32(int K, const float* A, int lda, const double* B, int ldb, float* C, int ldc,
                    DimExpr kdim, DimExpr ndim, int ncap, const int* dims, hipStream_t s);

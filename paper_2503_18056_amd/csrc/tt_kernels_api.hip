@@ -156,7 +156,7 @@ tt_status tt_kernel_gram_f32(const float* A, int32_t K, int32_t n, int32_t lda, 
   hd[0] = n;
   KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
   gram_split_partial(plan, A, dimv(0), colmax, part, dims, s);
-  gram_tall_reduce(plan, dimv(0), part, G, ldg, dims, s);
+  gram_split_reduce(plan, dimv(0), part, G, ldg, dims, s);
   KCHK(hipGetLastError());
   KCHK(hipStreamSynchronize(s));
   return TT_OK;

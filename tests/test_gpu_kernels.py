@@ -72,7 +72,8 @@ def test_gemm_tall(env, K, k, n):
     assert err < 1e-12 * max(1.0, k)
 
 
-@pytest.mark.parametrize("K,n", [(4, 16), (1, 1), (3, 5), (1000, 64), (1000, 65), (4097, 130), (65536, 322)])
+@pytest.mark.parametrize("K,n", [(4, 16), (1, 1), (3, 5), (1000, 64), (1000, 65), (4097, 130), (65536, 322),
+                                 (1000, 385), (4097, 400), (20000, 641), (30000, 897), (9000, 1024)])
 def test_gram(env, K, n):
     lib, torch = env
     rng = np.random.default_rng(K + n)
@@ -205,7 +206,8 @@ def test_svd(env, kind, a, b):
     assert nerr < 1e-13 * np.sqrt(q)
 
 
-@pytest.mark.parametrize("K,n", [(1, 1), (7, 5), (257, 64), (4099, 130), (65536, 142), (20000, 322)])
+@pytest.mark.parametrize("K,n", [(1, 1), (7, 5), (257, 64), (4099, 130), (65536, 142), (20000, 322),
+                                 (1500, 450)])
 def test_gram_f32(env, K, n):
     """Sliced FP32-MFMA Gram of an FP32 matrix against the FP64 Gram of the
     same values: error within 2^-44 (times a small count) of the column
