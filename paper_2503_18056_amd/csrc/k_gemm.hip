@@ -455,6 +455,103 @@ __global__ __launch_bounds__(256) void k_gemm_tall(int K, const double* __restri
       }
 }
 
+// Tall GEMM for wide outputs (ncap > 64): 128 x 128 output tile per block
+// (a 128-row panel of A times all of B's columns when n <= 128, so A streams
+// from HBM once), each wave a 64 x 64 quarter of sixteen 16 x 16
+// accumulators.  A panels (128 rows x 16 k) and B chunks (16 k x 128 cols)
+// are staged through LDS, double buffered.  The A panel's row stride of 17
+// doubles puts the 16 rows an MFMA operand reads down one column in
+// distinct banks; 16 x 16 output blocks wholly past K or n are skipped.
+constexpr int GP_KB = 16;
+constexpr int GP_LDA = 17;
+constexpr int GP_LDB = 144;
+
+__global__ __launch_bounds__(256) void k_gemm_panel(int K, const double* __restrict__ A, int lda,
+                                                    const double* __restrict__ B, int ldb,
+                                                    double* __restrict__ C, int ldc,
+                                                    DimExpr kdim, DimExpr ndim,
+                                                    const int* __restrict__ dims) {
+  const int kk_tot = eval_dim(dims, kdim), n = eval_dim(dims, ndim);
+  const int r0 = blockIdx.x * 128, c0 = blockIdx.y * 128;
+  if (c0 >= n) return;
+  __shared__ double sA[2][128][GP_LDA], sB[2][GP_KB][GP_LDB];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int a0 = wr * 64, b0 = wc * 64;
+  int np = 0, nq = 0;
+  for (int t = 0; t < 4; ++t) {
+    if (r0 + a0 + 16 * t < K) np = t + 1;
+    if (c0 + b0 + 16 * t < n) nq = t + 1;
+  }
+  // loads: A panel, thread t -> row t / 2, k (t % 2) * 8 .. +8;
+  //        B chunk, thread t -> k t / 16, columns (t % 16) * 8 .. +8
+  const int ar = tid >> 1, ak = (tid & 1) * 8;
+  const int bk = tid >> 4, bc = (tid & 15) * 8;
+  const bool var = r0 + ar < K;
+  const double* arow = A + (long long)(r0 + ar) * lda;
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + ak + u;
+      ra[u] = (var && k < kk_tot) ? arow[k] : 0.0;
+      const int kb = k0 + bk, cb = c0 + bc + u;
+      rb[u] = (kb < kk_tot && cb < n) ? B[(long long)kb * ldb + cb] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sA[buf][ar][ak + u] = ra[u];
+      sB[buf][bk][bc + u] = rb[u];
+    }
+  };
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nstage = (kk_tot + GP_KB - 1) / GP_KB;
+  if (nstage > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  const int col = lane & 15, kr = lane >> 4;
+  for (int st = 0; st < nstage; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nstage) load((st + 1) * GP_KB);
+#pragma unroll
+    for (int kk = 0; kk < GP_KB; kk += 4) {
+      double fa[4], fb[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        fa[t] = sA[buf][a0 + 16 * t + col][kk + kr];
+        fb[t] = sB[buf][kk + kr][b0 + 16 * t + col];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (p < np && q < nq) acc[p][q] = mfma16(fa[p], fb[q], acc[p][q]);
+    }
+    if (st + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (p >= np || q >= nq) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + a0 + 16 * p + (lane >> 4) + 4 * r;
+        const int j = c0 + b0 + 16 * q + (lane & 15);
+        if (i < K && j < n) C[(long long)i * ldc + j] = acc[p][q][r];
+      }
+    }
+}
+
 // ===========================================================================
 // FP32-mixed precision form: the N_s-long contractions on FP32 MFMA.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -857,6 +954,11 @@ void gemm_tall_f32(int K, const float* A, int lda, const double* B, int ldb, flo
 void gemm_tall(int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
                DimExpr kdim, DimExpr ndim, int kcap, int ncap, const int* dims, hipStream_t s) {
   (void)kcap;
+  if (ncap > 64) {
+    k_gemm_panel<<<dim3((K + 127) / 128, (ncap + 127) / 128), 256, 0, s>>>(K, A, lda, B, ldb, C, ldc,
+                                                                           kdim, ndim, dims);
+    return;
+  }
   dim3 grid((ncap + 63) / 64, (K + 63) / 64);
   k_gemm_tall<<<grid, 256, 0, s>>>(K, A, lda, B, ldb, C, ldc, kdim, ndim, dims);
 }
