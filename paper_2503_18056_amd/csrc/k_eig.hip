@@ -418,6 +418,7 @@ __global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
     const int i = (int)(e / n), j = (int)(e % n);
     D.Qa[(size_t)i * N2 + j] = i == j ? 1.0 : 0.0;
+    D.Qb[(size_t)i * N2 + j] = 0.0;
   }
   for (int i = blockIdx.x * 256 + threadIdx.x; i < N2; i += gridDim.x * 256) {
     double v = 0.0;
@@ -579,16 +580,26 @@ constexpr int PREP_BYTES_PER = 4 * 8 + 2 * 4;
 // merge, the merge's arrays staged in LDS.  The halves are merged in
 // parallel (each element's rank in the other half by binary search; ties
 // put the left element first); the deflation sweep, which carries the last
-// kept entry along, runs on one lane over LDS.
-__global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__ dims, int N, int S) {
+// kept entry along, runs on one lane over LDS.  The eigenvector blocks of
+// a level live in one of two buffers (par: 0 reads Qa and writes Qb, 1 the
+// reverse); a block with no merge at this level is copied across.
+__global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__ dims, int N, int S,
+                                                 int par) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
+  const double* Qs = par ? D.Qb : D.Qa;
+  double* Qd = par ? D.Qa : D.Qb;
   const int m = blockIdx.x, b0 = m * 2 * S;
   if (b0 + S >= n) {
     if (threadIdx.x == 0) D.mk[m] = -1;
+    const int nb = max(0, min(2 * S, n - b0));
+    for (int e = threadIdx.x; e < nb * nb; e += 256) {
+      const size_t o = (size_t)(b0 + e / nb) * N2 + b0 + e % nb;
+      Qd[o] = Qs[o];
+    }
     return;
   }
   extern __shared__ double smem[];
@@ -605,8 +616,8 @@ __global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__
   const double sgn = beta < 0.0 ? -1.0 : 1.0;
   double part = 0.0, pmax = 0.0;
   for (int c = tid; c < m2; c += 256) {
-    const double zq = c < nL ? D.Qa[(size_t)(b0 + S - 1) * N2 + b0 + c]
-                             : sgn * D.Qa[(size_t)(b0 + S) * N2 + b0 + c];
+    const double zq = c < nL ? Qs[(size_t)(b0 + S - 1) * N2 + b0 + c]
+                             : sgn * Qs[(size_t)(b0 + S) * N2 + b0 + c];
     const double dv = D.lam[b0 + c];
     zt[c] = zq;
     dt[c] = dv;
@@ -729,22 +740,6 @@ __global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__
     D.mk[m] = base;
     D.mrho[m] = rho;
     D.mm2[m] = m2;
-  }
-  __syncthreads();
-  // permute the merge block's columns into slot order and apply the Givens
-  // rotations of the deflation (a thread per row)
-  const int nrot = D.mnrot[m];
-  for (int r = b0 + tid; r < b0 + m2; r += 256) {
-    double* qb = D.Qb + (size_t)r * N2 + b0;
-    const double* qa = D.Qa + (size_t)r * N2 + b0;
-    for (int t = 0; t < m2; ++t) qb[t] = qa[perm[t]];
-    for (int t = 0; t < nrot; ++t) {
-      const int p = D.rp[b0 + t], q = D.rq[b0 + t];
-      const double c = D.rc[b0 + t], sn = D.rs[b0 + t];
-      const double xp = qb[p], xq = qb[q];
-      qb[p] = c * xp - sn * xq;
-      qb[q] = sn * xp + c * xq;
-    }
   }
 }
 
@@ -897,9 +892,14 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
   }
 }
 
-// Loewner z^, eigenvectors of D + rho z^ z^^T, sorted output, U block.
-// The merge's K arrays (d, d at each root's origin, tau, z^, slots) are
-// staged in LDS.
+// Loewner z^, eigenvectors of D + rho z^ z^^T, sorted output, and the
+// merge's update matrix W = P G U: U (slot rows, output columns) with the
+// deflation's Givens rotations G = G_0 ... G_{r-1} (which act on the slot
+// columns of the merge block) applied to its rows, and the slot-to-local
+// permutation P applied to its rows, so that the new eigenvector block is
+// the old block times W.  A thread owns whole columns of W, so the
+// rotations need no barrier.  The merge's K arrays (d, d at each root's
+// origin, tau, z^, slots) are staged in LDS.
 __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restrict__ dims, int N, int S) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
@@ -912,6 +912,7 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   if (b0 + S >= n) return;  // no merge in this block; its GEMM batch is skipped
   const int nk = D.mk[m];
   const int m2 = D.mm2[m];
+  const int nrot = D.mnrot[m];
   extern __shared__ double smem[];
   double* d = smem;
   double* dro = d + S2;
@@ -993,7 +994,7 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
     if (tag < 0 || tag >= 2 * m2) {
       atomicOr(&dims[D_FLAG], FLAG_EIG);
     } else if (tag >= m2) {
-      Ub[(size_t)(tag - m2) * S2 + pos] = 1.0;
+      Ub[(size_t)D.perm[b0 + tag - m2] * S2 + pos] = 1.0;
     } else {
       const int i = tag;
       const double di = dro[i], ti = rt[i];
@@ -1009,8 +1010,17 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
       const double inv = 1.0 / sqrt(nrm);
       for (int j = 0; j < nk; ++j) {
         const double u = zh[j] / ((d[j] - di) - ti);
-        Ub[(size_t)ks[j] * S2 + pos] = u * inv;
+        Ub[(size_t)D.perm[b0 + ks[j]] * S2 + pos] = u * inv;
       }
+    }
+    // rows of the rotations in local order, the last rotation first
+    for (int t = nrot - 1; t >= 0; --t) {
+      const size_t rp = (size_t)D.perm[b0 + D.rp[b0 + t]] * S2 + pos;
+      const size_t rq = (size_t)D.perm[b0 + D.rq[b0 + t]] * S2 + pos;
+      const double c = D.rc[b0 + t], sn = D.rs[b0 + t];
+      const double xp = Ub[rp], xq = Ub[rq];
+      Ub[rp] = c * xp + sn * xq;
+      Ub[rq] = c * xq - sn * xp;
     }
   }
 }
@@ -1032,7 +1042,8 @@ __host__ __device__ inline int ormtr_chunk(int N) {
   return c < 1 ? 1 : (c > ORM_CH ? ORM_CH : c);
 }
 
-__global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N) {
+__global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N,
+                                               int par) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
@@ -1051,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   double* ts = hs + (size_t)ch * N;
   double* y = ys[wave];
   if (active)
-    for (int i = lane; i < n; i += 64) y[i] = D.Qa[(size_t)i * N2 + j];
+    for (int i = lane; i < n; i += 64) y[i] = (par ? D.Qb : D.Qa)[(size_t)i * N2 + j];
   for (int k1 = n - 3; k1 >= 0; k1 -= ch) {
     const int k0 = max(0, k1 - ch + 1);
     __syncthreads();
@@ -1606,7 +1617,8 @@ __global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M
 // Vectors of the short side for the kept singular values, one wavefront per
 // vector: y = the even entries of the tridiagonal's eigenvector, normalised,
 // then y <- G_0 G_1 ... G_{q-2} y with the right reflectors.
-__global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict__ dims, int N) {
+__global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict__ dims, int N,
+                                                  int par) {
   const EigJob J = jobs.j[0];
   const int n = dims[J.n_idx], q = n / 2;
   Work W = work_of(J, N);
@@ -1623,7 +1635,7 @@ __global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict_
   // mixing of the +-sigma pair only rescales the v-part: normalise it
   double part0 = 0.0;
   for (int i = lane; i < q; i += 64) {
-    const double x = D.Qa[(size_t)(2 * i) * N2 + col];
+    const double x = (par ? D.Qb : D.Qa)[(size_t)(2 * i) * N2 + col];
     y[i] = x;
     part0 += x * x;
   }
@@ -1686,20 +1698,22 @@ size_t eig_work_doubles(int N) {
 namespace {
 
 // Divide-and-conquer levels for the tridiagonals (W.d, W.e) of the jobs.
-void dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims, hipStream_t s) {
+// Returns which buffer holds the eigenvectors at the end (0: Qa, 1: Qb).
+int dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims, hipStream_t s) {
   const int N2 = next_pow2(N);
   int ib = (int)(((long long)N2 * N2 + 255) / 256);
   if (ib > 2048) ib = 2048;
   k_dc_init<<<dim3(ib, njobs), 256, 0, s>>>(J, dims, N);
   k_dc_leaf<<<dim3((N + DC_LEAF - 1) / DC_LEAF, njobs), LEAF_T, 0, s>>>(J, dims, N);
-  for (int S = DC_LEAF; S < N; S *= 2) {
+  int par = 0;
+  for (int S = DC_LEAF; S < N; S *= 2, par ^= 1) {
     const int nm = (N + 2 * S - 1) / (2 * S);
-    k_dc_prep<<<dim3(nm, njobs), 256, (size_t)2 * S * PREP_BYTES_PER, s>>>(J, dims, N, S);
+    k_dc_prep<<<dim3(nm, njobs), 256, (size_t)2 * S * PREP_BYTES_PER, s>>>(J, dims, N, S, par);
     k_dc_secular<<<dim3((2 * S + 3) / 4, nm, njobs), 256, (size_t)2 * S * 16, s>>>(J, dims, N, S);
     k_dc_vectors<<<dim3(nm, njobs), 256, (size_t)2 * S * 36, s>>>(J, dims, N, S);
     {
-      // Q block <- Q_rot block * U block, for every merge block of this level
-      // of every job (one launch)
+      // new block <- old block * W, for every merge block of this level of
+      // every job (one launch)
       const int bm = (N + 2 * S - 1) / (2 * S);
       GemmDesc g;
       memset(&g, 0, sizeof(g));
@@ -1723,14 +1737,15 @@ void dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims
         const double* Qa = wbase + off_z + N2;
         const double* Qb = Qa + (size_t)N2 * N2;
         const double* U = Qb + (size_t)N2 * N2;
-        g.Aj[q] = Qb;
+        g.Aj[q] = par ? Qb : Qa;
         g.Bj[q] = U;
-        g.Cj[q] = const_cast<double*>(Qa);
+        g.Cj[q] = const_cast<double*>(par ? Qa : Qb);
         g.bclipj[q] = jobs[q].n_idx;
       }
       gemm(g, 2 * S, 2 * S, njobs * bm, dims, s);
     }
   }
+  return par;
 }
 
 }  // namespace
@@ -1745,9 +1760,9 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
     k_sytrd_grid_reset<<<nj, SYTRD_GRID_P, 0, s>>>(J, N);
     k_sytrd_grid<<<dim3(SYTRD_GRID_P, nj), SYTRD_GRID_T, sytrd_grid_lds(N), s>>>(J, dims, N);
   }
-  dc_levels(jobs, J, njobs, N, dims, s);
+  const int par = dc_levels(jobs, J, njobs, N, dims, s);
   k_ormtr<<<dim3((N + 3) / 4, njobs), 256, ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8, s>>>(
-      J, dims, N);
+      J, dims, N, par);
   k_eig_final<<<dim3((N + FINAL_COLS - 1) / FINAL_COLS, njobs), 256, 0, s>>>(J, dims, N);
 }
 
@@ -1770,8 +1785,8 @@ void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx
     k_gebrd_grid<<<P, 256, gebrd_grid_lds(pcap, qc), s>>>(J, dims, N, a_idx, b_idx, side_idx, pcap,
                                                           qc);
   }
-  dc_levels(&job, J, 1, N, dims, s);
-  k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N);
+  const int par = dc_levels(&job, J, 1, N, dims, s);
+  k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N, par);
   k_svd_final<<<1, 256, 0, s>>>(J, dims, N);
 }
 

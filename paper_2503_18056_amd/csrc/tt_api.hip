@@ -426,7 +426,8 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
   {
     Prof p(c, P_EIG2);
     EigJob j = {c->GL2, R2c, D_RC2, c->E[4].lam, c->E[4].V, N, c->E[4].sq, c->E[4].isq, D_KA2, 1.0, c->E[4].work};
-    eig_batched(&j, 1, N, c->dims, s);
+    // sized by the bond-2 capacity: fewer divide-and-conquer levels than N
+    eig_batched(&j, 1, R2c, c->dims, s);
   }
   truncate_bond(c, 2, c->E[4], c->E[2], c->E[5], c->M2, c->C2, c->Wm2, c->Ur2, c->P2, c->Mupd2,
                 R2c, c->r2c, D_RC2, tol, rmax);
