@@ -285,19 +285,21 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
 // reads LDS instead of L2.  Outputs (d, e, tau, reflectors) as k_sytrd.
 __device__ inline int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-__global__ __launch_bounds__(1024) void k_sytrd_lds(EigJobs jobs, int* __restrict__ dims, int N) {
+constexpr int SYL_T = 1024;            // threads of k_sytrd_lds
+constexpr int SYL_C = SYL_T / 128;     // column chunks of its matrix-vector product
+__global__ __launch_bounds__(SYL_T) void k_sytrd_lds(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.x];
   const int n = dims[J.n_idx];
   if (n > SYTRD_LDS_MAX) return;
   __shared__ double Lp[SYTRD_LDS_MAX * (SYTRD_LDS_MAX + 1) / 2];
-  __shared__ double sv[SYTRD_LDS_MAX], sw[SYTRD_LDS_MAX], sp[8][SYTRD_LDS_MAX];
+  __shared__ double sv[SYTRD_LDS_MAX], sw[SYTRD_LDS_MAX], sp[SYL_C][SYTRD_LDS_MAX];
   __shared__ double s_tau;
   const double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int rj = tid & 127, rc = tid >> 7;  // matvec: row, column chunk
-  for (int i = wave; i < n; i += 16)
+  const int rj = tid & 127, rc = tid >> 7;  // matvec: row, column chunk (SYL_C chunks)
+  for (int i = wave; i < n; i += SYL_T / 64)
     for (int j = lane; j <= i; j += 64) Lp[tri(i, j)] = A[(long long)i * lda + j];
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(1024) void k_sytrd_lds(EigJobs jobs, int* __restric
     // partial products of A22 v: row j, columns i = rc (mod 8)
     for (int j = rj; j < m; j += 128) {
       double acc = 0.0;
-      for (int i = rc; i < m; i += 8)
+      for (int i = rc; i < m; i += SYL_C)
         acc += (i <= j ? Lp[tri(o + j, o + i)] : Lp[tri(o + i, o + j)]) * sv[i];
       sp[rc][j] = acc;
     }
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_sytrd_lds(EigJobs jobs, int* __restric
       for (int j = lane; j < m; j += 64) {
         double p = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) p += sp[c][j];
+        for (int c = 0; c < SYL_C; ++c) p += sp[c][j];
         p *= tau;
         sw[j] = p;
         part += p * sv[j];
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(1024) void k_sytrd_lds(EigJobs jobs, int* __restric
     }
     __syncthreads();
     // A22 -= v w^T + w v^T on the lower triangle, a wavefront per row
-    for (int i = wave; i < m; i += 16) {
+    for (int i = wave; i < m; i += SYL_T / 64) {
       const double vi = sv[i], wi = sw[i];
       double* row = Lp + tri(o + i, o);
       for (int j = lane; j <= i; j += 64) row[j] -= vi * sw[j] + wi * sv[j];
@@ -1754,7 +1756,7 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   if (njobs <= 0 || N <= 0) return;
   EigJobs J;
   for (int i = 0; i < njobs && i < 4; ++i) J.j[i] = jobs[i];
-  k_sytrd_lds<<<njobs, 1024, 0, s>>>(J, dims, N);
+  k_sytrd_lds<<<njobs, SYL_T, 0, s>>>(J, dims, N);
   if (N > SYTRD_LDS_MAX) {
     const int nj = njobs < 4 ? njobs : 4;
     k_sytrd_grid_reset<<<nj, SYTRD_GRID_P, 0, s>>>(J, N);

@@ -9,11 +9,15 @@ namespace tt {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // row-slice Gram (k_gram_rows) shape
-constexpr int GR_CH = 16;
+constexpr int GR_CH = 16;     // rows per LDS chunk
 constexpr int GR_MAXN = 384;  // columns held per LDS row
-constexpr int GR_WAVES = 8;
-constexpr int GR_THREADS = GR_WAVES * 64;
-constexpr int GR_TPW = 2;     // tasks per wavefront per pass
+constexpr int GR_LD = 400;    // LDS row stride: row groups r and r+1 fall in opposite bank halves
+// waves per block and 32x32 tasks per wave and pass: FP64 sixteen waves of
+// one task (four waves a SIMD, held in registers without spilling); FP32 (the
+// sliced products need more registers per task) eight waves of two
+template <typename T> struct GrShape;
+template <> struct GrShape<double> { static constexpr int WAVES = 16, TPW = 1; };
+template <> struct GrShape<float> { static constexpr int WAVES = 8, TPW = 2; };
 
 
 // ---------------------------------------------------------------------------
@@ -378,7 +382,7 @@ size_t gram_partial_doubles(const GramPlan& p) {
 void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* partial,
                        const int* dims, hipStream_t s) {
   if (p.rows_mode) {
-    k_gram_rows<double><<<p.nblk, GR_THREADS, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n, dims, nullptr,
+    k_gram_rows<double><<<p.nblk, GrShape<double>::WAVES * 64, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n, dims, nullptr,
                                                 partial);
     return;
   }
@@ -764,16 +768,17 @@ __device__ inline void gr_task(int t, int& ti, int& tj, int T32) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(GR_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gram_rows(const T* __restrict__ A, int lda, int K,
+__global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves_per_eu(GrShape<T>::WAVES / 4, GrShape<T>::WAVES / 4))) void k_gram_rows(const T* __restrict__ A, int lda, int K,
                                                     int rows_per_blk, DimExpr ndim,
                                                     const int* __restrict__ dims,
                                                     const unsigned* __restrict__ colmax,
                                                     double* __restrict__ partial) {
+  constexpr int GR_WAVES = GrShape<T>::WAVES, GR_TPW = GrShape<T>::TPW, GR_THREADS = GR_WAVES * 64;
   const int n = eval_dim(dims, ndim);
   const int T32 = (n + 31) / 32, ntask = T32 * (T32 + 1) / 2;
   const int k_begin = blockIdx.x * rows_per_blk;
   const int k_end = min(K, k_begin + rows_per_blk);
-  __shared__ T lds[GR_CH][GR_MAXN + 1];
+  __shared__ T lds[GR_CH][GR_LD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int col = lane & 15, krow = lane >> 4;
   const int nld = GR_CH * n;  // elements staged per chunk
@@ -937,7 +942,7 @@ void gram_split_partial(const GramPlan& p, const float* A, DimExpr n, unsigned* 
   k_colmax<<<dim3((p.ncap + 63) / 64, (p.K + 255) / 256), 256, 0, s>>>(A, p.lda, p.K, n, dims,
                                                                        colmax);
   if (p.rows_mode) {
-    k_gram_rows<float><<<p.nblk, GR_THREADS, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n, dims, colmax,
+    k_gram_rows<float><<<p.nblk, GrShape<float>::WAVES * 64, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n, dims, colmax,
                                                partial);
     return;
   }
