@@ -223,7 +223,10 @@ def thick_3d_run(W, K):
             "ranks_entering_timed_steps": [list(r) for r in r_in],
             "ranks_end": list(st.ranks()),
             "ms_per_rounding": round_ms / K,
-            "gram": {"avg_launch_ms": gms / gn if gn else None,
+            "gram": {"kernel": ("k_gram_wide (FP64 MFMA, 128x128 tile pairs, rows staged through LDS)"
+                                if prec == TT_FP64 else
+                                "k_gram_split (sliced exact Gram on FP32 MFMA, 10 slice products)"),
+                     "avg_launch_ms": gms / gn if gn else None,
                      "achieved_algorithmic_TFLOPs": achieved,
                      "peak_TFLOPs": peak, "frac": achieved / peak},
             "kernel_breakdown_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
@@ -355,7 +358,7 @@ def main():
                     "truncation and core updates), from the library's HIP events",
         },
         "roofline": {
-            "kernel": GRAM_KERNEL64 if R1CAP <= GRAM_ROWS_MAX else "k_gram_tall + k_gram_reduce",
+            "kernel": GRAM_KERNEL64 if R1CAP <= GRAM_ROWS_MAX else "k_gram_wide + k_gram_wide_reduce",
             "bound": "mfma",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,

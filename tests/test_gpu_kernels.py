@@ -36,7 +36,8 @@ def _ws(torch, nbytes):
 
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
-@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (5, 7, 3), (70, 65, 17), (130, 33, 200), (4, 9, 0)])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (5, 7, 3), (70, 65, 17), (130, 33, 200), (4, 9, 0),
+                                   (512, 17, 3), (600, 70, 130), (5000, 130, 641), (1030, 260, 9)])
 def test_gemm(env, ta, tb, m, n, k):
     lib, torch = env
     rng = np.random.default_rng(m * 100 + n + k)
