@@ -180,7 +180,7 @@ def mixed_run(p, W, K, dt, hist, end64):
         "rank_history_equal_steps": sum(a == b for a, b in zip(histm, hist)),
         "ranks_end": list(sm.ranks()),
         "gram_kernel": {
-            "kernel": GRAM_KERNEL32 if R1CAP <= GRAM_ROWS_MAX else "k_gram_split",
+            "kernel": GRAM_KERNEL32 if R1CAP <= GRAM_ROWS_MAX else "k_gram_split_wide",
             "avg_launch_ms": gm_ms / gm_n if gm_n else None,
             "achieved_algorithmic_TFLOPs": flops_m / (gm_ms * 1e-3) / 1e12 if gm_ms > 0 else 0.0,
             "peak_fp32_mfma_TFLOPs": FP32_MFMA_PEAK_TFLOPS,
@@ -225,7 +225,7 @@ def thick_3d_run(W, K):
             "ms_per_rounding": round_ms / K,
             "gram": {"kernel": ("k_gram_wide (FP64 MFMA, 128x128 tile pairs, rows staged through LDS)"
                                 if prec == TT_FP64 else
-                                "k_gram_split (sliced exact Gram on FP32 MFMA, 10 slice products)"),
+                                "k_gram_split_wide (sliced exact Gram on FP32 MFMA, 10 slice products, 128x128 tile pairs)"),
                      "avg_launch_ms": gms / gn if gn else None,
                      "achieved_algorithmic_TFLOPs": achieved,
                      "peak_TFLOPs": peak, "frac": achieved / peak},

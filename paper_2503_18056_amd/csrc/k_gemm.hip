@@ -305,29 +305,6 @@ __global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restri
   }
 }
 
-// Fixed-order reduction of the sliced FP32 Gram's 64 x 64 tile pairs
-// (deterministic), mirrored into G.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ partial,
-                                                     int slices, int npairs, int tiles,
-                                                     DimExpr ndim, const int* __restrict__ dims,
-                                                     double* __restrict__ G, int ldg) {
-  const int n = eval_dim(dims, ndim);
-  const int pair = blockIdx.y;
-  int ti = 0, rem = pair;
-  while (rem >= tiles - ti) { rem -= tiles - ti; ++ti; }
-  const int tj = ti + rem;
-  if (ti * 64 >= n || tj * 64 >= n) return;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < 4096; e += gridDim.x * 256) {
-    const int ii = e >> 6, jj = e & 63;
-    const int i = ti * 64 + ii, j = tj * 64 + jj;
-    if (i >= n || j >= n) continue;
-    double s = 0.0;
-    for (int sl = 0; sl < slices; ++sl) s += partial[((long long)sl * npairs + pair) * 4096 + e];
-    G[(long long)i * ldg + j] = s;
-    G[(long long)j * ldg + i] = s;
-  }
-}
-
 template <typename T>
 __global__ void k_gram_rows(const T* __restrict__ A, int lda, int K, int rows_per_blk, DimExpr ndim,
                             const int* __restrict__ dims, const unsigned* __restrict__ colmax,
@@ -340,16 +317,6 @@ GramPlan gram_plan(int K, int ncap, int lda) {
   p.K = K;
   p.ncap = ncap;
   p.lda = lda;
-  p.tiles = (ncap + 63) / 64;
-  p.pairs = p.tiles * (p.tiles + 1) / 2;
-  int want = (2048 + p.pairs - 1) / p.pairs;          // aim at ~2048 blocks
-  int maxs = (K + 63) / 64;                            // at least 64 rows a slice
-  p.slices = want < maxs ? want : maxs;
-  if (p.slices < 1) p.slices = 1;
-  int ks = (K + p.slices - 1) / p.slices;
-  p.kslice = (ks + 3) / 4 * 4;
-  p.slices = (K + p.kslice - 1) / p.kslice;
-  if (p.slices < 1) p.slices = 1;
   // row-slice form (LDS-staged) when the columns fit one LDS row
   p.rows_mode = ncap <= 384;
   const int t32 = (ncap + 31) / 32;
@@ -374,9 +341,7 @@ GramPlan gram_plan(int K, int ncap, int lda) {
 
 size_t gram_partial_doubles(const GramPlan& p) {
   if (p.rows_mode) return (size_t)p.nblk * p.ntask_cap * 1024;
-  const size_t split = (size_t)p.slices * p.pairs * 4096;
-  const size_t wide = (size_t)p.wslices * p.wpairs * GW_T * GW_T;
-  return split > wide ? split : wide;
+  return (size_t)p.wslices * p.wpairs * GW_T * GW_T;
 }
 
 void gram_tall_partial(const GramPlan& p, const double* A, DimExpr n, double* partial,
@@ -404,8 +369,8 @@ void gram_split_reduce(const GramPlan& p, DimExpr n, const double* partial, doub
     k_gram_rows_reduce<<<dim3(16, p.ntask_cap), 256, 0, s>>>(partial, p.nblk, n, dims, G, ldg);
     return;
   }
-  k_gram_reduce<<<dim3(4, p.pairs), 256, 0, s>>>(partial, p.slices, p.pairs, p.tiles, n, dims, G,
-                                                 ldg);
+  k_gram_wide_reduce<<<dim3(8, p.wpairs), 256, 0, s>>>(partial, p.wslices, p.wpairs, p.wtiles, n,
+                                                       dims, G, ldg);
 }
 void gram_tall(const GramPlan& p, const double* A, DimExpr n, double* partial, double* G, int ldg,
                const int* dims, hipStream_t s) {
@@ -587,93 +552,141 @@ __device__ inline void split4(float x, int E, float s[4]) {
 }
 
 // Gram G = A^T A of an FP32 matrix on FP32 MFMA, exact to 2^-44 of each
-// column's largest entry (Ozaki-style error-free splitting).  Each entry is
-// split on a per-column exponent grid into 11-bit integer slices; the slice
-// pairs (s, t) with s + t <= 5 are multiplied on MFMA four rows at a time,
-// where every partial sum is an integer of at most 2^24 and so exact in FP32
-// (pairs sharing a scale 2^-11(s+t) share an accumulator when their bound
-// allows); each exact partial is flushed into FP64.  Output: the same
-// per-slice 64x64 partial tiles as k_gram_tall (reduced by k_gram_reduce).
-__global__ __launch_bounds__(256) void k_gram_split(const float* __restrict__ A, int lda, int K,
-                                                    int kslice, DimExpr ndim,
-                                                    const int* __restrict__ dims, int tiles,
-                                                    const unsigned* __restrict__ colmax,
-                                                    double* __restrict__ partial) {
+// column's largest entry (Ozaki-style error-free splitting), for more than
+// 384 columns.  Each entry is split on a per-column exponent grid into 11-bit
+// integer slices; the slice pairs (s, t), counted from 0, with s + t <= 3 are
+// multiplied on MFMA four rows at a time, where every partial sum is an
+// integer of at most 2^24 and so exact in FP32 (pairs sharing a scale
+// 2^-11(s+t) share an accumulator when their bound allows); each exact
+// partial is flushed into FP64.  Blocking, staging and block order as
+// k_gram_wide (128 x 128 tile pairs, 16-row stages through LDS, each wave a
+// 64 x 64 quarter); output in k_gram_wide's partial layout, scaled back by
+// the column exponents, for k_gram_wide_reduce.
+__global__ __launch_bounds__(256) void k_gram_split_wide(const float* __restrict__ A, int lda,
+                                                         int K, int kslice, int slices,
+                                                         DimExpr ndim, const int* __restrict__ dims,
+                                                         int tiles, int pairs,
+                                                         const unsigned* __restrict__ colmax,
+                                                         double* __restrict__ partial) {
   const int n = eval_dim(dims, ndim);
-  const int pair = blockIdx.x, slice = blockIdx.y;
-  int ti = 0, rem = pair;
-  while (rem >= tiles - ti) { rem -= tiles - ti; ++ti; }
-  const int tj = ti + rem;
-  if (ti * 64 >= n || tj * 64 >= n) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int x = blockIdx.x % GW_XCD, jx = blockIdx.x / GW_XCD;
+  const int pair = jx % pairs, slice = x + GW_XCD * (jx / pairs);
+  if (slice >= slices) return;
+  int ti, tj;
+  gw_pair(pair, tiles, ti, tj);
+  if (ti * GW_T >= n || tj * GW_T >= n) return;
+  const bool diag = ti == tj;
+  __shared__ float sA[2][GW_KB][GW_LD], sB[2][GW_KB][GW_LD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
-  const int a0 = ti * 64 + wr * 32, b0 = tj * 64 + wc * 32;
-  const int col = lane & 15, krow = lane >> 4;
+  const bool idle = diag && wr > wc;
+  const int ca = ti * GW_T, cb = tj * GW_T;
+  const int lc = tid & 127, lr = tid >> 7;
+  const bool va = ca + lc < n, vb = cb + lc < n;
   const int k_begin = slice * kslice;
   const int k_end = min(K, k_begin + kslice);
-  const bool va0 = a0 + col < n, va1 = a0 + 16 + col < n;
-  const bool vb0 = b0 + col < n, vb1 = b0 + 16 + col < n;
-  const int ea0 = va0 ? col_exponent(colmax[a0 + col]) : 0;
-  const int ea1 = va1 ? col_exponent(colmax[a0 + 16 + col]) : 0;
-  const int eb0 = vb0 ? col_exponent(colmax[b0 + col]) : 0;
-  const int eb1 = vb1 ? col_exponent(colmax[b0 + 16 + col]) : 0;
-  f64x4 acc[2][2];
+  const int a0 = wr * 64, b0 = wc * 64;
+  const int col = lane & 15, kr = lane >> 4;
+  int np = 0, nq = 0;
+  int ea[4], eb[4];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const double sc2 = 0x1p-22, sc3 = 0x1p-33, sc4 = 0x1p-44, sc5 = 0x1p-55;
-  for (int k = k_begin; k < k_end; k += 4) {
-    const int row = k + krow;
-    const bool vr = row < k_end;
-    const float* rp = A + (long long)row * lda;
-    float xs[2][4], ys[2][4];
-    split4((vr && va0) ? rp[a0 + col] : 0.0f, ea0, xs[0]);
-    split4((vr && va1) ? rp[a0 + 16 + col] : 0.0f, ea1, xs[1]);
-    split4((vr && vb0) ? rp[b0 + col] : 0.0f, eb0, ys[0]);
-    split4((vr && vb1) ? rp[b0 + 16 + col] : 0.0f, eb1, ys[1]);
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const float* x = xs[p];
-        const float* y = ys[q];
-        const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
-        // scale 2^-22: (0,0)
-        const f32x4 g2 = mfma16f(x[0], y[0], z);
-        // 2^-33: (0,1) + (1,0)           <= 8 * 2^21
-        const f32x4 g3 = mfma16f(x[1], y[0], mfma16f(x[0], y[1], z));
-        // 2^-44: (0,2) + (2,0)           <= 8 * 2^21;  (1,1) <= 4 * 2^20
-        const f32x4 g4a = mfma16f(x[2], y[0], mfma16f(x[0], y[2], z));
-        const f32x4 g4b = mfma16f(x[1], y[1], z);
-        // 2^-55: (0,3) + (3,0)           <= 8 * 2^21;  (1,2) + (2,1) <= 8 * 2^20
-        const f32x4 g5a = mfma16f(x[3], y[0], mfma16f(x[0], y[3], z));
-        const f32x4 g5b = mfma16f(x[2], y[1], mfma16f(x[1], y[2], z));
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          double v = acc[p][q][r];
-          v = fma((double)g2[r], sc2, v);
-          v = fma((double)g3[r], sc3, v);
-          v = fma((double)g4a[r] + (double)g4b[r], sc4, v);
-          v = fma((double)g5a[r] + (double)g5b[r], sc5, v);
-          acc[p][q][r] = v;
-        }
-      }
+  for (int t = 0; t < 4; ++t) {
+    if (ca + a0 + 16 * t < n) np = t + 1;
+    if (cb + b0 + 16 * t < n) nq = t + 1;
+    const int xa = ca + a0 + 16 * t + col, xb = cb + b0 + 16 * t + col;
+    ea[t] = xa < n ? col_exponent(colmax[xa]) : 0;
+    eb[t] = xb < n ? col_exponent(colmax[xb]) : 0;
   }
-  const int npairs = gridDim.x;
-  double* out = partial + ((long long)slice * npairs + pair) * 4096;
+  if (idle) np = nq = 0;
+  f64x4 acc[4][4];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < 4; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  float ra[8], rb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = k0 + lr + 2 * u;
+      const bool vr = row < k_end;
+      const float* rp = A + (long long)row * lda;
+      ra[u] = (vr && va) ? rp[ca + lc] : 0.0f;
+      rb[u] = (vr && vb && !diag) ? rp[cb + lc] : 0.0f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sA[buf][lr + 2 * u][lc] = ra[u];
+      if (!diag) sB[buf][lr + 2 * u][lc] = rb[u];
+    }
+  };
+  const int nstage = (k_end - k_begin + GW_KB - 1) / GW_KB;
+  if (nstage > 0) {
+    load(k_begin);
+    store(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nstage; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nstage) load(k_begin + (st + 1) * GW_KB);
+    const float(*SA)[GW_LD] = sA[buf];
+    const float(*SB)[GW_LD] = diag ? sA[buf] : sB[buf];
+    for (int kk = 0; kk < GW_KB; kk += 4) {
+      float xs[4][4], ys[4][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        split4(SA[kk + kr][a0 + 16 * t + col], ea[t], xs[t]);
+        split4(SB[kk + kr][b0 + 16 * t + col], eb[t], ys[t]);
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (p >= np || q >= nq) continue;
+          const float* xv = xs[p];
+          const float* yv = ys[q];
+          const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+          // scale 2^-22: (0,0)
+          const f32x4 g2 = mfma16f(xv[0], yv[0], z);
+          // 2^-33: (0,1) + (1,0)           <= 8 * 2^21
+          const f32x4 g3 = mfma16f(xv[1], yv[0], mfma16f(xv[0], yv[1], z));
+          // 2^-44: (0,2) + (2,0)           <= 8 * 2^21;  (1,1) <= 4 * 2^20
+          const f32x4 g4a = mfma16f(xv[2], yv[0], mfma16f(xv[0], yv[2], z));
+          const f32x4 g4b = mfma16f(xv[1], yv[1], z);
+          // 2^-55: (0,3) + (3,0)           <= 8 * 2^21;  (1,2) + (2,1) <= 8 * 2^20
+          const f32x4 g5a = mfma16f(xv[3], yv[0], mfma16f(xv[0], yv[3], z));
+          const f32x4 g5b = mfma16f(xv[2], yv[1], mfma16f(xv[1], yv[2], z));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double v = acc[p][q][r];
+            v = fma((double)g2[r], 0x1p-22, v);
+            v = fma((double)g3[r], 0x1p-33, v);
+            v = fma((double)g4a[r] + (double)g4b[r], 0x1p-44, v);
+            v = fma((double)g5a[r] + (double)g5b[r], 0x1p-55, v);
+            acc[p][q][r] = v;
+          }
+        }
+    }
+    if (st + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+  double* out = partial + ((long long)slice * pairs + pair) * (GW_T * GW_T);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (p >= np || q >= nq) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ii = wr * 32 + 16 * p + 4 * (lane >> 4) + r;
-        const int jj = wc * 32 + 16 * q + (lane & 15);
-        const int ga = ti * 64 + ii, gb = tj * 64 + jj;
-        const int e = (ga < n ? col_exponent(colmax[ga]) : 0) + (gb < n ? col_exponent(colmax[gb]) : 0);
-        out[ii * 64 + jj] = ldexp(acc[p][q][r], e);
+        // FP32 MFMA item r of lane l: row 4 (l / 16) + r, column l % 16
+        const int ii = a0 + 16 * p + 4 * (lane >> 4) + r;
+        const int jj = b0 + 16 * q + (lane & 15);
+        const int gi = ca + ii, gj = cb + jj;
+        const int e = (gi < n ? col_exponent(colmax[gi]) : 0) + (gj < n ? col_exponent(colmax[gj]) : 0);
+        out[ii * GW_T + jj] = ldexp(acc[p][q][r], e);
       }
+    }
 }
 
 // colmax[c] = bits of max_i |A[i][c]| over i < K, c < n (FP32 A, row-major);
@@ -758,7 +771,7 @@ __global__ __launch_bounds__(256) void k_gemm_tall_f32(int K, const float* __res
 // slice).  A is read from HBM
 // once; each block writes its slice's partial Gram (tasks x 1024 doubles),
 // reduced in a fixed order by k_gram_rows_reduce.  T = double: FP64 MFMA;
-// T = float: the sliced error-free products of k_gram_split.
+// T = float: the sliced error-free products of k_gram_split_wide.
 
 __device__ inline void gr_task(int t, int& ti, int& tj, int T32) {
   int a = 0, rem = t;
@@ -946,8 +959,8 @@ void gram_split_partial(const GramPlan& p, const float* A, DimExpr n, unsigned* 
                                                partial);
     return;
   }
-  k_gram_split<<<dim3(p.pairs, p.slices), 256, 0, s>>>(A, p.lda, p.K, p.kslice, n, dims, p.tiles,
-                                                       colmax, partial);
+  k_gram_split_wide<<<p.wslices * p.wpairs, 256, 0, s>>>(A, p.lda, p.K, p.wkslice, p.wslices, n,
+                                                         dims, p.wtiles, p.wpairs, colmax, partial);
 }
 
 void gemm_tall_f32(int K, const float* A, int lda, const double* B, int ldb, float* C, int ldc,

@@ -104,9 +104,8 @@ void sum_partials(const double* part, long long zstride, int nz, double* out, in
 // ---- tall Gram on MFMA: G = A^T A, A is K x n (row-major, lda), n <= ncap
 struct GramPlan {
   int K, ncap, lda;
-  // sliced FP32 form above 384 columns: 64-column tile pairs
-  int tiles, pairs, slices, kslice;
-  // FP64 form above 384 columns: 128-column tile pairs, wslices row slices
+  // above 384 columns (FP64 and the sliced FP32 form): 128-column tile
+  // pairs, wslices row slices of wkslice rows
   int wtiles, wpairs, wslices, wkslice;
   // row-slice form (ncap <= 384): nblk blocks of rows_per_blk rows, up to
   // ntask_cap upper-triangular 32x32 tasks each

@@ -209,7 +209,7 @@ def test_svd(env, kind, a, b):
 
 
 @pytest.mark.parametrize("K,n", [(1, 1), (7, 5), (257, 64), (4099, 130), (65536, 142), (20000, 322),
-                                 (1500, 450)])
+                                 (1500, 450), (2000, 641), (600, 1024)])
 def test_gram_f32(env, K, n):
     """Sliced FP32-MFMA Gram of an FP32 matrix against the FP64 Gram of the
     same values: error within 2^-44 (times a small count) of the column
