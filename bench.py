@@ -162,6 +162,50 @@ def cpu_baseline(p, start_cores, nsteps_target_s=15.0, max_steps=60):
                       f"NumPy FP64, {len(os.sched_getaffinity(0))} host cores visible"}
 
 
+def cpu_oracle_extra(p, start_cores, budget_s=12.0):
+    """More of the CPU oracle beside the GPU (bounded samples, host only):
+    the TT oracle on the crossing-beam workload at one BLAS thread; the TT
+    oracle's first five steps of the thick 3-D workload at all cores; and the
+    full-grid S_N oracle on the 32^2 parity case, in the paper's unit
+    (angle-updates/s; the paper's serial-Python S_N rates are 3.1-4.3e7)."""
+    import numpy as np
+    import workloads as wl
+    from oracle import Setup, full, tt
+    from threadpoolctl import threadpool_limits
+    out = {}
+    s = Setup(p)
+    X, Th, Ph = start_cores
+    T = s.T0.copy()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        n = 0
+        while n < 40 and time.perf_counter() - t0 < budget_s:
+            (X, Th, Ph), T, _ = tt.step(X, Th, Ph, T, s, p["tol"], p["rmax"])
+            n += 1
+        dt = time.perf_counter() - t0
+    out["tt_crossing_beams_1thread"] = {"steps_per_s": n / dt, "steps": n,
+                                        "sample": "consecutive steps from the GPU's post-warmup state"}
+    p4 = wl.c4(steps=5)
+    s4 = Setup(p4)
+    t0 = time.perf_counter()
+    tt.run(s4, 5)
+    dt = time.perf_counter() - t0
+    out["tt_thick3d_first5_allcores"] = {"steps_per_s": 5 / dt, "seconds": dt,
+                                         "cores": len(os.sched_getaffinity(0))}
+    p1 = wl.c1()
+    s1 = Setup(p1)
+    I = full.initial_intensity(s1)
+    t0 = time.perf_counter()
+    full.run(s1, p1["steps"], I=I)
+    dt = time.perf_counter() - t0
+    nang = p1["ntheta"] * p1["nphi"]
+    ns1 = p1["nx"] * p1["ny"]
+    out["full_grid_parity_case"] = {"steps_per_s": p1["steps"] / dt,
+                                    "angle_updates_per_s": ns1 * nang * p1["steps"] / dt,
+                                    "workload": "32x32 cells, 8x16 ordinates, 10 steps"}
+    return out
+
+
 def mixed_run(p, W, K, dt, hist, end64):
     """The FP32-mixed precision form on the same workload and protocol."""
     from paper_2503_18056_amd import TT_FP32_MIXED
@@ -382,6 +426,8 @@ def main():
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline (about 15 s)")
         out["cpu_baseline"] = cpu_baseline(p, warm_cores)
+        progress("more of the CPU oracle (one thread; thick 3-D first steps; full grid)")
+        out["cpu_oracle_extra"] = cpu_oracle_extra(p, warm_cores)
     print(json.dumps(out), flush=True)
 
 
