@@ -799,6 +799,10 @@ __global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves
   for (int pass = 0; pass * GR_WAVES * GR_TPW < ntask; ++pass) {
     int tI[GR_TPW], tJ[GR_TPW];
     bool act[GR_TPW];
+    // 16 x 16 blocks (a, b) of a task that hold entries: the second block
+    // row / column only when it starts below n, and not the lower-left block
+    // of a diagonal task (the transpose of its upper-right one)
+    bool ok01[GR_TPW], ok10[GR_TPW], ok11[GR_TPW];
     int ea[GR_TPW][2], eb[GR_TPW][2];
 #pragma unroll
     for (int q = 0; q < GR_TPW; ++q) {
@@ -806,6 +810,9 @@ __global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves
       act[q] = t < ntask;
       tI[q] = tJ[q] = 0;
       if (act[q]) gr_task(t, tI[q], tJ[q], T32);
+      ok01[q] = tJ[q] * 32 + 16 < n;
+      ok10[q] = tI[q] * 32 + 16 < n && tI[q] != tJ[q];
+      ok11[q] = tI[q] * 32 + 16 < n && tJ[q] * 32 + 16 < n;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int ca = tI[q] * 32 + 16 * h + col, cb = tJ[q] * 32 + 16 * h + col;
@@ -859,9 +866,9 @@ __global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves
           const T y0 = cb < n ? lds[r][cb] : T(0), y1 = cb + 16 < n ? lds[r][cb + 16] : T(0);
           if constexpr (sizeof(T) == 8) {
             acc[q][0][0] = mfma16(x0, y0, acc[q][0][0]);
-            acc[q][0][1] = mfma16(x0, y1, acc[q][0][1]);
-            acc[q][1][0] = mfma16(x1, y0, acc[q][1][0]);
-            acc[q][1][1] = mfma16(x1, y1, acc[q][1][1]);
+            if (ok01[q]) acc[q][0][1] = mfma16(x0, y1, acc[q][0][1]);
+            if (ok10[q]) acc[q][1][0] = mfma16(x1, y0, acc[q][1][0]);
+            if (ok11[q]) acc[q][1][1] = mfma16(x1, y1, acc[q][1][1]);
           } else {
             const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -870,6 +877,9 @@ __global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves
               split4(a == 0 ? x0 : x1, ea[q][a], xv);
 #pragma unroll
               for (int b = 0; b < 2; ++b) {
+                if ((a == 0 && b == 1 && !ok01[q]) || (a == 1 && b == 0 && !ok10[q]) ||
+                    (a == 1 && b == 1 && !ok11[q]))
+                  continue;
                 float yv[4];
                 split4(b == 0 ? y0 : y1, eb[q][b], yv);
                 const f32x4 g2 = mfma16f(xv[0], yv[0], z);
@@ -922,7 +932,8 @@ __global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves
 
 // G[a][b] = G[b][a] = sum over blocks of the partial tasks, in a fixed
 // order: four thread groups sum the blocks b = g (mod 4) for 64 elements,
-// then the four group sums are added in order.
+// then the four group sums are added in order (diagonal tasks from their
+// upper triangle).
 __global__ __launch_bounds__(256) void k_gram_rows_reduce(const double* __restrict__ partial,
                                                           int nblk, DimExpr ndim,
                                                           const int* __restrict__ dims,
@@ -944,7 +955,9 @@ __global__ __launch_bounds__(256) void k_gram_rows_reduce(const double* __restri
   const double v = ((part[0][el] + part[1][el]) + part[2][el]) + part[3][el];
   const int ii = e >> 5, jj = e & 31;
   const int i = ti * 32 + ii, j = tj * 32 + jj;
-  if (i >= n || j >= n) return;
+  // a diagonal tile's lower-left 16 x 16 block is not formed: its upper
+  // triangle gives both halves
+  if (i >= n || j >= n || (ti == tj && ii > jj)) return;
   G[(long long)i * ldg + j] = v;
   G[(long long)j * ldg + i] = v;
 }
