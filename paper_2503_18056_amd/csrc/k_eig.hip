@@ -47,10 +47,40 @@ __host__ __device__ inline int next_pow2(int n) {
   return p;
 }
 
+// Lane exchange inside rows of 16 lanes by DPP, on both halves of a double.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2);
+}
+__device__ inline double lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, returned on every lane, in a fixed
+// order: inside each row of 16 lanes, pairs (lane ^ 1), quads (lane ^ 2),
+// half rows (mirror of 8) and rows (mirror of 16), by DPP moves; then the four
+// row sums, read from lanes 0, 16, 32 and 48.  At every stage the lanes of a
+// row hold bitwise-equal sums (the two operands of each addition only swap),
+// so every lane returns the same value.  Call with the whole wavefront active.
+__device__ inline double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+
 // Deterministic block-wide sum (fixed combination order).
 template <int NT>
 __device__ double block_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = wave_sum(v);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
   if (lane == 0) red[wave] = v;
@@ -58,11 +88,6 @@ __device__ double block_sum(double v, double* red) {
   double s = 0.0;
   for (int i = 0; i < NT / 64; ++i) s += red[i];
   return s;
-}
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -361,11 +386,27 @@ __global__ __launch_bounds__(SYL_T) void k_sytrd_lds(EigJobs jobs, int* __restri
       for (int j = lane; j < m; j += 64) sw[j] -= hc * sv[j];
     }
     __syncthreads();
-    // A22 -= v w^T + w v^T on the lower triangle, a wavefront per row
-    for (int i = wave; i < m; i += SYL_T / 64) {
-      const double vi = sv[i], wi = sw[i];
-      double* row = Lp + tri(o + i, o);
-      for (int j = lane; j <= i; j += 64) row[j] -= vi * sw[j] + wi * sv[j];
+    // A22 -= v w^T + w v^T on the lower triangle, a wavefront per row; a lane
+    // always takes the columns lane + 64 c, so it holds their v and w in
+    // registers across the rows
+    {
+      constexpr int NCH = (SYTRD_LDS_MAX + 63) / 64;
+      double vr[NCH], wr[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int j = lane + 64 * c;
+        vr[c] = j < m ? sv[j] : 0.0;
+        wr[c] = j < m ? sw[j] : 0.0;
+      }
+      for (int i = wave; i < m; i += SYL_T / 64) {
+        const double vi = sv[i], wi = sw[i];
+        double* row = Lp + tri(o + i, o);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const int j = lane + 64 * c;
+          if (j <= i) row[j] -= vi * wr[c] + wi * vr[c];
+        }
+      }
     }
     __syncthreads();
   }
@@ -575,8 +616,14 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
   }
 }
 
-// Shared-memory bytes per merge element of k_dc_prep (4 doubles, 2 ints).
+// Shared-memory bytes per merge element of k_dc_prep (4 doubles, 2 ints)
+// and of k_dc_vectors (6 doubles and 4 ints with the permutation and the
+// rotations staged, up to VEC_STAGE_MAX rows; 4 doubles and 1 int above),
+// which also holds 32 KB of fixed arrays.
 constexpr int PREP_BYTES_PER = 4 * 8 + 2 * 4;
+constexpr int VEC_STAGE_MAX = 1024;
+constexpr int VEC_BYTES_STAGED = 6 * 8 + 4 * 4;
+constexpr int VEC_BYTES_GLOBAL = 4 * 8 + 1 * 4;
 
 // Sort of two ascending halves and deflation; one 256-thread block per
 // merge, the merge's arrays staged in LDS.  The halves are merged in
@@ -682,10 +729,14 @@ __global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__
         defl[sI] = 0;
         double dcur = dd[t], zcur = zz[t];
         if (p >= 0) {
-          const double r = hypot(zp, zcur);
-          const double c = zcur / r, sn = zp / r;
+          // |t c s| <= tol with c = z_cur / r, s = z_p / r, r^2 = z_p^2 + z_cur^2,
+          // tested without a square root or a division (the z are normalised
+          // and above tol / rho, so r^2 neither overflows nor underflows)
           const double tt = dcur - dp;
-          if (fabs(tt * c * sn) <= tol) {
+          const double r2 = zp * zp + zcur * zcur;
+          if (fabs(tt * zcur * zp) <= tol * r2) {
+            const double r = sqrt(r2);
+            const double c = zcur / r, sn = zp / r;
             D.rp[b0 + nrot] = p;
             D.rq[b0 + nrot] = sI;
             D.rc[b0 + nrot] = c;
@@ -900,8 +951,20 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
 // columns of the merge block) applied to its rows, and the slot-to-local
 // permutation P applied to its rows, so that the new eigenvector block is
 // the old block times W.  A thread owns whole columns of W, so the
-// rotations need no barrier.  The merge's K arrays (d, d at each root's
-// origin, tau, z^, slots) are staged in LDS.
+// rotations need no barrier.  Everything the per-column loops read (the K
+// arrays, the permutation, the rotations) is staged in LDS first, so they
+// wait on LDS only; merges of more than VEC_STAGE_MAX rows (the SVD's
+// Golub-Kahan order above 1024) read the permutation and the rotations from
+// global memory instead, to stay within the CU's LDS.
+//
+// The rotations are applied without reading W back.  Rotation t acts on
+// slots p_t < q_t, the q_t strictly increase with t and p_t >= q_{t-1}
+// (the deflation carries its last kept slot along).  Applied last first,
+// rotation t therefore meets slot p_t untouched (its U entry), and slot q_t
+// untouched or as the output of rotation t + 1 on its p side, carried in a
+// register; q_t is final after rotation t, and the carried slot is final
+// once the next rotation does not take it.
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restrict__ dims, int N, int S) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
@@ -920,47 +983,77 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   double* dro = d + S2;
   double* rt = dro + S2;
   double* zh = rt + S2;
-  int* ks = reinterpret_cast<int*>(zh + S2);
+  double* rcs_s = zh + S2;        // rotation cosines (staged)
+  double* rsn_s = rcs_s + S2;     // rotation sines (staged)
+  int* ks = reinterpret_cast<int*>(STAGE ? rsn_s + S2 : zh + S2);  // K index -> slot
+  int* pm_s = ks + S2;            // slot -> local row (staged)
+  int* rp_s = pm_s + S2;          // rotation t acts on slots rp[t] < rq[t] (staged)
+  int* rq_s = rp_s + S2;
+  const int* pm = STAGE ? pm_s : D.perm + b0;
+  const int* rp = STAGE ? rp_s : D.rp + b0;
+  const int* rq = STAGE ? rq_s : D.rq + b0;
+  const double* rcs = STAGE ? rcs_s : D.rc + b0;
+  const double* rsn = STAGE ? rsn_s : D.rs + b0;
+  __shared__ double sv[2048];
+  __shared__ int st[2048];
+  __shared__ int kix[2048];       // slot -> K index + 1, 0 for a deflated slot
+  __shared__ int wcnt[4];
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
   for (long long e = tid; e < (long long)m2 * S2; e += 256) Ub[e] = 0.0;
+  for (int c = tid; c < m2; c += 256) {
+    if (STAGE) pm_s[c] = D.perm[b0 + c];
+    kix[c] = 0;
+  }
   for (int j = tid; j < nk; j += 256) {
     d[j] = D.dK[b0 + j];
     rt[j] = D.rtau[b0 + j];
     ks[j] = D.Kslot[b0 + j];
   }
+  if (STAGE)
+    for (int t = tid; t < nrot; t += 256) {
+      rp_s[t] = D.rp[b0 + t];
+      rq_s[t] = D.rq[b0 + t];
+      rcs_s[t] = D.rc[b0 + t];
+      rsn_s[t] = D.rs[b0 + t];
+    }
   __syncthreads();
-  for (int j = tid; j < nk; j += 256) dro[j] = d[D.ro[b0 + j]];
+  for (int j = tid; j < nk; j += 256) {
+    dro[j] = d[D.ro[b0 + j]];
+    kix[ks[j]] = j + 1;
+  }
   __syncthreads();
   const double rho = D.mrho[m];
   for (int j = tid; j < nk; j += 256) {
     const double dj = d[j];
     double prod = -((dj - dro[j]) - rt[j]) / rho;
+#pragma unroll 4
     for (int i = 0; i < nk; ++i)
       if (i != j) prod *= ((dj - dro[i]) - rt[i]) / (dj - d[i]);
     zh[j] = copysign(sqrt(fmax(prod, 0.0)), D.zK[b0 + j]);
   }
-  // sort all outputs: roots (tag i) and deflated slots (tag m2 + slot)
-  __shared__ double sv[2048];
-  __shared__ int st[2048];
-  __shared__ int isk[2048];
-  for (int c = tid; c < m2; c += 256) isk[c] = 0;
-  __syncthreads();
-  for (int q = tid; q < nk; q += 256) isk[ks[q]] = 1;
-  __syncthreads();
-  // deflated slots in slot order: position among deflated = s - #K slots before s
-  __shared__ int s_bad;
-  if (tid == 0) {
-    int nd = 0;
-    s_bad = 0;
-    for (int c = 0; c < m2; ++c)
-      if (!isk[c]) {
-        const double v = D.dsl[b0 + c];
-        if (!(v == v)) s_bad = 1;
-        sv[nk + nd] = v == v ? v : DBL_MAX;
-        st[nk + nd] = m2 + c;
-        ++nd;
-      }
+  // sort all outputs: roots (tag i) and deflated slots (tag m2 + slot); the
+  // deflated slots enter in slot order, after the roots, by a block prefix
+  // count
+  int base = 0;
+  for (int c0 = 0; c0 < m2; c0 += 256) {
+    const int c = c0 + tid;
+    const int defl = c < m2 && kix[c] == 0;
+    const unsigned long long bal = __ballot(defl);
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) wcnt[wv] = __popcll(bal);
+    __syncthreads();
+    int off = base + __popcll(bal & ((1ULL << lane) - 1ULL));
+    for (int w = 0; w < wv; ++w) off += wcnt[w];
+    if (defl) {
+      const double v = D.dsl[b0 + c];
+      if (!(v == v)) s_bad = 1;
+      sv[nk + off] = v == v ? v : DBL_MAX;
+      st[nk + off] = m2 + c;
+    }
+    base += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
   }
-  __syncthreads();
   for (int i = tid; i < nk; i += 256) {
     const double v = dro[i] + rt[i];
     if (!(v == v)) s_bad = 1;
@@ -993,14 +1086,19 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   for (int pos = tid; pos < m2; pos += 256) {
     D.lam[b0 + pos] = sv[pos];
     const int tag = st[pos];
+    double* col = Ub + pos;
     if (tag < 0 || tag >= 2 * m2) {
       atomicOr(&dims[D_FLAG], FLAG_EIG);
-    } else if (tag >= m2) {
-      Ub[(size_t)D.perm[b0 + tag - m2] * S2 + pos] = 1.0;
-    } else {
-      const int i = tag;
-      const double di = dro[i], ti = rt[i];
+      continue;
+    }
+    const bool root = tag < m2;
+    const int dslot = root ? -1 : tag - m2;
+    double di = 0.0, ti = 0.0, inv = 0.0;
+    if (root) {
+      di = dro[tag];
+      ti = rt[tag];
       double nrm = 0.0;
+#pragma unroll 4
       for (int j = 0; j < nk; ++j) {
         const double u = zh[j] / ((d[j] - di) - ti);
         nrm += u * u;
@@ -1009,21 +1107,36 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
         atomicOr(&dims[D_FLAG], FLAG_EIG);
         continue;
       }
-      const double inv = 1.0 / sqrt(nrm);
-      for (int j = 0; j < nk; ++j) {
-        const double u = zh[j] / ((d[j] - di) - ti);
-        Ub[(size_t)D.perm[b0 + ks[j]] * S2 + pos] = u * inv;
-      }
+      inv = 1.0 / sqrt(nrm);
+#pragma unroll 4
+      for (int j = 0; j < nk; ++j) col[(size_t)pm[ks[j]] * S2] = zh[j] / ((d[j] - di) - ti) * inv;
+    } else {
+      col[(size_t)pm[dslot] * S2] = 1.0;
     }
-    // rows of the rotations in local order, the last rotation first
+    // U entry of this column at slot s, before any rotation
+    auto u0 = [&](int s) -> double {
+      if (!root) return s == dslot ? 1.0 : 0.0;
+      const int j = kix[s] - 1;
+      return j < 0 ? 0.0 : zh[j] / ((d[j] - di) - ti) * inv;
+    };
+    int crow = -1;
+    double cval = 0.0;
     for (int t = nrot - 1; t >= 0; --t) {
-      const size_t rp = (size_t)D.perm[b0 + D.rp[b0 + t]] * S2 + pos;
-      const size_t rq = (size_t)D.perm[b0 + D.rq[b0 + t]] * S2 + pos;
-      const double c = D.rc[b0 + t], sn = D.rs[b0 + t];
-      const double xp = Ub[rp], xq = Ub[rq];
-      Ub[rp] = c * xp + sn * xq;
-      Ub[rq] = c * xq - sn * xp;
+      const int p = rp[t], q = rq[t];
+      const double c = rcs[t], sn = rsn[t];
+      double xq;
+      if (q == crow) {
+        xq = cval;
+      } else {
+        if (crow >= 0) col[(size_t)pm[crow] * S2] = cval;
+        xq = u0(q);
+      }
+      const double xp = u0(p);
+      col[(size_t)pm[q] * S2] = c * xq - sn * xp;
+      crow = p;
+      cval = c * xp + sn * xq;
     }
+    if (crow >= 0) col[(size_t)pm[crow] * S2] = cval;
   }
 }
 
@@ -1035,15 +1148,18 @@ __device__ inline double keep_threshold(const EigJob& J, const double* w, int n)
 
 // ---------------------------------------------------------------------------
 // 3. Back-transformation V[:, n-1-j] = H_0 H_1 ... H_{n-3} q_j for the kept
-// eigenvectors q_j of T (columns of the D&C result), a wavefront per vector.
-// The reflectors are staged through LDS in chunks of ch (one cooperative
-// load per chunk), so the sequential loop over them reads only LDS.
+// eigenvectors q_j of T (columns of the D&C result), a wavefront per vector,
+// the vector in registers (lane l holds rows l + 64 c, c < NCH).  The
+// reflectors are staged through LDS in chunks of ch (one cooperative load
+// per chunk), so the sequential loop over them reads only LDS; a chunk is
+// sized so that two blocks fit one CU.
 constexpr int ORM_CH = 32;
 __host__ __device__ inline int ormtr_chunk(int N) {
-  const int c = 12288 / (N > 0 ? N : 1);
+  const int c = 9600 / (N > 0 ? N : 1);
   return c < 1 ? 1 : (c > ORM_CH ? ORM_CH : c);
 }
 
+template <int NCH>
 __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N,
                                                int par) {
   const EigJob J = jobs.j[blockIdx.y];
@@ -1059,12 +1175,14 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   // eigenvalues ascend, so the block's last vector is its largest
   if (!(D.lam[min(j0 + 3, n - 1)] > thr)) return;
   const bool active = j < n && D.lam[j] > thr;
-  __shared__ double ys[4][1024];
   extern __shared__ double hs[];  // ch reflectors of length N, then their tau
   double* ts = hs + (size_t)ch * N;
-  double* y = ys[wave];
-  if (active)
-    for (int i = lane; i < n; i += 64) y[i] = (par ? D.Qb : D.Qa)[(size_t)i * N2 + j];
+  double y[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int i = lane + 64 * c;
+    y[c] = active && i < n ? (par ? D.Qb : D.Qa)[(size_t)i * N2 + j] : 0.0;
+  }
   for (int k1 = n - 3; k1 >= 0; k1 -= ch) {
     const int k0 = max(0, k1 - ch + 1);
     __syncthreads();
@@ -1081,14 +1199,26 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
       if (tau == 0.0) continue;
       const double* v = hs + (size_t)(k - k0) * N;
       double part = 0.0;
-      for (int i = k + 1 + lane; i < n; i += 64) part += v[i] * y[i];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int i = lane + 64 * c;
+        if (64 * c + 63 > k && i > k && i < n) part += v[i] * y[c];
+      }
       const double dot = wave_sum(part) * tau;
-      for (int i = k + 1 + lane; i < n; i += 64) y[i] -= dot * v[i];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int i = lane + 64 * c;
+        if (64 * c + 63 > k && i > k && i < n) y[c] -= dot * v[i];
+      }
     }
   }
   if (!active) return;
   const int col = n - 1 - j;
-  for (int i = lane; i < n; i += 64) J.V[(size_t)i * J.ldv + col] = y[i];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int i = lane + 64 * c;
+    if (i < n) J.V[(size_t)i * J.ldv + col] = y[c];
+  }
 }
 
 // Sign gauge of columns c < ncol of V (rows < nrow): the largest-magnitude
@@ -1712,7 +1842,10 @@ int dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims,
     const int nm = (N + 2 * S - 1) / (2 * S);
     k_dc_prep<<<dim3(nm, njobs), 256, (size_t)2 * S * PREP_BYTES_PER, s>>>(J, dims, N, S, par);
     k_dc_secular<<<dim3((2 * S + 3) / 4, nm, njobs), 256, (size_t)2 * S * 16, s>>>(J, dims, N, S);
-    k_dc_vectors<<<dim3(nm, njobs), 256, (size_t)2 * S * 36, s>>>(J, dims, N, S);
+    if (2 * S <= VEC_STAGE_MAX)
+      k_dc_vectors<true><<<dim3(nm, njobs), 256, (size_t)2 * S * VEC_BYTES_STAGED, s>>>(J, dims, N, S);
+    else
+      k_dc_vectors<false><<<dim3(nm, njobs), 256, (size_t)2 * S * VEC_BYTES_GLOBAL, s>>>(J, dims, N, S);
     {
       // new block <- old block * W, for every merge block of this level of
       // every job (one launch)
@@ -1763,8 +1896,14 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
     k_sytrd_grid<<<dim3(SYTRD_GRID_P, nj), SYTRD_GRID_T, sytrd_grid_lds(N), s>>>(J, dims, N);
   }
   const int par = dc_levels(jobs, J, njobs, N, dims, s);
-  k_ormtr<<<dim3((N + 3) / 4, njobs), 256, ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8, s>>>(
-      J, dims, N, par);
+  {
+    const dim3 g((N + 3) / 4, njobs);
+    const size_t lds = ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8;
+    if (N <= 192) k_ormtr<3><<<g, 256, lds, s>>>(J, dims, N, par);
+    else if (N <= 384) k_ormtr<6><<<g, 256, lds, s>>>(J, dims, N, par);
+    else if (N <= 640) k_ormtr<10><<<g, 256, lds, s>>>(J, dims, N, par);
+    else k_ormtr<16><<<g, 256, lds, s>>>(J, dims, N, par);
+  }
   k_eig_final<<<dim3((N + FINAL_COLS - 1) / FINAL_COLS, njobs), 256, 0, s>>>(J, dims, N);
 }
 
