@@ -482,7 +482,11 @@ __global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__
 // rotations of a round applied together), its eigenvalues sorted ascending
 // with their vectors, and written where the merges up to blocks of 32
 // would have left them: lam[block] and the diagonal block of Q.  One
-// wavefront per leaf.
+// wavefront per leaf, a lane per entry: with R the round's rotations
+// (R[a][a] = R[b][b] = c, R[a][b] = -s, R[b][a] = s on each pair a < b), a
+// round forms A' = R A R^T and V' = V R^T entry by entry into a second
+// buffer, each entry from the two coefficients of its row's and its
+// column's pair, so a round is one pass between two barriers.
 constexpr int DC_LEAF = 8;
 constexpr int LEAF_T = 64;  // one wavefront per leaf: its barriers cost next to nothing
 
@@ -496,110 +500,97 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
   if (r0 >= n) return;
   const int nb = min(DC_LEAF, n - r0);
   const int nbe = nb + (nb & 1);  // even count for the pairing (a decoupled pad)
-  __shared__ double A[DC_LEAF][DC_LEAF + 1], V[DC_LEAF][DC_LEAF + 1];
-  __shared__ double rc_[DC_LEAF / 2], rs_[DC_LEAF / 2];
-  __shared__ int rp_[DC_LEAF / 2], rq_[DC_LEAF / 2];
-  __shared__ int s_rot, s_ord[DC_LEAF];
-  __shared__ double s_scale;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < DC_LEAF * DC_LEAF; e += LEAF_T) {
-    const int i = e / DC_LEAF, j = e % DC_LEAF;
-    double a = 0.0;
-    if (i < nb && j < nb) {
-      const int gi = r0 + i, gj = r0 + j;
-      if (i == j) {
-        a = W.d[gi];
-        if (i == 0 && gi > 0) a -= fabs(W.e[gi - 1]);
-        if (i == nb - 1 && gi + 1 < n) a -= fabs(W.e[gi]);
-      } else if (j == i + 1) {
-        a = W.e[gi];
-      } else if (i == j + 1) {
-        a = W.e[gj];
-      }
+  __shared__ double A[2][DC_LEAF][DC_LEAF + 1], V[2][DC_LEAF][DC_LEAF + 1];
+  __shared__ double s_al[DC_LEAF], s_be[DC_LEAF];  // index i: row i of R is al_i e_i + be_i e_pi(i)
+  __shared__ int s_pi[DC_LEAF];
+  __shared__ int s_ord[DC_LEAF];
+  const int tid = threadIdx.x, ti = tid / DC_LEAF, tj = tid % DC_LEAF;
+  double a0 = 0.0;
+  if (ti < nb && tj < nb) {
+    const int gi = r0 + ti, gj = r0 + tj;
+    if (ti == tj) {
+      a0 = W.d[gi];
+      if (ti == 0 && gi > 0) a0 -= fabs(W.e[gi - 1]);
+      if (ti == nb - 1 && gi + 1 < n) a0 -= fabs(W.e[gi]);
+    } else if (tj == ti + 1) {
+      a0 = W.e[gi];
+    } else if (ti == tj + 1) {
+      a0 = W.e[gj];
     }
-    A[i][j] = a;
-    V[i][j] = i == j ? 1.0 : 0.0;
   }
-  __syncthreads();
-  if (tid == 0) {
-    double f = 0.0;
-    for (int i = 0; i < nb; ++i)
-      for (int j = 0; j < nb; ++j) f += A[i][j] * A[i][j];
-    s_scale = sqrt(f);
+  A[0][ti][tj] = a0;
+  V[0][ti][tj] = ti == tj ? 1.0 : 0.0;
+  if (tid < DC_LEAF) {
+    s_al[tid] = 1.0;
+    s_be[tid] = 0.0;
+    s_pi[tid] = tid;
   }
+  const double tiny = U64 * sqrt(wave_sum(a0 * a0));
   __syncthreads();
-  const double tiny = U64 * s_scale;
-  const int npair = nbe / 2;
+  const int npair = nbe / 2, m1 = nbe - 1;
+  int cur = 0;
   for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    for (int round = 0; round < nbe - 1; ++round) {
+    int rot = 0;
+    for (int round = 0; round < m1; ++round) {
       // round-robin: position 0 fixed, the others rotate
       if (tid < npair) {
         const int k = tid;
-        int a = k == 0 ? 0 : 1 + (k - 1 + round) % (nbe - 1);
-        int b = 1 + (nbe - 2 - k + round) % (nbe - 1);
+        int xa = k - 1 + round, xb = nbe - 2 - k + round;
+        if (xa >= m1) xa -= m1;
+        if (xb >= m1) xb -= m1;
+        int a = k == 0 ? 0 : 1 + xa, b = 1 + xb;
         if (a > b) { const int t = a; a = b; b = t; }
         double c = 1.0, sn = 0.0;
         if (b < nb) {
-          const double apq = A[a][b], app = A[a][a], aqq = A[b][b];
+          const double apq = A[cur][a][b], app = A[cur][a][a], aqq = A[cur][b][b];
+          // tan(theta) = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = a_qq - a_pp,
+          // e = 2 a_pq; then c = D / q, s = sign(d) e / q with D = |d| + r,
+          // q = sqrt(D^2 + e^2): two square roots and one division, on d and e
+          // scaled by a power of two (exact; c and s do not change)
+          const double dd = aqq - app, ee = 2.0 * apq;
+          const int ex = ilogb(fmax(fabs(dd), fabs(ee)));
+          const double ds = ldexp(dd, -ex), es = ldexp(ee, -ex);
+          const double r = sqrt(ds * ds + es * es);
+          const double Dq = fabs(ds) + r;
+          const double inv = 1.0 / sqrt(Dq * Dq + es * es);
           // absolute threshold: the merges above deflate at 8 u ||T|| anyway, and a
           // relative one would chase rounding noise next to near-zero diagonals
-          if (fabs(apq) > fmax(U64 * sqrt(fabs(app) * fabs(aqq)), 0.125 * tiny) && apq != 0.0) {
-            const double th = (aqq - app) / (2.0 * apq);
-            const double t = copysign(1.0, th) / (fabs(th) + sqrt(1.0 + th * th));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-            s_rot = 1;
+          if (apq != 0.0 && fabs(apq) > 0.125 * tiny && fabs(apq) > U64 * sqrt(fabs(app) * fabs(aqq))) {
+            c = Dq * inv;
+            sn = (dd < 0.0 ? -es : es) * inv;
+            rot = 1;
           }
         }
-        rp_[k] = a;
-        rq_[k] = b;
-        rc_[k] = c;
-        rs_[k] = sn;
+        s_al[a] = c;
+        s_be[a] = -sn;
+        s_pi[a] = b;
+        s_al[b] = c;
+        s_be[b] = sn;
+        s_pi[b] = a;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = tid; e < npair * DC_LEAF; e += LEAF_T) {
-        const int k = e / DC_LEAF, j = e % DC_LEAF;
-        const int a = rp_[k], b = rq_[k];
-        if (b < nb && rs_[k] != 0.0) {
-          const double c = rc_[k], sn = rs_[k];
-          const double x = A[a][j], y = A[b][j];
-          A[a][j] = c * x - sn * y;
-          A[b][j] = sn * x + c * y;
-        }
+      {
+        const double ai = s_al[ti], bi = s_be[ti], aj = s_al[tj], bj = s_be[tj];
+        const int pi = s_pi[ti], pj = s_pi[tj];
+        const double x00 = A[cur][ti][tj], x01 = A[cur][ti][pj];
+        const double x10 = A[cur][pi][tj], x11 = A[cur][pi][pj];
+        A[cur ^ 1][ti][tj] = ai * (aj * x00 + bj * x01) + bi * (aj * x10 + bj * x11);
+        V[cur ^ 1][ti][tj] = aj * V[cur][ti][tj] + bj * V[cur][ti][pj];
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = tid; e < npair * DC_LEAF; e += LEAF_T) {
-        const int k = e / DC_LEAF, i = e % DC_LEAF;
-        const int a = rp_[k], b = rq_[k];
-        if (b < nb && rs_[k] != 0.0) {
-          const double c = rc_[k], sn = rs_[k];
-          const double x = A[i][a], y = A[i][b];
-          A[i][a] = c * x - sn * y;
-          A[i][b] = sn * x + c * y;
-          const double vx = V[i][a], vy = V[i][b];
-          V[i][a] = c * vx - sn * vy;
-          V[i][b] = sn * vx + c * vy;
-        }
-      }
+      cur ^= 1;
       __syncthreads();
     }
-    const int any = s_rot;
-    __syncthreads();
-    if (!any) break;
+    if (!__any(rot)) break;
   }
   // ascending order of the eigenvalues (stable: index breaks ties); the
   // identity first, so a NaN (flagged below) cannot leave a slot unset
   if (tid < DC_LEAF) s_ord[tid] = tid < nb ? tid : 0;
   __syncthreads();
   if (tid < nb) {
-    const double v = A[tid][tid];
+    const double v = A[cur][tid][tid];
     int pos = 0;
     for (int j = 0; j < nb; ++j) {
-      const double w = A[j][j];
+      const double w = A[cur][j][j];
       pos += (w < v) || (w == v && j < tid);
     }
     s_ord[pos] = tid;
@@ -607,10 +598,10 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
   __syncthreads();
   for (int e = tid; e < nb * nb; e += LEAF_T) {
     const int i = e / nb, c = e % nb;
-    D.Qa[(size_t)(r0 + i) * N2 + r0 + c] = V[i][s_ord[c]];
+    D.Qa[(size_t)(r0 + i) * N2 + r0 + c] = V[cur][i][s_ord[c]];
   }
   if (tid < nb) {
-    const double v = A[s_ord[tid]][s_ord[tid]];
+    const double v = A[cur][s_ord[tid]][s_ord[tid]];
     if (!(v == v)) atomicOr(&dims[D_FLAG], FLAG_EIG);
     D.lam[r0 + tid] = v;
   }
