@@ -727,7 +727,8 @@ __global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__
           const double r2 = zp * zp + zcur * zcur;
           if (fabs(tt * zcur * zp) <= tol * r2) {
             const double r = sqrt(r2);
-            const double c = zcur / r, sn = zp / r;
+            const double ir = 1.0 / r;
+            const double c = zcur * ir, sn = zp * ir;
             D.rp[b0 + nrot] = p;
             D.rq[b0 + nrot] = sI;
             D.rc[b0 + nrot] = c;
@@ -805,7 +806,11 @@ __device__ inline double secular(const double* d, const double* z2, int k, int o
 // (1978): the terms left of the root, psi, and right of it, phi, are each
 // replaced by a / (delta - tau) + b matching value and slope at the current
 // iterate at their nearest pole; the model's root in the bracket is the
-// next iterate (bisection when it falls outside).  Stops when |f| is at the
+// next iterate (bisection when it falls outside).  When an iteration leaves
+// f's sign unchanged and reduces |f| by less than 10x, the next step swaps to
+// the fixed-weight model (exact weight on the origin pole, fitted weight on
+// the other neighbour), and back, as LAPACK's dlaed4 does between its
+// middle-way and fixed-weight steps (Li, 1993).  Stops when |f| is at the
 // level of its evaluation error, 8u (1 + rho sum |terms|), or at a relative
 // change of 2u.
 __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restrict__ dims, int N, int S) {
@@ -873,6 +878,8 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
   }
   double x = (lo > 0.0 && hi > 4.0 * lo) ? sqrt(lo) * sqrt(hi)
            : (hi < 0.0 && lo < 4.0 * hi) ? -sqrt(-lo) * sqrt(-hi) : 0.5 * (lo + hi);
+  bool fw = false;
+  double fprev = 0.0;
   for (int it = 0; it < 100 && !done; ++it) {
     // psi, psi', phi, phi' at x
     double ps = 0.0, dps = 0.0, ph = 0.0, dph = 0.0;
@@ -892,13 +899,32 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
     if (f < 0.0) lo = x;
     else hi = x;
     if (hi - lo <= 4.0 * U64 * fmax(fabs(lo), fabs(hi))) { tau = 0.5 * (lo + hi); break; }
+    // when f keeps its sign and falls by less than a factor of 10, the
+    // other model takes the next step
+    if (it > 0 && f * fprev > 0.0 && fabs(f) > 0.1 * fabs(fprev)) fw = !fw;
+    fprev = f;
     // model: a0 + al / (pl - t) + ga / (pr - t) = 0
-    const double al = rho * dps * (pl - x) * (pl - x);
-    double a0 = 1.0 + rho * (ps - dps * (pl - x));
     double xn;
     if (has_right) {
-      const double ga = rho * dph * (pr - x) * (pr - x);
-      a0 += rho * (ph - dph * (pr - x));
+      double al, ga, a0;
+      if (fw) {
+        // fixed weight: the origin pole keeps its exact weight rho z_o^2; the
+        // other neighbouring pole's weight and the constant match f and f'
+        // at x.  It converges where the two-pole fit above does not: a root
+        // next to a pole of tiny weight, beside a heavy pole one step away.
+        const double fp = rho * (dps + dph);
+        const double po = o == i ? pl : pr, pq = o == i ? pr : pl;
+        const double wo = rho * z2[o];
+        const double wq = (fp - wo / ((po - x) * (po - x))) * (pq - x) * (pq - x);
+        a0 = f - wo / (po - x) - wq / (pq - x);
+        al = o == i ? wo : wq;
+        ga = o == i ? wq : wo;
+      } else {
+        al = rho * dps * (pl - x) * (pl - x);
+        a0 = 1.0 + rho * (ps - dps * (pl - x));
+        ga = rho * dph * (pr - x) * (pr - x);
+        a0 += rho * (ph - dph * (pr - x));
+      }
       // a0 t^2 - b t + c = 0
       const double b = a0 * (pl + pr) + al + ga;
       const double c = a0 * pl * pr + al * pr + ga * pl;
@@ -914,6 +940,8 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
       }
     } else {
       // a0 + al / (pl - t) = 0  ->  t = pl + al / a0 (phi is empty)
+      const double al = rho * dps * (pl - x) * (pl - x);
+      double a0 = 1.0 + rho * (ps - dps * (pl - x));
       a0 += rho * ph;
       xn = a0 != 0.0 ? pl + al / a0 : NAN;
     }
