@@ -21,7 +21,40 @@ template <> struct GrShape<float> { static constexpr int WAVES = 8, TPW = 2; };
 
 
 // ---------------------------------------------------------------------------
-// Generic GEMM (vector FP64, 64x64 tiles, 16-deep K slabs staged in LDS).
+// One K slab of the generic GEMM's operands into registers (NL values of A
+// and of B per thread), zero outside the matrices.
+template <int TA, int TB, int GK, int NL>
+__device__ __forceinline__ void gemm_slab_load(double (&ra)[NL], double (&rb)[NL], const double* A,
+                                               const double* B, int lda, int ldb,
+                                               const double* kscale, int i0, int j0, int m, int n,
+                                               int k, int l0, int tid) {
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + 256 * q;
+    int i, l;
+    if (TA == 0) { i = e / GK; l = e % GK; } else { l = e >> 6; i = e & 63; }
+    const int gi = i0 + i, gl = l0 + l;
+    double v = 0.0;
+    if (gi < m && gl < k) {
+      v = TA == 0 ? A[(long long)gi * lda + gl] : A[(long long)gl * lda + gi];
+      if (kscale) v *= kscale[gl];
+    }
+    ra[q] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + 256 * q;
+    int j, l;
+    if (TB == 0) { l = e >> 6; j = e & 63; } else { j = e / GK; l = e % GK; }
+    const int gj = j0 + j, gl = l0 + l;
+    double v = 0.0;
+    if (gj < n && gl < k) v = TB == 0 ? B[(long long)gl * ldb + gj] : B[(long long)gj * ldb + gl];
+    rb[q] = v;
+  }
+}
+
+// Generic GEMM (vector FP64, 64x64 tiles, 32-deep K slabs staged in LDS,
+// the next slab prefetched into registers).
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict__ dims) {
   if (g.cond_idx >= 0 && dims[g.cond_idx] != g.cond_val) return;
@@ -59,40 +92,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
     B = Bb + (TB == 0 ? k0 * g.ldb : k0);
     if (kscale) kscale += k0;
   }
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  // 32-deep K slabs through LDS; the next slab's global loads are issued
+  // into registers before the current slab's FMAs, so their latency is
+  // covered by the compute
+  constexpr int GK = 32, NL = GK * 64 / 256;
+  __shared__ double As[GK][65];
+  __shared__ double Bs[GK][65];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-  for (int l0 = 0; l0 < k; l0 += 16) {
+  double ra[NL], rb[NL];
+  gemm_slab_load<TA, TB, GK, NL>(ra, rb, A, B, g.lda, g.ldb, kscale, i0, j0, m, n, k, 0, tid);
+  for (int l0 = 0; l0 < k; l0 += GK) {
 #pragma unroll
-    for (int e = tid; e < 1024; e += 256) {
-      int i, l;
-      if (TA == 0) { i = e >> 4; l = e & 15; } else { l = e >> 6; i = e & 63; }
-      const int gi = i0 + i, gl = l0 + l;
-      double v = 0.0;
-      if (gi < m && gl < k) {
-        v = TA == 0 ? A[(long long)gi * g.lda + gl] : A[(long long)gl * g.lda + gi];
-        if (kscale) v *= kscale[gl];
-      }
-      As[l][i] = v;
-    }
-#pragma unroll
-    for (int e = tid; e < 1024; e += 256) {
-      int j, l;
-      if (TB == 0) { l = e >> 6; j = e & 63; } else { j = e >> 4; l = e & 15; }
-      const int gj = j0 + j, gl = l0 + l;
-      double v = 0.0;
-      if (gj < n && gl < k)
-        v = TB == 0 ? B[(long long)gl * g.ldb + gj] : B[(long long)gj * g.ldb + gl];
-      Bs[l][j] = v;
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + 256 * q;
+      if (TA == 0) As[e % GK][e / GK] = ra[q];
+      else As[e >> 6][e & 63] = ra[q];
+      if (TB == 0) Bs[e >> 6][e & 63] = rb[q];
+      else Bs[e % GK][e / GK] = rb[q];
     }
     __syncthreads();
+    if (l0 + GK < k)
+      gemm_slab_load<TA, TB, GK, NL>(ra, rb, A, B, g.lda, g.ldb, kscale, i0, j0, m, n, k, l0 + GK, tid);
 #pragma unroll 4
-    for (int l = 0; l < 16; ++l) {
+    for (int l = 0; l < GK; ++l) {
       double a[4], b[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) a[r] = As[l][ty + 16 * r];
