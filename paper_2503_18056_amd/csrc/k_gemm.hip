@@ -406,52 +406,7 @@ void gram_tall(const GramPlan& p, const double* A, DimExpr n, double* partial, d
 }
 
 // ---------------------------------------------------------------------------
-// Tall GEMM C[K x n] = A[K x k] B[k x n] on MFMA; 64x64 output tile per
-// block, 32x32 per wave.
-__global__ __launch_bounds__(256) void k_gemm_tall(int K, const double* __restrict__ A, int lda,
-                                                   const double* __restrict__ B, int ldb,
-                                                   double* __restrict__ C, int ldc,
-                                                   DimExpr kdim, DimExpr ndim,
-                                                   const int* __restrict__ dims) {
-  const int kk = eval_dim(dims, kdim), n = eval_dim(dims, ndim);
-  const int j0b = blockIdx.x * 64, i0b = blockIdx.y * 64;
-  if (j0b >= n) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i0 = i0b + (wave >> 1) * 32, j0 = j0b + (wave & 1) * 32;
-  const int l16 = lane & 15, l4 = lane >> 4;
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int ra0 = i0 + l16, ra1 = i0 + 16 + l16;
-  const bool vra0 = ra0 < K, vra1 = ra1 < K;
-  const bool vc0 = j0 + l16 < n, vc1 = j0 + 16 + l16 < n;
-  for (int k0 = 0; k0 < kk; k0 += 4) {
-    const int kq = k0 + l4;
-    const bool vk = kq < kk;
-    const double x0 = (vk && vra0) ? A[(long long)ra0 * lda + kq] : 0.0;
-    const double x1 = (vk && vra1) ? A[(long long)ra1 * lda + kq] : 0.0;
-    const double y0 = (vk && vc0) ? B[(long long)kq * ldb + j0 + l16] : 0.0;
-    const double y1 = (vk && vc1) ? B[(long long)kq * ldb + j0 + 16 + l16] : 0.0;
-    acc[0][0] = mfma16(x0, y0, acc[0][0]);
-    acc[0][1] = mfma16(x0, y1, acc[0][1]);
-    acc[1][0] = mfma16(x1, y0, acc[1][0]);
-    acc[1][1] = mfma16(x1, y1, acc[1][1]);
-  }
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + 16 * p + l4 + 4 * r;
-        const int j = j0 + 16 * q + l16;
-        if (i < K && j < n) C[(long long)i * ldc + j] = acc[p][q][r];
-      }
-}
-
-// Tall GEMM for wide outputs (ncap > 64): 128 x 128 output tile per block
+// Tall GEMM C[K x n] = A[K x k] B[k x n] on MFMA: 128 x 128 output tile per block
 // (a 128-row panel of A times all of B's columns when n <= 128, so A streams
 // from HBM once), each wave a 64 x 64 quarter of sixteen 16 x 16
 // accumulators.  A panels (128 rows x 16 k) and B chunks (16 k x 128 cols)
@@ -1012,13 +967,8 @@ void gemm_tall_f32(int K, const float* A, int lda, const double* B, int ldb, flo
 void gemm_tall(int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
                DimExpr kdim, DimExpr ndim, int kcap, int ncap, const int* dims, hipStream_t s) {
   (void)kcap;
-  if (ncap > 64) {
-    k_gemm_panel<<<dim3((K + 127) / 128, (ncap + 127) / 128), 256, 0, s>>>(K, A, lda, B, ldb, C, ldc,
-                                                                           kdim, ndim, dims);
-    return;
-  }
-  dim3 grid((ncap + 63) / 64, (K + 63) / 64);
-  k_gemm_tall<<<grid, 256, 0, s>>>(K, A, lda, B, ldb, C, ldc, kdim, ndim, dims);
+  k_gemm_panel<<<dim3((K + 127) / 128, (ncap + 127) / 128), 256, 0, s>>>(K, A, lda, B, ldb, C, ldc,
+                                                                         kdim, ndim, dims);
 }
 
 }  // namespace tt

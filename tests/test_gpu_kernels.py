@@ -54,7 +54,8 @@ def test_gemm(env, ta, tb, m, n, k):
     assert np.allclose(got, ref, rtol=1e-13, atol=1e-13 * max(1.0, np.abs(ref).max(initial=0)))
 
 
-@pytest.mark.parametrize("K,k,n", [(16, 4, 16), (1, 1, 1), (37, 5, 3), (1000, 33, 64), (4097, 130, 70),
+@pytest.mark.parametrize("K,k,n", [(16, 4, 16), (1, 1, 1), (37, 5, 3), (1000, 33, 64), (65536, 137, 27),
+                                   (5003, 323, 64), (130, 200, 1), (4097, 130, 70),
                                    (20000, 897, 128), (5000, 641, 128), (3001, 400, 200), (129, 17, 65)])
 def test_gemm_tall(env, K, k, n):
     lib, torch = env
