@@ -19,7 +19,7 @@ coupled material, rank cap 128; concatenated ranks up to 897) in both
 precisions, after its ranks have ramped to the cap, under "thick_3d".
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
-this build runs on one GPU.
+the hot path runs on one GPU.
 """
 import argparse
 import json
@@ -335,8 +335,8 @@ def main():
                          "warmup (a known-size kernel to scale hardware byte counters by)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs the "
-              "hot path on one GPU (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported; the hot path runs on one GPU "
+              "(sharding by spatial rows of X is designed, not built)", file=sys.stderr)
         sys.exit(2)
     import workloads as wl
     from paper_2503_18056_amd import TT_FP64

@@ -55,7 +55,7 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
   if (!(c->dt > 0) && !(c->cfl > 0)) { why = "need dt > 0 or cfl > 0"; return false; }
   if (!(c->tol >= 0)) { why = "tol must be >= 0"; return false; }
   if (c->precision != TT_FP64 && c->precision != TT_FP32_MIXED) { why = "bad precision"; return false; }
-  if (c->schedule != TT_ROUND_ONCE) { why = "only TT_ROUND_ONCE is available in this build"; return false; }
+  if (c->schedule != TT_ROUND_ONCE) { why = "only TT_ROUND_ONCE is implemented"; return false; }
   if (c->material != TT_MAT_FROZEN && c->material != TT_MAT_COUPLED) { why = "bad material"; return false; }
   if (c->rank_mode != TT_RANK_AUTO && c->rank_mode != TT_RANK_REPLAY) { why = "bad rank_mode"; return false; }
   for (int a = 0; a < c->dim; ++a) {
