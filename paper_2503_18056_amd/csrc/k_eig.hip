@@ -1867,24 +1867,25 @@ int dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims,
       k_dc_vectors<false><<<dim3(nm, njobs), 256, (size_t)2 * S * VEC_BYTES_GLOBAL, s>>>(J, dims, N, S);
     {
       // new block <- old block * W, for every merge block of this level of
-      // every job (one launch)
+      // every job (one launch).  The old block is block diagonal (the two
+      // solved halves), so each merge is two products: the left S x S block
+      // times rows [0, S) of W and the right block times rows [S, 2S), each
+      // giving all columns of its rows of the new block.
       const int bm = (N + 2 * S - 1) / (2 * S);
       GemmDesc g;
       memset(&g, 0, sizeof(g));
       g.lda = N2; g.ldb = 2 * S; g.ldc = N2;
-      g.sA = (long long)2 * S * (N2 + 1);
-      g.sB = (long long)4 * S * S;
-      g.sC = g.sA;
-      g.m = dimc(2 * S); g.n = dimc(2 * S); g.k = dimc(2 * S);
+      g.sA = (long long)S * (N2 + 1);
+      g.sB = (long long)2 * S * S;
+      g.sC = (long long)S * N2;
+      g.sC2 = 2 * S;
+      g.halves = S;
+      g.m = dimc(S); g.n = dimc(2 * S); g.k = dimc(S);
       g.alpha = 1.0;
       g.cond_idx = -1;
-      // block z holds rows/cols [z 2S, z 2S + min(2S, n - z 2S)); it has a
-      // merge only when n - z 2S > S
       g.bclip_idx = -1;
-      g.bclip_mul = 2 * S;
-      g.bclip_min = S;
       g.njob = njobs;
-      g.zper = bm;
+      g.zper = 2 * bm;
       for (int q = 0; q < njobs; ++q) {
         const double* wbase = jobs[q].work;
         const size_t off_z = 4 * (size_t)N + (size_t)N * N;
@@ -1896,7 +1897,7 @@ int dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims,
         g.Cj[q] = const_cast<double*>(par ? Qa : Qb);
         g.bclipj[q] = jobs[q].n_idx;
       }
-      gemm(g, 2 * S, 2 * S, njobs * bm, dims, s);
+      gemm(g, S, 2 * S, njobs * 2 * bm, dims, s);
     }
   }
   return par;

@@ -72,7 +72,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
     bidx = g.bclipj[jb];
   }
   int m = eval_dim(dims, g.m), n = eval_dim(dims, g.n), k = eval_dim(dims, g.k);
-  if (bidx >= 0) {
+  long long coff = (long long)z * g.sC;
+  if (g.halves > 0) {
+    const int S = g.halves, mg = z >> 1, h = z & 1;
+    const int lim = (bidx >= 0 ? dims[bidx] : m) - mg * 2 * S;
+    if (lim <= S) return;
+    n = min(2 * S, lim);
+    m = k = h == 0 ? S : min(S, lim - S);
+    coff += (long long)mg * g.sC2;
+  } else if (bidx >= 0) {
     const int lim = dims[bidx] - z * g.bclip_mul;
     if (lim <= g.bclip_min) return;
     m = min(m, lim);
@@ -83,7 +91,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
   if (i0 >= m || j0 >= n) return;
   const double* A = Ab + (long long)z * g.sA;
   const double* B = Bb + (long long)z * g.sB;
-  double* C = Cb + (long long)z * g.sC;
+  double* C = Cb + coff;
   const double* kscale = g.kscale;
   if (g.ksplit > 0) {
     const long long k0 = (long long)z * g.ksplit;
