@@ -333,6 +333,7 @@ __global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restri
     const int i = ti * GW_T + ii, j = tj * GW_T + jj;
     if (i >= n || j >= n || (ti == tj && ii > jj)) continue;
     double sum = 0.0;
+#pragma unroll 8
     for (int sl = 0; sl < slices; ++sl)
       sum += partial[((long long)sl * pairs + pair) * (GW_T * GW_T) + e];
     G[(long long)i * ldg + j] = sum;
@@ -937,7 +938,9 @@ __global__ __launch_bounds__(256) void k_gram_rows_reduce(const double* __restri
   __shared__ double part[4][64];
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + el;
+  // unrolled so that eight partial loads are in flight; the sum keeps its order
   double s = 0.0;
+#pragma unroll 8
   for (int b = g; b < nblk; b += 4) s += partial[((long long)b * ntask + t) * 1024 + e];
   part[g][el] = s;
   __syncthreads();
