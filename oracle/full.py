@@ -2,12 +2,18 @@
 
 The intensity is a dense array I[nz, ny, nx, N_theta, N_phi].
 
-Transport (Sec. 3.1, eq. lhs with the upwind flux of eq. upwind, applied per
-axis in multi-D):
-    I*_i = I_i - sum_a lam_a [ n_a^+ (I_i - I_{i-e_a}) + n_a^- (I_{i+e_a} - I_i) ],
+Transport (Sec. 3.1, eq. lhs, applied per axis in multi-D), with the
+interface flux of the workload:
+  upwind (eq. upwind): F_{i+1/2} = c n I_i if n >= 0, else c n I_{i+1}, so
+    I*_i = I_i - sum_a lam_a [ n_a^+ (I_i - I_{i-e_a}) + n_a^- (I_{i+e_a} - I_i) ];
+  Rusanov (eq. rusanov_flux_toro): F_{i+1/2} = (c n / 2)(I_i + I_{i+1})
+    - (S+ / 2)(I_{i+1} - I_i), so
+    I*_i = I_i - sum_a lam_a [ (n_a / 2)(I_{i+e_a} - I_{i-e_a})
+                              - (S+ / 2c)(I_{i+e_a} - 2 I_i + I_{i-e_a}) ],
 lam_a = c dt / Delta_a, n^+ = max(n, 0), n^- = min(n, 0).  Ghost values
 (Sec. 4.5): vacuum 0, periodic wrap, inflow (Dirichlet) a prescribed value
-g = face_w (x) theta_w (x) phi_w on the face.
+g = face_w (x) theta_w (x) phi_w on the face, outflow the adjacent interior
+cell.
 
 Energy density (Sec. 3, discrete form): E_i = (1/c) sum_{lp} I_ilp dOmega_lp.
 
@@ -16,7 +22,7 @@ Source step: I^{m+1} = d I* + s (see ``material``).
 import numpy as np
 
 from . import material as mat
-from .setup import PERIODIC, INFLOW
+from .setup import PERIODIC, INFLOW, OUTFLOW, RUSANOV
 
 
 def _ghost(setup, face, like_slice):
@@ -41,22 +47,29 @@ def neighbours(I, setup, axis):
     lo[ax] = 0
     hi[ax] = -1
     lo, hi = tuple(lo), tuple(hi)
-    if setup.bc_lo[axis] != PERIODIC:
-        Im[lo] = _ghost(setup, 2 * axis, Im[lo]) if setup.bc_lo[axis] == INFLOW else 0.0
-    if setup.bc_hi[axis] != PERIODIC:
-        Ip[hi] = _ghost(setup, 2 * axis + 1, Ip[hi]) if setup.bc_hi[axis] == INFLOW else 0.0
+    bl, bh = setup.bc_lo[axis], setup.bc_hi[axis]
+    if bl != PERIODIC:
+        Im[lo] = (_ghost(setup, 2 * axis, Im[lo]) if bl == INFLOW
+                  else I[lo] if bl == OUTFLOW else 0.0)
+    if bh != PERIODIC:
+        Ip[hi] = (_ghost(setup, 2 * axis + 1, Ip[hi]) if bh == INFLOW
+                  else I[hi] if bh == OUTFLOW else 0.0)
     return Im, Ip
 
 
 def transport(I, setup):
-    """One explicit upwind transport update (eq. lhs + eq. upwind)."""
+    """One explicit transport update (eq. lhs with the workload's flux)."""
     out = I.copy()
     for a in range(setup.dim):
         tf, pf = setup.cosine_factors(a)
         n = np.outer(tf, pf)
-        npos, nneg = np.maximum(n, 0.0), np.minimum(n, 0.0)
         Im, Ip = neighbours(I, setup, a)
-        out -= setup.lam[a] * (npos * (I - Im) + nneg * (Ip - I))
+        if setup.flux == RUSANOV:
+            out -= setup.lam[a] * (0.5 * n * (Ip - Im)
+                                   - 0.5 * setup.s_plus * (Ip - 2.0 * I + Im))
+        else:
+            npos, nneg = np.maximum(n, 0.0), np.minimum(n, 0.0)
+            out -= setup.lam[a] * (npos * (I - Im) + nneg * (Ip - I))
     return out
 
 

@@ -17,7 +17,10 @@ Rules where the paper is silent (applied identically by every form here):
   ||dG|| ~ R u sigma_1^2 moves sigma_r by ~R u sigma_1^2 / sigma_r);
 * clip rule for singular Gram matrices: eigenpairs with lambda <= tau
   lambda_max (tau = R u, R the Gram dimension, u = 2^-53) or lambda <= 0
-  are dropped before Sigma^-1 is formed;
+  are dropped before Sigma^-1 is formed; then the kept count of each side
+  is cut to the rank that side can have, its number of rows (a Gram of R
+  columns built from m < R rows has rank <= m, and eigenpairs past m are
+  rounding noise of size ~u lambda_max, App. A.4);
 * eigen/singular vectors in descending order, each column signed so that
   its largest-magnitude entry is positive (first such entry on ties);
 * a zero tensor rounds to rank 1 with zero cores.
@@ -126,8 +129,11 @@ def rank_margin(sig, delta2, rmax, eta=ETA_FP64, noise=0.0):
     return float(min(margins))
 
 
-def eig_desc_clipped(G):
-    """Symmetric eigendecomposition, descending, gauge-fixed, clip rule."""
+def eig_desc_clipped(G, rows=None):
+    """Symmetric eigendecomposition, descending, gauge-fixed, clip rule.
+
+    ``rows``: the number of rows of the factor whose Gram G is; the kept
+    count is cut to it (rank bound of G)."""
     R = G.shape[0]
     lam, V = np.linalg.eigh(G)
     lam, V = lam[::-1], V[:, ::-1]
@@ -137,10 +143,13 @@ def eig_desc_clipped(G):
     tau = R * U
     keep = (lam > tau * lam[0]) & (lam > 0.0)
     k = int(np.count_nonzero(keep))
+    if rows is not None:
+        k = min(k, int(rows))
     return lam[:k].copy(), V[:, :k].copy()
 
 
-def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None, perturb=None):
+def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None, perturb=None,
+                  b_rows=None):
     """Gram-SVD truncate of A B^T given A and the Gram of B (App. A.2).
 
     G_A = A^T A = V_A Sigma_A^2 V_A^T, G_B = V_B Sigma_B^2 V_B^T,
@@ -149,14 +158,15 @@ def gram_truncate(A, GB, *, tol, rmax, delta2=None, eta=ETA_FP64, rank=None, per
     Returns (A', M_upd, P, info) with A' = A P.
     ``perturb`` (tests only): applied to G_A and G_B before their
     eigendecompositions, to measure the method's own sensitivity to a
-    rounding-sized change of its Gram matrices.
+    rounding-sized change of its Gram matrices.  ``b_rows``: the number of
+    columns of B^T (the rank bound of G_B); A's bound is its row count.
     """
     R = A.shape[1]
     GA = A.T @ A
     if perturb is not None:
         GA, GB = perturb(GA), perturb(GB)
-    lamA, VA = eig_desc_clipped(GA)
-    lamB, VB = eig_desc_clipped(GB)
+    lamA, VA = eig_desc_clipped(GA, rows=A.shape[0])
+    lamB, VB = eig_desc_clipped(GB, rows=b_rows)
     info = dict(R=R, kA=lamA.size, kB=lamB.size)
     if lamA.size == 0 or lamB.size == 0:
         sig = np.zeros(0)
@@ -206,12 +216,13 @@ def round_gram(X, Th, Ph, tol, rmax, ranks=None, eta=ETA_FP64, perturb=None):
     GB1 = B1T @ B1T.T
     rk = (None, None) if ranks is None else ranks
     Xn, M1, _, info1 = gram_truncate(X, GB1, tol=tol, rmax=rmax, eta=eta, rank=rk[0],
-                                     perturb=perturb)
+                                     perturb=perturb, b_rows=nt * npf)
     r1n = Xn.shape[1]
     G2 = (M1 @ Th.reshape(r1, nt * r2)).reshape(r1n, nt, r2)
     A2 = G2.reshape(r1n * nt, r2)
     A2n, M2, _, info2 = gram_truncate(A2, GB2, tol=tol, rmax=rmax, eta=eta,
-                                      delta2=info1["delta2"], rank=rk[1], perturb=perturb)
+                                      delta2=info1["delta2"], rank=rk[1], perturb=perturb,
+                                      b_rows=npf)
     r2n = A2n.shape[1]
     return (Xn, A2n.reshape(r1n, nt, r2n), M2 @ Ph), (info1, info2)
 

@@ -4,12 +4,19 @@ Holds the grid, the quadrature, the time step and the per-cell fields of a
 workload dict (see the ``workloads`` package).  Time step: the paper bounds
 Delta t by CFL * Delta x / c (Sec. 3.1, below eq. lhs); the reading used is
 Delta t = CFL * min(Delta x, Delta y[, Delta z]) / c.
+
+Optional workload keys: ``flux`` ("upwind", the default, or "rusanov",
+Sec. 3.1), ``s_plus`` (the Rusanov wavespeed S+ in units of c, default 1),
+``kappa_s`` (per-cell scattering opacity, default 0, Sec. 3.2).  Boundary
+codes: vacuum, periodic, inflow (Dirichlet) and outflow (ghost cell = the
+adjacent interior cell, Sec. 4.5).
 """
 import numpy as np
 
 from . import quadrature
 
-VACUUM, PERIODIC, INFLOW = 0, 1, 2
+VACUUM, PERIODIC, INFLOW, OUTFLOW = 0, 1, 2, 3
+UPWIND, RUSANOV = "upwind", "rusanov"
 FROZEN, COUPLED = 0, 1
 
 
@@ -39,14 +46,22 @@ class Setup:
         self.rho = np.asarray(p["rho"], dtype=np.float64).copy()
         self.cv = np.asarray(p["cv"], dtype=np.float64).copy()
         self.T0 = np.asarray(p["T0"], dtype=np.float64).copy()
+        self.kappa_s = np.asarray(p.get("kappa_s", np.zeros(self.ns)), dtype=np.float64).copy()
+        self.flux = p.get("flux", UPWIND)
+        if self.flux not in (UPWIND, RUSANOV):
+            raise ValueError("flux must be 'upwind' or 'rusanov'")
+        self.s_plus = float(p.get("s_plus", 1.0))
         self.inflow = [(int(f), np.asarray(fw, float), np.asarray(tw, float),
                         np.asarray(pw, float)) for (f, fw, tw, pw) in p["inflow"]]
         self.mu, self.w, self.phi, self.v = quadrature.ordinates(self.nt, self.np_)
         self.sin_t, self.cos_p, self.sin_p, _ = quadrature.direction_cosines(self.nt, self.np_)
         self.domega = np.outer(self.w, self.v)
         self.cell_volume = float(np.prod(self.spacing))
-        # emission block present unless the temperature is frozen at zero
-        self.n_em = 0 if (self.material == FROZEN and not np.any(self.T0 != 0.0)) else 1
+        # isotropic source block (emission and scattering) present unless the
+        # temperature is frozen at zero and there is no scattering
+        self.scatter = bool(np.any(self.kappa_s != 0.0))
+        self.n_em = 0 if (self.material == FROZEN and not np.any(self.T0 != 0.0)
+                          and not self.scatter) else 1
 
     # direction-cosine factors per axis: (theta factor, phi factor) of n_a
     def cosine_factors(self, axis):

@@ -1,26 +1,38 @@
 """One step-then-truncate time step in TT form (paper Sec. 4).
 
-Transport (Sec. 4.3).  n_x = sin(theta) (x) cos(phi) and
-n_y = sin(theta) (x) sin(phi) are rank 1 and so are the upwind masks, so the
-explicit update of eq. lhs is a sum of TTs.  Reading used (one block per
-axis and sign):
+Transport (Sec. 4.3).  n_x = sin(theta) (x) cos(phi),
+n_y = sin(theta) (x) sin(phi) and n_z = mu (x) 1 are rank 1, and so are the
+upwind masks, so the explicit update of eq. lhs is a sum of TTs.
+
+Upwind flux, one block per axis and sign (reading of Sec. 4.3):
     I* = I + sum_a [ (D_a^- X) (tf_a^+ Theta) (-lam_a pf_a^+ Phi)
                    + (D_a^+ X) (tf_a^- Theta) (-lam_a pf_a^- Phi) ]
-with D_a^- X = X_i - X_{i-e_a}, D_a^+ X = X_{i+e_a} - X_i (ghost rows 0, or
-wrapped when periodic), and for x/y: tf^+ = tf^- = sin(theta),
-pf^+ = max(cos or sin, 0), pf^- = min(cos or sin, 0); for z (3-D):
-tf^+ = max(mu, 0), tf^- = min(mu, 0), pf = 1.  Dirichlet inflow adds one
-rank-1 block per inflow face (Sec. 4.5: ghost value added as a rank-1
-term): on a lo face  e_face (x) tf^+ theta_w (x) lam pf^+ phi_w, on a hi face
-e_face (x) tf^- theta_w (x) (-lam) pf^- phi_w.
+with D_a^- X = X_i - X_{i-e_a}, D_a^+ X = X_{i+e_a} - X_i, and for x/y:
+tf^+ = tf^- = sin(theta), pf^+ = max(cos or sin, 0), pf^- = min(cos or
+sin, 0); for z (3-D): tf^+ = max(mu, 0), tf^- = min(mu, 0), pf = 1.
 
-Source (Sec. 4.4): every X-block row i is scaled by d_i and the emission
-block s (x) 1 (x) 1 is appended (omitted when the temperature is frozen at
-zero everywhere).
+Rusanov flux (eq. rusanov_flux_toro; Sec. 4.3 Rusanov), one central block
+and one diffusion block per axis (the latter dropped when S+ = 0):
+    I* = I + sum_a [ (D_a^0 X) (tf_a Theta) (-lam_a pf_a Phi)
+                   + (D_a^2 X) Theta ((lam_a S+ / 2c) Phi) ]
+with D^0 X = (X_{i+e_a} - X_{i-e_a}) / 2, D^2 X = X_{i+e_a} - 2 X_i + X_{i-e_a}.
+
+Ghost rows of the stencils (Sec. 4.5): zero (vacuum, and inflow, whose
+ghost value enters as rank-1 blocks), wrapped (periodic), or the adjacent
+interior row (outflow).  A Dirichlet ghost value g = face_w (x) theta_w (x)
+phi_w adds what the stencils miss at the face: upwind, on a lo face
+e_face (x) tf^+ theta_w (x) lam pf^+ phi_w and on a hi face
+e_face (x) tf^- theta_w (x) (-lam) pf^- phi_w; Rusanov,
+e_face (x) tf theta_w (x) (+-lam/2) pf phi_w (+ on lo, - on hi) plus
+e_face (x) theta_w (x) (lam S+/2c) phi_w.
+
+Source (Sec. 4.4): every X-block row i is scaled by d_i and the isotropic
+source block s (x) 1 (x) 1 (emission and scattering) is appended (omitted
+when the temperature is frozen at zero and there is no scattering).
 
 TT sum (Sec. 4.1 Addition): cores concatenated, middle core block-diagonal.
-Block order: base, then per axis (minus, plus), then inflow entries in input
-order, then emission.
+Block order: base, then per axis (minus, plus) or (central, diffusion),
+then inflow entries in input order, then the source block.
 
 Rounding: Gram-SVD (``rounding.round_gram``), once after the fused
 transport + source sum by default; schedule "twice" also rounds after the
@@ -31,44 +43,56 @@ import numpy as np
 
 from . import material as mat
 from . import rounding
-from .setup import PERIODIC
+from .setup import PERIODIC, OUTFLOW, RUSANOV
 
 
 def shift(X, setup, axis, direction):
-    """Rows X_{i + direction*e_a}: zero ghost rows, or wrapped if periodic."""
+    """Rows X_{i + direction*e_a} with the ghost rows of the face crossed:
+    zero, wrapped (periodic) or the row itself (outflow)."""
     r = X.shape[1]
     G = X.reshape(setup.grid_shape() + (r,))
     ax = 2 - axis
     S = np.roll(G, -direction, axis=ax)
-    periodic = setup.bc_lo[axis] == PERIODIC
-    if not periodic:
+    bc = setup.bc_lo[axis] if direction < 0 else setup.bc_hi[axis]
+    if bc != PERIODIC:
         sl = [slice(None)] * 4
         sl[ax] = 0 if direction < 0 else -1
-        S[tuple(sl)] = 0.0
+        S[tuple(sl)] = G[tuple(sl)] if bc == OUTFLOW else 0.0
     return S.reshape(-1, r)
 
 
 def transport_blocks(X, Th, Ph, setup):
     blocks = [(X, Th, Ph)]
+    rus = setup.flux == RUSANOV
     for a in range(setup.dim):
         tf, pf = setup.cosine_factors(a)
         lam = setup.lam[a]
-        Dm = X - shift(X, setup, a, -1)
-        Dp = shift(X, setup, a, +1) - X
+        Xm, Xp = shift(X, setup, a, -1), shift(X, setup, a, +1)
+        if rus:
+            blocks.append((0.5 * (Xp - Xm), Th * tf[None, :, None], Ph * (-lam * pf)[None, :]))
+            if setup.s_plus != 0.0:
+                blocks.append((Xp - 2.0 * X + Xm, Th, Ph * (0.5 * lam * setup.s_plus)))
+            continue
         if a < 2:
             tpos = tneg = tf
             ppos, pneg = np.maximum(pf, 0.0), np.minimum(pf, 0.0)
         else:
             tpos, tneg = np.maximum(tf, 0.0), np.minimum(tf, 0.0)
             ppos = pneg = pf
-        blocks.append((Dm, Th * tpos[None, :, None], Ph * (-lam * ppos)[None, :]))
-        blocks.append((Dp, Th * tneg[None, :, None], Ph * (-lam * pneg)[None, :]))
+        blocks.append((X - Xm, Th * tpos[None, :, None], Ph * (-lam * ppos)[None, :]))
+        blocks.append((Xp - X, Th * tneg[None, :, None], Ph * (-lam * pneg)[None, :]))
     for (f, fw, tw, pw) in setup.inflow:
         a, hi = divmod(f, 2)
         tf, pf = setup.cosine_factors(a)
         lam = setup.lam[a]
         e = np.zeros(setup.ns)
         e[setup.face_cells(f)] = fw
+        if rus:
+            sgn = -1.0 if hi else 1.0
+            blocks.append((e[:, None], (tf * tw)[None, :, None], (sgn * 0.5 * lam * pf * pw)[None, :]))
+            if setup.s_plus != 0.0:
+                blocks.append((e[:, None], tw[None, :, None], (0.5 * lam * setup.s_plus * pw)[None, :]))
+            continue
         if a < 2:
             tpart = tf * tw
             ppart = (lam * np.maximum(pf, 0.0) if not hi else -lam * np.minimum(pf, 0.0)) * pw

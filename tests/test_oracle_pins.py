@@ -356,3 +356,251 @@ def test_rank_margin_flags_boundary_decisions():
     # a tie test sitting on eta sigma_1: sigma_2 - sigma_3 = eta sigma_1
     sig2 = np.array([1.0, 0.5, 0.5 - 1e-12, 1e-3])
     assert rounding.rank_margin(sig2, 0.3, 0) < 1e-3  # r = 2 before the tie test
+
+
+# ------------------------------------------------- clip to the row rank (Q11)
+def _noisy(scale, seed):
+    """A symmetric perturbation of ``scale`` unit roundoffs of max|G| (a
+    stand-in for the rounding error of another summation order)."""
+    r = np.random.default_rng(seed)
+
+    def pert(G):
+        E = r.uniform(-1.0, 1.0, G.shape)
+        return G + scale * rounding.U * np.abs(G).max() * 0.5 * (E + E.T)
+    return pert
+
+
+@pytest.mark.parametrize("scale", [0, 30, 300])
+def test_kept_eigenpairs_never_exceed_the_row_rank(scale):
+    """G_B at bond 2 is Phi Phi^T of order r2 = 20 built from N_phi = 8
+    columns, so it has rank <= 8 and every further eigenpair is rounding
+    noise.  Under Gram noise of up to 300 u max|G| the kept counts stay
+    within the row ranks, the TT ranks within the mode bounds (r2 <= N_phi,
+    r1 <= min(N_s, N_theta N_phi)), and the result is the dense-SVD rounding
+    of the same tensor (App. A.2 vs. the SVD of the unfoldings).  Without
+    the cut to the row rank the noise pairs are kept and r2 exceeds N_phi."""
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((40, 6))
+    Th = rng.standard_normal((6, 4, 20))
+    Ph = rng.standard_normal((20, 8))
+    T = metrics.reconstruct(X, Th, Ph)
+    (Xg, Tg, Pg), (i1, i2) = rounding.round_gram(X, Th, Ph, 1e-8, 0,
+                                                 perturb=_noisy(scale, 1) if scale else None)
+    assert i1["kA"] <= 40 and i1["kB"] <= 4 * 8
+    assert i2["kA"] <= Xg.shape[1] * 4 and i2["kB"] <= 8
+    assert Xg.shape[1] <= min(40, 32) and Pg.shape[0] <= 8
+    d = rounding.round_dense(T, 1e-8, 0)
+    assert (Xg.shape[1], Pg.shape[0]) == (d[0].shape[1], d[2].shape[0])
+    assert metrics.rel_diff((Xg, Tg, Pg), d) < 1e-12
+
+
+def test_c1_bond2_gram_beyond_its_row_rank():
+    """C1 after three steps: the concatenated angular core has R2 > N_phi =
+    16 rows, so G_R3 = Phi_cat Phi_cat^T is singular beyond rank 16.  The
+    kept count of its side is at most 16 and the step's rounding equals the
+    dense-SVD rounding of the untruncated step."""
+    p = wl.c1()
+    p["tol"] = 1e-6
+    s = Setup(p)
+    (X, Th, Ph), _, _ = tt.run(s, 3)
+    cat, _, _ = tt.step_untruncated(X, Th, Ph, s.T0, s)
+    assert cat[2].shape[0] > 16
+    (Xg, Tg, Pg), (i1, i2) = rounding.round_gram(*cat, p["tol"], 0)
+    assert i2["kB"] <= 16 and Pg.shape[0] <= 16
+    d = rounding.round_dense(metrics.reconstruct(*cat), p["tol"], 0)
+    assert (Xg.shape[1], Pg.shape[0]) == (d[0].shape[1], d[2].shape[0])
+    assert metrics.rel_diff((Xg, Tg, Pg), d) < 1e-9
+
+
+# --------------------------------------------- the two-rounding schedule (Sec. 4.2)
+@pytest.mark.parametrize("kw", [dict(seed=1), dict(bc="inflow", seed=3, material=wl.COUPLED),
+                                dict(dim=3, nx=4, ny=3, nz=4, bc="periodic", seed=5)])
+def test_twice_schedule_without_truncation_is_the_full_grid_step(kw):
+    """Rounding after the transport sum and again after the source update
+    (Sec. 4.2) changes nothing when nothing is truncated: with tol = 0 the
+    two-rounding step equals the full-grid step and the one-rounding step,
+    temperature included."""
+    p = wl.small_random(**kw)
+    s = Setup(p)
+    I1, T1, _ = full.step(full.initial_intensity(s), s.T0, s)
+    X0, Th0, Ph0 = p["X0"], p["Th0"], p["Ph0"]
+    tw, Tt, info = tt.step(X0, Th0, Ph0, s.T0, s, 0.0, 0, schedule="twice")
+    on, To, _ = tt.step(X0, Th0, Ph0, s.T0, s, 0.0, 0, schedule="once")
+    assert len(info["round"]) == 2
+    F = metrics.reconstruct(*tw).reshape(I1.shape)
+    assert np.linalg.norm(F - I1) < 1e-12 * np.linalg.norm(I1)
+    assert metrics.rel_diff(tw, on) < 1e-12
+    assert np.max(np.abs(Tt - T1)) < 1e-12 * np.max(np.abs(T1))
+    assert np.max(np.abs(Tt - To)) < 1e-12 * np.max(np.abs(T1))
+
+
+def test_twice_schedule_error_bound():
+    """With truncation, each of the two roundings moves its tensor by at most
+    tol times that tensor's norm (App. A note on rank truncation), and the
+    source update scales by d <= 1: the two-rounding step is within
+    tol (max d ||I*|| + ||I^{m+1}||) of the full-grid step, and its first
+    rounding sees only the transport blocks (ranks B r + n_bc)."""
+    p = wl.small_random(nx=8, ny=7, ntheta=6, nphi=12, r1=4, r2=3, seed=9, bc="inflow")
+    s = Setup(p)
+    tol = 1e-3
+    I0 = full.initial_intensity(s)
+    Istar = full.transport(I0, s)
+    I1, _, _ = full.step(I0, s.T0, s)
+    tw, _, info = tt.step(p["X0"], p["Th0"], p["Ph0"], s.T0, s, tol, 0, schedule="twice")
+    R1 = info["round"][0][0]["R"]
+    assert R1 == 5 * 4 + len(p["inflow"])
+    err = np.linalg.norm(metrics.reconstruct(*tw).reshape(I1.shape) - I1)
+    dmax = np.max(1.0 / (1.0 + s.c * s.dt * s.rho * s.kappa))
+    assert err <= tol * (dmax * np.linalg.norm(Istar) + np.linalg.norm(I1)) * (1 + 1e-9)
+
+
+# --------------------------------------- Rusanov flux, outflow, scattering
+def test_rusanov_fourier_amplification():
+    """Rusanov flux on a periodic line (eq. rusanov_flux_toro with piecewise
+    constant states): a Fourier mode evolves by the textbook factor
+    g = 1 - i nu sin h - lam s (1 - cos h), nu = lam n_x, s = S+ / c."""
+    for s_plus in (1.0, 0.3, 0.0):
+        p = _line_problem()
+        p["flux"], p["s_plus"] = "rusanov", s_plus
+        s = Setup(p)
+        k = 3
+        x = (np.arange(s.nx) + 0.5) * s.dx
+        theta = 2 * np.pi * k * x
+        h = 2 * np.pi * k * s.dx
+        I = np.broadcast_to(np.cos(theta)[None, None, :, None, None],
+                            (1, 1, s.nx, s.nt, s.np_)).copy()
+        m = 4
+        for _ in range(m):
+            I = full.transport(I, s)
+        lam = s.lam[0]
+        nu = lam * np.outer(s.sin_t, s.cos_p)
+        g = 1 - 1j * nu * np.sin(h) - lam * s_plus * (1 - np.cos(h))
+        expect = np.real(g[None, :, :] ** m * np.exp(1j * theta)[:, None, None])
+        assert np.max(np.abs(I[0, 0] - expect)) < 1e-13
+
+
+@pytest.mark.parametrize("flux", ["upwind", "rusanov"])
+def test_outflow_boundaries(flux):
+    """Outflow ghost cells copy the adjacent interior cell (Sec. 4.5): a
+    uniform field with outflow on every face is a steady state of the
+    transport step.  With outflow on x-lo and vacuum on x-hi (periodic in
+    y), upwind changes only the last column, and there only the directions
+    entering through the vacuum face (n_x < 0), by the factor 1 + lam n_x."""
+    p = _line_problem(nx=7)
+    p["flux"] = flux
+    p["bc_lo"] = [wl.OUTFLOW, wl.OUTFLOW, 0]
+    p["bc_hi"] = [wl.OUTFLOW, wl.OUTFLOW, 0]
+    s = Setup(p)
+    I = np.full((1, 1, s.nx, s.nt, s.np_), 1.7)
+    assert np.max(np.abs(full.transport(I, s) - I)) < 1e-15
+    if flux == "upwind":
+        p["bc_hi"] = [wl.VACUUM, wl.OUTFLOW, 0]
+        p["bc_lo"] = [wl.OUTFLOW, wl.OUTFLOW, 0]
+        s = Setup(p)
+        I1 = full.transport(I, s)
+        nx_ = np.outer(s.sin_t, s.cos_p)
+        assert np.max(np.abs(I1[0, 0, :-1] - 1.7)) < 1e-15
+        expect = np.where(nx_ < 0, 1.7 * (1 + s.lam[0] * nx_), 1.7)
+        assert np.max(np.abs(I1[0, 0, -1] - expect)) < 1e-15
+
+
+def test_scattering_relaxes_to_isotropy():
+    """Pure isotropic scattering (kappa_a = 0) in a uniform medium, eq.
+    couple_a: J^{m+1} = J*, so I^{m+1} = d I* + (1 - d) J* with
+    d = 1 / (1 + c dt rho kappa_s): the mean intensity is kept and the
+    anisotropic part decays by d per step."""
+    p = _line_problem(nx=4, bc="periodic", kappa=0.0)
+    p["kappa_s"] = np.full(4, 2.5)
+    s = Setup(p)
+    rng = np.random.default_rng(0)
+    ang = rng.random((s.nt, s.np_))
+    I = np.broadcast_to(ang[None, None, None], (1, 1, 4, s.nt, s.np_)).copy()
+    J0 = np.sum(ang * s.domega) / (4 * np.pi)
+    d = 1.0 / (1.0 + s.c * s.dt * 2.5)
+    for m in range(1, 4):
+        I, _, _ = full.step(I, s.T0, s)
+        expect = J0 + d ** m * (ang - J0)
+        assert np.max(np.abs(I[0, 0] - expect[None])) < 1e-14
+
+
+def test_scattering_conserves_energy_and_keeps_the_temperature_equation():
+    """Scattering moves no energy between radiation and material: with
+    kappa_a = 0, periodic boundaries, the total radiation energy of a step
+    is constant; with absorption and coupled material, adding kappa_s leaves
+    T_dag unchanged (eq. couple_b after eliminating J^{m+1}) and total energy
+    is conserved."""
+    p = wl.small_random(bc="periodic", seed=13, scatter=True)
+    p["kappa"][:] = 0.0
+    s = Setup(p)
+    I = full.initial_intensity(s)
+    E0 = full.energy(I, s).sum()
+    for _ in range(3):
+        I, _, _ = full.step(I, s.T0, s)
+        assert abs(full.energy(I, s).sum() - E0) < 1e-13 * E0
+    q = wl.small_random(bc="periodic", seed=14, material=wl.COUPLED, scatter=True)
+    sq = Setup(q)
+    q0 = dict(q)
+    q0["kappa_s"] = np.zeros_like(q["kappa_s"])
+    s0 = Setup(q0)
+    I = full.initial_intensity(sq)
+    _, T1, info = full.step(I, sq.T0, sq)
+    _, _, info0 = full.step(I, s0.T0, s0)
+    assert np.max(np.abs(info["Tdag"] - info0["Tdag"])) < 1e-14 * np.max(info0["Tdag"])
+    tot0 = full.energy(I, sq).sum() + np.sum(sq.rho * sq.cv * sq.T0)
+    I1, T1, _ = full.step(I, sq.T0, sq)
+    tot1 = full.energy(I1, sq).sum() + np.sum(sq.rho * sq.cv * T1)
+    assert abs(tot1 - tot0) < 1e-13 * tot0
+
+
+NEW_OPERATOR_CASES = [dict(bc="outflow", seed=31), dict(bc="mixed", seed=32),
+                      dict(flux="rusanov", bc="periodic", seed=33),
+                      dict(flux="rusanov", s_plus=0.0, bc="outflow", seed=34, scatter=True),
+                      dict(flux="rusanov", s_plus=0.4, bc="inflow", seed=35),
+                      dict(flux="rusanov", bc="mixed", seed=36, material=wl.COUPLED, scatter=True),
+                      dict(bc="inflow", seed=37, scatter=True),
+                      dict(dim=3, nx=4, ny=3, nz=4, bc="mixed", seed=38, scatter=True),
+                      dict(dim=3, nx=3, ny=4, nz=4, flux="rusanov", bc="inflow", seed=39)]
+
+
+@pytest.mark.parametrize("kw", NEW_OPERATOR_CASES, ids=[f"op{i}" for i in range(len(NEW_OPERATOR_CASES))])
+def test_new_operators_tt_without_truncation_is_the_full_grid_step(kw):
+    """Rusanov blocks, outflow ghost rows, the two-term Rusanov inflow and
+    the scattering source in TT form reconstruct the full-grid step exactly
+    when nothing is truncated (the TT form is an exact rewrite, Sec. 4)."""
+    p = wl.small_random(**kw)
+    s = Setup(p)
+    I1, T1, _ = full.step(full.initial_intensity(s), s.T0, s)
+    cat, T1t, _ = tt.step_untruncated(p["X0"], p["Th0"], p["Ph0"], s.T0, s)
+    F = metrics.reconstruct(*cat).reshape(I1.shape)
+    assert np.linalg.norm(F - I1) < 1e-13 * np.linalg.norm(I1)
+    assert np.max(np.abs(T1t - T1)) < 1e-13 * np.max(np.abs(T1))
+    (Xn, Thn, Phn), T2, _ = tt.step(p["X0"], p["Th0"], p["Ph0"], s.T0, s, 0.0, 0)
+    F2 = metrics.reconstruct(Xn, Thn, Phn).reshape(I1.shape)
+    assert np.linalg.norm(F2 - I1) < 1e-12 * np.linalg.norm(I1)
+
+
+def test_gaussian_diffusion_ranks_and_analytic_solution():
+    """Gaussian diffusion by isotropic scattering (Sec. 5.3), at reduced
+    size (64^2 cells on [0,5]^2, 8x16 ordinates, rho kappa_s = 1e3, outflow,
+    Rusanov with S+ = 0, tolerance 1e-4): the ranks stay at the (3, 3) the
+    paper prints throughout (the isotropic part and the two first-order
+    anisotropic terms n_x dJ/dx, n_y dJ/dy), the energy density follows
+    the diffusion solution A / (4 pi D (t0 + t)) exp(-r^2 / (4 D (t0 + t))),
+    D = c / (3 rho kappa_s), to well within the distance it travels, and the
+    total energy stays at A."""
+    p = wl.gaussian_diffusion(n=64, steps=300)
+    s = Setup(p)
+    (X, Th, Ph), _, hist = tt.run(s, 300)
+    assert set(hist) == {(3, 3)}
+    dif = p["diffusion"]
+    t = 300 * s.dt
+    xs = (np.arange(64) + 0.5) * 5.0 / 64 - 2.5
+    r2 = xs[None, :] ** 2 + xs[:, None] ** 2
+
+    def Ea(tt_):
+        return dif["A"] / (4 * np.pi * dif["D"] * (dif["t0"] + tt_)) * np.exp(-r2 / (4 * dif["D"] * (dif["t0"] + tt_)))
+    E = tt.energy(X, Th, Ph, s).reshape(64, 64)
+    err = np.linalg.norm(E - Ea(t)) / np.linalg.norm(Ea(t))
+    moved = np.linalg.norm(Ea(0.0) - Ea(t)) / np.linalg.norm(Ea(t))
+    assert moved > 0.03 and err < 0.1 * moved
+    assert abs(E.sum() * s.cell_volume - dif["A"]) < 1e-6

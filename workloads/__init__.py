@@ -20,7 +20,7 @@ c, a_r     speed of light, radiation constant
 cfl        time step = cfl * min cell size / c
 tol        relative Frobenius rounding tolerance
 rmax       rank cap (<= 0: none)
-bc_lo/hi   per axis: 0 vacuum, 1 periodic, 2 inflow
+bc_lo/hi   per axis: 0 vacuum, 1 periodic, 2 inflow, 3 outflow
 material   0 frozen temperature, 1 coupled (backward-Euler material)
 kappa,rho,cv,T0  per-cell float64 arrays of length N_s = nx*ny*nz
 X0,Th0,Ph0 initial cores, shapes (N_s,r1), (r1,ntheta,r2), (r2,nphi)
@@ -28,6 +28,9 @@ inflow     list of (face, face_w, theta_w, phi_w); face 0..5 =
            x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; face_w is indexed by the
            face's own 2-D cell index (see ``face_cells``)
 steps      number of steps of the workload
+flux       optional: "upwind" (default) or "rusanov"
+s_plus     optional: Rusanov wavespeed S+ in units of c (default 1)
+kappa_s    optional: per-cell scattering opacity (default 0)
 ========== ==============================================================
 
 Spatial cells are flattened as ``i = ix + nx*(iy + ny*iz)``.
@@ -36,7 +39,7 @@ from __future__ import annotations
 
 import numpy as np
 
-VACUUM, PERIODIC, INFLOW = 0, 1, 2
+VACUUM, PERIODIC, INFLOW, OUTFLOW = 0, 1, 2, 3
 FROZEN, COUPLED = 0, 1
 
 
@@ -240,9 +243,13 @@ def random_tt(ns, ntheta, nphi, r1, r2, seed, decay=None):
 
 
 def small_random(dim=2, nx=6, ny=5, nz=1, ntheta=4, nphi=8, r1=3, r2=2,
-                 seed=0, bc="vacuum", material=FROZEN, tol=1e-6, rmax=0):
+                 seed=0, bc="vacuum", material=FROZEN, tol=1e-6, rmax=0,
+                 flux="upwind", s_plus=1.0, scatter=False):
     """Small seeded problem for parity tests: random positive material
-    fields and random cores; ``bc`` in {vacuum, periodic, inflow}."""
+    fields and random cores; ``bc`` in {vacuum, periodic, inflow, outflow,
+    mixed} (mixed: inflow on x-lo, outflow on x-hi, vacuum on y-lo, outflow
+    on y-hi, periodic along z); ``scatter`` adds a random positive
+    scattering opacity."""
     rng = np.random.default_rng(seed)
     p = _base(dim, nx, ny, nz if dim == 3 else 1, ntheta, nphi, tol=tol,
               rmax=rmax, steps=3)
@@ -266,5 +273,46 @@ def small_random(dim=2, nx=6, ny=5, nz=1, ntheta=4, nphi=8, r1=3, r2=2,
                      4: nx * ny}[f]
             p["inflow"].append((f, rng.random(nface), rng.random(ntheta),
                                 rng.random(nphi)))
-    p["name"] = f"small_{dim}d_{bc}_s{seed}"
+    elif bc == "outflow":
+        p["bc_lo"] = [OUTFLOW] * 3
+        p["bc_hi"] = [OUTFLOW] * 3
+    elif bc == "mixed":
+        p["bc_lo"] = [INFLOW, VACUUM, PERIODIC]
+        p["bc_hi"] = [OUTFLOW, OUTFLOW, PERIODIC]
+        p["inflow"].append((0, rng.random(ny * p["nz"]), rng.random(ntheta), rng.random(nphi)))
+    p["flux"] = flux
+    p["s_plus"] = float(s_plus)
+    if scatter:
+        p["kappa_s"] = np.exp(rng.standard_normal(ns))
+    p["name"] = f"small_{dim}d_{bc}_{flux}{'_scat' if scatter else ''}_s{seed}"
+    return p
+
+
+def gaussian_diffusion(n=64, ntheta=8, nphi=16, steps=200, t0=200.0, rho_kappa_s=1e3, A=1.0,
+                       tol=1e-4):
+    """Diffusion of a Gaussian pulse by isotropic scattering (reduced size).
+
+    Domain [0, 5]^2 with the pulse at its centre, outflow boundaries,
+    rho kappa_s = 1e3, no absorption, Rusanov flux with S+ = 0.  Initial
+    intensity I = c E(0) / (4 pi), isotropic, with the diffusion solution
+    E(t) = A / (4 pi D (t0 + t)) exp(-r^2 / (4 D (t0 + t))), D = c / (3 rho kappa_s)
+    at t = 0 (rank (1, 1)).  Frozen temperature at zero."""
+    p = _base(2, n, n, 1, ntheta, nphi, tol=tol, rmax=0, steps=steps, l=5.0)
+    p["bc_lo"] = [OUTFLOW, OUTFLOW, VACUUM]
+    p["bc_hi"] = [OUTFLOW, OUTFLOW, VACUUM]
+    ns = n * n
+    p["kappa"][:] = 0.0
+    p["kappa_s"] = np.full(ns, rho_kappa_s)
+    p["T0"][:] = 0.0
+    p["flux"] = "rusanov"
+    p["s_plus"] = 0.0
+    D = p["c"] / (3.0 * rho_kappa_s)
+    xs = _cell_centres(n, 5.0) - 2.5
+    r2 = xs[None, :] ** 2 + xs[:, None] ** 2
+    E0 = A / (4 * np.pi * D * t0) * np.exp(-r2 / (4 * D * t0))
+    p["X0"] = (p["c"] * E0 / (4 * np.pi)).reshape(ns, 1)
+    p["Th0"] = np.ones((1, ntheta, 1))
+    p["Ph0"] = np.ones((1, nphi))
+    p["diffusion"] = dict(D=D, t0=t0, A=A)
+    p["name"] = f"gaussian_diffusion_{n}sq_{ntheta}x{nphi}"
     return p
