@@ -7,8 +7,9 @@
  *                                                     eq. tensor_decomp)
  * X: N_s x r1 (all spatial cells grouped into one mode), Theta:
  * r1 x N_theta x r2, Phi: r2 x N_phi.  One step (tt_step) applies the
- * explicit upwind transport operator in TT form (Sec. 3.1 eqs. lhs/upwind,
- * Sec. 4.3), the backward-Euler absorption/emission split (Sec. 3.2 eqs.
+ * explicit transport operator in TT form with the upwind or the Rusanov
+ * flux (Sec. 3.1 eqs. lhs, upwind, rusanov_flux_toro; Sec. 4.3), the
+ * backward-Euler absorption/emission/scattering split (Sec. 3.2 eqs.
  * couple_a/couple_b, Sec. 4.4), sums all terms by core concatenation
  * (Sec. 4.1 Addition) and rounds the sum with Gram-SVD (Sec. 4.2, App. A
  * Algorithm 1 with the truncate step of App. A.2).
@@ -52,13 +53,23 @@ typedef enum {
 
 /* Boundary condition per face (Sec. 4.5): vacuum = zero ghost cells;
  * periodic = wrapped ghost cells (must be set on both faces of an axis);
- * inflow = Dirichlet ghost values given as rank-1 terms (tt_inflow). */
-enum { TT_BC_VACUUM = 0, TT_BC_PERIODIC = 1, TT_BC_INFLOW = 2 };
+ * inflow = Dirichlet ghost values given as rank-1 terms (tt_inflow);
+ * outflow = the ghost cell copies the adjacent interior cell. */
+enum { TT_BC_VACUUM = 0, TT_BC_PERIODIC = 1, TT_BC_INFLOW = 2, TT_BC_OUTFLOW = 3 };
+/* Interface flux of the transport operator (Sec. 3.1, Sec. 4.3).
+ * UPWIND: eq. upwind, one stencil block per axis and direction sign.
+ * RUSANOV: eq. rusanov_flux_toro with the wavespeed S+ = s_plus * c: a
+ * central-difference block and a diffusion block per axis (the latter
+ * omitted when s_plus == 0, the thick-medium choice of Sec. 5.3); a
+ * Dirichlet face then adds two rank-1 terms per tt_inflow entry. */
+enum { TT_FLUX_UPWIND = 0, TT_FLUX_RUSANOV = 1 };
 /* Arithmetic of the N_s-long contractions and Gram formation. */
 enum { TT_FP64 = 0, TT_FP32_MIXED = 1 };
-/* ONCE: one rounding after the fused transport + source sum.
- * TWICE: also round after the transport sum (the paper rounds after each
- * transport update and after each operator-split update, Sec. 4.2). */
+/* ONCE: one rounding per step, after the transport and source terms are
+ * summed.  TWICE: the schedule of Sec. 4.2 Rounding -- the transport sum is
+ * rounded, the source update is applied to that rounded state, and the
+ * result is rounded again (two roundings per step, both with tol/rmax; in
+ * TT_RANK_REPLAY mode each rounding takes the next schedule entry). */
 enum { TT_ROUND_ONCE = 0, TT_ROUND_TWICE = 1 };
 /* FROZEN: temperature fixed (constant emission); COUPLED: backward-Euler
  * material temperature with energy-conserving update (Sec. 3.2). */
@@ -85,6 +96,8 @@ typedef struct {
   int32_t ckpt_every;          /* > 0: tt_step records a tape for tt_grad     */
   int32_t max_steps;           /* capacity of the rank history and the tape   */
   int32_t r1_cap, r2_cap;      /* 0: derived from rmax and the mode sizes     */
+  int32_t flux;                /* TT_FLUX_UPWIND / TT_FLUX_RUSANOV            */
+  double s_plus;               /* Rusanov wavespeed S+ in units of c (>= 0)   */
 } tt_config;
 
 /* One Dirichlet inflow term: the ghost value on `face` is
@@ -101,8 +114,13 @@ typedef struct tt_ctx tt_ctx;
 
 /* Bytes of device workspace a context needs for `cfg` with `n_inflow`
  * inflow terms (0 if cfg is invalid; see tt_last_error(NULL)).  The
- * concatenated rank capacity max(B r1_cap, B r2_cap) + n_inflow + 1
- * (B = 1 + 2 dim transport blocks) must not exceed 1024. */
+ * concatenated rank capacity max(B r1_cap, B r2_cap) + n_bc + 1 must not
+ * exceed 1024, where B is the number of transport blocks (1 + 2 dim; 1 + dim
+ * for Rusanov with s_plus == 0) and n_bc the number of rank-1 inflow terms
+ * (n_inflow, or 2 n_inflow for Rusanov with s_plus > 0).
+ * The tape (ckpt_every > 0) covers the upwind flux with vacuum, periodic or
+ * inflow faces, frozen material, no scattering and TT_ROUND_ONCE; other
+ * combinations are rejected with TT_ERR_INVALID_ARG. */
 size_t tt_workspace_bytes(const tt_config* cfg, int32_t n_inflow);
 
 /* Create a context.
@@ -115,8 +133,10 @@ size_t tt_workspace_bytes(const tt_config* cfg, int32_t n_inflow);
  *      other device memory.
  *  hip_stream: a hipStream_t (NULL = default stream), caller-owned.
  *  out: receives the context.
- * Errors: TT_ERR_INVALID_ARG (config / ranks), TT_ERR_OOM (ws_bytes too
- * small), TT_ERR_DEVICE. */
+ * Host inputs are validated before any device work: every value finite,
+ * kappa >= 0, rho > 0, cv > 0, T0 >= 0; inflow weights finite.
+ * Errors: TT_ERR_INVALID_ARG (config, ranks, non-finite or out-of-range
+ * input), TT_ERR_OOM (ws_bytes too small), TT_ERR_DEVICE. */
 tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho,
                     const double* cv, const double* T0, const tt_inflow* inflow,
                     int32_t n_inflow, const double* X0, const double* Th0,
@@ -124,15 +144,22 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
                     size_t ws_bytes, void* hip_stream, tt_ctx** out);
 
 /* Advance nsteps time steps (Sec. 3-4; one step = transport operator apply,
- * absorption/emission, TT sum, Gram-SVD rounding, material update).  Ranks
- * stay on the device; the call synchronises once at the end.  With
- * ckpt_every > 0 the steps are recorded for tt_grad (at most max_steps).
- * Errors: TT_ERR_STATE (poisoned / tape full), TT_ERR_NUMERIC. */
+ * absorption/emission/scattering, TT sum, Gram-SVD rounding (twice with
+ * TT_ROUND_TWICE), material update).  Ranks stay on the device; the call
+ * synchronises once at the end, then checks that the cores (X, Theta, Phi
+ * at their live ranks) and the temperature are finite.  With ckpt_every > 0
+ * the steps are recorded for tt_grad (at most max_steps).
+ * Errors: TT_ERR_STATE (poisoned / tape full), TT_ERR_NUMERIC (non-finite
+ * state, Newton failure, eigensolver failure, or a grid barrier of the
+ * large-order eigensolvers that timed out). */
 tt_status tt_step(tt_ctx* ctx, int32_t nsteps);
 
 /* Round the stored state once (App. A Algorithm 1, Gram-SVD truncate of
  * App. A.2) with tolerance `tol` and cap `rmax` (<= 0: the context's cap
- * capacity).  ranks_out (host, 2 ints, may be NULL) receives (r1, r2). */
+ * capacity).  ranks_out (host, 2 ints, may be NULL) receives (r1, r2).
+ * A rounding is not a recorded step: on a context with recorded steps the
+ * tape no longer describes the state, and tt_grad returns TT_ERR_STATE
+ * until tt_set_cores. */
 tt_status tt_round(tt_ctx* ctx, double tol, int32_t rmax, int32_t ranks_out[2]);
 
 /* Radiation energy density E_i = (1/c) X_i (sum_l Theta_l w_l)(sum_p Phi_p v_p)
@@ -141,24 +168,35 @@ tt_status tt_round(tt_ctx* ctx, double tol, int32_t rmax, int32_t ranks_out[2]);
  * sum_i rho_i c_v,i T_i dV. */
 tt_status tt_energy(tt_ctx* ctx, double* E_dev, double* rad_total, double* mat_total);
 
+/* Detector loss L = dV sum_i w_i E_i of the current state, with E the
+ * energy density of tt_energy (Sec. 4.1 eq. tt_energy_density) and dV the
+ * cell volume.  detector_w: host N_s weights (finite).  loss_out: host. */
+tt_status tt_detector_loss(tt_ctx* ctx, const double* detector_w, double* loss_out);
+
 /* Gradient of L = loss_w . E(final) dV with respect to the per-cell
  * absorption opacity, by reverse mode over the steps recorded since the
  * last tt_set_cores (ckpt_every > 0, frozen material).  detector_w: host
  * N_s weights.  loss_out: host, may be NULL.  dkappa_dev: device N_s,
- * receives loss_bar * dL/dkappa.  Errors: TT_ERR_STATE if nothing taped. */
+ * receives loss_bar * dL/dkappa.  Errors: TT_ERR_STATE if nothing taped,
+ * or if the tape is stale (tt_set_kappa or tt_round after the steps). */
 tt_status tt_grad(tt_ctx* ctx, const double* detector_w, double loss_bar,
                   double* loss_out, double* dkappa_dev);
 
 /* Replace the absorption opacity (device N_s doubles, copied). */
 tt_status tt_set_kappa(tt_ctx* ctx, const double* kappa_dev);
 
+/* Isotropic scattering opacity kappa_s (host N_s doubles, finite, >= 0;
+ * copied), Sec. 3.2 eq. couple_a with implicit J^{m+1}.  All zero turns
+ * scattering off.  Rejected (TT_ERR_INVALID_ARG) on a context with a tape. */
+tt_status tt_set_scattering(tt_ctx* ctx, const double* kappa_s);
+
 /* Copy the current cores to host buffers sized at least N_s*r1,
  * r1*N_theta*r2 and r2*N_phi (any may be NULL); r (host, 2 ints) receives
  * the ranks.  Call with all buffers NULL to query the ranks. */
 tt_status tt_get_cores(tt_ctx* ctx, double* X, double* Th, double* Ph, int32_t r[2]);
 
-/* Install new cores (host) with ranks r[0], r[1]; clears the poison flag,
- * the rank history and the tape. */
+/* Install new cores (host, finite) with ranks r[0], r[1]; clears the poison
+ * flag, the rank history and the tape. */
 tt_status tt_set_cores(tt_ctx* ctx, const double* X, const double* Th, const double* Ph,
                        const int32_t r[2]);
 

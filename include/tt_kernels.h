@@ -78,6 +78,15 @@ tt_status tt_kernel_gemm(const double* A, int32_t lda, int32_t ta, const double*
                          int32_t tb, double* C, int32_t ldc, int32_t m, int32_t n, int32_t k,
                          void* ws, size_t ws_bytes, void* stream);
 
+/* LDS budget check (host only, no device work): the largest static + dynamic
+ * LDS of any launch of the symmetric eigensolver at order n and of the SVD
+ * at Golub-Kahan order ncap2 (= 2 min(a, b)) with longer side pcap (0
+ * skips either), written to max_bytes.  TT_OK when every launch fits the
+ * 160 KiB of one CU, else TT_ERR_INVALID_ARG naming the kernel.  Every
+ * context and every eigh/svd call applies the same check, with the HIP
+ * runtime's static sizes, before launching. */
+tt_status tt_kernel_lds_check(int32_t n, int32_t ncap2, int32_t pcap, size_t* max_bytes);
+
 /* Message of the last failed kernel-level call on this thread. */
 const char* tt_kernel_last_error(void);
 

@@ -11,9 +11,10 @@ import functools
 import numpy as np
 
 from . import _ffi
-from ._ffi import (TT_BC_INFLOW, TT_BC_PERIODIC, TT_BC_VACUUM, TT_FP32_MIXED, TT_FP64,  # noqa: F401
-                   TT_MAT_COUPLED, TT_MAT_FROZEN, TT_RANK_AUTO, TT_RANK_REPLAY, TT_ROUND_ONCE,
-                   TT_ROUND_TWICE, STATUS_NAMES)
+from ._ffi import (TT_BC_INFLOW, TT_BC_OUTFLOW, TT_BC_PERIODIC, TT_BC_VACUUM,  # noqa: F401
+                   TT_FLUX_RUSANOV, TT_FLUX_UPWIND, TT_FP32_MIXED, TT_FP64, TT_MAT_COUPLED,
+                   TT_MAT_FROZEN, TT_RANK_AUTO, TT_RANK_REPLAY, TT_ROUND_ONCE, TT_ROUND_TWICE,
+                   STATUS_NAMES)
 
 
 class TTError(RuntimeError):
@@ -50,6 +51,8 @@ def make_config(p, *, precision=TT_FP64, schedule=TT_ROUND_ONCE, rank_mode=TT_RA
     cfg.ckpt_every = ckpt_every
     cfg.max_steps = int(max_steps if max_steps is not None else max(p.get("steps", 1), 1))
     cfg.r1_cap, cfg.r2_cap = r1_cap, r2_cap
+    cfg.flux = TT_FLUX_RUSANOV if p.get("flux", "upwind") == "rusanov" else TT_FLUX_UPWIND
+    cfg.s_plus = float(p.get("s_plus", 1.0))
     return cfg
 
 
@@ -90,6 +93,9 @@ class TTState:
         if st != 0:
             raise TTError(st, self.lib.tt_last_error(None).decode())
         self.ctx = ctx
+        ks = p.get("kappa_s")
+        if ks is not None and np.any(np.asarray(ks) != 0):
+            self.tt_set_scattering(ks)
 
     def _check(self, st):
         if st != 0:
@@ -173,6 +179,18 @@ class TTState:
         self._check(self.lib.tt_grad(self.ctx, _pd(w), float(loss_bar), C.byref(L),
                                      C.c_void_p(dkappa.data_ptr())))
         return L.value, dkappa
+
+    def tt_set_scattering(self, kappa_s):
+        """kappa_s: host array of N_s scattering opacities (copied)."""
+        k = _arr(kappa_s)
+        self._check(self.lib.tt_set_scattering(self.ctx, _pd(k)))
+
+    def tt_detector_loss(self, detector_w):
+        """L = dV sum_i w_i E_i of the current state, formed by the library."""
+        w = _arr(detector_w)
+        L = C.c_double()
+        self._check(self.lib.tt_detector_loss(self.ctx, _pd(w), C.byref(L)))
+        return L.value
 
     def cell_volume(self):
         p = self.p

@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtt.so")
 
 TT_OK, TT_ERR_INVALID_ARG, TT_ERR_DEVICE, TT_ERR_OOM, TT_ERR_NUMERIC, TT_ERR_STATE = 0, -1, -2, -3, -4, -5
-TT_BC_VACUUM, TT_BC_PERIODIC, TT_BC_INFLOW = 0, 1, 2
+TT_BC_VACUUM, TT_BC_PERIODIC, TT_BC_INFLOW, TT_BC_OUTFLOW = 0, 1, 2, 3
+TT_FLUX_UPWIND, TT_FLUX_RUSANOV = 0, 1
 TT_FP64, TT_FP32_MIXED = 0, 1
 TT_ROUND_ONCE, TT_ROUND_TWICE = 0, 1
 TT_MAT_FROZEN, TT_MAT_COUPLED = 0, 1
@@ -27,6 +28,7 @@ class tt_config(C.Structure):
         ("precision", C.c_int32), ("schedule", C.c_int32), ("material", C.c_int32),
         ("rank_mode", C.c_int32), ("ckpt_every", C.c_int32), ("max_steps", C.c_int32),
         ("r1_cap", C.c_int32), ("r2_cap", C.c_int32),
+        ("flux", C.c_int32), ("s_plus", C.c_double),
     ]
 
 
@@ -48,6 +50,8 @@ SIGNATURES = {
     "tt_energy": (C.c_int, [VP, VP, PD, PD]),
     "tt_grad": (C.c_int, [VP, PD, C.c_double, PD, VP]),
     "tt_set_kappa": (C.c_int, [VP, VP]),
+    "tt_set_scattering": (C.c_int, [VP, PD]),
+    "tt_detector_loss": (C.c_int, [VP, PD, PD]),
     "tt_get_cores": (C.c_int, [VP, PD, PD, PD, PI]),
     "tt_set_cores": (C.c_int, [VP, PD, PD, PD, PI]),
     "tt_get_temperature": (C.c_int, [VP, PD]),
@@ -73,6 +77,7 @@ SIGNATURES = {
                                       VP, C.c_int32, VP, C.c_size_t, VP]),
     "tt_kernel_gemm": (C.c_int, [VP, C.c_int32, C.c_int32, VP, C.c_int32, C.c_int32, VP, C.c_int32,
                                  C.c_int32, C.c_int32, C.c_int32, VP, C.c_size_t, VP]),
+    "tt_kernel_lds_check": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "tt_kernel_last_error": (C.c_char_p, []),
     "tt_destroy": (None, [VP]),
 }

@@ -114,8 +114,8 @@ constexpr int SYTRD_LDS_MAX = 180;  // packed lower triangle: 16290 doubles of L
 // resident, so an ordinary launch has all blocks resident together (a
 // cooperative launch would drain the queue on every call, also when all jobs
 // are small and the kernel returns at once); every wait is bounded by
-// SYTRD_SPIN_MAX polls, after which the eigensolver flag is raised and the
-// kernel runs out.  Outputs (d, e, tau, reflectors in H) as k_sytrd_lds.
+// SYTRD_SPIN_MAX polls, after which the barrier-timeout flag is raised and
+// the kernel runs out.  Outputs (d, e, tau, reflectors in H) as k_sytrd_lds.
 constexpr int SYTRD_GRID_P = 64;
 constexpr int SYTRD_GRID_T = 256;
 constexpr unsigned SYTRD_SPIN_MAX = 1u << 24;
@@ -164,7 +164,7 @@ __device__ inline void grid_barrier(unsigned* flag, unsigned ordinal, int P, int
       if (++spins > SYTRD_SPIN_MAX) {
         if (lane == 0) {
           *s_abort = 1;
-          atomicOr(&dims[D_FLAG], FLAG_EIG);
+          atomicOr(&dims[D_FLAG], FLAG_BARRIER);
         }
         break;
       }
@@ -1840,6 +1840,73 @@ __global__ __launch_bounds__(256) void k_svd_final(EigJobs jobs, int* __restrict
 }
 
 }  // namespace
+
+// ---- LDS budget of the launches with dynamic LDS -----------------------------
+// A CU has 160 KiB of LDS; a launch asking for more static + dynamic LDS than
+// that fails to dispatch.  These are the static sizes of the kernels launched
+// with dynamic LDS as compiled for gfx950; at run time the larger of this and
+// the runtime's own figure is used.
+namespace {
+constexpr size_t LDS_CU = 160 * 1024;
+constexpr size_t ST_SYTRD_GRID = 168, ST_DC_PREP = 48, ST_DC_SECULAR = 0, ST_DC_VECTORS = 32792,
+                 ST_ORMTR = 0, ST_GEBRD_GRID = 168;
+
+size_t static_lds(const void* fn, size_t table, bool runtime) {
+  if (!runtime) return table;
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, fn) == hipSuccess && (size_t)a.sharedSizeBytes > table)
+    return (size_t)a.sharedSizeBytes;
+  return table;
+}
+
+void lds_note(size_t bytes, const char* name, size_t& worst, const char** which) {
+  if (bytes > worst) {
+    worst = bytes;
+    if (which) *which = name;
+  }
+}
+
+// divide and conquer at order N (eigensolve N, or Golub-Kahan order 2q)
+void dc_lds(int N, bool rt, size_t& worst, const char** which) {
+  for (int S = DC_LEAF; S < N; S *= 2) {
+    lds_note(static_lds((const void*)k_dc_prep, ST_DC_PREP, rt) + (size_t)2 * S * PREP_BYTES_PER,
+             "k_dc_prep", worst, which);
+    lds_note(static_lds((const void*)k_dc_secular, ST_DC_SECULAR, rt) + (size_t)2 * S * 16,
+             "k_dc_secular", worst, which);
+    if (2 * S <= VEC_STAGE_MAX)
+      lds_note(static_lds((const void*)k_dc_vectors<true>, ST_DC_VECTORS, rt) +
+                   (size_t)2 * S * VEC_BYTES_STAGED, "k_dc_vectors<staged>", worst, which);
+    else
+      lds_note(static_lds((const void*)k_dc_vectors<false>, ST_DC_VECTORS, rt) +
+                   (size_t)2 * S * VEC_BYTES_GLOBAL, "k_dc_vectors<global>", worst, which);
+  }
+}
+}  // namespace
+
+size_t eig_lds_bytes(int N, bool runtime, const char** which) {
+  size_t worst = 0;
+  if (N > SYTRD_LDS_MAX)
+    lds_note(static_lds((const void*)k_sytrd_grid, ST_SYTRD_GRID, runtime) + sytrd_grid_lds(N),
+             "k_sytrd_grid", worst, which);
+  dc_lds(N, runtime, worst, which);
+  lds_note(static_lds((const void*)k_ormtr<16>, ST_ORMTR, runtime) +
+               ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8, "k_ormtr", worst, which);
+  return worst;
+}
+
+size_t svd_lds_bytes(int ncap2, int pcap, bool runtime, const char** which) {
+  size_t worst = 0;
+  const int qcap = ncap2 / 2;
+  if (pcap >= GEBRD_GRID_MIN) {
+    const int qc = qcap < pcap ? qcap : pcap;
+    lds_note(static_lds((const void*)k_gebrd_grid, ST_GEBRD_GRID, runtime) + gebrd_grid_lds(pcap, qc),
+             "k_gebrd_grid", worst, which);
+  }
+  dc_lds(ncap2, runtime, worst, which);
+  return worst;
+}
+
+bool lds_fits(size_t bytes) { return bytes <= LDS_CU; }
 
 size_t eig_work_doubles(int N) {
   const size_t N2 = next_pow2(N);

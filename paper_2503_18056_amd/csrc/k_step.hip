@@ -13,6 +13,23 @@
 namespace tt {
 
 // ---------------------------------------------------------------------------
+// Row i + dir e_ax of X with the ghost rule of the face crossed (Sec. 4.5):
+// zero (vacuum; inflow, whose ghost value enters as rank-1 blocks), wrapped
+// (periodic), or row i itself (outflow).
+template <typename TX>
+__device__ inline double neighbour(const StepGeom& G, const TX* __restrict__ X, int ldX, int i,
+                                   const int* coord, int ax, int dir, int a, double self) {
+  const int st = G.stride[ax], na = G.n[ax], ca = coord[ax];
+  if (dir < 0) {
+    if (ca > 0) return (double)X[(long long)(i - st) * ldX + a];
+    if (G.bclo[ax] == TT_BC_PERIODIC) return (double)X[(long long)(i + (na - 1) * st) * ldX + a];
+    return G.bclo[ax] == TT_BC_OUTFLOW ? self : 0.0;
+  }
+  if (ca < na - 1) return (double)X[(long long)(i + st) * ldX + a];
+  if (G.bchi[ax] == TT_BC_PERIODIC) return (double)X[(long long)(i - (na - 1) * st) * ldX + a];
+  return G.bchi[ax] == TT_BC_OUTFLOW ? self : 0.0;
+}
+
 // Spatial core of the concatenation, a wavefront per cell row.
 // TX / TC: element type of X and X_cat (double, or float in the FP32-mixed
 // form; the arithmetic is FP64 and each entry is rounded once on store).
@@ -37,22 +54,18 @@ __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __rest
     double v;
     if (col < nstencil) {
       const int b = col / r1, a = col - b * r1;
-      if (b == 0) {
-        v = (double)xi[a];
+      const double x0 = (double)xi[a];
+      const int kind = G.bkind[b], ax = G.baxis[b];
+      if (kind == BK_BASE) {
+        v = x0;
+      } else if (kind == BK_MINUS) {
+        v = x0 - neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
+      } else if (kind == BK_PLUS) {
+        v = neighbour(G, X, ldX, i, coord, ax, 1, a, x0) - x0;
       } else {
-        const int ax = (b - 1) >> 1;
-        const bool minus = ((b - 1) & 1) == 0;
-        const int st = G.stride[ax], na = G.n[ax], ca = coord[ax];
-        double nb = 0.0;
-        if (minus) {
-          if (ca > 0) nb = (double)X[(long long)(i - st) * ldX + a];
-          else if (G.periodic[ax]) nb = (double)X[(long long)(i + (na - 1) * st) * ldX + a];
-          v = (double)xi[a] - nb;
-        } else {
-          if (ca < na - 1) nb = (double)X[(long long)(i + st) * ldX + a];
-          else if (G.periodic[ax]) nb = (double)X[(long long)(i - (na - 1) * st) * ldX + a];
-          v = nb - (double)xi[a];
-        }
+        const double xm = neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
+        const double xp = neighbour(G, X, ldX, i, coord, ax, 1, a, x0);
+        v = kind == BK_CENTRAL ? 0.5 * (xp - xm) : (xp - 2.0 * x0) + xm;
       }
       v *= di;
     } else if (col < nstencil + G.nbc) {
@@ -153,6 +166,63 @@ __global__ void k_concat_dims(StepGeom G, int* __restrict__ dims) {
   }
 }
 
+// dims of the transport-only concatenation: R = B r + n_bc.
+__global__ void k_transport_dims(StepGeom G, int* __restrict__ dims) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dims[D_RC1] = G.B * dims[D_R1] + G.nbc;
+    dims[D_RC2] = G.B * dims[D_R2] + G.nbc;
+  }
+}
+
+// Source update of the two-rounding schedule as a TT sum: X_cat = [d X, s]
+// (a wavefront per cell row), Theta_cat = blockdiag(Theta, 1), Phi_cat =
+// [Phi; 1] (the source block only when G.nem).  dims[RC] = r + nem is set by
+// the caller's k_source_dims before this kernel.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_source_xcat(StepGeom G, const TX* __restrict__ X, int ldX,
+                                                     const double* __restrict__ d,
+                                                     const double* __restrict__ s,
+                                                     TX* __restrict__ Xc, int ldC,
+                                                     const int* __restrict__ dims) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= G.ns) return;
+  const int lane = threadIdx.x & 63;
+  const int r1 = dims[D_R1];
+  const double di = d[i];
+  const TX* xi = X + (long long)i * ldX;
+  TX* ci = Xc + (long long)i * ldC;
+  for (int a = lane; a < r1; a += 64) ci[a] = (TX)((double)xi[a] * di);
+  if (G.nem && lane == 0) ci[r1] = (TX)s[i];
+}
+__global__ void k_source_dims(StepGeom G, int* __restrict__ dims) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dims[D_RC1] = dims[D_R1] + G.nem;
+    dims[D_RC2] = dims[D_R2] + G.nem;
+  }
+}
+// Theta_cat rows [0, r1 + nem) x nt x R2c and Phi_cat rows [0, R2c).
+__global__ void k_source_angular(StepGeom G, const double* __restrict__ Th,
+                                 const double* __restrict__ Ph, double* __restrict__ Tc,
+                                 double* __restrict__ Pc, const int* __restrict__ dims) {
+  const int r1 = dims[D_R1], r2 = dims[D_R2];
+  const long long tot = (long long)(r1 + G.nem) * G.nt * G.R2c;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int cc = (int)(e % G.R2c);
+    const long long al = e / G.R2c;
+    const int a = (int)(al / G.nt);
+    double v = 0.0;
+    if (a < r1) v = cc < r2 ? Th[al * G.r2c + cc] : 0.0;
+    else v = cc == r2 ? 1.0 : 0.0;
+    Tc[e] = v;
+  }
+  const int tp = G.R2c * G.np;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tp; e += gridDim.x * blockDim.x) {
+    const int row = e / G.np;
+    Pc[e] = row < r2 ? Ph[e] : (row == r2 && G.nem ? 1.0 : 0.0);
+  }
+}
+
 // dims for rounding the stored state itself (no concatenation).
 __global__ void k_round_dims(int* __restrict__ dims) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -225,22 +295,29 @@ __global__ __launch_bounds__(256) void k_row_dot(const TX* __restrict__ X, int l
 }
 
 // ---------------------------------------------------------------------------
-// Source coefficients.  Frozen: T_dag = T.  Coupled: Newton on
-// f(T) = T - T^m + g (a_r T^4 - E*), g = c dt kappa / c_v / (1 + c dt rho kappa),
-// started at max(T^m, (max(E*,0)/a_r)^(1/4)) where f >= 0 (f increasing,
-// convex), stopping at |dT| <= 4u T (at most 50 iterations).
+// Source coefficients (Sec. 3.2).  d = 1 / (1 + c dt rho (kappa + kappa_s)).
+// Frozen: T_dag = T.  Coupled: Newton on
+// f(T) = T - T^m + g (a_r T^4 - E*), g = c dt kappa / c_v / (1 + c dt rho kappa)
+// (kappa_s drops out once J^{m+1} is eliminated), started at
+// max(T^m, (max(E*,0)/a_r)^(1/4)) where f >= 0 (f increasing, convex),
+// stopping at |dT| <= 4u T (at most 50 iterations).
+// s = d (c dt rho kappa_s J^{m+1} + e), e = c dt rho kappa (c/4pi) a_r T_dag^4,
+// J^{m+1} = ((c/4pi) E* + e) / (1 + c dt rho kappa).
 __global__ void k_material(int ns, double c, double dt, double a_r, int coupled,
-                           const double* __restrict__ kappa, const double* __restrict__ rho,
-                           const double* __restrict__ cv, const double* __restrict__ T,
-                           const double* __restrict__ Estar, double* __restrict__ Tdag,
-                           double* __restrict__ d, double* __restrict__ s,
-                           int* __restrict__ dims) {
+                           const double* __restrict__ kappa, const double* __restrict__ kappa_s,
+                           const double* __restrict__ rho, const double* __restrict__ cv,
+                           const double* __restrict__ T, const double* __restrict__ Estar,
+                           double* __restrict__ Tdag, double* __restrict__ d,
+                           double* __restrict__ s, int* __restrict__ dims) {
+  const double c4pi = c / (4.0 * 3.14159265358979323846);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
     const double rk = rho[i] * kappa[i];
-    const double di = 1.0 / (1.0 + c * dt * rk);
+    const double rs = kappa_s ? rho[i] * kappa_s[i] : 0.0;
+    const double da = 1.0 / (1.0 + c * dt * rk);
+    const double di = kappa_s ? 1.0 / (1.0 + c * dt * (rk + rs)) : da;
     double Td = T[i];
     if (coupled) {
-      const double g = c * dt * kappa[i] / cv[i] * di;
+      const double g = c * dt * kappa[i] / cv[i] * da;
       const double Es = Estar[i];
       const double Tm = T[i];
       double x = fmax(Tm, sqrt(sqrt(fmax(Es, 0.0) / a_r)));
@@ -260,8 +337,14 @@ __global__ void k_material(int ns, double c, double dt, double a_r, int coupled,
       Td = x;
     }
     const double T2 = Td * Td;
+    const double e = c * dt * rk * c4pi * a_r * T2 * T2;
+    double si = di * e;
+    if (kappa_s) {
+      const double Jn = (c4pi * Estar[i] + e) / (1.0 + c * dt * rk);
+      si = di * (c * dt * rs * Jn + e);
+    }
     d[i] = di;
-    s[i] = di * c * dt * rk * (c / (4.0 * 3.14159265358979323846)) * a_r * T2 * T2;
+    s[i] = si;
     if (Tdag) Tdag[i] = Td;
   }
 }
@@ -439,6 +522,31 @@ __global__ void k_check_finite(const double* __restrict__ x, int n, int* __restr
     }
 }
 
+// Finiteness of the live state: X (FP64 or FP32), Theta, Phi and T.
+template <typename TX>
+__global__ void k_check_state(const TX* __restrict__ X, int ldX, int ns,
+                              const double* __restrict__ Th, int nt, int r2c,
+                              const double* __restrict__ Ph, int np,
+                              const double* __restrict__ T, int* __restrict__ dims) {
+  const int r1 = dims[D_R1], r2 = dims[D_R2];
+  bool bad = false;
+  const long long nx = (long long)ns * r1;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (long long e = t0; e < nx && !bad; e += stride) {
+    const double v = (double)X[(e / r1) * ldX + e % r1];
+    bad = !(fabs(v) <= 1.79e308);
+  }
+  const long long nth = (long long)r1 * nt * r2;
+  for (long long e = t0; e < nth && !bad; e += stride) {
+    const double v = Th[(e / r2) * r2c + e % r2];
+    bad = !(fabs(v) <= 1.79e308);
+  }
+  for (long long e = t0; e < (long long)r2 * np && !bad; e += stride) bad = !(fabs(Ph[e]) <= 1.79e308);
+  for (long long e = t0; e < ns && !bad; e += stride) bad = !(fabs(T[e]) <= 1.79e308);
+  if (bad) atomicOr(&dims[D_FLAG], FLAG_NONFINITE);
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 void launch_build_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
@@ -511,10 +619,42 @@ void launch_convert(const float* a, int lda, double* b, int ldb, int rows, int c
   k_convert<float, double><<<1024, 256, 0, st>>>(a, lda, b, ldb, rows, cols);
 }
 void launch_material(int ns, double c, double dt, double a_r, int coupled, const double* kappa,
-                     const double* rho, const double* cv, const double* T, const double* Estar,
-                     double* Tdag, double* d, double* s, int* dims, hipStream_t st) {
-  k_material<<<(ns + 255) / 256, 256, 0, st>>>(ns, c, dt, a_r, coupled, kappa, rho, cv, T, Estar,
-                                               Tdag, d, s, dims);
+                     const double* kappa_s, const double* rho, const double* cv, const double* T,
+                     const double* Estar, double* Tdag, double* d, double* s, int* dims,
+                     hipStream_t st) {
+  k_material<<<(ns + 255) / 256, 256, 0, st>>>(ns, c, dt, a_r, coupled, kappa, kappa_s, rho, cv, T,
+                                               Estar, Tdag, d, s, dims);
+}
+void launch_check_state(const double* X, const float* Xf, int ldX, int ns, const double* Th,
+                        int nt, int r2c, const double* Ph, int np, const double* T, int* dims,
+                        hipStream_t st) {
+  if (Xf) k_check_state<float><<<1024, 256, 0, st>>>(Xf, ldX, ns, Th, nt, r2c, Ph, np, T, dims);
+  else k_check_state<double><<<1024, 256, 0, st>>>(X, ldX, ns, Th, nt, r2c, Ph, np, T, dims);
+}
+template <typename TX>
+static void source_cat_impl(const StepGeom& G, const TX* X, int ldX, const double* d,
+                            const double* s, TX* Xc, int ldC, const double* Th, const double* Ph,
+                            double* Tc, double* Pc, int* dims, hipStream_t st) {
+  k_source_dims<<<1, 64, 0, st>>>(G, dims);
+  k_source_xcat<TX><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, d, s, Xc, ldC, dims);
+  const long long tot = (long long)(G.r1c + 1) * G.nt * G.R2c;
+  int blocks = (int)((tot + 255) / 256);
+  if (blocks > 65535) blocks = 65535;
+  if (blocks < 1) blocks = 1;
+  k_source_angular<<<blocks, 256, 0, st>>>(G, Th, Ph, Tc, Pc, dims);
+}
+void launch_source_cat(const StepGeom& G, const double* X, int ldX, const double* d,
+                       const double* s, double* Xc, int ldC, const double* Th, const double* Ph,
+                       double* Tc, double* Pc, int* dims, hipStream_t st) {
+  source_cat_impl(G, X, ldX, d, s, Xc, ldC, Th, Ph, Tc, Pc, dims, st);
+}
+void launch_source_cat(const StepGeom& G, const float* X, int ldX, const double* d,
+                       const double* s, float* Xc, int ldC, const double* Th, const double* Ph,
+                       double* Tc, double* Pc, int* dims, hipStream_t st) {
+  source_cat_impl(G, X, ldX, d, s, Xc, ldC, Th, Ph, Tc, Pc, dims, st);
+}
+void launch_transport_dims(const StepGeom& G, int* dims, hipStream_t st) {
+  k_transport_dims<<<1, 64, 0, st>>>(G, dims);
 }
 void launch_temperature(int ns, const double* rho, const double* cv, const double* Estar,
                         const double* Enew, double* T, hipStream_t st) {

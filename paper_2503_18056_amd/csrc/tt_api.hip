@@ -55,12 +55,17 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
   if (!(c->dt > 0) && !(c->cfl > 0)) { why = "need dt > 0 or cfl > 0"; return false; }
   if (!(c->tol >= 0)) { why = "tol must be >= 0"; return false; }
   if (c->precision != TT_FP64 && c->precision != TT_FP32_MIXED) { why = "bad precision"; return false; }
-  if (c->schedule != TT_ROUND_ONCE) { why = "only TT_ROUND_ONCE is implemented"; return false; }
+  if (c->schedule != TT_ROUND_ONCE && c->schedule != TT_ROUND_TWICE) { why = "bad schedule"; return false; }
+  if (c->flux != TT_FLUX_UPWIND && c->flux != TT_FLUX_RUSANOV) { why = "bad flux"; return false; }
+  if (c->flux == TT_FLUX_RUSANOV && !(c->s_plus >= 0 && c->s_plus < 1e300)) {
+    why = "s_plus must be finite and >= 0";
+    return false;
+  }
   if (c->material != TT_MAT_FROZEN && c->material != TT_MAT_COUPLED) { why = "bad material"; return false; }
   if (c->rank_mode != TT_RANK_AUTO && c->rank_mode != TT_RANK_REPLAY) { why = "bad rank_mode"; return false; }
   for (int a = 0; a < c->dim; ++a) {
     const int lo = c->bc_lo[a], hi = c->bc_hi[a];
-    if (lo < 0 || lo > 2 || hi < 0 || hi > 2) { why = "bad bc code"; return false; }
+    if (lo < 0 || lo > 3 || hi < 0 || hi > 3) { why = "bad bc code"; return false; }
     if ((lo == TT_BC_PERIODIC) != (hi == TT_BC_PERIODIC)) { why = "periodic bc must be paired"; return false; }
   }
   if (n_inflow < 0 || n_inflow > 64) { why = "n_inflow out of range"; return false; }
@@ -69,6 +74,27 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
     why = "ckpt_every > 0 (the adjoint) needs TT_MAT_FROZEN";
     return false;
   }
+  if (c->ckpt_every > 0 && (c->flux != TT_FLUX_UPWIND || c->schedule != TT_ROUND_ONCE)) {
+    why = "ckpt_every > 0 (the adjoint) needs TT_FLUX_UPWIND and TT_ROUND_ONCE";
+    return false;
+  }
+  for (int a = 0; a < c->dim && c->ckpt_every > 0; ++a)
+    if (c->bc_lo[a] == TT_BC_OUTFLOW || c->bc_hi[a] == TT_BC_OUTFLOW) {
+      why = "ckpt_every > 0 (the adjoint) does not cover TT_BC_OUTFLOW";
+      return false;
+    }
+  return true;
+}
+
+// Rusanov with S+ > 0 has a diffusion block per axis and two rank-1 terms
+// per Dirichlet face entry.
+bool rusanov_diffusion(const tt_config& c) { return c.flux == TT_FLUX_RUSANOV && c.s_plus != 0.0; }
+int inflow_blocks(const tt_config& c, int n_inflow) {
+  return n_inflow * (rusanov_diffusion(c) ? 2 : 1);
+}
+bool all_finite(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!(fabs(a[i]) <= 1.79e308)) return false;
   return true;
 }
 
@@ -79,8 +105,9 @@ void geometry(tt_ctx* x, const tt_config& c, int n_inflow, int nem) {
   x->ns = c.nx * c.ny * nz;
   x->nt = c.ntheta;
   x->np = c.nphi;
-  x->B = 1 + 2 * c.dim;
-  x->nbc = n_inflow;
+  const bool rus = c.flux == TT_FLUX_RUSANOV, dif = rusanov_diffusion(c);
+  x->B = rus ? 1 + (dif ? 2 : 1) * c.dim : 1 + 2 * c.dim;
+  x->nbc = inflow_blocks(c, n_inflow);
   x->nem = nem;
   const long long big = 1LL << 30;
   long long cap1 = std::min<long long>(x->ns, (long long)x->nt * x->np);
@@ -109,7 +136,22 @@ void geometry(tt_ctx* x, const tt_config& c, int n_inflow, int nem) {
   G.ns = x->ns; G.nx = c.nx; G.ny = c.ny; G.nz = nz;
   G.n[0] = c.nx; G.n[1] = c.ny; G.n[2] = nz;
   G.stride[0] = 1; G.stride[1] = c.nx; G.stride[2] = c.nx * c.ny;
-  for (int a = 0; a < 3; ++a) G.periodic[a] = a < c.dim && c.bc_lo[a] == TT_BC_PERIODIC;
+  for (int a = 0; a < 3; ++a) {
+    G.periodic[a] = a < c.dim && c.bc_lo[a] == TT_BC_PERIODIC;
+    G.bclo[a] = a < c.dim ? c.bc_lo[a] : TT_BC_VACUUM;
+    G.bchi[a] = a < c.dim ? c.bc_hi[a] : TT_BC_VACUUM;
+  }
+  // transport blocks: base, then per axis (minus, plus) or (central[, diffusion])
+  for (int b = 0; b < MAX_BLOCKS; ++b) { G.bkind[b] = BK_BASE; G.baxis[b] = 0; }
+  for (int a = 0, b = 1; a < c.dim; ++a) {
+    if (rus) {
+      G.bkind[b] = BK_CENTRAL; G.baxis[b++] = a;
+      if (dif) { G.bkind[b] = BK_DIFF; G.baxis[b++] = a; }
+    } else {
+      G.bkind[b] = BK_MINUS; G.baxis[b++] = a;
+      G.bkind[b] = BK_PLUS; G.baxis[b++] = a;
+    }
+  }
   G.nt = x->nt; G.np = x->np; G.B = x->B; G.nbc = x->nbc; G.nem = x->nem;
   G.r1c = x->r1c; G.r2c = x->r2c; G.R1c = x->R1c; G.R2c = x->R2c;
 }
@@ -120,7 +162,8 @@ size_t carve(tt_ctx* x, char* base) {
   const int ms = std::max(1, x->cfg.max_steps);
   x->dims = cv.take<int>(D_NDIMS);
   x->hist = cv.take<int>(2 * (size_t)ms);
-  x->sched = cv.take<int>(2 * (size_t)ms);
+  // one replay entry per rounding: two per step with TT_ROUND_TWICE
+  x->sched = cv.take<int>(2 * (size_t)ms * (x->cfg.schedule == TT_ROUND_TWICE ? 2 : 1));
   x->diag = cv.take<double>(G_NDIAG);
   x->w = cv.take<double>(nt);
   x->v = cv.take<double>(np);
@@ -129,8 +172,10 @@ size_t carve(tt_ctx* x, char* base) {
   x->bc_e = cv.take<double>((size_t)std::max(1, x->nbc) * ns);
   x->bc_t = cv.take<double>((size_t)std::max(1, x->nbc) * nt);
   x->bc_p = cv.take<double>((size_t)std::max(1, x->nbc) * np);
-  double** fields[] = {&x->kappa, &x->rho, &x->cv, &x->T, &x->d, &x->s, &x->Estar, &x->Enew, &x->Tdag};
+  double** fields[] = {&x->kappa, &x->rho, &x->cv, &x->T, &x->d, &x->s, &x->Estar, &x->Enew, &x->Tdag,
+                       &x->kappa_s, &x->wbuf};
   for (double** f : fields) *f = cv.take<double>(ns);
+  x->lossbuf = cv.take<double>(8);
   x->X = cv.take<double>((size_t)ns * x->ldX);
   x->Xn = cv.take<double>((size_t)ns * x->ldX);
   x->Th = cv.take<double>((size_t)x->r1c * nt * x->r2c);
@@ -210,29 +255,25 @@ void host_factors(const tt_ctx* x, std::vector<double>& w, std::vector<double>& 
   }
   tf.assign((size_t)x->B * nt, 0.0);
   pf.assign((size_t)x->B * np, 0.0);
-  for (int l = 0; l < nt; ++l) tf[l] = 1.0;
-  for (int p = 0; p < np; ++p) pf[p] = 1.0;
-  for (int a = 0; a < x->dim; ++a) {
-    const int bm = 1 + 2 * a, bp = 2 + 2 * a;
+  const StepGeom& G = x->G;
+  for (int b = 0; b < x->B; ++b) {
+    const int a = G.baxis[b], kind = G.bkind[b];
     const double lam = x->lam[a];
     for (int l = 0; l < nt; ++l) {
-      if (a < 2) {
-        tf[bm * nt + l] = sint[l];
-        tf[bp * nt + l] = sint[l];
-      } else {
-        tf[bm * nt + l] = std::max(mu[l], 0.0);
-        tf[bp * nt + l] = std::min(mu[l], 0.0);
-      }
+      double t = 1.0;  // base and Rusanov diffusion blocks: isotropic in theta
+      if (kind == BK_MINUS) t = a < 2 ? sint[l] : std::max(mu[l], 0.0);
+      else if (kind == BK_PLUS) t = a < 2 ? sint[l] : std::min(mu[l], 0.0);
+      else if (kind == BK_CENTRAL) t = a < 2 ? sint[l] : mu[l];
+      tf[(size_t)b * nt + l] = t;
     }
     for (int p = 0; p < np; ++p) {
-      if (a < 2) {
-        const double n = a == 0 ? cosp[p] : sinp[p];
-        pf[bm * np + p] = -lam * std::max(n, 0.0);
-        pf[bp * np + p] = -lam * std::min(n, 0.0);
-      } else {
-        pf[bm * np + p] = -lam;
-        pf[bp * np + p] = -lam;
-      }
+      const double n = a == 0 ? cosp[p] : a == 1 ? sinp[p] : 1.0;
+      double f = 1.0;
+      if (kind == BK_MINUS) f = a < 2 ? -lam * std::max(n, 0.0) : -lam;
+      else if (kind == BK_PLUS) f = a < 2 ? -lam * std::min(n, 0.0) : -lam;
+      else if (kind == BK_CENTRAL) f = -lam * n;
+      else if (kind == BK_DIFF) f = 0.5 * lam * x->cfg.s_plus;
+      pf[(size_t)b * np + p] = f;
     }
   }
 }
@@ -456,7 +497,9 @@ tt_status check_flags(tt_ctx* c) {
     std::string m = "numerical failure:";
     if (flag & FLAG_NONFINITE) m += " non-finite state";
     if (flag & FLAG_NEWTON) m += " Newton did not converge";
-    if (flag & FLAG_EIG) m += " eigensolver produced NaN";
+    if (flag & FLAG_EIG) m += " eigensolver produced a non-finite value";
+    if (flag & FLAG_BARRIER)
+      m += " a grid barrier of a multi-block eigensolver timed out (blocks not co-resident)";
     return fail(c, TT_ERR_NUMERIC, m);
   }
   return TT_OK;
@@ -528,6 +571,7 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
   geometry(c, *cfg, n_inflow, 1);  // emission slot always reserved
   const int nem = emission_flag(*cfg, T0, ns);
   c->nem = nem;
+  c->nem_base = nem;
   c->G.nem = nem;
   c->st = (hipStream_t)hip_stream;
   for (int k = 0; k < n_inflow; ++k) {
@@ -541,10 +585,33 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
       delete c;
       return fail(nullptr, TT_ERR_INVALID_ARG, "inflow term on a face whose bc is not TT_BC_INFLOW");
     }
+    const size_t nface = face_cells(c, f).size();
+    if (!all_finite(inflow[k].face_w, nface) || !all_finite(inflow[k].theta_w, c->nt) ||
+        !all_finite(inflow[k].phi_w, c->np)) {
+      delete c;
+      return fail(nullptr, TT_ERR_INVALID_ARG, "non-finite inflow weights");
+    }
   }
   if (r1 < 1 || r2 < 1 || r1 > c->r1c || r2 > c->r2c) {
     delete c;
     return fail(nullptr, TT_ERR_INVALID_ARG, "initial ranks exceed the rank capacity");
+  }
+  {
+    // host inputs: finite, and in range, before any device work
+    std::string bad;
+    for (int i = 0; i < ns && bad.empty(); ++i) {
+      if (!(kappa[i] >= 0 && kappa[i] <= 1.79e308)) bad = "kappa must be finite and >= 0";
+      else if (rho && !(rho[i] > 0 && rho[i] <= 1.79e308)) bad = "rho must be finite and > 0";
+      else if (cv && !(cv[i] > 0 && cv[i] <= 1.79e308)) bad = "cv must be finite and > 0";
+      else if (!(T0[i] >= 0 && T0[i] <= 1.79e308)) bad = "T0 must be finite and >= 0";
+    }
+    if (bad.empty() && (!all_finite(X0, (size_t)ns * r1) || !all_finite(Th0, (size_t)r1 * c->nt * r2) ||
+                        !all_finite(Ph0, (size_t)r2 * c->np)))
+      bad = "non-finite initial cores";
+    if (!bad.empty()) {
+      delete c;
+      return fail(nullptr, TT_ERR_INVALID_ARG, bad);
+    }
   }
   if (c->N > 1024) {
     delete c;
@@ -554,6 +621,18 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
   if (!dev_workspace || ws_bytes < c->ws_need) {
     delete c;
     return fail(nullptr, TT_ERR_OOM, "workspace too small: need " + std::to_string(tt_workspace_bytes(cfg, n_inflow)) + " bytes");
+  }
+  {
+    // every eigensolver / SVD launch of a step must fit one CU's LDS
+    const char *w1 = "", *w2 = "", *w3 = "", *w4 = "";
+    const size_t l1 = eig_lds_bytes(c->N, true, &w1), l2 = eig_lds_bytes(c->R2c, true, &w2);
+    const size_t l3 = svd_lds_bytes(2 * c->q1c, c->R1c, true, &w3);
+    const size_t l4 = svd_lds_bytes(2 * c->q2c, c->R2c, true, &w4);
+    const char* bad = !lds_fits(l1) ? w1 : !lds_fits(l2) ? w2 : !lds_fits(l3) ? w3 : !lds_fits(l4) ? w4 : nullptr;
+    if (bad) {
+      delete c;
+      return fail(nullptr, TT_ERR_INVALID_ARG, std::string("LDS above 160 KiB in ") + bad);
+    }
   }
   carve(c, (char*)dev_workspace);
   hipStream_t s = c->st;
@@ -565,26 +644,34 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
   HIPCHK(nullptr, hipMemcpyAsync(c->tfac, tf.data(), tf.size() * 8, hipMemcpyHostToDevice, s));
   HIPCHK(nullptr, hipMemcpyAsync(c->pfac, pf.data(), pf.size() * 8, hipMemcpyHostToDevice, s));
   // inflow rank-1 terms: e (x) tpart (x) ppart
-  std::vector<double> be((size_t)std::max(1, n_inflow) * ns, 0.0), bt((size_t)std::max(1, n_inflow) * c->nt, 0.0),
-      bp((size_t)std::max(1, n_inflow) * c->np, 0.0);
+  const int nbk = std::max(1, c->nbc);
+  std::vector<double> be((size_t)nbk * ns, 0.0), bt((size_t)nbk * c->nt, 0.0), bp((size_t)nbk * c->np, 0.0);
+  // Dirichlet ghost value g = face_w (x) theta_w (x) phi_w of each entry: the
+  // part of the flux through its face that the stencil blocks (ghost rows
+  // zero) leave out, as rank-1 terms e_face (x) t (x) p (Sec. 4.5).
+  const bool rus = cfg->flux == TT_FLUX_RUSANOV, dif = rusanov_diffusion(*cfg);
+  const int per = dif ? 2 : 1;
   for (int k = 0; k < n_inflow; ++k) {
     const int f = inflow[k].face, a = f / 2, hi = f % 2;
     std::vector<int> cells = face_cells(c, f);
-    for (size_t q = 0; q < cells.size(); ++q) be[(size_t)k * ns + cells[q]] = inflow[k].face_w[q];
     const double lam = c->lam[a];
-    for (int l = 0; l < c->nt; ++l) {
-      double tfv = a < 2 ? sint[l] : (hi ? std::min(mu[l], 0.0) : std::max(mu[l], 0.0));
-      bt[(size_t)k * c->nt + l] = tfv * inflow[k].theta_w[l];
-    }
-    for (int p = 0; p < c->np; ++p) {
-      double pfv;
-      if (a < 2) {
-        const double n = a == 0 ? cosp[p] : sinp[p];
-        pfv = hi ? -lam * std::min(n, 0.0) : lam * std::max(n, 0.0);
-      } else {
-        pfv = hi ? -lam : lam;
+    for (int j = 0; j < per; ++j) {
+      const size_t kb = (size_t)k * per + j;  // rank-1 term index
+      for (size_t q = 0; q < cells.size(); ++q) be[kb * ns + cells[q]] = inflow[k].face_w[q];
+      for (int l = 0; l < c->nt; ++l) {
+        double tfv;
+        if (rus) tfv = j == 1 ? 1.0 : (a < 2 ? sint[l] : mu[l]);
+        else tfv = a < 2 ? sint[l] : (hi ? std::min(mu[l], 0.0) : std::max(mu[l], 0.0));
+        bt[kb * c->nt + l] = tfv * inflow[k].theta_w[l];
       }
-      bp[(size_t)k * c->np + p] = pfv * inflow[k].phi_w[p];
+      for (int p = 0; p < c->np; ++p) {
+        const double n = a == 0 ? cosp[p] : a == 1 ? sinp[p] : 1.0;
+        double pfv;
+        if (rus) pfv = j == 1 ? 0.5 * lam * cfg->s_plus : (hi ? -0.5 : 0.5) * lam * n;
+        else if (a < 2) pfv = hi ? -lam * std::min(n, 0.0) : lam * std::max(n, 0.0);
+        else pfv = hi ? -lam : lam;
+        bp[kb * c->np + p] = pfv * inflow[k].phi_w[p];
+      }
     }
   }
   if (n_inflow > 0) {
@@ -617,6 +704,9 @@ tt_status tt_set_cores(tt_ctx* c, const double* X, const double* Th, const doubl
   if (!c || !X || !Th || !Ph || !r) return fail(c, TT_ERR_INVALID_ARG, "null argument");
   if (r[0] < 1 || r[1] < 1 || r[0] > c->r1c || r[1] > c->r2c)
     return fail(c, TT_ERR_INVALID_ARG, "ranks exceed the rank capacity");
+  if (!all_finite(X, (size_t)c->ns * r[0]) || !all_finite(Th, (size_t)r[0] * c->nt * r[1]) ||
+      !all_finite(Ph, (size_t)r[1] * c->np))
+    return fail(c, TT_ERR_INVALID_ARG, "non-finite cores");
   hipStream_t s = c->st;
   // the padded device layouts are filled from host staging copies by plain
   // 1D transfers (kept alive until the synchronisation below)
@@ -634,9 +724,9 @@ tt_status tt_set_cores(tt_ctx* c, const double* X, const double* Th, const doubl
   hd[D_R1] = r[0];
   hd[D_R2] = r[1];
   HIPCHK(c, hipMemcpyAsync(c->dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
-  // frozen material: the source coefficients never change
-  launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, c->rho, c->cv, c->T, c->Estar,
-                  c->Tdag, c->d, c->s, c->dims, s);
+  // frozen material without scattering: the source coefficients never change
+  launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, nullptr, c->rho, c->cv, c->T,
+                  c->Estar, c->Tdag, c->d, c->s, c->dims, s);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(s));
   c->poisoned = false;
@@ -653,49 +743,99 @@ tt_status tt_step(tt_ctx* c, int32_t nsteps) {
   hipStream_t s = c->st;
   const tt_config& cf = c->cfg;
   const bool coupled = cf.material == TT_MAT_COUPLED;
+  // the source coefficients depend on this step's E* (Newton, or J^{m+1})
+  const bool dyn = coupled || c->scatter;
+  const double* ks = c->scatter ? c->kappa_s : nullptr;
+  const bool twice = cf.schedule == TT_ROUND_TWICE;
   if (c->gb.on && c->nhist + nsteps > std::max(1, cf.max_steps))
     return fail(c, TT_ERR_STATE, "tape full: more steps since tt_set_cores than max_steps");
-  for (int m = 0; m < nsteps; ++m) {
-    Prof pstep(c, P_STEP);
-    if (c->gb.on) HIPCHK(c, grad_record(c));
+  auto replay_next = [&]() {
     if (cf.rank_mode == TT_RANK_REPLAY) {
       k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->sched_pos, c->nsched);
       c->sched_pos++;
     }
-    {
-      Prof p(c, P_CONCAT);
-      launch_concat_dims(c->G, c->dims, s);
-      launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
-      launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
-      if (c->mixed)
-        launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims,
-                          coupled ? 0 : 1, s);
-      else
-        launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
-                          coupled ? 0 : 1, s);
-    }
-    if (coupled) {
-      Prof p(c, P_MAT);
-      // E* = (1/c) X_tr z over the transport columns (emission column excluded)
-      if (c->mixed)
-        launch_energy(c->Xcatf, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
-                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
-                      c->Estar, c->dims, c->R1c, c->R2c, s);
-      else
-        launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
-                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
-                      c->Estar, c->dims, c->R1c, c->R2c, s);
-      launch_material(c->ns, cf.c, c->dt, cf.a_r, 1, c->kappa, c->rho, c->cv, c->T, c->Estar,
-                      c->Tdag, c->d, c->s, c->dims, s);
-      if (c->mixed) launch_scale_xcat(c->G, c->d, c->s, c->Xcatf, c->ldC, c->dims, s);
-      else launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
-    }
-    if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
-    else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
-    launch_finish(c->dims, c->hist, c->nhist < std::max(1, cf.max_steps) ? c->nhist : -1, s);
-    c->nhist = std::min(c->nhist + 1, std::max(1, cf.max_steps));
+  };
+  auto swap_state = [&]() {
     if (c->mixed) std::swap(c->Xf, c->Xnf);
     else std::swap(c->X, c->Xn);
+  };
+  for (int m = 0; m < nsteps; ++m) {
+    Prof pstep(c, P_STEP);
+    if (c->gb.on) HIPCHK(c, grad_record(c));
+    replay_next();
+    const int slot = c->nhist < std::max(1, cf.max_steps) ? c->nhist : -1;
+    if (!twice) {
+      {
+        Prof p(c, P_CONCAT);
+        launch_concat_dims(c->G, c->dims, s);
+        launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
+        launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
+        if (c->mixed)
+          launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims,
+                            dyn ? 0 : 1, s);
+        else
+          launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
+                            dyn ? 0 : 1, s);
+      }
+      if (dyn) {
+        Prof p(c, P_MAT);
+        // E* = (1/c) X_tr z over the transport columns (source column excluded)
+        if (c->mixed)
+          launch_energy(c->Xcatf, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
+                        c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
+                        c->Estar, c->dims, c->R1c, c->R2c, s);
+        else
+          launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
+                        c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
+                        c->Estar, c->dims, c->R1c, c->R2c, s);
+        launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
+                        c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
+        if (c->mixed) launch_scale_xcat(c->G, c->d, c->s, c->Xcatf, c->ldC, c->dims, s);
+        else launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
+      }
+      if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
+      else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
+    } else {
+      // Sec. 4.2: round the transport sum, apply the source update to the
+      // rounded state, round again
+      StepGeom Gt = c->G;
+      Gt.nem = 0;
+      {
+        Prof p(c, P_CONCAT);
+        launch_transport_dims(Gt, c->dims, s);
+        launch_build_phcat(Gt, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
+        launch_build_thcat(Gt, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
+        if (c->mixed)
+          launch_build_xcat(Gt, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims, 0, s);
+        else
+          launch_build_xcat(Gt, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims, 0, s);
+      }
+      if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
+      else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
+      launch_finish(c->dims, nullptr, -1, s);
+      swap_state();
+      if (dyn) {
+        Prof p(c, P_MAT);
+        energy_of_state(c, c->Estar);
+        launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
+                        c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
+      }
+      replay_next();
+      {
+        Prof p(c, P_CONCAT);
+        if (c->mixed)
+          launch_source_cat(c->G, c->Xf, c->ldX, c->d, c->s, c->Xcatf, c->ldC, c->Th, c->Ph,
+                            c->Thcat, c->Phcat, c->dims, s);
+        else
+          launch_source_cat(c->G, c->X, c->ldX, c->d, c->s, c->Xcat, c->ldC, c->Th, c->Ph,
+                            c->Thcat, c->Phcat, c->dims, s);
+      }
+      if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->r1c + 1, cf.tol, cf.rmax, c->Xcatf);
+      else round_pipeline(c, c->Xcat, c->ldC, c->r1c + 1, cf.tol, cf.rmax);
+    }
+    launch_finish(c->dims, c->hist, slot, s);
+    c->nhist = std::min(c->nhist + 1, std::max(1, cf.max_steps));
+    swap_state();
     if (coupled) {
       Prof p(c, P_MAT);
       energy_of_state(c, c->Enew);
@@ -703,7 +843,8 @@ tt_status tt_step(tt_ctx* c, int32_t nsteps) {
     }
   }
   HIPCHK(c, hipGetLastError());
-  launch_check_finite(c->Ph, c->np, c->dims, s);
+  launch_check_state(c->X, c->mixed ? c->Xf : nullptr, c->ldX, c->ns, c->Th, c->nt, c->r2c, c->Ph,
+                     c->np, c->T, c->dims, s);
   return check_flags(c);
 }
 
@@ -712,6 +853,8 @@ tt_status tt_round(tt_ctx* c, double tol, int32_t rmax, int32_t ranks_out[2]) {
   if (c->poisoned) return fail(c, TT_ERR_STATE, "context poisoned");
   if (!(tol >= 0)) return fail(c, TT_ERR_INVALID_ARG, "tol must be >= 0");
   hipStream_t s = c->st;
+  // the recorded steps no longer end in the stored state
+  if (c->gb.on && c->nhist > 0) c->gb.stale = true;
   if (c->cfg.rank_mode == TT_RANK_REPLAY) {
     k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->sched_pos, c->nsched);
     c->sched_pos++;
@@ -764,10 +907,46 @@ tt_status tt_set_kappa(tt_ctx* c, const double* kappa_dev) {
   if (!c || !kappa_dev) return fail(c, TT_ERR_INVALID_ARG, "null argument");
   HIPCHK(c, hipMemcpyAsync(c->kappa, kappa_dev, c->ns * 8, hipMemcpyDeviceToDevice, c->st));
   if (c->nhist > 0) c->gb.stale = true;  // the taped steps used the old opacity
-  launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, c->rho, c->cv, c->T, c->Estar,
-                  c->Tdag, c->d, c->s, c->dims, c->st);
+  launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, nullptr, c->rho, c->cv, c->T,
+                  c->Estar, c->Tdag, c->d, c->s, c->dims, c->st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->st));
+  return TT_OK;
+}
+
+tt_status tt_set_scattering(tt_ctx* c, const double* kappa_s) {
+  if (!c || !kappa_s) return fail(c, TT_ERR_INVALID_ARG, "null argument");
+  if (c->cfg.ckpt_every > 0)
+    return fail(c, TT_ERR_INVALID_ARG, "scattering is not covered by the adjoint (ckpt_every > 0)");
+  bool any = false;
+  for (int i = 0; i < c->ns; ++i) {
+    if (!(kappa_s[i] >= 0 && kappa_s[i] <= 1.79e308))
+      return fail(c, TT_ERR_INVALID_ARG, "kappa_s must be finite and >= 0");
+    any = any || kappa_s[i] > 0;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->kappa_s, kappa_s, c->ns * 8, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->scatter = any;
+  // the isotropic source block carries the scattering term
+  c->nem = (c->nem_base || any) ? 1 : 0;
+  c->G.nem = c->nem;
+  return TT_OK;
+}
+
+tt_status tt_detector_loss(tt_ctx* c, const double* detector_w, double* loss_out) {
+  if (!c || !detector_w || !loss_out) return fail(c, TT_ERR_INVALID_ARG, "null argument");
+  if (!all_finite(detector_w, c->ns)) return fail(c, TT_ERR_INVALID_ARG, "non-finite detector weights");
+  hipStream_t s = c->st;
+  HIPCHK(c, hipMemcpyAsync(c->wbuf, detector_w, c->ns * 8, hipMemcpyHostToDevice, s));
+  energy_of_state(c, c->Enew);
+  launch_wdot(c->wbuf, c->Enew, c->ns, c->lossbuf, s);
+  HIPCHK(c, hipGetLastError());
+  double L = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&L, c->lossbuf, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const double dV = (c->cfg.lx / c->cfg.nx) * (c->cfg.ly / c->cfg.ny) *
+                    (c->cfg.dim == 3 ? c->cfg.lz / c->cfg.nz : 1.0);
+  *loss_out = L * dV;
   return TT_OK;
 }
 
@@ -820,8 +999,9 @@ tt_status tt_get_rank_history(tt_ctx* c, int32_t* buf, int32_t cap, int32_t* n) 
 
 tt_status tt_set_rank_schedule(tt_ctx* c, const int32_t* r1r2, int32_t nroundings) {
   if (!c || (nroundings > 0 && !r1r2)) return fail(c, TT_ERR_INVALID_ARG, "null argument");
-  if (nroundings < 0 || nroundings > std::max(1, c->cfg.max_steps))
-    return fail(c, TT_ERR_INVALID_ARG, "schedule longer than max_steps");
+  const int per_step = c->cfg.schedule == TT_ROUND_TWICE ? 2 : 1;
+  if (nroundings < 0 || nroundings > per_step * std::max(1, c->cfg.max_steps))
+    return fail(c, TT_ERR_INVALID_ARG, "schedule longer than the roundings of max_steps steps");
   for (int k = 0; k < 2 * nroundings; ++k)
     if (r1r2[k] < 1 || r1r2[k] > (k % 2 ? c->r2c : c->r1c))
       return fail(c, TT_ERR_INVALID_ARG, "scheduled rank exceeds the rank capacity");

@@ -91,6 +91,10 @@ struct tt_ctx {
   double* diag;
   double *w, *v, *tfac, *pfac, *bc_e, *bc_t, *bc_p;
   double *kappa, *rho, *cv, *T, *d, *s, *Estar, *Enew, *Tdag;
+  double* kappa_s;           // scattering opacity (zero unless tt_set_scattering)
+  double *wbuf, *lossbuf;    // detector weights and the loss of tt_detector_loss
+  bool scatter = false;      // some kappa_s > 0: the source depends on E* every step
+  int nem_base = 0;          // source block present without scattering
   double *X, *Xn, *Th, *Ph;
   bool mixed = false;        // TT_FP32_MIXED: X and X_cat stored in FP32
   float *Xf, *Xnf, *Xcatf;   // FP32 state / update / concatenation (mixed form only)

@@ -369,7 +369,9 @@ extern "C" tt_status tt_grad(tt_ctx* c, const double* detector_w, double loss_ba
   if (!g.on) return ctx_fail(c, TT_ERR_STATE, "no tape: the context was created with ckpt_every <= 0");
   if (c->poisoned) return ctx_fail(c, TT_ERR_STATE, "context poisoned by an earlier numerical failure");
   if (c->nhist == 0) return ctx_fail(c, TT_ERR_STATE, "no steps taped since tt_set_cores");
-  if (g.stale) return ctx_fail(c, TT_ERR_STATE, "kappa changed after the steps were taped");
+  if (g.stale)
+    return ctx_fail(c, TT_ERR_STATE,
+                    "the tape is stale: tt_set_kappa or tt_round after the recorded steps");
   hipStream_t s = c->st;
   const int nsteps = c->nhist, ns = c->ns;
   const tt_config& cf = c->cfg;

@@ -43,6 +43,7 @@ enum : int {
   FLAG_NONFINITE = 1,
   FLAG_NEWTON = 2,
   FLAG_EIG = 4,
+  FLAG_BARRIER = 8,  // a grid barrier of a multi-block eigensolver timed out
 };
 
 // diagnostics (double table)
@@ -180,5 +181,14 @@ void eig_batched(const EigJob* jobs, int njobs, int ncap, int* dims, hipStream_t
 // max(a, b) <= pcap <= 1024.
 void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx,
                     const EigJob& job, int ncap2, int pcap, int* dims, hipStream_t s);
+
+// Largest static + dynamic LDS (bytes) of the launches of eig_batched at
+// capacity N, and of svd_short_side at Golub-Kahan capacity ncap2 and longer
+// side pcap; `which` (may be null) names that kernel.  runtime: take the
+// static sizes from the HIP runtime where it reports more.  lds_fits: within
+// the 160 KiB of one CU.
+size_t eig_lds_bytes(int N, bool runtime, const char** which);
+size_t svd_lds_bytes(int ncap2, int pcap, bool runtime, const char** which);
+bool lds_fits(size_t bytes);
 
 }  // namespace tt

@@ -21,11 +21,23 @@ tt_status kfail(tt_status s, const std::string& m) {
   } while (0)
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace
 
 extern "C" {
 
 const char* tt_kernel_last_error(void) { return k_err.c_str(); }
+
+tt_status tt_kernel_lds_check(int32_t n, int32_t ncap2, int32_t pcap, size_t* max_bytes) {
+  if (n < 0 || ncap2 < 0 || pcap < 0) return kfail(TT_ERR_INVALID_ARG, "negative size");
+  const char *w1 = "", *w2 = "";
+  const size_t a = n > 0 ? eig_lds_bytes(n, false, &w1) : 0;
+  const size_t b = ncap2 > 0 ? svd_lds_bytes(ncap2, pcap, false, &w2) : 0;
+  if (max_bytes) *max_bytes = a > b ? a : b;
+  if (!lds_fits(a) || !lds_fits(b))
+    return kfail(TT_ERR_INVALID_ARG, std::string("LDS above 160 KiB in ") + (lds_fits(a) ? w2 : w1));
+  return TT_OK;
+}
 
 size_t tt_kernel_eigh_workspace(int32_t n) {
   if (n < 1 || n > 1024) return 0;
@@ -39,6 +51,12 @@ tt_status tt_kernel_eigh(const double* A, int32_t n, int32_t lda, double clip, d
   if (!A || !lam || !V || !ws || n < 1 || n > 1024 || lda < n || ldv < n)
     return kfail(TT_ERR_INVALID_ARG, "bad eigh arguments");
   if (ws_bytes < tt_kernel_eigh_workspace(n)) return kfail(TT_ERR_OOM, "workspace too small");
+  {
+    const char* which = "";
+    const size_t lds = eig_lds_bytes(n, true, &which);
+    if (!lds_fits(lds))
+      return kfail(TT_ERR_INVALID_ARG, std::string("LDS above 160 KiB in ") + which);
+  }
   hipStream_t s = (hipStream_t)stream;
   char* p = (char*)ws;
   int* dims = (int*)p;
@@ -80,6 +98,12 @@ tt_status tt_kernel_svd(const double* M, int32_t a, int32_t b, int32_t ldm, doub
   if (!M || !sig || !V || !ws || a < 1 || b < 1 || q > 1024 || p > 1024 || ldm < b || ldv < q)
     return kfail(TT_ERR_INVALID_ARG, "bad svd arguments");
   if (ws_bytes < tt_kernel_svd_workspace(a, b)) return kfail(TT_ERR_OOM, "workspace too small");
+  {
+    const char* which = "";
+    const size_t lds = svd_lds_bytes(2 * q, p, true, &which);
+    if (!lds_fits(lds))
+      return kfail(TT_ERR_INVALID_ARG, std::string("LDS above 160 KiB in ") + which);
+  }
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   int* dims = (int*)w;

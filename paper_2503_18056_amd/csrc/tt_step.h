@@ -1,13 +1,24 @@
 // Geometry of one context and the launchers of the per-step kernels.
 #pragma once
 
+#include "../../include/tt.h"
 #include "tt_internal.h"
 
 namespace tt {
 
+// Stencil of a transport block of the spatial core (Sec. 4.3): the base
+// block X, the upwind differences X_i - X_{i-e} and X_{i+e} - X_i, and the
+// Rusanov central difference (X_{i+e} - X_{i-e}) / 2 and diffusion
+// X_{i+e} - 2 X_i + X_{i-e}.
+enum : int { BK_BASE = 0, BK_MINUS = 1, BK_PLUS = 2, BK_CENTRAL = 3, BK_DIFF = 4 };
+constexpr int MAX_BLOCKS = 8;
+
 struct StepGeom {
   int ns, nx, ny, nz;
   int n[3], stride[3], periodic[3];
+  int bclo[3], bchi[3];   // TT_BC_* of each face (axes >= dim: vacuum)
+  int bkind[MAX_BLOCKS];  // BK_* of transport block b (b < B)
+  int baxis[MAX_BLOCKS];  // its axis
   int nt, np;
   int B;        // transport blocks: 1 + 2 dim
   int nbc;      // rank-1 inflow terms
@@ -56,9 +67,14 @@ void launch_energy(const double* X, int ldX, int ns, const double* Th, int nt, i
                    const double* Ph, int np, const double* w, const double* v, double* pv,
                    double* z, DimExpr r1, DimExpr r2, double inv_c, double* E, const int* dims,
                    int rcap1, int rcap2, hipStream_t st);
+// Source coefficients (Sec. 3.2): d = 1 / (1 + c dt rho (kappa + kappa_s)),
+// s = d (c dt rho kappa_s J^{m+1} + c dt rho kappa (c/4pi) a_r T_dag^4); T_dag
+// from Newton when coupled; kappa_s may be null (no scattering), else Estar
+// is the post-transport energy density.
 void launch_material(int ns, double c, double dt, double a_r, int coupled, const double* kappa,
-                     const double* rho, const double* cv, const double* T, const double* Estar,
-                     double* Tdag, double* d, double* s, int* dims, hipStream_t st);
+                     const double* kappa_s, const double* rho, const double* cv, const double* T,
+                     const double* Estar, double* Tdag, double* d, double* s, int* dims,
+                     hipStream_t st);
 void launch_temperature(int ns, const double* rho, const double* cv, const double* Estar,
                         const double* Enew, double* T, hipStream_t st);
 void launch_mside(int* dims, int ka, int kb, int km, int side, DimExpr abound, DimExpr bbound,
@@ -69,6 +85,24 @@ void launch_svd_vectors(const double* Uc, int ldu, const double* sqc, double* Ur
                         int zero, int rcap, hipStream_t st);
 void launch_finish(int* dims, int* hist, int slot, hipStream_t st);
 void launch_check_finite(const double* x, int n, int* dims, hipStream_t st);
+// Finiteness of the state: X (N_s x r1 live, ld ldX), Theta (r1 x nt x r2
+// live, ld r2c), Phi (r2 x np) and T (N_s); raises FLAG_NONFINITE.
+void launch_check_state(const double* X, const float* Xf, int ldX, int ns, const double* Th,
+                        int nt, int r2c, const double* Ph, int np, const double* T, int* dims,
+                        hipStream_t st);
+// Concatenation of the source update of the two-rounding schedule
+// (Sec. 4.2): X_cat = [d X, s], Theta_cat = blockdiag(Theta, 1),
+// Phi_cat = [Phi; 1] (the source column only when G.nem); sets dims[RC1],
+// dims[RC2] to r + nem.
+void launch_source_cat(const StepGeom& G, const double* X, int ldX, const double* d,
+                       const double* s, double* Xc, int ldC, const double* Th, const double* Ph,
+                       double* Tc, double* Pc, int* dims, hipStream_t st);
+void launch_source_cat(const StepGeom& G, const float* X, int ldX, const double* d,
+                       const double* s, float* Xc, int ldC, const double* Th, const double* Ph,
+                       double* Tc, double* Pc, int* dims, hipStream_t st);
+// dims[RC1], dims[RC2] for the transport-only concatenation (no source
+// column) of the two-rounding schedule.
+void launch_transport_dims(const StepGeom& G, int* dims, hipStream_t st);
 
 // ---- adjoint (reverse sweep) kernels -----------------------------------------
 void launch_svd_adj_inner(const double* G1, const double* G2, int ldg, const double* sv,

@@ -101,3 +101,91 @@ def test_create_rejects_bad_input_on_host(lib):
     st = lib.tt_create(C.byref(cfg), pd(k), pd(k), pd(k), pd(k), None, 0, pd(X0), pd(Th0), pd(Ph0),
                        10**6, 1, C.c_void_p(16), 1 << 40, None, C.byref(ctx))
     assert st == _ffi.TT_ERR_INVALID_ARG
+
+
+def test_lds_budget_of_the_eigensolvers(lib):
+    """Every dynamic-LDS launch of the eigensolver (order up to 1024) and of
+    the SVD (Golub-Kahan order up to 2048, longer side up to 1024) fits the
+    160 KiB of one CU; an order the kernels were not sized for is refused on
+    the host, naming the kernel, instead of being launched."""
+    nb = C.c_size_t()
+    for n, n2, pc in [(1024, 2048, 1024), (897, 1794, 897), (323, 646, 323), (64, 128, 64)]:
+        assert lib.tt_kernel_lds_check(n, n2, pc, C.byref(nb)) == 0, lib.tt_kernel_last_error()
+        assert 0 < nb.value <= 160 * 1024
+    assert lib.tt_kernel_lds_check(2048, 0, 0, C.byref(nb)) != 0
+    assert nb.value > 160 * 1024
+    assert b"k_sytrd_grid" in lib.tt_kernel_last_error()
+
+
+def _create(lib, p, **over):
+    """tt_create with a fake 8-byte workspace: host-side rejections come
+    first; a valid input then fails only on the workspace size (TT_ERR_OOM),
+    so no device work is issued."""
+    import numpy as np
+    from paper_2503_18056_amd import _ffi, make_config
+    cfg = make_config(p)
+    a = lambda x: np.ascontiguousarray(x, dtype=np.float64)  # noqa: E731
+    arrs = {k: a(over.get(k, p[k])) for k in ("kappa", "rho", "cv", "T0", "X0", "Th0", "Ph0")}
+    pd = lambda x: x.ctypes.data_as(_ffi.PD)  # noqa: E731
+    inflow = over.get("inflow", p["inflow"])
+    arr = (_ffi.tt_inflow * max(1, len(inflow)))()
+    keep = []
+    for k, (face, fw, tw, pw) in enumerate(inflow):
+        fw, tw, pw = a(fw), a(tw), a(pw)
+        keep += [fw, tw, pw]
+        arr[k].face, arr[k].face_w, arr[k].theta_w, arr[k].phi_w = face, pd(fw), pd(tw), pd(pw)
+    ctx = C.c_void_p()
+    st = lib.tt_create(C.byref(cfg), pd(arrs["kappa"]), pd(arrs["rho"]), pd(arrs["cv"]), pd(arrs["T0"]),
+                       arr, len(inflow), pd(arrs["X0"]), pd(arrs["Th0"]), pd(arrs["Ph0"]),
+                       arrs["X0"].shape[1], arrs["Ph0"].shape[0], C.c_void_p(16), 8, None, C.byref(ctx))
+    return st, lib.tt_last_error(None)
+
+
+def test_create_validates_host_inputs(lib):
+    import numpy as np
+    from paper_2503_18056_amd import _ffi
+    p = wl.small_random(bc="inflow", seed=2)
+    st, msg = _create(lib, p)
+    assert st == _ffi.TT_ERR_OOM, msg
+    for key, bad, word in [("kappa", np.nan, b"kappa"), ("kappa", -1.0, b"kappa"),
+                           ("rho", 0.0, b"rho"), ("cv", np.inf, b"cv"), ("T0", -0.5, b"T0"),
+                           ("X0", np.nan, b"cores"), ("Th0", np.inf, b"cores"), ("Ph0", np.nan, b"cores")]:
+        v = np.array(p[key], dtype=float, copy=True)
+        v.reshape(-1)[v.size // 2] = bad
+        st, msg = _create(lib, p, **{key: v})
+        assert st == _ffi.TT_ERR_INVALID_ARG and word in msg, (key, bad, msg)
+    inflow = [list(t) for t in p["inflow"]]
+    inflow[1][2] = np.array(inflow[1][2], copy=True)
+    inflow[1][2][0] = np.nan
+    st, msg = _create(lib, p, inflow=[tuple(t) for t in inflow])
+    assert st == _ffi.TT_ERR_INVALID_ARG and b"inflow" in msg
+
+
+def test_operator_options_validation(lib):
+    """Rusanov changes the block count (B = 1 + 2 dim, or 1 + dim when
+    S+ = 0) and doubles the rank-1 inflow terms when S+ > 0; outflow faces,
+    the two-rounding schedule and Rusanov are accepted, but not with a tape
+    (the reverse sweep covers the upwind, one-rounding step without outflow
+    faces)."""
+    from paper_2503_18056_amd import TT_FLUX_RUSANOV, TT_ROUND_TWICE, make_config
+    p = wl.small_random(bc="inflow", seed=2)
+    n_in = len(p["inflow"])
+    base = lib.tt_workspace_bytes(C.byref(make_config(p)), n_in)
+    assert base > 0
+    q = dict(p, flux="rusanov", s_plus=0.7)
+    assert lib.tt_workspace_bytes(C.byref(make_config(q)), n_in) > base
+    q0 = dict(p, flux="rusanov", s_plus=0.0)
+    assert 0 < lib.tt_workspace_bytes(C.byref(make_config(q0)), n_in) < base
+    assert lib.tt_workspace_bytes(C.byref(make_config(p, schedule=TT_ROUND_TWICE)), n_in) > 0
+    cfg = make_config(q)
+    cfg.s_plus = -1.0
+    assert lib.tt_workspace_bytes(C.byref(cfg), n_in) == 0 and b"s_plus" in lib.tt_last_error(None)
+    cfg = make_config(p)
+    cfg.flux = 7
+    assert lib.tt_workspace_bytes(C.byref(cfg), n_in) == 0 and b"flux" in lib.tt_last_error(None)
+    o = wl.small_random(bc="outflow", seed=2)
+    assert lib.tt_workspace_bytes(C.byref(make_config(o)), 0) > 0
+    for cfg in (make_config(o, ckpt_every=2), make_config(q, ckpt_every=2),
+                make_config(p, ckpt_every=2, schedule=TT_ROUND_TWICE)):
+        assert lib.tt_workspace_bytes(C.byref(cfg), n_in) == 0
+        assert b"adjoint" in lib.tt_last_error(None)

@@ -170,7 +170,7 @@ def test_grad_errors():
     with pytest.raises(TTError, match="tape full"):
         st.step(1)
     st.tt_set_kappa(p["kappa"] * 1.01)
-    with pytest.raises(TTError, match="kappa changed"):
+    with pytest.raises(TTError, match="stale"):
         st.tt_grad(det)
 
 

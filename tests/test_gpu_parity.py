@@ -3,11 +3,13 @@
 FP64 bar: identical ranks and a relative Frobenius difference of the
 reconstructed intensity below 1e-10 for one step from the same state.
 Forming Gram matrices squares their conditioning (App. A.4): a change of a
-Gram matrix by one unit roundoff -- what any other summation order or
-backward-stable eigensolver makes -- can move the oracle's own step by more
-than 1e-10 when kept singular values are tiny against sigma_1.  Where the
-oracle's own spread under such a change exceeds 1e-10, the bar is a small
-multiple of that spread, measured in the test.
+Gram matrix by one unit roundoff of its largest entry -- the norm-wise
+backward error of any backward-stable FP64 eigensolver -- can move the
+oracle's own step by more than 1e-10 when kept singular values are tiny
+against sigma_1 (more accurate Gram sums do not help; a CPU pin shows it).
+Each single-step comparison is therefore tagged: "pinned" where that spread
+of the oracle is below 1e-11 (bar 1e-10), "unpinned (eigensolver floor)"
+elsewhere (bar: four times the spread, printed with the difference).
 
 Multi-step runs: free-running, the ranks must equal the oracle's until the
 oracle meets a rank decision within MARGIN of its threshold (there FP64
@@ -140,13 +142,16 @@ def test_energy_matches_oracle():
 
 
 SPREAD_FACTOR = 4.0
+PIN_SPREAD = 1e-11  # the oracle's own spread below which a comparison is pinned at 1e-10
 MARGIN = 1e-3  # rank decisions closer than this to their threshold are rounding-determined
 
 
 def _oracle_spread(X, Th, Ph, s, p, ref, seeds=(0, 1)):
     """Largest relative change of the oracle's step (its ranks replayed) when
     every Gram matrix is moved by a seeded symmetric perturbation of one unit
-    roundoff of its largest entry."""
+    roundoff of its largest entry: the norm-wise backward error that any
+    backward-stable FP64 eigensolver leaves (its Gram sums are far more
+    accurate than that; see the CPU pin of this reading)."""
     worst = 0.0
     ranks = (ref[0].shape[1], ref[2].shape[0])
     for sd in seeds:
@@ -162,13 +167,21 @@ def _oracle_spread(X, Th, Ph, s, p, ref, seeds=(0, 1)):
 
 def _single_step_parity(p, states, steps_to_check, tol_single=1e-10):
     """One GPU step from the oracle's own state m against the oracle's step
-    from the same state: identical ranks (or, where the oracle's rank
-    decision is within MARGIN of its threshold, the oracle's ranks replayed);
-    relative difference below 1e-10, or below SPREAD_FACTOR times the
-    oracle's own spread where that is larger."""
+    from the same state.  Every comparison is tagged and printed:
+
+    - pinned: the oracle's own spread (``_oracle_spread``) is below 1e-11,
+      so an independent FP64 implementation is held to 1e-10 with identical
+      ranks;
+    - unpinned (eigensolver floor): the spread is larger; the bar is
+      SPREAD_FACTOR times the spread, printed beside the measured difference.
+
+    Where the oracle's own rank decision lies within MARGIN of its threshold
+    the ranks may differ; the test checks the margin, replays the oracle's
+    ranks and tags the comparison 'rank decision replayed'.  Returns
+    (worst pinned difference, number pinned, number unpinned)."""
     from paper_2503_18056_amd import TT_RANK_REPLAY
     s = Setup(p)
-    worst = 0.0
+    worst_pinned, npin, nun = 0.0, 0, 0
     st = _state(p, max_steps=4)
     for m in steps_to_check:
         X, Th, Ph = states[m]
@@ -181,7 +194,7 @@ def _single_step_parity(p, states, steps_to_check, tol_single=1e-10):
         if st.ranks() != ro:
             margin = min(b.get("margin", np.inf) for b in info["round"][-1])
             assert margin < MARGIN, (m, st.ranks(), ro, margin)
-            note = f" (rank decision at the threshold: gpu {st.ranks()}, oracle margin {margin:.1e}; replayed)"
+            note = f", rank decision replayed (gpu {st.ranks()}, oracle margin {margin:.1e})"
             sr = _state(p, max_steps=4, rank_mode=TT_RANK_REPLAY)
             sr.tt_set_cores(X, Th, Ph)
             sr.tt_set_rank_schedule([ro])
@@ -190,15 +203,20 @@ def _single_step_parity(p, states, steps_to_check, tol_single=1e-10):
             got = sr.cores()
             sr.close()
         err = metrics.rel_diff(got, (Xo, To, Po))
-        worst = max(worst, err)
-        bar = tol_single
-        if err >= tol_single:
-            spread = _oracle_spread(X, Th, Ph, s, p, (Xo, To, Po))
-            bar = max(tol_single, SPREAD_FACTOR * spread)
-            note += f" (oracle's own spread {spread:.2e}, bar {bar:.2e})"
-        _log(f"  {p['name']} single step from oracle state {m}: ranks {ro} err={err:.2e}{note}")
+        spread = _oracle_spread(X, Th, Ph, s, p, (Xo, To, Po))
+        if spread < PIN_SPREAD:
+            tag, bar = "pinned", tol_single
+            npin += 1
+            worst_pinned = max(worst_pinned, err)
+        else:
+            tag, bar = "unpinned (eigensolver floor)", max(tol_single, SPREAD_FACTOR * spread)
+            nun += 1
+        _log(f"  {p['name']} state {m}: ranks {ro} err={err:.2e} [{tag}; oracle spread "
+             f"{spread:.2e}, bar {bar:.1e}{note}]")
         assert err < bar
-    return worst
+    _log(f"  {p['name']}: {npin} pinned (worst {worst_pinned:.2e} < {tol_single:.0e}), "
+         f"{nun} unpinned")
+    return worst_pinned, npin, nun
 
 
 def _trajectory(p, nsteps):

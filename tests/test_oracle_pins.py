@@ -604,3 +604,50 @@ def test_gaussian_diffusion_ranks_and_analytic_solution():
     moved = np.linalg.norm(Ea(0.0) - Ea(t)) / np.linalg.norm(Ea(t))
     assert moved > 0.03 and err < 0.1 * moved
     assert abs(E.sum() * s.cell_volume - dif["A"]) < 1e-6
+
+
+def test_gram_summation_is_not_the_fp64_parity_floor(monkeypatch):
+    """Reading of the FP64 parity bar (App. A.4, Gram conditioning).  On C1
+    states 3-5 (kept singular values down to 1e-7 sigma_1), replacing the
+    plain FP64 Gram G_A = A^T A by one accumulated in 64-bit-mantissa
+    arithmetic (correctly rounded to FP64) moves the oracle's step by less
+    than 1e-11, while a symmetric change of one unit roundoff of lambda_max
+    -- the norm-wise backward error of any backward-stable FP64 eigensolver
+    -- moves it by more than 1e-10.  So compensated Gram sums cannot bring
+    two independent FP64 Gram-SVD implementations closer than the
+    eigensolvers' backward error allows; that spread is the bar of an
+    'unpinned' comparison."""
+    p = wl.c1()
+    s = Setup(p)
+    states = [(p["X0"], p["Th0"], p["Ph0"])]
+    tt.run(s, 5, callback=lambda m, c, T, i: states.append(c))
+    orig = rounding.gram_truncate
+
+    def exact_first(A, GB, **kw):
+        AL = np.asarray(A, dtype=np.longdouble)
+        GAe = (AL.T @ AL).astype(np.float64)
+        calls = [0]
+
+        def pert(G):
+            calls[0] += 1
+            return GAe if calls[0] == 1 else G
+        kw = dict(kw)
+        kw["perturb"] = pert
+        return orig(A, GB, **kw)
+    worst_spread = 0.0
+    for m in (3, 4, 5):
+        Xs, Ts, Ps = states[m]
+        ref, _, _ = tt.step(Xs, Ts, Ps, s.T0, s, p["tol"], p["rmax"])
+        ranks = (ref[0].shape[1], ref[2].shape[0])
+        monkeypatch.setattr(rounding, "gram_truncate", exact_first)
+        ex, _, _ = tt.step(Xs, Ts, Ps, s.T0, s, p["tol"], p["rmax"], ranks=ranks)
+        monkeypatch.setattr(rounding, "gram_truncate", orig)
+        assert metrics.rel_diff(ex, ref) < 1e-11
+        r = np.random.default_rng(1000 + m)
+
+        def pert(G):
+            E = r.uniform(-1.0, 1.0, G.shape)
+            return G + rounding.U * np.abs(G).max() * 0.5 * (E + E.T)
+        b, _, _ = tt.step(Xs, Ts, Ps, s.T0, s, p["tol"], p["rmax"], ranks=ranks, perturb=pert)
+        worst_spread = max(worst_spread, metrics.rel_diff(b, ref))
+    assert worst_spread > 1e-10
