@@ -53,6 +53,20 @@ size_t tt_kernel_gram_workspace(int32_t K, int32_t n, int32_t lda);
 tt_status tt_kernel_gram(const double* A, int32_t K, int32_t n, int32_t lda, double* G,
                          int32_t ldg, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * G = A^T A as tt_kernel_gram, with no workspace argument.  Its scratch (a
+ * 64-int size table and the per-block partial Gram tiles) lives in a
+ * library-owned 32 MiB device array per GPU, held until the process ends;
+ * the call allocates nothing.  Sizes whose partial tiles do not fit (about
+ * 256 row blocks x ceil(n/32)(ceil(n/32)+1)/2 tiles of 8 KiB for n <= 384,
+ * e.g. every K for n <= 160) return TT_ERR_INVALID_ARG.  All calls on one
+ * GPU share the array and every call overwrites it: calls that overlap on
+ * one GPU (other streams, other threads) race and must be serialised by the
+ * caller. */
+tt_status tt_kernel_gram_noalloc(const double* A, int32_t K, int32_t n, int32_t lda, double* G,
+                                 int32_t ldg, void* stream);
+
 /* G (n x n, ldg, FP64) = A^T A for an FP32 matrix A (K rows, n <= 1024
  * columns, lda >= n): the Gram formation of the FP32-mixed precision form.
  * Each entry is split on its column's exponent grid into four 11-bit integer

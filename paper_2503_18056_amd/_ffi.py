@@ -72,6 +72,7 @@ SIGNATURES = {
                                      C.c_size_t, VP]),
     "tt_kernel_gram_workspace": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "tt_kernel_gram": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, VP, C.c_int32, VP, C.c_size_t, VP]),
+    "tt_kernel_gram_noalloc": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, VP, C.c_int32, VP]),
     "tt_kernel_gemm_tall_workspace": (C.c_size_t, []),
     "tt_kernel_gemm_tall": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_int32, VP, C.c_int32, C.c_int32,
                                       VP, C.c_int32, VP, C.c_size_t, VP]),

@@ -1,6 +1,7 @@
 // Kernel-level entry points (include/tt_kernels.h).
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/tt_kernels.h"
@@ -22,7 +23,44 @@ tt_status kfail(tt_status s, const std::string& m) {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// ---- device scratch of tt_kernel_gram_noalloc --------------------------------
+// One array per GPU, owned by the library for the life of the process.  In
+// host code `noalloc_scratch` names a host-side stand-in; its device address
+// is taken once per device with hipGetSymbolAddress and used from then on.
+constexpr size_t NOALLOC_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char noalloc_scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEV] = {};
+
+// The device address of the scratch array on the current device (taken on
+// the first call on that device).
+hipError_t noalloc_scratch_ptr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return hipSuccess;
+}
+
+// dims table of a kernel-level call: all zero but dims[0] = n (a kernel, so
+// the call issues no memset or host copy into the scratch).
+__global__ void k_noalloc_dims(int* __restrict__ dims, int n) {
+  if (threadIdx.x < 64) dims[threadIdx.x] = threadIdx.x == 0 ? n : 0;
+}
 }  // namespace
+
+namespace tt {
+void kernel_error(const std::string& m) { k_err = m; }
+}  // namespace tt
 
 extern "C" {
 
@@ -151,6 +189,28 @@ tt_status tt_kernel_gram(const double* A, int32_t K, int32_t n, int32_t lda, dou
   hd[0] = n;
   KCHK(hipMemcpyAsync(dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
   gram_tall(gram_plan(K, n, lda), A, dimv(0), part, G, ldg, dims, s);
+  KCHK(hipGetLastError());
+  KCHK(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+tt_status tt_kernel_gram_noalloc(const double* A, int32_t K, int32_t n, int32_t lda, double* G,
+                                 int32_t ldg, void* stream) {
+  if (!A || !G || K < 1 || n < 1 || lda < n || ldg < n)
+    return kfail(TT_ERR_INVALID_ARG, "bad gram arguments");
+  const GramPlan plan = gram_plan(K, n, lda);
+  const size_t need = align256(64 * sizeof(int)) + align256(gram_partial_doubles(plan) * 8);
+  if (need > NOALLOC_BYTES)
+    return kfail(TT_ERR_INVALID_ARG, "gram_noalloc: the partial tiles need " + std::to_string(need) +
+                                         " bytes, above the " + std::to_string(NOALLOC_BYTES) +
+                                         "-byte device scratch (use tt_kernel_gram)");
+  void* base = nullptr;
+  KCHK(noalloc_scratch_ptr(&base));
+  hipStream_t s = (hipStream_t)stream;
+  int* dims = (int*)base;
+  double* part = (double*)((char*)base + align256(64 * sizeof(int)));
+  k_noalloc_dims<<<1, 64, 0, s>>>(dims, n);
+  gram_tall(plan, A, dimv(0), part, G, ldg, dims, s);
   KCHK(hipGetLastError());
   KCHK(hipStreamSynchronize(s));
   return TT_OK;
