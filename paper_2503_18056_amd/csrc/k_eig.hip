@@ -3,18 +3,22 @@
 // and the Gram of M for its SVD).
 //
 // Pipeline (one job per matrix, several jobs run side by side):
-//   1. Householder tridiagonalisation A = Q T Q^T in one 1024-thread block
-//      (the only step with O(n) sequential dependences; the matrix stays in
-//      L2 and every pass is coalesced along rows).
-//   2. Eigenpairs of T by divide and conquer from 1x1 leaves: all merges of
-//      a level run side by side, one wavefront per secular root, and the
-//      eigenvector updates are batched GEMMs.
+//   1. Householder tridiagonalisation A = Q T Q^T (the only step with O(n)
+//      sequential dependences): the matrix in one block's registers up to
+//      order 160, above that split by rows over 64 blocks' LDS.
+//   2. Eigenpairs of T by divide and conquer from 8x8 leaves, all levels in
+//      one persistent launch: the merges of a level run side by side, one
+//      wavefront per secular root, and the eigenvector updates are tiled
+//      products, with grid barriers between the phases.
 //   3. Back-transformation V = Q Z, one wavefront per kept vector.
 //   4. Descending order, sign gauge (largest |entry| positive), clip rule.
 // The same divide and conquer also serves the small SVD of M (section 5).
 #include <float.h>
 #include <string.h>
 
+#include <algorithm>
+
+#include "gemm_tile.h"
 #include "tt_internal.h"
 
 namespace tt {
@@ -47,6 +51,13 @@ __host__ __device__ inline int next_pow2(int n) {
   return p;
 }
 
+// Work area of one job at capacity N, before the grid-barrier words: d, e,
+// tau, w (4 N), reflectors (N x N), then the divide-and-conquer area.
+__host__ __device__ inline size_t eig_work_main(int N) {
+  const size_t N2 = next_pow2(N);
+  return 4 * (size_t)N + (size_t)N * N + N2 + 3 * N2 * N2 + 17 * N2 + 64;
+}
+
 // Lane exchange inside rows of 16 lanes by DPP, on both halves of a double.
 template <int CTRL>
 __device__ inline double dpp_d(double v) {
@@ -77,6 +88,17 @@ __device__ inline double wave_sum(double v) {
   return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
+// Barrier that orders LDS only: waits for this wavefront's LDS accesses
+// (lgkmcnt 0), not for its global stores, then s_barrier.  For loops whose
+// global stores nothing in the kernel reads back; the signal fences keep the
+// compiler from moving memory accesses across it.
+__device__ inline void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // vmcnt 63, expcnt 7, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Deterministic block-wide sum (fixed combination order).
 template <int NT>
 __device__ double block_sum(double v, double* red) {
@@ -93,9 +115,9 @@ __device__ double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------------
 // 1. Householder tridiagonalisation (lower form): for k = 0..n-3, H_k =
 // I - tau_k v v^T with v = [1, x_2..]/(alpha - beta) annihilates A[k+2:, k].
-constexpr int SYTRD_LDS_MAX = 180;  // packed lower triangle: 16290 doubles of LDS
+constexpr int SYR_MAX = 160;  // orders reduced in registers by k_sytrd_reg
 
-// Large orders (n > SYTRD_LDS_MAX): the matrix does not fit one CU's LDS,
+// Large orders (n > SYR_MAX): the matrix does not fit one CU's registers,
 // and one block streaming the trailing matrix from L2 is bound by that CU's
 // share of the memory system.  Instead SYTRD_GRID_P blocks per job each keep
 // the rows i = b (mod P) of the full symmetric square in their own LDS
@@ -115,14 +137,14 @@ constexpr int SYTRD_LDS_MAX = 180;  // packed lower triangle: 16290 doubles of L
 // cooperative launch would drain the queue on every call, also when all jobs
 // are small and the kernel returns at once); every wait is bounded by
 // SYTRD_SPIN_MAX polls, after which the barrier-timeout flag is raised and
-// the kernel runs out.  Outputs (d, e, tau, reflectors in H) as k_sytrd_lds.
+// the kernel runs out.  Outputs (d, e, tau, reflectors in H): d, e the tridiagonal, row k of H and
+// tau[k] the reflector H_k = I - tau_k v v^T (v_{k+1} = 1).
 constexpr int SYTRD_GRID_P = 64;
 constexpr int SYTRD_GRID_T = 256;
 constexpr unsigned SYTRD_SPIN_MAX = 1u << 24;
 
 struct SytrdGridBufs {
   double *Rp, *Pv, *Dv;  // published rows (2 x N), p (2 x N), block partial dots (2 x P)
-  unsigned* flag;        // per block: the last grid barrier it has reached
 };
 __device__ __host__ inline SytrdGridBufs sytrd_grid_bufs(double* work, int N) {
   // inside the divide-and-conquer area, which is free until the reduction ends
@@ -132,20 +154,47 @@ __device__ __host__ inline SytrdGridBufs sytrd_grid_bufs(double* work, int N) {
   B.Rp = z;
   B.Pv = z + 2 * (size_t)N;
   B.Dv = B.Pv + 2 * (size_t)N;
-  B.flag = reinterpret_cast<unsigned*>(B.Dv + 2 * SYTRD_GRID_P);
   return B;
 }
 inline int sytrd_grid_rows(int N) { return (N + SYTRD_GRID_P - 1) / SYTRD_GRID_P; }
 inline size_t sytrd_grid_lds(int N) { return ((size_t)sytrd_grid_rows(N) * N + 3 * (size_t)N) * 8; }
 
-__global__ void k_sytrd_grid_reset(EigJobs jobs, int N) {
-  sytrd_grid_bufs(jobs.j[blockIdx.x].work, N).flag[threadIdx.x] = 0u;
+// Grid barriers of the multi-block kernels.  A job's work area ends with one
+// flag per block and a launch generation.  Each launch takes its barrier
+// ordinals from gen * GRID_ORD_SPAN + 1, 2, ..., so they exceed every value
+// an earlier launch left in the flags (compared in serial-number arithmetic,
+// which survives the 32-bit wrap), and block 0 advances the generation at its
+// end.  Every block reads the generation before its first barrier and block 0
+// passes that barrier only after all have arrived, so no block can see the
+// advanced value.  Nothing needs resetting between launches (the area starts
+// zeroed with the rest of the workspace).
+constexpr int SYNC_MAXP = 256;                 // blocks one barrier may join
+constexpr unsigned GRID_ORD_SPAN = 1u << 16;   // barriers one launch may pass
+constexpr size_t SYNC_DOUBLES = SYNC_MAXP / 2 + 8;
+struct GridSync {
+  unsigned* flag;  // SYNC_MAXP
+  unsigned* gen;
+};
+__device__ inline GridSync grid_sync_of(double* work, int N) {
+  GridSync g;
+  g.flag = reinterpret_cast<unsigned*>(work + eig_work_main(N));
+  g.gen = g.flag + SYNC_MAXP;
+  return g;
+}
+__device__ inline unsigned grid_gen(const GridSync& g) {
+  return __hip_atomic_load(g.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// At the end of a launch that passed at least one barrier: block 0 advances
+// the generation (gen0 as read at the start).
+__device__ inline void grid_launch_end(const GridSync& g, unsigned gen0, bool used) {
+  if (used && blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(g.gen, gen0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Barrier number `ordinal` (1, 2, ...) over the P <= 256 blocks of one job: each
-// block stores its ordinal into its own flag (a release store after the block
-// barrier, which orders the block's earlier stores before it); one wave polls
-// all P flags with coherent loads, then an acquire fence.  No
+// Barrier with ordinal `ordinal` over the P <= SYNC_MAXP blocks of one launch:
+// each block stores its ordinal into its own flag (a release store after the
+// block barrier, which orders the block's earlier stores before it); one wave
+// polls all P flags with coherent loads, then an acquire fence.  No
 // read-modify-write, so no serialisation on one address.
 __device__ inline void grid_barrier(unsigned* flag, unsigned ordinal, int P, int* s_abort,
                                     int* dims) {
@@ -158,7 +207,8 @@ __device__ inline void grid_barrier(unsigned* flag, unsigned ordinal, int P, int
     while (true) {
       bool ok = true;
       for (int q = lane; q < P; q += 64)
-        ok = ok && __hip_atomic_load(&flag[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= ordinal;
+        ok = ok && (int)(__hip_atomic_load(&flag[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                         ordinal) >= 0;
       if (__all(ok)) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > SYTRD_SPIN_MAX) {
@@ -179,7 +229,7 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
   const int b = blockIdx.x, P = gridDim.x;
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
-  if (n <= SYTRD_LDS_MAX) return;  // k_sytrd_lds (the same decision on all blocks of the job)
+  if (n <= SYR_MAX) return;  // k_sytrd_reg (the same decision on all blocks of the job)
   Work W = work_of(J, N);
   const SytrdGridBufs G = sytrd_grid_bufs(J.work, N);
   const double* A = J.A;
@@ -201,7 +251,9 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
   for (int i = tid; i < N; i += SYTRD_GRID_T) svp[i] = swp[i] = 0.0;
   if (tid == 0) { s_taup = 0.0; s_abort = 0; }
   __syncthreads();
-  unsigned ordinal = 0;
+  const GridSync gs = grid_sync_of(J.work, N);
+  const unsigned gen0 = grid_gen(gs);
+  unsigned ordinal = gen0 * GRID_ORD_SPAN;
   for (int k = 0; k <= n - 2; ++k) {
     // w_{k-1} on indices >= k from the published p_{k-1} and partial dots
     // (every wave sums the P partials the same way), fused with row k of T_k
@@ -285,7 +337,7 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
         s_taup = tau;
       }
       for (int j = k + 1 + tid; j < n; j += SYTRD_GRID_T) svp[j] = sv[j];
-      grid_barrier(G.flag, ++ordinal, P, &s_abort, dims);
+      grid_barrier(gs.flag, ++ordinal, P, &s_abort, dims);
     }
     if (k == n - 2 && tid == 0) {
       // the last 2 x 2 block of T_{n-2}, from its owners' rows of T_{n-3}
@@ -302,42 +354,128 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
       }
     }
   }
+  grid_launch_end(gs, gen0, ordinal != gen0 * GRID_ORD_SPAN);
 }
 
-// The same reduction with the matrix resident in LDS (n <= SYTRD_LDS_MAX):
-// the lower triangle is packed, L(i, j) = Lp[i (i + 1) / 2 + j] for j <= i,
-// so every pass of a Householder step (column norm, A22 v, rank-2 update)
-// reads LDS instead of L2.  Outputs (d, e, tau, reflectors) as k_sytrd.
-__device__ inline int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+// The same reduction with the matrix in registers (n <= SYR_MAX), one
+// 512-thread block per matrix.  Wavefront w owns columns j = w + 8 s and
+// lane l holds their rows i = l + 64 c.  A Householder step k:
+//   (A) the owner of column k forms v_k (one wavefront sum for the norm)
+//       from the column it published in LDS at the end of step k - 1, and
+//       publishes v_k;
+//   (B) every wavefront publishes its partial A v over its columns;
+//   (C) each wavefront sums the 8 partials of 24 rows (p = tau A v) and
+//       publishes them and its share of p.v;
+// then each thread applies A -= v w^T + w v^T, w = p - (tau p.v / 2) v, to
+// its entries, and the owner of column k + 1 publishes that column.  Only
+// column slots and row chunks that meet the trailing block (rows and columns
+// > k) are touched, so the work per step falls as (n - k)^2; every
+// per-column condition is on a compile-time slot and a scalar wavefront
+// index, so it is a scalar branch.  v, p and the partial dots are double
+// buffered by the parity of k, so the owner of column k + 1 may publish
+// while slower wavefronts still read step k's.  The matrix is the lower
+// triangle of A: entries below the diagonal come from rows staged in LDS 64
+// at a time, those above from coalesced loads of the lower triangle's
+// columns.  Outputs (d, e, tau, reflectors in H) as k_sytrd_grid.
+// The loop issues no global memory access: the reflectors and d, e, tau stay
+// in LDS (the reflectors where the staged rows were) and are written out
+// after it.  A global store in flight holds its data registers until the
+// write is acknowledged, so a wavefront that stored inside the loop would
+// stall there on its next use of them, on every step.  Barriers inside the
+// loop therefore order LDS only (lds_barrier).
+// Eight wavefronts rather than sixteen: most of a step's instructions are
+// per wavefront (masks, addressing, reductions), and at four cycles per
+// wave64 VALU instruction the SIMD's issue rate, not the FMAs, bounds the
+// step; two wavefronts per SIMD may each hold 256 VGPRs.
+constexpr int SYR_WAVES = 8;                    // two per SIMD: up to 256 VGPRs each
+constexpr int SYR_T = 64 * SYR_WAVES;
+constexpr int SYR_SLOTS = SYR_MAX / SYR_WAVES;  // columns per wavefront
+constexpr int SYR_CH = (SYR_MAX + 63) / 64;     // rows per lane
+constexpr int SYR_LD = SYR_MAX + 1;             // LDS row stride of the staged rows
+constexpr int SYR_RPW = SYR_CH * 64 / SYR_WAVES;  // rows of p each wavefront reduces
+// LDS of the staged rows, then of the packed reflectors
+constexpr int SYR_BIG = 64 * SYR_LD > SYR_MAX * (SYR_MAX - 1) / 2 ? 64 * SYR_LD : SYR_MAX * (SYR_MAX - 1) / 2;
+// offset of v_k (n - 1 - k entries) in the packed reflector store
+__device__ inline int refl_off(int k, int n) { return k * (n - 1) - k * (k - 1) / 2; }
+constexpr int SYR_GS = 4;                       // slots per skip group
+constexpr int SYR_GROUPS = SYR_SLOTS / SYR_GS;
+static_assert(SYR_SLOTS % SYR_GS == 0, "whole skip groups");
 
-constexpr int SYL_T = 1024;            // threads of k_sytrd_lds
-constexpr int SYL_C = SYL_T / 128;     // column chunks of its matrix-vector product
-__global__ __launch_bounds__(SYL_T) void k_sytrd_lds(EigJobs jobs, int* __restrict__ dims, int N) {
+__global__ __launch_bounds__(SYR_T) void k_sytrd_reg(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.x];
   const int n = dims[J.n_idx];
-  if (n > SYTRD_LDS_MAX) return;
-  __shared__ double Lp[SYTRD_LDS_MAX * (SYTRD_LDS_MAX + 1) / 2];
-  __shared__ double sv[SYTRD_LDS_MAX], sw[SYTRD_LDS_MAX], sp[SYL_C][SYTRD_LDS_MAX];
-  __shared__ double s_tau;
+  if (n > SYR_MAX) return;  // k_sytrd_grid
+  // v, p and the published column cover every row a lane addresses
+  // (SYR_CH * 64 >= SYR_MAX); entries past n stay zero
+  // staged rows during the load, then the reflectors: v_k (rows k+1 .. n-1)
+  // packed from refl_off(k), written to H once after the loop
+  __shared__ double big[SYR_BIG];
+  double* const stage = big;
+  double* const refl = big;
+  __shared__ double sde[3][SYR_MAX];  // d, e, tau of the loop's steps
+  __shared__ double sv[2][SYR_CH * 64], sp[2][SYR_CH * 64], scol[SYR_CH * 64];
+  __shared__ double pp[SYR_WAVES][SYR_CH * 64];
+  __shared__ double red[2][SYR_WAVES];
+  __shared__ double s_tau[2];
   const double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int rj = tid & 127, rc = tid >> 7;  // matvec: row, column chunk (SYL_C chunks)
-  for (int i = wave; i < n; i += SYL_T / 64)
-    for (int j = lane; j <= i; j += 64) Lp[tri(i, j)] = A[(long long)i * lda + j];
-  __syncthreads();
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1, o = k + 1;  // trailing block rows/cols o..n-1
-    if (wave == 0) {
-      // Householder vector of column k, by one wavefront
-      double part = 0.0;
-      for (int i = 1 + lane; i < m; i += 64) {
-        const double x = Lp[tri(o + i, k)];
-        part += x * x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the wavefront index is uniform: in a scalar register, the per-column
+  // conditions below become scalar branches instead of exec masks
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < 2 * SYR_CH * 64; e += SYR_T) {
+    (&sv[0][0])[e] = 0.0;
+    (&sp[0][0])[e] = 0.0;
+  }
+  double a[SYR_SLOTS][SYR_CH];
+  // above the diagonal (i < j): L(j, i), column i of the lower triangle
+#pragma unroll
+  for (int s = 0; s < SYR_SLOTS; ++s) {
+    const int j = wave + SYR_WAVES * s;
+#pragma unroll
+    for (int c = 0; c < SYR_CH; ++c) {
+      const int i = lane + 64 * c;
+      a[s][c] = (j < n && i < j) ? A[(long long)j * lda + i] : 0.0;
+    }
+  }
+  // on and below the diagonal (i >= j): L(i, j), rows staged 64 at a time
+#pragma unroll
+  for (int c = 0; c < SYR_CH; ++c) {
+    const int r0 = 64 * c;
+    if (r0 < n) {
+      __syncthreads();
+      for (int r = wave; r < 64 && r0 + r < n; r += SYR_WAVES)
+        for (int j = lane; j <= r0 + r; j += 64)
+          stage[r * SYR_LD + j] = A[(long long)(r0 + r) * lda + j];
+      __syncthreads();
+      const int i = r0 + lane;
+#pragma unroll
+      for (int s = 0; s < SYR_SLOTS; ++s) {
+        const int j = wave + SYR_WAVES * s;
+        if (i < n && i >= j) a[s][c] = stage[lane * SYR_LD + j];
       }
+    }
+  }
+  if (wave == 0)
+#pragma unroll
+    for (int c = 0; c < SYR_CH; ++c) scol[lane + 64 * c] = a[0][c];
+  __syncthreads();  // stage is reused for the reflectors
+  for (int k = 0; k + 2 < n; ++k) {
+    const int o = k + 1, buf = k & 1;
+    if (wave == k % SYR_WAVES) {
+      // Householder vector of column k, by its owner (which published it)
+      double x[SYR_CH];
+      double part = 0.0;
+#pragma unroll
+      for (int c = 0; c < SYR_CH; ++c) {
+        const int i = lane + 64 * c;
+        const double t = scol[i];
+        x[c] = t;
+        if (i > o && i < n) part += t * t;
+      }
+      const double alpha = scol[o], dkk = scol[k];
       const double sumsq = wave_sum(part);
-      const double alpha = Lp[tri(o, k)];
       double tau, scal, beta;
       if (sumsq == 0.0) {
         tau = 0.0;
@@ -348,75 +486,143 @@ __global__ __launch_bounds__(SYL_T) void k_sytrd_lds(EigJobs jobs, int* __restri
         tau = (beta - alpha) / beta;
         scal = 1.0 / (alpha - beta);
       }
+#pragma unroll
+      for (int c = 0; c < SYR_CH; ++c) {
+        const int i = lane + 64 * c;
+        const double v = i == o ? 1.0 : (i > o && i < n ? x[c] * scal : 0.0);
+        sv[buf][i] = v;
+        if (i >= o && i < n) refl[refl_off(k, n) + i - o] = v;
+      }
       if (lane == 0) {
-        W.d[k] = Lp[tri(k, k)];
-        W.e[k] = beta;
-        W.tau[k] = tau;
-        s_tau = tau;
-      }
-      for (int i = lane; i < m; i += 64) {
-        const double v = i == 0 ? 1.0 : Lp[tri(o + i, k)] * scal;
-        sv[i] = v;
-        W.H[(long long)k * N + o + i] = v;
+        sde[0][k] = dkk;
+        sde[1][k] = beta;
+        sde[2][k] = tau;
+        s_tau[buf] = tau;
       }
     }
-    __syncthreads();
-    const double tau = s_tau;
-    if (tau == 0.0) continue;
-    // partial products of A22 v: row j, columns i = rc (mod 8)
-    for (int j = rj; j < m; j += 128) {
-      double acc = 0.0;
-      for (int i = rc; i < m; i += SYL_C)
-        acc += (i <= j ? Lp[tri(o + j, o + i)] : Lp[tri(o + i, o + j)]) * sv[i];
-      sp[rc][j] = acc;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      // p = tau A22 v, then w = p - (tau p.v / 2) v, by one wavefront
-      double part = 0.0;
-      for (int j = lane; j < m; j += 64) {
-        double p = 0.0;
+    lds_barrier();  // (A)
+    const double tau = s_tau[buf];
+    // o - wave as a scalar: slot s holds column o exactly when 8 s == ow, and
+    // the group of slots 4 g .. 4 g + 3 meets the trailing block when
+    // 32 g + 24 >= ow; rows chunk c meets it when 64 c + 63 >= o
+    const int ow = __builtin_amdgcn_readfirstlane(o - wave);
+    if (tau != 0.0) {
+      // partial A v over this wavefront's columns (v is zero outside the
+      // trailing block, so a group that meets it is taken whole)
+      double pc[SYR_CH];
 #pragma unroll
-        for (int c = 0; c < SYL_C; ++c) p += sp[c][j];
-        p *= tau;
-        sw[j] = p;
-        part += p * sv[j];
+      for (int c = 0; c < SYR_CH; ++c) pc[c] = 0.0;
+#pragma unroll
+      for (int g = 0; g < SYR_GROUPS; ++g) {
+        if (SYR_GS * SYR_WAVES * g + SYR_WAVES * (SYR_GS - 1) < ow) continue;
+        double vj[SYR_GS];
+#pragma unroll
+        for (int t = 0; t < SYR_GS; ++t) vj[t] = sv[buf][wave + SYR_WAVES * (SYR_GS * g + t)];
+#pragma unroll
+        for (int c = 0; c < SYR_CH; ++c) {
+          if (64 * c + 63 < o) continue;
+#pragma unroll
+          for (int t = 0; t < SYR_GS; ++t) pc[c] = fma(a[SYR_GS * g + t][c], vj[t], pc[c]);
+        }
       }
-      const double hc = 0.5 * tau * wave_sum(part);
-      for (int j = lane; j < m; j += 64) sw[j] -= hc * sv[j];
-    }
-    __syncthreads();
-    // A22 -= v w^T + w v^T on the lower triangle, a wavefront per row; a lane
-    // always takes the columns lane + 64 c, so it holds their v and w in
-    // registers across the rows
-    {
-      constexpr int NCH = (SYTRD_LDS_MAX + 63) / 64;
-      double vr[NCH], wr[NCH];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int j = lane + 64 * c;
-        vr[c] = j < m ? sv[j] : 0.0;
-        wr[c] = j < m ? sw[j] : 0.0;
+      for (int c = 0; c < SYR_CH; ++c) pp[wave][lane + 64 * c] = pc[c];
+      lds_barrier();  // (B)
+      {
+        // p = tau A v: wavefront w sums the 8 partials of rows 24 w .. 24 w + 23,
+        // two lanes per row (four partials each, then a pair sum), and
+        // publishes p and its share of p.v
+        const int rl = lane >> 1, g = lane & 1;
+        const int i = SYR_RPW * wave + rl;
+        double q = 0.0;
+        if (rl < SYR_RPW)
+          q = (pp[4 * g][i] + pp[4 * g + 1][i]) + (pp[4 * g + 2][i] + pp[4 * g + 3][i]);
+        q += dpp_d<0xB1>(q);  // quad_perm [1, 0, 3, 2]: the two halves of the row
+        const double pi = (rl < SYR_RPW && i >= o && i < n) ? tau * q : 0.0;
+        if (g == 0 && rl < SYR_RPW) sp[buf][i] = pi;
+        const double dot = wave_sum(g == 0 && rl < SYR_RPW ? pi * sv[buf][i] : 0.0);
+        if (lane == 0) red[buf][wave] = dot;
       }
-      for (int i = wave; i < m; i += SYL_T / 64) {
-        const double vi = sv[i], wi = sw[i];
-        double* row = Lp + tri(o + i, o);
+      lds_barrier();  // (C)
+      // A -= v w^T + w v^T on the entries of the groups and chunks that meet
+      // the trailing block (v and w vanish outside it)
+      double vi[SYR_CH], wi[SYR_CH];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const int j = lane + 64 * c;
-          if (j <= i) row[j] -= vi * wr[c] + wi * vr[c];
+      for (int c = 0; c < SYR_CH; ++c) {
+        vi[c] = sv[buf][lane + 64 * c];
+        wi[c] = sp[buf][lane + 64 * c];
+      }
+      double ptv = 0.0;
+#pragma unroll
+      for (int w = 0; w < SYR_WAVES; ++w) ptv += red[buf][w];
+      const double hc = 0.5 * tau * ptv;
+#pragma unroll
+      for (int c = 0; c < SYR_CH; ++c) wi[c] = fma(-hc, vi[c], wi[c]);
+#pragma unroll
+      for (int g = 0; g < SYR_GROUPS; ++g) {
+        if (SYR_GS * SYR_WAVES * g + SYR_WAVES * (SYR_GS - 1) < ow) continue;
+        double vj[SYR_GS], wj[SYR_GS];
+#pragma unroll
+        for (int t = 0; t < SYR_GS; ++t) {
+          const int j = wave + SYR_WAVES * (SYR_GS * g + t);
+          vj[t] = sv[buf][j];
+          wj[t] = sp[buf][j];
+        }
+#pragma unroll
+        for (int t = 0; t < SYR_GS; ++t) wj[t] = fma(-hc, vj[t], wj[t]);
+#pragma unroll
+        for (int c = 0; c < SYR_CH; ++c) {
+          if (64 * c + 63 < o) continue;
+#pragma unroll
+          for (int t = 0; t < SYR_GS; ++t) {
+            double& x = a[SYR_GS * g + t][c];
+            x = fma(-vi[c], wj[t], fma(-wi[c], vj[t], x));
+          }
         }
       }
     }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (n >= 2) {
-      W.d[n - 2] = Lp[tri(n - 2, n - 2)];
-      W.e[n - 2] = Lp[tri(n - 1, n - 2)];
-      W.tau[n - 2] = 0.0;
+    // column k + 1, for its owner's next step
+#pragma unroll
+    for (int s = 0; s < SYR_SLOTS; ++s) {
+      if (SYR_WAVES * s != ow) continue;
+#pragma unroll
+      for (int c = 0; c < SYR_CH; ++c) scol[lane + 64 * c] = a[s][c];
     }
-    if (n >= 1) W.d[n - 1] = Lp[tri(n - 1, n - 1)];
+  }
+  // the last 2 x 2 block: d[n-2], e[n-2] = A(n-1, n-2), d[n-1]
+  for (int r = n >= 2 ? n - 2 : 0; r < n; ++r) {
+    if (wave != r % SYR_WAVES) continue;
+    double dl = 0.0, el = 0.0;
+#pragma unroll
+    for (int s = 0; s < SYR_SLOTS; ++s) {
+      if (wave + SYR_WAVES * s != r) continue;
+#pragma unroll
+      for (int c = 0; c < SYR_CH; ++c) {
+        const int i = lane + 64 * c;
+        if (i == r) dl = a[s][c];
+        if (i == r + 1) el = a[s][c];
+      }
+    }
+    const double dr = wave_sum(dl), er = wave_sum(el);
+    if (lane == 0) {
+      W.d[r] = dr;
+      if (r == n - 2) {
+        W.e[r] = er;
+        W.tau[r] = 0.0;
+      }
+    }
+  }
+  // the loop's outputs, kept in LDS so that no global store was in flight
+  // across its barriers
+  __syncthreads();
+  for (int k = tid; k + 2 < n; k += SYR_T) {
+    W.d[k] = sde[0][k];
+    W.e[k] = sde[1][k];
+    W.tau[k] = sde[2][k];
+  }
+  for (int k = wave; k + 2 < n; k += SYR_WAVES) {
+    const int off = refl_off(k, n);
+    for (int i = k + 1 + lane; i < n; i += 64) W.H[(long long)k * N + i] = refl[off + i - k - 1];
   }
 }
 
@@ -430,7 +636,7 @@ __global__ __launch_bounds__(SYL_T) void k_sytrd_lds(EigJobs jobs, int* __restri
 //   1 + rho sum_j z_j^2 / (d_j - lambda) = 0,
 // solved in the shifted variable lambda = d_origin + tau; the eigenvectors
 // use the Loewner-recomputed z^ so that they are orthogonal to working
-// accuracy.  Vector updates Q <- Q_rot U are batched GEMMs.
+// accuracy.  Vector updates Q <- Q_rot U are tiled products (dc_merge_tile).
 struct DC {
   double *lam, *Qa, *Qb, *U, *dsl, *zsl, *rc, *rs, *rtau, *zhat, *dK, *zK, *mrho;
   int *perm, *Kslot, *rp, *rq, *ro, *mk, *mnrot, *mm2;
@@ -450,20 +656,20 @@ __device__ inline DC dc_of(const Work& W, int N) {
   return D;
 }
 
-__global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__ dims, int N) {
-  const EigJob J = jobs.j[blockIdx.y];
+// Q = I (both buffers' live blocks) and the torn diagonal, over blocks b of P.
+__device__ void dc_init_job(const EigJob& J, const int* __restrict__ dims, int N, int b, int P) {
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
   // only the live n x n block of Q is ever read
   const long long tot = (long long)n * n;
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += (long long)gridDim.x * 256) {
+  for (long long e = b * 256LL + threadIdx.x; e < tot; e += (long long)P * 256) {
     const int i = (int)(e / n), j = (int)(e % n);
     D.Qa[(size_t)i * N2 + j] = i == j ? 1.0 : 0.0;
     D.Qb[(size_t)i * N2 + j] = 0.0;
   }
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < N2; i += gridDim.x * 256) {
+  for (int i = b * 256 + threadIdx.x; i < N2; i += P * 256) {
     double v = 0.0;
     if (i < n) {
       v = W.d[i];
@@ -488,23 +694,40 @@ __global__ __launch_bounds__(256) void k_dc_init(EigJobs jobs, int* __restrict__
 // buffer, each entry from the two coefficients of its row's and its
 // column's pair, so a round is one pass between two barriers.
 constexpr int DC_LEAF = 8;
-constexpr int LEAF_T = 64;  // one wavefront per leaf: its barriers cost next to nothing
 
-__global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restrict__ dims, int N) {
-  const EigJob J = jobs.j[blockIdx.y];
+// A wavefront's LDS for one leaf.
+struct LeafLds {
+  double A[2][DC_LEAF][DC_LEAF + 1], V[2][DC_LEAF][DC_LEAF + 1];
+  double al[DC_LEAF], be[DC_LEAF];  // index i: row i of R is al_i e_i + be_i e_pi(i)
+  int pi[DC_LEAF];
+  int ord[DC_LEAF];
+};
+
+// Orders one wavefront's LDS accesses (its lanes' writes before their reads):
+// the leaves need no more than this, one wavefront each.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Leaf `leaf` of job J, by the calling wavefront (lane = threadIdx.x % 64).
+__device__ void dc_leaf_wave(const EigJob& J, int* __restrict__ dims, int N, int leaf, LeafLds& L) {
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
-  const int r0 = blockIdx.x * DC_LEAF;
+  const int r0 = leaf * DC_LEAF;
   if (r0 >= n) return;
   const int nb = min(DC_LEAF, n - r0);
   const int nbe = nb + (nb & 1);  // even count for the pairing (a decoupled pad)
-  __shared__ double A[2][DC_LEAF][DC_LEAF + 1], V[2][DC_LEAF][DC_LEAF + 1];
-  __shared__ double s_al[DC_LEAF], s_be[DC_LEAF];  // index i: row i of R is al_i e_i + be_i e_pi(i)
-  __shared__ int s_pi[DC_LEAF];
-  __shared__ int s_ord[DC_LEAF];
-  const int tid = threadIdx.x, ti = tid / DC_LEAF, tj = tid % DC_LEAF;
+  auto& A = L.A;
+  auto& V = L.V;
+  double* s_al = L.al;
+  double* s_be = L.be;
+  int* s_pi = L.pi;
+  int* s_ord = L.ord;
+  const int tid = threadIdx.x & 63, ti = tid / DC_LEAF, tj = tid % DC_LEAF;
   double a0 = 0.0;
   if (ti < nb && tj < nb) {
     const int gi = r0 + ti, gj = r0 + tj;
@@ -526,7 +749,7 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
     s_pi[tid] = tid;
   }
   const double tiny = U64 * sqrt(wave_sum(a0 * a0));
-  __syncthreads();
+  wave_sync();
   const int npair = nbe / 2, m1 = nbe - 1;
   int cur = 0;
   for (int sweep = 0; sweep < 30; ++sweep) {
@@ -568,7 +791,7 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
         s_be[b] = sn;
         s_pi[b] = a;
       }
-      __syncthreads();
+      wave_sync();
       {
         const double ai = s_al[ti], bi = s_be[ti], aj = s_al[tj], bj = s_be[tj];
         const int pi = s_pi[ti], pj = s_pi[tj];
@@ -578,14 +801,14 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
         V[cur ^ 1][ti][tj] = aj * V[cur][ti][tj] + bj * V[cur][ti][pj];
       }
       cur ^= 1;
-      __syncthreads();
+      wave_sync();
     }
     if (!__any(rot)) break;
   }
   // ascending order of the eigenvalues (stable: index breaks ties); the
   // identity first, so a NaN (flagged below) cannot leave a slot unset
   if (tid < DC_LEAF) s_ord[tid] = tid < nb ? tid : 0;
-  __syncthreads();
+  wave_sync();
   if (tid < nb) {
     const double v = A[cur][tid][tid];
     int pos = 0;
@@ -595,8 +818,8 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
     }
     s_ord[pos] = tid;
   }
-  __syncthreads();
-  for (int e = tid; e < nb * nb; e += LEAF_T) {
+  wave_sync();
+  for (int e = tid; e < nb * nb; e += 64) {
     const int i = e / nb, c = e % nb;
     D.Qa[(size_t)(r0 + i) * N2 + r0 + c] = V[cur][i][s_ord[c]];
   }
@@ -607,32 +830,31 @@ __global__ __launch_bounds__(LEAF_T) void k_dc_leaf(EigJobs jobs, int* __restric
   }
 }
 
-// Shared-memory bytes per merge element of k_dc_prep (4 doubles, 2 ints)
-// and of k_dc_vectors (6 doubles and 4 ints with the permutation and the
-// rotations staged, up to VEC_STAGE_MAX rows; 4 doubles and 1 int above),
-// which also holds 32 KB of fixed arrays.
+// Dynamic shared-memory bytes per merge element of the sort and deflation
+// (4 doubles, 2 ints) and of the vectors phase (6 doubles and 4 ints with the
+// permutation and the rotations staged, up to VEC_STAGE_MAX rows; 4 doubles
+// and 1 int above), which also uses 32 KB of fixed arrays (VecLds).
 constexpr int PREP_BYTES_PER = 4 * 8 + 2 * 4;
 constexpr int VEC_STAGE_MAX = 1024;
 constexpr int VEC_BYTES_STAGED = 6 * 8 + 4 * 4;
 constexpr int VEC_BYTES_GLOBAL = 4 * 8 + 1 * 4;
 
-// Sort of two ascending halves and deflation; one 256-thread block per
-// merge, the merge's arrays staged in LDS.  The halves are merged in
+// Sort of two ascending halves and deflation of merge m; one 256-thread
+// block, the merge's arrays staged in LDS.  The halves are merged in
 // parallel (each element's rank in the other half by binary search; ties
 // put the left element first); the deflation sweep, which carries the last
 // kept entry along, runs on one lane over LDS.  The eigenvector blocks of
 // a level live in one of two buffers (par: 0 reads Qa and writes Qb, 1 the
 // reverse); a block with no merge at this level is copied across.
-__global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__ dims, int N, int S,
-                                                 int par) {
-  const EigJob J = jobs.j[blockIdx.y];
+__device__ void dc_prep_merge(const EigJob& J, int* __restrict__ dims, int N, int S, int par, int m,
+                              double* smem) {
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
   const double* Qs = par ? D.Qb : D.Qa;
   double* Qd = par ? D.Qa : D.Qb;
-  const int m = blockIdx.x, b0 = m * 2 * S;
+  const int b0 = m * 2 * S;
   if (b0 + S >= n) {
     if (threadIdx.x == 0) D.mk[m] = -1;
     const int nb = max(0, min(2 * S, n - b0));
@@ -642,7 +864,6 @@ __global__ __launch_bounds__(256) void k_dc_prep(EigJobs jobs, int* __restrict__
     }
     return;
   }
-  extern __shared__ double smem[];
   const int nL = S, nR = min(S, n - b0 - S), m2 = nL + nR;
   double* dt = smem;            // original local order
   double* zt = dt + 2 * S;
@@ -799,8 +1020,8 @@ __device__ inline double secular(const double* d, const double* z2, int k, int o
 
 // Roots of the secular equation f(tau) = 1 + rho sum_j z_j^2 / (delta_j - tau)
 // (delta_j = d_j - d_o, o the nearer end of the root's interval), one
-// wavefront per root, the merge's d and z^2 staged in LDS (4 roots per
-// block).  f is increasing between the poles delta_i < tau < delta_{i+1};
+// wavefront per root, the merge's d and z^2 staged in LDS (roots 4 grp ..
+// 4 grp + 3 of merge m on one block).  f is increasing between the poles delta_i < tau < delta_{i+1};
 // the root is kept in a bracket [lo, hi] with f(lo) < 0 < f(hi).  Each
 // iteration fits the two-pole rational model of Bunch, Nielsen and Sorensen
 // (1978): the terms left of the root, psi, and right of it, phi, are each
@@ -813,16 +1034,15 @@ __device__ inline double secular(const double* d, const double* z2, int k, int o
 // middle-way and fixed-weight steps (Li, 1993).  Stops when |f| is at the
 // level of its evaluation error, 8u (1 + rho sum |terms|), or at a relative
 // change of 2u.
-__global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restrict__ dims, int N, int S) {
-  const EigJob J = jobs.j[blockIdx.z];
+__device__ void dc_secular_roots(const EigJob& J, int* __restrict__ dims, int N, int S, int m, int grp,
+                                 double* smem) {
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
-  const int m = blockIdx.y, b0 = m * 2 * S;
+  const int b0 = m * 2 * S;
   if (b0 + S >= n) return;
   const int nk = D.mk[m];
-  if (blockIdx.x * 4 >= nk) return;
-  extern __shared__ double smem[];
+  if (grp * 4 >= nk) return;
   double* d = smem;
   double* z2 = smem + 2 * S;
   for (int j = threadIdx.x; j < nk; j += 256) {
@@ -832,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wave;
+  const int i = grp * 4 + wave;
   if (i >= nk) return;
   const double rho = D.mrho[m];
   int o;
@@ -983,13 +1203,27 @@ __global__ __launch_bounds__(256) void k_dc_secular(EigJobs jobs, int* __restric
 // untouched or as the output of rotation t + 1 on its p side, carried in a
 // register; q_t is final after rotation t, and the carried slot is final
 // once the next rotation does not take it.
+// Fixed LDS of the vectors phase (one allocation for both of its forms):
+// sort keys and tags of up to 2048 outputs, the slot-to-K map.
+struct VecLds {
+  double sv[2048];
+  int st[2048];
+  int kix[2048];
+  int wcnt[4];
+  int bad;
+};
+__device__ inline VecLds& vec_lds() {
+  __shared__ VecLds L;
+  return L;
+}
+
 template <bool STAGE>
-__global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restrict__ dims, int N, int S) {
-  const EigJob J = jobs.j[blockIdx.y];
+__device__ void dc_vectors_merge(const EigJob& J, int* __restrict__ dims, int N, int S, int m,
+                                 double* smem) {
   const int n = dims[J.n_idx];
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
-  const int m = blockIdx.x, b0 = m * 2 * S;
+  const int b0 = m * 2 * S;
   const int S2 = 2 * S;
   double* Ub = D.U + (size_t)m * S2 * S2;
   const int tid = threadIdx.x;
@@ -997,7 +1231,6 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   const int nk = D.mk[m];
   const int m2 = D.mm2[m];
   const int nrot = D.mnrot[m];
-  extern __shared__ double smem[];
   double* d = smem;
   double* dro = d + S2;
   double* rt = dro + S2;
@@ -1013,11 +1246,12 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   const int* rq = STAGE ? rq_s : D.rq + b0;
   const double* rcs = STAGE ? rcs_s : D.rc + b0;
   const double* rsn = STAGE ? rsn_s : D.rs + b0;
-  __shared__ double sv[2048];
-  __shared__ int st[2048];
-  __shared__ int kix[2048];       // slot -> K index + 1, 0 for a deflated slot
-  __shared__ int wcnt[4];
-  __shared__ int s_bad;
+  VecLds& L = vec_lds();
+  double* sv = L.sv;
+  int* st = L.st;
+  int* kix = L.kix;  // slot -> K index + 1, 0 for a deflated slot
+  int* wcnt = L.wcnt;
+  int& s_bad = L.bad;
   if (tid == 0) s_bad = 0;
   for (long long e = tid; e < (long long)m2 * S2; e += 256) Ub[e] = 0.0;
   for (int c = tid; c < m2; c += 256) {
@@ -1159,6 +1393,137 @@ __global__ __launch_bounds__(256) void k_dc_vectors(EigJobs jobs, int* __restric
   }
 }
 
+// One 64 x 64 tile of a merge product: half h of merge m at level S takes
+// rows [b0 + h S, b0 + h S + mh) of the new eigenvector block as the old
+// block's h-th diagonal block (mh x mh, one solved half) times rows
+// [h S, h S + mh) of the merge's update matrix W (2 S x 2 S, row-major).
+__device__ void dc_merge_tile(const EigJob& J, const int* __restrict__ dims, int N, int S, int par,
+                              int m, int h, int ti, int tj, double* smem) {
+  const int n = dims[J.n_idx];
+  const int b0 = m * 2 * S, lim = n - b0;
+  if (lim <= S) return;  // no merge in this block
+  const int n2 = min(2 * S, lim);
+  const int mh = h == 0 ? S : min(S, lim - S);
+  const int i0 = ti * 64, j0 = tj * 64;
+  if (i0 >= mh || j0 >= n2) return;
+  Work W = work_of(J, N);
+  DC D = dc_of(W, N);
+  const int N2 = next_pow2(N);
+  const double* Qs = par ? D.Qb : D.Qa;
+  double* Qd = par ? D.Qa : D.Qb;
+  const int r0 = b0 + h * S;
+  const double* A = Qs + (size_t)r0 * N2 + r0;
+  const double* B = D.U + (size_t)m * 4 * S * S + (size_t)h * S * 2 * S;
+  double* C = Qd + (size_t)r0 * N2 + b0;
+  double(*As)[65] = reinterpret_cast<double(*)[65]>(smem);
+  double(*Bs)[65] = reinterpret_cast<double(*)[65]>(smem + GEMM_GK * 65);
+  double acc[4][4];
+  gemm_tile_acc<0, 0>(acc, A, B, N2, 2 * S, nullptr, i0, j0, mh, n2, mh, As, Bs);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + ty + 16 * r;
+    if (i >= mh) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + tx + 16 * c;
+      if (j < n2) C[(size_t)i * N2 + j] = acc[r][c];
+    }
+  }
+}
+
+// Levels of the divide and conquer at order n (merges of blocks S = 8, 16,
+// ... while S < n), and which buffer holds its eigenvectors at the end
+// (0: Qa, 1: Qb): the leaves write Qa and each level swaps.
+__host__ __device__ inline int dc_par(int n) {
+  int L = 0;
+  for (int S = DC_LEAF; S < n; S *= 2) ++L;
+  return L & 1;
+}
+
+// Job q's item t of a phase whose job q has cnt[q] items (t counts across
+// the jobs in order).
+__device__ inline bool dc_item(const int* cnt, int njobs, int t, int& q, int& r) {
+  for (q = 0; q < njobs; ++q) {
+    if (t < cnt[q]) {
+      r = t;
+      return true;
+    }
+    t -= cnt[q];
+  }
+  return false;
+}
+
+// The whole divide and conquer of up to 4 jobs in one launch of P
+// persistent 256-thread blocks: Q = I and the leaves, then per level the
+// sort and deflation of every merge, its secular roots (4 per item), its
+// vectors and update matrix, and the tiles of its products, each phase
+// spread over the blocks and ended by a grid barrier.  A job stops at its
+// own live order (dims), so its levels follow n, not the capacity N.  LDS:
+// the phases' arrays share the dynamic buffer (dc_fused_dyn_lds(N) bytes).
+constexpr int DCF_MAXP = 128;
+__global__ __launch_bounds__(256) void k_dc_fused(EigJobs jobs, int njobs, int* __restrict__ dims,
+                                                  int N) {
+  extern __shared__ double smem[];
+  __shared__ LeafLds leaf_lds[4];
+  __shared__ int s_abort;
+  const int b = blockIdx.x, P = gridDim.x, wave = threadIdx.x >> 6;
+  const GridSync gs = grid_sync_of(jobs.j[0].work, N);
+  if (threadIdx.x == 0) s_abort = 0;
+  const unsigned gen0 = grid_gen(gs);
+  unsigned ord = gen0 * GRID_ORD_SPAN;
+  int nq[4] = {0, 0, 0, 0}, nmax = 0;
+  for (int q = 0; q < njobs; ++q) {
+    nq[q] = dims[jobs.j[q].n_idx];
+    nmax = max(nmax, nq[q]);
+  }
+  for (int q = 0; q < njobs; ++q) dc_init_job(jobs.j[q], dims, N, b, P);
+  grid_barrier(gs.flag, ++ord, P, &s_abort, dims);
+  int cnt[4] = {0, 0, 0, 0}, tot = 0;
+  for (int q = 0; q < njobs; ++q) tot += cnt[q] = (nq[q] + DC_LEAF - 1) / DC_LEAF;
+  for (int t = b * 4 + wave; t < tot; t += 4 * P) {
+    int q, r;
+    if (dc_item(cnt, njobs, t, q, r)) dc_leaf_wave(jobs.j[q], dims, N, r, leaf_lds[wave]);
+  }
+  for (int S = DC_LEAF, par = 0; S < nmax; S *= 2, par ^= 1) {
+    int nm[4] = {0, 0, 0, 0}, tm = 0;
+    for (int q = 0; q < njobs; ++q) tm += nm[q] = nq[q] > S ? (nq[q] + 2 * S - 1) / (2 * S) : 0;
+    grid_barrier(gs.flag, ++ord, P, &s_abort, dims);
+    for (int t = b; t < tm; t += P) {
+      int q, r;
+      __syncthreads();  // the previous item's LDS reads are done
+      if (dc_item(nm, njobs, t, q, r)) dc_prep_merge(jobs.j[q], dims, N, S, par, r, smem);
+    }
+    grid_barrier(gs.flag, ++ord, P, &s_abort, dims);
+    const int X = (2 * S + 3) / 4;  // groups of 4 roots of a merge
+    for (int q = 0; q < njobs; ++q) cnt[q] = nm[q] * X;
+    for (int t = b; t < tm * X; t += P) {
+      int q, r;
+      __syncthreads();
+      if (dc_item(cnt, njobs, t, q, r)) dc_secular_roots(jobs.j[q], dims, N, S, r / X, r % X, smem);
+    }
+    grid_barrier(gs.flag, ++ord, P, &s_abort, dims);
+    for (int t = b; t < tm; t += P) {
+      int q, r;
+      __syncthreads();
+      if (!dc_item(nm, njobs, t, q, r)) continue;
+      if (2 * S <= VEC_STAGE_MAX) dc_vectors_merge<true>(jobs.j[q], dims, N, S, r, smem);
+      else dc_vectors_merge<false>(jobs.j[q], dims, N, S, r, smem);
+    }
+    grid_barrier(gs.flag, ++ord, P, &s_abort, dims);
+    const int TI = (S + 63) / 64, TJ = (2 * S + 63) / 64, TM = 2 * TI * TJ;
+    for (int q = 0; q < njobs; ++q) cnt[q] = nm[q] * TM;
+    for (int t = b; t < tm * TM; t += P) {
+      int q, r;
+      __syncthreads();
+      if (!dc_item(cnt, njobs, t, q, r)) continue;
+      const int m = r / TM, e = r % TM, h = e / (TI * TJ), ti = (e / TJ) % TI, tj = e % TJ;
+      dc_merge_tile(jobs.j[q], dims, N, S, par, m, h, ti, tj, smem);
+    }
+  }
+  grid_launch_end(gs, gen0, true);
+}
+
 // Threshold of the clip rule: eigenvalues above it are kept.
 __device__ inline double keep_threshold(const EigJob& J, const double* w, int n) {
   const double lmax = n > 0 ? w[n - 1] : 0.0;
@@ -1179,10 +1544,10 @@ __host__ __device__ inline int ormtr_chunk(int N) {
 }
 
 template <int NCH>
-__global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N,
-                                               int par) {
+__global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
+  const int par = dc_par(n);
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
@@ -1469,7 +1834,6 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
 
 struct GebrdGridBufs {
   double *C, *R, *Y;  // published column (p), rows (2 x q), partials (P x q)
-  unsigned* flag;
 };
 __device__ __host__ inline GebrdGridBufs gebrd_grid_bufs(double* work, int N, int P) {
   const size_t N2 = next_pow2(N);
@@ -1478,7 +1842,6 @@ __device__ __host__ inline GebrdGridBufs gebrd_grid_bufs(double* work, int N, in
   B.C = z;
   B.R = z + 1024;
   B.Y = B.R + 2 * (size_t)N;
-  B.flag = reinterpret_cast<unsigned*>(B.Y + (size_t)P * N);
   return B;
 }
 // blocks and dynamic LDS for rows up to pcap and columns up to qcap
@@ -1489,10 +1852,6 @@ inline int gebrd_grid_blocks(int pcap, int qcap) {
 inline size_t gebrd_grid_lds(int pcap, int qcap) {
   const int P = gebrd_grid_blocks(pcap, qcap);
   return ((size_t)((pcap + P - 1) / P) * qcap + (size_t)pcap + 3 * (size_t)qcap) * 8;
-}
-
-__global__ void k_gebrd_grid_reset(EigJobs jobs, int N, int P) {
-  gebrd_grid_bufs(jobs.j[0].work, N, P).flag[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restrict__ dims, int N,
@@ -1525,7 +1884,9 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
     for (int i = tid; i < 2 * q; i += 256) W.d[i] = 0.0;
   if (tid == 0) s_abort = 0;
   __syncthreads();
-  unsigned ordinal = 0;
+  const GridSync gs = grid_sync_of(J.work, N);
+  const unsigned gen0 = grid_gen(gs);
+  unsigned ordinal = gen0 * GRID_ORD_SPAN;
   for (int k = 0; k < q; ++k) {
     const int nc = q - k - 1;
     // A. left reflector of column k, rows k..p-1
@@ -1568,7 +1929,7 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
         yp[j] = acc;
       }
     }
-    grid_barrier(G.flag, ++ordinal, P, &s_abort, dims);
+    grid_barrier(gs.flag, ++ordinal, P, &s_abort, dims);
     // B. y, row k after the left reflector, right reflector
     const double* rk = k == 0 ? A : G.R + (size_t)(k & 1) * N;
     part = 0.0;
@@ -1627,8 +1988,9 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
         if (publish) rpub[k + 1 + j] = t;
       }
     }
-    grid_barrier(G.flag, ++ordinal, P, &s_abort, dims);
+    grid_barrier(gs.flag, ++ordinal, P, &s_abort, dims);
   }
+  grid_launch_end(gs, gen0, ordinal != gen0 * GRID_ORD_SPAN);
 }
 
 // Bidiagonalisation with the p x q matrix in LDS (p ldq <= GEBRD_LDS_MAX,
@@ -1768,10 +2130,10 @@ __global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M
 // Vectors of the short side for the kept singular values, one wavefront per
 // vector: y = the even entries of the tridiagonal's eigenvector, normalised,
 // then y <- G_0 G_1 ... G_{q-2} y with the right reflectors.
-__global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict__ dims, int N,
-                                                  int par) {
+__global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[0];
   const int n = dims[J.n_idx], q = n / 2;
+  const int par = dc_par(n);
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
@@ -1839,6 +2201,20 @@ __global__ __launch_bounds__(256) void k_svd_final(EigJobs jobs, int* __restrict
   gauge_columns(J.V, J.ldv, q, kept);
 }
 
+// Dynamic LDS of k_dc_fused at capacity N: the largest of its phases' needs
+// at the top level (sort and deflation, secular roots, vectors, product tiles).
+size_t dc_fused_dyn_lds(int N) {
+  size_t need = (size_t)2 * GEMM_GK * 65 * 8;
+  for (int S = DC_LEAF; S < N; S *= 2) {
+    const size_t m2 = (size_t)2 * S;
+    need = std::max(need, m2 * PREP_BYTES_PER);
+    need = std::max(need, m2 * 16);
+    need = std::max(need, m2 * (m2 <= VEC_STAGE_MAX ? VEC_BYTES_STAGED : VEC_BYTES_GLOBAL));
+  }
+  return need;
+}
+int dc_fused_blocks(int N) { return std::min(DCF_MAXP, std::max(8, (N + 3) / 4)); }
+
 }  // namespace
 
 // ---- LDS budget of the launches with dynamic LDS -----------------------------
@@ -1848,8 +2224,7 @@ __global__ __launch_bounds__(256) void k_svd_final(EigJobs jobs, int* __restrict
 // the runtime's own figure is used.
 namespace {
 constexpr size_t LDS_CU = 160 * 1024;
-constexpr size_t ST_SYTRD_GRID = 168, ST_DC_PREP = 48, ST_DC_SECULAR = 0, ST_DC_VECTORS = 32792,
-                 ST_ORMTR = 0, ST_GEBRD_GRID = 168;
+constexpr size_t ST_SYTRD_GRID = 168, ST_DC_FUSED = 42832, ST_ORMTR = 0, ST_GEBRD_GRID = 168;
 
 size_t static_lds(const void* fn, size_t table, bool runtime) {
   if (!runtime) return table;
@@ -1868,24 +2243,14 @@ void lds_note(size_t bytes, const char* name, size_t& worst, const char** which)
 
 // divide and conquer at order N (eigensolve N, or Golub-Kahan order 2q)
 void dc_lds(int N, bool rt, size_t& worst, const char** which) {
-  for (int S = DC_LEAF; S < N; S *= 2) {
-    lds_note(static_lds((const void*)k_dc_prep, ST_DC_PREP, rt) + (size_t)2 * S * PREP_BYTES_PER,
-             "k_dc_prep", worst, which);
-    lds_note(static_lds((const void*)k_dc_secular, ST_DC_SECULAR, rt) + (size_t)2 * S * 16,
-             "k_dc_secular", worst, which);
-    if (2 * S <= VEC_STAGE_MAX)
-      lds_note(static_lds((const void*)k_dc_vectors<true>, ST_DC_VECTORS, rt) +
-                   (size_t)2 * S * VEC_BYTES_STAGED, "k_dc_vectors<staged>", worst, which);
-    else
-      lds_note(static_lds((const void*)k_dc_vectors<false>, ST_DC_VECTORS, rt) +
-                   (size_t)2 * S * VEC_BYTES_GLOBAL, "k_dc_vectors<global>", worst, which);
-  }
+  lds_note(static_lds((const void*)k_dc_fused, ST_DC_FUSED, rt) + dc_fused_dyn_lds(N), "k_dc_fused",
+           worst, which);
 }
 }  // namespace
 
 size_t eig_lds_bytes(int N, bool runtime, const char** which) {
   size_t worst = 0;
-  if (N > SYTRD_LDS_MAX)
+  if (N > SYR_MAX)
     lds_note(static_lds((const void*)k_sytrd_grid, ST_SYTRD_GRID, runtime) + sytrd_grid_lds(N),
              "k_sytrd_grid", worst, which);
   dc_lds(N, runtime, worst, which);
@@ -1908,66 +2273,14 @@ size_t svd_lds_bytes(int ncap2, int pcap, bool runtime, const char** which) {
 
 bool lds_fits(size_t bytes) { return bytes <= LDS_CU; }
 
-size_t eig_work_doubles(int N) {
-  const size_t N2 = next_pow2(N);
-  return 4 * (size_t)N + (size_t)N * N + N2 + 3 * N2 * N2 + 17 * N2 + 64;
-}
+size_t eig_work_doubles(int N) { return eig_work_main(N) + SYNC_DOUBLES; }
 
 namespace {
 
-// Divide-and-conquer levels for the tridiagonals (W.d, W.e) of the jobs.
-// Returns which buffer holds the eigenvectors at the end (0: Qa, 1: Qb).
-int dc_levels(const EigJob* jobs, const EigJobs& J, int njobs, int N, int* dims, hipStream_t s) {
-  const int N2 = next_pow2(N);
-  int ib = (int)(((long long)N2 * N2 + 255) / 256);
-  if (ib > 2048) ib = 2048;
-  k_dc_init<<<dim3(ib, njobs), 256, 0, s>>>(J, dims, N);
-  k_dc_leaf<<<dim3((N + DC_LEAF - 1) / DC_LEAF, njobs), LEAF_T, 0, s>>>(J, dims, N);
-  int par = 0;
-  for (int S = DC_LEAF; S < N; S *= 2, par ^= 1) {
-    const int nm = (N + 2 * S - 1) / (2 * S);
-    k_dc_prep<<<dim3(nm, njobs), 256, (size_t)2 * S * PREP_BYTES_PER, s>>>(J, dims, N, S, par);
-    k_dc_secular<<<dim3((2 * S + 3) / 4, nm, njobs), 256, (size_t)2 * S * 16, s>>>(J, dims, N, S);
-    if (2 * S <= VEC_STAGE_MAX)
-      k_dc_vectors<true><<<dim3(nm, njobs), 256, (size_t)2 * S * VEC_BYTES_STAGED, s>>>(J, dims, N, S);
-    else
-      k_dc_vectors<false><<<dim3(nm, njobs), 256, (size_t)2 * S * VEC_BYTES_GLOBAL, s>>>(J, dims, N, S);
-    {
-      // new block <- old block * W, for every merge block of this level of
-      // every job (one launch).  The old block is block diagonal (the two
-      // solved halves), so each merge is two products: the left S x S block
-      // times rows [0, S) of W and the right block times rows [S, 2S), each
-      // giving all columns of its rows of the new block.
-      const int bm = (N + 2 * S - 1) / (2 * S);
-      GemmDesc g;
-      memset(&g, 0, sizeof(g));
-      g.lda = N2; g.ldb = 2 * S; g.ldc = N2;
-      g.sA = (long long)S * (N2 + 1);
-      g.sB = (long long)2 * S * S;
-      g.sC = (long long)S * N2;
-      g.sC2 = 2 * S;
-      g.halves = S;
-      g.m = dimc(S); g.n = dimc(2 * S); g.k = dimc(S);
-      g.alpha = 1.0;
-      g.cond_idx = -1;
-      g.bclip_idx = -1;
-      g.njob = njobs;
-      g.zper = 2 * bm;
-      for (int q = 0; q < njobs; ++q) {
-        const double* wbase = jobs[q].work;
-        const size_t off_z = 4 * (size_t)N + (size_t)N * N;
-        const double* Qa = wbase + off_z + N2;
-        const double* Qb = Qa + (size_t)N2 * N2;
-        const double* U = Qb + (size_t)N2 * N2;
-        g.Aj[q] = par ? Qb : Qa;
-        g.Bj[q] = U;
-        g.Cj[q] = const_cast<double*>(par ? Qa : Qb);
-        g.bclipj[q] = jobs[q].n_idx;
-      }
-      gemm(g, S, 2 * S, njobs * 2 * bm, dims, s);
-    }
-  }
-  return par;
+// Divide and conquer of the tridiagonals (W.d, W.e) of the jobs; the
+// eigenvectors end in buffer dc_par(n) of each job.
+void dc_solve(const EigJobs& J, int njobs, int N, int* dims, hipStream_t s) {
+  k_dc_fused<<<dc_fused_blocks(N), 256, dc_fused_dyn_lds(N), s>>>(J, njobs, dims, N);
 }
 
 }  // namespace
@@ -1976,20 +2289,19 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   if (njobs <= 0 || N <= 0) return;
   EigJobs J;
   for (int i = 0; i < njobs && i < 4; ++i) J.j[i] = jobs[i];
-  k_sytrd_lds<<<njobs, SYL_T, 0, s>>>(J, dims, N);
-  if (N > SYTRD_LDS_MAX) {
+  k_sytrd_reg<<<njobs, SYR_T, 0, s>>>(J, dims, N);
+  if (N > SYR_MAX) {
     const int nj = njobs < 4 ? njobs : 4;
-    k_sytrd_grid_reset<<<nj, SYTRD_GRID_P, 0, s>>>(J, N);
     k_sytrd_grid<<<dim3(SYTRD_GRID_P, nj), SYTRD_GRID_T, sytrd_grid_lds(N), s>>>(J, dims, N);
   }
-  const int par = dc_levels(jobs, J, njobs, N, dims, s);
+  dc_solve(J, njobs < 4 ? njobs : 4, N, dims, s);
   {
     const dim3 g((N + 3) / 4, njobs);
     const size_t lds = ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8;
-    if (N <= 192) k_ormtr<3><<<g, 256, lds, s>>>(J, dims, N, par);
-    else if (N <= 384) k_ormtr<6><<<g, 256, lds, s>>>(J, dims, N, par);
-    else if (N <= 640) k_ormtr<10><<<g, 256, lds, s>>>(J, dims, N, par);
-    else k_ormtr<16><<<g, 256, lds, s>>>(J, dims, N, par);
+    if (N <= 192) k_ormtr<3><<<g, 256, lds, s>>>(J, dims, N);
+    else if (N <= 384) k_ormtr<6><<<g, 256, lds, s>>>(J, dims, N);
+    else if (N <= 640) k_ormtr<10><<<g, 256, lds, s>>>(J, dims, N);
+    else k_ormtr<16><<<g, 256, lds, s>>>(J, dims, N);
   }
   k_eig_final<<<dim3((N + FINAL_COLS - 1) / FINAL_COLS, njobs), 256, 0, s>>>(J, dims, N);
 }
@@ -2009,12 +2321,11 @@ void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx
   if (pcap >= GEBRD_GRID_MIN) {
     const int qc = qcap < pcap ? qcap : pcap;
     const int P = gebrd_grid_blocks(pcap, qc);
-    k_gebrd_grid_reset<<<1, P, 0, s>>>(J, N, P);
     k_gebrd_grid<<<P, 256, gebrd_grid_lds(pcap, qc), s>>>(J, dims, N, a_idx, b_idx, side_idx, pcap,
                                                           qc);
   }
-  const int par = dc_levels(&job, J, 1, N, dims, s);
-  k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N, par);
+  dc_solve(J, 1, N, dims, s);
+  k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N);
   k_svd_final<<<1, 256, 0, s>>>(J, dims, N);
 }
 

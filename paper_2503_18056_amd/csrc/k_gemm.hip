@@ -3,6 +3,7 @@
 // the left Gram of the spatial core (G = X_cat^T X_cat, App. A.2 G_A = A^T A)
 // and the spatial core update (X' = X_cat P, App. A.2 A' = A V_A S_A^-1 U).
 #include "tt_internal.h"
+#include "gemm_tile.h"
 
 namespace tt {
 
@@ -20,67 +21,16 @@ template <> struct GrShape<double> { static constexpr int WAVES = 16, TPW = 1; }
 template <> struct GrShape<float> { static constexpr int WAVES = 8, TPW = 2; };
 
 
-// ---------------------------------------------------------------------------
-// One K slab of the generic GEMM's operands into registers (NL values of A
-// and of B per thread), zero outside the matrices.
-template <int TA, int TB, int GK, int NL>
-__device__ __forceinline__ void gemm_slab_load(double (&ra)[NL], double (&rb)[NL], const double* A,
-                                               const double* B, int lda, int ldb,
-                                               const double* kscale, int i0, int j0, int m, int n,
-                                               int k, int l0, int tid) {
-#pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int e = tid + 256 * q;
-    int i, l;
-    if (TA == 0) { i = e / GK; l = e % GK; } else { l = e >> 6; i = e & 63; }
-    const int gi = i0 + i, gl = l0 + l;
-    double v = 0.0;
-    if (gi < m && gl < k) {
-      v = TA == 0 ? A[(long long)gi * lda + gl] : A[(long long)gl * lda + gi];
-      if (kscale) v *= kscale[gl];
-    }
-    ra[q] = v;
-  }
-#pragma unroll
-  for (int q = 0; q < NL; ++q) {
-    const int e = tid + 256 * q;
-    int j, l;
-    if (TB == 0) { l = e >> 6; j = e & 63; } else { j = e / GK; l = e % GK; }
-    const int gj = j0 + j, gl = l0 + l;
-    double v = 0.0;
-    if (gj < n && gl < k) v = TB == 0 ? B[(long long)gl * ldb + gj] : B[(long long)gj * ldb + gl];
-    rb[q] = v;
-  }
-}
-
 // Generic GEMM (vector FP64, 64x64 tiles, 32-deep K slabs staged in LDS,
 // the next slab prefetched into registers).
 template <int TA, int TB>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict__ dims) {
   if (g.cond_idx >= 0 && dims[g.cond_idx] != g.cond_val) return;
-  int z = blockIdx.z;
-  const double* Ab = g.A;
-  const double* Bb = g.B;
-  double* Cb = g.C;
-  int bidx = g.bclip_idx;
-  if (g.njob > 0) {
-    const int jb = z / g.zper;
-    z -= jb * g.zper;
-    Ab = g.Aj[jb];
-    Bb = g.Bj[jb];
-    Cb = g.Cj[jb];
-    bidx = g.bclipj[jb];
-  }
+  const int z = blockIdx.z;
+  const int bidx = g.bclip_idx;
   int m = eval_dim(dims, g.m), n = eval_dim(dims, g.n), k = eval_dim(dims, g.k);
-  long long coff = (long long)z * g.sC;
-  if (g.halves > 0) {
-    const int S = g.halves, mg = z >> 1, h = z & 1;
-    const int lim = (bidx >= 0 ? dims[bidx] : m) - mg * 2 * S;
-    if (lim <= S) return;
-    n = min(2 * S, lim);
-    m = k = h == 0 ? S : min(S, lim - S);
-    coff += (long long)mg * g.sC2;
-  } else if (bidx >= 0) {
+  const long long coff = (long long)z * g.sC;
+  if (bidx >= 0) {
     const int lim = dims[bidx] - z * g.bclip_mul;
     if (lim <= g.bclip_min) return;
     m = min(m, lim);
@@ -89,57 +39,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g, const int* __restrict_
   }
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   if (i0 >= m || j0 >= n) return;
-  const double* A = Ab + (long long)z * g.sA;
-  const double* B = Bb + (long long)z * g.sB;
-  double* C = Cb + coff;
+  const double* A = g.A + (long long)z * g.sA;
+  const double* B = g.B + (long long)z * g.sB;
+  double* C = g.C + coff;
   const double* kscale = g.kscale;
   if (g.ksplit > 0) {
     const long long k0 = (long long)z * g.ksplit;
     k = (int)max(0LL, min((long long)g.ksplit, (long long)k - k0));
-    A = Ab + (TA == 0 ? k0 : k0 * g.lda);
-    B = Bb + (TB == 0 ? k0 * g.ldb : k0);
+    A = g.A + (TA == 0 ? k0 : k0 * g.lda);
+    B = g.B + (TB == 0 ? k0 * g.ldb : k0);
     if (kscale) kscale += k0;
   }
-  // 32-deep K slabs through LDS; the next slab's global loads are issued
-  // into registers before the current slab's FMAs, so their latency is
-  // covered by the compute
-  constexpr int GK = 32, NL = GK * 64 / 256;
-  __shared__ double As[GK][65];
-  __shared__ double Bs[GK][65];
+  __shared__ double As[GEMM_GK][65];
+  __shared__ double Bs[GEMM_GK][65];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   double acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-  double ra[NL], rb[NL];
-  gemm_slab_load<TA, TB, GK, NL>(ra, rb, A, B, g.lda, g.ldb, kscale, i0, j0, m, n, k, 0, tid);
-  for (int l0 = 0; l0 < k; l0 += GK) {
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int e = tid + 256 * q;
-      if (TA == 0) As[e % GK][e / GK] = ra[q];
-      else As[e >> 6][e & 63] = ra[q];
-      if (TB == 0) Bs[e >> 6][e & 63] = rb[q];
-      else Bs[e % GK][e / GK] = rb[q];
-    }
-    __syncthreads();
-    if (l0 + GK < k)
-      gemm_slab_load<TA, TB, GK, NL>(ra, rb, A, B, g.lda, g.ldb, kscale, i0, j0, m, n, k, l0 + GK, tid);
-#pragma unroll 4
-    for (int l = 0; l < GK; ++l) {
-      double a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[l][ty + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[l][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
-    }
-    __syncthreads();
-  }
+  gemm_tile_acc<TA, TB>(acc, A, B, g.lda, g.ldb, kscale, i0, j0, m, n, k, As, Bs);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + ty + 16 * r;

@@ -87,20 +87,6 @@ struct GemmDesc {
   // (A, B, kscale offset along k in the kernel; sA, sB unused); a batch past
   // the end writes zeros, so its partial slot is defined
   int ksplit;
-  // njob > 0: blockIdx.z = job * zper + z over up to 4 jobs, each with its own
-  // A, B, C base pointers and bclip index (per-batch strides as above)
-  int njob, zper;
-  // halves = S > 0 (a divide-and-conquer merge level): A is block diagonal
-  // with S x S blocks, so batch z = 2 merge + h multiplies only its h-th
-  // diagonal block by rows [h S, h S + S) of B: m = k = that block's live
-  // size, n = the merge's live size (lim = dims[bclip] - 2 S merge, skipped
-  // when lim <= S); the C offset is z sC + merge sC2
-  int halves;
-  long long sC2;
-  const double* Aj[4];
-  const double* Bj[4];
-  double* Cj[4];
-  int bclipj[4];
 };
 void gemm(const GemmDesc& g, int mcap, int ncap, int batch, const int* dims, hipStream_t s);
 // out[i][j] = sum_{z < nz} part[z][i][j] (fixed order) + beta out[i][j],
