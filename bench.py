@@ -5,18 +5,19 @@ A step is one pass of the whole hot path: TT-format upwind transport
 operator, absorption/emission, TT sum by concatenation, Gram-SVD rounding
 (Gram contractions, eigensolves, truncation, core updates).  The workload is
 the crossing-beam case: 256^2 cells, 32 x 64 ordinates, kappa = 1e-3, cold
-medium, two inflow beams, tolerance 1e-6, rank cap 64, 400 steps in total
-(warmup + timed steps).  Inputs are resident in HBM before timing.  The
-same protocol is then run in the FP32-mixed precision form; its steps/s,
-speedup over FP64 and end-state difference from the FP64 run are reported
-under "fp32_mixed".  Last, the reverse sweep: on the differentiation workload
-(128^2 cells, 16 x 32 ordinates, kappa = exp(random field), Gaussian pulse,
-tolerance 1e-6, rank cap 128, 50 steps, a checkpoint every 10 steps) the
-taped forward and tt_grad (d L / d kappa of the detector-patch energy) are
-timed and reported under "gradient".  Then the optically thick 3-D workload
-(128^3 cells, 32 x 64 ordinates, kappa = 1e3 in the central 64^3 cube,
-coupled material, rank cap 128; concatenated ranks up to 897) in both
-precisions, after its ranks have ramped to the cap, under "thick_3d".
+medium, two inflow beams, tolerance 1e-6, rank cap 64, a 400-step run.  The
+steps before the warmup (400 - warmup - steps, when positive) ramp the ranks
+up untimed, so the timed steps are the run's last ones, at the rank plateau;
+with the default flags the timed steps are 21-400 (the whole run after a
+warmup).  Inputs are resident in HBM before timing, and only the roofline
+kernel's HIP event pair is live in the timed region; the per-phase breakdown
+and roofline fractions come from further, fully profiled steps of the same
+context.  Then: the same protocol in the FP32-mixed form ("fp32_mixed"); the
+rounding benchmark (a seeded synthetic state whose step concatenates to
+(R1, R2) = (322, 62), 100 repeats per precision, "rounding_bench"); the
+reverse sweep of the differentiation workload ("gradient"); the optically
+thick 3-D workload in both precisions ("thick_3d"); machine peaks measured in
+the same process ("measured_peaks"); the CPU oracle on the host's cores.
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported:
 the hot path runs on one GPU.
@@ -40,6 +41,8 @@ ROUNDING_PHASES = ("gram_tall", "gram_reduce", "eig_bond1", "eig_M1", "eig_bond2
                    "x_update", "small_gemm")
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+RUN_STEPS = 400              # the crossing-beam run
+BREAKDOWN_STEPS = 20         # fully profiled steps after the timed ones
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "crossing_beams_256sq_fp64_gram_rows_traffic.md")
@@ -113,17 +116,19 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def timed_run(p, W, K, precision):
-    """Steps 1..W untimed, W+1..W+K timed (inputs resident in HBM)."""
+def timed_run(p, ramp, W, K, precision, nbreak=BREAKDOWN_STEPS):
+    """Steps 1..ramp+W untimed, the next K timed with only the Gram kernel's
+    event pair live, then nbreak steps with every profiling class (the
+    breakdown); inputs resident in HBM throughout."""
     import torch
     from paper_2503_18056_amd import TTState
-    st = TTState(p, device=0, max_steps=W + K, precision=precision)
-    if W:
-        st.step(W)
+    st = TTState(p, device=0, max_steps=ramp + W + K + nbreak, precision=precision)
+    if ramp + W:
+        st.step(ramp + W)
     torch.cuda.synchronize()
     warm = st.cores()
     r_start = st.ranks()
-    st.tt_profile_enable(True)
+    st.tt_profile_enable(True, classes=["gram_tall"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st.step(K)
@@ -131,7 +136,105 @@ def timed_run(p, W, K, precision):
     t1 = time.perf_counter()
     prof = st.tt_profile_read()
     st.tt_profile_enable(False)
-    return st, t1 - t0, prof, warm, r_start
+    r_break = st.ranks()
+    st.tt_profile_enable(True)
+    st.step(nbreak)
+    torch.cuda.synchronize()
+    breakdown = st.tt_profile_read()
+    st.tt_profile_enable(False)
+    return st, t1 - t0, prof, warm, r_start, breakdown, r_break
+
+
+def host_info():
+    """CPU model, visible cores and the BLAS NumPy uses (for the oracle rows)."""
+    info = {"cores_visible": len(os.sched_getaffinity(0))}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if blas:
+            info["blas"] = {"library": blas[0].get("internal_api"), "version": blas[0].get("version"),
+                            "threads": blas[0].get("num_threads")}
+    except Exception:
+        pass
+    return info
+
+
+def measured_peaks():
+    """HBM copy bandwidth and dense FP64 / FP32 MFMA rates of this GPU,
+    measured in this process by the library's microbenchmarks."""
+    import ctypes as C
+    import torch
+    from paper_2503_18056_amd import _ffi
+    lib = _ffi.load()
+    out = {}
+    for which, name, nbytes, iters in ((0, "hbm_copy_GBs", 1 << 30, 10), (1, "fp64_mfma_TFLOPs", 0, 20000),
+                                       (2, "fp32_mfma_TFLOPs", 0, 20000)):
+        wsb = lib.tt_kernel_microbench_workspace(which, nbytes)
+        ws = torch.empty(int(wsb), dtype=torch.uint8, device="cuda")
+        r = C.c_double()
+        st = lib.tt_kernel_microbench(which, nbytes, iters, C.c_void_p(ws.data_ptr()), int(wsb),
+                                      C.byref(r), None)
+        out[name] = r.value if st == 0 else None
+        del ws
+    out["note"] = ("HBM: streaming copy of 1 GiB, read + write bytes; MFMA: v_mfma_f64_16x16x4f64 / "
+                   "v_mfma_f32_16x16x4f32 on register operands, 2048 blocks of 4 wavefronts")
+    return out
+
+
+def phase_roofline(prof, ranks, nsteps, ns, nbc, peaks):
+    """Per-phase roofline of the crossing-beam step (SURVEY 8(d) reading):
+    concat HBM-bound (read X, write X_cat), Gram and X update max(MFMA,
+    HBM), the rank-sized products and eigensolves latency-bound (their
+    measured time is their roofline time).  ``ranks``: (r1, r2) entering
+    each profiled step, and the r1' it rounded to."""
+    def fp64_time(flops, nbytes, peak_tf, bw_gbs):
+        return max(flops / (peak_tf * 1e12), nbytes / (bw_gbs * 1e9))
+    out = {}
+    for label, peak_tf, bw in (("vendor", FP64_PEAK_TFLOPS, HBM_PEAK_GBS),
+                               ("measured", peaks.get("fp64_mfma_TFLOPs"), peaks.get("hbm_copy_GBs"))):
+        if not peak_tf or not bw:
+            continue
+        roof = {"concat": 0.0, "gram_tall": 0.0, "x_update": 0.0}
+        for (r1, r2, r1n) in ranks:
+            R1 = 5 * r1 + nbc
+            roof["concat"] += fp64_time(0.0, ns * (r1 + R1) * 8.0, peak_tf, bw)
+            roof["gram_tall"] += fp64_time(ns * R1 * (R1 + 1.0), ns * R1 * 8.0, peak_tf, bw)
+            roof["x_update"] += fp64_time(2.0 * ns * R1 * r1n, ns * (R1 + r1n) * 8.0, peak_tf, bw)
+        phases = {}
+        tot_meas = prof.get("step", (0.0, 0))[0]
+        tot_roof = 0.0
+        for k, (ms, n) in prof.items():
+            if k in ("step", "material_energy") or n == 0:
+                continue
+            if k in roof:
+                r_ms = roof[k] * 1e3
+                phases[k] = {"measured_ms_per_step": ms / nsteps, "roofline_ms_per_step": r_ms / nsteps,
+                             "frac": r_ms / ms if ms > 0 else None}
+                tot_roof += r_ms
+            elif k == "gram_reduce":
+                phases[k] = {"measured_ms_per_step": ms / nsteps, "roofline_ms_per_step": 0.0,
+                             "frac": 0.0, "note": "no algorithmic work (sums the per-block Gram tiles)"}
+            else:
+                phases[k] = {"measured_ms_per_step": ms / nsteps, "bound": "latency",
+                             "roofline_ms_per_step": ms / nsteps, "frac": 1.0}
+                tot_roof += ms
+        eig_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("eig_bond1", "eig_M1", "eig_bond2", "eig_M2"))
+        small_ms = prof.get("small_gemm", (0.0, 0))[0]
+        bound_ms = tot_roof - eig_ms - small_ms
+        out[label] = {"peaks": {"fp64_TFLOPs": peak_tf, "hbm_GBs": bw}, "phases": phases,
+                      "step_frac_latency_phases_as_measured": tot_roof / tot_meas if tot_meas else None,
+                      "step_frac_bandwidth_and_mfma_phases": (bound_ms / (tot_meas - eig_ms - small_ms)
+                                                              if tot_meas > eig_ms + small_ms else None),
+                      "step_measured_ms": tot_meas / nsteps,
+                      "latency_bound_ms_per_step": (eig_ms + small_ms) / nsteps}
+    return out
 
 
 def cpu_baseline(p, start_cores, nsteps_target_s=15.0, max_steps=60):
@@ -158,8 +261,9 @@ def cpu_baseline(p, start_cores, nsteps_target_s=15.0, max_steps=60):
                 "sample": f"oracle state became non-finite within {n} steps; no rate reported"}
     return {"value": n / dt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} consecutive steps of the same workload starting from the GPU "
-                      f"state after the warmup (ranks {X.shape[1]},{Ph.shape[0]}), "
-                      f"NumPy FP64, {len(os.sched_getaffinity(0))} host cores visible"}
+                      f"state at the start of the timed steps (ranks {X.shape[1]},{Ph.shape[0]}), "
+                      f"NumPy FP64, {len(os.sched_getaffinity(0))} host cores visible",
+            "host": host_info()}
 
 
 def cpu_oracle_extra(p, start_cores, budget_s=12.0):
@@ -206,15 +310,16 @@ def cpu_oracle_extra(p, start_cores, budget_s=12.0):
     return out
 
 
-def mixed_run(p, W, K, dt, hist, end64):
+def mixed_run(p, ramp, W, K, dt, hist, end64):
     """The FP32-mixed precision form on the same workload and protocol."""
     from paper_2503_18056_amd import TT_FP32_MIXED
     ns = p["nx"] * p["ny"]
-    sm, dtm, profm, _, rm_start = timed_run(p, W, K, TT_FP32_MIXED)
+    sm, dtm, profm, _, rm_start, bdm, _ = timed_run(p, ramp, W, K, TT_FP32_MIXED)
     histm = sm.tt_get_rank_history()
     endm = sm.cores()
     gm_ms, gm_n = profm.get("gram_tall", (0.0, 0))
-    rm_in = [rm_start] + histm[W:W + K - 1]
+    s0 = ramp + W
+    rm_in = [rm_start] + histm[s0:s0 + K - 1]
     flops_m = sum(gram_flops(ns, 5 * r1 + 2) for (r1, _) in rm_in)
     mixed = {
         "steps_per_s": K / dtm,
@@ -230,10 +335,51 @@ def mixed_run(p, W, K, dt, hist, end64):
             "peak_fp32_mfma_TFLOPs": FP32_MFMA_PEAK_TFLOPS,
         },
         "kernel_breakdown_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
-                                for k, v in profm.items()},
+                                for k, v in bdm.items()},
+        "breakdown_steps": BREAKDOWN_STEPS,
     }
     sm.close()
     return mixed
+
+
+def rounding_bench(p, reps=100):
+    """Rounding throughput at the crossing-beam cap shape: a seeded
+    synthetic state (orthonormal X and Phi rows, bond-1 spectrum 10^(-k/8),
+    ranks (64, 12)) is installed and stepped once, which concatenates it to
+    (R1, R2) = (322, 62) and rounds that; repeated ``reps`` times per
+    precision with every profiling class on.  Reports the rounding phases
+    per rounding and the whole step."""
+    import torch
+    import workloads as wl
+    from paper_2503_18056_amd import TT_FP32_MIXED, TT_FP64, TTState
+    X, Th, Ph = wl.rounding_bench_cores(p)
+    ns = p["nx"] * p["ny"]
+    out = {"workload": "seeded state on the crossing-beam shape (256^2, 32x64): orthonormal X "
+                       "65536x64, Theta 64x32x12, Phi 12x64, bond-1 singular values 10^(-k/8); "
+                       f"one step concatenates it to (R1, R2) = (322, 62); {reps} repeats"}
+    for name, prec in (("fp64", TT_FP64), ("fp32_mixed", TT_FP32_MIXED)):
+        st = TTState(p, device=0, max_steps=2, precision=prec, cores=(X, Th, Ph))
+        st.step(1)  # first call: module load, not timed
+        st.tt_profile_enable(True)
+        for _ in range(reps):
+            st.tt_set_cores(X, Th, Ph)
+            st.step(1)
+        torch.cuda.synchronize()
+        prof = st.tt_profile_read()
+        st.tt_profile_enable(False)
+        info = st.tt_get_round_info()
+        round_ms = sum(prof.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES) / reps
+        step_ms = prof.get("step", (0.0, 0))[0] / reps
+        R1, r1n = int(info["R1"]), int(info["r1"])
+        # Gram-SVD multiply-adds of the two N_s-long contractions (left Gram, X update)
+        flops = gram_flops(ns, R1) + 2.0 * ns * R1 * r1n
+        out[name] = {"ms_per_rounding": round_ms, "roundings_per_s": 1e3 / round_ms if round_ms else None,
+                     "ms_per_step": step_ms, "R1": R1, "ranks_after": list(st.ranks()),
+                     "ns_long_flops_per_rounding": flops,
+                     "ns_long_TFLOPs": flops / (round_ms * 1e-3) / 1e12 if round_ms else None,
+                     "phases_ms_per_rounding": {k: prof[k][0] / reps for k in ROUNDING_PHASES if k in prof}}
+        st.close()
+    return out
 
 
 def thick_3d_run(W, K):
@@ -243,7 +389,7 @@ def thick_3d_run(W, K):
     to the cap, then K timed steps."""
     import workloads as wl
     from paper_2503_18056_amd import TT_FP32_MIXED, TT_FP64
-    p = wl.c4(steps=W + K)
+    p = wl.c4(steps=W + K + 2)
     ns = p["nx"] * p["ny"] * p["nz"]
     blocks = 1 + 2 * p["dim"]
     out = {"workload": f"{p['name']}: 128^3 cells, 32x64 ordinates, kappa 1e3 in the central "
@@ -252,7 +398,7 @@ def thick_3d_run(W, K):
     ends = {}
     for name, prec in (("fp64", TT_FP64), ("fp32_mixed", TT_FP32_MIXED)):
         progress(f"thick 3-D, {name}: {W} warmup + {K} timed steps")
-        st, dt, prof, _, r_start = timed_run(p, W, K, prec)
+        st, dt, prof, _, r_start, bd, _ = timed_run(p, 0, W, K, prec, nbreak=2)
         hist = st.tt_get_rank_history()
         r_in = [r_start] + hist[W:W + K - 1]
         # concatenated rank at bond 1: (1 + 2 dim) r1 plus the emission slot
@@ -260,7 +406,7 @@ def thick_3d_run(W, K):
         gms, gn = prof.get("gram_tall", (0.0, 0))
         peak = FP64_PEAK_TFLOPS if prec == TT_FP64 else FP32_MFMA_PEAK_TFLOPS
         achieved = flops / (gms * 1e-3) / 1e12 if gms > 0 else 0.0
-        round_ms = sum(prof.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES)
+        round_ms = sum(bd.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES) * K / 2.0
         out[name] = {
             "steps_per_s": K / dt,
             "ms_per_step": dt * 1e3 / K,
@@ -273,8 +419,8 @@ def thick_3d_run(W, K):
                      "avg_launch_ms": gms / gn if gn else None,
                      "achieved_algorithmic_TFLOPs": achieved,
                      "peak_TFLOPs": peak, "frac": achieved / peak},
-            "kernel_breakdown_ms": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
-                                    for k, v in prof.items()},
+            "kernel_breakdown_ms_2_steps": {k: {"ms_total": round(v[0], 3), "launches": v[1]}
+                                            for k, v in bd.items()},
         }
         ends[name] = st.cores()
         st.close()
@@ -327,6 +473,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed run")
     ap.add_argument("--no-grad", action="store_true", help="skip the reverse-sweep run")
+    ap.add_argument("--no-rounding-bench", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the peak microbenchmarks")
     ap.add_argument("--thick3d-steps", type=int, default=6,
                     help="timed steps of the thick 3-D workload in each precision (0 skips it)")
     ap.add_argument("--thick3d-warmup", type=int, default=6)
@@ -342,6 +490,7 @@ def main():
     from paper_2503_18056_amd import TT_FP64
 
     W, K = args.warmup, args.steps
+    ramp = max(0, RUN_STEPS - W - K)
     if args.calib_copy_mib > 0:
         import torch
         n = args.calib_copy_mib * (1 << 20) // 8
@@ -350,30 +499,38 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    p = wl.c2(steps=W + K)
-    progress(f"crossing beams, FP64: {W} warmup + {K} timed steps")
-    st, dt, prof, warm_cores, r_start = timed_run(p, W, K, TT_FP64)
+    p = wl.c2(steps=ramp + W + K)
+    progress(f"crossing beams, FP64: {ramp} ramp + {W} warmup + {K} timed steps")
+    st, dt, prof, warm_cores, r_start, bd, r_break = timed_run(p, ramp, W, K, TT_FP64)
     progress(f"FP64 done: {K / dt:.1f} steps/s")
     hist = st.tt_get_rank_history()
     ns = p["nx"] * p["ny"]
     nang = p["ntheta"] * p["nphi"]
+    nbc = len(p["inflow"])
+    s0 = ramp + W
     # concatenated rank R1 entering each timed step: 5 r1 + 2 inflow terms
-    r_in = [r_start] + hist[W:W + K - 1]
-    R1s = [5 * r1 + 2 for (r1, _) in r_in]
+    r_in = [r_start] + hist[s0:s0 + K - 1]
+    R1s = [5 * r1 + nbc for (r1, _) in r_in]
     gram_ms, gram_n = prof.get("gram_tall", (0.0, 0))
     flops = sum(gram_flops(ns, R) for R in R1s)
     achieved = flops / (gram_ms * 1e-3) / 1e12 if gram_ms > 0 else 0.0
-    breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1]} for k, v in prof.items()}
-    round_ms = sum(prof.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES)
+    breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1]} for k, v in bd.items()}
+    # ranks entering each breakdown step and the r1' each rounded to
+    hb = [r_break] + hist[s0 + K:s0 + K + BREAKDOWN_STEPS]
+    ranks_b = [(hb[i][0], hb[i][1], hb[i + 1][0]) for i in range(len(hb) - 1)]
+    round_ms = sum(bd.get(k, (0.0, 0))[0] for k in ROUNDING_PHASES)
     traffic, alg_bytes = stored_traffic()
     end64 = st.cores()
     ranks64 = list(st.ranks())
     st.close()
     progress(f"FP64 end state: ranks {ranks64}, max |X| {abs(end64[0]).max():.3e}, "
              f"max |Phi| {abs(end64[2]).max():.3e}")
+    peaks = {} if args.no_peaks else measured_peaks()
+    if peaks:
+        progress(f"measured peaks: {peaks}")
     if not args.no_mixed:
         progress("crossing beams, FP32-mixed")
-    mixed = None if args.no_mixed else mixed_run(p, W, K, dt, hist, end64)
+    mixed = None if args.no_mixed else mixed_run(p, ramp, W, K, dt, hist, end64)
     out = {
         "metric": METRIC,
         "value": K / dt,
@@ -388,18 +545,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "crossing beams 256x256 cells, 32x64 ordinates, kappa 1e-3, "
-                               "cold medium, 2 inflow beams, tol 1e-6, rank cap 64, steps "
-                               f"{W + 1}-{W + K} of {W + K}",
+                               "cold medium, 2 inflow beams, tol 1e-6, rank cap 64, timed steps "
+                               f"{s0 + 1}-{s0 + K} of a {s0 + K}-step run",
                    "precision": "fp64", "nx": 256, "ny": 256, "ntheta": 32, "nphi": 64,
                    "tol": 1e-6, "rmax": 64},
+        "ranks_timed_start": list(r_start),
         "ranks_end": ranks64,
         "zcps": ns * K / dt,
         "angle_updates_per_s": ns * nang * K / dt,
         "rounding": {
-            "ms_per_rounding": round_ms / K,
-            "roundings_per_s": K / (round_ms * 1e-3) if round_ms > 0 else None,
-            "note": "Gram-SVD rounding phases of the timed steps (Grams, eigensolves, SVDs, "
-                    "truncation and core updates), from the library's HIP events",
+            "ms_per_rounding": round_ms / BREAKDOWN_STEPS,
+            "roundings_per_s": BREAKDOWN_STEPS / (round_ms * 1e-3) if round_ms > 0 else None,
+            "note": "Gram-SVD rounding phases (Grams, eigensolves, SVDs, truncation and core "
+                    f"updates) of {BREAKDOWN_STEPS} fully profiled steps after the timed ones",
         },
         "roofline": {
             "kernel": GRAM_KERNEL64 if R1CAP <= GRAM_ROWS_MAX else "k_gram_wide + k_gram_wide_reduce",
@@ -408,16 +566,26 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
+            "frac_of_measured_peak": (achieved / peaks["fp64_mfma_TFLOPs"]
+                                      if peaks.get("fp64_mfma_TFLOPs") else None),
             "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
                             "profiles/crossing_beams_256sq_fp64_gram_rows_traffic.md)",
             "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_ms": gram_ms / gram_n if gram_n else None,
             "algorithmic_flops_per_launch_avg": flops / max(1, gram_n),
+            "timing": "HIP events on the library's stream around each launch in the timed steps "
+                      "(the only events live there)",
         },
+        "phase_roofline": phase_roofline(bd, ranks_b, BREAKDOWN_STEPS, ns, nbc, peaks),
         "kernel_breakdown_ms": breakdown,
+        "breakdown_steps": f"{BREAKDOWN_STEPS} fully profiled steps after the timed ones",
+        "measured_peaks": peaks or None,
         "fp32_mixed": mixed,
     }
+    if not args.no_rounding_bench:
+        progress("rounding benchmark at (R1, R2) = (322, 62)")
+        out["rounding_bench"] = rounding_bench(wl.c2(steps=2))
     if not args.no_grad:
         progress("differentiation workload: taped forward and reverse sweep")
         out["gradient"] = gradient_run()

@@ -219,7 +219,9 @@ tt_status tt_set_rank_schedule(tt_ctx* ctx, const int32_t* r1r2, int32_t nroundi
 tt_status tt_get_round_info(tt_ctx* ctx, double out[16]);
 
 /* Kernel timing with HIP events on the context's stream.  enable != 0
- * starts recording (resets counters).  tt_profile_read fills, for up to
+ * starts recording (resets counters): 1 records every class, any other
+ * value records the classes k whose bit k + 1 is set (one event pair per
+ * timed region of those classes only).  tt_profile_read fills, for up to
  * `cap` kernel classes, the total milliseconds, the launch count and a
  * static name; returns the number of classes in *n. */
 tt_status tt_profile_enable(tt_ctx* ctx, int32_t enable);

@@ -101,6 +101,18 @@ tt_status tt_kernel_gemm(const double* A, int32_t lda, int32_t ta, const double*
  * runtime's static sizes, before launching. */
 tt_status tt_kernel_lds_check(int32_t n, int32_t ncap2, int32_t pcap, size_t* max_bytes);
 
+/* Peak microbenchmarks of this GPU, for roofline fractions against what it
+ * delivers: which = 0, HBM streaming copy of copy_bytes (16-byte loads and
+ * stores), repeated `iters` times, result in GB/s counting read + write;
+ * which = 1 / 2, dense FP64 / FP32 MFMA (16x16x4 on register operands,
+ * `iters` rounds of four independent products per wavefront on 2048 blocks
+ * of four wavefronts), result in TFLOP/s.  ws: device scratch of
+ * tt_kernel_microbench_workspace(which, copy_bytes) bytes.  Timed with HIP
+ * events on `stream` after one untimed launch. */
+size_t tt_kernel_microbench_workspace(int32_t which, size_t copy_bytes);
+tt_status tt_kernel_microbench(int32_t which, size_t copy_bytes, int32_t iters, void* ws,
+                               size_t ws_bytes, double* result, void* stream);
+
 /* Message of the last failed kernel-level call on this thread. */
 const char* tt_kernel_last_error(void);
 

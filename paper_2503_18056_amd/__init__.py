@@ -203,8 +203,21 @@ class TTState:
                 "s1", "s_r1", "s_r1p", "s_r2", "s_r2p", "R1"]
         return dict(zip(keys, out.tolist()))
 
-    def tt_profile_enable(self, on=True):
-        self._check(self.lib.tt_profile_enable(self.ctx, 1 if on else 0))
+    PROFILE_CLASSES = ("concat", "gram_tall", "gram_reduce", "eig_bond1", "eig_M1", "eig_bond2",
+                       "eig_M2", "x_update", "small_gemm", "material_energy", "step")
+
+    def tt_profile_enable(self, on=True, classes=None):
+        """Start (on) or stop recording HIP-event timings; ``classes`` (names
+        from PROFILE_CLASSES) restricts recording to those regions."""
+        if not on:
+            mask = 0
+        elif classes is None:
+            mask = 1
+        else:
+            mask = 0
+            for name in classes:
+                mask |= 1 << (self.PROFILE_CLASSES.index(name) + 1)
+        self._check(self.lib.tt_profile_enable(self.ctx, mask))
 
     def tt_profile_read(self):
         cap = 32

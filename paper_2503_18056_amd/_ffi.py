@@ -79,6 +79,8 @@ SIGNATURES = {
     "tt_kernel_gemm": (C.c_int, [VP, C.c_int32, C.c_int32, VP, C.c_int32, C.c_int32, VP, C.c_int32,
                                  C.c_int32, C.c_int32, C.c_int32, VP, C.c_size_t, VP]),
     "tt_kernel_lds_check": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "tt_kernel_microbench_workspace": (C.c_size_t, [C.c_int32, C.c_size_t]),
+    "tt_kernel_microbench": (C.c_int, [C.c_int32, C.c_size_t, C.c_int32, VP, C.c_size_t, PD, VP]),
     "tt_kernel_last_error": (C.c_char_p, []),
     "tt_destroy": (None, [VP]),
 }

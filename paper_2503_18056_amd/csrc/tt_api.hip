@@ -302,7 +302,7 @@ std::vector<int> face_cells(const tt_ctx* x, int face) {
 // Each timed region reserves one (start, end) event pair on the context's
 // stream; tt_profile_read sums the elapsed times per class.
 long prof_begin(tt_ctx* c, int cls) {
-  if (!c->prof) return -1;
+  if (!c->prof || !((c->prof_mask >> cls) & 1u)) return -1;
   if (c->ev_used >= c->ev.size()) {
     if (c->ev.size() >= 200000) return -1;
     hipEvent_t a, b;
@@ -1033,6 +1033,8 @@ tt_status tt_profile_enable(tt_ctx* c, int32_t enable) {
   if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->prof = enable != 0;
+  // 1: every class; otherwise bit k + 1 selects class k
+  c->prof_mask = enable == 1 ? ~0u : ((unsigned)enable >> 1);
   c->ev_used = 0;
   return TT_OK;
 }

@@ -112,6 +112,7 @@ struct tt_ctx {
   std::string err;
   // profiling
   bool prof = false;
+  unsigned prof_mask = 0;    // classes recorded (bit k: class k)
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
   size_t ev_used = 0;
 };

@@ -316,3 +316,22 @@ def gaussian_diffusion(n=64, ntheta=8, nphi=16, steps=200, t0=200.0, rho_kappa_s
     p["diffusion"] = dict(D=D, t0=t0, A=A)
     p["name"] = f"gaussian_diffusion_{n}sq_{ntheta}x{nphi}"
     return p
+
+
+def rounding_bench_cores(p, r1=64, r2=12, seed=2, decades_per_8=1.0):
+    """Seeded synthetic state on the crossing-beam shape for the rounding
+    benchmark: orthonormal X (N_s x r1), orthonormal Phi rows (r2 x N_phi)
+    and a middle core whose bond-1 unfolding is diag(s) Q with Q having
+    orthonormal rows, so the bond-1 singular values are s_k = 10^(-k/8)
+    (k = 0 .. r1-1).  One step of the crossing-beam workload from this state
+    concatenates it to ranks (5 r1 + 2, 5 r2 + 2) = (322, 62) before
+    rounding."""
+    rng = np.random.default_rng(seed)
+    ns = p["nx"] * p["ny"] * p["nz"]
+    nt, npf = p["ntheta"], p["nphi"]
+    X = np.linalg.qr(rng.standard_normal((ns, r1)))[0]
+    Ph = np.linalg.qr(rng.standard_normal((npf, r2)))[0].T
+    Q = np.linalg.qr(rng.standard_normal((nt * r2, r1)))[0].T  # r1 x (nt r2), orthonormal rows
+    s = 10.0 ** (-np.arange(r1) * decades_per_8 / 8.0)
+    Th = (s[:, None] * Q).reshape(r1, nt, r2)
+    return X, Th, Ph
