@@ -228,6 +228,18 @@ tt_status tt_profile_enable(tt_ctx* ctx, int32_t enable);
 tt_status tt_profile_read(tt_ctx* ctx, double* ms, int32_t* count, const char** names,
                           int32_t cap, int32_t* n);
 
+/* Step execution mode.  enable != 0 (the default): tt_step replays the
+ * step's launch sequence as a HIP graph, captured on first use once per
+ * state buffer (the step alternates two) on a private non-blocking stream
+ * of the context and launched on the context's stream; steps taken while
+ * event timing is on or while the gradient tape records run eagerly, and
+ * so does every step after a capture the runtime refuses.  enable == 0:
+ * every step launches its kernels one by one.  Both modes compute the same
+ * bits.  Captured graphs are dropped when this is called, when the
+ * scattering field or the rank schedule changes, and by tt_destroy.
+ * Synchronises the context's stream. */
+tt_status tt_use_graphs(tt_ctx* ctx, int32_t enable);
+
 const char* tt_last_error(const tt_ctx* ctx);
 
 /* Destroy a context (NULL is accepted); the workspace is not freed. */

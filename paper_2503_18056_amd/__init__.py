@@ -206,6 +206,11 @@ class TTState:
     PROFILE_CLASSES = ("concat", "gram_tall", "gram_reduce", "eig_bond1", "eig_M1", "eig_bond2",
                        "eig_M2", "x_update", "small_gemm", "material_energy", "step")
 
+    def use_graphs(self, on=True):
+        """Replay each step as a captured HIP graph (default) or launch its
+        kernels one by one; both give the same bits."""
+        self._check(self.lib.tt_use_graphs(self.ctx, 1 if on else 0))
+
     def tt_profile_enable(self, on=True, classes=None):
         """Start (on) or stop recording HIP-event timings; ``classes`` (names
         from PROFILE_CLASSES) restricts recording to those regions."""

@@ -502,14 +502,17 @@ __global__ __launch_bounds__(256) void k_svd_vectors(const double* __restrict__ 
   }
 }
 
-// Close a step: new ranks become the state ranks, history, finiteness.
-__global__ void k_finish(int* __restrict__ dims, int* __restrict__ hist, int slot) {
+// Close a step: new ranks become the state ranks; with hist, the ranks go
+// to history slot dims[D_HSLOT] while it is below hmax, and the slot advances.
+__global__ void k_finish(int* __restrict__ dims, int* __restrict__ hist, int hmax) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   dims[D_R1] = dims[D_R1N];
   dims[D_R2] = dims[D_R2N];
-  if (hist && slot >= 0) {
+  const int slot = dims[D_HSLOT];
+  if (hist && slot < hmax) {
     hist[2 * slot] = dims[D_R1N];
     hist[2 * slot + 1] = dims[D_R2N];
+    dims[D_HSLOT] = slot + 1;
   }
 }
 
@@ -672,8 +675,8 @@ void launch_svd_vectors(const double* Uc, int ldu, const double* sqc, double* Ur
                         int zero, int rcap, hipStream_t st) {
   k_svd_vectors<<<rcap, 256, 0, st>>>(Uc, ldu, sqc, Ur, ldr, Wm, ldw, dims, ka, kb, side, rn, zero);
 }
-void launch_finish(int* dims, int* hist, int slot, hipStream_t st) {
-  k_finish<<<1, 64, 0, st>>>(dims, hist, slot);
+void launch_finish(int* dims, int* hist, int hmax, hipStream_t st) {
+  k_finish<<<1, 64, 0, st>>>(dims, hist, hmax);
 }
 void launch_check_finite(const double* x, int n, int* dims, hipStream_t st) {
   int blocks = (n + 255) / 256;

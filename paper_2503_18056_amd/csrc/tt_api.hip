@@ -481,11 +481,19 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
   }
 }
 
-__global__ void k_set_replay(int* dims, const int* sched, int k, int n) {
+// Ranks of the next replayed rounding: schedule entry dims[D_SCHEDPOS] (0
+// past its end: the rank rule), then the position advances.
+__global__ void k_set_replay(int* dims, const int* sched, int n) {
   if (threadIdx.x == 0) {
+    const int k = dims[D_SCHEDPOS];
     dims[D_REPLAY1] = k < n ? sched[2 * k] : 0;
     dims[D_REPLAY2] = k < n ? sched[2 * k + 1] : 0;
+    dims[D_SCHEDPOS] = k + 1;
   }
+}
+
+__global__ void k_set_dim(int* dims, int idx, int v) {
+  if (threadIdx.x == 0) dims[idx] = v;
 }
 
 tt_status check_flags(tt_ctx* c) {
@@ -536,6 +544,184 @@ void step_body_frozen(tt_ctx* c) {
 }
 
 }  // namespace tt
+
+namespace {
+
+// Every launch of one step on c->st, with its host bookkeeping (state
+// buffer swaps, history count, schedule position).  No host synchronisation
+// and no memset, so the sequence can be captured as a graph.
+void step_once(tt_ctx* c) {
+  hipStream_t s = c->st;
+  const tt_config& cf = c->cfg;
+  const bool coupled = cf.material == TT_MAT_COUPLED;
+  // the source coefficients depend on this step's E* (Newton, or J^{m+1})
+  const bool dyn = coupled || c->scatter;
+  const double* ks = c->scatter ? c->kappa_s : nullptr;
+  const bool twice = cf.schedule == TT_ROUND_TWICE;
+  auto replay_next = [&]() {
+    if (cf.rank_mode == TT_RANK_REPLAY) {
+      k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->nsched);
+      c->sched_pos++;
+    }
+  };
+  auto swap_state = [&]() {
+    if (c->mixed) std::swap(c->Xf, c->Xnf);
+    else std::swap(c->X, c->Xn);
+  };
+  replay_next();
+  if (!twice) {
+    {
+      Prof p(c, P_CONCAT);
+      launch_concat_dims(c->G, c->dims, s);
+      launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
+      launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
+      if (c->mixed)
+        launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims,
+                          dyn ? 0 : 1, s);
+      else
+        launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
+                          dyn ? 0 : 1, s);
+    }
+    if (dyn) {
+      Prof p(c, P_MAT);
+      // E* = (1/c) X_tr z over the transport columns (source column excluded)
+      if (c->mixed)
+        launch_energy(c->Xcatf, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
+                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
+                      c->Estar, c->dims, c->R1c, c->R2c, s);
+      else
+        launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
+                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
+                      c->Estar, c->dims, c->R1c, c->R2c, s);
+      launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
+                      c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
+      if (c->mixed) launch_scale_xcat(c->G, c->d, c->s, c->Xcatf, c->ldC, c->dims, s);
+      else launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
+    }
+    if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
+    else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
+  } else {
+    // Sec. 4.2: round the transport sum, apply the source update to the
+    // rounded state, round again
+    StepGeom Gt = c->G;
+    Gt.nem = 0;
+    {
+      Prof p(c, P_CONCAT);
+      launch_transport_dims(Gt, c->dims, s);
+      launch_build_phcat(Gt, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
+      launch_build_thcat(Gt, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
+      if (c->mixed)
+        launch_build_xcat(Gt, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims, 0, s);
+      else
+        launch_build_xcat(Gt, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims, 0, s);
+    }
+    if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
+    else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
+    launch_finish(c->dims, nullptr, 0, s);
+    swap_state();
+    if (dyn) {
+      Prof p(c, P_MAT);
+      energy_of_state(c, c->Estar);
+      launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
+                      c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
+    }
+    replay_next();
+    {
+      Prof p(c, P_CONCAT);
+      if (c->mixed)
+        launch_source_cat(c->G, c->Xf, c->ldX, c->d, c->s, c->Xcatf, c->ldC, c->Th, c->Ph,
+                          c->Thcat, c->Phcat, c->dims, s);
+      else
+        launch_source_cat(c->G, c->X, c->ldX, c->d, c->s, c->Xcat, c->ldC, c->Th, c->Ph,
+                          c->Thcat, c->Phcat, c->dims, s);
+    }
+    if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->r1c + 1, cf.tol, cf.rmax, c->Xcatf);
+    else round_pipeline(c, c->Xcat, c->ldC, c->r1c + 1, cf.tol, cf.rmax);
+  }
+  launch_finish(c->dims, c->hist, std::max(1, cf.max_steps), s);
+  c->nhist = std::min(c->nhist + 1, std::max(1, cf.max_steps));
+  swap_state();
+  if (coupled) {
+    Prof p(c, P_MAT);
+    energy_of_state(c, c->Enew);
+    launch_temperature(c->ns, c->rho, c->cv, c->Estar, c->Enew, c->T, s);
+  }
+}
+
+void graphs_drop(tt_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->gexec[k]) hipGraphExecDestroy(c->gexec[k]);
+    c->gexec[k] = nullptr;
+    c->gkey[k] = nullptr;
+  }
+}
+
+// One step by graph replay.  The step's launches depend on the host state
+// only through which buffer holds the state (the swaps alternate it), so
+// one graph per buffer is captured on first use, on the context's own
+// capture stream (the null stream cannot be captured), and launched on
+// c->st.  The host bookkeeping the capture performed is undone and then
+// applied after each launch, as step_once does.
+hipError_t step_graph(tt_ctx* c) {
+  const void* key = c->mixed ? (const void*)c->Xf : (const void*)c->X;
+  int k = c->gkey[0] == key ? 0 : c->gkey[1] == key ? 1 : -1;
+  if (k < 0) {
+    k = c->gexec[0] ? 1 : 0;
+    if (c->gexec[k]) {
+      graphs_drop(c);
+      k = 0;
+    }
+    hipError_t e = hipSuccess;
+    if (!c->cap_st) {
+      e = hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    hipStream_t st0 = c->st;
+    double *X0 = c->X, *Xn0 = c->Xn;
+    float *Xf0 = c->Xf, *Xnf0 = c->Xnf;
+    const int nh0 = c->nhist, sp0 = c->sched_pos;
+    c->st = c->cap_st;
+    e = hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      c->st = st0;
+      return e;
+    }
+    step_once(c);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap_st, &g);
+    c->gafter[k][0] = c->X;
+    c->gafter[k][1] = c->Xn;
+    c->gafterf[k][0] = c->Xf;
+    c->gafterf[k][1] = c->Xnf;
+    c->gsched[k] = c->sched_pos - sp0;
+    c->st = st0;
+    c->X = X0;
+    c->Xn = Xn0;
+    c->Xf = Xf0;
+    c->Xnf = Xnf0;
+    c->nhist = nh0;
+    c->sched_pos = sp0;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->gexec[k] = nullptr;
+      return e;
+    }
+    c->gkey[k] = key;
+  }
+  const hipError_t e = hipGraphLaunch(c->gexec[k], c->st);
+  if (e != hipSuccess) return e;
+  c->X = c->gafter[k][0];
+  c->Xn = c->gafter[k][1];
+  c->Xf = c->gafterf[k][0];
+  c->Xnf = c->gafterf[k][1];
+  c->sched_pos += c->gsched[k];
+  c->nhist = std::min(c->nhist + 1, std::max(1, c->cfg.max_steps));
+  return hipSuccess;
+}
+
+}  // namespace
 
 // ============================================================================
 extern "C" {
@@ -742,105 +928,23 @@ tt_status tt_step(tt_ctx* c, int32_t nsteps) {
   if (nsteps < 0) return fail(c, TT_ERR_INVALID_ARG, "nsteps < 0");
   hipStream_t s = c->st;
   const tt_config& cf = c->cfg;
-  const bool coupled = cf.material == TT_MAT_COUPLED;
-  // the source coefficients depend on this step's E* (Newton, or J^{m+1})
-  const bool dyn = coupled || c->scatter;
-  const double* ks = c->scatter ? c->kappa_s : nullptr;
-  const bool twice = cf.schedule == TT_ROUND_TWICE;
   if (c->gb.on && c->nhist + nsteps > std::max(1, cf.max_steps))
     return fail(c, TT_ERR_STATE, "tape full: more steps since tt_set_cores than max_steps");
-  auto replay_next = [&]() {
-    if (cf.rank_mode == TT_RANK_REPLAY) {
-      k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->sched_pos, c->nsched);
-      c->sched_pos++;
-    }
-  };
-  auto swap_state = [&]() {
-    if (c->mixed) std::swap(c->Xf, c->Xnf);
-    else std::swap(c->X, c->Xn);
-  };
+  // graph replay unless a step needs host work of its own (event timing,
+  // the gradient tape's checkpoints)
+  const bool use_graph = c->graphs && !c->prof && !c->gb.on;
   for (int m = 0; m < nsteps; ++m) {
+    if (use_graph) {
+      const hipError_t e = step_graph(c);
+      if (e == hipSuccess) continue;
+      // capture unavailable here: eager steps from now on
+      (void)hipGetLastError();
+      graphs_drop(c);
+      c->graphs = false;
+    }
     Prof pstep(c, P_STEP);
     if (c->gb.on) HIPCHK(c, grad_record(c));
-    replay_next();
-    const int slot = c->nhist < std::max(1, cf.max_steps) ? c->nhist : -1;
-    if (!twice) {
-      {
-        Prof p(c, P_CONCAT);
-        launch_concat_dims(c->G, c->dims, s);
-        launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
-        launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
-        if (c->mixed)
-          launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims,
-                            dyn ? 0 : 1, s);
-        else
-          launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
-                            dyn ? 0 : 1, s);
-      }
-      if (dyn) {
-        Prof p(c, P_MAT);
-        // E* = (1/c) X_tr z over the transport columns (source column excluded)
-        if (c->mixed)
-          launch_energy(c->Xcatf, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
-                        c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
-                        c->Estar, c->dims, c->R1c, c->R2c, s);
-        else
-          launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
-                        c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
-                        c->Estar, c->dims, c->R1c, c->R2c, s);
-        launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
-                        c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
-        if (c->mixed) launch_scale_xcat(c->G, c->d, c->s, c->Xcatf, c->ldC, c->dims, s);
-        else launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
-      }
-      if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
-      else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
-    } else {
-      // Sec. 4.2: round the transport sum, apply the source update to the
-      // rounded state, round again
-      StepGeom Gt = c->G;
-      Gt.nem = 0;
-      {
-        Prof p(c, P_CONCAT);
-        launch_transport_dims(Gt, c->dims, s);
-        launch_build_phcat(Gt, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
-        launch_build_thcat(Gt, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
-        if (c->mixed)
-          launch_build_xcat(Gt, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims, 0, s);
-        else
-          launch_build_xcat(Gt, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims, 0, s);
-      }
-      if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
-      else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);
-      launch_finish(c->dims, nullptr, -1, s);
-      swap_state();
-      if (dyn) {
-        Prof p(c, P_MAT);
-        energy_of_state(c, c->Estar);
-        launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
-                        c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
-      }
-      replay_next();
-      {
-        Prof p(c, P_CONCAT);
-        if (c->mixed)
-          launch_source_cat(c->G, c->Xf, c->ldX, c->d, c->s, c->Xcatf, c->ldC, c->Th, c->Ph,
-                            c->Thcat, c->Phcat, c->dims, s);
-        else
-          launch_source_cat(c->G, c->X, c->ldX, c->d, c->s, c->Xcat, c->ldC, c->Th, c->Ph,
-                            c->Thcat, c->Phcat, c->dims, s);
-      }
-      if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->r1c + 1, cf.tol, cf.rmax, c->Xcatf);
-      else round_pipeline(c, c->Xcat, c->ldC, c->r1c + 1, cf.tol, cf.rmax);
-    }
-    launch_finish(c->dims, c->hist, slot, s);
-    c->nhist = std::min(c->nhist + 1, std::max(1, cf.max_steps));
-    swap_state();
-    if (coupled) {
-      Prof p(c, P_MAT);
-      energy_of_state(c, c->Enew);
-      launch_temperature(c->ns, c->rho, c->cv, c->Estar, c->Enew, c->T, s);
-    }
+    step_once(c);
   }
   HIPCHK(c, hipGetLastError());
   launch_check_state(c->X, c->mixed ? c->Xf : nullptr, c->ldX, c->ns, c->Th, c->nt, c->r2c, c->Ph,
@@ -856,14 +960,14 @@ tt_status tt_round(tt_ctx* c, double tol, int32_t rmax, int32_t ranks_out[2]) {
   // the recorded steps no longer end in the stored state
   if (c->gb.on && c->nhist > 0) c->gb.stale = true;
   if (c->cfg.rank_mode == TT_RANK_REPLAY) {
-    k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->sched_pos, c->nsched);
+    k_set_replay<<<1, 64, 0, s>>>(c->dims, c->sched, c->nsched);
     c->sched_pos++;
   }
   launch_round_dims(c->dims, s);
   launch_state_as_cat(c->G, c->Th, c->Ph, c->Thcat, c->Phcat, c->dims, s);
   if (c->mixed) round_pipeline(c, nullptr, c->ldX, c->r1c, tol, rmax, c->Xf);
   else round_pipeline(c, c->X, c->ldX, c->r1c, tol, rmax);
-  launch_finish(c->dims, nullptr, -1, s);
+  launch_finish(c->dims, nullptr, 0, s);
   if (c->mixed) std::swap(c->Xf, c->Xnf);
   else std::swap(c->X, c->Xn);
   HIPCHK(c, hipGetLastError());
@@ -930,6 +1034,7 @@ tt_status tt_set_scattering(tt_ctx* c, const double* kappa_s) {
   // the isotropic source block carries the scattering term
   c->nem = (c->nem_base || any) ? 1 : 0;
   c->G.nem = c->nem;
+  graphs_drop(c);  // the step's launch list changed
   return TT_OK;
 }
 
@@ -1008,8 +1113,11 @@ tt_status tt_set_rank_schedule(tt_ctx* c, const int32_t* r1r2, int32_t nrounding
   if (nroundings > 0)
     HIPCHK(c, hipMemcpyAsync(c->sched, r1r2, 2 * nroundings * sizeof(int), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  k_set_dim<<<1, 64, 0, c->st>>>(c->dims, D_SCHEDPOS, 0);
+  HIPCHK(c, hipStreamSynchronize(c->st));
   c->nsched = nroundings;
   c->sched_pos = 0;
+  graphs_drop(c);  // the replay launches carry the schedule length
   return TT_OK;
 }
 
@@ -1064,9 +1172,19 @@ tt_status tt_profile_read(tt_ctx* c, double* ms, int32_t* count, const char** na
 
 const char* tt_last_error(const tt_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
+tt_status tt_use_graphs(tt_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  graphs_drop(c);
+  c->graphs = enable != 0;
+  return TT_OK;
+}
+
 void tt_destroy(tt_ctx* c) {
   if (!c) return;
   hipStreamSynchronize(c->st);
+  graphs_drop(c);
+  if (c->cap_st) hipStreamDestroy(c->cap_st);
   for (auto& e : c->ev) {
     hipEventDestroy(e.second.first);
     hipEventDestroy(e.second.second);

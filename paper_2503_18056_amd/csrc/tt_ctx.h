@@ -110,6 +110,16 @@ struct tt_ctx {
   int nhist = 0, nsched = 0, sched_pos = 0;
   bool poisoned = false;
   std::string err;
+  // step graphs: one per state buffer (the step swaps buffers), captured on
+  // cap_st; gafter / gafterf / gsched are the host bookkeeping one replay
+  // performs (buffers after the step, schedule entries consumed)
+  bool graphs = true;
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  const void* gkey[2] = {nullptr, nullptr};
+  double* gafter[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  float* gafterf[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int gsched[2] = {0, 0};
   // profiling
   bool prof = false;
   unsigned prof_mask = 0;    // classes recorded (bit k: class k)

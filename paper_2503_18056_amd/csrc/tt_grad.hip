@@ -402,7 +402,7 @@ extern "C" tt_status tt_grad(tt_ctx* c, const double* detector_w, double loss_ba
       if (m == m1 - 1) break;
       launch_replay_from_hist(d, c->hist, m, s);
       step_body_frozen(c);
-      launch_finish(d, nullptr, -1, s);
+      launch_finish(d, nullptr, 0, s);
       swap_state(c);
     }
     for (int m = m1 - 1; m >= m0; --m) {

@@ -36,6 +36,8 @@ enum DimIndex : int {
   D_ZERO2,
   D_TGK1,        // order 2 min(kA, kB) of the Golub-Kahan tridiagonal, bond 1
   D_TGK2,
+  D_HSLOT,       // next rank-history slot (steps recorded since the cores were set)
+  D_SCHEDPOS,    // next entry of the replayed rank schedule
   D_NDIMS = 64
 };
 

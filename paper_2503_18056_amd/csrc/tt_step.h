@@ -83,7 +83,9 @@ void launch_rank(const double* sig, int* dims, double* diag, const RankArgs& ra,
 void launch_svd_vectors(const double* Uc, int ldu, const double* sqc, double* Ur, int ldr,
                         double* Wm, int ldw, const int* dims, int ka, int kb, int side, int rn,
                         int zero, int rcap, hipStream_t st);
-void launch_finish(int* dims, int* hist, int slot, hipStream_t st);
+// Close a step (state ranks <- new ranks); with hist, record them in the
+// history slot dims[D_HSLOT] while it is below hmax.
+void launch_finish(int* dims, int* hist, int hmax, hipStream_t st);
 void launch_check_finite(const double* x, int n, int* dims, hipStream_t st);
 // Finiteness of the state: X (N_s x r1 live, ld ldX), Theta (r1 x nt x r2
 // live, ld r2c), Phi (r2 x np) and T (N_s); raises FLAG_NONFINITE.
