@@ -330,6 +330,11 @@ def test_grad_c5_full_size():
     ok = err <= 1e-4 * gmax + 2.0 * est
     err_m = np.abs(gm[cells] - f1)
     tight = int(np.sum(err <= 1e-4 * np.abs(f1)))
+    # the per-cell target 1e-4 max(|g_FD|, 1e-2 max|g_FD|): reported, not met
+    # at this size (the forward's FP64 Gram floor, amplified by 1 / (2 h),
+    # dominates small cells); the asserted bar below adds the measured spread
+    # of three step sizes and is a diagnostic of agreement within that noise
+    q26 = int(np.sum(err <= 1e-4 * np.maximum(np.abs(f1), 1e-2 * np.max(np.abs(f1)))))
     # (3) full-grid adjoint, (4) mixed vs FP64
     _log("  differences done; the oracle's full-grid adjoint next")
     Lf, gf = oadj.grad_full(Setup(p), steps, det)
@@ -338,6 +343,8 @@ def test_grad_c5_full_size():
     _log(f"c5 full size: ranks end {ranks[-1]} (max r1 {max(r for r, _ in ranks)}), L={L:.10e}, "
          f"mixed L={Lm:.10e} (ranks equal: {ranks_m == ranks}), full-grid L={Lf:.10e}")
     _log(f"  Taylor test along the gradient: fp64 {rel_dir:.2e}, mixed {rel_dir_m:.2e}")
+    _log(f"  32 cells, h=1e-3: per-cell target 1e-4 max(|g_FD|, 1e-2 max|g_FD|) met by {q26}/32 "
+         f"(not asserted); within 1e-4 of their own value: {tight}/32")
     _log(f"  32 cells, h=1e-3: max rel err {np.max(err / np.abs(f1)):.2e}; within 1e-4: {tight}/32; "
          f"within 1e-4 max|g| + 2 spread: {int(ok.sum())}/32; max err/spread "
          f"{np.max(err / np.maximum(est, 1e-300)):.2f}")

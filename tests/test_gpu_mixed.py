@@ -80,7 +80,8 @@ def test_mixed_round_vs_oracle():
 def test_mixed_crossing_beams_400_steps_vs_oracle():
     """The crossing-beam workload (256^2 cells, 32x64 ordinates, tolerance
     1e-6, cap 64) over all 400 steps: the mixed form within 1e-5 of the FP64
-    oracle; the FP64 form's difference is logged beside it."""
+    oracle, the FP64 form within 1.5e-6 (about ten times its measured
+    1.4e-7)."""
     from paper_2503_18056_amd import TTState
     p = wl.c2(steps=400)
     s = Setup(p)
@@ -99,3 +100,4 @@ def test_mixed_crossing_beams_400_steps_vs_oracle():
     _log(f"crossing beams 400 steps: mixed err={err:.2e} (ranks equal to the oracle's at "
          f"{same}/400 steps, end {hm[-1]} vs {hist[-1]}); fp64 err={err64:.2e} ({same64}/400)")
     assert err < 1e-5
+    assert err64 < 1.5e-6

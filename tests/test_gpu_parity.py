@@ -271,25 +271,27 @@ def test_c1_parity():
     """C1 (32^2, 8x16, 10 steps, tolerance 1e-8 at the FP64 Gram floor, and
     the same case at 1e-6): every step from the oracle's state matches (see
     _single_step_parity) with identical ranks; the free-running 10-step
-    runs keep the oracle's ranks (see _free_run) and stay within 1e-6; with
-    the oracle's ranks replayed the 10-step runs agree to 1e-6."""
+    runs keep the oracle's ranks (see _free_run) and, like the runs with the
+    oracle's ranks replayed, end within 2e-8 (about ten times the measured
+    0.9-1.8e-9)."""
     for tol in (1e-6, 1e-8):
         p = wl.c1()
         p["tol"] = tol
         states, infos = _trajectory(p, 10)
         _single_step_parity(p, states, range(10))
-        hist = _free_run(p, states, infos, 10, 1e-6)
-        _replay_run(p, hist, states, 10, 1e-6)
+        hist = _free_run(p, states, infos, 10, 2e-8)
+        _replay_run(p, hist, states, 10, 2e-8)
 
 
 def test_c2_parity():
     """C2 (256^2, 32x64, cap 64), first 40 steps: single steps from oracle
     states (see _single_step_parity) with identical ranks; the free run keeps
     the oracle's ranks up to a rounding-determined decision and ends within
-    1e-5 (ten times the tolerance); with the oracle's ranks replayed the
-    40-step run agrees to 1e-6."""
+    1.5e-6 (about ten times the measured 0.45-1.3e-7, the upper value when a
+    rank decision inside MARGIN went the other way); with the oracle's ranks
+    replayed the 40-step run agrees to 5e-7 (measured 4.5e-8)."""
     p = wl.c2(steps=40)
     states, infos = _trajectory(p, 40)
     _single_step_parity(p, states, [0, 1, 2, 5, 13, 20, 39])
-    hist = _free_run(p, states, infos, 40, 1e-5)
-    _replay_run(p, hist, states, 40, 1e-6)
+    hist = _free_run(p, states, infos, 40, 1.5e-6)
+    _replay_run(p, hist, states, 40, 5e-7)

@@ -16,6 +16,12 @@ oracle once and by the library in FP64 and in the FP32-mixed form:
   the same bars;
 - FP32-mixed: state below 1e-5 (the precision target), temperature below
   1e-5 relative (its update differences energies of FP32-stored cores).
+
+Inside the capped regime (after steps 20 and 100 of the library's own run)
+one oracle step and one library step from the same state are compared:
+identical ranks, temperature to 1e-10, and the state tagged pinned (1e-10)
+or unpinned (a bar of four times the oracle's own spread) as in the smaller
+cases' single-step parity.
 """
 import sys
 import time
@@ -24,12 +30,32 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from oracle import Setup, metrics, tt
+from oracle import Setup, metrics, rounding, tt
 
 pytestmark = pytest.mark.gpu
 
 NSTEPS = 5
 MARGIN = 1e-3
+SPREAD_FACTOR = 4.0
+PIN_SPREAD = 1e-11
+
+
+def _oracle_spread(X, Th, Ph, s, p, ref, seeds=(0, 1)):
+    """Largest relative change of the oracle's step (its ranks replayed) when
+    every Gram matrix is moved by a seeded symmetric perturbation of one unit
+    roundoff of its largest entry: the backward error any backward-stable
+    FP64 eigensolver leaves."""
+    worst = 0.0
+    ranks = (ref[0].shape[1], ref[2].shape[0])
+    for sd in seeds:
+        rng = np.random.default_rng(1000 + sd)
+
+        def pert(G):
+            E = rng.uniform(-1.0, 1.0, G.shape)
+            return G + rounding.U * np.abs(G).max() * 0.5 * (E + E.T)
+        b, _, _ = tt.step(X, Th, Ph, s.T0, s, p["tol"], p["rmax"], ranks=ranks, perturb=pert)
+        worst = max(worst, metrics.rel_diff(b, ref))
+    return worst
 
 
 def _log(*a):
@@ -102,3 +128,57 @@ def test_thick3d_mixed_vs_oracle(oracle_run):
         sr.step(NSTEPS)
         assert _compare(p, sr, oracle_run, 1e-5, 1e-5, "fp32-mixed replayed ranks") == NSTEPS
         sr.close()
+
+
+def test_thick3d_single_steps_in_capped_regime():
+    """Single steps well inside the capped regime: the library runs the
+    workload to steps 20 and 100 (bond-1 rank at the cap 128, concatenated
+    rank 897); from each of those states (its cores and temperature) the
+    oracle and a fresh library context take one step.  Ranks identical (or,
+    when the oracle's decision lies within MARGIN of its threshold, the
+    oracle's ranks replayed) and temperature within 1e-10 relative.  The
+    state is tagged as the smaller cases' single steps are: pinned (bar
+    1e-10) when the oracle's own spread under one-ulp Gram perturbations is
+    below 1e-11, else unpinned with a bar of SPREAD_FACTOR times that spread
+    (at the cap the cut falls inside the spectrum, where the gap between the
+    kept and dropped singular values, not the tolerance, sets the spread)."""
+    from paper_2503_18056_amd import TT_RANK_REPLAY, TTState
+    p = wl.c4(steps=100)
+    run = TTState(p, device=0, max_steps=100)
+    done = 0
+    for at in (20, 100):
+        run.step(at - done)
+        done = at
+        X, Th, Ph = run.cores()
+        T = run.tt_get_temperature()
+        q = dict(p, X0=X, Th0=Th, Ph0=Ph, T0=T, steps=1)
+        infos = []
+        t0 = time.time()
+        (Xo, To, Po), To_T, hist = tt.run(Setup(q), 1, callback=lambda m, c, T_, i: infos.append(i))
+        _log(f"  oracle step {at + 1} from the library's state (ranks {X.shape[1]},{Ph.shape[0]}): "
+             f"{time.time() - t0:.1f}s")
+        one = TTState(q, device=0, max_steps=1)
+        one.step(1)
+        rg, ro = one.ranks(), tuple(hist[0])
+        note = ""
+        if rg != ro:
+            margin = min(b.get("margin", np.inf) for b in infos[0]["round"][-1])
+            assert margin < MARGIN, (at + 1, rg, ro, margin)
+            one.close()
+            one = TTState(q, device=0, max_steps=1, rank_mode=TT_RANK_REPLAY)
+            one.tt_set_rank_schedule([ro])
+            one.step(1)
+            note = f" (gpu ranks {rg}; the oracle's {ro} replayed, its margin {margin:.1e})"
+        err = metrics.rel_diff(one.cores(), (Xo, To, Po))
+        terr = float(np.max(np.abs(one.tt_get_temperature() - To_T)) / np.max(np.abs(To_T)))
+        one.close()
+        spread = _oracle_spread(X, Th, Ph, Setup(q), q, (Xo, To, Po))
+        if spread < PIN_SPREAD:
+            tag, bar = "pinned", 1e-10
+        else:
+            tag, bar = "unpinned (eigensolver floor)", max(1e-10, SPREAD_FACTOR * spread)
+        _log(f"  C4 single step {at + 1}: ranks {ro}, err={err:.2e} Terr={terr:.2e} [{tag}; oracle "
+             f"spread {spread:.2e}, bar {bar:.1e}]{note}")
+        assert err < bar
+        assert terr < 1e-10
+    run.close()
