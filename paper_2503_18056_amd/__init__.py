@@ -256,7 +256,7 @@ def _autograd_function():
         ``state`` must be a TTState created with ckpt_every > 0 (FP64, frozen
         material) and max_steps >= nsteps.  Forward installs kappa, resets the
         cores to ``cores`` (default: the workload's initial cores), steps and
-        evaluates the loss from the library's energy density; backward calls
+        takes the loss from the library (tt_detector_loss); backward calls
         tt_grad with the incoming loss cotangent.
         """
 
@@ -266,11 +266,10 @@ def _autograd_function():
             X0, Th0, Ph0 = cores if cores is not None else (state.p["X0"], state.p["Th0"], state.p["Ph0"])
             state.tt_set_cores(X0, Th0, Ph0)
             state.tt_step(int(nsteps))
-            E, _, _ = state.tt_energy()
-            w = torch.as_tensor(np.asarray(detector_w, float), device=E.device)
-            state.stream.synchronize()
-            ctx.state, ctx.w = state, np.asarray(detector_w, float)
-            return (torch.dot(w, E) * state.cell_volume()).reshape(())
+            w = np.asarray(detector_w, float)
+            L = state.tt_detector_loss(w)
+            ctx.state, ctx.w = state, w
+            return torch.tensor(L, dtype=torch.float64, device=kappa.device)
 
         @staticmethod
         def backward(ctx, gout):

@@ -658,7 +658,7 @@ __device__ inline DC dc_of(const Work& W, int N) {
 
 // Q = I (both buffers' live blocks) and the torn diagonal, over blocks b of P.
 __device__ void dc_init_job(const EigJob& J, const int* __restrict__ dims, int N, int b, int P) {
-  const int n = dims[J.n_idx];
+  const int n = max(0, dims[J.n_idx]);  // -1: an SVD solved by k_svd_jacobi
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
@@ -713,7 +713,7 @@ __device__ inline void wave_sync() {
 
 // Leaf `leaf` of job J, by the calling wavefront (lane = threadIdx.x % 64).
 __device__ void dc_leaf_wave(const EigJob& J, int* __restrict__ dims, int N, int leaf, LeafLds& L) {
-  const int n = dims[J.n_idx];
+  const int n = max(0, dims[J.n_idx]);
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
@@ -1474,9 +1474,10 @@ __global__ __launch_bounds__(256) void k_dc_fused(EigJobs jobs, int njobs, int* 
   unsigned ord = gen0 * GRID_ORD_SPAN;
   int nq[4] = {0, 0, 0, 0}, nmax = 0;
   for (int q = 0; q < njobs; ++q) {
-    nq[q] = dims[jobs.j[q].n_idx];
+    nq[q] = max(0, dims[jobs.j[q].n_idx]);  // -1: an SVD solved by k_svd_jacobi
     nmax = max(nmax, nq[q]);
   }
+  if (nmax == 0) return;  // nothing to solve (every block sees the same sizes)
   for (int q = 0; q < njobs; ++q) dc_init_job(jobs.j[q], dims, N, b, P);
   grid_barrier(gs.flag, ++ord, P, &s_abort, dims);
   int cnt[4] = {0, 0, 0, 0}, tot = 0;
@@ -1708,6 +1709,179 @@ __global__ __launch_bounds__(256) void k_svd_load(const double* __restrict__ M, 
   }
 }
 
+// Small SVDs by one-sided Jacobi (Hestenes), in one 512-thread block: when
+// the short side q <= JAC_QMAX and the p x q work matrix B (B = M for side 1,
+// M^T for side 0; p >= q) fits LDS, its columns are orthogonalised by plane
+// rotations, B V = U S, and the right vectors V (the vectors of M's short
+// side) and S come out directly, with no bidiagonalisation and no
+// tridiagonal eigensolve.  The q columns are paired round-robin (q - 1
+// rounds of q / 2 disjoint pairs per sweep); each pair belongs to one row of
+// 16 lanes, whose sums need only the four in-row DPP steps, so the up to 32
+// pairs of a round run side by side on at most eight wavefronts, and a
+// wavefront whose rows all lack a pair skips the round.  (The step is bound
+// by instruction issue: every wave64 VALU instruction holds its SIMD for four
+// cycles, so the work per round is kept on as few wavefronts as the pairs
+// need.)  A pair (i, j) with a = |b_i|^2, b = |b_j|^2, g = b_i . b_j is
+// rotated when g^2 > (p u)^2 a b, by the angle that zeroes g: with d = b - a,
+// t = sign(d) 2 g / (|d| + sqrt(d^2 + 4 g^2)) (the smaller root of
+// t^2 + (d / g) t - 1 = 0), c = 1 / sqrt(1 + t^2), s = c t.  A sweep without
+// a rotation ends the iteration (at most JAC_MAXSW sweeps; more raises the
+// eigensolver flag).  Singular values are the final column norms, sorted
+// descending (index breaks ties); the kept count, the scalings and the sign
+// gauge follow the same rules as the Golub-Kahan path, whose launches then
+// return at once: the Golub-Kahan order dims[J.n_idx] is set to -1 to say so.
+constexpr int JAC_QMAX = 64;
+constexpr int JAC_PQ = 12288;   // doubles of B in LDS (96 KB: q columns of p rows padded to 16), plus V
+constexpr int JAC_PMAX = 512;
+constexpr int JAC_MAXSW = 40;
+constexpr int JAC_T = 512;
+constexpr int JAC_WAVES = JAC_T / 64;
+__device__ inline int jacobi_ld(int p) { return (p + 15) & ~15; }
+__device__ inline bool jacobi_fits(int p, int q) {
+  return q >= 1 && q <= JAC_QMAX && p <= JAC_PMAX && jacobi_ld(p) * q <= JAC_PQ;
+}
+
+// Sum over each row of 16 lanes, returned on every lane of the row (the
+// first four steps of wave_sum).
+__device__ inline double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
+__global__ __launch_bounds__(JAC_T) void k_svd_jacobi(const double* __restrict__ M, int ldm,
+                                                      EigJobs jobs, int* __restrict__ dims,
+                                                      int a_idx, int b_idx, int side_idx) {
+  const EigJob J = jobs.j[0];
+  const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
+  const int p = side ? a : b, q = side ? b : a;
+  if (!jacobi_fits(p, q)) return;  // the Golub-Kahan path
+  __shared__ double Bs[JAC_PQ];
+  __shared__ double Vs[JAC_QMAX * JAC_QMAX];
+  __shared__ double ssig[JAC_QMAX];
+  __shared__ int spos[JAC_QMAX];
+  __shared__ int s_rot[2];
+  __shared__ int s_kept;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rl = lane & 15;              // lane within the row of 16
+  const int k = 4 * wave + (lane >> 4);  // the pair of this row
+  // B column-major (column j at Bs + j ld, rows p .. ld - 1 zero), V = I
+  const int ld = jacobi_ld(p);
+  for (int e = tid; e < ld * q; e += JAC_T) {
+    const int i = e % ld, j = e / ld;
+    Bs[e] = i >= p ? 0.0 : side ? M[(long long)i * ldm + j] : M[(long long)j * ldm + i];
+  }
+  for (int e = tid; e < q * q; e += JAC_T) Vs[e] = (e % q) == (e / q) ? 1.0 : 0.0;
+  if (tid < 2) s_rot[tid] = 0;
+  __syncthreads();
+  const int qe = q + (q & 1), npair = qe / 2, m1 = qe - 1;
+  const int nch = ld / 16;
+  const double tol2 = ((double)p * U64) * ((double)p * U64);
+  int sw = 0;
+  for (; sw < JAC_MAXSW; ++sw) {
+    const int flag = sw & 1;
+    for (int rnd = 0; rnd < m1; ++rnd) {
+      if (4 * wave < npair) {
+        // round-robin: position 0 fixed, the others rotate
+        int xa = k - 1 + rnd, xb = qe - 2 - k + rnd;
+        if (xa >= m1) xa -= m1;
+        if (xb >= m1) xb -= m1;
+        int ci = k == 0 ? 0 : 1 + xa, cj = 1 + xb;
+        if (ci > cj) { const int t = ci; ci = cj; cj = t; }
+        // a row without a pair this round (k >= npair, or the padding
+        // column of an odd q) reads column 0 and never rotates; every load is
+        // in bounds and unconditional (the columns are zero-padded to ld)
+        const bool live = k < npair && cj < q;
+        double* bi = Bs + (size_t)(live ? ci : 0) * ld;
+        double* bj = Bs + (size_t)(live ? cj : 0) * ld;
+        double pa = 0.0, pb = 0.0, pg = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < nch; ++c) {
+          const double xv = bi[rl + 16 * c], yv = bj[rl + 16 * c];
+          pa = fma(xv, xv, pa);
+          pb = fma(yv, yv, pb);
+          pg = fma(xv, yv, pg);
+        }
+        const double aa = row16_sum(pa), bb = row16_sum(pb), g = row16_sum(pg);
+        if (live && g != 0.0 && g * g > tol2 * aa * bb) {
+          const double d = bb - aa, g2 = 2.0 * g;
+          const double t = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(d * d + g2 * g2));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          // the columns are read again from LDS: holding them in registers
+          // costs more instructions than the reads (and spills at p = 512)
+#pragma unroll 8
+          for (int c = 0; c < nch; ++c) {
+            const int i = rl + 16 * c;
+            const double xv = bi[i], yv = bj[i];
+            bi[i] = cs * xv - sn * yv;  // padding rows stay zero
+            bj[i] = sn * xv + cs * yv;
+          }
+          double* vi = Vs + (size_t)ci * q;
+          double* vj = Vs + (size_t)cj * q;
+          for (int r = rl; r < q; r += 16) {
+            const double u = vi[r], w = vj[r];
+            vi[r] = cs * u - sn * w;
+            vj[r] = sn * u + cs * w;
+          }
+          if (rl == 0) s_rot[flag] = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = s_rot[flag];
+    if (tid == 0) s_rot[flag ^ 1] = 0;  // the next sweep's flag
+    __syncthreads();
+    if (!any) break;
+  }
+  if (sw == JAC_MAXSW && tid == 0) atomicOr(&dims[D_FLAG], FLAG_EIG);
+  // singular values: column norms; descending order (index breaks ties)
+  for (int j = wave; j < q; j += JAC_WAVES) {
+    double part = 0.0;
+    for (int i = lane; i < p; i += 64) part = fma(Bs[(size_t)j * ld + i], Bs[(size_t)j * ld + i], part);
+    const double s2 = wave_sum(part);
+    if (lane == 0) ssig[j] = sqrt(s2);
+  }
+  __syncthreads();
+  if (tid < q) {
+    const double v = ssig[tid];
+    if (!(v == v)) atomicOr(&dims[D_FLAG], FLAG_EIG);
+    int pos = 0;
+    for (int kk = 0; kk < q; ++kk) {
+      const double w = ssig[kk];
+      pos += (w > v) || (w == v && kk < tid);
+    }
+    spos[tid] = pos;
+  }
+  __syncthreads();
+  for (int j = tid; j < q; j += JAC_T) J.lam[spos[j]] = ssig[j];
+  for (int e = tid; e < q * q; e += JAC_T) {
+    const int i = e % q, j = e / q;
+    J.V[(size_t)i * J.ldv + spos[j]] = Vs[e];
+  }
+  if (tid == 0) {
+    // the Golub-Kahan path's clip rule at its order 2q: sigma > clip 2q u sigma_1
+    double smax = 0.0;
+    for (int j = 0; j < q; ++j) smax = fmax(smax, ssig[j]);
+    const double thr = fmax(J.clip * (double)(2 * q) * U64 * smax, 0.0);
+    int kk = 0;
+    for (int j = 0; j < q; ++j) kk += ssig[j] > thr;
+    s_kept = kk;
+    dims[J.kept_idx] = kk;
+    dims[J.n_idx] = -1;
+  }
+  __syncthreads();  // J.V and J.lam written by this block
+  const int kept = s_kept;
+  for (int c = tid; c < kept; c += JAC_T) {
+    const double sg = J.lam[c];
+    J.sq[c] = sg;
+    J.isq[c] = 1.0 / sg;
+  }
+  if (tid < 256) gauge_columns(J.V, J.ldv, q, kept);
+}
+
 // Householder bidiagonalisation of the p x q work matrix (p >= q) in one
 // 1024-thread block: left reflectors zero column k below the diagonal (d_k),
 // right reflectors zero row k right of the superdiagonal (e_k).  Only the
@@ -1716,6 +1890,7 @@ __global__ __launch_bounds__(256) void k_svd_load(const double* __restrict__ M, 
 __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ dims, int N,
                                                 int a_idx, int b_idx, int side_idx) {
   const EigJob J = jobs.j[0];
+  if (dims[J.n_idx] < 0) return;  // solved by k_svd_jacobi
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
   if (gebrd_fits(p, q) || p >= GEBRD_GRID_MIN) return;  // k_gebrd_lds or k_gebrd_grid
@@ -1858,6 +2033,7 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
                                                     int a_idx, int b_idx, int side_idx, int pcap,
                                                     int qcap) {
   const EigJob J = jobs.j[0];
+  if (dims[J.n_idx] < 0) return;  // solved by k_svd_jacobi
   const int a = dims[a_idx], bb = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : bb, q = side ? bb : a;
   if (gebrd_fits(p, q) || p < GEBRD_GRID_MIN) return;  // k_gebrd_lds or k_gebrd
@@ -2003,6 +2179,7 @@ __global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M
                                                     EigJobs jobs, int* __restrict__ dims, int N,
                                                     int a_idx, int b_idx, int side_idx) {
   const EigJob J = jobs.j[0];
+  if (dims[J.n_idx] < 0) return;  // solved by k_svd_jacobi
   const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : b, q = side ? b : a;
   if (!gebrd_fits(p, q)) return;
@@ -2133,6 +2310,7 @@ __global__ __launch_bounds__(1024) void k_gebrd_lds(const double* __restrict__ M
 __global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[0];
   const int n = dims[J.n_idx], q = n / 2;
+  if (n < 0) return;  // solved by k_svd_jacobi
   const int par = dc_par(n);
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
@@ -2171,6 +2349,7 @@ __global__ __launch_bounds__(256) void k_svd_back(EigJobs jobs, int* __restrict_
 __global__ __launch_bounds__(256) void k_svd_final(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[0];
   const int n = dims[J.n_idx], q = n / 2;
+  if (n < 0) return;  // solved by k_svd_jacobi
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   __shared__ int s_kept;
@@ -2224,7 +2403,8 @@ int dc_fused_blocks(int N) { return std::min(DCF_MAXP, std::max(8, (N + 3) / 4))
 // the runtime's own figure is used.
 namespace {
 constexpr size_t LDS_CU = 160 * 1024;
-constexpr size_t ST_SYTRD_GRID = 168, ST_DC_FUSED = 42832, ST_ORMTR = 0, ST_GEBRD_GRID = 168;
+constexpr size_t ST_SYTRD_GRID = 168, ST_DC_FUSED = 42832, ST_ORMTR = 0, ST_GEBRD_GRID = 168,
+                 ST_SVD_JACOBI = 131856;
 
 size_t static_lds(const void* fn, size_t table, bool runtime) {
   if (!runtime) return table;
@@ -2261,6 +2441,7 @@ size_t eig_lds_bytes(int N, bool runtime, const char** which) {
 
 size_t svd_lds_bytes(int ncap2, int pcap, bool runtime, const char** which) {
   size_t worst = 0;
+  lds_note(static_lds((const void*)k_svd_jacobi, ST_SVD_JACOBI, runtime), "k_svd_jacobi", worst, which);
   const int qcap = ncap2 / 2;
   if (pcap >= GEBRD_GRID_MIN) {
     const int qc = qcap < pcap ? qcap : pcap;
@@ -2316,6 +2497,7 @@ void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx
   if (lb > 1024) lb = 1024;
   if (lb < 1) lb = 1;
   k_svd_load<<<lb, 256, 0, s>>>(M, ldm, J, dims, a_idx, b_idx, side_idx);
+  k_svd_jacobi<<<1, JAC_T, 0, s>>>(M, ldm, J, dims, a_idx, b_idx, side_idx);
   k_gebrd_lds<<<1, 1024, 0, s>>>(M, ldm, J, dims, N, a_idx, b_idx, side_idx);
   k_gebrd<<<1, 1024, 0, s>>>(J, dims, N, a_idx, b_idx, side_idx);
   if (pcap >= GEBRD_GRID_MIN) {
