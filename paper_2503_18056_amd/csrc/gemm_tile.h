@@ -1,6 +1,6 @@
-// One 64 x 64 tile of an FP64 product C = op(A) op(B) on a 256-thread block:
-// the vector-FMA inner loop shared by the generic GEMM kernel and the
-// divide-and-conquer merge products.  op(A) is m x k, op(B) is k x n; TA / TB
+// One 64 x 64 tile of an FP64 product C = op(A) op(B) on a 256-thread block
+// (FP64 MFMA), shared by the generic GEMM kernel and the divide-and-conquer
+// merge products.  op(A) is m x k, op(B) is k x n; TA / TB
 // select the transposed reads (A[l][i] / B[j][l]).  Thread (ty, tx) =
 // (tid / 16, tid % 16) accumulates rows i0 + ty + 16 r, columns j0 + tx + 16 c.
 #pragma once
@@ -42,11 +42,21 @@ __device__ __forceinline__ void gemm_slab_load(double (&ra)[NL], double (&rb)[NL
   }
 }
 
+typedef double gemm_f64x4 __attribute__((ext_vector_type(4)));
+
 // acc = op(A) op(B) over the tile (i0, j0), with op(A)'s columns scaled by
-// kscale when given.  32-deep K slabs go through LDS (As, Bs: GEMM_GK x 65);
-// the next slab's global loads are issued into registers before the current
-// slab's FMAs, so their latency is covered by the compute.  Every thread of
-// the block must call it (it holds block barriers).
+// kscale when given.  32-deep K slabs go through LDS (As, Bs: GEMM_GK x 65,
+// As[l][i] = op(A)[i0 + i][l0 + l], Bs[l][j] = op(B)[l0 + l][j0 + j]); the
+// next slab's global loads are issued into registers before the current
+// slab's products, so their latency is covered.  The products run on FP64
+// MFMA 16x16x4: wavefront w owns rows 16 w .. 16 w + 15 of the tile, four
+// 16x16 blocks side by side; lane l feeds A[16 w + l % 16][k + l / 16] and
+// B[k + l / 16][16 c + l % 16], and item r of block c's accumulator holds
+// C[16 w + l / 16 + 4 r][16 c + l % 16].  At the end the accumulators go
+// through LDS (rows 0..31 in As, 32..63 in Bs) into the layout the callers
+// read: thread (ty, tx) = (tid / 16, tid % 16) gets rows ty + 16 r, columns
+// tx + 16 c.  Every thread of the block must call it (it holds block
+// barriers).
 template <int TA, int TB>
 __device__ __forceinline__ void gemm_tile_acc(double (&acc)[4][4], const double* A, const double* B,
                                               int lda, int ldb, const double* kscale, int i0, int j0,
@@ -54,10 +64,10 @@ __device__ __forceinline__ void gemm_tile_acc(double (&acc)[4][4], const double*
                                               double (*Bs)[65]) {
   constexpr int GK = GEMM_GK, NL = GK * 64 / 256;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, w = tid >> 6, lr = lane & 15, lk = lane >> 4;
+  gemm_f64x4 c4[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  for (int c = 0; c < 4; ++c) c4[c] = gemm_f64x4{0.0, 0.0, 0.0, 0.0};
   double ra[NL], rb[NL];
   gemm_slab_load<TA, TB, GK, NL>(ra, rb, A, B, lda, ldb, kscale, i0, j0, m, n, k, 0, tid);
   for (int l0 = 0; l0 < k; l0 += GK) {
@@ -72,20 +82,31 @@ __device__ __forceinline__ void gemm_tile_acc(double (&acc)[4][4], const double*
     __syncthreads();
     if (l0 + GK < k)
       gemm_slab_load<TA, TB, GK, NL>(ra, rb, A, B, lda, ldb, kscale, i0, j0, m, n, k, l0 + GK, tid);
-#pragma unroll 4
-    for (int l = 0; l < GK; ++l) {
-      double a[4], b[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[l][ty + 16 * r];
+    for (int kk = 0; kk < GK; kk += 4) {
+      const double a = As[kk + lk][16 * w + lr];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[l][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+      for (int c = 0; c < 4; ++c)
+        c4[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[kk + lk][16 * c + lr], c4[c], 0, 0, 0);
     }
     __syncthreads();
   }
+  // accumulators to the (ty, tx) layout through LDS
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * w + lk + 4 * r;
+      (i < 32 ? As[i] : Bs[i - 32])[16 * c + lr] = c4[c][r];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ty + 16 * r;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = (i < 32 ? As[i] : Bs[i - 32])[tx + 16 * c];
+  }
+  __syncthreads();  // the staging rows are free for the next tile
 }
 
 }  // namespace tt
