@@ -99,6 +99,14 @@ __device__ inline void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Orders one wavefront's LDS accesses (its lanes' writes before their reads),
+// for code that one wavefront runs alone (the leaves, the order-64 reduction).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Deterministic block-wide sum (fixed combination order).
 template <int NT>
 __device__ double block_sum(double v, double* red) {
@@ -401,6 +409,97 @@ constexpr int SYR_GS = 4;                       // slots per skip group
 constexpr int SYR_GROUPS = SYR_SLOTS / SYR_GS;
 static_assert(SYR_SLOTS % SYR_GS == 0, "whole skip groups");
 
+
+// Orders n <= SYW_MAX: the whole reduction on one wavefront, lane i owning
+// row i of the full symmetric matrix held in LDS (row stride SYW_LD), so no
+// step needs a block barrier or a cross-wavefront sum: the Householder
+// vector of column k (one wavefront sum), p = tau A v over the trailing
+// rows (each lane its row against v broadcast from LDS), K = tau p.v / 2
+// (one wavefront sum), w = p - K v, and the rank-2 update of each lane's row
+// (v and w read as one 16-byte broadcast per column).  Reflectors and d, e,
+// tau go to LDS and are written out after the loop, as in k_sytrd_reg.
+constexpr int SYW_MAX = 64;
+constexpr int SYW_LD = SYW_MAX + 1;
+static_assert(SYW_MAX * SYW_LD + SYW_MAX * (SYW_MAX - 1) / 2 + 2 * SYW_MAX <= SYR_BIG,
+              "the one-wavefront layout fits the block's staging array");
+static_assert((SYW_MAX * SYW_LD + SYW_MAX * (SYW_MAX - 1) / 2) % 2 == 0, "(v, w) pairs 16-byte aligned");
+__device__ void sytrd_one_wave(const EigJob& J, int n, int N, const Work& W, double* lds,
+                               double (*sde)[SYR_MAX]) {
+  const int lane = threadIdx.x & 63;
+  double* As = lds;                         // SYW_MAX x SYW_LD
+  double* refl = As + SYW_MAX * SYW_LD;     // packed reflectors
+  double2* svw = reinterpret_cast<double2*>(refl + SYW_MAX * (SYW_MAX - 1) / 2);  // (v_j, w_j)
+  const double* A = J.A;
+  const long long lda = J.lda;
+  // the lower triangle of A, mirrored
+  for (int e = lane; e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    As[i * SYW_LD + j] = j <= i ? A[(long long)i * lda + j] : A[(long long)j * lda + i];
+  }
+  svw[lane] = make_double2(0.0, 0.0);
+  wave_sync();
+  const bool row = lane < n;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int o = k + 1;
+    const double x = row && lane > k ? As[lane * SYW_LD + k] : 0.0;
+    const double alpha = As[o * SYW_LD + k], dkk = As[k * SYW_LD + k];
+    const double sumsq = wave_sum(row && lane > o ? x * x : 0.0);
+    double tau, scal, beta;
+    if (sumsq == 0.0) {
+      tau = 0.0;
+      scal = 0.0;
+      beta = alpha;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    const double v = lane == o ? 1.0 : (row && lane > o ? x * scal : 0.0);
+    if (row && lane >= o) refl[refl_off(k, n) + lane - o] = v;
+    if (lane == 0) {
+      sde[0][k] = dkk;
+      sde[1][k] = beta;
+      sde[2][k] = tau;
+    }
+    if (tau == 0.0) continue;  // uniform: nothing to reduce in this column
+    svw[lane].x = v;
+    wave_sync();
+    double p = 0.0;
+    if (row && lane > k)
+      for (int j = o; j < n; ++j) p = fma(As[lane * SYW_LD + j], svw[j].x, p);
+    p *= tau;
+    const double K = 0.5 * tau * wave_sum(p * v);
+    const double w = p - K * v;
+    svw[lane].y = w;
+    wave_sync();
+    if (row && lane > k)
+      for (int j = o; j < n; ++j) {
+        const double2 vw = svw[j];
+        double* a = As + lane * SYW_LD + j;
+        *a = fma(-v, vw.y, fma(-w, vw.x, *a));
+      }
+    wave_sync();
+  }
+  // the last 2 x 2 block: d[n-2], e[n-2] = A(n-1, n-2), d[n-1]
+  if (lane == 0) {
+    if (n >= 2) {
+      W.d[n - 2] = As[(n - 2) * SYW_LD + n - 2];
+      W.e[n - 2] = As[(n - 1) * SYW_LD + n - 2];
+      W.tau[n - 2] = 0.0;
+    }
+    W.d[n - 1] = As[(n - 1) * SYW_LD + n - 1];
+  }
+  for (int k = lane; k + 2 < n; k += 64) {
+    W.d[k] = sde[0][k];
+    W.e[k] = sde[1][k];
+    W.tau[k] = sde[2][k];
+  }
+  for (int k = 0; k + 2 < n; ++k) {
+    const int off = refl_off(k, n);
+    for (int i = k + 1 + lane; i < n; i += 64) W.H[(long long)k * N + i] = refl[off + i - k - 1];
+  }
+}
+
 __global__ __launch_bounds__(SYR_T) void k_sytrd_reg(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.x];
   const int n = dims[J.n_idx];
@@ -409,7 +508,7 @@ __global__ __launch_bounds__(SYR_T) void k_sytrd_reg(EigJobs jobs, int* __restri
   // (SYR_CH * 64 >= SYR_MAX); entries past n stay zero
   // staged rows during the load, then the reflectors: v_k (rows k+1 .. n-1)
   // packed from refl_off(k), written to H once after the loop
-  __shared__ double big[SYR_BIG];
+  __shared__ __align__(16) double big[SYR_BIG];
   double* const stage = big;
   double* const refl = big;
   __shared__ double sde[3][SYR_MAX];  // d, e, tau of the loop's steps
@@ -424,6 +523,10 @@ __global__ __launch_bounds__(SYR_T) void k_sytrd_reg(EigJobs jobs, int* __restri
   // the wavefront index is uniform: in a scalar register, the per-column
   // conditions below become scalar branches instead of exec masks
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (n <= SYW_MAX) {  // one wavefront; the others leave before any barrier
+    if (wave == 0 && n >= 1) sytrd_one_wave(J, n, N, W, big, sde);
+    return;
+  }
   for (int e = tid; e < 2 * SYR_CH * 64; e += SYR_T) {
     (&sv[0][0])[e] = 0.0;
     (&sp[0][0])[e] = 0.0;
@@ -703,13 +806,6 @@ struct LeafLds {
   int ord[DC_LEAF];
 };
 
-// Orders one wavefront's LDS accesses (its lanes' writes before their reads):
-// the leaves need no more than this, one wavefront each.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Leaf `leaf` of job J, by the calling wavefront (lane = threadIdx.x % 64).
 __device__ void dc_leaf_wave(const EigJob& J, int* __restrict__ dims, int N, int leaf, LeafLds& L) {
