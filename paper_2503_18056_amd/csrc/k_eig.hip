@@ -410,40 +410,130 @@ constexpr int SYR_GROUPS = SYR_SLOTS / SYR_GS;
 static_assert(SYR_SLOTS % SYR_GS == 0, "whole skip groups");
 
 
-// Orders n <= SYW_MAX: the whole reduction on one wavefront, lane i owning
-// row i of the full symmetric matrix held in LDS (row stride SYW_LD), so no
-// step needs a block barrier or a cross-wavefront sum: the Householder
-// vector of column k (one wavefront sum), p = tau A v over the trailing
-// rows (each lane its row against v broadcast from LDS), K = tau p.v / 2
-// (one wavefront sum), w = p - K v, and the rank-2 update of each lane's row
-// (v and w read as one 16-byte broadcast per column).  Reflectors and d, e,
-// tau go to LDS and are written out after the loop, as in k_sytrd_reg.
+// Orders n <= SYW_MAX: the whole reduction on one wavefront, no block
+// barrier and no cross-wavefront sum.  Lane i holds row i of the full
+// symmetric matrix in registers (a[j] = A(i, j), zero outside n x n).  Step
+// k: column k is each lane's a[k] (k is uniform: a scalar branch picks the
+// register), alpha and A(k, k) are read from lanes k + 1 and k, the
+// Householder vector costs one wavefront sum; v goes to LDS, each lane forms
+// p_i = tau sum_j A(i, j) v_j over the trailing columns with v_j read as
+// broadcast pairs, K = tau p.v / 2 is the second wavefront sum, w = p - K v
+// goes to LDS, and each lane applies A(i, j) -= v_i w_j + w_i v_j to its row.
+// Columns are taken in groups of 8; a group wholly left of the trailing block
+// or wholly past n is skipped by a scalar branch, and rows and columns of the
+// finished part see v = w = 0, so no lane needs masking.  Reflectors and d,
+// e, tau go to LDS and are written out after the loop, as in the block path.
 constexpr int SYW_MAX = 64;
-constexpr int SYW_LD = SYW_MAX + 1;
-static_assert(SYW_MAX * SYW_LD + SYW_MAX * (SYW_MAX - 1) / 2 + 2 * SYW_MAX <= SYR_BIG,
-              "the one-wavefront layout fits the block's staging array");
-static_assert((SYW_MAX * SYW_LD + SYW_MAX * (SYW_MAX - 1) / 2) % 2 == 0, "(v, w) pairs 16-byte aligned");
+constexpr int SYW_LD = SYW_MAX + 1;  // LDS row stride of the staged matrix
+static_assert(SYW_MAX * SYW_LD <= SYR_BIG && SYW_MAX * (SYW_MAX - 1) / 2 + 2 * SYW_MAX <= SYR_BIG,
+              "the one-wavefront staging fits the block's LDS array");
+
+__device__ __forceinline__ double reg_pick(const double (&a)[SYW_MAX], int k) {
+  switch (k) {
+    case 0: return a[0];
+    case 1: return a[1];
+    case 2: return a[2];
+    case 3: return a[3];
+    case 4: return a[4];
+    case 5: return a[5];
+    case 6: return a[6];
+    case 7: return a[7];
+    case 8: return a[8];
+    case 9: return a[9];
+    case 10: return a[10];
+    case 11: return a[11];
+    case 12: return a[12];
+    case 13: return a[13];
+    case 14: return a[14];
+    case 15: return a[15];
+    case 16: return a[16];
+    case 17: return a[17];
+    case 18: return a[18];
+    case 19: return a[19];
+    case 20: return a[20];
+    case 21: return a[21];
+    case 22: return a[22];
+    case 23: return a[23];
+    case 24: return a[24];
+    case 25: return a[25];
+    case 26: return a[26];
+    case 27: return a[27];
+    case 28: return a[28];
+    case 29: return a[29];
+    case 30: return a[30];
+    case 31: return a[31];
+    case 32: return a[32];
+    case 33: return a[33];
+    case 34: return a[34];
+    case 35: return a[35];
+    case 36: return a[36];
+    case 37: return a[37];
+    case 38: return a[38];
+    case 39: return a[39];
+    case 40: return a[40];
+    case 41: return a[41];
+    case 42: return a[42];
+    case 43: return a[43];
+    case 44: return a[44];
+    case 45: return a[45];
+    case 46: return a[46];
+    case 47: return a[47];
+    case 48: return a[48];
+    case 49: return a[49];
+    case 50: return a[50];
+    case 51: return a[51];
+    case 52: return a[52];
+    case 53: return a[53];
+    case 54: return a[54];
+    case 55: return a[55];
+    case 56: return a[56];
+    case 57: return a[57];
+    case 58: return a[58];
+    case 59: return a[59];
+    case 60: return a[60];
+    case 61: return a[61];
+    case 62: return a[62];
+    case 63: return a[63];
+  }
+  return 0.0;
+}
+
 __device__ void sytrd_one_wave(const EigJob& J, int n, int N, const Work& W, double* lds,
                                double (*sde)[SYR_MAX]) {
   const int lane = threadIdx.x & 63;
-  double* As = lds;                         // SYW_MAX x SYW_LD
-  double* refl = As + SYW_MAX * SYW_LD;     // packed reflectors
-  double2* svw = reinterpret_cast<double2*>(refl + SYW_MAX * (SYW_MAX - 1) / 2);  // (v_j, w_j)
   const double* A = J.A;
   const long long lda = J.lda;
-  // the lower triangle of A, mirrored
-  for (int e = lane; e < n * n; e += 64) {
-    const int i = e / n, j = e % n;
-    As[i * SYW_LD + j] = j <= i ? A[(long long)i * lda + j] : A[(long long)j * lda + i];
+  // the lower triangle, staged through LDS: coalesced row reads, 8 in flight
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    double t[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int i = i0 + r;
+      t[r] = (i < n && lane <= i) ? A[(long long)i * lda + lane] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int i = i0 + r;
+      if (i < n && lane <= i) lds[i * SYW_LD + lane] = t[r];
+    }
   }
-  svw[lane] = make_double2(0.0, 0.0);
   wave_sync();
-  const bool row = lane < n;
+  double a[SYW_MAX];
+#pragma unroll
+  for (int j = 0; j < SYW_MAX; ++j) {
+    double t = 0.0;
+    if (lane < n && j < n) t = j <= lane ? lds[lane * SYW_LD + j] : lds[j * SYW_LD + lane];
+    a[j] = t;
+  }
+  wave_sync();  // the staging area becomes the reflectors and v, w
+  double* refl = lds;                                        // packed reflectors
+  double* sv = lds + SYW_MAX * (SYW_MAX - 1) / 2;            // v, 16-byte aligned
+  double* sw = sv + SYW_MAX;                                 // w
   for (int k = 0; k + 2 < n; ++k) {
     const int o = k + 1;
-    const double x = row && lane > k ? As[lane * SYW_LD + k] : 0.0;
-    const double alpha = As[o * SYW_LD + k], dkk = As[k * SYW_LD + k];
-    const double sumsq = wave_sum(row && lane > o ? x * x : 0.0);
+    const double x = reg_pick(a, k);  // A(lane, k)
+    const double alpha = lane_d(x, o), dkk = lane_d(x, k);
+    const double sumsq = wave_sum(lane > o && lane < n ? x * x : 0.0);
     double tau, scal, beta;
     if (sumsq == 0.0) {
       tau = 0.0;
@@ -454,49 +544,67 @@ __device__ void sytrd_one_wave(const EigJob& J, int n, int N, const Work& W, dou
       tau = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    const double v = lane == o ? 1.0 : (row && lane > o ? x * scal : 0.0);
-    if (row && lane >= o) refl[refl_off(k, n) + lane - o] = v;
+    const double v = lane == o ? 1.0 : (lane > o && lane < n ? x * scal : 0.0);
+    if (lane >= o && lane < n) refl[refl_off(k, n) + lane - o] = v;
     if (lane == 0) {
       sde[0][k] = dkk;
       sde[1][k] = beta;
       sde[2][k] = tau;
     }
     if (tau == 0.0) continue;  // uniform: nothing to reduce in this column
-    svw[lane].x = v;
+    sv[lane] = v;
     wave_sync();
-    double p = 0.0;
-    if (row && lane > k)
-      for (int j = o; j < n; ++j) p = fma(As[lane * SYW_LD + j], svw[j].x, p);
-    p *= tau;
+    double pa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < SYW_MAX / 8; ++g) {
+      if (8 * g + 7 < o || 8 * g >= n) continue;
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        const double2 vj = *reinterpret_cast<const double2*>(sv + 8 * g + t);
+        pa[t / 2] = fma(a[8 * g + t], vj.x, pa[t / 2]);
+        pa[t / 2] = fma(a[8 * g + t + 1], vj.y, pa[t / 2]);
+      }
+    }
+    const double p = lane > k ? tau * ((pa[0] + pa[1]) + (pa[2] + pa[3])) : 0.0;
     const double K = 0.5 * tau * wave_sum(p * v);
     const double w = p - K * v;
-    svw[lane].y = w;
+    sw[lane] = w;
     wave_sync();
-    if (row && lane > k)
-      for (int j = o; j < n; ++j) {
-        const double2 vw = svw[j];
-        double* a = As + lane * SYW_LD + j;
-        *a = fma(-v, vw.y, fma(-w, vw.x, *a));
+#pragma unroll
+    for (int g = 0; g < SYW_MAX / 8; ++g) {
+      if (8 * g + 7 < o || 8 * g >= n) continue;
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        const double2 vj = *reinterpret_cast<const double2*>(sv + 8 * g + t);
+        const double2 wj = *reinterpret_cast<const double2*>(sw + 8 * g + t);
+        a[8 * g + t] = fma(-v, wj.x, fma(-w, vj.x, a[8 * g + t]));
+        a[8 * g + t + 1] = fma(-v, wj.y, fma(-w, vj.y, a[8 * g + t + 1]));
       }
-    wave_sync();
+    }
+    wave_sync();  // sv, sw are rewritten by the next step
   }
   // the last 2 x 2 block: d[n-2], e[n-2] = A(n-1, n-2), d[n-1]
+  const double xl = n >= 2 ? reg_pick(a, n - 2) : 0.0, yl = reg_pick(a, n - 1);
+  const double dn2 = n >= 2 ? lane_d(xl, n - 2) : 0.0, en2 = n >= 2 ? lane_d(xl, n - 1) : 0.0;
+  const double dn1 = lane_d(yl, n - 1);
   if (lane == 0) {
     if (n >= 2) {
-      W.d[n - 2] = As[(n - 2) * SYW_LD + n - 2];
-      W.e[n - 2] = As[(n - 1) * SYW_LD + n - 2];
+      W.d[n - 2] = dn2;
+      W.e[n - 2] = en2;
       W.tau[n - 2] = 0.0;
     }
-    W.d[n - 1] = As[(n - 1) * SYW_LD + n - 1];
+    W.d[n - 1] = dn1;
   }
   for (int k = lane; k + 2 < n; k += 64) {
     W.d[k] = sde[0][k];
     W.e[k] = sde[1][k];
     W.tau[k] = sde[2][k];
   }
+  // reflector k: rows k + 1 .. n - 1 of H's row k (one lane per row)
+#pragma unroll 8
   for (int k = 0; k + 2 < n; ++k) {
-    const int off = refl_off(k, n);
-    for (int i = k + 1 + lane; i < n; i += 64) W.H[(long long)k * N + i] = refl[off + i - k - 1];
+    const int i = k + 1 + lane;
+    if (i < n) W.H[(long long)k * N + i] = refl[refl_off(k, n) + lane];
   }
 }
 
