@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gemm_tile.h"
 #include "tt_internal.h"
@@ -365,138 +366,79 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
   grid_launch_end(gs, gen0, ordinal != gen0 * GRID_ORD_SPAN);
 }
 
-// The same reduction with the matrix in registers (n <= SYR_MAX), one
-// 512-thread block per matrix.  Wavefront w owns columns j = w + 8 s and
-// lane l holds their rows i = l + 64 c.  A Householder step k:
-//   (A) the owner of column k forms v_k (one wavefront sum for the norm)
-//       from the column it published in LDS at the end of step k - 1, and
-//       publishes v_k;
-//   (B) every wavefront publishes its partial A v over its columns;
-//   (C) each wavefront sums the 8 partials of 24 rows (p = tau A v) and
-//       publishes them and its share of p.v;
-// then each thread applies A -= v w^T + w v^T, w = p - (tau p.v / 2) v, to
-// its entries, and the owner of column k + 1 publishes that column.  Only
-// column slots and row chunks that meet the trailing block (rows and columns
-// > k) are touched, so the work per step falls as (n - k)^2; every
-// per-column condition is on a compile-time slot and a scalar wavefront
-// index, so it is a scalar branch.  v, p and the partial dots are double
-// buffered by the parity of k, so the owner of column k + 1 may publish
-// while slower wavefronts still read step k's.  The matrix is the lower
-// triangle of A: entries below the diagonal come from rows staged in LDS 64
-// at a time, those above from coalesced loads of the lower triangle's
-// columns.  Outputs (d, e, tau, reflectors in H) as k_sytrd_grid.
+// The same reduction with the matrix in registers (n <= SYR_MAX), one block
+// per matrix.  Orders up to SYW_MAX run on one wavefront (sytrd_one_wave);
+// larger ones on SYP_WAVES wavefronts with each row split over two lanes:
+// lane l of wavefront w holds row r = 32 w + l % 32 and, with h = l / 32,
+// the columns of parity h, shifted: before step k, a[c] = A(r, 2 (c + s) + h)
+// with s = floor(k / 2), so column k is a[0] on the lanes of parity k % 2 and
+// column k + 1 is a[k % 2] on the others; the update of an odd step writes
+// A(r, 2 (c + 1 + s) + h) into a[c] (the shift costs nothing), and no
+// register is ever picked by a run-time index.  The two halves of a row are
+// lanes l and l ^ 32 of one wavefront, and the columns still live at step k
+// are spread evenly over both.  A Householder step k, with two block barriers:
+//   the lanes of parity k % 2 publish column k in LDS (zero at rows <= k + 1)
+//   and each wavefront its share of the column norm; (B1)
+//   every wavefront forms tau, beta, scal from the partial norms (summed in
+//   a fixed order) and its rows' v_r; the matrix-vector product over the
+//   lane's columns p_r = tau (A(r, k+1) + scal sum_{j > k+1} A(r, j) x_j)
+//   (x the published column), the two halves combined by a lane exchange;
+//   p and each wavefront's share of p.v to LDS; (B2)
+//   with K = tau p.v / 2 and u_r = p_r - 2 K v_r, each lane applies
+//   A(r, j) -= v_r p_j + u_r v_j = v_r w_j + w_r v_j (w = p - K v) to its
+//   columns, v_j = scal x_j from the published column and column k + 1
+//   (v = 1 there) separately.
+// The published column and p sit at positions relative to s, once at c and
+// once at c + 1, so that the unshifted and the shifted update both read
+// aligned pairs; the last row of each parity also zeroes the positions past
+// its own, which the step two before had filled.  Columns are taken in
+// groups of 8 per lane (16 of the matrix); a group wholly past n is skipped
+// by a scalar branch.  The published arrays and the partial sums are double
+// buffered by the parity of k, so step k + 1 may publish while a slower
+// wavefront still reads step k's.  The matrix is the lower triangle of A:
+// entries above the diagonal come from coalesced loads of its columns, those
+// on and below from rows staged in LDS 64 at a time.
 // The loop issues no global memory access: the reflectors and d, e, tau stay
 // in LDS (the reflectors where the staged rows were) and are written out
 // after it.  A global store in flight holds its data registers until the
 // write is acknowledged, so a wavefront that stored inside the loop would
 // stall there on its next use of them, on every step.  Barriers inside the
 // loop therefore order LDS only (lds_barrier).
-// Eight wavefronts rather than sixteen: most of a step's instructions are
-// per wavefront (masks, addressing, reductions), and at four cycles per
-// wave64 VALU instruction the SIMD's issue rate, not the FMAs, bounds the
-// step; two wavefronts per SIMD may each hold 256 VGPRs.
-constexpr int SYR_WAVES = 8;                    // two per SIMD: up to 256 VGPRs each
-constexpr int SYR_T = 64 * SYR_WAVES;
-constexpr int SYR_SLOTS = SYR_MAX / SYR_WAVES;  // columns per wavefront
-constexpr int SYR_CH = (SYR_MAX + 63) / 64;     // rows per lane
-constexpr int SYR_LD = SYR_MAX + 1;             // LDS row stride of the staged rows
-constexpr int SYR_RPW = SYR_CH * 64 / SYR_WAVES;  // rows of p each wavefront reduces
+constexpr int SYP_C = SYR_MAX / 2;       // columns per lane
+constexpr int SYP_PUB = SYP_C + 8;       // positions of each published array
+constexpr int SYP_WAVES = SYR_MAX / 32;  // 32 rows per wavefront
+constexpr int SYR_T = 64 * SYP_WAVES;
+constexpr int SYR_LD = SYR_MAX + 1;      // LDS row stride of the staged rows
 // LDS of the staged rows, then of the packed reflectors
 constexpr int SYR_BIG = 64 * SYR_LD > SYR_MAX * (SYR_MAX - 1) / 2 ? 64 * SYR_LD : SYR_MAX * (SYR_MAX - 1) / 2;
 // offset of v_k (n - 1 - k entries) in the packed reflector store
 __device__ inline int refl_off(int k, int n) { return k * (n - 1) - k * (k - 1) / 2; }
-constexpr int SYR_GS = 4;                       // slots per skip group
-constexpr int SYR_GROUPS = SYR_SLOTS / SYR_GS;
-static_assert(SYR_SLOTS % SYR_GS == 0, "whole skip groups");
 
 
 // Orders n <= SYW_MAX: the whole reduction on one wavefront, no block
 // barrier and no cross-wavefront sum.  Lane i holds row i of the full
-// symmetric matrix in registers (a[j] = A(i, j), zero outside n x n).  Step
-// k: column k is each lane's a[k] (k is uniform: a scalar branch picks the
-// register), alpha and A(k, k) are read from lanes k + 1 and k, the
-// Householder vector costs one wavefront sum; v goes to LDS, each lane forms
-// p_i = tau sum_j A(i, j) v_j over the trailing columns with v_j read as
-// broadcast pairs, K = tau p.v / 2 is the second wavefront sum, w = p - K v
-// goes to LDS, and each lane applies A(i, j) -= v_i w_j + w_i v_j to its row.
-// Columns are taken in groups of 8; a group wholly left of the trailing block
-// or wholly past n is skipped by a scalar branch, and rows and columns of the
-// finished part see v = w = 0, so no lane needs masking.  Reflectors and d,
-// e, tau go to LDS and are written out after the loop, as in the block path.
+// symmetric matrix in registers, shifted so that at step k a[c] = A(i, k + c)
+// (zero past n): column k is always a[0].  Each step's update writes the
+// updated A(i, k + 1 + c) into a[c], so the shift costs nothing, and no
+// register is ever picked by a run-time index (a tree of scalar branches
+// costs hundreds of cycles per pick).  Step k: alpha and A(k, k) are read
+// from lanes k + 1 and k; the Householder vector costs one wavefront sum;
+// v goes to LDS by position relative to k; each lane forms
+// p_i = tau sum_c A(i, k + c) v_{k+c} with v read as broadcast pairs;
+// K = tau p.v / 2 is the second wavefront sum; w = p - K v goes to LDS; each
+// lane applies A(i, j) -= v_i w_j + w_i v_j to its row while shifting it.
+// v and w are stored twice, at positions c and c + 1, so that both passes
+// read aligned pairs; the lane of row n - 1 also zeroes the position past
+// the end, which the previous step had filled.  Columns are taken in groups
+// of 8; a group wholly past n is skipped by a scalar branch.  Reflectors and
+// d, e, tau go to LDS and are written out after the loop.
 constexpr int SYW_MAX = 64;
 constexpr int SYW_LD = SYW_MAX + 1;  // LDS row stride of the staged matrix
-static_assert(SYW_MAX * SYW_LD <= SYR_BIG && SYW_MAX * (SYW_MAX - 1) / 2 + 2 * SYW_MAX <= SYR_BIG,
+constexpr int SYW_PUB = SYW_MAX + 8; // entries of each published copy of v, w
+static_assert(SYW_MAX * SYW_LD <= SYR_BIG &&
+                  SYW_MAX * (SYW_MAX - 1) / 2 + 3 * SYW_PUB <= SYR_BIG,
               "the one-wavefront staging fits the block's LDS array");
 
-__device__ __forceinline__ double reg_pick(const double (&a)[SYW_MAX], int k) {
-  switch (k) {
-    case 0: return a[0];
-    case 1: return a[1];
-    case 2: return a[2];
-    case 3: return a[3];
-    case 4: return a[4];
-    case 5: return a[5];
-    case 6: return a[6];
-    case 7: return a[7];
-    case 8: return a[8];
-    case 9: return a[9];
-    case 10: return a[10];
-    case 11: return a[11];
-    case 12: return a[12];
-    case 13: return a[13];
-    case 14: return a[14];
-    case 15: return a[15];
-    case 16: return a[16];
-    case 17: return a[17];
-    case 18: return a[18];
-    case 19: return a[19];
-    case 20: return a[20];
-    case 21: return a[21];
-    case 22: return a[22];
-    case 23: return a[23];
-    case 24: return a[24];
-    case 25: return a[25];
-    case 26: return a[26];
-    case 27: return a[27];
-    case 28: return a[28];
-    case 29: return a[29];
-    case 30: return a[30];
-    case 31: return a[31];
-    case 32: return a[32];
-    case 33: return a[33];
-    case 34: return a[34];
-    case 35: return a[35];
-    case 36: return a[36];
-    case 37: return a[37];
-    case 38: return a[38];
-    case 39: return a[39];
-    case 40: return a[40];
-    case 41: return a[41];
-    case 42: return a[42];
-    case 43: return a[43];
-    case 44: return a[44];
-    case 45: return a[45];
-    case 46: return a[46];
-    case 47: return a[47];
-    case 48: return a[48];
-    case 49: return a[49];
-    case 50: return a[50];
-    case 51: return a[51];
-    case 52: return a[52];
-    case 53: return a[53];
-    case 54: return a[54];
-    case 55: return a[55];
-    case 56: return a[56];
-    case 57: return a[57];
-    case 58: return a[58];
-    case 59: return a[59];
-    case 60: return a[60];
-    case 61: return a[61];
-    case 62: return a[62];
-    case 63: return a[63];
-  }
-  return 0.0;
-}
 
 __device__ void sytrd_one_wave(const EigJob& J, int n, int N, const Work& W, double* lds,
                                double (*sde)[SYR_MAX]) {
@@ -526,12 +468,15 @@ __device__ void sytrd_one_wave(const EigJob& J, int n, int N, const Work& W, dou
     a[j] = t;
   }
   wave_sync();  // the staging area becomes the reflectors and v, w
-  double* refl = lds;                                        // packed reflectors
-  double* sv = lds + SYW_MAX * (SYW_MAX - 1) / 2;            // v, 16-byte aligned
-  double* sw = sv + SYW_MAX;                                 // w
+  double* refl = lds;                                // packed reflectors
+  double* sva = lds + SYW_MAX * (SYW_MAX - 1) / 2;   // v_{k+c} at c (16-byte aligned)
+  double* svb = sva + SYW_PUB;                       // v_{k+c} at c + 1
+  double* swb = svb + SYW_PUB;                       // w_{k+c} at c + 1
+  for (int e = lane; e < 3 * SYW_PUB; e += 64) sva[e] = 0.0;
+  wave_sync();
   for (int k = 0; k + 2 < n; ++k) {
-    const int o = k + 1;
-    const double x = reg_pick(a, k);  // A(lane, k)
+    const int o = k + 1, c = lane - k;  // this lane's row, as a position
+    const double x = a[0];              // A(lane, k)
     const double alpha = lane_d(x, o), dkk = lane_d(x, k);
     const double sumsq = wave_sum(lane > o && lane < n ? x * x : 0.0);
     double tau, scal, beta;
@@ -551,16 +496,23 @@ __device__ void sytrd_one_wave(const EigJob& J, int n, int N, const Work& W, dou
       sde[1][k] = beta;
       sde[2][k] = tau;
     }
-    if (tau == 0.0) continue;  // uniform: nothing to reduce in this column
-    sv[lane] = v;
+    if (c >= 0 && lane < n) {
+      sva[c] = v;
+      svb[c + 1] = v;
+    }
+    if (lane == n - 1) {  // the previous step's last entries, one position on
+      sva[c + 1] = 0.0;
+      svb[c + 2] = 0.0;
+      swb[c + 2] = 0.0;
+    }
     wave_sync();
     double pa[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int g = 0; g < SYW_MAX / 8; ++g) {
-      if (8 * g + 7 < o || 8 * g >= n) continue;
+      if (8 * g >= n - k) continue;
 #pragma unroll
       for (int t = 0; t < 8; t += 2) {
-        const double2 vj = *reinterpret_cast<const double2*>(sv + 8 * g + t);
+        const double2 vj = *reinterpret_cast<const double2*>(sva + 8 * g + t);
         pa[t / 2] = fma(a[8 * g + t], vj.x, pa[t / 2]);
         pa[t / 2] = fma(a[8 * g + t + 1], vj.y, pa[t / 2]);
       }
@@ -568,25 +520,28 @@ __device__ void sytrd_one_wave(const EigJob& J, int n, int N, const Work& W, dou
     const double p = lane > k ? tau * ((pa[0] + pa[1]) + (pa[2] + pa[3])) : 0.0;
     const double K = 0.5 * tau * wave_sum(p * v);
     const double w = p - K * v;
-    sw[lane] = w;
+    if (c >= 0 && lane < n) swb[c + 1] = w;
     wave_sync();
+    // a[c] <- A(lane, k + 1 + c) - v w_{k+1+c} - w v_{k+1+c}
 #pragma unroll
     for (int g = 0; g < SYW_MAX / 8; ++g) {
-      if (8 * g + 7 < o || 8 * g >= n) continue;
+      if (8 * g >= n - k) continue;
 #pragma unroll
       for (int t = 0; t < 8; t += 2) {
-        const double2 vj = *reinterpret_cast<const double2*>(sv + 8 * g + t);
-        const double2 wj = *reinterpret_cast<const double2*>(sw + 8 * g + t);
-        a[8 * g + t] = fma(-v, wj.x, fma(-w, vj.x, a[8 * g + t]));
-        a[8 * g + t + 1] = fma(-v, wj.y, fma(-w, vj.y, a[8 * g + t + 1]));
+        const int q = 8 * g + t;
+        const double2 vj = *reinterpret_cast<const double2*>(svb + q + 2);
+        const double2 wj = *reinterpret_cast<const double2*>(swb + q + 2);
+        const double nxt = q + 2 < SYW_MAX ? a[q + 2] : 0.0;
+        a[q] = fma(-v, wj.x, fma(-w, vj.x, a[q + 1]));
+        a[q + 1] = fma(-v, wj.y, fma(-w, vj.y, nxt));
       }
     }
-    wave_sync();  // sv, sw are rewritten by the next step
+    wave_sync();  // v, w are rewritten by the next step
   }
-  // the last 2 x 2 block: d[n-2], e[n-2] = A(n-1, n-2), d[n-1]
-  const double xl = n >= 2 ? reg_pick(a, n - 2) : 0.0, yl = reg_pick(a, n - 1);
-  const double dn2 = n >= 2 ? lane_d(xl, n - 2) : 0.0, en2 = n >= 2 ? lane_d(xl, n - 1) : 0.0;
-  const double dn1 = lane_d(yl, n - 1);
+  // the last 2 x 2 block, at positions 0 and 1: d[n-2], e[n-2] = A(n-1, n-2), d[n-1]
+  const int kl = n >= 2 ? n - 2 : 0;
+  const double dn2 = lane_d(a[0], kl), en2 = lane_d(a[0], kl + 1 < n ? kl + 1 : kl);
+  const double dn1 = lane_d(n >= 2 ? a[1] : a[0], n - 1);
   if (lane == 0) {
     if (n >= 2) {
       W.d[n - 2] = dn2;
@@ -612,216 +567,178 @@ __global__ __launch_bounds__(SYR_T) void k_sytrd_reg(EigJobs jobs, int* __restri
   const EigJob J = jobs.j[blockIdx.x];
   const int n = dims[J.n_idx];
   if (n > SYR_MAX) return;  // k_sytrd_grid
-  // v, p and the published column cover every row a lane addresses
-  // (SYR_CH * 64 >= SYR_MAX); entries past n stay zero
   // staged rows during the load, then the reflectors: v_k (rows k+1 .. n-1)
   // packed from refl_off(k), written to H once after the loop
   __shared__ __align__(16) double big[SYR_BIG];
   double* const stage = big;
   double* const refl = big;
   __shared__ double sde[3][SYR_MAX];  // d, e, tau of the loop's steps
-  __shared__ double sv[2][SYR_CH * 64], sp[2][SYR_CH * 64], scol[SYR_CH * 64];
-  __shared__ double pp[SYR_WAVES][SYR_CH * 64];
-  __shared__ double red[2][SYR_WAVES];
-  __shared__ double s_tau[2];
+  // published column x and p, [parity of k][parity of the row][position]:
+  // A at the row's position, S one further on (read by the shifting update)
+  __shared__ __align__(16) double xA[2][2][SYP_PUB], xS[2][2][SYP_PUB];
+  __shared__ __align__(16) double pA[2][2][SYP_PUB], pS[2][2][SYP_PUB];
+  __shared__ double red[2][SYP_WAVES], red2[2][SYP_WAVES];
+  __shared__ double s_ad[2][2];  // A(k+1, k), A(k, k)
   const double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
-  const int tid = threadIdx.x, lane = tid & 63;
-  // the wavefront index is uniform: in a scalar register, the per-column
-  // conditions below become scalar branches instead of exec masks
+  const int tid = threadIdx.x, l = tid & 63;
+  // the wavefront index is uniform: in a scalar register
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (n <= SYW_MAX) {  // one wavefront; the others leave before any barrier
     if (wave == 0 && n >= 1) sytrd_one_wave(J, n, N, W, big, sde);
     return;
   }
-  for (int e = tid; e < 2 * SYR_CH * 64; e += SYR_T) {
-    (&sv[0][0])[e] = 0.0;
-    (&sp[0][0])[e] = 0.0;
+  const int h = l >> 5, r = 32 * wave + (l & 31);
+  const bool row = r < n;
+  // the last row of this lane's row parity
+  const bool lastp = row && (r == n - 1 || r == n - 2);
+  for (int e = tid; e < 2 * 2 * SYP_PUB; e += SYR_T) {
+    (&xA[0][0][0])[e] = 0.0;
+    (&xS[0][0][0])[e] = 0.0;
+    (&pA[0][0][0])[e] = 0.0;
+    (&pS[0][0][0])[e] = 0.0;
   }
-  double a[SYR_SLOTS][SYR_CH];
-  // above the diagonal (i < j): L(j, i), column i of the lower triangle
+  double a[SYP_C];
+  // above the diagonal (j > r): L(j, r), column r of the lower triangle
 #pragma unroll
-  for (int s = 0; s < SYR_SLOTS; ++s) {
-    const int j = wave + SYR_WAVES * s;
+  for (int c = 0; c < SYP_C; ++c) {
+    const int j = 2 * c + h;
+    a[c] = (row && j < n && j > r) ? A[(long long)j * lda + r] : 0.0;
+  }
+  // on and below the diagonal (j <= r): L(r, j), rows staged 64 at a time
+  for (int r0 = 0; r0 < n; r0 += 64) {
+    __syncthreads();
+    for (int rr = wave; rr < 64 && r0 + rr < n; rr += SYP_WAVES)
+      for (int j = l; j <= r0 + rr; j += 64) stage[rr * SYR_LD + j] = A[(long long)(r0 + rr) * lda + j];
+    __syncthreads();
+    if (row && r >= r0 && r < r0 + 64) {
+      const double* sr = stage + (r - r0) * SYR_LD;
 #pragma unroll
-    for (int c = 0; c < SYR_CH; ++c) {
-      const int i = lane + 64 * c;
-      a[s][c] = (j < n && i < j) ? A[(long long)j * lda + i] : 0.0;
+      for (int c = 0; c < SYP_C; ++c)
+        if (2 * c + h <= r) a[c] = sr[2 * c + h];
     }
   }
-  // on and below the diagonal (i >= j): L(i, j), rows staged 64 at a time
-#pragma unroll
-  for (int c = 0; c < SYR_CH; ++c) {
-    const int r0 = 64 * c;
-    if (r0 < n) {
-      __syncthreads();
-      for (int r = wave; r < 64 && r0 + r < n; r += SYR_WAVES)
-        for (int j = lane; j <= r0 + r; j += 64)
-          stage[r * SYR_LD + j] = A[(long long)(r0 + r) * lda + j];
-      __syncthreads();
-      const int i = r0 + lane;
-#pragma unroll
-      for (int s = 0; s < SYR_SLOTS; ++s) {
-        const int j = wave + SYR_WAVES * s;
-        if (i < n && i >= j) a[s][c] = stage[lane * SYR_LD + j];
-      }
-    }
-  }
-  if (wave == 0)
-#pragma unroll
-    for (int c = 0; c < SYR_CH; ++c) scol[lane + 64 * c] = a[0][c];
   __syncthreads();  // stage is reused for the reflectors
-  for (int k = 0; k + 2 < n; ++k) {
-    const int o = k + 1, buf = k & 1;
-    if (wave == k % SYR_WAVES) {
-      // Householder vector of column k, by its owner (which published it)
-      double x[SYR_CH];
-      double part = 0.0;
+  // step k; SHIFT (k odd) writes the updated A(r, 2 (c + 1 + s) + h) into
+  // a[c], so the row moves down one register at no cost.  Steps run in pairs
+  // (even, odd) so that the register array has one layout at the loop's back
+  // edge.
+  auto step = [&](const int k, auto shift_tag) {
+    constexpr bool SHIFT = decltype(shift_tag)::value;
+    const int o = k + 1, buf = k & 1, hk = k & 1, sh = k >> 1;
+    const int pos = (r >> 1) - sh;  // this row's position in the published arrays
+    // column k: a[0] on the lanes of parity k % 2
+    const double x = a[0];
+    const bool own = row && h == hk;
+    if (own) {
+      const double xv = r > o ? x : 0.0;
+      if (pos >= 0) {
+        xA[buf][r & 1][pos] = xv;
+        xS[buf][r & 1][pos + 1] = xv;
+      }
+      if (lastp) {  // the step two before wrote one position further on
+        xA[buf][r & 1][pos + 1] = 0.0;
+        xS[buf][r & 1][pos + 2] = 0.0;
+      }
+      if (r == o) s_ad[buf][0] = x;
+      if (r == k) s_ad[buf][1] = x;
+    }
+    const double ss = wave_sum(own && r > o ? x * x : 0.0);
+    if (l == 0) red[buf][wave] = ss;
+    lds_barrier();  // (B1)
+    double sumsq = 0.0;
 #pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) {
-        const int i = lane + 64 * c;
-        const double t = scol[i];
-        x[c] = t;
-        if (i > o && i < n) part += t * t;
-      }
-      const double alpha = scol[o], dkk = scol[k];
-      const double sumsq = wave_sum(part);
-      double tau, scal, beta;
-      if (sumsq == 0.0) {
-        tau = 0.0;
-        scal = 0.0;
-        beta = alpha;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
+    for (int w = 0; w < SYP_WAVES; ++w) sumsq += red[buf][w];
+    const double alpha = s_ad[buf][0], dkk = s_ad[buf][1];
+    double tau, scal, beta;
+    if (sumsq == 0.0) {
+      tau = 0.0;
+      scal = 0.0;
+      beta = alpha;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (tid == 0) {
+      sde[0][k] = dkk;
+      sde[1][k] = beta;
+      sde[2][k] = tau;
+    }
+    const double xr = row && pos >= 0 ? xA[buf][r & 1][pos] : 0.0;  // A(r, k) below row k + 1
+    const double vr = r == o ? 1.0 : xr * scal;
+    if (row && h == 0 && r >= o) refl[refl_off(k, n) + r - o] = vr;
+    // p over this lane's columns (both halves: one lane exchange)
+    double pa[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) {
-        const int i = lane + 64 * c;
-        const double v = i == o ? 1.0 : (i > o && i < n ? x[c] * scal : 0.0);
-        sv[buf][i] = v;
-        if (i >= o && i < n) refl[refl_off(k, n) + i - o] = v;
-      }
-      if (lane == 0) {
-        sde[0][k] = dkk;
-        sde[1][k] = beta;
-        sde[2][k] = tau;
-        s_tau[buf] = tau;
+    for (int g = 0; g < SYP_C / 8; ++g) {
+      if (2 * (8 * g + sh) >= n) continue;
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        const double2 xs = *reinterpret_cast<const double2*>(&xA[buf][h][8 * g + t]);
+        pa[t / 2] = fma(a[8 * g + t], xs.x, pa[t / 2]);
+        pa[t / 2] = fma(a[8 * g + t + 1], xs.y, pa[t / 2]);
       }
     }
-    lds_barrier();  // (A)
-    const double tau = s_tau[buf];
-    // o - wave as a scalar: slot s holds column o exactly when 8 s == ow, and
-    // the group of slots 4 g .. 4 g + 3 meets the trailing block when
-    // 32 g + 24 >= ow; rows chunk c meets it when 64 c + 63 >= o
-    const int ow = __builtin_amdgcn_readfirstlane(o - wave);
-    if (tau != 0.0) {
-      // partial A v over this wavefront's columns (v is zero outside the
-      // trailing block, so a group that meets it is taken whole)
-      double pc[SYR_CH];
+    const bool ocol = h == (o & 1);  // lanes holding column k + 1 (at position k % 2)
+    double pp = scal * ((pa[0] + pa[1]) + (pa[2] + pa[3]));
+    if (ocol) pp += SHIFT ? a[1] : a[0];  // A(r, k + 1), v = 1 there
+    const double pr = row && r > k ? tau * (pp + __shfl_xor(pp, 32)) : 0.0;
+    if (row && h == 0 && pos >= 0) {
+      pA[buf][r & 1][pos] = pr;
+      pS[buf][r & 1][pos + 1] = pr;
+    }
+    if (lastp && h == 0) {
+      pA[buf][r & 1][pos + 1] = 0.0;
+      pS[buf][r & 1][pos + 2] = 0.0;
+    }
+    const double kp = wave_sum(h == 0 ? pr * vr : 0.0);
+    if (l == 0) red2[buf][wave] = kp;
+    lds_barrier();  // (B2)
+    double kd = 0.0;
 #pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) pc[c] = 0.0;
+    for (int w = 0; w < SYP_WAVES; ++w) kd += red2[buf][w];
+    const double K = 0.5 * tau * kd;
+    const double ur = pr - 2.0 * K * vr, us = ur * scal;
 #pragma unroll
-      for (int g = 0; g < SYR_GROUPS; ++g) {
-        if (SYR_GS * SYR_WAVES * g + SYR_WAVES * (SYR_GS - 1) < ow) continue;
-        double vj[SYR_GS];
+    for (int g = 0; g < SYP_C / 8; ++g) {
+      if (2 * (8 * g + sh) >= n) continue;  // a group wholly past n holds zeros
 #pragma unroll
-        for (int t = 0; t < SYR_GS; ++t) vj[t] = sv[buf][wave + SYR_WAVES * (SYR_GS * g + t)];
-#pragma unroll
-        for (int c = 0; c < SYR_CH; ++c) {
-          if (64 * c + 63 < o) continue;
-#pragma unroll
-          for (int t = 0; t < SYR_GS; ++t) pc[c] = fma(a[SYR_GS * g + t][c], vj[t], pc[c]);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) pp[wave][lane + 64 * c] = pc[c];
-      lds_barrier();  // (B)
-      {
-        // p = tau A v: wavefront w sums the 8 partials of rows 24 w .. 24 w + 23,
-        // two lanes per row (four partials each, then a pair sum), and
-        // publishes p and its share of p.v
-        const int rl = lane >> 1, g = lane & 1;
-        const int i = SYR_RPW * wave + rl;
-        double q = 0.0;
-        if (rl < SYR_RPW)
-          q = (pp[4 * g][i] + pp[4 * g + 1][i]) + (pp[4 * g + 2][i] + pp[4 * g + 3][i]);
-        q += dpp_d<0xB1>(q);  // quad_perm [1, 0, 3, 2]: the two halves of the row
-        const double pi = (rl < SYR_RPW && i >= o && i < n) ? tau * q : 0.0;
-        if (g == 0 && rl < SYR_RPW) sp[buf][i] = pi;
-        const double dot = wave_sum(g == 0 && rl < SYR_RPW ? pi * sv[buf][i] : 0.0);
-        if (lane == 0) red[buf][wave] = dot;
-      }
-      lds_barrier();  // (C)
-      // A -= v w^T + w v^T on the entries of the groups and chunks that meet
-      // the trailing block (v and w vanish outside it)
-      double vi[SYR_CH], wi[SYR_CH];
-#pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) {
-        vi[c] = sv[buf][lane + 64 * c];
-        wi[c] = sp[buf][lane + 64 * c];
-      }
-      double ptv = 0.0;
-#pragma unroll
-      for (int w = 0; w < SYR_WAVES; ++w) ptv += red[buf][w];
-      const double hc = 0.5 * tau * ptv;
-#pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) wi[c] = fma(-hc, vi[c], wi[c]);
-#pragma unroll
-      for (int g = 0; g < SYR_GROUPS; ++g) {
-        if (SYR_GS * SYR_WAVES * g + SYR_WAVES * (SYR_GS - 1) < ow) continue;
-        double vj[SYR_GS], wj[SYR_GS];
-#pragma unroll
-        for (int t = 0; t < SYR_GS; ++t) {
-          const int j = wave + SYR_WAVES * (SYR_GS * g + t);
-          vj[t] = sv[buf][j];
-          wj[t] = sp[buf][j];
-        }
-#pragma unroll
-        for (int t = 0; t < SYR_GS; ++t) wj[t] = fma(-hc, vj[t], wj[t]);
-#pragma unroll
-        for (int c = 0; c < SYR_CH; ++c) {
-          if (64 * c + 63 < o) continue;
-#pragma unroll
-          for (int t = 0; t < SYR_GS; ++t) {
-            double& x = a[SYR_GS * g + t][c];
-            x = fma(-vi[c], wj[t], fma(-wi[c], vj[t], x));
-          }
+      for (int t = 0; t < 8; t += 2) {
+        const int q = 8 * g + t;
+        if (SHIFT) {  // positions q + 1, q + 2 into q, q + 1
+          const double2 xs = *reinterpret_cast<const double2*>(&xS[buf][h][q + 2]);
+          const double2 ps = *reinterpret_cast<const double2*>(&pS[buf][h][q + 2]);
+          const double nxt = q + 2 < SYP_C ? a[q + 2] : 0.0;
+          a[q] = fma(-vr, ps.x, fma(-us, xs.x, a[q + 1]));
+          a[q + 1] = fma(-vr, ps.y, fma(-us, xs.y, nxt));
+        } else {
+          const double2 xs = *reinterpret_cast<const double2*>(&xA[buf][h][q]);
+          const double2 ps = *reinterpret_cast<const double2*>(&pA[buf][h][q]);
+          a[q] = fma(-vr, ps.x, fma(-us, xs.x, a[q]));
+          a[q + 1] = fma(-vr, ps.y, fma(-us, xs.y, a[q + 1]));
         }
       }
     }
-    // column k + 1, for its owner's next step
-#pragma unroll
-    for (int s = 0; s < SYR_SLOTS; ++s) {
-      if (SYR_WAVES * s != ow) continue;
-#pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) scol[lane + 64 * c] = a[s][c];
-    }
+    if (ocol) a[0] -= ur;  // column k + 1 (v = 1), now at position 0
+  };
+  int k0 = 0;
+  for (; k0 + 3 < n; k0 += 2) {
+    step(k0, std::false_type());
+    step(k0 + 1, std::true_type());
   }
-  // the last 2 x 2 block: d[n-2], e[n-2] = A(n-1, n-2), d[n-1]
-  for (int r = n >= 2 ? n - 2 : 0; r < n; ++r) {
-    if (wave != r % SYR_WAVES) continue;
-    double dl = 0.0, el = 0.0;
-#pragma unroll
-    for (int s = 0; s < SYR_SLOTS; ++s) {
-      if (wave + SYR_WAVES * s != r) continue;
-#pragma unroll
-      for (int c = 0; c < SYR_CH; ++c) {
-        const int i = lane + 64 * c;
-        if (i == r) dl = a[s][c];
-        if (i == r + 1) el = a[s][c];
-      }
+  if (k0 + 2 < n) step(k0, std::false_type());
+  // the last 2 x 2 block: d[n-2] and e[n-2] = A(n-1, n-2) at position 0 on
+  // parity (n - 2) % 2, d[n-1] at position n % 2 on parity (n - 1) % 2
+  {
+    const double y1 = (n & 1) ? a[1] : a[0];
+    if (h == (n & 1)) {
+      if (r == n - 2) W.d[n - 2] = a[0];
+      if (r == n - 1) W.e[n - 2] = a[0];
     }
-    const double dr = wave_sum(dl), er = wave_sum(el);
-    if (lane == 0) {
-      W.d[r] = dr;
-      if (r == n - 2) {
-        W.e[r] = er;
-        W.tau[r] = 0.0;
-      }
-    }
+    if (h == ((n - 1) & 1) && r == n - 1) W.d[n - 1] = y1;
+    if (tid == 0) W.tau[n - 2] = 0.0;
   }
   // the loop's outputs, kept in LDS so that no global store was in flight
   // across its barriers
@@ -831,9 +748,9 @@ __global__ __launch_bounds__(SYR_T) void k_sytrd_reg(EigJobs jobs, int* __restri
     W.e[k] = sde[1][k];
     W.tau[k] = sde[2][k];
   }
-  for (int k = wave; k + 2 < n; k += SYR_WAVES) {
+  for (int k = wave; k + 2 < n; k += SYP_WAVES) {
     const int off = refl_off(k, n);
-    for (int i = k + 1 + lane; i < n; i += 64) W.H[(long long)k * N + i] = refl[off + i - k - 1];
+    for (int i = k + 1 + l; i < n; i += 64) W.H[(long long)k * N + i] = refl[off + i - k - 1];
   }
 }
 
