@@ -36,7 +36,7 @@ FP64_PEAK_TFLOPS = 78.6
 GRAM_ROWS_MAX = 384          # widest concatenated rank the row-slice Gram holds in LDS
 R1CAP = 5 * 64 + 2 + 1       # crossing beams: B r1_cap + 2 inflow terms + emission slot
 GRAM_KERNEL64 = "k_gram_rows<double> (left Gram X_cat^T X_cat, row slices staged in LDS, FP64 MFMA)"
-GRAM_KERNEL32 = "k_gram_rows<float> (sliced exact Gram on FP32 MFMA, 10 slice products)"
+GRAM_KERNEL32 = "k_gram_rows_f32<4> (sliced exact Gram on FP32 MFMA, 10 slice products)"
 ROUNDING_PHASES = ("gram_tall", "gram_reduce", "eig_bond1", "eig_M1", "eig_bond2", "eig_M2",
                    "x_update", "small_gemm")
 FP32_MFMA_PEAK_TFLOPS = 157.3
@@ -342,6 +342,56 @@ def mixed_run(p, ramp, W, K, dt, hist, end64):
     return mixed
 
 
+def slice_sweep(p, nsteps, slices=(1, 2, 3, 4, 5, 6), prof_steps=20):
+    """Slice count of the FP32-mixed Gram (tt_set_gram_slices) against the
+    FP64 library on the same run: for each count, the whole run's steps/s,
+    the rank history against FP64's, the end state's difference from FP64's,
+    and the average Gram launch over ``prof_steps`` profiled steps after it."""
+    import torch
+    from paper_2503_18056_amd import TT_FP32_MIXED, TT_FP64, TTState
+    warm = TTState(p, device=0, max_steps=2, precision=TT_FP32_MIXED)
+    for sl in slices:  # module load and first launch of every instance, untimed
+        warm.tt_set_gram_slices(sl)
+        warm.step(1)
+    warm.close()
+
+    def run(prec, sl=None):
+        st = TTState(p, device=0, max_steps=nsteps + prof_steps, precision=prec)
+        if sl is not None:
+            st.tt_set_gram_slices(sl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(nsteps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        hist, end = st.tt_get_rank_history(), st.cores()
+        st.tt_profile_enable(True, classes=["gram_tall"])
+        st.step(prof_steps)
+        torch.cuda.synchronize()
+        gms, gn = st.tt_profile_read().get("gram_tall", (0.0, 0))
+        st.close()
+        return dt, hist, end, (gms / gn if gn else None)
+
+    dt64, h64, e64, g64 = run(TT_FP64)
+    out = {"workload": f"{p['name']}: the first {nsteps} steps (rank ramp included), then "
+                       f"{prof_steps} steps with the Gram timed",
+           "fp64": {"steps_per_s": nsteps / dt64, "gram_avg_launch_ms": g64,
+                    "ranks_end": list(h64[-1]) if h64 else None},
+           "slices": {}}
+    for sl in slices:
+        progress(f"Gram slice sweep: {sl} slices")
+        dt, h, e, g = run(TT_FP32_MIXED, sl)
+        out["slices"][str(sl)] = {
+            "slice_products": sl * (sl + 1) // 2,
+            "steps_per_s": nsteps / dt,
+            "gram_avg_launch_ms": g,
+            "rank_history_equal_steps": sum(a == b for a, b in zip(h, h64)),
+            "ranks_end": list(h[-1]) if h else None,
+            "rel_diff_vs_fp64_end": tt_rel_diff(e, e64),
+        }
+    return out
+
+
 def rounding_bench(p, reps=100):
     """Rounding throughput at the crossing-beam cap shape: a seeded
     synthetic state (orthonormal X and Phi rows, bond-1 spectrum 10^(-k/8),
@@ -478,6 +528,10 @@ def main():
     ap.add_argument("--thick3d-steps", type=int, default=6,
                     help="timed steps of the thick 3-D workload in each precision (0 skips it)")
     ap.add_argument("--thick3d-warmup", type=int, default=6)
+    ap.add_argument("--no-slice-sweep", action="store_true",
+                    help="skip the FP32-mixed Gram slice-count sweep on the crossing beams")
+    ap.add_argument("--slice-sweep-thick3d", type=int, default=0,
+                    help="also sweep the slice count on the thick 3-D workload for this many steps")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "warmup (a known-size kernel to scale hardware byte counters by)")
@@ -583,6 +637,11 @@ def main():
         "measured_peaks": peaks or None,
         "fp32_mixed": mixed,
     }
+    if not args.no_slice_sweep:
+        out["gram_slice_sweep"] = slice_sweep(wl.c2(steps=RUN_STEPS + 20), RUN_STEPS)
+    if args.slice_sweep_thick3d > 0:
+        out["gram_slice_sweep_thick3d"] = slice_sweep(wl.c4(steps=args.slice_sweep_thick3d + 2),
+                                                      args.slice_sweep_thick3d, prof_steps=2)
     if not args.no_rounding_bench:
         progress("rounding benchmark at (R1, R2) = (322, 62)")
         out["rounding_bench"] = rounding_bench(wl.c2(steps=2))

@@ -228,6 +228,18 @@ tt_status tt_profile_enable(tt_ctx* ctx, int32_t enable);
 tt_status tt_profile_read(tt_ctx* ctx, double* ms, int32_t* count, const char** names,
                           int32_t cap, int32_t* n);
 
+/* Slices of the FP32-mixed Gram (TT_FP32_MIXED only; no effect in TT_FP64).
+ * Each FP32 entry is split on its column's exponent grid into `slices`
+ * 11-bit integer slices and the slice pairs (a, b) with a + b < slices are
+ * multiplied exactly on FP32 MFMA and accumulated in FP64, so the Gram is
+ * exact to about 2^(-11 slices) of each column's largest entry (1 slice: 11
+ * bits, below FP32's own 24; 3 or more cover all 24) at slices (slices + 1)
+ * / 2 MFMA passes.  Default 4.  A speed/accuracy knob beside the paper's
+ * method (its Gram is FP64), kept for measuring that trade-off.  Drops the
+ * captured step graphs and synchronises the context's stream.
+ * Errors: TT_ERR_INVALID_ARG unless 1 <= slices <= 6. */
+tt_status tt_set_gram_slices(tt_ctx* ctx, int32_t slices);
+
 /* Step execution mode.  enable != 0 (the default): tt_step replays the
  * step's launch sequence as a HIP graph, captured on first use once per
  * state buffer (the step alternates two) on a private non-blocking stream

@@ -211,6 +211,10 @@ class TTState:
         kernels one by one; both give the same bits."""
         self._check(self.lib.tt_use_graphs(self.ctx, 1 if on else 0))
 
+    def tt_set_gram_slices(self, slices):
+        """11-bit slices per entry of the FP32-mixed Gram (1 .. 6, default 4)."""
+        self._check(self.lib.tt_set_gram_slices(self.ctx, int(slices)))
+
     def tt_profile_enable(self, on=True, classes=None):
         """Start (on) or stop recording HIP-event timings; ``classes`` (names
         from PROFILE_CLASSES) restricts recording to those regions."""

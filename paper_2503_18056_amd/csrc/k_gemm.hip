@@ -443,31 +443,55 @@ __device__ inline int col_exponent(unsigned bits) {
   return m > 0.0f ? ilogbf(m) + 1 : 0;
 }
 
-// Error-free split of x (|x| < 2^E) into four integer slices of 11 bits:
-// x = 2^E (s0 2^-11 + s1 2^-22 + s2 2^-33 + s3 2^-44) + remainder below
-// 2^(E-45); |s0| <= 2^11, |s1..3| <= 2^10.  Every step is exact in FP32.
-__device__ inline void split4(float x, int E, float s[4]) {
+// Error-free split of x (|x| < 2^E) into S integer slices of 11 bits:
+// x = 2^E (s0 2^-11 + s1 2^-22 + ... + s_{S-1} 2^-11S) + remainder below
+// 2^(E-11S-1); |s0| <= 2^11, |s1..| <= 2^10.  Every step is exact in FP32.
+template <int S>
+__device__ inline void split_slices(float x, int E, float s[S]) {
   float t = ldexpf(x, 11 - E);
-  s[0] = rintf(t);
-  t = (t - s[0]) * 2048.0f;
-  s[1] = rintf(t);
-  t = (t - s[1]) * 2048.0f;
-  s[2] = rintf(t);
-  t = (t - s[2]) * 2048.0f;
-  s[3] = rintf(t);
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    s[q] = rintf(t);
+    t = (t - s[q]) * 2048.0f;
+  }
 }
 
-// Gram G = A^T A of an FP32 matrix on FP32 MFMA, exact to 2^-44 of each
-// column's largest entry (Ozaki-style error-free splitting), for more than
-// 384 columns.  Each entry is split on a per-column exponent grid into 11-bit
-// integer slices; the slice pairs (s, t), counted from 0, with s + t <= 3 are
-// multiplied on MFMA four rows at a time, where every partial sum is an
-// integer of at most 2^24 and so exact in FP32 (pairs sharing a scale
-// 2^-11(s+t) share an accumulator when their bound allows); each exact
-// partial is flushed into FP64.  Blocking, staging and block order as
+// acc += sum over slice pairs (a, b) with a + b = L < S of x_a y_b
+// 2^-11 (L + 2), on FP32 MFMA 16x16x4.  Per level L the pairs (0, L) and
+// (L, 0) share one accumulator and the pairs with both indices >= 1 (at
+// most four for S <= 6) a second: four rows of products of at most 2^21
+// (resp. 2^20) keep every partial an integer below 2^24, exact in FP32.
+// Each level's two partials are added in FP64 and flushed at its scale.
+template <int S>
+__device__ inline void sliced_products(const float* xv, const float* yv, f64x4& acc) {
+  static_assert(S >= 1 && S <= 6, "slice count");
+  const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int L = 0; L < S; ++L) {
+    const f32x4 ga = L == 0 ? mfma16f(xv[0], yv[0], z) : mfma16f(xv[L], yv[0], mfma16f(xv[0], yv[L], z));
+    f32x4 gb = z;
+#pragma unroll
+    for (int a = 1; a < L; ++a) gb = mfma16f(xv[a], yv[L - a], gb);
+    const double sc = L == 0 ? 0x1p-22 : L == 1 ? 0x1p-33 : L == 2 ? 0x1p-44
+                    : L == 3 ? 0x1p-55 : L == 4 ? 0x1p-66 : 0x1p-77;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      acc[r] = fma(L >= 2 ? (double)ga[r] + (double)gb[r] : (double)ga[r], sc, acc[r]);
+  }
+}
+
+// Gram G = A^T A of an FP32 matrix on FP32 MFMA, exact to 2^-11S of each
+// column's largest entry (Ozaki-style error-free splitting; S = 4 slices by
+// default, 1 .. 6 selectable), for more than 384 columns.  Each entry is
+// split on a per-column exponent grid into S 11-bit integer slices; the
+// slice pairs (s, t), counted from 0, with s + t < S are multiplied on MFMA
+// four rows at a time (sliced_products), where every partial sum is an
+// integer of at most 2^24 and so exact in FP32; each exact partial is
+// flushed into FP64.  Blocking, staging and block order as
 // k_gram_wide (128 x 128 tile pairs, 16-row stages through LDS, each wave a
 // 64 x 64 quarter); output in k_gram_wide's partial layout, scaled back by
 // the column exponents, for k_gram_wide_reduce.
+template <int S>
 __global__ __launch_bounds__(256) void k_gram_split_wide(const float* __restrict__ A, int lda,
                                                          int K, int kslice, int slices,
                                                          DimExpr ndim, const int* __restrict__ dims,
@@ -539,39 +563,18 @@ __global__ __launch_bounds__(256) void k_gram_split_wide(const float* __restrict
     const float(*SA)[GW_LD] = sA[buf];
     const float(*SB)[GW_LD] = diag ? sA[buf] : sB[buf];
     for (int kk = 0; kk < GW_KB; kk += 4) {
-      float xs[4][4], ys[4][4];
+      float xs[4][S], ys[4][S];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        split4(SA[kk + kr][a0 + 16 * t + col], ea[t], xs[t]);
-        split4(SB[kk + kr][b0 + 16 * t + col], eb[t], ys[t]);
+        split_slices<S>(SA[kk + kr][a0 + 16 * t + col], ea[t], xs[t]);
+        split_slices<S>(SB[kk + kr][b0 + 16 * t + col], eb[t], ys[t]);
       }
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (p >= np || q >= nq) continue;
-          const float* xv = xs[p];
-          const float* yv = ys[q];
-          const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
-          // scale 2^-22: (0,0)
-          const f32x4 g2 = mfma16f(xv[0], yv[0], z);
-          // 2^-33: (0,1) + (1,0)           <= 8 * 2^21
-          const f32x4 g3 = mfma16f(xv[1], yv[0], mfma16f(xv[0], yv[1], z));
-          // 2^-44: (0,2) + (2,0)           <= 8 * 2^21;  (1,1) <= 4 * 2^20
-          const f32x4 g4a = mfma16f(xv[2], yv[0], mfma16f(xv[0], yv[2], z));
-          const f32x4 g4b = mfma16f(xv[1], yv[1], z);
-          // 2^-55: (0,3) + (3,0)           <= 8 * 2^21;  (1,2) + (2,1) <= 8 * 2^20
-          const f32x4 g5a = mfma16f(xv[3], yv[0], mfma16f(xv[0], yv[3], z));
-          const f32x4 g5b = mfma16f(xv[2], yv[1], mfma16f(xv[1], yv[2], z));
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double v = acc[p][q][r];
-            v = fma((double)g2[r], 0x1p-22, v);
-            v = fma((double)g3[r], 0x1p-33, v);
-            v = fma((double)g4a[r] + (double)g4b[r], 0x1p-44, v);
-            v = fma((double)g5a[r] + (double)g5b[r], 0x1p-55, v);
-            acc[p][q][r] = v;
-          }
+          sliced_products<S>(xs[p], ys[q], acc[p][q]);
         }
     }
     if (st + 1 < nstage) store(buf ^ 1);
@@ -686,8 +689,8 @@ __device__ inline void gr_task(int t, int& ti, int& tj, int T32) {
   tj = a + rem;
 }
 
-template <typename T>
-__global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves_per_eu(GrShape<T>::WAVES / 4, GrShape<T>::WAVES / 4))) void k_gram_rows(const T* __restrict__ A, int lda, int K,
+template <typename T, int S>
+__device__ __forceinline__ void gram_rows_body(const T* __restrict__ A, int lda, int K,
                                                     int rows_per_blk, DimExpr ndim,
                                                     const int* __restrict__ dims,
                                                     const unsigned* __restrict__ colmax,
@@ -776,33 +779,18 @@ __global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves
             if (ok10[q]) acc[q][1][0] = mfma16(x1, y0, acc[q][1][0]);
             if (ok11[q]) acc[q][1][1] = mfma16(x1, y1, acc[q][1][1]);
           } else {
-            const f32x4 z = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-              float xv[4];
-              split4(a == 0 ? x0 : x1, ea[q][a], xv);
+              float xv[S];
+              split_slices<S>(a == 0 ? x0 : x1, ea[q][a], xv);
 #pragma unroll
               for (int b = 0; b < 2; ++b) {
                 if ((a == 0 && b == 1 && !ok01[q]) || (a == 1 && b == 0 && !ok10[q]) ||
                     (a == 1 && b == 1 && !ok11[q]))
                   continue;
-                float yv[4];
-                split4(b == 0 ? y0 : y1, eb[q][b], yv);
-                const f32x4 g2 = mfma16f(xv[0], yv[0], z);
-                const f32x4 g3 = mfma16f(xv[1], yv[0], mfma16f(xv[0], yv[1], z));
-                const f32x4 g4a = mfma16f(xv[2], yv[0], mfma16f(xv[0], yv[2], z));
-                const f32x4 g4b = mfma16f(xv[1], yv[1], z);
-                const f32x4 g5a = mfma16f(xv[3], yv[0], mfma16f(xv[0], yv[3], z));
-                const f32x4 g5b = mfma16f(xv[2], yv[1], mfma16f(xv[1], yv[2], z));
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                  double v = acc[q][a][b][rr];
-                  v = fma((double)g2[rr], 0x1p-22, v);
-                  v = fma((double)g3[rr], 0x1p-33, v);
-                  v = fma((double)g4a[rr] + (double)g4b[rr], 0x1p-44, v);
-                  v = fma((double)g5a[rr] + (double)g5b[rr], 0x1p-55, v);
-                  acc[q][a][b][rr] = v;
-                }
+                float yv[S];
+                split_slices<S>(b == 0 ? y0 : y1, eb[q][b], yv);
+                sliced_products<S>(xv, yv, acc[q][a][b]);
               }
             }
           }
@@ -834,6 +822,26 @@ __global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves
           }
     }
   }
+}
+
+// FP64 form (MFMA 16x16x4 f64).
+template <typename T>
+__global__ __launch_bounds__(GrShape<T>::WAVES * 64) __attribute__((amdgpu_waves_per_eu(GrShape<T>::WAVES / 4, GrShape<T>::WAVES / 4))) void k_gram_rows(const T* __restrict__ A, int lda, int K,
+                                                    int rows_per_blk, DimExpr ndim,
+                                                    const int* __restrict__ dims,
+                                                    const unsigned* __restrict__ colmax,
+                                                    double* __restrict__ partial) {
+  gram_rows_body<T, 1>(A, lda, K, rows_per_blk, ndim, dims, colmax, partial);
+}
+
+// FP32-mixed form: S 11-bit slices per entry (sliced_products).
+template <int S>
+__global__ __launch_bounds__(GrShape<float>::WAVES * 64) __attribute__((amdgpu_waves_per_eu(GrShape<float>::WAVES / 4, GrShape<float>::WAVES / 4))) void k_gram_rows_f32(const float* __restrict__ A, int lda, int K,
+                                                    int rows_per_blk, DimExpr ndim,
+                                                    const int* __restrict__ dims,
+                                                    const unsigned* __restrict__ colmax,
+                                                    double* __restrict__ partial) {
+  gram_rows_body<float, S>(A, lda, K, rows_per_blk, ndim, dims, colmax, partial);
 }
 
 // G[a][b] = G[b][a] = sum over blocks of the partial tasks, in a fixed
@@ -870,18 +878,30 @@ __global__ __launch_bounds__(256) void k_gram_rows_reduce(const double* __restri
   G[(long long)j * ldg + i] = v;
 }
 
+template <int S>
+static void gram_split_launch(const GramPlan& p, const float* A, DimExpr n, const unsigned* colmax,
+                              double* partial, const int* dims, hipStream_t s) {
+  if (p.rows_mode)
+    k_gram_rows_f32<S><<<p.nblk, GrShape<float>::WAVES * 64, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n,
+                                                                        dims, colmax, partial);
+  else
+    k_gram_split_wide<S><<<p.wslices * p.wpairs, 256, 0, s>>>(A, p.lda, p.K, p.wkslice, p.wslices, n,
+                                                              dims, p.wtiles, p.wpairs, colmax, partial);
+}
+
 void gram_split_partial(const GramPlan& p, const float* A, DimExpr n, unsigned* colmax,
-                        double* partial, const int* dims, hipStream_t s) {
+                        double* partial, const int* dims, hipStream_t s, int slices) {
   k_zero_u32<<<(p.ncap + 255) / 256, 256, 0, s>>>(colmax, p.ncap);
   k_colmax<<<dim3((p.ncap + 63) / 64, (p.K + 255) / 256), 256, 0, s>>>(A, p.lda, p.K, n, dims,
                                                                        colmax);
-  if (p.rows_mode) {
-    k_gram_rows<float><<<p.nblk, GrShape<float>::WAVES * 64, 0, s>>>(A, p.lda, p.K, p.rows_per_blk, n, dims, colmax,
-                                               partial);
-    return;
+  switch (slices) {
+    case 1: gram_split_launch<1>(p, A, n, colmax, partial, dims, s); break;
+    case 2: gram_split_launch<2>(p, A, n, colmax, partial, dims, s); break;
+    case 3: gram_split_launch<3>(p, A, n, colmax, partial, dims, s); break;
+    case 5: gram_split_launch<5>(p, A, n, colmax, partial, dims, s); break;
+    case 6: gram_split_launch<6>(p, A, n, colmax, partial, dims, s); break;
+    default: gram_split_launch<4>(p, A, n, colmax, partial, dims, s); break;
   }
-  k_gram_split_wide<<<p.wslices * p.wpairs, 256, 0, s>>>(A, p.lda, p.K, p.wkslice, p.wslices, n,
-                                                         dims, p.wtiles, p.wpairs, colmax, partial);
 }
 
 void gemm_tall_f32(int K, const float* A, int lda, const double* B, int ldb, float* C, int ldc,

@@ -424,7 +424,7 @@ void round_pipeline(tt_ctx* c, const double* xc, int ldxc, int ncap1, double tol
     GramPlan plan = gram_plan(c->ns, ncap1, ldxc);
     {
       Prof p(c, P_GRAM);
-      if (xcf) gram_split_partial(plan, xcf, dimv(D_RC1), c->colmax, c->gpart, c->dims, s);
+      if (xcf) gram_split_partial(plan, xcf, dimv(D_RC1), c->colmax, c->gpart, c->dims, s, c->gram_slices);
       else gram_tall_partial(plan, xc, dimv(D_RC1), c->gpart, c->dims, s);
     }
     Prof p(c, P_GRAMRED);
@@ -1171,6 +1171,15 @@ tt_status tt_profile_read(tt_ctx* c, double* ms, int32_t* count, const char** na
 }
 
 const char* tt_last_error(const tt_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+tt_status tt_set_gram_slices(tt_ctx* c, int32_t slices) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  if (slices < 1 || slices > 6) return fail(c, TT_ERR_INVALID_ARG, "gram slices must be 1 .. 6");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  graphs_drop(c);  // the captured launches name the kernel of the old count
+  c->gram_slices = slices;
+  return TT_OK;
+}
 
 tt_status tt_use_graphs(tt_ctx* c, int32_t enable) {
   if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");

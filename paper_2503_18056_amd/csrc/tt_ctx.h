@@ -114,6 +114,7 @@ struct tt_ctx {
   // cap_st; gafter / gafterf / gsched are the host bookkeeping one replay
   // performs (buffers after the step, schedule entries consumed)
   bool graphs = true;
+  int gram_slices = tt::GRAM_SLICES_DEFAULT;  // 11-bit slices of the FP32-mixed Gram
   hipStream_t cap_st = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   const void* gkey[2] = {nullptr, nullptr};

@@ -119,9 +119,11 @@ void gram_tall_reduce(const GramPlan& p, DimExpr n, const double* partial, doubl
 
 // ---- FP32-mixed form: sliced (error-free) Gram of an FP32 matrix on FP32
 // MFMA into partial tiles (reduce with gram_split_reduce); colmax is scratch
-// of ncap words.
+// of ncap words; slices: 11-bit slices per entry (1 .. 6; others give 4).
+constexpr int GRAM_SLICES_DEFAULT = 4;
 void gram_split_partial(const GramPlan& p, const float* A, DimExpr n, unsigned* colmax,
-                        double* partial, const int* dims, hipStream_t s);
+                        double* partial, const int* dims, hipStream_t s,
+                        int slices = GRAM_SLICES_DEFAULT);
 void gram_split_reduce(const GramPlan& p, DimExpr n, const double* partial, double* G, int ldg,
                        const int* dims, hipStream_t s);
 // C (FP32) = A (FP32) * B (FP64, split hi/lo) on FP32 MFMA.

@@ -65,6 +65,37 @@ def test_mixed_steps_vs_oracle(kw):
     assert terr < 1e-5
 
 
+def test_gram_slices():
+    """tt_set_gram_slices: 4 slices (the default) give the default's bits;
+    every count 1 .. 6 runs; 3 or more (33+ bits, all of FP32's 24) keep the
+    3-step result within the default's bar of the oracle; 1 slice (11 bits)
+    is worse than 4; counts outside 1 .. 6 are rejected."""
+    p = wl.small_random(bc="inflow", seed=3, material=wl.COUPLED)
+    p["tol"] = 1e-6
+    (X, Th, Ph), _, _ = tt.run(Setup(p), 3)
+    base = _mixed(p, max_steps=3)
+    base.step(3)
+    errs = {}
+    for sl in range(1, 7):
+        st = _mixed(p, max_steps=3)
+        st.tt_set_gram_slices(sl)
+        st.step(3)
+        if sl == 4:
+            for a, b in zip(st.cores(), base.cores()):
+                assert np.array_equal(a, b)
+        errs[sl] = metrics.rel_diff(st.cores(), (X, Th, Ph))
+        assert np.isfinite(errs[sl])
+        if sl >= 3:
+            assert errs[sl] < 1e-6, (sl, errs[sl])
+        if sl == 6:
+            for bad in (0, 7):
+                with pytest.raises(Exception):
+                    st.tt_set_gram_slices(bad)
+        st.close()
+    _log("gram slices: 3-step err vs oracle " + ", ".join(f"{k}: {v:.2e}" for k, v in errs.items()))
+    assert errs[1] > errs[4]
+
+
 def test_mixed_round_vs_oracle():
     X, Th, Ph = wl.random_tt(300, 6, 12, 8, 5, 0, decay=0.15)
     p = wl.small_random(nx=20, ny=15, ntheta=6, nphi=12, seed=0)
