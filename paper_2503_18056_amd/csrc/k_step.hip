@@ -30,9 +30,28 @@ __device__ inline double neighbour(const StepGeom& G, const TX* __restrict__ X, 
   return G.bchi[ax] == TT_BC_OUTFLOW ? self : 0.0;
 }
 
+// Column col of row i of the unscaled concatenation X_cat (a transport
+// stencil block or a rank-1 inflow term; col < B r1 + nbc), in FP64.
+template <typename TX>
+__device__ inline double xcat_entry(const StepGeom& G, const TX* __restrict__ X, int ldX,
+                                    const double* __restrict__ bc_e, int i, const int* coord,
+                                    int col, int r1, int nstencil) {
+  if (col >= nstencil) return bc_e[(long long)(col - nstencil) * G.ns + i];
+  const int b = col / r1, a = col - b * r1;
+  const double x0 = (double)X[(long long)i * ldX + a];
+  const int kind = G.bkind[b], ax = G.baxis[b];
+  if (kind == BK_BASE) return x0;
+  if (kind == BK_MINUS) return x0 - neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
+  if (kind == BK_PLUS) return neighbour(G, X, ldX, i, coord, ax, 1, a, x0) - x0;
+  const double xm = neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
+  const double xp = neighbour(G, X, ldX, i, coord, ax, 1, a, x0);
+  return kind == BK_CENTRAL ? 0.5 * (xp - xm) : (xp - 2.0 * x0) + xm;
+}
+
 // Spatial core of the concatenation, a wavefront per cell row.
 // TX / TC: element type of X and X_cat (double, or float in the FP32-mixed
 // form; the arithmetic is FP64 and each entry is rounded once on store).
+// scaled: rows times d_i and the emission column s_i (else 1 and 0).
 template <typename TX, typename TC>
 __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __restrict__ X, int ldX,
                                                     const double* __restrict__ bc_e,
@@ -46,53 +65,37 @@ __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __rest
   const int r1 = dims[D_R1];
   const int R1 = dims[D_RC1];
   const int nstencil = G.B * r1;
-  const int ix = i % G.nx, iy = (i / G.nx) % G.ny, iz = i / (G.nx * G.ny);
-  const int coord[3] = {ix, iy, iz};
+  const int coord[3] = {i % G.nx, (i / G.nx) % G.ny, i / (G.nx * G.ny)};
   const double di = scaled ? d[i] : 1.0;
-  const TX* xi = X + (long long)i * ldX;
   for (int col = lane; col < R1; col += 64) {
-    double v;
-    if (col < nstencil) {
-      const int b = col / r1, a = col - b * r1;
-      const double x0 = (double)xi[a];
-      const int kind = G.bkind[b], ax = G.baxis[b];
-      if (kind == BK_BASE) {
-        v = x0;
-      } else if (kind == BK_MINUS) {
-        v = x0 - neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
-      } else if (kind == BK_PLUS) {
-        v = neighbour(G, X, ldX, i, coord, ax, 1, a, x0) - x0;
-      } else {
-        const double xm = neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
-        const double xp = neighbour(G, X, ldX, i, coord, ax, 1, a, x0);
-        v = kind == BK_CENTRAL ? 0.5 * (xp - xm) : (xp - 2.0 * x0) + xm;
-      }
-      v *= di;
-    } else if (col < nstencil + G.nbc) {
-      v = bc_e[(long long)(col - nstencil) * G.ns + i] * di;
-    } else {
-      v = scaled ? s[i] : 0.0;
-    }
+    const double v = col < nstencil + G.nbc ? xcat_entry(G, X, ldX, bc_e, i, coord, col, r1, nstencil) * di
+                                            : (scaled ? s[i] : 0.0);
     Xc[(long long)i * ldC + col] = (TC)v;
   }
 }
 
-// Scale the transport columns of an unscaled concatenation by d_i and fill
-// the emission column with s_i (coupled material, after the Newton solve).
-template <typename TC>
-__global__ __launch_bounds__(256) void k_scale_xcat(StepGeom G, const double* __restrict__ d,
-                                                    const double* __restrict__ s,
-                                                    TC* __restrict__ Xc, int ldC,
-                                                    const int* __restrict__ dims) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);  // a wavefront per cell row
+// E_i = sum over the transport and inflow columns of the unscaled
+// concatenation of X_cat[i][col] z[col], with the entries formed from X as
+// k_build_xcat forms them (X_cat is neither written nor read): the
+// post-transport energy density before the source coefficients exist, so
+// that X_cat can then be built once with them.  Sum order as k_row_dot.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_xcat_row_dot(StepGeom G, const TX* __restrict__ X, int ldX,
+                                                      const double* __restrict__ bc_e,
+                                                      const double* __restrict__ z,
+                                                      double* __restrict__ E,
+                                                      const int* __restrict__ dims) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= G.ns) return;
   const int lane = threadIdx.x & 63;
-  const int R1 = dims[D_RC1];
-  const int ntr = R1 - G.nem;
-  const double di = d[i];
-  TC* row = Xc + (long long)i * ldC;
-  for (int col = lane; col < ntr; col += 64) row[col] = (TC)((double)row[col] * di);
-  if (G.nem && lane == 0) row[R1 - 1] = (TC)s[i];
+  const int r1 = dims[D_R1];
+  const int nstencil = G.B * r1, ncol = nstencil + G.nbc;
+  const int coord[3] = {i % G.nx, (i / G.nx) % G.ny, i / (G.nx * G.ny)};
+  double acc = 0.0;
+  for (int col = lane; col < ncol; col += 64)
+    acc += xcat_entry(G, X, ldX, bc_e, i, coord, col, r1, nstencil) * z[col];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) E[i] = acc;
 }
 
 // Core conversion between FP64 and FP32 storage (rows x cols, leading dims).
@@ -562,14 +565,6 @@ void launch_build_xcat(const StepGeom& G, const float* X, int ldX, const double*
                        int scaled, hipStream_t st) {
   k_build_xcat<float, float><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims, scaled);
 }
-void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, double* Xc, int ldC,
-                       const int* dims, hipStream_t st) {
-  k_scale_xcat<double><<<(G.ns + 3) / 4, 256, 0, st>>>(G, d, s, Xc, ldC, dims);
-}
-void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, float* Xc, int ldC,
-                       const int* dims, hipStream_t st) {
-  k_scale_xcat<float><<<(G.ns + 3) / 4, 256, 0, st>>>(G, d, s, Xc, ldC, dims);
-}
 void launch_build_phcat(const StepGeom& G, const double* Ph, const double* pfac,
                         const double* bc_p, double* Pc, const int* dims, hipStream_t st) {
   const int tot = G.R2c * G.np;
@@ -614,6 +609,28 @@ void launch_energy(const float* X, int ldX, int ns, const double* Th, int nt, in
                    double* z, DimExpr r1, DimExpr r2, double inv_c, double* E, const int* dims,
                    int rcap1, int rcap2, hipStream_t st) {
   energy_impl(X, ldX, ns, Th, nt, ldb, Ph, np, w, v, pv, z, r1, r2, inv_c, E, dims, rcap1, rcap2, st);
+}
+template <typename TX>
+static void energy_xcat_impl(const StepGeom& G, const TX* X, int ldX, const double* bc_e,
+                             const double* Tc, const double* Pc, const double* w, const double* v,
+                             double* pv, double* z, DimExpr r2, double inv_c, double* E,
+                             const int* dims, hipStream_t st) {
+  const DimExpr ncol = dimv(D_RC1, 1, -G.nem);
+  k_phi_moment<<<(G.R2c + 63) / 64, 64, 0, st>>>(Pc, G.np, v, pv, r2, dims);
+  k_theta_moment<<<(G.R1c + 63) / 64, 64, 0, st>>>(Tc, G.nt, G.R2c, w, pv, z, ncol, r2, inv_c, dims);
+  k_xcat_row_dot<TX><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, z, E, dims);
+}
+void launch_energy_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
+                        const double* Tc, const double* Pc, const double* w, const double* v,
+                        double* pv, double* z, DimExpr r2, double inv_c, double* E,
+                        const int* dims, hipStream_t st) {
+  energy_xcat_impl(G, X, ldX, bc_e, Tc, Pc, w, v, pv, z, r2, inv_c, E, dims, st);
+}
+void launch_energy_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
+                        const double* Tc, const double* Pc, const double* w, const double* v,
+                        double* pv, double* z, DimExpr r2, double inv_c, double* E,
+                        const int* dims, hipStream_t st) {
+  energy_xcat_impl(G, X, ldX, bc_e, Tc, Pc, w, v, pv, z, r2, inv_c, E, dims, st);
 }
 void launch_convert(const double* a, int lda, float* b, int ldb, int rows, int cols, hipStream_t st) {
   k_convert<double, float><<<1024, 256, 0, st>>>(a, lda, b, ldb, rows, cols);

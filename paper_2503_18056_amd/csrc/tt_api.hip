@@ -575,28 +575,27 @@ void step_once(tt_ctx* c) {
       launch_concat_dims(c->G, c->dims, s);
       launch_build_phcat(c->G, c->Ph, c->pfac, c->bc_p, c->Phcat, c->dims, s);
       launch_build_thcat(c->G, c->Th, c->tfac, c->bc_t, c->Thcat, c->dims, s);
-      if (c->mixed)
-        launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims,
-                          dyn ? 0 : 1, s);
-      else
-        launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims,
-                          dyn ? 0 : 1, s);
     }
     if (dyn) {
       Prof p(c, P_MAT);
-      // E* = (1/c) X_tr z over the transport columns (source column excluded)
+      // E* = (1/c) X_tr z over the transport columns (source column
+      // excluded), X_tr formed from X on the fly, so that X_cat is written
+      // once, with the source coefficients
       if (c->mixed)
-        launch_energy(c->Xcatf, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
-                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
-                      c->Estar, c->dims, c->R1c, c->R2c, s);
+        launch_energy_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->Thcat, c->Phcat, c->w, c->v, c->pv,
+                           c->z, dimv(D_RC2), 1.0 / cf.c, c->Estar, c->dims, s);
       else
-        launch_energy(c->Xcat, c->ldC, c->ns, c->Thcat, c->nt, c->R2c, c->Phcat, c->np, c->w,
-                      c->v, c->pv, c->z, dimv(D_RC1, 1, -c->nem), dimv(D_RC2), 1.0 / cf.c,
-                      c->Estar, c->dims, c->R1c, c->R2c, s);
+        launch_energy_xcat(c->G, c->X, c->ldX, c->bc_e, c->Thcat, c->Phcat, c->w, c->v, c->pv,
+                           c->z, dimv(D_RC2), 1.0 / cf.c, c->Estar, c->dims, s);
       launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
                       c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
-      if (c->mixed) launch_scale_xcat(c->G, c->d, c->s, c->Xcatf, c->ldC, c->dims, s);
-      else launch_scale_xcat(c->G, c->d, c->s, c->Xcat, c->ldC, c->dims, s);
+    }
+    {
+      Prof p(c, P_CONCAT);
+      if (c->mixed)
+        launch_build_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->d, c->s, c->Xcatf, c->ldC, c->dims, 1, s);
+      else
+        launch_build_xcat(c->G, c->X, c->ldX, c->bc_e, c->d, c->s, c->Xcat, c->ldC, c->dims, 1, s);
     }
     if (c->mixed) round_pipeline(c, nullptr, c->ldC, c->R1c, cf.tol, cf.rmax, c->Xcatf);
     else round_pipeline(c, c->Xcat, c->ldC, c->R1c, cf.tol, cf.rmax);

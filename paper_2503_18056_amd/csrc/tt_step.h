@@ -41,18 +41,25 @@ struct RankArgs {
 void launch_build_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
                        const double* d, const double* s, double* Xc, int ldC, const int* dims,
                        int scaled, hipStream_t st);
-void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, double* Xc, int ldC,
-                       const int* dims, hipStream_t st);
 // FP32-mixed form: X and X_cat stored in FP32 (FP64 arithmetic inside).
 void launch_build_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
                        const double* d, const double* s, float* Xc, int ldC, const int* dims,
                        int scaled, hipStream_t st);
-void launch_scale_xcat(const StepGeom& G, const double* d, const double* s, float* Xc, int ldC,
-                       const int* dims, hipStream_t st);
 void launch_energy(const float* X, int ldX, int ns, const double* Th, int nt, int ldb,
                    const double* Ph, int np, const double* w, const double* v, double* pv,
                    double* z, DimExpr r1, DimExpr r2, double inv_c, double* E, const int* dims,
                    int rcap1, int rcap2, hipStream_t st);
+// The post-transport energy density E = (1/c) X_cat z of the unscaled
+// concatenation (transport and inflow columns; Tc, Pc its angular cores),
+// with X_cat's entries formed from X on the fly.
+void launch_energy_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
+                        const double* Tc, const double* Pc, const double* w, const double* v,
+                        double* pv, double* z, DimExpr r2, double inv_c, double* E,
+                        const int* dims, hipStream_t st);
+void launch_energy_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
+                        const double* Tc, const double* Pc, const double* w, const double* v,
+                        double* pv, double* z, DimExpr r2, double inv_c, double* E,
+                        const int* dims, hipStream_t st);
 void launch_convert(const double* a, int lda, float* b, int ldb, int rows, int cols, hipStream_t st);
 void launch_convert(const float* a, int lda, double* b, int ldb, int rows, int cols, hipStream_t st);
 void launch_build_phcat(const StepGeom& G, const double* Ph, const double* pfac,
