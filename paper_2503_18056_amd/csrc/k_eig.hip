@@ -1655,14 +1655,34 @@ __device__ inline double keep_threshold(const EigJob& J, const double* w, int n)
 // ---------------------------------------------------------------------------
 // 3. Back-transformation V[:, n-1-j] = H_0 H_1 ... H_{n-3} q_j for the kept
 // eigenvectors q_j of T (columns of the D&C result), a wavefront per vector,
-// the vector in registers (lane l holds rows l + 64 c, c < NCH).  The
-// reflectors are staged through LDS in chunks of ch (one cooperative load
-// per chunk), so the sequential loop over them reads only LDS; a chunk is
-// sized so that two blocks fit one CU.
+// the vector in registers (lane l holds rows l + 64 c, c < NCH; row chunks
+// past n are skipped by a scalar branch).  The reflectors are applied four
+// at a time in compact WY form: G = H_k H_{k+1} H_{k+2} H_{k+3} = I - V T V^T
+// with V = [v_k .. v_{k+3}] and T upper triangular (T_jj = tau_j,
+// T(0:j-1, j) = -tau_j T(0:j-1, 0:j-1) V(:, 0:j-1)^T v_j), so G y = y - V (T
+// (V^T y)): four dot products whose wavefront sums run side by side, a 4 x 4
+// triangular product, one pass of axpys.  The reflectors are staged through
+// LDS in chunks of whole groups (one cooperative load per chunk, every load
+// in flight before the first store; rows zero outside each reflector, up to
+// n rounded to 64), one wavefront forms each group's T there, and the
+// sequential loop over the groups reads only LDS; a chunk is sized so that
+// two blocks fit one CU.
+constexpr int ORM_G = 4;   // reflectors per compact WY group
 constexpr int ORM_CH = 32;
+// reflector doubles staged per chunk (two blocks per CU), and of them per
+// thread; ch * ld stays within it for every capacity up to 1024 (ld <= 1024,
+// ch >= 4 only when ld <= 2400)
+constexpr int ORM_LDS_DBL = 9600;
+constexpr int ORM_PER = (ORM_LDS_DBL + 255) / 256;
+__host__ __device__ inline int ormtr_ld(int N) { return ((N > 0 ? N : 1) + 63) & ~63; }
 __host__ __device__ inline int ormtr_chunk(int N) {
-  const int c = 9600 / (N > 0 ? N : 1);
-  return c < 1 ? 1 : (c > ORM_CH ? ORM_CH : c);
+  int c = ORM_LDS_DBL / ormtr_ld(N);
+  c = c < ORM_G ? ORM_G : (c > ORM_CH ? ORM_CH : c);
+  return c - c % ORM_G;
+}
+__host__ __device__ inline size_t ormtr_lds_doubles(int N) {
+  const int ch = ormtr_chunk(N);
+  return (size_t)ch * ormtr_ld(N) + (size_t)(ch / ORM_G) * 16;
 }
 
 template <int NCH>
@@ -1673,7 +1693,7 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
   const int N2 = next_pow2(N);
-  const int ch = ormtr_chunk(N);
+  const int ch = ormtr_chunk(N), ld = ormtr_ld(N), gpc = ch / ORM_G;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j0 = blockIdx.x * 4, j = j0 + wave;
   if (j0 >= n) return;
@@ -1681,40 +1701,101 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   // eigenvalues ascend, so the block's last vector is its largest
   if (!(D.lam[min(j0 + 3, n - 1)] > thr)) return;
   const bool active = j < n && D.lam[j] > thr;
-  extern __shared__ double hs[];  // ch reflectors of length N, then their tau
-  double* ts = hs + (size_t)ch * N;
+  extern __shared__ double hs[];  // ch reflectors (rows 0 .. ld - 1), then each group's T
+  double* Ts = hs + (size_t)ch * ld;
   double y[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int i = lane + 64 * c;
     y[c] = active && i < n ? (par ? D.Qb : D.Qa)[(size_t)i * N2 + j] : 0.0;
   }
-  for (int k1 = n - 3; k1 >= 0; k1 -= ch) {
-    const int k0 = max(0, k1 - ch + 1);
+  const int nref = n - 2;  // reflectors 0 .. n - 3
+  const int ngrp = nref > 0 ? (nref + ORM_G - 1) / ORM_G : 0;
+  for (int g1 = ngrp - 1; g1 >= 0; g1 -= gpc) {
+    const int g0 = max(0, g1 - gpc + 1), kbase = ORM_G * g0, nr = ORM_G * (g1 - g0 + 1);
+    __syncthreads();  // the previous chunk is no longer read
+    // flat over (reflector, row): every load of the chunk in flight before the
+    // first store
+    const int tot = nr * ld;
+    double t[ORM_PER];
+#pragma unroll
+    for (int u = 0; u < ORM_PER; ++u) {
+      const int e = threadIdx.x + 256 * u, q = e / ld, i = e - q * ld, kk = kbase + q;
+      t[u] = (e < tot && kk < nref && i > kk && i < n) ? W.H[(size_t)kk * N + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < ORM_PER; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < tot) hs[e] = t[u];
+    }
     __syncthreads();
-    for (int kk = k0 + wave; kk <= k1; kk += 4) {
-      const double* src = W.H + (size_t)kk * N;
-      double* dst = hs + (size_t)(kk - k0) * N;
-      for (int i = kk + 1 + lane; i < n; i += 64) dst[i] = src[i];
-      if (lane == 0) ts[kk - k0] = W.tau[kk];
+    for (int gq = wave; gq <= g1 - g0; gq += 4) {
+      const double* v = hs + (size_t)(ORM_G * gq) * ld;
+      const int kb = kbase + ORM_G * gq;
+      double d01 = 0.0, d02 = 0.0, d03 = 0.0, d12 = 0.0, d13 = 0.0, d23 = 0.0;
+      for (int i = kb + 1 + lane; i < n; i += 64) {
+        const double a0 = v[i], a1 = v[ld + i], a2 = v[2 * ld + i], a3 = v[3 * ld + i];
+        d01 = fma(a0, a1, d01);
+        d02 = fma(a0, a2, d02);
+        d03 = fma(a0, a3, d03);
+        d12 = fma(a1, a2, d12);
+        d13 = fma(a1, a3, d13);
+        d23 = fma(a2, a3, d23);
+      }
+      d01 = wave_sum(d01);
+      d02 = wave_sum(d02);
+      d03 = wave_sum(d03);
+      d12 = wave_sum(d12);
+      d13 = wave_sum(d13);
+      d23 = wave_sum(d23);
+      const double t0 = kb < nref ? W.tau[kb] : 0.0, t1 = kb + 1 < nref ? W.tau[kb + 1] : 0.0;
+      const double t2 = kb + 2 < nref ? W.tau[kb + 2] : 0.0, t3 = kb + 3 < nref ? W.tau[kb + 3] : 0.0;
+      const double T01 = -t1 * t0 * d01;
+      const double T02 = -t2 * (t0 * d02 + T01 * d12), T12 = -t2 * t1 * d12;
+      const double T03 = -t3 * ((t0 * d03 + T01 * d13) + T02 * d23);
+      const double T13 = -t3 * (t1 * d13 + T12 * d23), T23 = -t3 * t2 * d23;
+      if (lane < 16) {
+        const int rr = lane >> 2, cc = lane & 3;
+        double tv = 0.0;
+        if (rr == cc) tv = rr == 0 ? t0 : rr == 1 ? t1 : rr == 2 ? t2 : t3;
+        else if (rr < cc)
+          tv = rr == 0 ? (cc == 1 ? T01 : cc == 2 ? T02 : T03) : rr == 1 ? (cc == 2 ? T12 : T13) : T23;
+        Ts[gq * 16 + lane] = tv;
+      }
     }
     __syncthreads();
     if (!active) continue;
-    for (int k = k1; k >= k0; --k) {
-      const double tau = ts[k - k0];
-      if (tau == 0.0) continue;
-      const double* v = hs + (size_t)(k - k0) * N;
-      double part = 0.0;
+    for (int gq = g1 - g0; gq >= 0; --gq) {
+      const double* v = hs + (size_t)(ORM_G * gq) * ld;
+      const int kb = kbase + ORM_G * gq;
+      double vv[ORM_G][NCH];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+        for (int q = 0; q < ORM_G; ++q) vv[q][c] = 0.0;
+        if (64 * c >= n || 64 * c + 63 <= kb) continue;  // no rows of the group here
         const int i = lane + 64 * c;
-        if (64 * c + 63 > k && i > k && i < n) part += v[i] * y[c];
+#pragma unroll
+        for (int q = 0; q < ORM_G; ++q) vv[q][c] = v[(size_t)q * ld + i];
+        s0 = fma(vv[0][c], y[c], s0);
+        s1 = fma(vv[1][c], y[c], s1);
+        s2 = fma(vv[2][c], y[c], s2);
+        s3 = fma(vv[3][c], y[c], s3);
       }
-      const double dot = wave_sum(part) * tau;
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      s3 = wave_sum(s3);
+      const double* T = Ts + gq * 16;
+      const double u0 = ((T[0] * s0 + T[1] * s1) + T[2] * s2) + T[3] * s3;
+      const double u1 = (T[5] * s1 + T[6] * s2) + T[7] * s3;
+      const double u2 = T[10] * s2 + T[11] * s3;
+      const double u3 = T[15] * s3;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
-        const int i = lane + 64 * c;
-        if (64 * c + 63 > k && i > k && i < n) y[c] -= dot * v[i];
+        if (64 * c >= n || 64 * c + 63 <= kb) continue;
+        y[c] -= ((vv[0][c] * u0 + vv[1][c] * u1) + vv[2][c] * u2) + vv[3][c] * u3;
       }
     }
   }
@@ -2555,8 +2636,8 @@ size_t eig_lds_bytes(int N, bool runtime, const char** which) {
     lds_note(static_lds((const void*)k_sytrd_grid, ST_SYTRD_GRID, runtime) + sytrd_grid_lds(N),
              "k_sytrd_grid", worst, which);
   dc_lds(N, runtime, worst, which);
-  lds_note(static_lds((const void*)k_ormtr<16>, ST_ORMTR, runtime) +
-               ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8, "k_ormtr", worst, which);
+  lds_note(static_lds((const void*)k_ormtr<16>, ST_ORMTR, runtime) + ormtr_lds_doubles(N) * 8,
+           "k_ormtr", worst, which);
   return worst;
 }
 
@@ -2599,7 +2680,7 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   dc_solve(J, njobs < 4 ? njobs : 4, N, dims, s);
   {
     const dim3 g((N + 3) / 4, njobs);
-    const size_t lds = ((size_t)ormtr_chunk(N) * N + ormtr_chunk(N)) * 8;
+    const size_t lds = ormtr_lds_doubles(N) * 8;
     if (N <= 192) k_ormtr<3><<<g, 256, lds, s>>>(J, dims, N);
     else if (N <= 384) k_ormtr<6><<<g, 256, lds, s>>>(J, dims, N);
     else if (N <= 640) k_ormtr<10><<<g, 256, lds, s>>>(J, dims, N);
