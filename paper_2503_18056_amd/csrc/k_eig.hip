@@ -1665,14 +1665,14 @@ __device__ inline double keep_threshold(const EigJob& J, const double* w, int n)
 // LDS in chunks of whole groups (one cooperative load per chunk, every load
 // in flight before the first store; rows zero outside each reflector, up to
 // n rounded to 64), one wavefront forms each group's T there, and the
-// sequential loop over the groups reads only LDS; a chunk is sized so that
-// two blocks fit one CU.
+// sequential loop over the groups reads only LDS.
 constexpr int ORM_G = 4;   // reflectors per compact WY group
-constexpr int ORM_CH = 32;
-// reflector doubles staged per chunk (two blocks per CU), and of them per
-// thread; ch * ld stays within it for every capacity up to 1024 (ld <= 1024,
-// ch >= 4 only when ld <= 2400)
-constexpr int ORM_LDS_DBL = 9600;
+constexpr int ORM_CH = 64;
+// reflector doubles staged per chunk, and of them per thread: one block per
+// CU (a launch has one block per four kept vectors, well under the CU
+// count at the orders that matter), so a chunk may take most of the LDS;
+// ch * ld stays within it for every capacity up to 1024 (ch >= 4)
+constexpr int ORM_LDS_DBL = 18432;
 constexpr int ORM_PER = (ORM_LDS_DBL + 255) / 256;
 __host__ __device__ inline int ormtr_ld(int N) { return ((N > 0 ? N : 1) + 63) & ~63; }
 __host__ __device__ inline int ormtr_chunk(int N) {
@@ -1682,7 +1682,7 @@ __host__ __device__ inline int ormtr_chunk(int N) {
 }
 __host__ __device__ inline size_t ormtr_lds_doubles(int N) {
   const int ch = ormtr_chunk(N);
-  return (size_t)ch * ormtr_ld(N) + (size_t)(ch / ORM_G) * 16;
+  return (size_t)ch * ormtr_ld(N) + (size_t)(ch / ORM_G) * 16 + ch;
 }
 
 template <int NCH>
@@ -1701,8 +1701,9 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   // eigenvalues ascend, so the block's last vector is its largest
   if (!(D.lam[min(j0 + 3, n - 1)] > thr)) return;
   const bool active = j < n && D.lam[j] > thr;
-  extern __shared__ double hs[];  // ch reflectors (rows 0 .. ld - 1), then each group's T
+  extern __shared__ double hs[];  // ch reflectors (rows 0 .. ld - 1), each group's T, the taus
   double* Ts = hs + (size_t)ch * ld;
+  double* taus = Ts + (size_t)gpc * 16;
   double y[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
@@ -1723,11 +1724,13 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
       const int e = threadIdx.x + 256 * u, q = e / ld, i = e - q * ld, kk = kbase + q;
       t[u] = (e < tot && kk < nref && i > kk && i < n) ? W.H[(size_t)kk * N + i] : 0.0;
     }
+    const double tv = threadIdx.x < nr && kbase + (int)threadIdx.x < nref ? W.tau[kbase + threadIdx.x] : 0.0;
 #pragma unroll
     for (int u = 0; u < ORM_PER; ++u) {
       const int e = threadIdx.x + 256 * u;
       if (e < tot) hs[e] = t[u];
     }
+    if (threadIdx.x < nr) taus[threadIdx.x] = tv;
     __syncthreads();
     for (int gq = wave; gq <= g1 - g0; gq += 4) {
       const double* v = hs + (size_t)(ORM_G * gq) * ld;
@@ -1748,8 +1751,8 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
       d12 = wave_sum(d12);
       d13 = wave_sum(d13);
       d23 = wave_sum(d23);
-      const double t0 = kb < nref ? W.tau[kb] : 0.0, t1 = kb + 1 < nref ? W.tau[kb + 1] : 0.0;
-      const double t2 = kb + 2 < nref ? W.tau[kb + 2] : 0.0, t3 = kb + 3 < nref ? W.tau[kb + 3] : 0.0;
+      const double t0 = taus[ORM_G * gq], t1 = taus[ORM_G * gq + 1];
+      const double t2 = taus[ORM_G * gq + 2], t3 = taus[ORM_G * gq + 3];
       const double T01 = -t1 * t0 * d01;
       const double T02 = -t2 * (t0 * d02 + T01 * d12), T12 = -t2 * t1 * d12;
       const double T03 = -t3 * ((t0 * d03 + T01 * d13) + T02 * d23);
