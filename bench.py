@@ -55,7 +55,7 @@ def gram_rows_digest():
     s = open(os.path.join(ROOT, "paper_2503_18056_amd", "csrc", "k_gemm.hip")).read()
     a = s.index("// row-slice Gram (k_gram_rows) shape")
     b = s.index("\n", s.index("template <> struct GrShape<float>"))
-    k0 = s.index("template <typename T>\n__global__ __launch_bounds__(GrShape<T>::WAVES * 64)")
+    k0 = s.index("template <typename T, int S>\n__device__ __forceinline__ void gram_rows_body(")
     k1 = s.index("__global__ __launch_bounds__(256) void k_gram_rows_reduce")
     return hashlib.sha256((s[a:b] + s[k0:k1]).encode()).hexdigest()[:16]
 
