@@ -1837,7 +1837,7 @@ __device__ void gauge_columns(double* V, int ldv, int nrow, int ncol) {
 // 4. Descending eigenvalues, kept count, sqrt scalings and sign gauge.  Each
 // block takes 16 columns of the gauge (and recounts the kept eigenvalues from
 // an LDS copy of them); block 0 also writes the count and the scalings.
-constexpr int FINAL_COLS = 16;
+constexpr int FINAL_COLS = 4;  // one column per wavefront: the gauge is latency-bound
 __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
@@ -1845,27 +1845,31 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
   if (c0 >= n && blockIdx.x > 0) return;  // block 0 always writes the count
   Work W = work_of(J, N);
   DC D = dc_of(W, N);
-  __shared__ int s_kept;
+  __shared__ int s_low, s_bad;
   __shared__ double sl[1024];
   const int tid = threadIdx.x;
   const double thr = keep_threshold(J, D.lam, n);
+  if (tid == 0) {
+    s_low = -1;
+    s_bad = 0;
+  }
   for (int c = tid; c < n; c += 256) sl[c] = D.lam[c];
   __syncthreads();
-  if (tid == 0) {
-    int k = 0, bad = 0;
-    for (int j = n - 1; j >= 0; --j) {
-      if (!(sl[j] == sl[j])) bad = 1;
-      if (sl[j] > thr) ++k;
-      else break;
-    }
-    s_kept = k;
-    if (blockIdx.x == 0) {
-      dims[J.kept_idx] = k;
-      if (bad) atomicOr(&dims[D_FLAG], FLAG_EIG);
-    }
+  // ascending eigenvalues: the kept ones are those above the highest index
+  // whose value is not above the threshold (a NaN counts as not above)
+  int low = -1, bad = 0;
+  for (int j = tid; j < n; j += 256) {
+    if (!(sl[j] == sl[j])) bad = 1;
+    if (!(sl[j] > thr)) low = j;
   }
+  if (low >= 0) atomicMax(&s_low, low);
+  if (bad) s_bad = 1;
   __syncthreads();
-  const int kept = s_kept;
+  const int kept = n - 1 - s_low;
+  if (tid == 0 && blockIdx.x == 0) {
+    dims[J.kept_idx] = kept;
+    if (s_bad) atomicOr(&dims[D_FLAG], FLAG_EIG);
+  }
   if (blockIdx.x == 0) {
     for (int c = tid; c < n; c += 256) {
       const double l = sl[n - 1 - c];
