@@ -30,22 +30,44 @@ __device__ inline double neighbour(const StepGeom& G, const TX* __restrict__ X, 
   return G.bchi[ax] == TT_BC_OUTFLOW ? self : 0.0;
 }
 
-// Column col of row i of the unscaled concatenation X_cat (a transport
-// stencil block or a rank-1 inflow term; col < B r1 + nbc), in FP64.
-template <typename TX>
-__device__ inline double xcat_entry(const StepGeom& G, const TX* __restrict__ X, int ldX,
-                                    const double* __restrict__ bc_e, int i, const int* coord,
-                                    int col, int r1, int nstencil) {
-  if (col >= nstencil) return bc_e[(long long)(col - nstencil) * G.ns + i];
-  const int b = col / r1, a = col - b * r1;
+// Row i of the unscaled concatenation X_cat by column a of the state, for
+// every transport block at once: X(i, a) and its neighbours along the axes
+// the blocks use are loaded once, then block b's entry (column b r1 + a) is
+// formed from them: the state row itself (BK_BASE), the one-sided
+// differences (BK_MINUS, BK_PLUS), the central difference (BK_CENTRAL) or
+// the second difference (BK_DIFF) along the block's axis.  f(b, v) receives
+// each entry.
+template <typename TX, typename F>
+__device__ __forceinline__ void xcat_row_blocks(const StepGeom& G, const TX* __restrict__ X, int ldX,
+                                                int i, const int* coord, int a, int axm, F&& f) {
   const double x0 = (double)X[(long long)i * ldX + a];
-  const int kind = G.bkind[b], ax = G.baxis[b];
-  if (kind == BK_BASE) return x0;
-  if (kind == BK_MINUS) return x0 - neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
-  if (kind == BK_PLUS) return neighbour(G, X, ldX, i, coord, ax, 1, a, x0) - x0;
-  const double xm = neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
-  const double xp = neighbour(G, X, ldX, i, coord, ax, 1, a, x0);
-  return kind == BK_CENTRAL ? 0.5 * (xp - xm) : (xp - 2.0 * x0) + xm;
+  double xm[3] = {0.0, 0.0, 0.0}, xp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax)
+    if ((axm >> ax) & 1) {
+      xm[ax] = neighbour(G, X, ldX, i, coord, ax, -1, a, x0);
+      xp[ax] = neighbour(G, X, ldX, i, coord, ax, 1, a, x0);
+    }
+  for (int b = 0; b < G.B; ++b) {
+    const int kind = G.bkind[b], ax = G.baxis[b];
+    const double m = ax == 0 ? xm[0] : ax == 1 ? xm[1] : xm[2];
+    const double p = ax == 0 ? xp[0] : ax == 1 ? xp[1] : xp[2];
+    double v;
+    if (kind == BK_BASE) v = x0;
+    else if (kind == BK_MINUS) v = x0 - m;
+    else if (kind == BK_PLUS) v = p - x0;
+    else if (kind == BK_CENTRAL) v = 0.5 * (p - m);
+    else v = (p - 2.0 * x0) + m;
+    f(b, v);
+  }
+}
+
+// Axes whose neighbours some transport block reads (bit ax).
+__device__ inline int xcat_axes(const StepGeom& G) {
+  int m = 0;
+  for (int b = 0; b < G.B; ++b)
+    if (G.bkind[b] != BK_BASE) m |= 1 << G.baxis[b];
+  return m;
 }
 
 // Spatial core of the concatenation, a wavefront per cell row.
@@ -66,11 +88,15 @@ __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __rest
   const int R1 = dims[D_RC1];
   const int nstencil = G.B * r1;
   const int coord[3] = {i % G.nx, (i / G.nx) % G.ny, i / (G.nx * G.ny)};
+  const int axm = xcat_axes(G);
   const double di = scaled ? d[i] : 1.0;
-  for (int col = lane; col < R1; col += 64) {
-    const double v = col < nstencil + G.nbc ? xcat_entry(G, X, ldX, bc_e, i, coord, col, r1, nstencil) * di
+  TC* out = Xc + (long long)i * ldC;
+  for (int a = lane; a < r1; a += 64)
+    xcat_row_blocks(G, X, ldX, i, coord, a, axm, [&](int b, double v) { out[b * r1 + a] = (TC)(v * di); });
+  for (int col = nstencil + lane; col < R1; col += 64) {
+    const double v = col < nstencil + G.nbc ? bc_e[(long long)(col - nstencil) * G.ns + i] * di
                                             : (scaled ? s[i] : 0.0);
-    Xc[(long long)i * ldC + col] = (TC)v;
+    out[col] = (TC)v;
   }
 }
 
@@ -78,7 +104,7 @@ __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __rest
 // concatenation of X_cat[i][col] z[col], with the entries formed from X as
 // k_build_xcat forms them (X_cat is neither written nor read): the
 // post-transport energy density before the source coefficients exist, so
-// that X_cat can then be built once with them.  Sum order as k_row_dot.
+// that X_cat can then be built once with them.
 template <typename TX>
 __global__ __launch_bounds__(256) void k_xcat_row_dot(StepGeom G, const TX* __restrict__ X, int ldX,
                                                       const double* __restrict__ bc_e,
@@ -89,11 +115,14 @@ __global__ __launch_bounds__(256) void k_xcat_row_dot(StepGeom G, const TX* __re
   if (i >= G.ns) return;
   const int lane = threadIdx.x & 63;
   const int r1 = dims[D_R1];
-  const int nstencil = G.B * r1, ncol = nstencil + G.nbc;
+  const int nstencil = G.B * r1;
   const int coord[3] = {i % G.nx, (i / G.nx) % G.ny, i / (G.nx * G.ny)};
+  const int axm = xcat_axes(G);
   double acc = 0.0;
-  for (int col = lane; col < ncol; col += 64)
-    acc += xcat_entry(G, X, ldX, bc_e, i, coord, col, r1, nstencil) * z[col];
+  for (int a = lane; a < r1; a += 64)
+    xcat_row_blocks(G, X, ldX, i, coord, a, axm, [&](int b, double v) { acc += v * z[b * r1 + a]; });
+  for (int col = nstencil + lane; col < nstencil + G.nbc; col += 64)
+    acc += bc_e[(long long)(col - nstencil) * G.ns + i] * z[col];
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0) E[i] = acc;
 }
