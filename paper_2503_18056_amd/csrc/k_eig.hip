@@ -54,9 +54,15 @@ __host__ __device__ inline int next_pow2(int n) {
 
 // Work area of one job at capacity N, before the grid-barrier words: d, e,
 // tau, w (4 N), reflectors (N x N), then the divide-and-conquer area.
+// d, e, tau, w, H (N x N), then an area that the divide and conquer uses
+// and, before it, the grid reductions' exchange buffers (k_gebrd_grid's
+// double-buffered partials need 2 (N + 128 N + 128) doubles, more than the
+// divide and conquer for small N).
 __host__ __device__ inline size_t eig_work_main(int N) {
   const size_t N2 = next_pow2(N);
-  return 4 * (size_t)N + (size_t)N * N + N2 + 3 * N2 * N2 + 17 * N2 + 64;
+  const size_t dc = 3 * N2 * N2 + 17 * N2 + 64;
+  const size_t grid = 2 * ((size_t)N + 128 * (size_t)N + 128) + 64;
+  return 4 * (size_t)N + (size_t)N * N + N2 + (dc > grid ? dc : grid);
 }
 
 // Lane exchange inside rows of 16 lanes by DPP, on both halves of a double.
@@ -150,6 +156,9 @@ constexpr int SYR_MAX = 160;  // orders reduced in registers by k_sytrd_reg
 // tau[k] the reflector H_k = I - tau_k v v^T (v_{k+1} = 1).
 constexpr int SYTRD_GRID_P = 64;
 constexpr int SYTRD_GRID_T = 256;
+constexpr int SYTRD_GRID_NMAX = 1024;                          // largest order
+constexpr int SYG_M = SYTRD_GRID_NMAX / SYTRD_GRID_T;          // columns per thread
+constexpr int SYG_T = SYTRD_GRID_NMAX / 64;                    // columns per lane
 constexpr unsigned SYTRD_SPIN_MAX = 1u << 24;
 
 struct SytrdGridBufs {
@@ -265,26 +274,40 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
   unsigned ordinal = gen0 * GRID_ORD_SPAN;
   for (int k = 0; k <= n - 2; ++k) {
     // w_{k-1} on indices >= k from the published p_{k-1} and partial dots
-    // (every wave sums the P partials the same way), fused with row k of T_k
-    double hc = 0.0;
-    const double* pp = G.Pv + (size_t)((k - 1) & 1) * N;
-    if (k >= 1) {
-      const double* dp = G.Dv + (size_t)((k - 1) & 1) * SYTRD_GRID_P;
-      hc = 0.5 * s_taup * wave_sum(lane < P ? dp[lane] : 0.0);
+    // (every wave sums the P partials the same way), fused with row k of T_k.
+    // Every load of the step is issued before the first use: one round trip.
+    const int par = (k - 1) & 1;
+    const double* pp = G.Pv + (size_t)par * N;
+    const double* src = k == 0 ? A : G.Rp + (size_t)par * N;
+    const double dpv = (k >= 1 && lane < P) ? G.Dv[(size_t)par * SYTRD_GRID_P + lane] : 0.0;
+    const double ppk = k >= 1 ? pp[k] : 0.0;
+    double ppv[SYG_M], srv[SYG_M];
+#pragma unroll
+    for (int m = 0; m < SYG_M; ++m) {
+      const int j = k + tid + SYTRD_GRID_T * m;
+      ppv[m] = (k >= 1 && j < n) ? pp[j] : 0.0;
+      srv[m] = j < n ? src[j] : 0.0;
     }
+    const double hc = k >= 1 ? 0.5 * s_taup * wave_sum(dpv) : 0.0;
     const double vk0 = svp[k];
-    const double wk0 = k >= 1 ? pp[k] - hc * vk0 : 0.0;
+    const double wk0 = k >= 1 ? ppk - hc * vk0 : 0.0;
     if (k == n - 2) {
-      for (int j = k + tid; j < n; j += SYTRD_GRID_T) swp[j] = pp[j] - hc * svp[j];
+#pragma unroll
+      for (int m = 0; m < SYG_M; ++m) {
+        const int j = k + tid + SYTRD_GRID_T * m;
+        if (j < n) swp[j] = ppv[m] - hc * svp[j];
+      }
       __syncthreads();
     } else {
       // row k of T_k (columns >= k)
-      const double* src = k == 0 ? A : G.Rp + (size_t)((k - 1) & 1) * N;
       double part = 0.0;
-      for (int j = k + tid; j < n; j += SYTRD_GRID_T) {
-        const double wj = k >= 1 ? pp[j] - hc * svp[j] : 0.0;
+#pragma unroll
+      for (int m = 0; m < SYG_M; ++m) {
+        const int j = k + tid + SYTRD_GRID_T * m;
+        if (j >= n) continue;
+        const double wj = k >= 1 ? ppv[m] - hc * svp[j] : 0.0;
         swp[j] = wj;
-        const double r = src[j] - vk0 * wj - wk0 * svp[j];
+        const double r = srv[m] - vk0 * wj - wk0 * svp[j];
         if (j == k) s_d = r;
         sv[j] = r;
         if (j >= k + 2) part += r * r;
@@ -317,26 +340,44 @@ __global__ __launch_bounds__(SYTRD_GRID_T) void k_sytrd_grid(EigJobs jobs, int* 
         if (b == 0) W.H[(long long)k * N + j] = v;
       }
       __syncthreads();
-      // own rows: T_k = T_{k-1} - v w^T - w v^T, and p_k = tau T_k,22 v_k
+      // own rows: T_k = T_{k-1} - v w^T - w v^T, and p_k = tau T_k,22 v_k.
+      // Lane l handles the columns j = k + 1 + l + 64 t of every row it
+      // updates, so it keeps v_{k-1}, w_{k-1} and v_k at those columns in
+      // registers: per element only the row entry moves through LDS.
       double* pk = G.Pv + (size_t)(k & 1) * N;
       double* rpub = G.Rp + (size_t)(k & 1) * N;
       const int i0 = k + 1 + ((b - (k + 1)) % P + P) % P;
+      const int j0 = k + 1 + lane;
+      double cv[SYG_T], cw[SYG_T], cs[SYG_T];
+#pragma unroll
+      for (int t = 0; t < SYG_T; ++t) {
+        const int j = j0 + 64 * t;
+        const bool ok = j < n;
+        cv[t] = ok ? svp[j] : 0.0;
+        cw[t] = ok ? swp[j] : 0.0;
+        cs[t] = ok ? sv[j] : 0.0;
+      }
       double wpart = 0.0;
       for (int i = i0 + wave * P; i < n; i += 4 * P) {
         const double vi = svp[i], wi = swp[i];
         double* r = Lr + (size_t)(i / P) * N;
         const bool publish = i == k + 1;
         double acc = 0.0;
-        for (int j = k + 1 + lane; j < n; j += 64) {
-          const double t = r[j] - vi * swp[j] - wi * svp[j];
-          r[j] = t;
-          if (publish) rpub[j] = t;
-          acc += t * sv[j];
+#pragma unroll
+        for (int t = 0; t < SYG_T; ++t) {
+          if (k + 1 + 64 * t >= n) break;
+          const int j = j0 + 64 * t;
+          if (j < n) {
+            const double x = r[j] - vi * cw[t] - wi * cv[t];
+            r[j] = x;
+            if (publish) rpub[j] = x;
+            acc += x * cs[t];
+          }
         }
         acc = wave_sum(acc);
-        const double p = tau * acc;
-        if (lane == 0) pk[i] = p;
-        wpart += p * sv[i];
+        const double pv = tau * acc;
+        if (lane == 0) pk[i] = pv;
+        wpart += pv * sv[i];
       }
       __syncthreads();
       if (lane == 0) red[wave] = wpart;
@@ -1896,6 +1937,10 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
 
 constexpr int GEBRD_LDS_MAX = 16384;  // p q doubles held in LDS by k_gebrd_lds
 constexpr int GEBRD_GRID_MIN = 384;   // longer side from which k_gebrd_grid takes over
+constexpr int GEBRD_GRID_PMAX = 128;  // blocks of k_gebrd_grid at most
+static_assert(GEBRD_GRID_PMAX <= 128, "eig_work_main sizes the grid partials for 128 blocks");
+constexpr int GBG_M = 4;   // columns per thread in k_gebrd_grid's partial sums (q <= 1024)
+constexpr int GBG_U = 16;  // block partials loaded together
 __device__ inline int gebrd_ld(int q) { return q | 1; }
 __device__ inline bool gebrd_fits(int p, int q) {
   return (long long)p * gebrd_ld(q) <= GEBRD_LDS_MAX && p <= 1024;
@@ -2200,38 +2245,39 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
 }
 
 // The same bidiagonalisation for large matrices (p >= GEBRD_GRID_MIN) on P
-// blocks, each holding the rows i = b (mod P) in LDS (row stride q).  Step k:
-//   A. every block reads column k of the current matrix (published by the
-//      row owners) and forms the left reflector u_k, tau_L, d_k from it
-//      redundantly; each block then publishes its partial of
-//      y = A(k:, k+1:)^T u over its own rows;
-//   -- grid barrier --
-//   B. every block sums the P partials in block order (y = tau_L sum), forms
-//      row k after the left reflector from the published row k and y, and
-//      from it the right reflector v_k, tau_R, e_k; each block applies both
-//      reflectors to its own rows in LDS (A_i -= u_i y, then
-//      A_i -= tau_R (A_i . v) v) and publishes column k+1 of its rows and,
-//      for the owner, row k+1;
-//   -- grid barrier --
+// blocks, each holding the rows i = b (mod P) in LDS (row stride q), with one
+// grid barrier per step.  The left reflector of column k is
+// u = e_k + s_L c, c = A(k+1:, k), and its product with the trailing matrix is
+// y = tau_L (A(k, k+1:) + s_L sum_{i > k} A(i, k) A(i, k+1:)): each block can
+// form its share of that sum, and of |c|^2, from its own rows before the
+// reflector exists.  So before the barrier that opens step k every block
+// publishes those two partials over its own rows i > k, and the owner of row
+// k publishes the row; step k then runs without another barrier:
+//   every block sums the P partials in block order, forms the left reflector
+//   (alpha = A(k, k)), y, row k after it, and from that row the right
+//   reflector v_k, tau_R, e_k, redundantly; it applies both reflectors to its
+//   own rows in LDS (A_i -= s_L A(i, k) y, then A_i -= tau_R (A_i . v) v) and
+//   publishes the partials of step k + 1 (double-buffered by step parity: a
+//   block may write step k + 1's while another still reads step k's).
 // Outputs (W.e[2k] = d_k, W.e[2k+1] = e_k, W.tau, right reflectors in W.H)
 // as k_gebrd.  Launch and barrier as k_sytrd_grid.
 
 struct GebrdGridBufs {
-  double *C, *R, *Y;  // published column (p), rows (2 x q), partials (P x q)
+  double *R, *Y, *S;  // published rows (2 x N), partial sums (2 x P x N), |c|^2 partials (2 x P)
 };
-__device__ __host__ inline GebrdGridBufs gebrd_grid_bufs(double* work, int N, int P) {
+__device__ __host__ inline GebrdGridBufs gebrd_grid_bufs(double* work, int N) {
   const size_t N2 = next_pow2(N);
   double* z = work + 4 * (size_t)N + (size_t)N * N + N2;
   GebrdGridBufs B;
-  B.C = z;
-  B.R = z + 1024;
-  B.Y = B.R + 2 * (size_t)N;
+  B.R = z;
+  B.Y = z + 2 * (size_t)N;
+  B.S = B.Y + 2 * (size_t)GEBRD_GRID_PMAX * N;
   return B;
 }
 // blocks and dynamic LDS for rows up to pcap and columns up to qcap
 inline int gebrd_grid_blocks(int pcap, int qcap) {
   const size_t small = ((size_t)4 * 1024 + 64) * 8;  // vectors and statics
-  return ((size_t)((pcap + 63) / 64) * qcap * 8 + small <= 160 * 1024) ? 64 : 128;
+  return ((size_t)((pcap + 63) / 64) * qcap * 8 + small <= 160 * 1024) ? 64 : GEBRD_GRID_PMAX;
 }
 inline size_t gebrd_grid_lds(int pcap, int qcap) {
   const int P = gebrd_grid_blocks(pcap, qcap);
@@ -2250,15 +2296,14 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
   const double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
-  const GebrdGridBufs G = gebrd_grid_bufs(J.work, N, P);
+  const GebrdGridBufs G = gebrd_grid_bufs(J.work, N);
   extern __shared__ double lds[];
   const int RB = (pcap + P - 1) / P;
   double* Lr = lds;                    // own rows: row i at Lr + (i / P) q
-  double* su = Lr + (size_t)RB * qcap; // u_k (p)
-  double* sy = su + pcap;              // y (q)
+  double* sy = Lr + (size_t)RB * qcap; // y (q)
   double* sv = sy + qcap;              // row k, then v_k (q)
   __shared__ double red[16];
-  __shared__ double s_tl, s_sl, s_bl, s_tr, s_sr;
+  __shared__ double s_tr, s_sr;
   __shared__ int s_abort;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int li = wave; li * P + b < p; li += 4) {
@@ -2269,76 +2314,108 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
     for (int i = tid; i < 2 * q; i += 256) W.d[i] = 0.0;
   if (tid == 0) s_abort = 0;
   __syncthreads();
+  // partials of step k over the own rows i > k (rows already in LDS), and
+  // row k from its owner
+  auto publish = [&](int k) {
+    const int par = k & 1;
+    double* yp = G.Y + ((size_t)par * GEBRD_GRID_PMAX + b) * N;
+    const int ifirst = k + 1 + ((b - (k + 1)) % P + P) % P;
+    for (int j = tid; j < q - k - 1; j += 256) {
+      double acc = 0.0;
+      for (int i = ifirst; i < p; i += P) {
+        const double* r = Lr + (size_t)(i / P) * q;
+        acc += r[k] * r[k + 1 + j];
+      }
+      yp[j] = acc;
+    }
+    if (wave == 0) {
+      double part = 0.0;
+      for (int i = ifirst + lane * P; i < p; i += 64 * P) {
+        const double c = Lr[(size_t)(i / P) * q + k];
+        part += c * c;
+      }
+      part = wave_sum(part);
+      if (lane == 0) G.S[(size_t)par * GEBRD_GRID_PMAX + b] = part;
+    }
+    if (k % P == b) {
+      const double* r = Lr + (size_t)(k / P) * q;
+      double* rpub = G.R + (size_t)par * N;
+      for (int j = k + tid; j < q; j += 256) rpub[j] = r[j];
+    }
+  };
   const GridSync gs = grid_sync_of(J.work, N);
   const unsigned gen0 = grid_gen(gs);
   unsigned ordinal = gen0 * GRID_ORD_SPAN;
+  publish(0);
+  grid_barrier(gs.flag, ++ordinal, P, &s_abort, dims);
   for (int k = 0; k < q; ++k) {
-    const int nc = q - k - 1;
-    // A. left reflector of column k, rows k..p-1
-    double part = 0.0;
-    for (int i = k + tid; i < p; i += 256) {
-      const double c = k == 0 ? A[(long long)i * lda] : G.C[i];
-      su[i] = c;
-      if (i > k) part += c * c;
+    const int nc = q - k - 1, par = k & 1;
+    const double* rk = G.R + (size_t)par * N;
+    const double* S = G.S + (size_t)par * GEBRD_GRID_PMAX;
+    // left reflector of column k (every thread forms the same scalars)
+    const double sumsq =
+        wave_sum((lane < P ? S[lane] : 0.0) + (lane + 64 < P ? S[lane + 64] : 0.0));
+    const double alpha = rk[k];
+    double tl, sl, bl;
+    if (sumsq == 0.0) {
+      tl = 0.0;
+      sl = 0.0;
+      bl = alpha;
+    } else {
+      bl = -copysign(sqrt(alpha * alpha + sumsq), alpha);
+      tl = (bl - alpha) / bl;
+      sl = 1.0 / (alpha - bl);
     }
-    const double sumsq = block_sum<256>(part, red);
-    if (tid == 0) {
-      const double alpha = su[k];
-      if (sumsq == 0.0) {
-        s_tl = 0.0;
-        s_sl = 0.0;
-        s_bl = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        s_tl = (beta - alpha) / beta;
-        s_sl = 1.0 / (alpha - beta);
-        s_bl = beta;
-      }
-      if (b == 0) {
-        W.e[2 * k] = s_bl;
-        if (nc <= 0) W.tau[k] = 0.0;
-      }
+    if (b == 0 && tid == 0) {
+      W.e[2 * k] = bl;
+      if (nc <= 0) W.tau[k] = 0.0;
     }
-    __syncthreads();
     if (nc <= 0) break;  // the last column: no right reflector
-    const double tl = s_tl, sl = s_sl;
-    for (int i = k + tid; i < p; i += 256) su[i] = i == k ? 1.0 : su[i] * sl;
-    __syncthreads();
-    {
-      // this block's partial of A(k:, k+1:)^T u over its own rows
-      const int ifirst = k + ((b - k) % P + P) % P;
-      double* yp = G.Y + (size_t)b * N;
-      for (int j = tid; j < nc; j += 256) {
-        double acc = 0.0;
-        for (int i = ifirst; i < p; i += P) acc += su[i] * Lr[(size_t)(i / P) * q + k + 1 + j];
-        yp[j] = acc;
+    // y, and row k after the left reflector
+    // (the P partials of a column are summed in block order; the loads of up
+    // to GBG_M columns times GBG_U blocks are issued together)
+    const double* Yp = G.Y + (size_t)par * GEBRD_GRID_PMAX * N;
+    double acc[GBG_M];
+#pragma unroll
+    for (int m = 0; m < GBG_M; ++m) acc[m] = 0.0;
+    for (int q0 = 0; q0 < P; q0 += GBG_U) {
+      double v[GBG_M][GBG_U];
+#pragma unroll
+      for (int m = 0; m < GBG_M; ++m) {
+        const int j = tid + 256 * m;
+#pragma unroll
+        for (int u = 0; u < GBG_U; ++u)
+          v[m][u] = (j < nc && q0 + u < P) ? Yp[(size_t)(q0 + u) * N + j] : 0.0;
       }
+#pragma unroll
+      for (int m = 0; m < GBG_M; ++m)
+#pragma unroll
+        for (int u = 0; u < GBG_U; ++u) acc[m] += v[m][u];
     }
-    grid_barrier(gs.flag, ++ordinal, P, &s_abort, dims);
-    // B. y, row k after the left reflector, right reflector
-    const double* rk = k == 0 ? A : G.R + (size_t)(k & 1) * N;
-    part = 0.0;
-    for (int j = tid; j < nc; j += 256) {
-      double acc = 0.0;
-      for (int q2 = 0; q2 < P; ++q2) acc += G.Y[(size_t)q2 * N + j];
-      const double y = tl * acc;
+    double part = 0.0;
+#pragma unroll
+    for (int m = 0; m < GBG_M; ++m) {
+      const int j = tid + 256 * m;
+      if (j >= nc) continue;
+      const double rkj = rk[k + 1 + j];
+      const double y = tl * (rkj + sl * acc[m]);
       sy[j] = y;
-      const double r = rk[k + 1 + j] - y;
+      const double r = rkj - y;
       sv[j] = r;
       if (j > 0) part += r * r;
     }
     const double sumr = block_sum<256>(part, red);
     if (tid == 0) {
-      const double alpha = sv[0];
+      const double alpha_r = sv[0];
       double beta;
       if (sumr == 0.0) {
         s_tr = 0.0;
         s_sr = 0.0;
-        beta = alpha;
+        beta = alpha_r;
       } else {
-        beta = -copysign(sqrt(alpha * alpha + sumr), alpha);
-        s_tr = (beta - alpha) / beta;
-        s_sr = 1.0 / (alpha - beta);
+        beta = -copysign(sqrt(alpha_r * alpha_r + sumr), alpha_r);
+        s_tr = (beta - alpha_r) / beta;
+        s_sr = 1.0 / (alpha_r - beta);
       }
       if (b == 0) {
         W.e[2 * k + 1] = beta;
@@ -2353,26 +2430,40 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
       if (b == 0) W.H[(long long)k * N + k + 1 + j] = v;
     }
     __syncthreads();
-    double* rpub = G.R + (size_t)((k + 1) & 1) * N;
+    // own rows: lane l handles the columns k + 1 + l + 64 t of every row, so y
+    // and v at those columns stay in registers, and so does the row between
+    // the two reflectors: one LDS read and one write per element
     const int i0 = k + 1 + ((b - (k + 1)) % P + P) % P;
+    double cy[SYG_T], cv[SYG_T];
+#pragma unroll
+    for (int t = 0; t < SYG_T; ++t) {
+      const int j = lane + 64 * t;
+      cy[t] = j < nc ? sy[j] : 0.0;
+      cv[t] = j < nc ? sv[j] : 0.0;
+    }
     for (int i = i0 + wave * P; i < p; i += 4 * P) {
-      double* r = Lr + (size_t)(i / P) * q + k + 1;
-      const double ui = su[i];
+      double* rowp = Lr + (size_t)(i / P) * q;
+      double* r = rowp + k + 1;
+      const double ui = sl * rowp[k];
+      double x[SYG_T];
       double acc = 0.0;
-      for (int j = lane; j < nc; j += 64) {
-        const double t = r[j] - ui * sy[j];
-        r[j] = t;
-        acc += t * sv[j];
+#pragma unroll
+      for (int t = 0; t < SYG_T; ++t) {
+        if (64 * t >= nc) break;
+        const int j = lane + 64 * t;
+        x[t] = j < nc ? r[j] - ui * cy[t] : 0.0;
+        acc += x[t] * cv[t];
       }
       const double z = tr * wave_sum(acc);
-      const bool publish = i == k + 1;
-      for (int j = lane; j < nc; j += 64) {
-        const double t = r[j] - z * sv[j];
-        r[j] = t;
-        if (j == 0) G.C[i] = t;
-        if (publish) rpub[k + 1 + j] = t;
+#pragma unroll
+      for (int t = 0; t < SYG_T; ++t) {
+        if (64 * t >= nc) break;
+        const int j = lane + 64 * t;
+        if (j < nc) r[j] = x[t] - z * cv[t];
       }
     }
+    __syncthreads();
+    publish(k + 1);
     grid_barrier(gs.flag, ++ordinal, P, &s_abort, dims);
   }
   grid_launch_end(gs, gen0, ordinal != gen0 * GRID_ORD_SPAN);

@@ -119,10 +119,14 @@ __device__ inline f64x4 mfma16(double a, double b, f64x4 c) {
 // buffered: the next stage is loaded into registers while the current one
 // feeds the MFMAs); each of the four waves owns a 64 x 64 quarter, sixteen
 // independent 16 x 16 accumulators.  16 x 16 blocks wholly past n are
-// skipped, and so is the lower quarter of a diagonal tile (its transpose is
-// the upper one).  XCD-aware order: consecutive blocks go to consecutive
-// XCDs, and all tile pairs of one row slice go to the same XCD, so the rows
-// they share are fetched into one L2.
+// skipped.  A diagonal pair forms only its 36 upper 16 x 16 blocks (block row
+// p, block column q >= p), dealt to the waves by block rows {w, 7 - w}, nine
+// each.  When the last live tile holds at most 16 columns, the diagonal pair
+// (t, t) also forms tile t against those columns as a ninth block column
+// (eleven blocks per wave), and the pair (t, last) is skipped: it would
+// stream all of tile t's rows again for one narrow block.  XCD-aware order:
+// consecutive blocks go to consecutive XCDs, and all tile pairs of one row
+// slice go to the same XCD, so the rows they share are fetched into one L2.
 constexpr int GW_T = 128;
 constexpr int GW_KB = 16;
 constexpr int GW_LD = 144;  // LDS row stride: rows r and r+1 fall in opposite bank halves
@@ -133,6 +137,111 @@ __device__ inline void gw_pair(int pair, int tiles, int& ti, int& tj) {
   while (rem >= tiles - t) { rem -= tiles - t; ++t; }
   ti = t;
   tj = t + rem;
+}
+
+__device__ inline int gw_pair_index(int ti, int tj, int tiles) {
+  return ti * tiles - ti * (ti - 1) / 2 + (tj - ti);
+}
+
+// Diagonal tile pair (ti, ti) of k_gram_wide, wave W: block rows W and 7 - W,
+// block columns q >= the row (q == 8: the folded thin columns).  Operands are
+// read from LDS for every kk step whether or not a block is live, so the reads
+// are issued ahead of the MFMAs; a block is formed when both its row and its
+// column hold live columns.
+template <int W, typename Load, typename Store>
+__device__ __forceinline__ void gram_wide_diag_wave(int nt, bool fold, int nstage, int k_begin,
+                                                    const double (*sA)[GW_KB][GW_LD],
+                                                    const double (*sX)[GW_KB][16],
+                                                    double* __restrict__ out,
+                                                    double* __restrict__ outx,
+                                                    const Load& load, const Store& store) {
+  constexpr int P1 = W, P2 = 7 - W;
+  const int lane = threadIdx.x & 63, col = lane & 15, kr = lane >> 4;
+  auto live = [&](int p, int q) { return q == 8 ? fold : (16 * p < nt && 16 * q < nt); };
+  f64x4 acc1[9 - P1], acc2[9 - P2];
+#pragma unroll
+  for (int m = 0; m < 9 - P1; ++m) acc1[m] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < 9 - P2; ++m) acc2[m] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int st = 0; st < nstage; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nstage) load(k_begin + (st + 1) * GW_KB);
+    const double(*SA)[GW_LD] = sA[buf];
+    const double(*SX)[16] = sX[buf];
+#pragma unroll
+    for (int kk = 0; kk < GW_KB; kk += 4) {
+      const double fa1 = SA[kk + kr][16 * P1 + col];
+      const double fa2 = SA[kk + kr][16 * P2 + col];
+      double fb[9 - P1];
+#pragma unroll
+      for (int m = 0; m < 9 - P1; ++m)
+        fb[m] = P1 + m == 8 ? SX[kk + kr][col] : SA[kk + kr][16 * (P1 + m) + col];
+#pragma unroll
+      for (int m = 0; m < 9 - P1; ++m)
+        if (live(P1, P1 + m)) acc1[m] = mfma16(fa1, fb[m], acc1[m]);
+#pragma unroll
+      for (int m = 0; m < 9 - P2; ++m)
+        if (live(P2, P2 + m)) acc2[m] = mfma16(fa2, fb[m + P2 - P1], acc2[m]);
+    }
+    if (st + 1 < nstage) store(buf ^ 1);
+    __syncthreads();
+  }
+  auto put = [&](int p, int q, const f64x4& a) {
+    double* o = q == 8 ? outx : out;
+    const int jj = (q == 8 ? 0 : 16 * q) + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[(16 * p + (lane >> 4) + 4 * r) * GW_T + jj] = a[r];
+  };
+#pragma unroll
+  for (int m = 0; m < 9 - P1; ++m)
+    if (live(P1, P1 + m)) put(P1, P1 + m, acc1[m]);
+#pragma unroll
+  for (int m = 0; m < 9 - P2; ++m)
+    if (live(P2, P2 + m)) put(P2, P2 + m, acc2[m]);
+}
+
+// Diagonal tile pair (ti, ti) of k_gram_wide; with fold, also tile ti against
+// the (at most 16) columns of the last live tile tl, written to pair (ti, tl)
+// (outx).  Rows stream through LDS as in the off-diagonal pairs.
+__device__ __forceinline__ void gram_wide_diag(const double* __restrict__ A, int lda, int n,
+                                               int ti, int tl, bool fold, int k_begin, int k_end,
+                                               double* __restrict__ out, double* __restrict__ outx,
+                                               double (*sA)[GW_KB][GW_LD],
+                                               double (*sX)[GW_KB][16]) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int ca = ti * GW_T, cx = tl * GW_T;
+  const int nt = n - ca;  // live columns of the tile (all 128 unless it is the last)
+  const int lc = tid & 127, lr = tid >> 7;
+  const bool va = lc < nt;
+  const int xr = tid >> 4, xc = tid & 15;  // thin columns: one element per thread
+  const bool vx = fold && cx + xc < n;
+  double ra[8], rx;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int row = k0 + lr + 2 * u;
+      ra[u] = (row < k_end && va) ? A[(long long)row * lda + ca + lc] : 0.0;
+    }
+    const int row = k0 + xr;
+    rx = (row < k_end && vx) ? A[(long long)row * lda + cx + xc] : 0.0;
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sA[buf][lr + 2 * u][lc] = ra[u];
+    sX[buf][xr][xc] = rx;
+  };
+  const int nstage = (k_end - k_begin + GW_KB - 1) / GW_KB;
+  if (nstage > 0) {
+    load(k_begin);
+    store(0);
+  }
+  __syncthreads();
+  switch (wave) {
+    case 0: gram_wide_diag_wave<0>(nt, fold, nstage, k_begin, sA, sX, out, outx, load, store); break;
+    case 1: gram_wide_diag_wave<1>(nt, fold, nstage, k_begin, sA, sX, out, outx, load, store); break;
+    case 2: gram_wide_diag_wave<2>(nt, fold, nstage, k_begin, sA, sX, out, outx, load, store); break;
+    default: gram_wide_diag_wave<3>(nt, fold, nstage, k_begin, sA, sX, out, outx, load, store);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A, int lda, int K,
@@ -146,17 +255,30 @@ __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A,
   int ti, tj;
   gw_pair(pair, tiles, ti, tj);
   if (ti * GW_T >= n || tj * GW_T >= n) return;
+  // last live tile; when it holds at most 16 columns the diagonal pairs form
+  // the products with it
+  const int tl = (n - 1) / GW_T;
+  const bool thin = tl > 0 && n - tl * GW_T <= 16;
+  if (thin && tj == tl && ti < tl) return;
   const bool diag = ti == tj;
   __shared__ double sA[2][GW_KB][GW_LD], sB[2][GW_KB][GW_LD];
+  const int k_begin = slice * kslice;
+  const int k_end = min(K, k_begin + kslice);
+  if (diag) {
+    const bool fold = thin && ti < tl;
+    double* out = partial + ((long long)slice * pairs + pair) * (GW_T * GW_T);
+    double* outx =
+        partial + ((long long)slice * pairs + gw_pair_index(ti, tl, tiles)) * (GW_T * GW_T);
+    gram_wide_diag(A, lda, n, ti, tl, fold, k_begin, k_end, out, outx, sA,
+                   reinterpret_cast<double(*)[GW_KB][16]>(&sB[0][0][0]));
+    return;
+  }
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
-  const bool idle = diag && wr > wc;  // lower quarter of a diagonal tile
   const int ca = ti * GW_T, cb = tj * GW_T;
   // loads: thread t moves column t % 128 of rows t / 128 + 2u, u = 0..7
   const int lc = tid & 127, lr = tid >> 7;
   const bool va = ca + lc < n, vb = cb + lc < n;
-  const int k_begin = slice * kslice;
-  const int k_end = min(K, k_begin + kslice);
   // valid 16 x 16 blocks of this wave
   const int a0 = wr * 64, b0 = wc * 64;
   int np = 0, nq = 0;
@@ -164,7 +286,6 @@ __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A,
     if (ca + a0 + 16 * t < n) np = t + 1;
     if (cb + b0 + 16 * t < n) nq = t + 1;
   }
-  if (idle) np = nq = 0;
   f64x4 acc[4][4];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
@@ -178,14 +299,14 @@ __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A,
       const bool vr = row < k_end;
       const double* rp = A + (long long)row * lda;
       ra[u] = (vr && va) ? rp[ca + lc] : 0.0;
-      rb[u] = (vr && vb && !diag) ? rp[cb + lc] : 0.0;
+      rb[u] = (vr && vb) ? rp[cb + lc] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       sA[buf][lr + 2 * u][lc] = ra[u];
-      if (!diag) sB[buf][lr + 2 * u][lc] = rb[u];
+      sB[buf][lr + 2 * u][lc] = rb[u];
     }
   };
   const int nstage = (k_end - k_begin + GW_KB - 1) / GW_KB;
@@ -199,7 +320,7 @@ __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A,
     const int buf = st & 1;
     if (st + 1 < nstage) load(k_begin + (st + 1) * GW_KB);
     const double(*SA)[GW_LD] = sA[buf];
-    const double(*SB)[GW_LD] = diag ? sA[buf] : sB[buf];
+    const double(*SB)[GW_LD] = sB[buf];
 #pragma unroll
     for (int kk = 0; kk < GW_KB; kk += 4) {
       double fa[4], fb[4];
@@ -233,7 +354,8 @@ __global__ __launch_bounds__(256) void k_gram_wide(const double* __restrict__ A,
 }
 
 // Fixed-order sum of the wide Gram's slices, mirrored into G.  Diagonal tiles
-// take the upper triangle (ii <= jj) only: their lower quarter is not formed.
+// take the upper triangle (ii <= jj) only: their blocks below the diagonal
+// are not formed.
 __global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restrict__ partial,
                                                           int slices, int pairs, int tiles,
                                                           DimExpr ndim, const int* __restrict__ dims,

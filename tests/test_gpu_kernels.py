@@ -77,7 +77,8 @@ def test_gemm_tall(env, K, k, n):
 
 
 @pytest.mark.parametrize("K,n", [(4, 16), (1, 1), (3, 5), (1000, 64), (1000, 65), (4097, 130), (65536, 322),
-                                 (1000, 385), (4097, 400), (20000, 641), (30000, 897), (9000, 1024)])
+                                 (1000, 385), (4097, 400), (2000, 401), (20000, 641), (3001, 770),
+                                 (30000, 897), (9000, 1024)])
 def test_gram(env, K, n):
     lib, torch = env
     rng = np.random.default_rng(K + n)
@@ -165,7 +166,8 @@ def _svd_case(kind, a, b, rng):
 @pytest.mark.parametrize("a,b", [(1, 1), (1, 6), (6, 1), (7, 7), (40, 33), (33, 40), (142, 36),
                                  (36, 142), (62, 12), (1024, 12), (192, 64), (64, 192), (193, 64),
                                  (65, 64), (130, 200), (322, 150), (143, 322), (383, 383),
-                                 (420, 390), (897, 641), (641, 897), (1000, 1024)])
+                                 (420, 390), (1024, 16), (16, 1024), (897, 641), (641, 897),
+                                 (1000, 1024)])
 def test_svd(env, kind, a, b):
     lib, torch = env
     rng = np.random.default_rng(a * 1000 + b + len(kind))
