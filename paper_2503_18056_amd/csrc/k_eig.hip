@@ -134,8 +134,9 @@ constexpr int SYR_MAX = 160;  // orders reduced in registers by k_sytrd_reg
 
 // Large orders (n > SYR_MAX): the matrix does not fit one CU's registers,
 // and one block streaming the trailing matrix from L2 is bound by that CU's
-// share of the memory system.  Instead SYTRD_GRID_P blocks per job each keep
-// the rows i = b (mod P) of the full symmetric square in their own LDS
+// share of the memory system.  Instead P blocks per job (32 when their rows
+// fit LDS, else SYTRD_GRID_P) each keep the rows i = b (mod P) of the full
+// symmetric square in their own LDS
 // (at most ceil(N / P) rows), and step k, which needs T_k (the matrix after
 // reflectors 0..k-1), runs as:
 //   - every block forms row k of T_k from row k of T_{k-1} (published by its
@@ -174,8 +175,16 @@ __device__ __host__ inline SytrdGridBufs sytrd_grid_bufs(double* work, int N) {
   B.Dv = B.Pv + 2 * (size_t)N;
   return B;
 }
-inline int sytrd_grid_rows(int N) { return (N + SYTRD_GRID_P - 1) / SYTRD_GRID_P; }
-inline size_t sytrd_grid_lds(int N) { return ((size_t)sytrd_grid_rows(N) * N + 3 * (size_t)N) * 8; }
+// Blocks per job: 32 when their rows fit LDS (fewer blocks make the grid
+// barrier and the partial-dot sum cheaper), else SYTRD_GRID_P.
+constexpr size_t GRID_DYN_LDS_MAX = 150 * 1024;  // dynamic LDS a grid reduction may ask for
+inline size_t sytrd_grid_lds_p(int N, int P) {
+  return ((size_t)((N + P - 1) / P) * N + 3 * (size_t)N) * 8;
+}
+inline int sytrd_grid_blocks(int N) {
+  return sytrd_grid_lds_p(N, 32) <= GRID_DYN_LDS_MAX ? 32 : SYTRD_GRID_P;
+}
+inline size_t sytrd_grid_lds(int N) { return sytrd_grid_lds_p(N, sytrd_grid_blocks(N)); }
 
 // Grid barriers of the multi-block kernels.  A job's work area ends with one
 // flag per block and a launch generation.  Each launch takes its barrier
@@ -1936,7 +1945,10 @@ __global__ __launch_bounds__(256) void k_eig_final(EigJobs jobs, int* __restrict
 // ~u sigma_1 absolutely and the vectors to ~u sigma_1 / gap.
 
 constexpr int GEBRD_LDS_MAX = 16384;  // p q doubles held in LDS by k_gebrd_lds
-constexpr int GEBRD_GRID_MIN = 384;   // longer side from which k_gebrd_grid takes over
+// Longer side from which k_gebrd_grid takes a matrix that does not fit
+// k_gebrd_lds.  With p >= q, a p x q matrix with p < 128 always fits
+// (p (q | 1) <= 127^2 < GEBRD_LDS_MAX), so every other one goes to the grid.
+constexpr int GEBRD_GRID_MIN = 128;
 constexpr int GEBRD_GRID_PMAX = 128;  // blocks of k_gebrd_grid at most
 static_assert(GEBRD_GRID_PMAX <= 128, "eig_work_main sizes the grid partials for 128 blocks");
 constexpr int GBG_M = 4;   // columns per thread in k_gebrd_grid's partial sums (q <= 1024)
@@ -2136,116 +2148,15 @@ __global__ __launch_bounds__(JAC_T) void k_svd_jacobi(const double* __restrict__
   if (tid < 256) gauge_columns(J.V, J.ldv, q, kept);
 }
 
-// Householder bidiagonalisation of the p x q work matrix (p >= q) in one
-// 1024-thread block: left reflectors zero column k below the diagonal (d_k),
-// right reflectors zero row k right of the superdiagonal (e_k).  Only the
-// right reflectors are kept (W.H rows, W.tau): the vectors of the short side
-// are Q_R times the v-part of the tridiagonal's eigenvectors.
-__global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ dims, int N,
-                                                int a_idx, int b_idx, int side_idx) {
-  const EigJob J = jobs.j[0];
-  if (dims[J.n_idx] < 0) return;  // solved by k_svd_jacobi
-  const int a = dims[a_idx], b = dims[b_idx], side = dims[side_idx];
-  const int p = side ? a : b, q = side ? b : a;
-  if (gebrd_fits(p, q) || p >= GEBRD_GRID_MIN) return;  // k_gebrd_lds or k_gebrd_grid
-  double* A = J.A;
-  const long long lda = J.lda;
-  Work W = work_of(J, N);
-  __shared__ double sv[1024], sp[4][1024], red[16];
-  __shared__ double s_tau, s_scal;
-  const int tid = threadIdx.x, cj = tid & 255, g = tid >> 8;
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < 2 * q; i += 1024) W.d[i] = 0.0;
-  for (int k = 0; k < q; ++k) {
-    // left reflector on column k, rows k..p-1
-    const int mr = p - k;
-    double part = 0.0;
-    for (int i = 1 + tid; i < mr; i += 1024) {
-      const double x = A[(long long)(k + i) * lda + k];
-      part += x * x;
-    }
-    double sumsq = block_sum<1024>(part, red);
-    if (tid == 0) {
-      const double alpha = A[(long long)k * lda + k];
-      if (sumsq == 0.0) {
-        s_tau = 0.0;
-        s_scal = 0.0;
-        W.e[2 * k] = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        s_tau = (beta - alpha) / beta;
-        s_scal = 1.0 / (alpha - beta);
-        W.e[2 * k] = beta;
-      }
-    }
-    __syncthreads();
-    double tau = s_tau, scal = s_scal;
-    const int nc = q - k - 1;  // trailing columns k+1..q-1
-    if (tau != 0.0 && nc > 0) {
-      for (int i = tid; i < mr; i += 1024) sv[i] = i == 0 ? 1.0 : A[(long long)(k + i) * lda + k] * scal;
-      __syncthreads();
-      for (int j = cj; j < nc; j += 256) {
-        double acc = 0.0;
-        for (int i = g; i < mr; i += 4) acc += A[(long long)(k + i) * lda + k + 1 + j] * sv[i];
-        sp[g][j] = acc;
-      }
-      __syncthreads();
-      for (int j = cj; j < nc; j += 256) {
-        const double wj = tau * (((sp[0][j] + sp[1][j]) + sp[2][j]) + sp[3][j]);
-        for (int i = g; i < mr; i += 4) A[(long long)(k + i) * lda + k + 1 + j] -= sv[i] * wj;
-      }
-      __syncthreads();
-    }
-    if (nc <= 0) {
-      if (tid == 0) W.tau[k] = 0.0;
-      continue;
-    }
-    // right reflector on row k, columns k+1..q-1
-    part = 0.0;
-    for (int j = 1 + tid; j < nc; j += 1024) {
-      const double x = A[(long long)k * lda + k + 1 + j];
-      part += x * x;
-    }
-    sumsq = block_sum<1024>(part, red);
-    if (tid == 0) {
-      const double alpha = A[(long long)k * lda + k + 1];
-      if (sumsq == 0.0) {
-        s_tau = 0.0;
-        s_scal = 0.0;
-        W.e[2 * k + 1] = alpha;
-      } else {
-        const double beta = -copysign(sqrt(alpha * alpha + sumsq), alpha);
-        s_tau = (beta - alpha) / beta;
-        s_scal = 1.0 / (alpha - beta);
-        W.e[2 * k + 1] = beta;
-      }
-      W.tau[k] = s_tau;
-    }
-    __syncthreads();
-    tau = s_tau;
-    scal = s_scal;
-    for (int j = tid; j < nc; j += 1024) {
-      const double v = j == 0 ? 1.0 : A[(long long)k * lda + k + 1 + j] * scal;
-      sv[j] = v;
-      W.H[(long long)k * N + k + 1 + j] = v;
-    }
-    __syncthreads();
-    if (tau != 0.0) {
-      // rows k+1..p-1: A[i, k+1:] -= tau (A[i, k+1:] . v) v^T, a wave per row
-      for (int i = k + 1 + wave; i < p; i += 16) {
-        double* row = A + (long long)i * lda + k + 1;
-        double sdot = 0.0;
-        for (int j = lane; j < nc; j += 64) sdot += row[j] * sv[j];
-        sdot = wave_sum(sdot) * tau;
-        for (int j = lane; j < nc; j += 64) row[j] -= sdot * sv[j];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// The same bidiagonalisation for large matrices (p >= GEBRD_GRID_MIN) on P
-// blocks, each holding the rows i = b (mod P) in LDS (row stride q), with one
+// Householder bidiagonalisation of the p x q work matrix (p >= q): left
+// reflectors zero column k below the diagonal (d_k), right reflectors zero
+// row k right of the superdiagonal (e_k).  Only the right reflectors are kept
+// (W.H rows, W.tau): the vectors of the short side are Q_R times the v-part
+// of the tridiagonal's eigenvectors.  Two kernels: k_gebrd_lds when the
+// matrix fits one block's LDS, else k_gebrd_grid.
+//
+// k_gebrd_grid: P blocks, each holding the rows i = b (mod P) in LDS (row
+// stride q), with one
 // grid barrier per step.  The left reflector of column k is
 // u = e_k + s_L c, c = A(k+1:, k), and its product with the trailing matrix is
 // y = tau_L (A(k, k+1:) + s_L sum_{i > k} A(i, k) A(i, k+1:)): each block can
@@ -2259,8 +2170,8 @@ __global__ __launch_bounds__(1024) void k_gebrd(EigJobs jobs, int* __restrict__ 
 //   own rows in LDS (A_i -= s_L A(i, k) y, then A_i -= tau_R (A_i . v) v) and
 //   publishes the partials of step k + 1 (double-buffered by step parity: a
 //   block may write step k + 1's while another still reads step k's).
-// Outputs (W.e[2k] = d_k, W.e[2k+1] = e_k, W.tau, right reflectors in W.H)
-// as k_gebrd.  Launch and barrier as k_sytrd_grid.
+// Outputs: W.e[2k] = d_k, W.e[2k+1] = e_k, W.tau, right reflectors in W.H.
+// Launch and barrier as k_sytrd_grid.
 
 struct GebrdGridBufs {
   double *R, *Y, *S;  // published rows (2 x N), partial sums (2 x P x N), |c|^2 partials (2 x P)
@@ -2274,14 +2185,19 @@ __device__ __host__ inline GebrdGridBufs gebrd_grid_bufs(double* work, int N) {
   B.S = B.Y + 2 * (size_t)GEBRD_GRID_PMAX * N;
   return B;
 }
-// blocks and dynamic LDS for rows up to pcap and columns up to qcap
+// blocks and dynamic LDS for rows up to pcap and columns up to qcap: the
+// fewest blocks (16, 32, 64, 128) whose rows fit LDS, since the barrier and
+// the partial sums cost more with more blocks
+inline size_t gebrd_grid_lds_p(int pcap, int qcap, int P) {
+  return ((size_t)((pcap + P - 1) / P) * qcap + (size_t)pcap + 3 * (size_t)qcap) * 8;
+}
 inline int gebrd_grid_blocks(int pcap, int qcap) {
-  const size_t small = ((size_t)4 * 1024 + 64) * 8;  // vectors and statics
-  return ((size_t)((pcap + 63) / 64) * qcap * 8 + small <= 160 * 1024) ? 64 : GEBRD_GRID_PMAX;
+  for (int P = 16; P < GEBRD_GRID_PMAX; P *= 2)
+    if (gebrd_grid_lds_p(pcap, qcap, P) <= GRID_DYN_LDS_MAX) return P;
+  return GEBRD_GRID_PMAX;
 }
 inline size_t gebrd_grid_lds(int pcap, int qcap) {
-  const int P = gebrd_grid_blocks(pcap, qcap);
-  return ((size_t)((pcap + P - 1) / P) * qcap + (size_t)pcap + 3 * (size_t)qcap) * 8;
+  return gebrd_grid_lds_p(pcap, qcap, gebrd_grid_blocks(pcap, qcap));
 }
 
 __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restrict__ dims, int N,
@@ -2291,7 +2207,7 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
   if (dims[J.n_idx] < 0) return;  // solved by k_svd_jacobi
   const int a = dims[a_idx], bb = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : bb, q = side ? bb : a;
-  if (gebrd_fits(p, q) || p < GEBRD_GRID_MIN) return;  // k_gebrd_lds or k_gebrd
+  if (gebrd_fits(p, q) || p < GEBRD_GRID_MIN) return;  // k_gebrd_lds
   const int b = blockIdx.x, P = gridDim.x;
   const double* A = J.A;
   const long long lda = J.lda;
@@ -2469,9 +2385,10 @@ __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restric
   grid_launch_end(gs, gen0, ordinal != gen0 * GRID_ORD_SPAN);
 }
 
-// Bidiagonalisation with the p x q matrix in LDS (p ldq <= GEBRD_LDS_MAX,
-// ldq = q rounded up to odd so a thread per row reads distinct banks;
-// p <= 1024): loads the taller orientation of M directly.  Householder
+// k_gebrd_lds: the p x q matrix in LDS (p ldq <= GEBRD_LDS_MAX, ldq = q
+// rounded up to odd so a thread per row reads distinct banks; p <= 1024),
+// loaded in the taller orientation from M directly; outputs as k_gebrd_grid.
+// Householder
 // vectors are formed by one wavefront; the left reflector is applied by
 // column partial sums, the right one by a thread per row.
 
@@ -2773,7 +2690,8 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   k_sytrd_reg<<<njobs, SYR_T, 0, s>>>(J, dims, N);
   if (N > SYR_MAX) {
     const int nj = njobs < 4 ? njobs : 4;
-    k_sytrd_grid<<<dim3(SYTRD_GRID_P, nj), SYTRD_GRID_T, sytrd_grid_lds(N), s>>>(J, dims, N);
+    k_sytrd_grid<<<dim3(sytrd_grid_blocks(N), nj), SYTRD_GRID_T, sytrd_grid_lds(N), s>>>(J, dims,
+                                                                                         N);
   }
   dc_solve(J, njobs < 4 ? njobs : 4, N, dims, s);
   {
@@ -2799,7 +2717,6 @@ void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx
   k_svd_load<<<lb, 256, 0, s>>>(M, ldm, J, dims, a_idx, b_idx, side_idx);
   k_svd_jacobi<<<1, JAC_T, 0, s>>>(M, ldm, J, dims, a_idx, b_idx, side_idx);
   k_gebrd_lds<<<1, 1024, 0, s>>>(M, ldm, J, dims, N, a_idx, b_idx, side_idx);
-  k_gebrd<<<1, 1024, 0, s>>>(J, dims, N, a_idx, b_idx, side_idx);
   if (pcap >= GEBRD_GRID_MIN) {
     const int qc = qcap < pcap ? qcap : pcap;
     const int P = gebrd_grid_blocks(pcap, qc);
