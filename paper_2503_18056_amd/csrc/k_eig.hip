@@ -175,14 +175,16 @@ __device__ __host__ inline SytrdGridBufs sytrd_grid_bufs(double* work, int N) {
   B.Dv = B.Pv + 2 * (size_t)N;
   return B;
 }
-// Blocks per job: 32 when their rows fit LDS (fewer blocks make the grid
-// barrier and the partial-dot sum cheaper), else SYTRD_GRID_P.
-constexpr size_t GRID_DYN_LDS_MAX = 150 * 1024;  // dynamic LDS a grid reduction may ask for
+// Blocks per job: the fewest of 32, 48, 64 whose rows fit LDS (fewer blocks
+// make the grid barrier and the partial-dot sum cheaper).
+constexpr size_t GRID_DYN_LDS_MAX = 158 * 1024;  // dynamic LDS a grid reduction may ask for
 inline size_t sytrd_grid_lds_p(int N, int P) {
   return ((size_t)((N + P - 1) / P) * N + 3 * (size_t)N) * 8;
 }
 inline int sytrd_grid_blocks(int N) {
-  return sytrd_grid_lds_p(N, 32) <= GRID_DYN_LDS_MAX ? 32 : SYTRD_GRID_P;
+  for (int P = 32; P < SYTRD_GRID_P; P += 16)
+    if (sytrd_grid_lds_p(N, P) <= GRID_DYN_LDS_MAX) return P;
+  return SYTRD_GRID_P;
 }
 inline size_t sytrd_grid_lds(int N) { return sytrd_grid_lds_p(N, sytrd_grid_blocks(N)); }
 
@@ -2200,24 +2202,37 @@ inline size_t gebrd_grid_lds(int pcap, int qcap) {
   return gebrd_grid_lds_p(pcap, qcap, gebrd_grid_blocks(pcap, qcap));
 }
 
+// The launch is sized for the capacities (pcap, qcap); the live p x q matrix
+// runs on the fewest of 16, 32, ... launched blocks whose rows of stride q,
+// with y and v after them, fit the lds_doubles the launch provides, and the
+// other blocks return at once.
+__device__ inline int gebrd_grid_live_blocks(int p, int q, int qcap, int launched,
+                                             int lds_doubles) {
+  for (int P = 16; P < launched; P *= 2)
+    if ((long long)((p + P - 1) / P) * q + 2LL * qcap <= lds_doubles) return P;
+  return launched;
+}
+
 __global__ __launch_bounds__(256) void k_gebrd_grid(EigJobs jobs, int* __restrict__ dims, int N,
-                                                    int a_idx, int b_idx, int side_idx, int pcap,
-                                                    int qcap) {
+                                                    int a_idx, int b_idx, int side_idx, int qcap,
+                                                    int lds_doubles) {
   const EigJob J = jobs.j[0];
   if (dims[J.n_idx] < 0) return;  // solved by k_svd_jacobi
   const int a = dims[a_idx], bb = dims[b_idx], side = dims[side_idx];
   const int p = side ? a : bb, q = side ? bb : a;
   if (gebrd_fits(p, q) || p < GEBRD_GRID_MIN) return;  // k_gebrd_lds
-  const int b = blockIdx.x, P = gridDim.x;
+  const int P = gebrd_grid_live_blocks(p, q, qcap, gridDim.x, lds_doubles);
+  const int b = blockIdx.x;
+  if (b >= P) return;
   const double* A = J.A;
   const long long lda = J.lda;
   Work W = work_of(J, N);
   const GebrdGridBufs G = gebrd_grid_bufs(J.work, N);
   extern __shared__ double lds[];
-  const int RB = (pcap + P - 1) / P;
-  double* Lr = lds;                    // own rows: row i at Lr + (i / P) q
-  double* sy = Lr + (size_t)RB * qcap; // y (q)
-  double* sv = sy + qcap;              // row k, then v_k (q)
+  const int RB = (p + P - 1) / P;
+  double* Lr = lds;                 // own rows: row i at Lr + (i / P) q
+  double* sy = Lr + (size_t)RB * q; // y (q)
+  double* sv = sy + qcap;           // row k, then v_k (q)
   __shared__ double red[16];
   __shared__ double s_tr, s_sr;
   __shared__ int s_abort;
@@ -2720,8 +2735,8 @@ void svd_short_side(const double* M, int ldm, int a_idx, int b_idx, int side_idx
   if (pcap >= GEBRD_GRID_MIN) {
     const int qc = qcap < pcap ? qcap : pcap;
     const int P = gebrd_grid_blocks(pcap, qc);
-    k_gebrd_grid<<<P, 256, gebrd_grid_lds(pcap, qc), s>>>(J, dims, N, a_idx, b_idx, side_idx, pcap,
-                                                          qc);
+    const size_t lds = gebrd_grid_lds(pcap, qc);
+    k_gebrd_grid<<<P, 256, lds, s>>>(J, dims, N, a_idx, b_idx, side_idx, qc, (int)(lds / 8));
   }
   dc_solve(J, 1, N, dims, s);
   k_svd_back<<<(qcap + 3) / 4, 256, 0, s>>>(J, dims, N);
