@@ -127,6 +127,51 @@ __global__ __launch_bounds__(256) void k_xcat_row_dot(StepGeom G, const TX* __re
   if (lane == 0) E[i] = acc;
 }
 
+// The same E* in FP64 without forming X_cat's entries: the stencils are
+// linear, so sum_b (D_b X)(i, :) z_b = sum_b (D_b y_b)(i) with y_b = X z_b.
+// k_gemm_panel forms Y = X Zt (Zt[a][b] = z[b r1 + a], an N_s x B product
+// that reads X once), then this kernel applies each block's stencil to its
+// column of Y, with the ghost values of neighbour(), and adds the inflow
+// columns.
+__global__ void k_z_blocks(const double* __restrict__ z, double* __restrict__ Zt, int ldz, int B,
+                           const int* __restrict__ dims) {
+  const int r1 = dims[D_R1];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < r1 * B; e += gridDim.x * blockDim.x) {
+    const int a = e / B, b = e % B;
+    Zt[(long long)a * ldz + b] = z[(long long)b * r1 + a];
+  }
+}
+__global__ __launch_bounds__(256) void k_energy_stencil(StepGeom G, const double* __restrict__ Y,
+                                                        int ldy, const double* __restrict__ bc_e,
+                                                        const double* __restrict__ z,
+                                                        double* __restrict__ E,
+                                                        const int* __restrict__ dims) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.ns) return;
+  const int r1 = dims[D_R1];
+  const int nstencil = G.B * r1;
+  const int coord[3] = {i % G.nx, (i / G.nx) % G.ny, i / (G.nx * G.ny)};
+  double acc = 0.0;
+  for (int b = 0; b < G.B; ++b) {
+    const int kind = G.bkind[b], ax = G.baxis[b];
+    const double y0 = Y[(long long)i * ldy + b];
+    double v;
+    if (kind == BK_BASE) {
+      v = y0;
+    } else {
+      const double m = neighbour(G, Y, ldy, i, coord, ax, -1, b, y0);
+      const double p = neighbour(G, Y, ldy, i, coord, ax, 1, b, y0);
+      if (kind == BK_MINUS) v = y0 - m;
+      else if (kind == BK_PLUS) v = p - y0;
+      else if (kind == BK_CENTRAL) v = 0.5 * (p - m);
+      else v = (p - 2.0 * y0) + m;
+    }
+    acc += v;
+  }
+  for (int c = 0; c < G.nbc; ++c) acc += bc_e[(long long)c * G.ns + i] * z[nstencil + c];
+  E[i] = acc;
+}
+
 // Core conversion between FP64 and FP32 storage (rows x cols, leading dims).
 template <typename TA, typename TB>
 __global__ void k_convert(const TA* __restrict__ a, int lda, TB* __restrict__ b, int ldb, int rows,
@@ -293,21 +338,26 @@ __global__ void k_phi_moment(const double* __restrict__ Ph, int np, const double
   }
 }
 // z[a] = (1/c) sum_l w_l sum_b Th[a][l][b] pv[b], a < r1 (Th ld = ldb per l)
-__global__ void k_theta_moment(const double* __restrict__ Th, int nt, int ldb,
-                               const double* __restrict__ w, const double* __restrict__ pv,
-                               double* __restrict__ z, DimExpr rows, DimExpr cols, double inv_c,
-                               const int* __restrict__ dims) {
+__global__ __launch_bounds__(256) void k_theta_moment(const double* __restrict__ Th, int nt,
+                                                      int ldb, const double* __restrict__ w,
+                                                      const double* __restrict__ pv,
+                                                      double* __restrict__ z, DimExpr rows,
+                                                      DimExpr cols, double inv_c,
+                                                      const int* __restrict__ dims) {
+  // a wavefront per row a of the core: its nt x r2 slab is read once,
+  // coalesced, lane l taking the columns b = l + 64 m of every ordinate
   const int r1 = eval_dim(dims, rows), r2 = eval_dim(dims, cols);
-  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < r1; a += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int l = 0; l < nt; ++l) {
-      const double* t = Th + ((long long)a * nt + l) * ldb;
-      double sl = 0.0;
-      for (int b = 0; b < r2; ++b) sl += t[b] * pv[b];
-      s += w[l] * sl;
-    }
-    z[a] = s * inv_c;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (a >= r1) return;
+  double acc = 0.0;
+  for (int l = 0; l < nt; ++l) {
+    const double* t = Th + ((long long)a * nt + l) * ldb;
+    double sl = 0.0;
+    for (int b = lane; b < r2; b += 64) sl += t[b] * pv[b];
+    acc += w[l] * sl;
   }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) z[a] = acc * inv_c;
 }
 // E[i] = sum_{a < ncols} X[i][a] z[a]
 template <typename TX>
@@ -624,7 +674,7 @@ static void energy_impl(const TX* X, int ldX, int ns, const double* Th, int nt, 
                         double* z, DimExpr r1, DimExpr r2, double inv_c, double* E,
                         const int* dims, int rcap1, int rcap2, hipStream_t st) {
   k_phi_moment<<<(rcap2 + 63) / 64, 64, 0, st>>>(Ph, np, v, pv, r2, dims);
-  k_theta_moment<<<(rcap1 + 63) / 64, 64, 0, st>>>(Th, nt, ldb, w, pv, z, r1, r2, inv_c, dims);
+  k_theta_moment<<<(rcap1 + 3) / 4, 256, 0, st>>>(Th, nt, ldb, w, pv, z, r1, r2, inv_c, dims);
   k_row_dot<TX><<<(ns + 3) / 4, 256, 0, st>>>(X, ldX, ns, z, r1, E, dims);
 }
 void launch_energy(const double* X, int ldX, int ns, const double* Th, int nt, int ldb,
@@ -646,14 +696,20 @@ static void energy_xcat_impl(const StepGeom& G, const TX* X, int ldX, const doub
                              const int* dims, hipStream_t st) {
   const DimExpr ncol = dimv(D_RC1, 1, -G.nem);
   k_phi_moment<<<(G.R2c + 63) / 64, 64, 0, st>>>(Pc, G.np, v, pv, r2, dims);
-  k_theta_moment<<<(G.R1c + 63) / 64, 64, 0, st>>>(Tc, G.nt, G.R2c, w, pv, z, ncol, r2, inv_c, dims);
+  k_theta_moment<<<(G.R1c + 3) / 4, 256, 0, st>>>(Tc, G.nt, G.R2c, w, pv, z, ncol, r2, inv_c, dims);
   k_xcat_row_dot<TX><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, z, E, dims);
 }
 void launch_energy_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
                         const double* Tc, const double* Pc, const double* w, const double* v,
-                        double* pv, double* z, DimExpr r2, double inv_c, double* E,
-                        const int* dims, hipStream_t st) {
-  energy_xcat_impl(G, X, ldX, bc_e, Tc, Pc, w, v, pv, z, r2, inv_c, E, dims, st);
+                        double* pv, double* z, DimExpr r2, double inv_c, double* E, double* Y,
+                        double* Zt, const int* dims, hipStream_t st) {
+  const DimExpr ncol = dimv(D_RC1, 1, -G.nem);
+  k_phi_moment<<<(G.R2c + 63) / 64, 64, 0, st>>>(Pc, G.np, v, pv, r2, dims);
+  k_theta_moment<<<(G.R1c + 3) / 4, 256, 0, st>>>(Tc, G.nt, G.R2c, w, pv, z, ncol, r2, inv_c, dims);
+  constexpr int LDY = MAX_BLOCKS;
+  k_z_blocks<<<(G.r1c * G.B + 255) / 256, 256, 0, st>>>(z, Zt, LDY, G.B, dims);
+  gemm_tall(G.ns, X, ldX, Zt, LDY, Y, LDY, dimv(D_R1), dimc(G.B), G.r1c, LDY, dims, st);
+  k_energy_stencil<<<(G.ns + 255) / 256, 256, 0, st>>>(G, Y, LDY, bc_e, z, E, dims);
 }
 void launch_energy_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
                         const double* Tc, const double* Pc, const double* w, const double* v,

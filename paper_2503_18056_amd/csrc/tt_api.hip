@@ -222,6 +222,7 @@ size_t carve(tt_ctx* x, char* base) {
   x->Mupd2 = cv.take<double>((size_t)x->r2c * x->R2c);
   x->pv = cv.take<double>(std::max(x->R2c, x->r2c) + 8);
   x->z = cv.take<double>(std::max(x->R1c, x->r1c) + 8);
+  x->zt = cv.take<double>((size_t)x->r1c * MAX_BLOCKS);
   if (x->cfg.ckpt_every > 0) grad_carve(x, cv);
   return cv.off + 256;
 }
@@ -585,8 +586,9 @@ void step_once(tt_ctx* c) {
         launch_energy_xcat(c->G, c->Xf, c->ldX, c->bc_e, c->Thcat, c->Phcat, c->w, c->v, c->pv,
                            c->z, dimv(D_RC2), 1.0 / cf.c, c->Estar, c->dims, s);
       else
+        // Y in X_cat's buffer, free until the build below writes it
         launch_energy_xcat(c->G, c->X, c->ldX, c->bc_e, c->Thcat, c->Phcat, c->w, c->v, c->pv,
-                           c->z, dimv(D_RC2), 1.0 / cf.c, c->Estar, c->dims, s);
+                           c->z, dimv(D_RC2), 1.0 / cf.c, c->Estar, c->Xcat, c->zt, c->dims, s);
       launch_material(c->ns, cf.c, c->dt, cf.a_r, coupled ? 1 : 0, c->kappa, ks, c->rho, c->cv,
                       c->T, c->Estar, c->Tdag, c->d, c->s, c->dims, s);
     }

@@ -105,6 +105,7 @@ struct tt_ctx {
   double *M1, *C1, *Wm1, *Ur1, *P1, *Mupd1, *Thp;
   double *M2, *C2, *Wm2, *Ur2, *P2, *Mupd2;
   double *pv, *z;
+  double* zt;  // z by stencil block, r1c x MAX_BLOCKS (energy through Y = X Zt)
   tt::GradBufs gb;
   size_t ws_need;
   int nhist = 0, nsched = 0, sched_pos = 0;

@@ -52,10 +52,12 @@ void launch_energy(const float* X, int ldX, int ns, const double* Th, int nt, in
 // The post-transport energy density E = (1/c) X_cat z of the unscaled
 // concatenation (transport and inflow columns; Tc, Pc its angular cores),
 // with X_cat's entries formed from X on the fly.
+// FP64: E* through Y = X Zt (Y: N_s x MAX_BLOCKS doubles, Zt: r1c x
+// MAX_BLOCKS, the blocks of z as columns) and the stencils applied to Y.
 void launch_energy_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
                         const double* Tc, const double* Pc, const double* w, const double* v,
-                        double* pv, double* z, DimExpr r2, double inv_c, double* E,
-                        const int* dims, hipStream_t st);
+                        double* pv, double* z, DimExpr r2, double inv_c, double* E, double* Y,
+                        double* Zt, const int* dims, hipStream_t st);
 void launch_energy_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
                         const double* Tc, const double* Pc, const double* w, const double* v,
                         double* pv, double* z, DimExpr r2, double inv_c, double* E,
