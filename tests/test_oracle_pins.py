@@ -651,3 +651,54 @@ def test_gram_summation_is_not_the_fp64_parity_floor(monkeypatch):
         b, _, _ = tt.step(Xs, Ts, Ps, s.T0, s, p["tol"], p["rmax"], ranks=ranks, perturb=pert)
         worst_spread = max(worst_spread, metrics.rel_diff(b, ref))
     assert worst_spread > 1e-10
+
+
+# ------------------------------------------------------------------ hohlraum
+def _hohlraum_J_by_quadrature(t, x, y, c=1.0, nth=1000, nph=2000):
+    """Mean intensity as the solid-angle fraction (midpoint rule in theta,
+    phi) of directions whose backward ray from (x, y) leaves the quadrant
+    x, y > 0 through a wall within path length c t (Sec. 5.1's set-up)."""
+    th = (np.arange(nth) + 0.5) * np.pi / nth
+    ph = (np.arange(nph) + 0.5) * 2 * np.pi / nph
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    st = np.sin(TH)
+    hx, hy = st * np.cos(PH), st * np.sin(PH)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sx = np.where(hx > 0, x / hx, np.inf)
+        sy = np.where(hy > 0, y / hy, np.inf)
+    w = st * (np.pi / nth) * (2 * np.pi / nph)
+    return float((w * (np.minimum(sx, sy) <= c * t)).sum() / (4 * np.pi))
+
+
+def test_hohlraum_analytic_matches_quadrature():
+    """The closed form of Sec. 5.1 (J_left + J_bottom) against a direct
+    solid-angle quadrature of the same set-up, on both sides of the fronts
+    x = c t and y = c t."""
+    from oracle.analytic import hohlraum_J
+    for (x, y) in [(0.1, 0.2), (0.5, 0.3), (0.2, 0.9), (0.74, 0.01), (0.05, 0.7), (0.8, 0.3),
+                   (0.9, 0.9)]:
+        a = float(hohlraum_J(0.75, x, y))
+        q = _hohlraum_J_by_quadrature(0.75, x, y)
+        assert abs(a - q) < 1e-4, (x, y, a, q)
+    # symmetric in x and y; a half-space's 1/2 at a wall far from the corner
+    assert abs(float(hohlraum_J(0.75, 0.3, 0.6)) - float(hohlraum_J(0.75, 0.6, 0.3))) < 1e-15
+    assert abs(float(hohlraum_J(0.5, 1e-12, 0.9)) - 0.5) < 1e-9
+
+
+def test_hohlraum_full_grid_first_order():
+    """The full-grid S_N solution of the reduced hohlraum (16 x 32 ordinates)
+    against the analytic J over [0, 1]^2: the area-weighted L1 error is below
+    2e-2 at 32^2 cells and falls at first order in the cell size."""
+    from oracle.analytic import hohlraum_J
+    errs = []
+    for n in (32, 64):
+        p = wl.hohlraum(n=n, ntheta=16, nphi=32)
+        s = Setup(p)
+        I, _ = full.run(s, p["steps"])
+        J = s.c * full.energy(I, s).reshape(n, n) / (4 * np.pi)
+        xc = (np.arange(n) + 0.5) * 2.0 / n
+        Ja = hohlraum_J(p["hohlraum"]["t"], xc[None, :], xc[:, None])
+        m = n // 2
+        errs.append(np.abs(J[:m, :m] - Ja[:m, :m]).sum() * (2.0 / n) ** 2)
+    assert errs[0] < 2e-2
+    assert errs[1] < 0.65 * errs[0]

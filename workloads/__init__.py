@@ -318,6 +318,28 @@ def gaussian_diffusion(n=64, ntheta=8, nphi=16, steps=200, t0=200.0, rho_kappa_s
     return p
 
 
+def hohlraum(n=64, ntheta=16, nphi=32, tol=1e-4, rmax=0, t_end=0.75):
+    """Hohlraum (Sec. 5.1) at reduced size: domain [0, 2]^2, vacuum (no
+    opacity, no emission), isotropic intensity I = 1 entering through the
+    x-lo and y-lo faces (Dirichlet inflow g = 1 for every ordinate; the
+    upwind stencil reads it only for entering directions), the other faces
+    vacuum.  Zero initial state; CFL 0.5, so Delta t = 1/n and the run has
+    t_end n steps (n a multiple of 4 for t_end = 0.75)."""
+    steps = int(round(t_end * n))
+    p = _base(2, n, n, 1, ntheta, nphi, tol=tol, rmax=rmax, steps=steps, l=2.0)
+    p["bc_lo"] = [INFLOW, INFLOW, VACUUM]
+    p["bc_hi"] = [VACUUM, VACUUM, VACUUM]
+    ns = n * n
+    p["kappa"][:] = 0.0
+    p["T0"][:] = 0.0
+    p["X0"], p["Th0"], p["Ph0"] = zero_cores(p)
+    p["inflow"] = [(0, np.ones(n), np.ones(ntheta), np.ones(nphi)),
+                   (2, np.ones(n), np.ones(ntheta), np.ones(nphi))]
+    p["hohlraum"] = dict(t=steps * p["cfl"] * (2.0 / n) / p["c"])
+    p["name"] = f"hohlraum_{n}sq_{ntheta}x{nphi}"
+    return p
+
+
 def rounding_bench_cores(p, r1=64, r2=12, seed=2, decades_per_8=1.0):
     """Seeded synthetic state on the crossing-beam shape for the rounding
     benchmark: orthonormal X (N_s x r1), orthonormal Phi rows (r2 x N_phi)
