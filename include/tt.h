@@ -240,6 +240,17 @@ tt_status tt_profile_read(tt_ctx* ctx, double* ms, int32_t* count, const char** 
  * Errors: TT_ERR_INVALID_ARG unless 1 <= slices <= 6. */
 tt_status tt_set_gram_slices(tt_ctx* ctx, int32_t slices);
 
+/* Caps the sweeps of the one-sided Jacobi SVD of M (used when the short side
+ * of M is at most 64) at jacobi_max_sweeps (0, the default: its own limit of
+ * 40).  For exercising the failure path: with a cap too low for the matrix
+ * the solver stops unconverged (its rotations keep every value finite), the
+ * next tt_step or tt_round returns TT_ERR_NUMERIC ("the Jacobi SVD did not
+ * converge") and the context is poisoned.  Synchronises the context's
+ * stream; captured step graphs stay valid (the kernels read the cap from the
+ * device at run time).
+ * Errors: TT_ERR_INVALID_ARG if jacobi_max_sweeps < 0. */
+tt_status tt_set_solver_limits(tt_ctx* ctx, int32_t jacobi_max_sweeps);
+
 /* Step execution mode.  enable != 0 (the default): tt_step replays the
  * step's launch sequence as a HIP graph, captured on first use once per
  * state buffer (the step alternates two) on a private non-blocking stream

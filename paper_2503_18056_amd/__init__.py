@@ -215,6 +215,11 @@ class TTState:
         """11-bit slices per entry of the FP32-mixed Gram (1 .. 6, default 4)."""
         self._check(self.lib.tt_set_gram_slices(self.ctx, int(slices)))
 
+    def tt_set_solver_limits(self, jacobi_max_sweeps):
+        """Cap on the Jacobi SVD's sweeps (0: the solver's own limit); a cap
+        too low makes the next step fail with TT_ERR_NUMERIC."""
+        self._check(self.lib.tt_set_solver_limits(self.ctx, int(jacobi_max_sweeps)))
+
     def tt_profile_enable(self, on=True, classes=None):
         """Start (on) or stop recording HIP-event timings; ``classes`` (names
         from PROFILE_CLASSES) restricts recording to those regions."""

@@ -62,6 +62,7 @@ SIGNATURES = {
     "tt_profile_read": (C.c_int, [VP, PD, PI, C.POINTER(C.c_char_p), C.c_int32, PI]),
     "tt_use_graphs": (C.c_int, [VP, C.c_int32]),
     "tt_set_gram_slices": (C.c_int, [VP, C.c_int32]),
+    "tt_set_solver_limits": (C.c_int, [VP, C.c_int32]),
     "tt_last_error": (C.c_char_p, [VP]),
     "tt_kernel_eigh_workspace": (C.c_size_t, [C.c_int32]),
     "tt_kernel_eigh": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_double, VP, VP, C.c_int32, PI, VP,

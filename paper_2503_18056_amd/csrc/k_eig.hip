@@ -2048,8 +2048,12 @@ __global__ __launch_bounds__(JAC_T) void k_svd_jacobi(const double* __restrict__
   const int qe = q + (q & 1), npair = qe / 2, m1 = qe - 1;
   const int nch = ld / 16;
   const double tol2 = ((double)p * U64) * ((double)p * U64);
+  // sweeps allowed: JAC_MAXSW, or fewer when the host caps them (a test of
+  // the failure path: the rotations stay finite, only convergence is lost)
+  const int capsw = dims[D_JAC_MAXSW];
+  const int maxsw = capsw > 0 && capsw < JAC_MAXSW ? capsw : JAC_MAXSW;
   int sw = 0;
-  for (; sw < JAC_MAXSW; ++sw) {
+  for (; sw < maxsw; ++sw) {
     const int flag = sw & 1;
     for (int rnd = 0; rnd < m1; ++rnd) {
       if (4 * wave < npair) {
@@ -2104,7 +2108,7 @@ __global__ __launch_bounds__(JAC_T) void k_svd_jacobi(const double* __restrict__
     __syncthreads();
     if (!any) break;
   }
-  if (sw == JAC_MAXSW && tid == 0) atomicOr(&dims[D_FLAG], FLAG_EIG);
+  if (sw == maxsw && tid == 0) atomicOr(&dims[D_FLAG], FLAG_NOCONV);
   // singular values: column norms; descending order (index breaks ties)
   for (int j = wave; j < q; j += JAC_WAVES) {
     double part = 0.0;

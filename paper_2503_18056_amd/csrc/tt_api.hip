@@ -507,6 +507,7 @@ tt_status check_flags(tt_ctx* c) {
     if (flag & FLAG_NONFINITE) m += " non-finite state";
     if (flag & FLAG_NEWTON) m += " Newton did not converge";
     if (flag & FLAG_EIG) m += " eigensolver produced a non-finite value";
+    if (flag & FLAG_NOCONV) m += " the Jacobi SVD did not converge";
     if (flag & FLAG_BARRIER)
       m += " a grid barrier of a multi-block eigensolver timed out (blocks not co-resident)";
     return fail(c, TT_ERR_NUMERIC, m);
@@ -910,6 +911,7 @@ tt_status tt_set_cores(tt_ctx* c, const double* X, const double* Th, const doubl
   memset(hd, 0, sizeof(hd));
   hd[D_R1] = r[0];
   hd[D_R2] = r[1];
+  hd[D_JAC_MAXSW] = c->jac_maxsw;
   HIPCHK(c, hipMemcpyAsync(c->dims, hd, sizeof(hd), hipMemcpyHostToDevice, s));
   // frozen material without scattering: the source coefficients never change
   launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, nullptr, c->rho, c->cv, c->T,
@@ -1179,6 +1181,18 @@ tt_status tt_set_gram_slices(tt_ctx* c, int32_t slices) {
   HIPCHK(c, hipStreamSynchronize(c->st));
   graphs_drop(c);  // the captured launches name the kernel of the old count
   c->gram_slices = slices;
+  return TT_OK;
+}
+
+tt_status tt_set_solver_limits(tt_ctx* c, int32_t jacobi_max_sweeps) {
+  if (!c) return fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  if (jacobi_max_sweeps < 0) return fail(c, TT_ERR_INVALID_ARG, "jacobi_max_sweeps must be >= 0");
+  c->jac_maxsw = jacobi_max_sweeps;
+  // the kernels read the cap from the device table when they run, so the
+  // captured step graphs stay valid
+  HIPCHK(c, hipMemcpyAsync(c->dims + D_JAC_MAXSW, &c->jac_maxsw, sizeof(int), hipMemcpyHostToDevice,
+                           c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
   return TT_OK;
 }
 

@@ -115,7 +115,8 @@ struct tt_ctx {
   // cap_st; gafter / gafterf / gsched are the host bookkeeping one replay
   // performs (buffers after the step, schedule entries consumed)
   bool graphs = true;
-  int gram_slices = tt::GRAM_SLICES_DEFAULT;  // 11-bit slices of the FP32-mixed Gram
+  int gram_slices = tt::GRAM_SLICES_DEFAULT;
+  int jac_maxsw = 0;  // tt_set_solver_limits (0: the solver's own limit)  // 11-bit slices of the FP32-mixed Gram
   hipStream_t cap_st = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   const void* gkey[2] = {nullptr, nullptr};

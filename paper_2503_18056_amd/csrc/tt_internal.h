@@ -38,6 +38,7 @@ enum DimIndex : int {
   D_TGK2,
   D_HSLOT,       // next rank-history slot (steps recorded since the cores were set)
   D_SCHEDPOS,    // next entry of the replayed rank schedule
+  D_JAC_MAXSW,   // cap on the one-sided Jacobi SVD's sweeps (<= 0: its own limit)
   D_NDIMS = 64
 };
 
@@ -46,6 +47,7 @@ enum : int {
   FLAG_NEWTON = 2,
   FLAG_EIG = 4,
   FLAG_BARRIER = 8,  // a grid barrier of a multi-block eigensolver timed out
+  FLAG_NOCONV = 16,  // the one-sided Jacobi SVD ran out of sweeps
 };
 
 // diagnostics (double table)

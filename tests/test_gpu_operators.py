@@ -184,3 +184,33 @@ def test_grad_after_round_is_stale():
     st.step(2)
     L, g = st.tt_grad(np.ones(24 * 24))
     assert np.isfinite(L) and np.all(np.isfinite(g.cpu().numpy()))
+
+
+def test_jacobi_sweep_cap_reports_non_convergence():
+    """The failure path of the SVD of M, forced from the host: with
+    tt_set_solver_limits capping the one-sided Jacobi SVD at one sweep (too
+    few for the dense M of a step), the step returns TT_ERR_NUMERIC naming
+    that solver and the context is poisoned; without the cap the same steps
+    run.  The solver's rotations keep every value finite, so every kernel
+    exits normally."""
+    from paper_2503_18056_amd import TTError
+    from paper_2503_18056_amd._ffi import TT_ERR_INVALID_ARG, TT_ERR_NUMERIC, TT_ERR_STATE
+    p = wl.small_random(nx=33, ny=17, ntheta=8, nphi=16, r1=5, r2=3, seed=41, bc="mixed")
+    p["tol"] = 1e-6
+    st = _state(p, max_steps=4)
+    with pytest.raises(TTError) as e:
+        st.tt_set_solver_limits(-1)
+    assert e.value.status == TT_ERR_INVALID_ARG
+    st.step(2)
+    st.tt_set_solver_limits(1)
+    with pytest.raises(TTError) as e:
+        st.step(1)
+    _log(f"capped Jacobi: {e.value}")
+    assert e.value.status == TT_ERR_NUMERIC
+    assert "Jacobi SVD did not converge" in str(e.value)
+    with pytest.raises(TTError) as e:
+        st.step(1)
+    assert e.value.status == TT_ERR_STATE
+    ok = _state(p, max_steps=4)
+    ok.tt_set_solver_limits(0)
+    ok.step(3)
