@@ -92,11 +92,13 @@ _lib = None
 
 
 def load(path=None):
-    """Load libtt.so; raises if the HIP library has not been built."""
+    """Load libtt.so; raises if the HIP library has not been built.  The
+    environment variable TT_LIBRARY names another build of the same library
+    (the host-sanitizer build of the host-side checks)."""
     global _lib
     if _lib is not None and path is None:
         return _lib
-    p = path or LIB_PATH
+    p = path or os.environ.get("TT_LIBRARY") or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"HIP library {p} is missing: run paper_2503_18056_amd.build.build()")
     lib = C.CDLL(p)

@@ -27,9 +27,19 @@ def _hipcc():
     return "hipcc"
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# Host AddressSanitizer build of the whole library (the host code
+# instrumented, the device code as usual): libtt_asan.so in _build_asan/,
+# for running the host-side ABI checks under the sanitizer.  It needs the
+# shared sanitizer runtime preloaded (asan_runtime()).  Not the product
+# library: nothing loads it unless asked to (TT_LIBRARY).
+BUILD_ASAN = os.path.join(HERE, "_build_asan")
+LIB_ASAN = os.path.join(BUILD_ASAN, "libtt_asan.so")
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def _compile(src, build_dir=BUILD, extra=()):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [_hipcc(), *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -49,6 +59,32 @@ def build(verbose=False):
     if verbose:
         print("built", LIB)
     return LIB
+
+
+def build_host_asan(verbose=False):
+    os.makedirs(BUILD_ASAN, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(lambda src: _compile(src, BUILD_ASAN, ASAN_FLAGS), SOURCES))
+    tmp = LIB_ASAN + ".tmp"
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-shared-libasan", *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, LIB_ASAN)
+    if verbose:
+        print("built", LIB_ASAN)
+    return LIB_ASAN
+
+
+def asan_runtime():
+    """Path of the shared sanitizer runtime of the compiler that built it."""
+    r = subprocess.run([_hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
+                       text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("sanitizer runtime not found")
+    return path
 
 
 if __name__ == "__main__":
