@@ -1726,6 +1726,8 @@ constexpr int ORM_CH = 64;
 // ch * ld stays within it for every capacity up to 1024 (ch >= 4)
 constexpr int ORM_LDS_DBL = 18432;
 constexpr int ORM_PER = (ORM_LDS_DBL + 255) / 256;
+constexpr int ORM_BATCH = 24;  // staged doubles a thread loads before storing them
+static_assert(ORM_PER % ORM_BATCH == 0, "whole staging batches");
 __host__ __device__ inline int ormtr_ld(int N) { return ((N > 0 ? N : 1) + 63) & ~63; }
 __host__ __device__ inline int ormtr_chunk(int N) {
   int c = ORM_LDS_DBL / ormtr_ld(N);
@@ -1737,7 +1739,11 @@ __host__ __device__ inline size_t ormtr_lds_doubles(int N) {
   return (size_t)ch * ormtr_ld(N) + (size_t)(ch / ORM_G) * 16 + ch;
 }
 
-template <int NCH>
+// VPW vectors per wavefront (4 VPW per block): every block stages all the
+// reflectors, so at large orders, where the blocks outnumber the CUs and the
+// staging traffic (blocks x reflector bytes) bounds the launch, each
+// wavefront carries several vectors through the same staged chunks.
+template <int NCH, int VPW>
 __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.y];
   const int n = dims[J.n_idx];
@@ -1747,40 +1753,53 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
   const int N2 = next_pow2(N);
   const int ch = ormtr_chunk(N), ld = ormtr_ld(N), gpc = ch / ORM_G;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j0 = blockIdx.x * 4, j = j0 + wave;
+  const int j0 = blockIdx.x * 4 * VPW;
   if (j0 >= n) return;
   const double thr = keep_threshold(J, D.lam, n);
   // eigenvalues ascend, so the block's last vector is its largest
-  if (!(D.lam[min(j0 + 3, n - 1)] > thr)) return;
-  const bool active = j < n && D.lam[j] > thr;
+  if (!(D.lam[min(j0 + 4 * VPW - 1, n - 1)] > thr)) return;
+  // vector v of this wavefront: j = j0 + 4 v + wave
+  bool active[VPW];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < VPW; ++v) {
+    const int j = j0 + 4 * v + wave;
+    active[v] = j < n && D.lam[j] > thr;
+    any = any || active[v];
+  }
   extern __shared__ double hs[];  // ch reflectors (rows 0 .. ld - 1), each group's T, the taus
   double* Ts = hs + (size_t)ch * ld;
   double* taus = Ts + (size_t)gpc * 16;
-  double y[NCH];
+  double y[VPW][NCH];
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    const int i = lane + 64 * c;
-    y[c] = active && i < n ? (par ? D.Qb : D.Qa)[(size_t)i * N2 + j] : 0.0;
-  }
+  for (int v = 0; v < VPW; ++v)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int i = lane + 64 * c, j = j0 + 4 * v + wave;
+      y[v][c] = active[v] && i < n ? (par ? D.Qb : D.Qa)[(size_t)i * N2 + j] : 0.0;
+    }
   const int nref = n - 2;  // reflectors 0 .. n - 3
   const int ngrp = nref > 0 ? (nref + ORM_G - 1) / ORM_G : 0;
   for (int g1 = ngrp - 1; g1 >= 0; g1 -= gpc) {
     const int g0 = max(0, g1 - gpc + 1), kbase = ORM_G * g0, nr = ORM_G * (g1 - g0 + 1);
     __syncthreads();  // the previous chunk is no longer read
-    // flat over (reflector, row): every load of the chunk in flight before the
-    // first store
+    // flat over (reflector, row), in batches of ORM_BATCH elements a thread:
+    // every load of a batch in flight before its first store
     const int tot = nr * ld;
-    double t[ORM_PER];
-#pragma unroll
-    for (int u = 0; u < ORM_PER; ++u) {
-      const int e = threadIdx.x + 256 * u, q = e / ld, i = e - q * ld, kk = kbase + q;
-      t[u] = (e < tot && kk < nref && i > kk && i < n) ? W.H[(size_t)kk * N + i] : 0.0;
-    }
     const double tv = threadIdx.x < nr && kbase + (int)threadIdx.x < nref ? W.tau[kbase + threadIdx.x] : 0.0;
+    for (int u0 = 0; u0 < ORM_PER; u0 += ORM_BATCH) {
+      if (256 * u0 >= tot) break;
+      double t[ORM_BATCH];
 #pragma unroll
-    for (int u = 0; u < ORM_PER; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < tot) hs[e] = t[u];
+      for (int u = 0; u < ORM_BATCH; ++u) {
+        const int e = threadIdx.x + 256 * (u0 + u), q = e / ld, i = e - q * ld, kk = kbase + q;
+        t[u] = (e < tot && kk < nref && i > kk && i < n) ? W.H[(size_t)kk * N + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < ORM_BATCH; ++u) {
+        const int e = threadIdx.x + 256 * (u0 + u);
+        if (e < tot) hs[e] = t[u];
+      }
     }
     if (threadIdx.x < nr) taus[threadIdx.x] = tv;
     __syncthreads();
@@ -1819,47 +1838,64 @@ __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ d
       }
     }
     __syncthreads();
-    if (!active) continue;
+    if (!any) continue;
     for (int gq = g1 - g0; gq >= 0; --gq) {
       const double* v = hs + (size_t)(ORM_G * gq) * ld;
       const int kb = kbase + ORM_G * gq;
-      double vv[ORM_G][NCH];
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      // one vector: the group's rows stay in registers for the update; more:
+      // they are read from LDS again (registers hold the vectors)
+      constexpr bool KEEP = VPW == 1;
+      double vv[ORM_G][KEEP ? NCH : 1];
+      double sv[VPW][ORM_G];
+#pragma unroll
+      for (int w = 0; w < VPW; ++w)
+#pragma unroll
+        for (int q = 0; q < ORM_G; ++q) sv[w][q] = 0.0;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
+        const int ck = KEEP ? c : 0;
 #pragma unroll
-        for (int q = 0; q < ORM_G; ++q) vv[q][c] = 0.0;
+        for (int q = 0; q < ORM_G; ++q) vv[q][ck] = 0.0;
         if (64 * c >= n || 64 * c + 63 <= kb) continue;  // no rows of the group here
         const int i = lane + 64 * c;
 #pragma unroll
-        for (int q = 0; q < ORM_G; ++q) vv[q][c] = v[(size_t)q * ld + i];
-        s0 = fma(vv[0][c], y[c], s0);
-        s1 = fma(vv[1][c], y[c], s1);
-        s2 = fma(vv[2][c], y[c], s2);
-        s3 = fma(vv[3][c], y[c], s3);
-      }
-      s0 = wave_sum(s0);
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
-      s3 = wave_sum(s3);
-      const double* T = Ts + gq * 16;
-      const double u0 = ((T[0] * s0 + T[1] * s1) + T[2] * s2) + T[3] * s3;
-      const double u1 = (T[5] * s1 + T[6] * s2) + T[7] * s3;
-      const double u2 = T[10] * s2 + T[11] * s3;
-      const double u3 = T[15] * s3;
+        for (int q = 0; q < ORM_G; ++q) vv[q][ck] = v[(size_t)q * ld + i];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        if (64 * c >= n || 64 * c + 63 <= kb) continue;
-        y[c] -= ((vv[0][c] * u0 + vv[1][c] * u1) + vv[2][c] * u2) + vv[3][c] * u3;
+        for (int w = 0; w < VPW; ++w)
+#pragma unroll
+          for (int q = 0; q < ORM_G; ++q) sv[w][q] = fma(vv[q][ck], y[w][c], sv[w][q]);
+      }
+      const double* T = Ts + gq * 16;
+#pragma unroll
+      for (int w = 0; w < VPW; ++w) {
+        const double s0 = wave_sum(sv[w][0]), s1 = wave_sum(sv[w][1]);
+        const double s2 = wave_sum(sv[w][2]), s3 = wave_sum(sv[w][3]);
+        const double u0 = ((T[0] * s0 + T[1] * s1) + T[2] * s2) + T[3] * s3;
+        const double u1 = (T[5] * s1 + T[6] * s2) + T[7] * s3;
+        const double u2 = T[10] * s2 + T[11] * s3;
+        const double u3 = T[15] * s3;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          if (64 * c >= n || 64 * c + 63 <= kb) continue;
+          const int i = lane + 64 * c;
+          const double a0 = KEEP ? vv[0][KEEP ? c : 0] : v[i];
+          const double a1 = KEEP ? vv[1][KEEP ? c : 0] : v[(size_t)ld + i];
+          const double a2 = KEEP ? vv[2][KEEP ? c : 0] : v[2 * (size_t)ld + i];
+          const double a3 = KEEP ? vv[3][KEEP ? c : 0] : v[3 * (size_t)ld + i];
+          y[w][c] -= ((a0 * u0 + a1 * u1) + a2 * u2) + a3 * u3;
+        }
       }
     }
   }
-  if (!active) return;
-  const int col = n - 1 - j;
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    const int i = lane + 64 * c;
-    if (i < n) J.V[(size_t)i * J.ldv + col] = y[c];
+  for (int w = 0; w < VPW; ++w) {
+    if (!active[w]) continue;
+    const int col = n - 1 - (j0 + 4 * w + wave);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int i = lane + 64 * c;
+      if (i < n) J.V[(size_t)i * J.ldv + col] = y[w][c];
+    }
   }
 }
 
@@ -2670,7 +2706,7 @@ size_t eig_lds_bytes(int N, bool runtime, const char** which) {
     lds_note(static_lds((const void*)k_sytrd_grid, ST_SYTRD_GRID, runtime) + sytrd_grid_lds(N),
              "k_sytrd_grid", worst, which);
   dc_lds(N, runtime, worst, which);
-  lds_note(static_lds((const void*)k_ormtr<16>, ST_ORMTR, runtime) + ormtr_lds_doubles(N) * 8,
+  lds_note(static_lds((const void*)k_ormtr<16, 4>, ST_ORMTR, runtime) + ormtr_lds_doubles(N) * 8,
            "k_ormtr", worst, which);
   return worst;
 }
@@ -2714,12 +2750,12 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
   }
   dc_solve(J, njobs < 4 ? njobs : 4, N, dims, s);
   {
-    const dim3 g((N + 3) / 4, njobs);
+    const dim3 g((N + 3) / 4, njobs), g4((N + 15) / 16, njobs);
     const size_t lds = ormtr_lds_doubles(N) * 8;
-    if (N <= 192) k_ormtr<3><<<g, 256, lds, s>>>(J, dims, N);
-    else if (N <= 384) k_ormtr<6><<<g, 256, lds, s>>>(J, dims, N);
-    else if (N <= 640) k_ormtr<10><<<g, 256, lds, s>>>(J, dims, N);
-    else k_ormtr<16><<<g, 256, lds, s>>>(J, dims, N);
+    if (N <= 192) k_ormtr<3, 1><<<g, 256, lds, s>>>(J, dims, N);
+    else if (N <= 384) k_ormtr<6, 1><<<g, 256, lds, s>>>(J, dims, N);
+    else if (N <= 640) k_ormtr<10, 4><<<g4, 256, lds, s>>>(J, dims, N);
+    else k_ormtr<16, 4><<<g4, 256, lds, s>>>(J, dims, N);
   }
   k_eig_final<<<dim3((N + FINAL_COLS - 1) / FINAL_COLS, njobs), 256, 0, s>>>(J, dims, N);
 }
