@@ -1740,9 +1740,10 @@ __host__ __device__ inline size_t ormtr_lds_doubles(int N) {
 }
 
 // VPW vectors per wavefront (4 VPW per block): every block stages all the
-// reflectors, so at large orders, where the blocks outnumber the CUs and the
-// staging traffic (blocks x reflector bytes) bounds the launch, each
-// wavefront carries several vectors through the same staged chunks.
+// reflectors, so at large orders (capacity above 640), where the blocks
+// outnumber the CUs and the staging traffic (blocks x reflector bytes) bounds
+// the launch, each wavefront carries four vectors through the same staged
+// chunks; below that one vector a wavefront is faster.
 template <int NCH, int VPW>
 __global__ __launch_bounds__(256) void k_ormtr(EigJobs jobs, int* __restrict__ dims, int N) {
   const EigJob J = jobs.j[blockIdx.y];
@@ -2754,7 +2755,7 @@ void eig_batched(const EigJob* jobs, int njobs, int N, int* dims, hipStream_t s)
     const size_t lds = ormtr_lds_doubles(N) * 8;
     if (N <= 192) k_ormtr<3, 1><<<g, 256, lds, s>>>(J, dims, N);
     else if (N <= 384) k_ormtr<6, 1><<<g, 256, lds, s>>>(J, dims, N);
-    else if (N <= 640) k_ormtr<10, 4><<<g4, 256, lds, s>>>(J, dims, N);
+    else if (N <= 640) k_ormtr<10, 1><<<g, 256, lds, s>>>(J, dims, N);
     else k_ormtr<16, 4><<<g4, 256, lds, s>>>(J, dims, N);
   }
   k_eig_final<<<dim3((N + FINAL_COLS - 1) / FINAL_COLS, njobs), 256, 0, s>>>(J, dims, N);

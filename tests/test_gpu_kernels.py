@@ -117,7 +117,8 @@ def _eig_case(kind, n, rng):
 
 
 @pytest.mark.parametrize("kind", ["random", "gram", "cluster", "lowrank"])
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 31, 62, 63, 64, 65, 100, 142, 160, 161, 175, 181, 322, 641, 897, 1024])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 31, 62, 63, 64, 65, 100, 142, 160, 161, 175, 181, 322, 400, 600,
+                               641, 897, 1024])
 def test_eigh(env, kind, n):
     lib, torch = env
     rng = np.random.default_rng(n + len(kind))
