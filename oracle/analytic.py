@@ -14,6 +14,11 @@ gives it in closed form as J = J_left + J_bottom, with
     eta_x = acos(min(y / sqrt((c t)^2 - x^2), 1)),
 
 J_left = 0 for x >= c t, and J_bottom the same with x and y exchanged.
+
+Line source (Sec. 5.4): a pulse U0 delta(x, y) of radiation energy in
+vacuum spreads as E(t, r) = U0 H(c t - r) / (2 pi c t sqrt((c t)^2 - r^2)),
+whose integral over the plane is U0 at every t (total energy is conserved);
+the smoothed initial condition is the Gaussian of width omega.
 """
 import numpy as np
 
@@ -37,3 +42,14 @@ def _hohlraum_wall(t, a, b, c):
 def hohlraum_J(t, x, y, c=1.0):
     """Analytic mean intensity of the hohlraum problem (Sec. 5.1)."""
     return _hohlraum_wall(t, x, y, c) + _hohlraum_wall(t, y, x, c)
+
+
+def line_source_E(t, r, U0=1.0, c=1.0):
+    """Energy density of the vacuum line source from a delta pulse (Sec. 5.4);
+    zero outside the front r >= c t (the front itself is singular)."""
+    r = np.asarray(r, dtype=float)
+    ct = c * t
+    out = np.zeros(r.shape)
+    m = r < ct
+    out[m] = U0 / (2.0 * np.pi * ct * np.sqrt(ct * ct - r[m] ** 2))
+    return out

@@ -1,5 +1,5 @@
-"""Reduced-size analytic validation: the hohlraum (Sec. 5.1) through the C
-ABI.
+"""Reduced-size analytic validations through the C ABI: the hohlraum
+(Sec. 5.1) and the line source's energy conservation (Sec. 5.4).
 
 Isotropic inflow I = 1 through the x-lo and y-lo faces into vacuum; the
 mean intensity J = c E / (4 pi) at t = 0.75 is compared over the cells of
@@ -15,6 +15,16 @@ in test_oracle_pins.py), as an area-weighted L1 error.
 - 64^2, 128^2, 256^2 cells, 32 x 64 ordinates, rank cap 160: the L1 error
   falls at first order in the cell size (the scheme is first order in
   space, Sec. 5.1).
+
+Line source: an isotropic Gaussian pulse (width 0.03, U0 = 1) in vacuum on
+[-1.1, 1.1]^2, run to t = 0.5 so that the front stays inside the domain and
+the upwind scheme moves energy only between cells: what the total loses is
+what the roundings drop.  Sec. 5.4 reports conservation errors of 8e-5 U0
+(tolerance 1e-4) and 2e-4 U0 (tolerance 1e-3) for its full run.
+- 64^2 cells, 16 x 32 ordinates, both tolerances: the library's total energy
+  after every step against the TT oracle's (parity), both under those
+  figures.
+- 256^2 cells, 16 x 32 ordinates, both tolerances: under those figures.
 """
 import sys
 
@@ -92,3 +102,61 @@ def test_hohlraum_first_order_convergence():
     assert l1[0] < 1e-2
     assert l1[1] < 0.65 * l1[0]
     assert l1[2] < 0.65 * l1[1]
+
+
+def _total(E, p):
+    return float(np.sum(E)) * (p["lx"] / p["nx"]) * (p["ly"] / p["ny"])
+
+
+@pytest.mark.parametrize("tol,paper", [(1e-4, 8e-5), (1e-3, 2e-4)])
+def test_line_source_conservation_vs_oracle(tol, paper):
+    p = wl.line_source(n=64, ntheta=16, nphi=32, tol=tol, rmax=200)
+    nsteps = p["steps"]
+    _log(f"line source 64^2 16x32 tol {tol}: {nsteps} steps")
+    s = Setup(p)
+    E0 = _total(tt.energy(p["X0"], p["Th0"], p["Ph0"], s), p)
+    def run_gpu(**kw):
+        st = _state(p, max_steps=nsteps, **kw)
+        if kw:
+            st.tt_set_rank_schedule(hist)
+        e = []
+        for _ in range(nsteps):
+            st.step(1)
+            e.append(_total(st.tt_energy()[0].cpu().numpy(), p))
+        return st, np.array(e)
+
+    eo = []
+    _, _, hist = tt.run(s, nsteps, callback=lambda m, c, T, i: eo.append(_total(tt.energy(*c, s), p)))
+    eo = np.array(eo)
+    st, eg = run_gpu()
+    cg, co = np.max(np.abs(eg - E0)), np.max(np.abs(eo - E0))
+    same = st.tt_get_rank_history() == hist
+    _log(f"  ranks gpu {st.tt_get_rank_history()[-1]} oracle {hist[-1]} identical {same}; conservation "
+         f"error gpu {cg:.3e} oracle {co:.3e}; totals differ by {np.max(np.abs(eg - eo)):.2e}")
+    if not same:
+        # a near-tie at some cut: the same map with the oracle's ranks replayed
+        from paper_2503_18056_amd import TT_RANK_REPLAY
+        _, er = run_gpu(rank_mode=TT_RANK_REPLAY)
+        _log(f"  replayed ranks: totals differ by {np.max(np.abs(er - eo)):.2e}")
+    else:
+        er = eg
+    # unpinned (Gram floor): each rounding drops, to within the Gram route's
+    # floor, the same part of the spectrum on both sides; measured 3.5e-9 of
+    # U0 at tolerance 1e-4 against conservation errors near 2e-8
+    assert np.max(np.abs(er - eo)) < 1e-7
+    assert cg < 10 * co + 1e-8
+    assert cg < paper
+
+
+def test_line_source_256_conservation():
+    for tol, paper in ((1e-4, 8e-5), (1e-3, 2e-4)):
+        p = wl.line_source(n=256, ntheta=16, nphi=32, tol=tol, rmax=204)
+        _log(f"line source 256^2 16x32 tol {tol}: {p['steps']} steps")
+        s = Setup(p)
+        E0 = _total(tt.energy(p["X0"], p["Th0"], p["Ph0"], s), p)
+        st = _state(p, max_steps=p["steps"])
+        st.step(p["steps"])
+        err = abs(_total(st.tt_energy()[0].cpu().numpy(), p) - E0)
+        _log(f"  ranks {st.tt_get_rank_history()[-1]} (cap 204), conservation error {err:.3e} "
+             f"(Sec. 5.4: {paper:.0e} for its full run)")
+        assert err < paper

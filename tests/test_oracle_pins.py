@@ -702,3 +702,33 @@ def test_hohlraum_full_grid_first_order():
         errs.append(np.abs(J[:m, :m] - Ja[:m, :m]).sum() * (2.0 / n) ** 2)
     assert errs[0] < 2e-2
     assert errs[1] < 0.65 * errs[0]
+
+
+# --------------------------------------------------------------- line source
+def test_line_source_analytic_integrates_to_U0():
+    """The delta-pulse solution of Sec. 5.4 carries U0 at every time: its
+    integral over the plane, 2 pi int_0^{ct} E r dr, by a substitution that
+    removes the front's singularity (r = c t sin(a))."""
+    from oracle.analytic import line_source_E
+    for t, U0 in ((0.3, 1.0), (1.0, 2.5)):
+        a = (np.arange(20000) + 0.5) * (0.5 * np.pi / 20000)
+        r = t * np.sin(a)
+        integrand = 2 * np.pi * line_source_E(t, r, U0) * r * t * np.cos(a)
+        assert abs(integrand.sum() * (0.5 * np.pi / 20000) - U0) < 1e-8 * U0
+    assert line_source_E(0.5, 0.6) == 0.0
+
+
+def test_line_source_full_grid_conserves_energy():
+    """The upwind finite-volume step moves energy between cells only: with the
+    pulse and its front inside the domain (vacuum, no opacity), the full-grid
+    oracle keeps sum_i E_i dA to rounding, and the TT oracle at a tolerance
+    far below the state's spectrum does too."""
+    p = wl.line_source(n=32, ntheta=8, nphi=16, t_end=0.25, tol=1e-13, rmax=0)
+    s = Setup(p)
+    dA = (p["lx"] / p["nx"]) ** 2
+    I0 = full.initial_intensity(s)
+    E0 = full.energy(I0, s).sum() * dA
+    I, _ = full.run(s, p["steps"], I=I0)
+    assert abs(full.energy(I, s).sum() * dA - E0) < 1e-12 * E0
+    (X, Th, Ph), _, _ = tt.run(s, p["steps"])
+    assert abs(tt.energy(X, Th, Ph, s).sum() * dA - E0) < 1e-10 * E0

@@ -340,6 +340,24 @@ def hohlraum(n=64, ntheta=16, nphi=32, tol=1e-4, rmax=0, t_end=0.75):
     return p
 
 
+def line_source(n=64, ntheta=16, nphi=32, tol=1e-4, rmax=200, t_end=0.5, omega=0.03, U0=1.0):
+    """Line source (Sec. 5.4) at reduced size: domain [-1.1, 1.1]^2 (extent
+    2.2, the pulse at its centre), vacuum everywhere, no opacity or emission,
+    CFL 0.4, an isotropic Gaussian pulse of width omega carrying U0 (rank
+    (1, 1)).  t_end = 0.5 keeps the front (and the upwind scheme's smearing
+    of it) inside the domain, so the energy leaves only through truncation."""
+    p = _base(2, n, n, 1, ntheta, nphi, tol=tol, rmax=rmax, steps=0, l=2.2)
+    p["cfl"] = 0.4
+    p["kappa"][:] = 0.0
+    p["T0"][:] = 0.0
+    p["X0"], p["Th0"], p["Ph0"] = gaussian_pulse_cores(p, sigma=omega, U0=U0)
+    dt = p["cfl"] * (2.2 / n) / p["c"]
+    p["steps"] = int(round(t_end / dt))
+    p["line_source"] = dict(U0=U0, omega=omega, t=p["steps"] * dt)
+    p["name"] = f"line_source_{n}sq_{ntheta}x{nphi}"
+    return p
+
+
 def rounding_bench_cores(p, r1=64, r2=12, seed=2, decades_per_8=1.0):
     """Seeded synthetic state on the crossing-beam shape for the rounding
     benchmark: orthonormal X (N_s x r1), orthonormal Phi rows (r2 x N_phi)
