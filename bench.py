@@ -189,7 +189,7 @@ def measured_peaks():
 
 
 def phase_roofline(prof, ranks, nsteps, ns, nbc, peaks):
-    """Per-phase roofline of the crossing-beam step (SURVEY 8(d) reading):
+    """Per-phase roofline of the crossing-beam step:
     concat HBM-bound (read X, write X_cat), Gram and X update max(MFMA,
     HBM), the rank-sized products and eigensolves latency-bound (their
     measured time is their roofline time).  ``ranks``: (r1, r2) entering
