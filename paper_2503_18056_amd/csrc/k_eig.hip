@@ -2199,8 +2199,7 @@ __global__ __launch_bounds__(JAC_T) void k_svd_jacobi(const double* __restrict__
 // matrix fits one block's LDS, else k_gebrd_grid.
 //
 // k_gebrd_grid: P blocks, each holding the rows i = b (mod P) in LDS (row
-// stride q), with one
-// grid barrier per step.  The left reflector of column k is
+// stride q), with one grid barrier per step.  The left reflector of column k is
 // u = e_k + s_L c, c = A(k+1:, k), and its product with the trailing matrix is
 // y = tau_L (A(k, k+1:) + s_L sum_{i > k} A(i, k) A(i, k+1:)): each block can
 // form its share of that sum, and of |c|^2, from its own rows before the
