@@ -278,3 +278,31 @@ def round_ttsvd(X, Th, Ph, tol, rmax, eta=ETA_FP64):
     U2, sg2 = gauge(U2[:, :b])
     C2 = (S2[:b, None] * V2[:b]) * sg2[:, None]
     return Uu, U2.reshape(a, nt, b), C2 @ Ph_o
+
+
+def round_randomized(X, Th, Ph, omegas):
+    """Randomized TT rounding to fixed target ranks (App. A.3, eqs.
+    randfinal and randprojection), over the two bonds from left to right.
+
+    Bond k holds the TT as A_k B_k^T: A_1 = X, B_1^T = (Theta x Phi) unfolded
+    to r1 x (N_theta N_phi); A_2 = the updated middle core unfolded to
+    (r1' N_theta) x r2, B_2^T = Phi.  ``omegas`` = (Omega_1, Omega_2) are the
+    Gaussian test matrices, (N_theta N_phi) x r1' and N_phi x r2', drawn by
+    the caller; their column counts are the target ranks.  W = B_k^T Omega_k
+    (r_k x r'_k) is the sketch formed from the small factor, and Q, with
+    Q R = A_k W, an orthonormal basis of the sketched range A_k B_k^T Omega_k
+    (reading: the text names the QR "of W", which for Q to have A_k's rows
+    can only mean of A_k W).  Then A_k' = Q and M_upd = Q^T A_k, carried
+    into the next core (B_k'^T = M_upd B_k^T).  The left factors come out
+    with orthonormal columns.
+    """
+    O1, O2 = omegas
+    r1, nt, r2 = Th.shape
+    npf = Ph.shape[1]
+    B1T = (Th.reshape(r1 * nt, r2) @ Ph).reshape(r1, nt * npf)
+    Q1, _ = np.linalg.qr(X @ (B1T @ O1))
+    M1 = Q1.T @ X
+    A2 = (M1 @ Th.reshape(r1, nt * r2)).reshape(-1, r2)
+    Q2, _ = np.linalg.qr(A2 @ (Ph @ O2))
+    M2 = Q2.T @ A2
+    return Q1, Q2.reshape(Q1.shape[1], nt, Q2.shape[1]), M2 @ Ph

@@ -732,3 +732,69 @@ def test_line_source_full_grid_conserves_energy():
     assert abs(full.energy(I, s).sum() * dA - E0) < 1e-12 * E0
     (X, Th, Ph), _, _ = tt.run(s, p["steps"])
     assert abs(tt.energy(X, Th, Ph, s).sum() * dA - E0) < 1e-10 * E0
+
+
+# ------------------------------------------------------- randomized rounding
+def test_randomized_rounding_exact_on_low_rank():
+    """A TT whose bond ranks exceed the tensor's (the concatenation of a
+    rank-(3, 2) TT with twice itself: ranks (6, 4), tensor 3 X Theta Phi) is
+    reproduced to rounding by randomized rounding at the true ranks (App. A.3),
+    and both left factors come out with orthonormal columns."""
+    rng = np.random.default_rng(11)
+    ns, nt, npf = 40, 6, 8
+    X = rng.standard_normal((ns, 3))
+    Th = rng.standard_normal((3, nt, 2))
+    Ph = rng.standard_normal((2, npf))
+    Xc = np.hstack([X, 2.0 * X])
+    Thc = np.zeros((6, nt, 4))
+    Thc[:3, :, :2] = Th
+    Thc[3:, :, 2:] = Th
+    Phc = np.vstack([Ph, Ph])
+    T = 3.0 * metrics.reconstruct(X, Th, Ph)
+    Xr, Thr, Phr = rounding.round_randomized(Xc, Thc, Phc, wl.gaussian_test_matrices(nt, npf, 3, 2, 5))
+    assert Xr.shape == (ns, 3) and Thr.shape == (3, nt, 2) and Phr.shape == (2, npf)
+    R = metrics.reconstruct(Xr, Thr, Phr)
+    assert np.linalg.norm(R - T) < 1e-12 * np.linalg.norm(T)
+    assert np.abs(Xr.T @ Xr - np.eye(3)).max() < 1e-13
+    A2 = Thr.reshape(3 * nt, 2)
+    assert np.abs(A2.T @ A2 - np.eye(2)).max() < 1e-13
+
+
+@pytest.mark.parametrize("decay_in", ["X", "Theta"])
+def test_randomized_rounding_expected_error_bound(decay_in):
+    """Bond 1 with oversampling (target k + p, k = 6, p = 4; bond 2 kept at
+    its full rank, which the sketch reproduces exactly): over 40 seeds the
+    mean Frobenius error is within the expected-error bound of a Gaussian
+    sketch, sqrt(1 + k / (p - 1)) times the optimal rank-k error (Halko,
+    Martinsson and Tropp, SIAM Review 2011, Thm. 10.5), and no trial beats
+    the optimal rank-(k + p) error (Eckart-Young).  The spectrum's decay is
+    put in X or in Theta: with it in Theta, a sketch of X alone (without
+    B^T Omega) would miss the dominant directions."""
+    rng = np.random.default_rng(12)
+    ns, nt, npf, r1, r2 = 60, 8, 16, 24, 4
+    U, _ = np.linalg.qr(rng.standard_normal((ns, r1)))
+    s = 0.7 ** np.arange(r1)
+    # Theta unfolded (r1 x nt r2) and Phi with orthonormal rows, and the
+    # weights s on X's columns or on Theta's rows: the bond-1 singular values
+    # of the tensor are exactly s either way
+    Qt, _ = np.linalg.qr(rng.standard_normal((nt * r2, r1)))
+    if decay_in == "X":
+        X = U * s
+        Th = Qt.T.reshape(r1, nt, r2)
+    else:
+        X = U
+        Th = (s[:, None] * Qt.T).reshape(r1, nt, r2)
+    Qp, _ = np.linalg.qr(rng.standard_normal((npf, r2)))
+    Ph = Qp.T
+    T1 = metrics.reconstruct(X, Th, Ph).reshape(ns, nt * npf)
+    assert np.allclose(np.linalg.svd(T1, compute_uv=False)[:r1], s, rtol=0, atol=1e-13)
+    k, p = 6, 4
+    tail = lambda j: np.sqrt(np.sum(s[j:] ** 2))
+    errs = []
+    for seed in range(40):
+        Xr, Thr, Phr = rounding.round_randomized(X, Th, Ph,
+                                                 wl.gaussian_test_matrices(nt, npf, k + p, r2, 100 + seed))
+        errs.append(np.linalg.norm(metrics.reconstruct(Xr, Thr, Phr).reshape(ns, -1) - T1))
+    errs = np.array(errs)
+    assert errs.mean() <= np.sqrt(1 + k / (p - 1)) * tail(k)
+    assert errs.min() >= tail(k + p) * (1 - 1e-10)

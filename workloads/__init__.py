@@ -375,3 +375,11 @@ def rounding_bench_cores(p, r1=64, r2=12, seed=2, decades_per_8=1.0):
     s = 10.0 ** (-np.arange(r1) * decades_per_8 / 8.0)
     Th = (s[:, None] * Q).reshape(r1, nt, r2)
     return X, Th, Ph
+
+
+def gaussian_test_matrices(ntheta, nphi, r1t, r2t, seed):
+    """Seeded standard Gaussian test matrices for randomized rounding: Omega_1
+    of shape (ntheta nphi, r1t) and Omega_2 of shape (nphi, r2t)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((ntheta * nphi, r1t)), rng.standard_normal((nphi, r2t))
+
