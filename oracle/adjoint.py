@@ -13,7 +13,7 @@ backward and forward neighbours (the transposed stencil).
 import numpy as np
 
 from . import full
-from .setup import PERIODIC
+from .setup import PERIODIC, UPWIND
 
 
 def _shift_zero(J, setup, axis, direction):
@@ -67,8 +67,10 @@ def _with_kappa(setup, kappa):
 
 
 def grad_full(setup, nsteps, detector):
-    """(L, dL/dkappa) by the discrete adjoint (frozen temperature)."""
+    """(L, dL/dkappa) by the discrete adjoint (frozen temperature, upwind
+    flux: with the HLL flux kappa would also enter the face weights)."""
     assert setup.material == 0
+    assert setup.flux == UPWIND
     c, dt, a_r = setup.c, setup.dt, setup.a_r
     shp = setup.grid_shape() + (1, 1)
     I = full.initial_intensity(setup)

@@ -10,6 +10,9 @@ interface flux of the workload:
     - (S+ / 2)(I_{i+1} - I_i), so
     I*_i = I_i - sum_a lam_a [ (n_a / 2)(I_{i+e_a} - I_{i-e_a})
                               - (S+ / 2c)(I_{i+e_a} - 2 I_i + I_{i-e_a}) ],
+  HLL (eq. hll with the wavespeeds of Sec. 3.1 and tau_c of eq. tauc):
+    F_{i+1/2} = c n (alpha I_i + beta I_{i+1}) with per-face weights (see
+    Setup.hll_weights), I*_i = I_i - sum_a lam_a (F_{i+1/2} - F_{i-1/2}) / c,
 lam_a = c dt / Delta_a, n^+ = max(n, 0), n^- = min(n, 0).  Ghost values
 (Sec. 4.5): vacuum 0, periodic wrap, inflow (Dirichlet) a prescribed value
 g = face_w (x) theta_w (x) phi_w on the face, outflow the adjacent interior
@@ -22,7 +25,7 @@ Source step: I^{m+1} = d I* + s (see ``material``).
 import numpy as np
 
 from . import material as mat
-from .setup import PERIODIC, INFLOW, OUTFLOW, RUSANOV
+from .setup import PERIODIC, INFLOW, OUTFLOW, RUSANOV, HLL
 
 
 def _ghost(setup, face, like_slice):
@@ -67,6 +70,17 @@ def transport(I, setup):
         if setup.flux == RUSANOV:
             out -= setup.lam[a] * (0.5 * n * (Ip - Im)
                                    - 0.5 * setup.s_plus * (Ip - 2.0 * I + Im))
+        elif setup.flux == HLL:
+            # eq. hll: F_{i+1/2} / c = n (alpha U_i + beta U_{i+1}), weights per
+            # sign of n from the face's optical depth (Setup.hll_weights)
+            shp = setup.grid_shape() + (1, 1)
+            hi, lo = setup.hll_face_weights(a)
+            ap, bp, am, bm = (w.reshape(shp) for w in hi)
+            apl, bpl, aml, bml = (w.reshape(shp) for w in lo)
+            npos, nneg = np.maximum(n, 0.0), np.minimum(n, 0.0)
+            f_hi = npos * (ap * I + bp * Ip) + nneg * (am * I + bm * Ip)
+            f_lo = npos * (apl * Im + bpl * I) + nneg * (aml * Im + bml * I)
+            out -= setup.lam[a] * (f_hi - f_lo)
         else:
             npos, nneg = np.maximum(n, 0.0), np.minimum(n, 0.0)
             out -= setup.lam[a] * (npos * (I - Im) + nneg * (Ip - I))

@@ -16,7 +16,7 @@ import numpy as np
 from . import quadrature
 
 VACUUM, PERIODIC, INFLOW, OUTFLOW = 0, 1, 2, 3
-UPWIND, RUSANOV = "upwind", "rusanov"
+UPWIND, RUSANOV, HLL = "upwind", "rusanov", "hll"
 FROZEN, COUPLED = 0, 1
 
 
@@ -48,9 +48,11 @@ class Setup:
         self.T0 = np.asarray(p["T0"], dtype=np.float64).copy()
         self.kappa_s = np.asarray(p.get("kappa_s", np.zeros(self.ns)), dtype=np.float64).copy()
         self.flux = p.get("flux", UPWIND)
-        if self.flux not in (UPWIND, RUSANOV):
-            raise ValueError("flux must be 'upwind' or 'rusanov'")
+        if self.flux not in (UPWIND, RUSANOV, HLL):
+            raise ValueError("flux must be 'upwind', 'rusanov' or 'hll'")
         self.s_plus = float(p.get("s_plus", 1.0))
+        self.hll_beta = float(p.get("hll_beta", 1.0))
+        self.hll_threshold = float(p.get("hll_tau_threshold", 1e-2))
         self.inflow = [(int(f), np.asarray(fw, float), np.asarray(tw, float),
                         np.asarray(pw, float)) for (f, fw, tw, pw) in p["inflow"]]
         self.mu, self.w, self.phi, self.v = quadrature.ordinates(self.nt, self.np_)
@@ -86,3 +88,66 @@ class Setup:
             return (ix[None, :] + nx * (y + ny * iz[:, None])).reshape(-1)
         z = nz - 1 if hi else 0
         return (ix[None, :] + nx * (iy[:, None] + ny * z)).reshape(-1)
+
+    # ---- HLL flux (Sec. 3.1, eqs. hll and tauc) --------------------------
+    def hll_tau(self, axis):
+        """Optical depth tau_c at the hi face (i + 1/2 along ``axis``) of every
+        cell, flattened: 2 beta Delta / (1/(rho k)_i + 1/(rho k)_{i+1}) with k
+        the absorption plus scattering opacity (eq. tauc; reading: the second
+        term is cell i+1's, the printed rho_i in both taken as a slip).  A
+        face on a non-periodic boundary takes the interior cell's extinction
+        on both sides (beta Delta (rho k)_i); zero extinction gives tau = 0."""
+        ext = (self.rho * (self.kappa + self.kappa_s)).reshape(self.grid_shape())
+        ax = 2 - axis
+        nxt = np.roll(ext, -1, axis=ax)
+        if self.bc_hi[axis] != PERIODIC:
+            sl = [slice(None)] * 3
+            sl[ax] = -1
+            nxt[tuple(sl)] = ext[tuple(sl)]
+        with np.errstate(divide="ignore"):
+            inv = 1.0 / ext + 1.0 / nxt
+        tau = np.where(np.isfinite(inv), 2.0 * self.hll_beta * self.spacing[axis] / inv, 0.0)
+        return tau.reshape(-1)
+
+    def hll_weights(self, tau):
+        """Weights of the HLL face flux F = c n (alpha U_L + beta U_R) for n >= 0
+        (alpha_p, beta_p) and n < 0 (alpha_m, beta_m).  With the wavespeeds of
+        Sec. 3.1 written S_R = c n A, S_L = -c n B for n >= 0 and S_R = -c n B,
+        S_L = c n A for n < 0, where A = sqrt((1 - exp(-tau^2)) / tau^2) and
+        B = sqrt((1 - exp(-tau^4)) / tau^2) (their expansions sqrt(1 - tau^2/2)
+        and tau below the threshold), eq. hll with F_{L,R} = c n U_{L,R} gives
+        alpha_p = A (1 + B) / (A + B), beta_p = B (1 - A) / (A + B), and the
+        n < 0 pair swapped: alpha_m = beta_p, beta_m = alpha_p.  tau -> 0 is
+        the upwind flux (alpha_p = beta_m = 1); large tau the Rusanov flux
+        with S+ = c |n| / tau."""
+        tau = np.asarray(tau, dtype=float)
+        small = tau < self.hll_threshold
+        with np.errstate(divide="ignore", invalid="ignore"):
+            A = np.where(small, np.sqrt(np.maximum(1.0 - 0.5 * tau * tau, 0.0)),
+                         np.sqrt((1.0 - np.exp(-tau * tau)) / (tau * tau)))
+            B = np.where(small, tau, np.sqrt((1.0 - np.exp(-tau ** 4)) / (tau * tau)))
+        ap = A * (1.0 + B) / (A + B)
+        bp = B * (1.0 - A) / (A + B)
+        return ap, bp, bp, ap
+
+    def hll_face_weights(self, axis):
+        """(alpha_p, beta_p, alpha_m, beta_m) at every cell's hi face and at its
+        lo face (the hi face of the cell before it, or the boundary face),
+        flattened over cells."""
+        hi = self.hll_weights(self.hll_tau(axis))
+        ax = 2 - axis
+        lo = []
+        # the lo face of a cell: the previous cell's hi face; at a
+        # non-periodic lo boundary the face takes the cell's own extinction
+        ext = (self.rho * (self.kappa + self.kappa_s)).reshape(self.grid_shape())
+        tb = (self.hll_beta * self.spacing[axis] * ext).reshape(-1)
+        wb = self.hll_weights(tb)
+        for h, b in zip(hi, wb):
+            g = np.roll(h.reshape(self.grid_shape()), 1, axis=ax)
+            if self.bc_lo[axis] != PERIODIC:
+                sl = [slice(None)] * 3
+                sl[ax] = 0
+                g[tuple(sl)] = b.reshape(self.grid_shape())[tuple(sl)]
+            lo.append(g.reshape(-1))
+        return hi, tuple(lo)
+

@@ -43,7 +43,7 @@ import numpy as np
 
 from . import material as mat
 from . import rounding
-from .setup import PERIODIC, OUTFLOW, RUSANOV
+from .setup import PERIODIC, OUTFLOW, RUSANOV, HLL
 
 
 def shift(X, setup, axis, direction):
@@ -61,13 +61,32 @@ def shift(X, setup, axis, direction):
     return S.reshape(-1, r)
 
 
+def _signed_factors(tf, pf, a):
+    """(theta, phi) factors of n^+ = max(n, 0) and n^- = min(n, 0) on axis a:
+    for x and y the sign is the phi factor's (sin(theta) >= 0), for z the
+    theta factor's (mu)."""
+    if a < 2:
+        return (tf, np.maximum(pf, 0.0)), (tf, np.minimum(pf, 0.0))
+    return (np.maximum(tf, 0.0), pf), (np.minimum(tf, 0.0), pf)
+
+
 def transport_blocks(X, Th, Ph, setup):
     blocks = [(X, Th, Ph)]
     rus = setup.flux == RUSANOV
+    hll = setup.flux == HLL
     for a in range(setup.dim):
         tf, pf = setup.cosine_factors(a)
         lam = setup.lam[a]
         Xm, Xp = shift(X, setup, a, -1), shift(X, setup, a, +1)
+        if hll:
+            # one block per sign of n: the variable-weight stencil
+            # (alpha_hi - beta_lo) X_i + beta_hi X_{i+1} - alpha_lo X_{i-1}
+            (ap, bp, am, bm), (apl, bpl, aml, bml) = setup.hll_face_weights(a)
+            for (al_hi, be_hi, al_lo, be_lo), (ts, ps) in zip(
+                    ((ap, bp, apl, bpl), (am, bm, aml, bml)), _signed_factors(tf, pf, a)):
+                Y = (al_hi - be_lo)[:, None] * X + be_hi[:, None] * Xp - al_lo[:, None] * Xm
+                blocks.append((Y, Th * ts[None, :, None], Ph * (-lam * ps)[None, :]))
+            continue
         if rus:
             blocks.append((0.5 * (Xp - Xm), Th * tf[None, :, None], Ph * (-lam * pf)[None, :]))
             if setup.s_plus != 0.0:
@@ -87,6 +106,15 @@ def transport_blocks(X, Th, Ph, setup):
         lam = setup.lam[a]
         e = np.zeros(setup.ns)
         e[setup.face_cells(f)] = fw
+        if hll:
+            # the ghost value g enters F at the face: + lam n alpha_lo g on a lo
+            # face, - lam n beta_hi g on a hi face, one block per sign of n
+            (ap, bp, am, bm), (apl, bpl, aml, bml) = setup.hll_face_weights(a)
+            wts = (bp, bm) if hi else (apl, aml)
+            for w, (ts, ps) in zip(wts, _signed_factors(tf, pf, a)):
+                blocks.append(((e * w)[:, None], (ts * tw)[None, :, None],
+                               ((-lam if hi else lam) * ps * pw)[None, :]))
+            continue
         if rus:
             sgn = -1.0 if hi else 1.0
             blocks.append((e[:, None], (tf * tw)[None, :, None], (sgn * 0.5 * lam * pf * pw)[None, :]))

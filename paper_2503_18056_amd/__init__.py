@@ -51,7 +51,10 @@ def make_config(p, *, precision=TT_FP64, schedule=TT_ROUND_ONCE, rank_mode=TT_RA
     cfg.ckpt_every = ckpt_every
     cfg.max_steps = int(max_steps if max_steps is not None else max(p.get("steps", 1), 1))
     cfg.r1_cap, cfg.r2_cap = r1_cap, r2_cap
-    cfg.flux = TT_FLUX_RUSANOV if p.get("flux", "upwind") == "rusanov" else TT_FLUX_UPWIND
+    flux = p.get("flux", "upwind")
+    if flux not in ("upwind", "rusanov"):
+        raise NotImplementedError(f"flux {flux!r}: the library steps the upwind and Rusanov fluxes")
+    cfg.flux = TT_FLUX_RUSANOV if flux == "rusanov" else TT_FLUX_UPWIND
     cfg.s_plus = float(p.get("s_plus", 1.0))
     return cfg
 

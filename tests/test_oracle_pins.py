@@ -798,3 +798,136 @@ def test_randomized_rounding_expected_error_bound(decay_in):
     errs = np.array(errs)
     assert errs.mean() <= np.sqrt(1 + k / (p - 1)) * tail(k)
     assert errs.min() >= tail(k + p) * (1 - 1e-10)
+
+
+# ------------------------------------------------------------------ HLL flux
+def _hll_speeds(n, tau, c, thr):
+    """(S_L, S_R) of Sec. 3.1, case by case as printed."""
+    if tau >= thr:
+        a = np.sqrt((1.0 - np.exp(-tau ** 2)) / tau ** 2)
+        b = np.sqrt((1.0 - np.exp(-tau ** 4)) / tau ** 2)
+    else:
+        a = np.sqrt(1.0 - tau ** 2 / 2.0)
+        b = tau
+    if n >= 0:
+        return -c * n * b, c * n * a
+    return c * n * a, -c * n * b
+
+
+def test_hll_step_brute_force_from_the_wavespeeds():
+    """eq. hll evaluated face by face in plain loops, with the four-case
+    wavespeeds of Sec. 3.1 and the harmonic-mean tau_c of eq. tauc (cell
+    i+1's extinction in the second term), on a periodic line whose random
+    extinction puts faces on both sides of tau_threshold."""
+    rng = np.random.default_rng(7)
+    nx, beta = 10, 1.7
+    p = _line_problem(nx=nx)
+    p["flux"], p["hll_beta"] = "hll", beta
+    s0 = Setup(p)
+    p["rho"][:] = 0.5 + rng.random(nx)
+    p["kappa"][:] = 10.0 ** rng.uniform(-4.0, 1.8, nx) / (beta * s0.dx * p["rho"])
+    s = Setup(p)
+    ext = s.rho * (s.kappa + s.kappa_s)
+    taus = [2 * beta * s.dx / (1 / ext[i] + 1 / ext[(i + 1) % nx]) for i in range(nx)]
+    assert min(taus) < s.hll_threshold < max(taus) and max(taus) > 2
+    I = rng.random((1, 1, nx, s.nt, s.np_))
+    c = s.c
+
+    def flux(i, l, q):                      # F at face i + 1/2
+        j = (i + 1) % nx
+        n = s.sin_t[l] * s.cos_p[q]
+        sl, sr = _hll_speeds(n, taus[i], c, s.hll_threshold)
+        ul, ur = I[0, 0, i, l, q], I[0, 0, j, l, q]
+        return (sr * c * n * ul - sl * c * n * ur + sl * sr * (ur - ul)) / (sr - sl)
+
+    expect = np.empty_like(I)
+    for i in range(nx):
+        for l in range(s.nt):
+            for q in range(s.np_):
+                expect[0, 0, i, l, q] = I[0, 0, i, l, q] - s.dt / s.dx * (
+                    flux(i, l, q) - flux((i - 1) % nx, l, q))
+    assert np.max(np.abs(full.transport(I, s) - expect)) < 1e-13
+
+
+def test_hll_zero_optical_depth_is_upwind():
+    """tau -> 0 recovers the upwind flux (Sec. 3.1): exactly at zero
+    extinction (inflow, outflow and vacuum faces included), and to O(tau^2)
+    below the threshold."""
+    p = wl.small_random(bc="mixed", seed=61)
+    p["kappa"][:] = 0.0
+    s_up = Setup(p)
+    I = full.initial_intensity(s_up)
+    Iu = full.transport(I, s_up)
+    p["flux"] = "hll"
+    assert np.max(np.abs(full.transport(I, Setup(p)) - Iu)) < 1e-15 * np.max(np.abs(Iu))
+    p["kappa"][:] = 1e-4
+    s = Setup(p)
+    tmax = max(s.hll_tau(a).max() for a in range(s.dim))
+    assert 0 < tmax < s.hll_threshold
+    assert np.max(np.abs(full.transport(I, s) - Iu)) < 4 * tmax ** 2 * np.max(np.abs(I))
+
+
+@pytest.mark.parametrize("tau", [12.0, 6.0])
+def test_hll_thick_limit_is_rusanov_fourier(tau):
+    """Large tau_c: the HLL flux is the Rusanov flux with S+ = c |n_x| / tau_c
+    (Sec. 3.1), up to terms of order exp(-tau^2); on a periodic line of
+    uniform extinction a Fourier mode evolves by
+    g = 1 - i nu sin h - lam (|n_x| / tau)(1 - cos h), nu = lam n_x."""
+    p = _line_problem()
+    p["flux"] = "hll"
+    s0 = Setup(p)
+    p["kappa"][:] = tau / (s0.dx * p["rho"])
+    s = Setup(p)
+    assert np.allclose(s.hll_tau(0), tau, rtol=1e-14)
+    k = 3
+    x = (np.arange(s.nx) + 0.5) * s.dx
+    theta = 2 * np.pi * k * x
+    h = 2 * np.pi * k * s.dx
+    I = np.broadcast_to(np.cos(theta)[None, None, :, None, None], (1, 1, s.nx, s.nt, s.np_)).copy()
+    m = 4
+    for _ in range(m):
+        I = full.transport(I, s)
+    lam = s.lam[0]
+    n = np.outer(s.sin_t, s.cos_p)
+    g = 1 - 1j * lam * n * np.sin(h) - lam * (np.abs(n) / tau) * (1 - np.cos(h))
+    expect = np.real(g[None, :, :] ** m * np.exp(1j * theta)[:, None, None])
+    assert np.max(np.abs(I[0, 0] - expect)) < 1e-13 + 10 * np.exp(-tau ** 2)
+
+
+def test_hll_flux_form_conservation_and_outflow_steady_state():
+    """The HLL update is in flux form with alpha + beta = 1 at every face: on
+    a periodic grid with random extinction each direction's total is kept,
+    and with outflow on every face a uniform field is steady."""
+    p = wl.small_random(bc="periodic", seed=62, flux="hll", hll_beta=3.0, scatter=True)
+    s = Setup(p)
+    I = full.initial_intensity(s)
+    I1 = full.transport(I, s)
+    tot0, tot1 = I.sum(axis=(0, 1, 2)), I1.sum(axis=(0, 1, 2))
+    assert np.max(np.abs(tot1 - tot0)) < 1e-13 * np.max(np.abs(tot0))
+    p = wl.small_random(bc="outflow", seed=63, flux="hll", hll_beta=0.3)
+    s = Setup(p)
+    U = np.full(s.grid_shape() + (s.nt, s.np_), 1.7)
+    assert np.max(np.abs(full.transport(U, s) - U)) < 1e-14
+
+
+HLL_CASES = [dict(flux="hll", bc="periodic", seed=41),
+             dict(flux="hll", hll_beta=2.5, bc="inflow", seed=42, scatter=True),
+             dict(flux="hll", bc="mixed", seed=43, material=wl.COUPLED),
+             dict(flux="hll", hll_beta=0.01, bc="outflow", seed=44),
+             dict(dim=3, nx=4, ny=3, nz=4, flux="hll", hll_beta=0.05, bc="mixed", seed=45,
+                  scatter=True),
+             dict(dim=3, nx=3, ny=4, nz=4, flux="hll", bc="inflow", seed=46)]
+
+
+@pytest.mark.parametrize("kw", HLL_CASES, ids=[f"hll{i}" for i in range(len(HLL_CASES))])
+def test_hll_tt_without_truncation_is_the_full_grid_step(kw):
+    """The HLL flux in TT form (one variable-weight stencil block per axis
+    and sign of n, the inflow ghost as rank-1 blocks per sign; Sec. 4.3)
+    reconstructs the full-grid step exactly when nothing is truncated."""
+    p = wl.small_random(**kw)
+    s = Setup(p)
+    I1, T1, _ = full.step(full.initial_intensity(s), s.T0, s)
+    cat, T1t, _ = tt.step_untruncated(p["X0"], p["Th0"], p["Ph0"], s.T0, s)
+    F = metrics.reconstruct(*cat).reshape(I1.shape)
+    assert np.linalg.norm(F - I1) < 1e-13 * np.linalg.norm(I1)
+    assert np.max(np.abs(T1t - T1)) < 1e-13 * np.max(np.abs(T1))

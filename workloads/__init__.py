@@ -28,8 +28,10 @@ inflow     list of (face, face_w, theta_w, phi_w); face 0..5 =
            x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; face_w is indexed by the
            face's own 2-D cell index (see ``face_cells``)
 steps      number of steps of the workload
-flux       optional: "upwind" (default) or "rusanov"
+flux       optional: "upwind" (default), "rusanov" or "hll"
 s_plus     optional: Rusanov wavespeed S+ in units of c (default 1)
+hll_beta   optional: HLL optical-depth factor beta (default 1)
+hll_tau_threshold  optional: HLL wavespeed series threshold (default 1e-2)
 kappa_s    optional: per-cell scattering opacity (default 0)
 ========== ==============================================================
 
@@ -244,7 +246,7 @@ def random_tt(ns, ntheta, nphi, r1, r2, seed, decay=None):
 
 def small_random(dim=2, nx=6, ny=5, nz=1, ntheta=4, nphi=8, r1=3, r2=2,
                  seed=0, bc="vacuum", material=FROZEN, tol=1e-6, rmax=0,
-                 flux="upwind", s_plus=1.0, scatter=False):
+                 flux="upwind", s_plus=1.0, scatter=False, hll_beta=1.0):
     """Small seeded problem for parity tests: random positive material
     fields and random cores; ``bc`` in {vacuum, periodic, inflow, outflow,
     mixed} (mixed: inflow on x-lo, outflow on x-hi, vacuum on y-lo, outflow
@@ -282,6 +284,7 @@ def small_random(dim=2, nx=6, ny=5, nz=1, ntheta=4, nphi=8, r1=3, r2=2,
         p["inflow"].append((0, rng.random(ny * p["nz"]), rng.random(ntheta), rng.random(nphi)))
     p["flux"] = flux
     p["s_plus"] = float(s_plus)
+    p["hll_beta"] = float(hll_beta)
     if scatter:
         p["kappa_s"] = np.exp(rng.standard_normal(ns))
     p["name"] = f"small_{dim}d_{bc}_{flux}{'_scat' if scatter else ''}_s{seed}"
