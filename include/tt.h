@@ -61,8 +61,17 @@ enum { TT_BC_VACUUM = 0, TT_BC_PERIODIC = 1, TT_BC_INFLOW = 2, TT_BC_OUTFLOW = 3
  * RUSANOV: eq. rusanov_flux_toro with the wavespeed S+ = s_plus * c: a
  * central-difference block and a diffusion block per axis (the latter
  * omitted when s_plus == 0, the thick-medium choice of Sec. 5.3); a
- * Dirichlet face then adds two rank-1 terms per tt_inflow entry. */
-enum { TT_FLUX_UPWIND = 0, TT_FLUX_RUSANOV = 1 };
+ * Dirichlet face then adds two rank-1 terms per tt_inflow entry.
+ * HLL: eq. hll with the asymptotic wavespeeds of Sec. 3.1 and the local
+ * optical depth of eq. tauc (tau_c at face i+1/2 = 2 hll_beta dx /
+ * (1/(rho k)_i + 1/(rho k)_{i+1}), k = kappa + kappa_s; a non-periodic
+ * boundary face takes the interior cell's rho k on both sides; the series
+ * forms below hll_tau_threshold).  With piecewise-constant states the face
+ * flux is c n (alpha U_L + beta U_R), alpha + beta = 1, per sign of n: one
+ * variable-weight stencil block per axis and sign (B = 1 + 2 dim) and two
+ * rank-1 terms per tt_inflow entry.  The weights are formed on the device
+ * at tt_create and again by tt_set_kappa and tt_set_scattering. */
+enum { TT_FLUX_UPWIND = 0, TT_FLUX_RUSANOV = 1, TT_FLUX_HLL = 2 };
 /* Arithmetic of the N_s-long contractions and Gram formation. */
 enum { TT_FP64 = 0, TT_FP32_MIXED = 1 };
 /* ONCE: one rounding per step, after the transport and source terms are
@@ -96,8 +105,10 @@ typedef struct {
   int32_t ckpt_every;          /* > 0: tt_step records a tape for tt_grad     */
   int32_t max_steps;           /* capacity of the rank history and the tape   */
   int32_t r1_cap, r2_cap;      /* 0: derived from rmax and the mode sizes     */
-  int32_t flux;                /* TT_FLUX_UPWIND / TT_FLUX_RUSANOV            */
+  int32_t flux;                /* TT_FLUX_UPWIND / _RUSANOV / _HLL            */
   double s_plus;               /* Rusanov wavespeed S+ in units of c (>= 0)   */
+  double hll_beta;             /* HLL: optical-depth factor beta (> 0)        */
+  double hll_tau_threshold;    /* HLL: series threshold of tau_c (>= 0)       */
 } tt_config;
 
 /* One Dirichlet inflow term: the ghost value on `face` is

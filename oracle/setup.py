@@ -53,6 +53,8 @@ class Setup:
         self.s_plus = float(p.get("s_plus", 1.0))
         self.hll_beta = float(p.get("hll_beta", 1.0))
         self.hll_threshold = float(p.get("hll_tau_threshold", 1e-2))
+        if self.flux == HLL and not (0 < self.hll_beta < 1e300 and 0 < self.hll_threshold < 1e300):
+            raise ValueError("hll_beta and hll_tau_threshold must be finite and > 0")
         self.inflow = [(int(f), np.asarray(fw, float), np.asarray(tw, float),
                         np.asarray(pw, float)) for (f, fw, tw, pw) in p["inflow"]]
         self.mu, self.w, self.phi, self.v = quadrature.ordinates(self.nt, self.np_)

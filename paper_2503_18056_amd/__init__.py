@@ -12,7 +12,7 @@ import numpy as np
 
 from . import _ffi
 from ._ffi import (TT_BC_INFLOW, TT_BC_OUTFLOW, TT_BC_PERIODIC, TT_BC_VACUUM,  # noqa: F401
-                   TT_FLUX_RUSANOV, TT_FLUX_UPWIND, TT_FP32_MIXED, TT_FP64, TT_MAT_COUPLED,
+                   TT_FLUX_HLL, TT_FLUX_RUSANOV, TT_FLUX_UPWIND, TT_FP32_MIXED, TT_FP64, TT_MAT_COUPLED,
                    TT_MAT_FROZEN, TT_RANK_AUTO, TT_RANK_REPLAY, TT_ROUND_ONCE, TT_ROUND_TWICE,
                    STATUS_NAMES)
 
@@ -52,10 +52,13 @@ def make_config(p, *, precision=TT_FP64, schedule=TT_ROUND_ONCE, rank_mode=TT_RA
     cfg.max_steps = int(max_steps if max_steps is not None else max(p.get("steps", 1), 1))
     cfg.r1_cap, cfg.r2_cap = r1_cap, r2_cap
     flux = p.get("flux", "upwind")
-    if flux not in ("upwind", "rusanov"):
-        raise NotImplementedError(f"flux {flux!r}: the library steps the upwind and Rusanov fluxes")
-    cfg.flux = TT_FLUX_RUSANOV if flux == "rusanov" else TT_FLUX_UPWIND
+    codes = {"upwind": TT_FLUX_UPWIND, "rusanov": TT_FLUX_RUSANOV, "hll": TT_FLUX_HLL}
+    if flux not in codes:
+        raise ValueError(f"flux {flux!r}: one of {sorted(codes)}")
+    cfg.flux = codes[flux]
     cfg.s_plus = float(p.get("s_plus", 1.0))
+    cfg.hll_beta = float(p.get("hll_beta", 1.0))
+    cfg.hll_tau_threshold = float(p.get("hll_tau_threshold", 1e-2))
     return cfg
 
 

@@ -7,7 +7,7 @@ LIB_PATH = os.path.join(HERE, "libtt.so")
 
 TT_OK, TT_ERR_INVALID_ARG, TT_ERR_DEVICE, TT_ERR_OOM, TT_ERR_NUMERIC, TT_ERR_STATE = 0, -1, -2, -3, -4, -5
 TT_BC_VACUUM, TT_BC_PERIODIC, TT_BC_INFLOW, TT_BC_OUTFLOW = 0, 1, 2, 3
-TT_FLUX_UPWIND, TT_FLUX_RUSANOV = 0, 1
+TT_FLUX_UPWIND, TT_FLUX_RUSANOV, TT_FLUX_HLL = 0, 1, 2
 TT_FP64, TT_FP32_MIXED = 0, 1
 TT_ROUND_ONCE, TT_ROUND_TWICE = 0, 1
 TT_MAT_FROZEN, TT_MAT_COUPLED = 0, 1
@@ -29,6 +29,7 @@ class tt_config(C.Structure):
         ("rank_mode", C.c_int32), ("ckpt_every", C.c_int32), ("max_steps", C.c_int32),
         ("r1_cap", C.c_int32), ("r2_cap", C.c_int32),
         ("flux", C.c_int32), ("s_plus", C.c_double),
+        ("hll_beta", C.c_double), ("hll_tau_threshold", C.c_double),
     ]
 
 

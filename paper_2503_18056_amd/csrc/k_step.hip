@@ -30,14 +30,28 @@ __device__ inline double neighbour(const StepGeom& G, const TX* __restrict__ X, 
   return G.bchi[ax] == TT_BC_OUTFLOW ? self : 0.0;
 }
 
+// HLL block entry (Sec. 3.1 eq. hll; Sec. 4.3) of cell i from its value x0
+// and its neighbours m, p along ax: with the sign's weights at the cell's
+// faces, (alpha_hi - beta_lo) x0 + beta_hi p - alpha_lo m; for n < 0 the
+// weights are the n >= 0 pair swapped.
+__device__ __forceinline__ double hll_entry(const StepGeom& G, int kind, int ax, int i, double x0,
+                                            double m, double p) {
+  const double* w = G.hllw + ((long long)ax * G.ns + i) * 4;
+  const double aph = w[HLLW_AP_HI], bph = w[HLLW_BP_HI], apl = w[HLLW_AP_LO], bpl = w[HLLW_BP_LO];
+  if (kind == BK_HLL_POS) return (aph - bpl) * x0 + bph * p - apl * m;
+  return (bph - apl) * x0 + aph * p - bpl * m;
+}
+
 // Row i of the unscaled concatenation X_cat by column a of the state, for
 // every transport block at once: X(i, a) and its neighbours along the axes
 // the blocks use are loaded once, then block b's entry (column b r1 + a) is
 // formed from them: the state row itself (BK_BASE), the one-sided
-// differences (BK_MINUS, BK_PLUS), the central difference (BK_CENTRAL) or
-// the second difference (BK_DIFF) along the block's axis.  f(b, v) receives
-// each entry.
-template <typename TX, typename F>
+// differences (BK_MINUS, BK_PLUS), the central difference (BK_CENTRAL), the
+// second difference (BK_DIFF) or the weighted HLL stencil (BK_HLL_*) along
+// the block's axis.  f(b, v) receives each entry.  HLL: the HLL kinds are
+// compiled in (a separate instantiation, so that the other fluxes' kernels
+// keep their register budget).
+template <bool HLL, typename TX, typename F>
 __device__ __forceinline__ void xcat_row_blocks(const StepGeom& G, const TX* __restrict__ X, int ldX,
                                                 int i, const int* coord, int a, int axm, F&& f) {
   const double x0 = (double)X[(long long)i * ldX + a];
@@ -57,7 +71,8 @@ __device__ __forceinline__ void xcat_row_blocks(const StepGeom& G, const TX* __r
     else if (kind == BK_MINUS) v = x0 - m;
     else if (kind == BK_PLUS) v = p - x0;
     else if (kind == BK_CENTRAL) v = 0.5 * (p - m);
-    else v = (p - 2.0 * x0) + m;
+    else if (!HLL || kind == BK_DIFF) v = (p - 2.0 * x0) + m;
+    else v = hll_entry(G, kind, ax, i, x0, m, p);
     f(b, v);
   }
 }
@@ -77,7 +92,7 @@ __device__ inline int xcat_axes(const StepGeom& G) {
 // X_cat is written with non-temporal stores: it is read back only by the next
 // kernels' streams, and keeping it out of the caches leaves them to the X
 // rows that neighbouring cells load again (thick 3-D: 6.2 -> 5.3 ms).
-template <typename TX, typename TC>
+template <typename TX, typename TC, bool HLL>
 __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __restrict__ X, int ldX,
                                                     const double* __restrict__ bc_e,
                                                     const double* __restrict__ d,
@@ -95,7 +110,7 @@ __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __rest
   const double di = scaled ? d[i] : 1.0;
   TC* out = Xc + (long long)i * ldC;
   for (int a = lane; a < r1; a += 64)
-    xcat_row_blocks(G, X, ldX, i, coord, a, axm, [&](int b, double v) {
+    xcat_row_blocks<HLL>(G, X, ldX, i, coord, a, axm, [&](int b, double v) {
       __builtin_nontemporal_store((TC)(v * di), &out[b * r1 + a]);
     });
   for (int col = nstencil + lane; col < R1; col += 64) {
@@ -110,7 +125,7 @@ __global__ __launch_bounds__(256) void k_build_xcat(StepGeom G, const TX* __rest
 // k_build_xcat forms them (X_cat is neither written nor read): the
 // post-transport energy density before the source coefficients exist, so
 // that X_cat can then be built once with them.
-template <typename TX>
+template <typename TX, bool HLL>
 __global__ __launch_bounds__(256) void k_xcat_row_dot(StepGeom G, const TX* __restrict__ X, int ldX,
                                                       const double* __restrict__ bc_e,
                                                       const double* __restrict__ z,
@@ -125,7 +140,7 @@ __global__ __launch_bounds__(256) void k_xcat_row_dot(StepGeom G, const TX* __re
   const int axm = xcat_axes(G);
   double acc = 0.0;
   for (int a = lane; a < r1; a += 64)
-    xcat_row_blocks(G, X, ldX, i, coord, a, axm, [&](int b, double v) { acc += v * z[b * r1 + a]; });
+    xcat_row_blocks<HLL>(G, X, ldX, i, coord, a, axm, [&](int b, double v) { acc += v * z[b * r1 + a]; });
   for (int col = nstencil + lane; col < nstencil + G.nbc; col += 64)
     acc += bc_e[(long long)(col - nstencil) * G.ns + i] * z[col];
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -146,6 +161,7 @@ __global__ void k_z_blocks(const double* __restrict__ z, double* __restrict__ Zt
     Zt[(long long)a * ldz + b] = z[(long long)b * r1 + a];
   }
 }
+template <bool HLL>
 __global__ __launch_bounds__(256) void k_energy_stencil(StepGeom G, const double* __restrict__ Y,
                                                         int ldy, const double* __restrict__ bc_e,
                                                         const double* __restrict__ z,
@@ -169,12 +185,80 @@ __global__ __launch_bounds__(256) void k_energy_stencil(StepGeom G, const double
       if (kind == BK_MINUS) v = y0 - m;
       else if (kind == BK_PLUS) v = p - y0;
       else if (kind == BK_CENTRAL) v = 0.5 * (p - m);
-      else v = (p - 2.0 * y0) + m;
+      else if (!HLL || kind == BK_DIFF) v = (p - 2.0 * y0) + m;
+      else v = hll_entry(G, kind, ax, i, y0, m, p);
     }
     acc += v;
   }
   for (int c = 0; c < G.nbc; ++c) acc += bc_e[(long long)c * G.ns + i] * z[nstencil + c];
   E[i] = acc;
+}
+
+// HLL weights of a face of optical depth tau (Sec. 3.1): with
+// A = sqrt((1 - exp(-tau^2)) / tau^2) and B = sqrt((1 - exp(-tau^4)) / tau^2),
+// or their series sqrt(1 - tau^2 / 2) and tau below the threshold, the
+// wavespeeds S_R = c n A, S_L = -c n B (n >= 0) put eq. hll with F = c n U
+// in the form c n (alpha_p U_L + beta_p U_R), alpha_p = A (1 + B) / (A + B),
+// beta_p = B (1 - A) / (A + B).  tau -> 0 gives (1, 0), the upwind flux.
+__device__ inline void hll_pair(double tau, double thr, double& ap, double& bp) {
+  double A, B;
+  if (tau < thr) {
+    A = sqrt(fmax(1.0 - 0.5 * tau * tau, 0.0));
+    B = tau;
+  } else {
+    const double t2 = tau * tau;
+    A = sqrt((1.0 - exp(-t2)) / t2);
+    B = sqrt((1.0 - exp(-t2 * t2)) / t2);
+  }
+  ap = A * (1.0 + B) / (A + B);
+  bp = B * (1.0 - A) / (A + B);
+}
+
+// tau_c of eq. tauc for a face between extinctions ea and eb (rho (kappa +
+// kappa_s) of the two cells): 2 beta h / (1/ea + 1/eb); zero when either
+// side has none.
+__device__ inline double hll_face_tau(double ea, double eb, double bh) {
+  const double inv = 1.0 / ea + 1.0 / eb;
+  return inv < __builtin_inf() ? 2.0 * bh / inv : 0.0;
+}
+
+// One thread per cell; per axis, the weights of its hi face (the neighbour
+// i + e, wrapped on a periodic axis) and of its lo face (i - e).  A face on a
+// non-periodic boundary sees the cell's own extinction on both sides.
+__global__ void k_hll_weights(StepGeom G, int dim, const double* __restrict__ rho,
+                              const double* __restrict__ kappa, const double* __restrict__ kappa_s,
+                              double beta, double h0, double h1, double h2, double thr,
+                              double* __restrict__ W) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G.ns) return;
+  const int coord[3] = {i % G.nx, (i / G.nx) % G.ny, i / (G.nx * G.ny)};
+  const double ei = rho[i] * (kappa[i] + kappa_s[i]);
+  for (int ax = 0; ax < dim; ++ax) {
+    const int st = G.stride[ax], na = G.n[ax], ca = coord[ax];
+    const int jp = ca < na - 1 ? i + st : (G.periodic[ax] ? i - (na - 1) * st : i);
+    const int jm = ca > 0 ? i - st : (G.periodic[ax] ? i + (na - 1) * st : i);
+    const double ep = rho[jp] * (kappa[jp] + kappa_s[jp]);
+    const double em = rho[jm] * (kappa[jm] + kappa_s[jm]);
+    const double bh = beta * (ax == 0 ? h0 : ax == 1 ? h1 : h2);
+    double* w = W + ((long long)ax * G.ns + i) * 4;
+    double ap, bp;
+    hll_pair(hll_face_tau(ei, ep, bh), thr, ap, bp);
+    w[HLLW_AP_HI] = ap;
+    w[HLLW_BP_HI] = bp;
+    hll_pair(hll_face_tau(em, ei, bh), thr, ap, bp);
+    w[HLLW_AP_LO] = ap;
+    w[HLLW_BP_LO] = bp;
+  }
+}
+
+__global__ void k_hll_inflow(int ns, const double* __restrict__ bc_e0, const int* __restrict__ code,
+                             int nbc, const double* __restrict__ W, double* __restrict__ bc_e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  for (int c = 0; c < nbc; ++c) {
+    const int ax = code[c] >> 2, sel = code[c] & 3;
+    bc_e[(long long)c * ns + i] = bc_e0[(long long)c * ns + i] * W[((long long)ax * ns + i) * 4 + sel];
+  }
 }
 
 // Core conversion between FP64 and FP32 storage (rows x cols, leading dims).
@@ -642,12 +726,22 @@ __global__ void k_check_state(const TX* __restrict__ X, int ldX, int ns,
 void launch_build_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
                        const double* d, const double* s, double* Xc, int ldC, const int* dims,
                        int scaled, hipStream_t st) {
-  k_build_xcat<double, double><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims, scaled);
+  if (G.hllw)
+    k_build_xcat<double, double, true><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims,
+                                                                       scaled);
+  else
+    k_build_xcat<double, double, false><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims,
+                                                                        scaled);
 }
 void launch_build_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
                        const double* d, const double* s, float* Xc, int ldC, const int* dims,
                        int scaled, hipStream_t st) {
-  k_build_xcat<float, float><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims, scaled);
+  if (G.hllw)
+    k_build_xcat<float, float, true><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims,
+                                                                     scaled);
+  else
+    k_build_xcat<float, float, false><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, d, s, Xc, ldC, dims,
+                                                                      scaled);
 }
 void launch_build_phcat(const StepGeom& G, const double* Ph, const double* pfac,
                         const double* bc_p, double* Pc, const int* dims, hipStream_t st) {
@@ -702,7 +796,8 @@ static void energy_xcat_impl(const StepGeom& G, const TX* X, int ldX, const doub
   const DimExpr ncol = dimv(D_RC1, 1, -G.nem);
   k_phi_moment<<<(G.R2c + 63) / 64, 64, 0, st>>>(Pc, G.np, v, pv, r2, dims);
   k_theta_moment<<<(G.R1c + 3) / 4, 256, 0, st>>>(Tc, G.nt, G.R2c, w, pv, z, ncol, r2, inv_c, dims);
-  k_xcat_row_dot<TX><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, z, E, dims);
+  if (G.hllw) k_xcat_row_dot<TX, true><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, z, E, dims);
+  else k_xcat_row_dot<TX, false><<<(G.ns + 3) / 4, 256, 0, st>>>(G, X, ldX, bc_e, z, E, dims);
 }
 void launch_energy_xcat(const StepGeom& G, const double* X, int ldX, const double* bc_e,
                         const double* Tc, const double* Pc, const double* w, const double* v,
@@ -714,13 +809,24 @@ void launch_energy_xcat(const StepGeom& G, const double* X, int ldX, const doubl
   constexpr int LDY = MAX_BLOCKS;
   k_z_blocks<<<(G.r1c * G.B + 255) / 256, 256, 0, st>>>(z, Zt, LDY, G.B, dims);
   gemm_tall(G.ns, X, ldX, Zt, LDY, Y, LDY, dimv(D_R1), dimc(G.B), G.r1c, LDY, dims, st);
-  k_energy_stencil<<<(G.ns + 255) / 256, 256, 0, st>>>(G, Y, LDY, bc_e, z, E, dims);
+  if (G.hllw) k_energy_stencil<true><<<(G.ns + 255) / 256, 256, 0, st>>>(G, Y, LDY, bc_e, z, E, dims);
+  else k_energy_stencil<false><<<(G.ns + 255) / 256, 256, 0, st>>>(G, Y, LDY, bc_e, z, E, dims);
 }
 void launch_energy_xcat(const StepGeom& G, const float* X, int ldX, const double* bc_e,
                         const double* Tc, const double* Pc, const double* w, const double* v,
                         double* pv, double* z, DimExpr r2, double inv_c, double* E,
                         const int* dims, hipStream_t st) {
   energy_xcat_impl(G, X, ldX, bc_e, Tc, Pc, w, v, pv, z, r2, inv_c, E, dims, st);
+}
+void launch_hll_weights(const StepGeom& G, int dim, const double* rho, const double* kappa,
+                        const double* kappa_s, double beta, const double* h, double thr, double* W,
+                        hipStream_t st) {
+  k_hll_weights<<<(G.ns + 255) / 256, 256, 0, st>>>(G, dim, rho, kappa, kappa_s, beta, h[0], h[1], h[2],
+                                                    thr, W);
+}
+void launch_hll_inflow(const StepGeom& G, const double* bc_e0, const int* code, int nbc,
+                       const double* W, double* bc_e, hipStream_t st) {
+  if (nbc > 0) k_hll_inflow<<<(G.ns + 255) / 256, 256, 0, st>>>(G.ns, bc_e0, code, nbc, W, bc_e);
 }
 void launch_convert(const double* a, int lda, float* b, int ldb, int rows, int cols, hipStream_t st) {
   k_convert<double, float><<<1024, 256, 0, st>>>(a, lda, b, ldb, rows, cols);

@@ -56,7 +56,15 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
   if (!(c->tol >= 0)) { why = "tol must be >= 0"; return false; }
   if (c->precision != TT_FP64 && c->precision != TT_FP32_MIXED) { why = "bad precision"; return false; }
   if (c->schedule != TT_ROUND_ONCE && c->schedule != TT_ROUND_TWICE) { why = "bad schedule"; return false; }
-  if (c->flux != TT_FLUX_UPWIND && c->flux != TT_FLUX_RUSANOV) { why = "bad flux"; return false; }
+  if (c->flux != TT_FLUX_UPWIND && c->flux != TT_FLUX_RUSANOV && c->flux != TT_FLUX_HLL) {
+    why = "bad flux";
+    return false;
+  }
+  if (c->flux == TT_FLUX_HLL && !(c->hll_beta > 0 && c->hll_beta < 1e300 && c->hll_tau_threshold > 0 &&
+                                  c->hll_tau_threshold < 1e300)) {
+    why = "hll_beta and hll_tau_threshold must be finite and > 0";
+    return false;
+  }
   if (c->flux == TT_FLUX_RUSANOV && !(c->s_plus >= 0 && c->s_plus < 1e300)) {
     why = "s_plus must be finite and >= 0";
     return false;
@@ -87,10 +95,10 @@ bool validate(const tt_config* c, int n_inflow, std::string& why) {
 }
 
 // Rusanov with S+ > 0 has a diffusion block per axis and two rank-1 terms
-// per Dirichlet face entry.
+// per Dirichlet face entry; HLL two rank-1 terms per entry (one per sign of n).
 bool rusanov_diffusion(const tt_config& c) { return c.flux == TT_FLUX_RUSANOV && c.s_plus != 0.0; }
 int inflow_blocks(const tt_config& c, int n_inflow) {
-  return n_inflow * (rusanov_diffusion(c) ? 2 : 1);
+  return n_inflow * (rusanov_diffusion(c) || c.flux == TT_FLUX_HLL ? 2 : 1);
 }
 bool all_finite(const double* a, size_t n) {
   for (size_t i = 0; i < n; ++i)
@@ -147,11 +155,15 @@ void geometry(tt_ctx* x, const tt_config& c, int n_inflow, int nem) {
     if (rus) {
       G.bkind[b] = BK_CENTRAL; G.baxis[b++] = a;
       if (dif) { G.bkind[b] = BK_DIFF; G.baxis[b++] = a; }
+    } else if (c.flux == TT_FLUX_HLL) {
+      G.bkind[b] = BK_HLL_POS; G.baxis[b++] = a;
+      G.bkind[b] = BK_HLL_NEG; G.baxis[b++] = a;
     } else {
       G.bkind[b] = BK_MINUS; G.baxis[b++] = a;
       G.bkind[b] = BK_PLUS; G.baxis[b++] = a;
     }
   }
+  G.hllw = nullptr;
   G.nt = x->nt; G.np = x->np; G.B = x->B; G.nbc = x->nbc; G.nem = x->nem;
   G.r1c = x->r1c; G.r2c = x->r2c; G.R1c = x->R1c; G.R2c = x->R2c;
 }
@@ -172,6 +184,11 @@ size_t carve(tt_ctx* x, char* base) {
   x->bc_e = cv.take<double>((size_t)std::max(1, x->nbc) * ns);
   x->bc_t = cv.take<double>((size_t)std::max(1, x->nbc) * nt);
   x->bc_p = cv.take<double>((size_t)std::max(1, x->nbc) * np);
+  const bool hll = x->cfg.flux == TT_FLUX_HLL;
+  x->hllw = hll ? cv.take<double>((size_t)x->dim * ns * 4) : nullptr;
+  x->bc_e0 = hll ? cv.take<double>((size_t)std::max(1, x->nbc) * ns) : nullptr;
+  x->bc_code = hll ? cv.take<int>((size_t)std::max(1, x->nbc)) : nullptr;
+  x->G.hllw = x->hllw;
   double** fields[] = {&x->kappa, &x->rho, &x->cv, &x->T, &x->d, &x->s, &x->Estar, &x->Enew, &x->Tdag,
                        &x->kappa_s, &x->wbuf};
   for (double** f : fields) *f = cv.take<double>(ns);
@@ -262,21 +279,32 @@ void host_factors(const tt_ctx* x, std::vector<double>& w, std::vector<double>& 
     const double lam = x->lam[a];
     for (int l = 0; l < nt; ++l) {
       double t = 1.0;  // base and Rusanov diffusion blocks: isotropic in theta
-      if (kind == BK_MINUS) t = a < 2 ? sint[l] : std::max(mu[l], 0.0);
-      else if (kind == BK_PLUS) t = a < 2 ? sint[l] : std::min(mu[l], 0.0);
+      if (kind == BK_MINUS || kind == BK_HLL_POS) t = a < 2 ? sint[l] : std::max(mu[l], 0.0);
+      else if (kind == BK_PLUS || kind == BK_HLL_NEG) t = a < 2 ? sint[l] : std::min(mu[l], 0.0);
       else if (kind == BK_CENTRAL) t = a < 2 ? sint[l] : mu[l];
       tf[(size_t)b * nt + l] = t;
     }
     for (int p = 0; p < np; ++p) {
       const double n = a == 0 ? cosp[p] : a == 1 ? sinp[p] : 1.0;
       double f = 1.0;
-      if (kind == BK_MINUS) f = a < 2 ? -lam * std::max(n, 0.0) : -lam;
-      else if (kind == BK_PLUS) f = a < 2 ? -lam * std::min(n, 0.0) : -lam;
+      if (kind == BK_MINUS || kind == BK_HLL_POS) f = a < 2 ? -lam * std::max(n, 0.0) : -lam;
+      else if (kind == BK_PLUS || kind == BK_HLL_NEG) f = a < 2 ? -lam * std::min(n, 0.0) : -lam;
       else if (kind == BK_CENTRAL) f = -lam * n;
       else if (kind == BK_DIFF) f = 0.5 * lam * x->cfg.s_plus;
       pf[(size_t)b * np + p] = f;
     }
   }
+}
+
+// HLL flux: the face weights from the current rho, kappa and kappa_s, then
+// the inflow columns weighted by them (queued on the context's stream).
+void hll_refresh(tt_ctx* x) {
+  if (x->cfg.flux != TT_FLUX_HLL) return;
+  const tt_config& c = x->cfg;
+  const double h[3] = {c.lx / c.nx, c.ly / c.ny, c.dim == 3 ? c.lz / x->G.nz : 1.0};
+  launch_hll_weights(x->G, x->dim, x->rho, x->kappa, x->kappa_s, c.hll_beta, h, c.hll_tau_threshold,
+                     x->hllw, x->st);
+  launch_hll_inflow(x->G, x->bc_e0, x->bc_code, x->nbc, x->hllw, x->bc_e, x->st);
 }
 
 std::vector<int> face_cells(const tt_ctx* x, int face) {
@@ -837,8 +865,14 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
   // Dirichlet ghost value g = face_w (x) theta_w (x) phi_w of each entry: the
   // part of the flux through its face that the stencil blocks (ghost rows
   // zero) leave out, as rank-1 terms e_face (x) t (x) p (Sec. 4.5).
+  // HLL: the ghost value enters F at the face with the face's weight, per
+  // sign of n (term j = 0: n >= 0, j = 1: n < 0): + lam n alpha_lo g on a lo
+  // face, - lam n beta_hi g on a hi face; the spatial part is weighted on
+  // the device (k_hll_inflow, code = 4 axis + weight slot).
   const bool rus = cfg->flux == TT_FLUX_RUSANOV, dif = rusanov_diffusion(*cfg);
-  const int per = dif ? 2 : 1;
+  const bool hll = cfg->flux == TT_FLUX_HLL;
+  const int per = dif || hll ? 2 : 1;
+  std::vector<int> code((size_t)nbk, 0);
   for (int k = 0; k < n_inflow; ++k) {
     const int f = inflow[k].face, a = f / 2, hi = f % 2;
     std::vector<int> cells = face_cells(c, f);
@@ -846,24 +880,29 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
     for (int j = 0; j < per; ++j) {
       const size_t kb = (size_t)k * per + j;  // rank-1 term index
       for (size_t q = 0; q < cells.size(); ++q) be[kb * ns + cells[q]] = inflow[k].face_w[q];
+      const bool neg = hll ? j == 1 : hi;  // upwind: the incoming sign only
+      if (hll) code[kb] = 4 * a + (hi ? (j ? HLLW_AP_HI : HLLW_BP_HI) : (j ? HLLW_BP_LO : HLLW_AP_LO));
       for (int l = 0; l < c->nt; ++l) {
         double tfv;
         if (rus) tfv = j == 1 ? 1.0 : (a < 2 ? sint[l] : mu[l]);
-        else tfv = a < 2 ? sint[l] : (hi ? std::min(mu[l], 0.0) : std::max(mu[l], 0.0));
+        else tfv = a < 2 ? sint[l] : (neg ? std::min(mu[l], 0.0) : std::max(mu[l], 0.0));
         bt[kb * c->nt + l] = tfv * inflow[k].theta_w[l];
       }
       for (int p = 0; p < c->np; ++p) {
         const double n = a == 0 ? cosp[p] : a == 1 ? sinp[p] : 1.0;
+        const double sl = hi ? -lam : lam;
         double pfv;
         if (rus) pfv = j == 1 ? 0.5 * lam * cfg->s_plus : (hi ? -0.5 : 0.5) * lam * n;
-        else if (a < 2) pfv = hi ? -lam * std::min(n, 0.0) : lam * std::max(n, 0.0);
-        else pfv = hi ? -lam : lam;
+        else if (a < 2) pfv = sl * (neg ? std::min(n, 0.0) : std::max(n, 0.0));
+        else pfv = sl;
         bp[kb * c->np + p] = pfv * inflow[k].phi_w[p];
       }
     }
   }
   if (n_inflow > 0) {
-    HIPCHK(nullptr, hipMemcpyAsync(c->bc_e, be.data(), be.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(nullptr, hipMemcpyAsync(hll ? c->bc_e0 : c->bc_e, be.data(), be.size() * 8,
+                                   hipMemcpyHostToDevice, s));
+    if (hll) HIPCHK(nullptr, hipMemcpyAsync(c->bc_code, code.data(), code.size() * 4, hipMemcpyHostToDevice, s));
     HIPCHK(nullptr, hipMemcpyAsync(c->bc_t, bt.data(), bt.size() * 8, hipMemcpyHostToDevice, s));
     HIPCHK(nullptr, hipMemcpyAsync(c->bc_p, bp.data(), bp.size() * 8, hipMemcpyHostToDevice, s));
   }
@@ -875,6 +914,8 @@ tt_status tt_create(const tt_config* cfg, const double* kappa, const double* rho
   HIPCHK(nullptr, hipMemcpyAsync(c->rho, c->h_rho.data(), ns * 8, hipMemcpyHostToDevice, s));
   HIPCHK(nullptr, hipMemcpyAsync(c->cv, c->h_cv.data(), ns * 8, hipMemcpyHostToDevice, s));
   HIPCHK(nullptr, hipMemcpyAsync(c->T, T0, ns * 8, hipMemcpyHostToDevice, s));
+  hll_refresh(c);
+  HIPCHK(nullptr, hipGetLastError());
   HIPCHK(nullptr, hipStreamSynchronize(s));
   const int32_t rr[2] = {r1, r2};
   tt_status st = tt_set_cores(c, X0, Th0, Ph0, rr);
@@ -1016,6 +1057,7 @@ tt_status tt_set_kappa(tt_ctx* c, const double* kappa_dev) {
   if (c->nhist > 0) c->gb.stale = true;  // the taped steps used the old opacity
   launch_material(c->ns, c->cfg.c, c->dt, c->cfg.a_r, 0, c->kappa, nullptr, c->rho, c->cv, c->T,
                   c->Estar, c->Tdag, c->d, c->s, c->dims, c->st);
+  hll_refresh(c);  // the HLL face weights depend on kappa
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->st));
   return TT_OK;
@@ -1032,6 +1074,8 @@ tt_status tt_set_scattering(tt_ctx* c, const double* kappa_s) {
     any = any || kappa_s[i] > 0;
   }
   HIPCHK(c, hipMemcpyAsync(c->kappa_s, kappa_s, c->ns * 8, hipMemcpyHostToDevice, c->st));
+  hll_refresh(c);  // the HLL face weights depend on kappa_s
+  HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->scatter = any;
   // the isotropic source block carries the scattering term

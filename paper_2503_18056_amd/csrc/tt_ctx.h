@@ -90,6 +90,9 @@ struct tt_ctx {
   int *dims, *hist, *sched;
   double* diag;
   double *w, *v, *tfac, *pfac, *bc_e, *bc_t, *bc_p;
+  double* hllw;              // HLL face weights (dim x N_s x 4), HLL flux only
+  double* bc_e0;             // HLL: unweighted inflow columns (nbc x N_s)
+  int* bc_code;              // HLL: weight selector of each inflow column (4 axis + slot)
   double *kappa, *rho, *cv, *T, *d, *s, *Estar, *Enew, *Tdag;
   double* kappa_s;           // scattering opacity (zero unless tt_set_scattering)
   double *wbuf, *lossbuf;    // detector weights and the loss of tt_detector_loss

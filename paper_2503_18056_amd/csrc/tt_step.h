@@ -7,11 +7,19 @@
 namespace tt {
 
 // Stencil of a transport block of the spatial core (Sec. 4.3): the base
-// block X, the upwind differences X_i - X_{i-e} and X_{i+e} - X_i, and the
+// block X, the upwind differences X_i - X_{i-e} and X_{i+e} - X_i, the
 // Rusanov central difference (X_{i+e} - X_{i-e}) / 2 and diffusion
-// X_{i+e} - 2 X_i + X_{i-e}.
-enum : int { BK_BASE = 0, BK_MINUS = 1, BK_PLUS = 2, BK_CENTRAL = 3, BK_DIFF = 4 };
+// X_{i+e} - 2 X_i + X_{i-e}, and the HLL blocks of n >= 0 and n < 0:
+// (alpha_hi - beta_lo) X_i + beta_hi X_{i+e} - alpha_lo X_{i-e} with the
+// sign's weights at the cell's hi and lo faces (HllW).
+enum : int { BK_BASE = 0, BK_MINUS = 1, BK_PLUS = 2, BK_CENTRAL = 3, BK_DIFF = 4, BK_HLL_POS = 5,
+             BK_HLL_NEG = 6 };
 constexpr int MAX_BLOCKS = 8;
+// HLL face weights per axis and cell, four doubles at
+// hllw[(axis * N_s + i) * 4]: alpha_p and beta_p (n >= 0) of the cell's hi
+// face, then of its lo face.  The n < 0 pair is the swap: alpha_m = beta_p,
+// beta_m = alpha_p.
+enum : int { HLLW_AP_HI = 0, HLLW_BP_HI = 1, HLLW_AP_LO = 2, HLLW_BP_LO = 3 };
 
 struct StepGeom {
   int ns, nx, ny, nz;
@@ -25,6 +33,7 @@ struct StepGeom {
   int nem;      // emission block present (0/1)
   int r1c, r2c; // state rank capacities
   int R1c, R2c; // concatenated rank capacities
+  const double* hllw;  // HLL face weights (device; null for the other fluxes)
 };
 
 struct RankArgs {
@@ -62,6 +71,16 @@ void launch_energy_xcat(const StepGeom& G, const float* X, int ldX, const double
                         const double* Tc, const double* Pc, const double* w, const double* v,
                         double* pv, double* z, DimExpr r2, double inv_c, double* E,
                         const int* dims, hipStream_t st);
+// HLL face weights (layout above) from rho, kappa and kappa_s: tau_c of
+// eq. tauc with beta and the cell sizes h[3], then the weights of eq. hll
+// with the wavespeeds of Sec. 3.1 (series forms below thr).
+void launch_hll_weights(const StepGeom& G, int dim, const double* rho, const double* kappa,
+                        const double* kappa_s, double beta, const double* h, double thr, double* W,
+                        hipStream_t st);
+// Inflow columns of the HLL flux: bc_e[c][i] = bc_e0[c][i] * W[ax_c][i][sel_c]
+// with code[c] = 4 ax_c + sel_c (host-built; one code per rank-1 term).
+void launch_hll_inflow(const StepGeom& G, const double* bc_e0, const int* code, int nbc,
+                       const double* W, double* bc_e, hipStream_t st);
 void launch_convert(const double* a, int lda, float* b, int ldb, int rows, int cols, hipStream_t st);
 void launch_convert(const float* a, int lda, double* b, int ldb, int rows, int cols, hipStream_t st);
 void launch_build_phcat(const StepGeom& G, const double* Ph, const double* pfac,

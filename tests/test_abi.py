@@ -163,10 +163,11 @@ def test_create_validates_host_inputs(lib):
 
 def test_operator_options_validation(lib):
     """Rusanov changes the block count (B = 1 + 2 dim, or 1 + dim when
-    S+ = 0) and doubles the rank-1 inflow terms when S+ > 0; outflow faces,
-    the two-rounding schedule and Rusanov are accepted, but not with a tape
-    (the reverse sweep covers the upwind, one-rounding step without outflow
-    faces)."""
+    S+ = 0) and doubles the rank-1 inflow terms when S+ > 0, HLL doubles
+    them and adds its face weights (beta and the threshold finite and
+    positive); outflow faces, the two-rounding schedule, Rusanov and HLL
+    are accepted, but not with a tape (the reverse sweep covers the upwind,
+    one-rounding step without outflow faces)."""
     from paper_2503_18056_amd import TT_FLUX_RUSANOV, TT_ROUND_TWICE, make_config
     p = wl.small_random(bc="inflow", seed=2)
     n_in = len(p["inflow"])
@@ -185,7 +186,14 @@ def test_operator_options_validation(lib):
     assert lib.tt_workspace_bytes(C.byref(cfg), n_in) == 0 and b"flux" in lib.tt_last_error(None)
     o = wl.small_random(bc="outflow", seed=2)
     assert lib.tt_workspace_bytes(C.byref(make_config(o)), 0) > 0
+    h = dict(p, flux="hll", hll_beta=2.0)
+    assert lib.tt_workspace_bytes(C.byref(make_config(h)), n_in) > base  # weights, 2 terms per entry
+    for beta, thr in ((0.0, 1e-2), (-1.0, 1e-2), (1.0, 0.0), (float("nan"), 1e-2), (1.0, float("inf"))):
+        cfg = make_config(h)
+        cfg.hll_beta, cfg.hll_tau_threshold = beta, thr
+        assert lib.tt_workspace_bytes(C.byref(cfg), n_in) == 0 and b"hll" in lib.tt_last_error(None)
     for cfg in (make_config(o, ckpt_every=2), make_config(q, ckpt_every=2),
+                make_config(h, ckpt_every=2),
                 make_config(p, ckpt_every=2, schedule=TT_ROUND_TWICE)):
         assert lib.tt_workspace_bytes(C.byref(cfg), n_in) == 0
         assert b"adjoint" in lib.tt_last_error(None)

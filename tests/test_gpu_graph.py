@@ -62,6 +62,7 @@ CASES = {
     "rusanov_scatter_coupled": (dict(flux="rusanov", bc="mixed", seed=36, material=wl.COUPLED,
                                      scatter=True), {}),
     "outflow_3d": (dict(dim=3, nx=4, ny=3, nz=5, bc="outflow", seed=4), {}),
+    "hll_inflow_scatter": (dict(flux="hll", hll_beta=2.5, bc="inflow", seed=42, scatter=True), {}),
 }
 
 
