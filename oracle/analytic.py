@@ -18,7 +18,9 @@ J_left = 0 for x >= c t, and J_bottom the same with x and y exchanged.
 Line source (Sec. 5.4): a pulse U0 delta(x, y) of radiation energy in
 vacuum spreads as E(t, r) = U0 H(c t - r) / (2 pi c t sqrt((c t)^2 - r^2)),
 whose integral over the plane is U0 at every t (total energy is conserved);
-the smoothed initial condition is the Gaussian of width omega.
+the smoothed initial condition is the Gaussian of width omega,
+G(r) = U0 / (2 pi omega^2) exp(-r^2 / (2 omega^2)), and its solution the
+plane convolution of the two (line_source_smoothed_E).
 """
 import numpy as np
 
@@ -53,3 +55,31 @@ def line_source_E(t, r, U0=1.0, c=1.0):
     m = r < ct
     out[m] = U0 / (2.0 * np.pi * ct * np.sqrt(ct * ct - r[m] ** 2))
     return out
+
+
+def line_source_smoothed_E(t, r, U0=1.0, omega=0.03, c=1.0, n=20000):
+    """Energy density of the line source from the Gaussian pulse of width
+    omega (Sec. 5.4): the plane convolution of the delta-pulse solution with
+    the normalised Gaussian.  In polar coordinates about the point, the
+    angular integral of the Gaussian over a circle of radius s about a point
+    at distance r from its centre is 2 pi exp(-(r^2 + s^2) / (2 omega^2))
+    I_0(r s / omega^2), so
+
+        E(t, r) = U0 / (2 pi omega^2 c t) int_0^{c t} s exp(-(r - s)^2 / (2 omega^2))
+                  i0e(r s / omega^2) / sqrt((c t)^2 - s^2) ds,
+
+    with i0e(z) = exp(-z) I_0(z).  The substitution s = c t sin(phi) removes
+    the front's inverse square root; the phi integral over [0, pi/2] is
+    taken by the midpoint rule on n points."""
+    from scipy.special import i0e
+    r = np.atleast_1d(np.asarray(r, dtype=float))
+    ct = c * t
+    h = 0.5 * np.pi / n
+    s = ct * np.sin((np.arange(n) + 0.5) * h)
+    w2 = omega * omega
+    out = np.empty(r.shape)
+    for k0 in range(0, r.size, 256):
+        rr = r.reshape(-1)[k0:k0 + 256, None]
+        f = s[None, :] * np.exp(-(rr - s[None, :]) ** 2 / (2 * w2)) * i0e(rr * s[None, :] / w2)
+        out.reshape(-1)[k0:k0 + 256] = f.sum(axis=1) * h
+    return U0 / (2 * np.pi * w2 * ct) * out

@@ -25,6 +25,15 @@ what the roundings drop.  Sec. 5.4 reports conservation errors of 8e-5 U0
   after every step against the TT oracle's (parity), both under those
   figures.
 - 256^2 cells, 16 x 32 ordinates, both tolerances: under those figures.
+- The profile (Sec. 5.4 compares azimuthal averages with the exact
+  solution): the azimuthal average of E over annuli one cell wide against
+  that of the Gaussian-smoothed analytic solution
+  (`oracle.analytic.line_source_smoothed_E`, pinned in test_oracle_pins.py),
+  as an L1 distance relative to U0, at 64^2 / 8 x 16, 128^2 / 16 x 32 and
+  256^2 / 32 x 64 (tolerance 1e-4): it falls with each refinement of space
+  and angle together.  The full-grid oracle gives 0.43 and 0.29 for the
+  first two; the error is the first-order scheme's smearing of the ring and
+  the ray effects of the coarse ordinates, as Sec. 5.4 discusses.
 """
 import sys
 
@@ -33,7 +42,7 @@ import pytest
 
 import workloads as wl
 from oracle import Setup, metrics, tt
-from oracle.analytic import hohlraum_J
+from oracle.analytic import hohlraum_J, line_source_smoothed_E
 
 pytestmark = pytest.mark.gpu
 
@@ -160,3 +169,34 @@ def test_line_source_256_conservation():
         _log(f"  ranks {st.tt_get_rank_history()[-1]} (cap 204), conservation error {err:.3e} "
              f"(Sec. 5.4: {paper:.0e} for its full run)")
         assert err < paper
+
+
+def _azimuthal_l1(E, p):
+    """L1 distance, relative to U0, between the azimuthal averages of E and
+    of the smoothed analytic solution over annuli one cell wide about the
+    pulse's centre (each annulus weighted by its cells' area)."""
+    n = p["nx"]
+    dx = p["lx"] / n
+    xs = (np.arange(n) + 0.5) * dx - 0.5 * p["lx"]
+    R = np.sqrt(xs[None, :] ** 2 + xs[:, None] ** 2).reshape(-1)
+    ls = p["line_source"]
+    Ea = line_source_smoothed_E(ls["t"], R, U0=ls["U0"], omega=ls["omega"], c=p["c"])
+    b = np.floor(R / dx).astype(int)
+    cnt = np.bincount(b)
+    Eb = np.bincount(b, np.asarray(E).reshape(-1)) / np.maximum(cnt, 1)
+    Ab = np.bincount(b, Ea) / np.maximum(cnt, 1)
+    return float(np.sum(np.abs(Eb - Ab) * cnt) * dx * dx / ls["U0"])
+
+
+def test_line_source_profile_converges_to_the_smoothed_solution():
+    errs = []
+    for n, nt, npf in ((64, 8, 16), (128, 16, 32), (256, 32, 64)):
+        p = wl.line_source(n=n, ntheta=nt, nphi=npf, tol=1e-4, rmax=200)
+        _log(f"line source {n}^2 {nt}x{npf}: {p['steps']} steps")
+        st = _state(p, max_steps=p["steps"])
+        st.step(p["steps"])
+        errs.append(_azimuthal_l1(st.tt_energy()[0].cpu().numpy(), p))
+        _log(f"  ranks {st.tt_get_rank_history()[-1]}, azimuthal L1 {errs[-1]:.4f}")
+    assert errs[0] < 0.5
+    assert errs[1] < 0.8 * errs[0]
+    assert errs[2] < 0.8 * errs[1]

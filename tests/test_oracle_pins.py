@@ -931,3 +931,30 @@ def test_hll_tt_without_truncation_is_the_full_grid_step(kw):
     F = metrics.reconstruct(*cat).reshape(I1.shape)
     assert np.linalg.norm(F - I1) < 1e-13 * np.linalg.norm(I1)
     assert np.max(np.abs(T1t - T1)) < 1e-13 * np.max(np.abs(T1))
+
+
+def test_line_source_smoothed_solution():
+    """The Gaussian-smoothed line source (Sec. 5.4): its plane integral is
+    U0 at every t, it tends to the initial Gaussian as c t / omega -> 0, and
+    at four radii (inside, near and past the front) it equals the plane
+    convolution of the delta-pulse solution with the Gaussian taken by brute
+    force over the circle (no Bessel reduction)."""
+    from oracle import analytic as an
+    om = 0.03
+    for t in (0.25, 0.5, 1.0):
+        r = np.linspace(0.0, t + 12 * om, 6001)
+        tot = 2 * np.pi * np.trapezoid(an.line_source_smoothed_E(t, r, U0=1.3, omega=om, n=6000) * r, r)
+        assert abs(tot - 1.3) < 1e-7
+    r = np.linspace(0.0, 0.1, 11)
+    G = np.exp(-r ** 2 / (2 * om ** 2)) / (2 * np.pi * om ** 2)
+    assert np.max(np.abs(an.line_source_smoothed_E(1e-4, r, omega=om) - G)) < 1e-5 * G.max()
+    t = ct = 0.5
+    nphi, npsi = 4000, 1024
+    rho = ct * np.sin((np.arange(nphi) + 0.5) * (0.5 * np.pi / nphi))
+    psi = (np.arange(npsi) + 0.5) * (2 * np.pi / npsi)
+    for rp in (0.1, 0.3, 0.48, 0.52):
+        d2 = rp ** 2 + rho[:, None] ** 2 - 2 * rp * rho[:, None] * np.cos(psi[None, :])
+        G = np.exp(-d2 / (2 * om ** 2)) / (2 * np.pi * om ** 2)
+        # E_delta(rho) rho drho = rho dphi / (2 pi c t) with rho = c t sin(phi)
+        brute = np.sum(rho[:, None] * G) * (0.5 * np.pi / nphi) * (2 * np.pi / npsi) / (2 * np.pi * ct)
+        assert abs(an.line_source_smoothed_E(t, rp, omega=om)[0] - brute) < 1e-7 * brute
