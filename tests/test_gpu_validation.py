@@ -1,5 +1,5 @@
 """Reduced-size analytic validations through the C ABI: the hohlraum
-(Sec. 5.1) and the line source's energy conservation (Sec. 5.4).
+(Sec. 5.1) and the line source's energy conservation and profile (Sec. 5.4).
 
 Isotropic inflow I = 1 through the x-lo and y-lo faces into vacuum; the
 mean intensity J = c E / (4 pi) at t = 0.75 is compared over the cells of
@@ -31,8 +31,8 @@ what the roundings drop.  Sec. 5.4 reports conservation errors of 8e-5 U0
   (`oracle.analytic.line_source_smoothed_E`, pinned in test_oracle_pins.py),
   as an L1 distance relative to U0, at 64^2 / 8 x 16, 128^2 / 16 x 32 and
   256^2 / 32 x 64 (tolerance 1e-4): it falls with each refinement of space
-  and angle together.  The full-grid oracle gives 0.43 and 0.29 for the
-  first two; the error is the first-order scheme's smearing of the ring and
+  and angle together (measured 0.427, 0.287, 0.186; the full-grid oracle
+  gives the same first two); the error is the first-order scheme's smearing of the ring and
   the ray effects of the coarse ordinates, as Sec. 5.4 discusses.
 """
 import sys
