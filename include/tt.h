@@ -173,6 +173,27 @@ tt_status tt_step(tt_ctx* ctx, int32_t nsteps);
  * until tt_set_cores. */
 tt_status tt_round(tt_ctx* ctx, double tol, int32_t rmax, int32_t ranks_out[2]);
 
+/* Randomized rounding of the stored state to the fixed target ranks
+ * (k1, k2) (App. A.3, eqs. randfinal and randprojection), bond 1 then
+ * bond 2.  omega1: device, (N_theta N_phi) x k1 row-major, row l N_phi + p
+ * for ordinate (l, p); omega2: device, N_phi x k2 row-major.  They are the
+ * Gaussian test matrices the caller draws (read only, caller-owned); their
+ * column counts are the target ranks.  Each bond sketches its right factor
+ * (W = B^T Omega), takes an orthonormal basis Q of A W (shifted
+ * CholeskyQR3 on the FP64 MFMA Gram and product kernels) and carries
+ * Q^T A into the next core; X' and Theta' come out with orthonormal
+ * columns.  TT_FP64 contexts only; needs 1 <= k1 <= min(r1, N_theta N_phi)
+ * and 1 <= k2 <= min(r2, N_phi, k1 N_theta) at the current ranks (r1, r2),
+ * and room for three 8-column-aligned slots in the concatenation buffers
+ * (k1 + r1 + k1 columns of X_cat, k2 + r2 + k2 of Theta_cat; always true
+ * when the ranks are multiples of 8).  ranks_out (host, may be NULL)
+ * receives (k1, k2).  Like tt_round it is not a recorded step.
+ * Errors: TT_ERR_INVALID_ARG (sizes, null pointers, FP32-mixed context),
+ * TT_ERR_NUMERIC (a sketch Gram not positive definite after its shift:
+ * the context is then poisoned). */
+tt_status tt_round_randomized(tt_ctx* ctx, const double* omega1, int32_t k1, const double* omega2,
+                              int32_t k2, int32_t ranks_out[2]);
+
 /* Radiation energy density E_i = (1/c) X_i (sum_l Theta_l w_l)(sum_p Phi_p v_p)
  * (Sec. 4.1 eq. tt_energy_density).  E_dev: device N_s doubles or NULL.
  * rad_total / mat_total (host, may be NULL): sum_i E_i dV and

@@ -118,6 +118,26 @@ class TTState:
         self._check(self.lib.tt_round(self.ctx, float(tol), int(rmax), r))
         return int(r[0]), int(r[1])
 
+    def tt_round_randomized(self, omega1, omega2):
+        """Randomized rounding to the target ranks given by the test matrices'
+        column counts: omega1 ((N_theta N_phi) x k1), omega2 (N_phi x k2),
+        host arrays or float64 tensors (copied to this device)."""
+        om = []
+        for o in (omega1, omega2):
+            if isinstance(o, self.torch.Tensor):
+                t = o.detach().to(device=self.device, dtype=self.torch.float64).contiguous()
+            else:
+                t = self.torch.as_tensor(np.ascontiguousarray(o, dtype=np.float64), device=self.device)
+            om.append(t)
+        if om[0].dim() != 2 or om[1].dim() != 2 or om[0].shape[0] != self.nt * self.np_ \
+                or om[1].shape[0] != self.np_:
+            raise ValueError("omega1 must be (N_theta N_phi) x k1 and omega2 N_phi x k2")
+        r = (C.c_int32 * 2)()
+        self.torch.cuda.synchronize(self.device)
+        self._check(self.lib.tt_round_randomized(self.ctx, C.c_void_p(om[0].data_ptr()), int(om[0].shape[1]),
+                                                 C.c_void_p(om[1].data_ptr()), int(om[1].shape[1]), r))
+        return int(r[0]), int(r[1])
+
     def tt_energy(self, E=None):
         """Return (E tensor on device, radiation total, material total)."""
         if E is None:

@@ -48,6 +48,7 @@ SIGNATURES = {
                             PD, PD, PD, C.c_int32, C.c_int32, VP, C.c_size_t, VP, C.POINTER(VP)]),
     "tt_step": (C.c_int, [VP, C.c_int32]),
     "tt_round": (C.c_int, [VP, C.c_double, C.c_int32, PI]),
+    "tt_round_randomized": (C.c_int, [VP, VP, C.c_int32, VP, C.c_int32, PI]),
     "tt_energy": (C.c_int, [VP, VP, PD, PD]),
     "tt_grad": (C.c_int, [VP, PD, C.c_double, PD, VP]),
     "tt_set_kappa": (C.c_int, [VP, VP]),

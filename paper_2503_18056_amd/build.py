@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtt.so")
 SOURCES = ["k_gemm.hip", "k_eig.hip", "k_step.hip", "k_adj.hip", "tt_api.hip", "tt_grad.hip",
-           "tt_kernels_api.hip", "k_micro.hip"]
+           "tt_kernels_api.hip", "k_micro.hip", "tt_rand.hip"]
 ARCH = os.environ.get("TT_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -48,6 +48,7 @@ enum : int {
   FLAG_EIG = 4,
   FLAG_BARRIER = 8,  // a grid barrier of a multi-block eigensolver timed out
   FLAG_NOCONV = 16,  // the one-sided Jacobi SVD ran out of sweeps
+  FLAG_CHOL = 32,    // a Cholesky factor of a sketch Gram met a non-positive pivot
 };
 
 // diagnostics (double table)

@@ -1,0 +1,253 @@
+// Randomized TT rounding to fixed target ranks (App. A.3, eqs. randfinal and
+// randprojection), over the two bonds from left to right.
+//
+// Bond k holds the TT as A_k B_k^T.  With the caller's Gaussian test matrix
+// Omega_k (its column count is the target rank), the sketch of the small
+// factor W = B_k^T Omega_k is formed first, then Y = A_k W, an orthonormal
+// basis Q of range(Y), A_k' = Q and M_upd = Q^T A_k carried into the next
+// core (reading: the QR that the text attaches to W can only be of A_k W,
+// whose rows are A_k's).  Bond 1: A_1 = X (N_s x r1), B_1^T = (Theta x Phi)
+// unfolded to r1 x (N_theta N_phi).  Bond 2: A_2 = (M_upd1 Theta) unfolded
+// to (k1 N_theta) x r2, B_2^T = Phi.
+//
+// The orthonormal basis is the shifted CholeskyQR3 of Fukaya, Kannan,
+// Nakatsukasa, Yamamoto and Yanagisawa (2020): a Gram with a diagonal shift
+// s = 11 (m n + n (n + 1)) u ||Y||^2 (the trace bounds ||Y||_2^2), its upper
+// Cholesky factor R and Q = Y R^{-1}, then two plain CholeskyQR passes on
+// Q; the result is orthonormal to O(u) for cond(Y) up to about 1/u.  Every
+// pass is a tall Gram and a tall product on the FP64 MFMA kernels; the last
+// pass's Gram also holds Q''^T A_k, so M_upd = R3^{-T} (Q''^T A_k) needs no
+// further sweep over the tall factor.  No eigensolver runs.
+#include <math.h>
+
+#include <algorithm>
+
+#include "tt_ctx.h"
+
+namespace tt {
+
+namespace {
+
+constexpr double UNIT_ROUNDOFF = 1.1102230246251565e-16;  // 2^-53
+
+// Upper Cholesky factor R of a k x k Gram G (G = R^T R; only G's upper
+// triangle is read), with s added to the diagonal first when shift_rows > 0,
+// and R^{-1}, in one block.  R and Ri are k x k (ld ldr) with zero lower
+// parts.  A pivot that is not positive raises FLAG_CHOL (its row then
+// continues with pivot 1 so that the kernel ends normally).
+__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int ldg, int k,
+                                                  long long shift_rows, double* __restrict__ R,
+                                                  double* __restrict__ Ri, int ldr,
+                                                  int* __restrict__ dims) {
+  __shared__ double red[256];
+  __shared__ double sdiag;
+  const int t = threadIdx.x;
+  double shift = 0.0;
+  if (shift_rows > 0) {
+    double a = 0.0;
+    for (int i = t; i < k; i += 256) a += G[(long long)i * ldg + i];
+    red[t] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) red[t] += red[t + o];
+      __syncthreads();
+    }
+    shift = 11.0 * ((double)shift_rows * k + (double)k * (k + 1)) * UNIT_ROUNDOFF * red[0];
+  }
+  for (int j = 0; j < k; ++j) {
+    if (t == 0) {
+      double d = G[(long long)j * ldg + j] + shift;
+      for (int i = 0; i < j; ++i) d -= R[(long long)i * ldr + j] * R[(long long)i * ldr + j];
+      sdiag = d;
+    }
+    __syncthreads();
+    const double d = sdiag;
+    const bool bad = !(d > 0.0);
+    const double rjj = bad ? 1.0 : sqrt(d);
+    if (bad && t == 0) atomicOr(&dims[D_FLAG], FLAG_CHOL);
+    for (int l = j + t; l < k; l += 256) {
+      double v = rjj;
+      if (l > j) {
+        v = G[(long long)j * ldg + l];
+        for (int i = 0; i < j; ++i) v -= R[(long long)i * ldr + j] * R[(long long)i * ldr + l];
+        v /= rjj;
+      }
+      R[(long long)j * ldr + l] = v;
+    }
+    for (int l = t; l < j; l += 256) R[(long long)j * ldr + l] = 0.0;
+    __syncthreads();
+  }
+  // column c of R^{-1} solves R x = e_c by back substitution (a thread each)
+  for (int cc = t; cc < k; cc += 256) {
+    for (int i = k - 1; i > cc; --i) Ri[(long long)i * ldr + cc] = 0.0;
+    Ri[(long long)cc * ldr + cc] = 1.0 / R[(long long)cc * ldr + cc];
+    for (int i = cc - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int l = i + 1; l <= cc; ++l) v += R[(long long)i * ldr + l] * Ri[(long long)l * ldr + cc];
+      Ri[(long long)i * ldr + cc] = -v / R[(long long)i * ldr + i];
+    }
+  }
+}
+
+__global__ void k_set_ranks(int* __restrict__ dims, int r1, int r2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dims[D_R1] = r1;
+    dims[D_R2] = r2;
+  }
+}
+
+int ru8(int x) { return (x + 7) / 8 * 8; }
+
+#define RCHK(ctx, call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ctx_fail(ctx, TT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// The gram of columns [off, off + n) of Z (K rows, ld ldz) into G (ld N):
+// the tall MFMA Gram for the spatial bond, the generic product for bond 2.
+struct Tall {
+  int K;
+  double* Z;
+  int ldz;
+  bool spatial;
+};
+
+void gram_cols(tt_ctx* c, const Tall& t, int off, int n, double* G, int ldg, const GramPlan* p) {
+  if (t.spatial) {
+    gram_tall(*p, t.Z + off, dimc(n), c->gpart, G, ldg, c->dims, c->st);
+  } else {
+    GemmDesc g = gd(t.Z + off, t.ldz, 1, t.Z + off, t.ldz, 0, G, ldg, dimc(n), dimc(n), dimc(t.K));
+    gemm(g, n, n, 1, c->dims, c->st);
+  }
+}
+
+// C (K x n, ld ldc) = Z[:, off : off + kk] B (kk x n, ld ldb).
+void tall_product(tt_ctx* c, const Tall& t, int off, int kk, const double* B, int ldb, double* C,
+                  int ldc, int n) {
+  if (t.spatial) {
+    gemm_tall(t.K, t.Z + off, t.ldz, B, ldb, C, ldc, dimc(kk), dimc(n), kk, n, c->dims, c->st);
+  } else {
+    GemmDesc g = gd(t.Z + off, t.ldz, 0, B, ldb, 0, C, ldc, dimc(t.K), dimc(n), dimc(kk));
+    gemm(g, t.K, n, 1, c->dims, c->st);
+  }
+}
+
+// Shifted CholeskyQR3 of Y = Z[:, 0 : k] next to A = Z[:, o1 : o1 + r]
+// (slot b at o2 >= o1 + r, the gaps zero): Q (K x k) into Qout (ld ldq) and
+// M = Q^T A (k x r) into Mout (ld ldm).  Scratch: three N x N eigen slots.
+void cholqr3(tt_ctx* c, const Tall& t, int k, int r, int o1, int o2, double* Qout, int ldq,
+             double* Mout, int ldm, const GramPlan* p) {
+  const int N = c->N;
+  double *G = c->E[0].V, *R = c->E[1].V, *Ri = c->E[2].V;
+  hipStream_t s = c->st;
+  // pass 1: shifted, Y -> slot b
+  gram_cols(c, t, 0, k, G, N, p);
+  k_chol_inv<<<1, 256, 0, s>>>(G, N, k, (long long)t.K, R, Ri, N, c->dims);
+  tall_product(c, t, 0, k, Ri, N, t.Z + o2, t.ldz, k);
+  // pass 2: slot b -> slot a (Y is no longer needed); the Gram of [A | gap | Q']
+  gram_cols(c, t, o1, o2 - o1 + k, G, N, p);
+  const int b = o2 - o1;
+  k_chol_inv<<<1, 256, 0, s>>>(G + (size_t)b * N + b, N, k, 0, R, Ri, N, c->dims);
+  tall_product(c, t, o2, k, Ri, N, t.Z, t.ldz, k);
+  // pass 3: slot a -> Qout; the Gram of [Q'' | gap | A] holds Q''^T A
+  gram_cols(c, t, 0, o1 + r, G, N, p);
+  k_chol_inv<<<1, 256, 0, s>>>(G, N, k, 0, R, Ri, N, c->dims);
+  tall_product(c, t, 0, k, Ri, N, Qout, ldq, k);
+  // M = R3^{-T} (Q''^T A)
+  GemmDesc m = gd(Ri, N, 1, G + o1, N, 0, Mout, ldm, dimc(k), dimc(r), dimc(k));
+  gemm(m, k, r, 1, c->dims, s);
+}
+
+}  // namespace
+
+}  // namespace tt
+
+using namespace tt;
+
+extern "C" tt_status tt_round_randomized(tt_ctx* c, const double* omega1, int32_t k1,
+                                         const double* omega2, int32_t k2, int32_t ranks_out[2]) {
+  if (!c) return ctx_fail(nullptr, TT_ERR_INVALID_ARG, "null context");
+  if (c->poisoned) return ctx_fail(c, TT_ERR_STATE, "context poisoned");
+  if (!omega1 || !omega2) return ctx_fail(c, TT_ERR_INVALID_ARG, "null test matrix");
+  if (c->mixed) return ctx_fail(c, TT_ERR_INVALID_ARG, "randomized rounding needs a TT_FP64 context");
+  hipStream_t s = c->st;
+  int r[2];
+  RCHK(c, hipMemcpyAsync(r, c->dims, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  RCHK(c, hipStreamSynchronize(s));
+  const int r1 = r[0], r2 = r[1], nt = c->nt, np = c->np, ns = c->ns, N = c->N;
+  if (k1 < 1 || k2 < 1 || k1 > r1 || k2 > r2 || k1 > nt * np || k2 > np || k2 > k1 * nt)
+    return ctx_fail(c, TT_ERR_INVALID_ARG,
+                    "target ranks must satisfy 1 <= k1 <= min(r1, N_theta N_phi) and "
+                    "1 <= k2 <= min(r2, N_phi, k1 N_theta)");
+  // slot layout of the two tall factors: [Y/Q'' | A | Q'], 8-column aligned
+  const int o1 = ru8(k1), o2 = o1 + ru8(r1);
+  const int q1 = ru8(k2), q2 = q1 + ru8(r2);
+  if (o2 + k1 > std::min(c->R1c, c->ldC) || q2 + k2 > c->R2c)
+    return ctx_fail(c, TT_ERR_INVALID_ARG, "rank capacity too small for the sketch slots");
+  if (c->gb.on && c->nhist > 0) c->gb.stale = true;
+  const int r2c = c->r2c, R1c = c->R1c, R2c = c->R2c;
+  // ---- bond 1 ---------------------------------------------------------------
+  // E_l = Phi Omega1_l (r2 x k1 per theta ordinate l; rows (l, b) of T1)
+  GemmDesc e = gd(c->Ph, np, 0, omega1, k1, 0, c->T1, k1, dimc(r2), dimc(k1), dimc(np));
+  e.sB = (long long)np * k1;
+  e.sC = (long long)r2 * k1;
+  gemm(e, r2, k1, nt, c->dims, s);
+  // W1 = sum_l Theta_l E_l (r1 x k1): per-l partials, summed in a fixed order
+  GemmDesc w = gd(c->Th, nt * r2c, 0, c->T1, k1, 0, c->gpart, k1, dimc(r1), dimc(k1), dimc(r2));
+  w.sA = r2c;
+  w.sB = (long long)r2 * k1;
+  w.sC = (long long)r1 * k1;
+  gemm(w, r1, k1, nt, c->dims, s);
+  double* W1 = c->M1;
+  sum_partials(c->gpart, (long long)r1 * k1, nt, W1, k1, k1, dimc(r1), dimc(k1), r1, k1, c->dims, s);
+  double* Z = c->Xcat;
+  const int ldz = c->ldC;
+  RCHK(c, hipMemset2DAsync(Z, (size_t)ldz * 8, 0, (size_t)(o2 + k1) * 8, ns, s));
+  gemm_tall(ns, c->X, c->ldX, W1, k1, Z, ldz, dimc(r1), dimc(k1), r1, k1, c->dims, s);
+  RCHK(c, hipMemcpy2DAsync(Z + o1, (size_t)ldz * 8, c->X, (size_t)c->ldX * 8, (size_t)r1 * 8, ns,
+                           hipMemcpyDeviceToDevice, s));
+  const GramPlan p1 = gram_plan(ns, R1c, ldz);
+  double* M1 = c->Mupd1;  // k1 x r1, ld R1c
+  cholqr3(c, Tall{ns, Z, ldz, true}, k1, r1, o1, o2, c->Xn, c->ldX, M1, R1c, &p1);
+  // ---- bond 2 ---------------------------------------------------------------
+  // A2 = M1 Theta: rows (i, l) of T1 with ld r2c (columns past r2 unused)
+  GemmDesc a = gd(M1, R1c, 0, c->Th, nt * r2c, 0, c->T1, nt * r2c, dimc(k1), dimc(nt * r2c), dimc(r1));
+  gemm(a, k1, nt * r2c, 1, c->dims, s);
+  // W2 = Phi Omega2 (r2 x k2)
+  double* W2 = c->E[4].V;  // r2 x k2
+  GemmDesc w2 = gd(c->Ph, np, 0, omega2, k2, 0, W2, k2, dimc(r2), dimc(k2), dimc(np));
+  gemm(w2, r2, k2, 1, c->dims, s);
+  const int K2 = k1 * nt;
+  double* Z2 = c->Thcat;
+  RCHK(c, hipMemset2DAsync(Z2, (size_t)R2c * 8, 0, (size_t)(q2 + k2) * 8, K2, s));
+  GemmDesc y2 = gd(c->T1, r2c, 0, W2, k2, 0, Z2, R2c, dimc(K2), dimc(k2), dimc(r2));
+  gemm(y2, K2, k2, 1, c->dims, s);
+  RCHK(c, hipMemcpy2DAsync(Z2 + q1, (size_t)R2c * 8, c->T1, (size_t)r2c * 8, (size_t)r2 * 8, K2,
+                           hipMemcpyDeviceToDevice, s));
+  double* M2 = c->E[3].V;  // k2 x r2, ld N
+  // Theta' = Q2 reshaped: rows (i, l) of the state's Theta (ld r2c)
+  cholqr3(c, Tall{K2, Z2, R2c, false}, k2, r2, q1, q2, c->Th, r2c, M2, N, nullptr);
+  // Phi' = M2 Phi (k2 x N_phi), through Phi_cat
+  GemmDesc ph = gd(M2, N, 0, c->Ph, np, 0, c->Phcat, np, dimc(k2), dimc(np), dimc(r2));
+  gemm(ph, k2, np, 1, c->dims, s);
+  RCHK(c, hipMemcpyAsync(c->Ph, c->Phcat, (size_t)k2 * np * 8, hipMemcpyDeviceToDevice, s));
+  k_set_ranks<<<1, 64, 0, s>>>(c->dims, k1, k2);
+  RCHK(c, hipGetLastError());
+  std::swap(c->X, c->Xn);
+  int flag = 0;
+  RCHK(c, hipMemcpyAsync(&flag, c->dims + D_FLAG, sizeof(int), hipMemcpyDeviceToHost, s));
+  RCHK(c, hipStreamSynchronize(s));
+  if (flag) {
+    c->poisoned = true;
+    return ctx_fail(c, TT_ERR_NUMERIC,
+                    flag & FLAG_CHOL ? "numerical failure: a sketch Gram lost definiteness"
+                                     : "numerical failure");
+  }
+  if (ranks_out) {
+    ranks_out[0] = k1;
+    ranks_out[1] = k2;
+  }
+  return TT_OK;
+}
