@@ -180,13 +180,13 @@ tt_status tt_round(tt_ctx* ctx, double tol, int32_t rmax, int32_t ranks_out[2]);
  * Gaussian test matrices the caller draws (read only, caller-owned); their
  * column counts are the target ranks.  Each bond sketches its right factor
  * (W = B^T Omega), takes an orthonormal basis Q of A W (shifted
- * CholeskyQR3 on the FP64 MFMA Gram and product kernels) and carries
- * Q^T A into the next core; X' and Theta' come out with orthonormal
- * columns.  TT_FP64 contexts only; needs 1 <= k1 <= min(r1, N_theta N_phi)
- * and 1 <= k2 <= min(r2, N_phi, k1 N_theta) at the current ranks (r1, r2),
- * and room for three 8-column-aligned slots in the concatenation buffers
- * (k1 + r1 + k1 columns of X_cat, k2 + r2 + k2 of Theta_cat; always true
- * when the ranks are multiples of 8).  ranks_out (host, may be NULL)
+ * CholeskyQR3: k x k Grams and tall products on the FP64 MFMA kernels) and
+ * carries Q^T A into the next core; X' and Theta' come out with
+ * orthonormal columns.  TT_FP64 contexts only; needs
+ * 1 <= k1 <= min(r1, N_theta N_phi) and 1 <= k2 <= min(r2, N_phi, k1 N_theta)
+ * at the current ranks (r1, r2), and two 8-column-aligned sketch slots in
+ * the concatenation buffers (round_up(k1, 8) + k1 <= the X_cat capacity,
+ * round_up(k2, 8) + k2 <= the Theta_cat capacity).  ranks_out (host, may be NULL)
  * receives (k1, k2).  Like tt_round it is not a recorded step.
  * Errors: TT_ERR_INVALID_ARG (sizes, null pointers, FP32-mixed context),
  * TT_ERR_NUMERIC (a sketch Gram not positive definite after its shift:

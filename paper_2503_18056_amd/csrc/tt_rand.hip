@@ -15,9 +15,10 @@
 // s = 11 (m n + n (n + 1)) u ||Y||^2 (the trace bounds ||Y||_2^2), its upper
 // Cholesky factor R and Q = Y R^{-1}, then two plain CholeskyQR passes on
 // Q; the result is orthonormal to O(u) for cond(Y) up to about 1/u.  Every
-// pass is a tall Gram and a tall product on the FP64 MFMA kernels; the last
-// pass's Gram also holds Q''^T A_k, so M_upd = R3^{-T} (Q''^T A_k) needs no
-// further sweep over the tall factor.  No eigensolver runs.
+// pass is a k x k Gram of the tall sketch and a tall product on the FP64
+// MFMA kernels, and M_upd = Q^T A_k one split-K product over the rows: the
+// N_s-long work is N_s r k for the sketch and for M_upd plus six N_s k^2
+// products, against N_s R^2 for the Gram route.  No eigensolver runs.
 #include <math.h>
 
 #include <algorithm>
@@ -105,7 +106,7 @@ int ru8(int x) { return (x + 7) / 8 * 8; }
       return ctx_fail(ctx, TT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// The gram of columns [off, off + n) of Z (K rows, ld ldz) into G (ld N):
+// The Gram of columns [off, off + n) of Z (K rows, ld ldz) into G (ld N):
 // the tall MFMA Gram for the spatial bond, the generic product for bond 2.
 struct Tall {
   int K;
@@ -134,30 +135,43 @@ void tall_product(tt_ctx* c, const Tall& t, int off, int kk, const double* B, in
   }
 }
 
-// Shifted CholeskyQR3 of Y = Z[:, 0 : k] next to A = Z[:, o1 : o1 + r]
-// (slot b at o2 >= o1 + r, the gaps zero): Q (K x k) into Qout (ld ldq) and
-// M = Q^T A (k x r) into Mout (ld ldm).  Scratch: three N x N eigen slots.
-void cholqr3(tt_ctx* c, const Tall& t, int k, int r, int o1, int o2, double* Qout, int ldq,
-             double* Mout, int ldm, const GramPlan* p) {
+// Shifted CholeskyQR3 of Y = Z[:, 0 : k] (slot b at column o1 >= k): Q
+// (K x k) into Qout (ld ldq).  Each pass: the k x k Gram of its slot, the
+// Cholesky factor and inverse, and the product into the other slot (the
+// last one into Qout).  Scratch: three N x N eigen slots.
+void cholqr3(tt_ctx* c, const Tall& t, int k, int o1, double* Qout, int ldq, const GramPlan* p) {
   const int N = c->N;
   double *G = c->E[0].V, *R = c->E[1].V, *Ri = c->E[2].V;
   hipStream_t s = c->st;
-  // pass 1: shifted, Y -> slot b
+  // pass 1, shifted: Y -> slot b
   gram_cols(c, t, 0, k, G, N, p);
   k_chol_inv<<<1, 256, 0, s>>>(G, N, k, (long long)t.K, R, Ri, N, c->dims);
-  tall_product(c, t, 0, k, Ri, N, t.Z + o2, t.ldz, k);
-  // pass 2: slot b -> slot a (Y is no longer needed); the Gram of [A | gap | Q']
-  gram_cols(c, t, o1, o2 - o1 + k, G, N, p);
-  const int b = o2 - o1;
-  k_chol_inv<<<1, 256, 0, s>>>(G + (size_t)b * N + b, N, k, 0, R, Ri, N, c->dims);
-  tall_product(c, t, o2, k, Ri, N, t.Z, t.ldz, k);
-  // pass 3: slot a -> Qout; the Gram of [Q'' | gap | A] holds Q''^T A
-  gram_cols(c, t, 0, o1 + r, G, N, p);
+  tall_product(c, t, 0, k, Ri, N, t.Z + o1, t.ldz, k);
+  // pass 2: slot b -> slot a (Y is no longer needed)
+  gram_cols(c, t, o1, k, G, N, p);
+  k_chol_inv<<<1, 256, 0, s>>>(G, N, k, 0, R, Ri, N, c->dims);
+  tall_product(c, t, o1, k, Ri, N, t.Z, t.ldz, k);
+  // pass 3: slot a -> Qout
+  gram_cols(c, t, 0, k, G, N, p);
   k_chol_inv<<<1, 256, 0, s>>>(G, N, k, 0, R, Ri, N, c->dims);
   tall_product(c, t, 0, k, Ri, N, Qout, ldq, k);
-  // M = R3^{-T} (Q''^T A)
-  GemmDesc m = gd(Ri, N, 1, G + o1, N, 0, Mout, ldm, dimc(k), dimc(r), dimc(k));
-  gemm(m, k, r, 1, c->dims, s);
+}
+
+// M (m x n, ld ldm) = Q^T A over K rows (Q: K x m, A: K x n), split over
+// row slices into per-slice partials (gpart) summed in a fixed order.
+void contract_tall(tt_ctx* c, const double* Q, int ldq, const double* A, int lda, int K, int m, int n,
+                   double* M, int ldm) {
+  const long long tile = (long long)m * n;
+  const long long avail = (long long)c->nt * c->R1c * c->R1c;  // gpart holds at least this
+  const int zmax = (int)std::max<long long>(1, std::min<long long>(avail / tile, 1024));
+  int ks = (K + zmax - 1) / zmax;
+  ks = std::max(64, (ks + 15) / 16 * 16);
+  const int nz = (K + ks - 1) / ks;
+  GemmDesc g = gd(Q, ldq, 1, A, lda, 0, c->gpart, n, dimc(m), dimc(n), dimc(K));
+  g.ksplit = ks;
+  g.sC = tile;
+  gemm(g, m, n, nz, c->dims, c->st);
+  sum_partials(c->gpart, tile, nz, M, ldm, n, dimc(m), dimc(n), m, n, c->dims, c->st);
 }
 
 }  // namespace
@@ -181,10 +195,9 @@ extern "C" tt_status tt_round_randomized(tt_ctx* c, const double* omega1, int32_
     return ctx_fail(c, TT_ERR_INVALID_ARG,
                     "target ranks must satisfy 1 <= k1 <= min(r1, N_theta N_phi) and "
                     "1 <= k2 <= min(r2, N_phi, k1 N_theta)");
-  // slot layout of the two tall factors: [Y/Q'' | A | Q'], 8-column aligned
-  const int o1 = ru8(k1), o2 = o1 + ru8(r1);
-  const int q1 = ru8(k2), q2 = q1 + ru8(r2);
-  if (o2 + k1 > std::min(c->R1c, c->ldC) || q2 + k2 > c->R2c)
+  // two 8-column-aligned slots per tall factor: [Y / Q'' | Q']
+  const int o1 = ru8(k1), q1 = ru8(k2);
+  if (o1 + k1 > std::min(c->R1c, c->ldC) || q1 + k2 > c->R2c)
     return ctx_fail(c, TT_ERR_INVALID_ARG, "rank capacity too small for the sketch slots");
   if (c->gb.on && c->nhist > 0) c->gb.stale = true;
   const int r2c = c->r2c, R1c = c->R1c, R2c = c->R2c;
@@ -204,13 +217,11 @@ extern "C" tt_status tt_round_randomized(tt_ctx* c, const double* omega1, int32_
   sum_partials(c->gpart, (long long)r1 * k1, nt, W1, k1, k1, dimc(r1), dimc(k1), r1, k1, c->dims, s);
   double* Z = c->Xcat;
   const int ldz = c->ldC;
-  RCHK(c, hipMemset2DAsync(Z, (size_t)ldz * 8, 0, (size_t)(o2 + k1) * 8, ns, s));
   gemm_tall(ns, c->X, c->ldX, W1, k1, Z, ldz, dimc(r1), dimc(k1), r1, k1, c->dims, s);
-  RCHK(c, hipMemcpy2DAsync(Z + o1, (size_t)ldz * 8, c->X, (size_t)c->ldX * 8, (size_t)r1 * 8, ns,
-                           hipMemcpyDeviceToDevice, s));
   const GramPlan p1 = gram_plan(ns, R1c, ldz);
-  double* M1 = c->Mupd1;  // k1 x r1, ld R1c
-  cholqr3(c, Tall{ns, Z, ldz, true}, k1, r1, o1, o2, c->Xn, c->ldX, M1, R1c, &p1);
+  cholqr3(c, Tall{ns, Z, ldz, true}, k1, o1, c->Xn, c->ldX, &p1);
+  double* M1 = c->Mupd1;  // k1 x r1 = Q1^T X, ld R1c
+  contract_tall(c, c->Xn, c->ldX, c->X, c->ldX, ns, k1, r1, M1, R1c);
   // ---- bond 2 ---------------------------------------------------------------
   // A2 = M1 Theta: rows (i, l) of T1 with ld r2c (columns past r2 unused)
   GemmDesc a = gd(M1, R1c, 0, c->Th, nt * r2c, 0, c->T1, nt * r2c, dimc(k1), dimc(nt * r2c), dimc(r1));
@@ -221,14 +232,12 @@ extern "C" tt_status tt_round_randomized(tt_ctx* c, const double* omega1, int32_
   gemm(w2, r2, k2, 1, c->dims, s);
   const int K2 = k1 * nt;
   double* Z2 = c->Thcat;
-  RCHK(c, hipMemset2DAsync(Z2, (size_t)R2c * 8, 0, (size_t)(q2 + k2) * 8, K2, s));
   GemmDesc y2 = gd(c->T1, r2c, 0, W2, k2, 0, Z2, R2c, dimc(K2), dimc(k2), dimc(r2));
   gemm(y2, K2, k2, 1, c->dims, s);
-  RCHK(c, hipMemcpy2DAsync(Z2 + q1, (size_t)R2c * 8, c->T1, (size_t)r2c * 8, (size_t)r2 * 8, K2,
-                           hipMemcpyDeviceToDevice, s));
-  double* M2 = c->E[3].V;  // k2 x r2, ld N
   // Theta' = Q2 reshaped: rows (i, l) of the state's Theta (ld r2c)
-  cholqr3(c, Tall{K2, Z2, R2c, false}, k2, r2, q1, q2, c->Th, r2c, M2, N, nullptr);
+  cholqr3(c, Tall{K2, Z2, R2c, false}, k2, q1, c->Th, r2c, nullptr);
+  double* M2 = c->E[3].V;  // k2 x r2 = Q2^T A2, ld N
+  contract_tall(c, c->Th, r2c, c->T1, r2c, K2, k2, r2, M2, N);
   // Phi' = M2 Phi (k2 x N_phi), through Phi_cat
   GemmDesc ph = gd(M2, N, 0, c->Ph, np, 0, c->Phcat, np, dimc(k2), dimc(np), dimc(r2));
   gemm(ph, k2, np, 1, c->dims, s);
