@@ -10,15 +10,16 @@
 // unfolded to r1 x (N_theta N_phi).  Bond 2: A_2 = (M_upd1 Theta) unfolded
 // to (k1 N_theta) x r2, B_2^T = Phi.
 //
-// The orthonormal basis is the shifted CholeskyQR3 of Fukaya, Kannan,
+// The orthonormal basis follows the shifted CholeskyQR3 of Fukaya, Kannan,
 // Nakatsukasa, Yamamoto and Yanagisawa (2020): a Gram with a diagonal shift
 // s = 11 (m n + n (n + 1)) u ||Y||^2 (the trace bounds ||Y||_2^2), its upper
-// Cholesky factor R and Q = Y R^{-1}, then two plain CholeskyQR passes on
-// Q; the result is orthonormal to O(u) for cond(Y) up to about 1/u.  Every
-// pass is a k x k Gram of the tall sketch and a tall product on the FP64
-// MFMA kernels, and M_upd = Q^T A_k one split-K product over the rows: the
-// N_s-long work is N_s r k for the sketch and for M_upd plus six N_s k^2
-// products, against N_s R^2 for the Gram route.  No eigensolver runs.
+// Cholesky factor R and Q = Y R^{-1}, then plain CholeskyQR passes on Q;
+// with one more shifted pass (cholqr) it also covers a sketch of lower
+// numerical rank than its width.  Every pass is a k x k Gram of the tall
+// sketch and a tall product on the FP64 MFMA kernels, and M_upd = Q^T A_k
+// one split-K product over the rows: the N_s-long work is N_s r k for the
+// sketch and for M_upd plus ten N_s k^2 products, against N_s R^2 for the
+// Gram route.  No eigensolver runs.
 #include <math.h>
 
 #include <algorithm>
@@ -90,6 +91,98 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
   }
 }
 
+// The same for k <= CHOL_LDS_K, LDS-resident (k (k + 1) doubles of dynamic LDS):
+// right-looking Cholesky (per pivot: scale its row, update the trailing
+// upper triangle), then R^{-1} in place column by column (column j from the
+// inverted leading block and R's column j), so that every step is parallel
+// over rows and the serial chain is k steps of LDS work.
+constexpr int CHOL_LDS_K = 128;
+
+__global__ __launch_bounds__(256) void k_chol_inv_lds(const double* __restrict__ G, int ldg, int k,
+                                                      long long shift_rows, double* __restrict__ R,
+                                                      double* __restrict__ Ri, int ldr,
+                                                      int* __restrict__ dims) {
+  extern __shared__ double A[];  // k x k, ld lk = k + 1 (odd: rows in distinct banks)
+  __shared__ double red[256];
+  const int t = threadIdx.x, lk = k + 1;
+  double a = 0.0;
+  for (int i = t; i < k; i += 256) a += G[(long long)i * ldg + i];
+  red[t] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  const double shift =
+      shift_rows > 0 ? 11.0 * ((double)shift_rows * k + (double)k * (k + 1)) * UNIT_ROUNDOFF * red[0] : 0.0;
+  for (int e = t; e < k * k; e += 256) {
+    const int i = e / k, l = e % k;
+    A[i * lk + l] = l >= i ? G[(long long)i * ldg + l] + (l == i ? shift : 0.0) : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    __syncthreads();  // the previous pivot's trailing update is complete
+    const double d = A[j * lk + j];
+    const bool bad = !(d > 0.0);
+    const double rjj = bad ? 1.0 : sqrt(d);
+    if (bad && t == 0) atomicOr(&dims[D_FLAG], FLAG_CHOL);
+    __syncthreads();
+    const double inv = 1.0 / rjj;
+    for (int l = j + t; l < k; l += 256) A[j * lk + l] = l == j ? rjj : A[j * lk + l] * inv;
+    __syncthreads();
+    for (int i = j + 1 + (t >> 4); i < k; i += 16) {
+      const double rji = A[j * lk + i];
+      for (int l = i + (t & 15); l < k; l += 16) A[i * lk + l] -= rji * A[j * lk + l];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < k * k; e += 256) {
+    const int i = e / k, l = e % k;
+    R[(long long)i * ldr + l] = l >= i ? A[i * lk + l] : 0.0;
+  }
+  // in place: after column j, A[0:j+1, 0:j+1] holds the leading block of
+  // R^{-1}; row i's dot product for column j is split between threads i and
+  // i + 128 (halves of l in [i, j)), each with four independent partial sums
+  const int ri = t & 127, half = t >> 7;
+  for (int j = 0; j < k; ++j) {
+    const double ajj = 1.0 / A[j * lk + j];
+    double v = 0.0;
+    if (ri < j) {
+      const int mid = (ri + j) >> 1;
+      const int l0 = half ? mid : ri, l1 = half ? j : mid;
+      double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+      int l = l0;
+      for (; l + 3 < l1; l += 4) {
+        v0 += A[ri * lk + l] * A[l * lk + j];
+        v1 += A[ri * lk + l + 1] * A[(l + 1) * lk + j];
+        v2 += A[ri * lk + l + 2] * A[(l + 2) * lk + j];
+        v3 += A[ri * lk + l + 3] * A[(l + 3) * lk + j];
+      }
+      for (; l < l1; ++l) v0 += A[ri * lk + l] * A[l * lk + j];
+      v = (v0 + v1) + (v2 + v3);
+    }
+    red[t] = v;
+    __syncthreads();
+    if (t < j) A[t * lk + j] = -(red[t] + red[t + 128]) * ajj;
+    if (t == 0) A[j * lk + j] = ajj;
+    __syncthreads();
+  }
+  for (int e = t; e < k * k; e += 256) {
+    const int i = e / k, l = e % k;
+    Ri[(long long)i * ldr + l] = l >= i ? A[i * lk + l] : 0.0;
+  }
+}
+
+// One factorisation: the LDS kernel when k fits, else the global one.
+void chol_inv(const double* G, int ldg, int k, long long shift_rows, double* R, double* Ri, int ldr,
+              int* dims, hipStream_t s) {
+  if (k <= CHOL_LDS_K)
+    k_chol_inv_lds<<<1, 256, (size_t)k * (k + 1) * sizeof(double), s>>>(G, ldg, k, shift_rows, R, Ri, ldr,
+                                                                          dims);
+  else
+    k_chol_inv<<<1, 256, 0, s>>>(G, ldg, k, shift_rows, R, Ri, ldr, dims);
+}
+
 __global__ void k_set_ranks(int* __restrict__ dims, int r1, int r2) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     dims[D_R1] = r1;
@@ -106,6 +199,23 @@ int ru8(int x) { return (x + 7) / 8 * 8; }
       return ctx_fail(ctx, TT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// M (m x n, ld ldm) = Q^T A over K rows (Q: K x m, A: K x n), split over
+// row slices into per-slice partials (gpart) summed in a fixed order.
+void contract_tall(tt_ctx* c, const double* Q, int ldq, const double* A, int lda, int K, int m, int n,
+                   double* M, int ldm) {
+  const long long tile = (long long)m * n;
+  const long long avail = (long long)c->nt * c->R1c * c->R1c;  // gpart holds at least this
+  const int zmax = (int)std::max<long long>(1, std::min<long long>(avail / tile, 128));
+  int ks = (K + zmax - 1) / zmax;
+  ks = std::max(64, (ks + 15) / 16 * 16);
+  const int nz = (K + ks - 1) / ks;
+  GemmDesc g = gd(Q, ldq, 1, A, lda, 0, c->gpart, n, dimc(m), dimc(n), dimc(K));
+  g.ksplit = ks;
+  g.sC = tile;
+  gemm(g, m, n, nz, c->dims, c->st);
+  sum_partials(c->gpart, tile, nz, M, ldm, n, dimc(m), dimc(n), m, n, c->dims, c->st);
+}
+
 // The Gram of columns [off, off + n) of Z (K rows, ld ldz) into G (ld N):
 // the tall MFMA Gram for the spatial bond, the generic product for bond 2.
 struct Tall {
@@ -119,8 +229,7 @@ void gram_cols(tt_ctx* c, const Tall& t, int off, int n, double* G, int ldg, con
   if (t.spatial) {
     gram_tall(*p, t.Z + off, dimc(n), c->gpart, G, ldg, c->dims, c->st);
   } else {
-    GemmDesc g = gd(t.Z + off, t.ldz, 1, t.Z + off, t.ldz, 0, G, ldg, dimc(n), dimc(n), dimc(t.K));
-    gemm(g, n, n, 1, c->dims, c->st);
+    contract_tall(c, t.Z + off, t.ldz, t.Z + off, t.ldz, t.K, n, n, G, ldg);
   }
 }
 
@@ -135,44 +244,32 @@ void tall_product(tt_ctx* c, const Tall& t, int off, int kk, const double* B, in
   }
 }
 
-// Shifted CholeskyQR3 of Y = Z[:, 0 : k] (slot b at column o1 >= k): Q
-// (K x k) into Qout (ld ldq).  Each pass: the k x k Gram of its slot, the
-// Cholesky factor and inverse, and the product into the other slot (the
-// last one into Qout).  Scratch: three N x N eigen slots.
-void cholqr3(tt_ctx* c, const Tall& t, int k, int o1, double* Qout, int ldq, const GramPlan* p) {
+// Orthonormal basis of Y = Z[:, 0 : k] (slot b at column o1 >= k) into
+// Qout (K x k, ld ldq): three shifted CholeskyQR passes, then two plain
+// ones (shifted CholeskyQR3 with two more shifted passes).  A
+// well-conditioned Y needs only the first shift; the others lift directions
+// that Y holds at rounding level (a target rank past the numerical rank) by
+// 1/sqrt(s) each (at least about 30x at K k^2 <= 1e9 rows x columns^2), so
+// that the plain passes, which need cond < u^{-1/2}, finish them
+// orthonormal as a Householder QR would.  Each pass: the k x k Gram of its slot, the
+// Cholesky factor and inverse, and the product into the other slot (the last
+// into Qout).  Scratch: three N x N eigen slots.
+constexpr int CHOLQR_PASSES = 5, CHOLQR_SHIFTED = 3;
+
+void cholqr(tt_ctx* c, const Tall& t, int k, int o1, double* Qout, int ldq, const GramPlan* p) {
   const int N = c->N;
   double *G = c->E[0].V, *R = c->E[1].V, *Ri = c->E[2].V;
   hipStream_t s = c->st;
-  // pass 1, shifted: Y -> slot b
-  gram_cols(c, t, 0, k, G, N, p);
-  k_chol_inv<<<1, 256, 0, s>>>(G, N, k, (long long)t.K, R, Ri, N, c->dims);
-  tall_product(c, t, 0, k, Ri, N, t.Z + o1, t.ldz, k);
-  // pass 2: slot b -> slot a (Y is no longer needed)
-  gram_cols(c, t, o1, k, G, N, p);
-  k_chol_inv<<<1, 256, 0, s>>>(G, N, k, 0, R, Ri, N, c->dims);
-  tall_product(c, t, o1, k, Ri, N, t.Z, t.ldz, k);
-  // pass 3: slot a -> Qout
-  gram_cols(c, t, 0, k, G, N, p);
-  k_chol_inv<<<1, 256, 0, s>>>(G, N, k, 0, R, Ri, N, c->dims);
-  tall_product(c, t, 0, k, Ri, N, Qout, ldq, k);
+  int from = 0, to = o1;
+  for (int pass = 0; pass < CHOLQR_PASSES; ++pass) {
+    gram_cols(c, t, from, k, G, N, p);
+    chol_inv(G, N, k, pass < CHOLQR_SHIFTED ? (long long)t.K : 0, R, Ri, N, c->dims, s);
+    if (pass == CHOLQR_PASSES - 1) tall_product(c, t, from, k, Ri, N, Qout, ldq, k);
+    else tall_product(c, t, from, k, Ri, N, t.Z + to, t.ldz, k);
+    std::swap(from, to);
+  }
 }
 
-// M (m x n, ld ldm) = Q^T A over K rows (Q: K x m, A: K x n), split over
-// row slices into per-slice partials (gpart) summed in a fixed order.
-void contract_tall(tt_ctx* c, const double* Q, int ldq, const double* A, int lda, int K, int m, int n,
-                   double* M, int ldm) {
-  const long long tile = (long long)m * n;
-  const long long avail = (long long)c->nt * c->R1c * c->R1c;  // gpart holds at least this
-  const int zmax = (int)std::max<long long>(1, std::min<long long>(avail / tile, 1024));
-  int ks = (K + zmax - 1) / zmax;
-  ks = std::max(64, (ks + 15) / 16 * 16);
-  const int nz = (K + ks - 1) / ks;
-  GemmDesc g = gd(Q, ldq, 1, A, lda, 0, c->gpart, n, dimc(m), dimc(n), dimc(K));
-  g.ksplit = ks;
-  g.sC = tile;
-  gemm(g, m, n, nz, c->dims, c->st);
-  sum_partials(c->gpart, tile, nz, M, ldm, n, dimc(m), dimc(n), m, n, c->dims, c->st);
-}
 
 }  // namespace
 
@@ -218,8 +315,15 @@ extern "C" tt_status tt_round_randomized(tt_ctx* c, const double* omega1, int32_
   double* Z = c->Xcat;
   const int ldz = c->ldC;
   gemm_tall(ns, c->X, c->ldX, W1, k1, Z, ldz, dimc(r1), dimc(k1), r1, k1, c->dims, s);
-  const GramPlan p1 = gram_plan(ns, R1c, ldz);
-  cholqr3(c, Tall{ns, Z, ldz, true}, k1, o1, c->Xn, c->ldX, &p1);
+  // the sketch's k1 columns (row-slice form up to 384), when its partial
+  // tiles fit the Gram partial buffer (sized at creation as below)
+  GramPlan p1 = gram_plan(ns, k1, ldz);
+  const size_t gpart_doubles =
+      std::max(std::max(gram_partial_doubles(gram_plan(ns, R1c, ldz)),
+                        gram_partial_doubles(gram_plan(ns, c->r1c, c->ldX))),
+               std::max((size_t)nt * R1c * R1c, (size_t)nt * R2c * R2c));
+  if (gram_partial_doubles(p1) > gpart_doubles) p1 = gram_plan(ns, R1c, ldz);
+  cholqr(c, Tall{ns, Z, ldz, true}, k1, o1, c->Xn, c->ldX, &p1);
   double* M1 = c->Mupd1;  // k1 x r1 = Q1^T X, ld R1c
   contract_tall(c, c->Xn, c->ldX, c->X, c->ldX, ns, k1, r1, M1, R1c);
   // ---- bond 2 ---------------------------------------------------------------
@@ -235,7 +339,7 @@ extern "C" tt_status tt_round_randomized(tt_ctx* c, const double* omega1, int32_
   GemmDesc y2 = gd(c->T1, r2c, 0, W2, k2, 0, Z2, R2c, dimc(K2), dimc(k2), dimc(r2));
   gemm(y2, K2, k2, 1, c->dims, s);
   // Theta' = Q2 reshaped: rows (i, l) of the state's Theta (ld r2c)
-  cholqr3(c, Tall{K2, Z2, R2c, false}, k2, q1, c->Th, r2c, nullptr);
+  cholqr(c, Tall{K2, Z2, R2c, false}, k2, q1, c->Th, r2c, nullptr);
   double* M2 = c->E[3].V;  // k2 x r2 = Q2^T A2, ld N
   contract_tall(c, c->Th, r2c, c->T1, r2c, K2, k2, r2, M2, N);
   // Phi' = M2 Phi (k2 x N_phi), through Phi_cat

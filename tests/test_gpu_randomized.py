@@ -70,6 +70,26 @@ def test_randomized_rounding_matches_the_oracle(k1, k2):
     assert ox < 1e-13 and ot < 1e-13
 
 
+def test_randomized_rounding_past_the_numerical_rank():
+    """Target ranks beyond the state's numerical ranks (singular values
+    0.05^i in both bonds: rounding level past about 12): the sketch is
+    numerically rank deficient, the second shifted pass lifts its null
+    directions, and the result is the unrounded tensor to rounding with
+    orthonormal factors."""
+    p = _problem()
+    X, Th, Ph = _decaying_tt(p, 24, 12, seed=81, decay=0.05)
+    om = wl.gaussian_test_matrices(p["ntheta"], p["nphi"], 20, 12, seed=82)
+    st = _state(p, (X, Th, Ph))
+    assert st.tt_round_randomized(*om) == (20, 12)
+    Xg, Thg, Phg = st.tt_get_cores()
+    full = metrics.rel_diff((Xg, Thg, Phg), (X, Th, Ph))
+    ox, ot = _orth_err(Xg), _orth_err(Thg.reshape(20 * p["ntheta"], 12))
+    _log(f"past the numerical rank: vs the unrounded TT {full:.2e}, orthonormality X {ox:.1e} "
+         f"Theta {ot:.1e}")
+    assert full < 1e-13
+    assert ox < 1e-13 and ot < 1e-13
+
+
 def test_randomized_rounding_exact_on_padded_low_rank():
     p = _problem()
     rng = np.random.default_rng(74)
