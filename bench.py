@@ -432,6 +432,46 @@ def rounding_bench(p, reps=100):
     return out
 
 
+def randomized_rounding_bench(p, reps=10):
+    """Gram-SVD rounding (tt_round, tolerance 1e-6, cap 64) against randomized
+    rounding to fixed target ranks (tt_round_randomized, App. A.3) of one
+    seeded state on the crossing-beam shape (256^2, 32x64): orthonormal X
+    65536x192 and Phi rows 48x64, bond-1 singular values 10^(-k/8).  Each
+    rounding starts from the same state (re-installed, untimed); host-timed
+    median of ``reps`` calls, each ending in a synchronisation."""
+    import time
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2503_18056_amd import TTState
+    X, Th, Ph = wl.rounding_bench_cores(p, r1=192, r2=48)
+    st = TTState(p, device=0, cores=(X, Th, Ph), r1_cap=192, r2_cap=48, max_steps=2)
+
+    def timed(fn):
+        ts, r = [], None
+        for i in range(reps + 1):
+            st.tt_set_cores(X, Th, Ph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            if i:
+                ts.append(time.perf_counter() - t0)
+        return r, 1e3 * float(np.median(ts))
+
+    out = {"workload": "seeded state on the crossing-beam shape (256^2, 32x64), ranks (192, 48), "
+                       f"bond-1 singular values 10^(-k/8); median of {reps}"}
+    r, ms = timed(lambda: st.tt_round(1e-6, 64))
+    out["gram_svd"] = {"ms": ms, "ranks": list(r)}
+    out["randomized"] = []
+    for k1, k2 in ((64, 12), (72, 16), (64, 48), (128, 32)):
+        om = wl.gaussian_test_matrices(p["ntheta"], p["nphi"], k1, k2, seed=3)
+        r, ms = timed(lambda: st.tt_round_randomized(*om))
+        out["randomized"].append({"target": [k1, k2], "ms": ms, "ranks": list(r)})
+    st.close()
+    return out
+
+
 def thick_3d_run(W, K):
     """The optically thick 3-D workload (128^3 cells, 32 x 64 ordinates,
     kappa = 1e3 in the central 64^3 cube, coupled material, rank cap 128) in
@@ -535,6 +575,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this many MiB before the "
                          "warmup (a known-size kernel to scale hardware byte counters by)")
+    ap.add_argument("--randomized-only", action="store_true",
+                    help="only compare Gram-SVD and randomized rounding on one state (prints that JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the hot path runs on one GPU "
@@ -543,6 +585,9 @@ def main():
     import workloads as wl
     from paper_2503_18056_amd import TT_FP64
 
+    if args.randomized_only:
+        print(json.dumps({"randomized_rounding_bench": randomized_rounding_bench(wl.c2(steps=2))}))
+        return
     W, K = args.warmup, args.steps
     ramp = max(0, RUN_STEPS - W - K)
     if args.calib_copy_mib > 0:
@@ -645,6 +690,9 @@ def main():
     if not args.no_rounding_bench:
         progress("rounding benchmark at (R1, R2) = (322, 62)")
         out["rounding_bench"] = rounding_bench(wl.c2(steps=2))
+    if not args.no_rounding_bench:
+        progress("Gram-SVD against randomized rounding at ranks (192, 48)")
+        out["randomized_rounding_bench"] = randomized_rounding_bench(wl.c2(steps=2))
     if not args.no_grad:
         progress("differentiation workload: taped forward and reverse sweep")
         out["gradient"] = gradient_run()
